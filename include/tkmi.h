@@ -1,0 +1,216 @@
+/*
+ * tkmi -- randomized (H-)Tucker decomposition on MI355X (gfx950).
+ *
+ * C ABI of libtkmi.so.  The operations follow the problem statements of
+ * Sub-R-HOSVD (Algorithm 1: [S, {U_k}] = Sub-R-HOSVD(X, r, p, s)) and
+ * Sub-R-RtL-HT (Algorithm 2: [{U_k}, {B_S}] = Sub-R-RtL-HT(X, T, r, w, p)) of
+ * "A practical mode-parallel implementation of the (H-)Tucker decomposition
+ * via randomization".  The random quantities of those algorithms (the fiber
+ * samples E_k and the Gaussian matrices Omega_k) are drawn by the caller and
+ * passed in.
+ *
+ * Conventions shared by every entry point
+ *  - Layout: dense tensors are C-ordered (last mode fastest).  The column
+ *    index of the mode-k unfolding X^(k) is the C-order linear index of the
+ *    remaining modes in increasing mode order; the rows of a multi-mode
+ *    unfolding X^(S) are C-ordered over the modes of S.  Matrices are
+ *    row-major.  All sizes and indices are 64-bit.
+ *  - Ownership: every data pointer is a device pointer owned by the caller;
+ *    the library never allocates or frees caller memory.  Descriptor structs
+ *    and pointer arrays are host memory, read during the call only.
+ *  - Workspace: `ws` is caller-provided device memory of *ws_bytes bytes.
+ *    Calling with ws == NULL is a size query: the required byte count is
+ *    written to *ws_bytes, TK_OK is returned and nothing is enqueued.
+ *  - Asynchrony: work is enqueued on `stream` (a hipStream_t; NULL = the
+ *    default stream) and the call returns without synchronising.  Calls on
+ *    one stream that share a workspace are ordered by the stream.
+ *  - Errors: arguments are validated on the host before anything is
+ *    enqueued, so a call that returns an error has no side effects.
+ *    tk_last_error() returns the calling thread's message for the last
+ *    non-OK status.  Numerical events (a Gram matrix that is not numerically
+ *    positive definite) are reported through a device `info` array, as in
+ *    LAPACK.
+ *  - Determinism: the same inputs on the same device give bitwise-identical
+ *    outputs (all reductions have a fixed order, no floating-point atomics).
+ */
+#ifndef TKMI_H
+#define TKMI_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define TK_MAX_ORDER 16
+
+typedef enum { TK_F64 = 0, TK_F32 = 1, TK_BF16 = 2, TK_F16 = 3 } tk_dtype;
+
+typedef enum {
+  TK_OK = 0,
+  TK_EINVAL = 1,        /* invalid argument (message in tk_last_error) */
+  TK_EWORKSPACE = 2,    /* workspace smaller than the size query returned */
+  TK_ENOTPD = 3,        /* reserved: numerical failure reported on the host */
+  TK_EDEVICE = 4,       /* a HIP call or kernel launch failed */
+  TK_EUNSUPPORTED = 5   /* valid request outside what this build implements */
+} tk_status;
+
+/* Dense order-d tensor in device memory (C-order).  Factors, cores, sketches
+ * and bases that belong to a tensor use its "factor dtype": TK_F64 for an
+ * F64 tensor, TK_F32 for F32, BF16 and F16 tensors. */
+typedef struct {
+  int32_t order;                 /* 1 .. TK_MAX_ORDER */
+  int32_t dtype;                 /* tk_dtype of the stored entries */
+  int64_t dims[TK_MAX_ORDER];    /* n_1 .. n_d, each >= 1 */
+  const void* data;              /* device pointer to prod(dims) entries */
+} tk_tensor;
+
+/* Fiber sample and Gaussian test matrix of one mode (or one tree node):
+ * the sampling matrix E_k of Section 3.1 and Omega_k of Algorithm 1. */
+typedef struct {
+  int64_t s;             /* number of sampled columns, ell <= s <= ncols */
+  int32_t ell;           /* sketch width r + p (>= 1) */
+  int32_t reserved;      /* must be 0 */
+  const int64_t* idx;    /* device [s]: strictly increasing column indices of the
+                            unfolding, each in [0, ncols); NULL = every column
+                            (then s must equal ncols: the dense R-HOSVD sketch) */
+  const void* omega;     /* device [s x ell] row-major, factor dtype */
+} tk_sketch;
+
+/* Balanced dimension tree (Section 4, dimension-tree definition), heap order,
+ * node 0 = root.  Every node covers the contiguous modes
+ * first_mode[t] .. first_mode[t] + num_modes[t] - 1; left/right are child
+ * node indices or -1 for a leaf, and the left child covers the first modes. */
+typedef struct {
+  int32_t num_nodes;
+  const int32_t* left;
+  const int32_t* right;
+  const int32_t* first_mode;
+  const int32_t* num_modes;
+} tk_tree;
+
+/* Range sketches of every mode in one call (Algorithm 1, fiber sampling and
+ * sketch steps; Section 3.1):  Y_k = X^(k) E_k  (n_k x s_k, the sampled mode-k
+ * fibers, gathered without forming any unfolding) and Z_k = Y_k Omega_k
+ * (n_k x ell_k).
+ *   X      tensor (any dtype).
+ *   sk     host array [order] of sketches, one per mode.
+ *   Z      host array [order] of device pointers, Z[k] is n_k x ell_k FP64,
+ *          row-major (accumulated in FP64 whatever the tensor dtype).
+ *   Y      NULL, or host array [order] of device pointers (entries may be
+ *          NULL): Y[k] receives Y_k (n_k x s_k, row-major, X's dtype), the
+ *          input of the W step of tucker_qr.
+ * Errors: TK_EINVAL for a bad descriptor, ell > s, s > ncols, a non-zero
+ * reserved field or NULL required pointers; TK_EWORKSPACE; TK_EDEVICE. */
+tk_status tucker_sketch_all_modes(const tk_tensor* X, const tk_sketch* sk, double* const* Z,
+                                  void* const* Y, void* ws, size_t* ws_bytes, void* stream);
+
+/* Thin QR of a batch of sketches and the rank truncation of Algorithm 1
+ * (orthonormal basis step, then W_k = dominant r_k left singular vectors of
+ * Q_k^T Y_k and U_k = Q_k W_k).  The QR is CholeskyQR2 with an FP64 Gram and
+ * FP64 Cholesky; when a pivot of the first Gram is not safely positive the
+ * first pass is shifted (shifted CholeskyQR3) and info[i] is set to 1.
+ * Q_i is unique up to rounding when Z_i has full column rank (R_ii > 0).
+ *   nmat     number of matrices.
+ *   m, ell   host arrays [nmat]: rows and columns of Z_i (ell_i <= m_i).
+ *   Z        host array [nmat] of device FP64 m_i x ell_i row-major, replaced
+ *            by Q_i.
+ *   Y        NULL (QR only) or host array [nmat] of device m_i x s_i row-major
+ *            matrices of dtype ydtype.
+ *   s, r     host arrays [nmat] (ignored when Y is NULL): columns of Y_i and
+ *            target rank r_i (1 <= r_i <= ell_i).
+ *   U        host array [nmat] of device m_i x r_i row-major outputs in
+ *            udtype (TK_F64 or TK_F32); each column's largest-magnitude entry
+ *            (first on ties) is made positive.  With r_i = ell_i the columns
+ *            of U_i span Range(Q_i).
+ *   info     device int32 [nmat] (may be NULL).
+ * Errors: TK_EINVAL, TK_EWORKSPACE, TK_EDEVICE. */
+tk_status tucker_qr(int32_t nmat, const int64_t* m, const int32_t* ell, double* const* Z,
+                    const void* const* Y, int32_t ydtype, const int64_t* s, const int32_t* r,
+                    void* const* U, int32_t udtype, int32_t* info, void* ws, size_t* ws_bytes,
+                    void* stream);
+
+/* Core projection (Algorithm 1, core step):  G = X x_1 F_1^T x_2 ... x_d F_d^T.
+ * The one full read of X.
+ *   F      host array [order] of device n_k x c_k row-major factors in the
+ *          factor dtype.
+ *   cols   host array [order]: c_k (1 <= c_k <= n_k).
+ *   G      device output c_1 x ... x c_d (C-order), factor dtype.
+ * Accumulation: FP64 for F64 tensors; FP32 MFMA with FP64 combination of
+ * partial sums for F32; BF16/F16 MFMA with FP32 accumulation for BF16/F16
+ * tensors (factors enter as a hi+lo pair).
+ * Errors: TK_EINVAL, TK_EWORKSPACE, TK_EDEVICE. */
+tk_status tucker_core(const tk_tensor* X, const void* const* F, const int32_t* cols, void* G,
+                      void* ws, size_t* ws_bytes, void* stream);
+
+/* Reconstruction X_hat = G x_1 F_1 x_2 ... x_d F_d (Tucker format, Section 3)
+ * and, fused with it, the squared residual against a reference tensor.
+ *   dims, order  size n_1..n_d of X_hat; G is c_1 x ... x c_d in the factor
+ *                dtype `fdtype`, F as in tucker_core.
+ *   Xref   NULL or the reference tensor (same dims; its dtype decides fdtype).
+ *   Xhat   NULL or a device output of prod(dims) entries in fdtype.
+ *   resid2 NULL or device double[2]: ||Xref - X_hat||_F^2 and ||Xref||_F^2,
+ *          accumulated in FP64 (requires Xref).
+ * At least one of Xhat and resid2 must be non-NULL.
+ * Errors: TK_EINVAL, TK_EWORKSPACE, TK_EDEVICE. */
+tk_status tucker_reconstruct(int32_t order, const int64_t* dims, int32_t fdtype, const void* G,
+                             const void* const* F, const int32_t* cols, const tk_tensor* Xref,
+                             void* Xhat, double* resid2, void* ws, size_t* ws_bytes,
+                             void* stream);
+
+/* Sub-R-RtL-HT (Algorithm 2) on a balanced dimension tree: for every non-root
+ * node S the sampled sketch Y_S = X^(S) E_S, Z_S = Y_S Omega_S, its QR and W
+ * step giving the explicit basis U_S (n_S x r_S); the transfer tensor
+ * B_S(i,j,k) = <U_S(:,i), U_Sl(:,j) kron U_Sr(:,k)> of every internal non-root
+ * node (transfer-tensor equation of Section 4); and the root transfer
+ * B_R(0,j,k) = <vec X, U_Rl(:,j) kron U_Rr(:,k)> (one full read of X).
+ *   X       tensor (F64 or F32).
+ *   tree    balanced tree over X's modes (num_nodes = 2 order - 1).
+ *   rank    host int32 [num_nodes]: r_S for every node (rank[0] is ignored;
+ *           the root rank is 1).
+ *   sk      host array [num_nodes] of sketches (sk[0] ignored).
+ *   U       host array [num_nodes] of device outputs, U[t] is n_S x r_S
+ *           row-major in the factor dtype (U[0] ignored).
+ *   B       host array [num_nodes] of device outputs, B[t] is r_t x r_l x r_r
+ *           (C-order) for internal nodes, 1 x r_l x r_r for the root, in the
+ *           factor dtype; entries for leaves are ignored.
+ *   info    device int32 [num_nodes] or NULL (as in tucker_qr, index = node).
+ * Errors: TK_EINVAL (also for a tree that is not the balanced heap tree of
+ * this order), TK_EWORKSPACE, TK_EDEVICE. */
+tk_status htucker_decompose(const tk_tensor* X, const tk_tree* tree, const int32_t* rank,
+                            const tk_sketch* sk, void* const* U, void* const* B, int32_t* info,
+                            void* ws, size_t* ws_bytes, void* stream);
+
+/* Vector-Jacobian product of the core projection G = X x_k F_k^T (the
+ * differentiation form of the method; follows from the TTM definition of
+ * Section 2.2): given Gbar (c_1 x .. x c_d),
+ *   Xbar  (+)= Gbar x_1 F_1 .. x_d F_d             (prod(dims), factor dtype)
+ *   Fbar_k (+)= (X x_{j!=k} F_j^T)^(k) (Gbar^(k))^T  (n_k x c_k, factor dtype)
+ * Xbar or Fbar (or individual Fbar[k]) may be NULL to skip them.  accumulate
+ * != 0 adds to the outputs instead of overwriting them.  X is recontracted,
+ * no unfolding is stored.  Errors: TK_EINVAL, TK_EWORKSPACE, TK_EDEVICE. */
+tk_status tucker_core_vjp(const tk_tensor* X, const void* const* F, const int32_t* cols,
+                          const void* Gbar, void* Xbar, void* const* Fbar, int32_t accumulate,
+                          void* ws, size_t* ws_bytes, void* stream);
+
+/* Vector-Jacobian product of the reconstruction X_hat = G x_k F_k: given
+ * H = dL/dX_hat (prod(dims), factor dtype),
+ *   Gbar   = H x_1 F_1^T .. x_d F_d^T                  (c_1 x .. x c_d)
+ *   Fbar_k = H^(k) ((G x_{j!=k} F_j)^(k))^T            (n_k x c_k)
+ * Gbar or Fbar may be NULL.  Errors as above. */
+tk_status tucker_reconstruct_vjp(int32_t order, const int64_t* dims, int32_t fdtype,
+                                 const void* G, const void* const* F, const int32_t* cols,
+                                 const void* H, void* Gbar, void* const* Fbar, void* ws,
+                                 size_t* ws_bytes, void* stream);
+
+/* Message for the calling thread's last non-OK status ("" if none). */
+const char* tk_last_error(void);
+
+/* Library version string. */
+const char* tk_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TKMI_H */

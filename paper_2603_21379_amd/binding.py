@@ -1,0 +1,279 @@
+"""ctypes binding of libtkmi.so: argument marshalling only.
+
+Every function here has the name of a C entry point (tkmi.h) and does
+nothing but turn torch tensors into device pointers, sizes and descriptor
+structs, allocate the workspace the library asks for, and raise on a non-OK
+status.  All arithmetic happens in the library's HIP kernels; there is no
+fallback path.  If the library is missing, `lib()` raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import threading
+
+import torch
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libtkmi.so")
+
+TK_F64, TK_F32, TK_BF16, TK_F16 = 0, 1, 2, 3
+TK_MAX_ORDER = 16
+STATUS = {0: "TK_OK", 1: "TK_EINVAL", 2: "TK_EWORKSPACE", 3: "TK_ENOTPD", 4: "TK_EDEVICE",
+          5: "TK_EUNSUPPORTED"}
+
+_DT = {torch.float64: TK_F64, torch.float32: TK_F32, torch.bfloat16: TK_BF16,
+       torch.float16: TK_F16}
+
+
+class TkTensor(C.Structure):
+    _fields_ = [("order", C.c_int32), ("dtype", C.c_int32),
+                ("dims", C.c_int64 * TK_MAX_ORDER), ("data", C.c_void_p)]
+
+
+class TkSketch(C.Structure):
+    _fields_ = [("s", C.c_int64), ("ell", C.c_int32), ("reserved", C.c_int32),
+                ("idx", C.c_void_p), ("omega", C.c_void_p)]
+
+
+class TkTree(C.Structure):
+    _fields_ = [("num_nodes", C.c_int32), ("left", C.POINTER(C.c_int32)),
+                ("right", C.POINTER(C.c_int32)), ("first_mode", C.POINTER(C.c_int32)),
+                ("num_modes", C.POINTER(C.c_int32))]
+
+
+class TkError(RuntimeError):
+    def __init__(self, fn, status, msg):
+        super().__init__(f"{fn}: {STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+_lib = None
+_lock = threading.Lock()
+
+EXPORTS = ("tucker_sketch_all_modes", "tucker_qr", "tucker_core", "tucker_reconstruct",
+           "htucker_decompose", "tucker_core_vjp", "tucker_reconstruct_vjp", "tk_last_error",
+           "tk_version")
+
+
+def lib():
+    """Load libtkmi.so (once).  Raises if it has not been built."""
+    global _lib
+    with _lock:
+        if _lib is None:
+            if not os.path.exists(LIB_PATH):
+                raise ImportError(f"{LIB_PATH} is missing: build it with "
+                                  "`python -m paper_2603_21379_amd.build`")
+            L = C.CDLL(LIB_PATH)
+            vp, pp = C.c_void_p, C.POINTER(C.c_void_p)
+            sz = C.POINTER(C.c_size_t)
+            i64p, i32p = C.POINTER(C.c_int64), C.POINTER(C.c_int32)
+            L.tk_last_error.restype = C.c_char_p
+            L.tk_version.restype = C.c_char_p
+            sig = {
+                "tucker_sketch_all_modes": [C.POINTER(TkTensor), C.POINTER(TkSketch), pp, pp, vp, sz, vp],
+                "tucker_qr": [C.c_int32, i64p, i32p, pp, pp, C.c_int32, i64p, i32p, pp, C.c_int32,
+                              vp, vp, sz, vp],
+                "tucker_core": [C.POINTER(TkTensor), pp, i32p, vp, vp, sz, vp],
+                "tucker_reconstruct": [C.c_int32, i64p, C.c_int32, vp, pp, i32p, C.POINTER(TkTensor),
+                                       vp, vp, vp, sz, vp],
+                "htucker_decompose": [C.POINTER(TkTensor), C.POINTER(TkTree), i32p, C.POINTER(TkSketch),
+                                      pp, pp, vp, vp, sz, vp],
+                "tucker_core_vjp": [C.POINTER(TkTensor), pp, i32p, vp, vp, pp, C.c_int32, vp, sz, vp],
+                "tucker_reconstruct_vjp": [C.c_int32, i64p, C.c_int32, vp, pp, i32p, vp, vp, pp, vp,
+                                           sz, vp],
+            }
+            for name, args in sig.items():
+                f = getattr(L, name)
+                f.argtypes = args
+                f.restype = C.c_int
+            _lib = L
+    return _lib
+
+
+# ------------------------------------------------------------------ helpers
+def dtype_code(t: torch.dtype) -> int:
+    if t not in _DT:
+        raise TypeError(f"unsupported dtype {t}")
+    return _DT[t]
+
+
+def factor_torch_dtype(t: torch.dtype) -> torch.dtype:
+    return torch.float64 if t == torch.float64 else torch.float32
+
+
+def ptr(t) -> int | None:
+    if t is None:
+        return None
+    return t.data_ptr()
+
+
+def tensor_desc(X: torch.Tensor) -> TkTensor:
+    if not X.is_contiguous():
+        raise ValueError("tensor must be contiguous (C-order)")
+    d = TkTensor()
+    d.order = X.dim()
+    d.dtype = dtype_code(X.dtype)
+    for k, n in enumerate(X.shape):
+        d.dims[k] = n
+    d.data = X.data_ptr()
+    return d
+
+
+def ptr_array(ts):
+    arr = (C.c_void_p * len(ts))()
+    for i, t in enumerate(ts):
+        arr[i] = None if t is None else t.data_ptr()
+    return arr
+
+
+def _stream(stream):
+    if stream is None:
+        return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    return C.c_void_p(getattr(stream, "cuda_stream", stream))
+
+
+def _check(name, status):
+    if status != 0:
+        raise TkError(name, status, lib().tk_last_error().decode())
+
+
+class _WS:
+    """Per-device workspace that grows on demand (device memory via torch)."""
+
+    def __init__(self):
+        self.buf = {}
+
+    def get(self, nbytes: int, device) -> torch.Tensor:
+        key = torch.device(device)
+        b = self.buf.get(key)
+        if b is None or b.numel() < nbytes:
+            b = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=key)
+            self.buf[key] = b
+        return b
+
+
+_ws = _WS()
+
+
+def _call(name, args_before_ws, device, stream, ws=None):
+    """Query the workspace size, provide it, then call.  `args_before_ws` is
+    everything up to (not including) the ws/ws_bytes/stream arguments."""
+    f = getattr(lib(), name)
+    n = C.c_size_t(0)
+    _check(name, f(*args_before_ws, None, C.byref(n), _stream(stream)))
+    need = n.value
+    buf = ws if ws is not None else _ws.get(need, device)
+    if buf.numel() < need:
+        raise ValueError(f"{name}: workspace of {buf.numel()} bytes < required {need}")
+    n2 = C.c_size_t(buf.numel())
+    _check(name, f(*args_before_ws, C.c_void_p(buf.data_ptr()), C.byref(n2), _stream(stream)))
+    return need
+
+
+def workspace_bytes(name, args_before_ws):
+    f = getattr(lib(), name)
+    n = C.c_size_t(0)
+    _check(name, f(*args_before_ws, None, C.byref(n), None))
+    return n.value
+
+
+def sketch_descs(sketches):
+    """sketches: list of (idx int64 tensor or None, omega tensor [s x ell])."""
+    arr = (TkSketch * len(sketches))()
+    for i, (idx, om) in enumerate(sketches):
+        arr[i].s = om.shape[0]
+        arr[i].ell = om.shape[1]
+        arr[i].reserved = 0
+        arr[i].idx = None if idx is None else idx.data_ptr()
+        arr[i].omega = om.data_ptr()
+    return arr
+
+
+# ------------------------------------------------------------------ entry points
+def tucker_sketch_all_modes(X, sketches, Z, Y=None, stream=None, ws=None):
+    xd = tensor_desc(X)
+    sk = sketch_descs(sketches)
+    args = [C.byref(xd), sk, ptr_array(Z), ptr_array(Y) if Y is not None else None]
+    return _call("tucker_sketch_all_modes", args, X.device, stream, ws)
+
+
+def tucker_qr(Z, Y=None, r=None, U=None, info=None, stream=None, ws=None):
+    n = len(Z)
+    m = (C.c_int64 * n)(*[z.shape[0] for z in Z])
+    ell = (C.c_int32 * n)(*[z.shape[1] for z in Z])
+    if Y is not None:
+        s = (C.c_int64 * n)(*[y.shape[1] for y in Y])
+        rr = (C.c_int32 * n)(*r)
+        ydt = dtype_code(Y[0].dtype)
+        udt = dtype_code(U[0].dtype)
+        args = [n, m, ell, ptr_array(Z), ptr_array(Y), ydt, s, rr, ptr_array(U), udt, ptr(info)]
+    else:
+        args = [n, m, ell, ptr_array(Z), None, 0, None, None, None, 0, ptr(info)]
+    dev = Z[0].device if n else torch.device("cuda")
+    return _call("tucker_qr", args, dev, stream, ws)
+
+
+def tucker_core(X, F, G, stream=None, ws=None):
+    xd = tensor_desc(X)
+    cols = (C.c_int32 * X.dim())(*[f.shape[1] for f in F])
+    args = [C.byref(xd), ptr_array(F), cols, G.data_ptr()]
+    return _call("tucker_core", args, X.device, stream, ws)
+
+
+def tucker_reconstruct(dims, G, F, Xref=None, Xhat=None, resid2=None, stream=None, ws=None):
+    d = len(dims)
+    dd = (C.c_int64 * d)(*dims)
+    cols = (C.c_int32 * d)(*[f.shape[1] for f in F])
+    xr = tensor_desc(Xref) if Xref is not None else None
+    args = [d, dd, dtype_code(G.dtype), G.data_ptr(), ptr_array(F), cols,
+            C.byref(xr) if xr is not None else None, ptr(Xhat), ptr(resid2)]
+    return _call("tucker_reconstruct", args, G.device, stream, ws)
+
+
+def tree_desc(tree):
+    n = tree.num_nodes
+    arrs = [(C.c_int32 * n)(*v) for v in (tree.left, tree.right, tree.first, tree.count)]
+    t = TkTree()
+    t.num_nodes = n
+    t.left, t.right, t.first_mode, t.num_modes = [C.cast(a, C.POINTER(C.c_int32)) for a in arrs]
+    t._keep = arrs
+    return t
+
+
+def htucker_decompose(X, tree, ranks, sketches, U, B, info=None, stream=None, ws=None):
+    """ranks/sketches/U/B: lists indexed by node (entry 0 = root; sketch/U for
+    the root and B for leaves are ignored and may be None)."""
+    xd = tensor_desc(X)
+    td = tree_desc(tree)
+    n = tree.num_nodes
+    rk = (C.c_int32 * n)(*[int(r) if r else 0 for r in ranks])
+    sk = (TkSketch * n)()
+    for t in range(1, n):
+        idx, om = sketches[t]
+        sk[t].s, sk[t].ell, sk[t].reserved = om.shape[0], om.shape[1], 0
+        sk[t].idx = None if idx is None else idx.data_ptr()
+        sk[t].omega = om.data_ptr()
+    args = [C.byref(xd), C.byref(td), rk, sk, ptr_array(U), ptr_array(B), ptr(info)]
+    return _call("htucker_decompose", args, X.device, stream, ws)
+
+
+def tucker_core_vjp(X, F, Gbar, Xbar=None, Fbar=None, accumulate=False, stream=None, ws=None):
+    xd = tensor_desc(X)
+    cols = (C.c_int32 * X.dim())(*[f.shape[1] for f in F])
+    args = [C.byref(xd), ptr_array(F), cols, Gbar.data_ptr(), ptr(Xbar),
+            ptr_array(Fbar) if Fbar is not None else None, int(bool(accumulate))]
+    return _call("tucker_core_vjp", args, X.device, stream, ws)
+
+
+def tucker_reconstruct_vjp(dims, G, F, H, Gbar=None, Fbar=None, stream=None, ws=None):
+    d = len(dims)
+    dd = (C.c_int64 * d)(*dims)
+    cols = (C.c_int32 * d)(*[f.shape[1] for f in F])
+    args = [d, dd, dtype_code(G.dtype), G.data_ptr(), ptr_array(F), cols, H.data_ptr(),
+            ptr(Gbar), ptr_array(Fbar) if Fbar is not None else None]
+    return _call("tucker_reconstruct_vjp", args, G.device, stream, ws)
+
+
+def version() -> str:
+    return lib().tk_version().decode()

@@ -1,0 +1,127 @@
+// Sampled range sketches of every mode (or tree node) in one launch.
+//
+// Fiber sampling (Section 3.1): column j of the unfolding X^(S) is the fiber
+// X[a, :, b] of X viewed as (A, n_S, B) with (a, b) = divmod(j, B); it is read
+// directly from the C-ordered tensor, no unfolding is formed.  Each block
+// gathers a 64-row x 32-column tile of Y_S = X^(S) E_S into LDS (optionally
+// writing it out for the W step) and multiplies it by the matching 32 rows
+// of Omega_S in FP64.  Per-chunk partial products go to the workspace and a
+// second kernel sums them in a fixed order, so Z_S = Y_S Omega_S is
+// deterministic.
+#include "tk_kernels.hpp"
+
+namespace tk {
+namespace {
+
+__device__ __forceinline__ int find_unit(const SketchBatch& b, int64_t blk) {
+  int u = 0;
+  while (u + 1 < b.count && b.u[u + 1].block_begin <= blk) ++u;
+  return u;
+}
+
+template <typename TX, typename TO>
+__global__ __launch_bounds__(256) void sketch_gather_kernel(const SketchBatch b) {
+  __shared__ double sY[kSketchRows][kSketchCols + 1];
+  __shared__ double sO[kSketchCols][64 + 1];
+  const int64_t blk = blockIdx.x;
+  const SketchUnit& U = b.u[find_unit(b, blk)];
+  const int64_t lb = blk - U.block_begin;
+  const int64_t chunk = lb / U.rowblocks;
+  const int64_t rb = lb - chunk * U.rowblocks;
+  const int64_t i0 = rb * kSketchRows, t0 = chunk * kSketchCols;
+  const TX* X = static_cast<const TX*>(U.X);
+  TX* Y = static_cast<TX*>(U.Y);
+  const int tid = threadIdx.x;
+  const bool rows_fast = (U.B == 1);  // fibers contiguous: walk along the fiber
+
+  for (int e = tid; e < kSketchRows * kSketchCols; e += blockDim.x) {
+    int i, t;
+    if (rows_fast) { i = e % kSketchRows; t = e / kSketchRows; }
+    else { t = e % kSketchCols; i = e / kSketchCols; }
+    const int64_t gi = i0 + i, gt = t0 + t;
+    double v = 0.0;
+    if (gi < U.n && gt < U.s) {
+      const int64_t j = U.idx ? U.idx[gt] : gt;
+      if (j >= 0 && j < U.A * U.B) {  // a column index outside the unfolding reads nothing
+        const int64_t a = j / U.B;
+        const int64_t bb = j - a * U.B;
+        const TX x = X[(a * U.n + gi) * U.B + bb];
+        v = to_double(x);
+        if (Y) Y[gi * U.s + gt] = x;
+      } else {
+        v = __builtin_nan("");
+      }
+    }
+    sY[i][t] = v;
+  }
+  const TO* Om = static_cast<const TO*>(U.omega);
+  const int row = tid >> 2, lane4 = tid & 3;
+  for (int e0 = 0; e0 < U.ell; e0 += 64) {
+    __syncthreads();
+    for (int e = tid; e < kSketchCols * 64; e += blockDim.x) {
+      const int t = e >> 6, jj = e & 63;
+      const int64_t gt = t0 + t;
+      sO[t][jj] = (gt < U.s && e0 + jj < U.ell) ? to_double(Om[gt * U.ell + e0 + jj]) : 0.0;
+    }
+    __syncthreads();
+    double acc[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) acc[q] = 0.0;
+    for (int t = 0; t < kSketchCols; ++t) {
+      const double y = sY[row][t];
+#pragma unroll
+      for (int q = 0; q < 16; ++q) acc[q] = fma(y, sO[t][lane4 + 4 * q], acc[q]);
+    }
+    const int64_t gi = i0 + row;
+    if (gi < U.n) {
+#pragma unroll
+      for (int q = 0; q < 16; ++q) {
+        const int jj = e0 + lane4 + 4 * q;
+        if (jj < U.ell) U.partial[(chunk * U.n + gi) * U.ell + jj] = acc[q];
+      }
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void sketch_reduce_kernel(const SketchBatch b) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= b.total_out) return;
+  int64_t base = 0;
+  int u = 0;
+  for (; u < b.count; ++u) {
+    const int64_t cnt = b.u[u].n * b.u[u].ell;
+    if (g < base + cnt) break;
+    base += cnt;
+  }
+  const SketchUnit& U = b.u[u];
+  const int64_t e = g - base;
+  const int64_t plane = U.n * U.ell;
+  double acc = 0.0;
+  for (int c = 0; c < U.nchunks; ++c) acc += U.partial[c * plane + e];
+  U.Z[e] = acc;
+}
+
+template <typename TX, typename TO>
+hipError_t run(const SketchBatch& b, hipStream_t st) {
+  if (b.total_blocks > 0)
+    hipLaunchKernelGGL((sketch_gather_kernel<TX, TO>), dim3((unsigned)b.total_blocks), dim3(256), 0,
+                       st, b);
+  if (b.total_out > 0)
+    hipLaunchKernelGGL(sketch_reduce_kernel, dim3((unsigned)ceil_div(b.total_out, 256)), dim3(256),
+                       0, st, b);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_sketch(int dtype, const SketchBatch& b, hipStream_t st) {
+  switch (dtype) {
+    case TK_F64: return run<double, double>(b, st);
+    case TK_F32: return run<float, float>(b, st);
+    case TK_BF16: return run<bf16, float>(b, st);
+    case TK_F16: return run<f16, float>(b, st);
+  }
+  return hipErrorInvalidValue;
+}
+
+}  // namespace tk

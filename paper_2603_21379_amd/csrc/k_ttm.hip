@@ -1,0 +1,301 @@
+// Generic mode products (the TTM of Section 2.2) used by the core projection,
+// the reconstruction and their VJPs for any order, sizes and dtypes:
+//
+//   out[a][p][b] = sum_q in[a][q][b] * M[p][q]
+//
+// over a tensor viewed as (A, Q, B).  A contraction with F^T takes
+// M[p][q] = F[q][p]; an expansion with F takes M[p][q] = F[p][q].  All
+// arithmetic is FP64 (FP64 and non-packed FP32 FMA have the same rate on
+// CDNA4), with the output rounded to its storage type.
+//
+// Two layouts: B == 1 (the contracted mode is the contiguous one) stages a
+// 64-row x 64-column tile of `in` through LDS so the loads are coalesced;
+// B > 1 maps consecutive threads to consecutive b so every load of a fixed q
+// is coalesced.  The last expansion of a reconstruction is fused with the
+// squared residual against the reference tensor (FP64 partial sums per
+// block, then a fixed-order final sum).
+#include "tk_kernels.hpp"
+
+namespace tk {
+namespace {
+
+template <typename T> __device__ __forceinline__ double ld(const void* p, int64_t i) {
+  return to_double(static_cast<const T*>(p)[i]);
+}
+
+template <typename TIn, typename TOut, typename TM, int PMAX>
+__global__ __launch_bounds__(256) void mode_rows_kernel(const ModeProduct mp) {
+  // B == 1: out[a][p] = sum_q in[a][q] M[p][q]
+  __shared__ double sX[64][65];
+  __shared__ double sM[64][PMAX + 1];
+  const int tid = threadIdx.x;
+  const int row = tid & 63, pg = tid >> 6;  // 4 p-groups
+  constexpr int PK = PMAX / 4;
+  const int64_t a0 = (int64_t)blockIdx.x * 64;
+  const int p0 = blockIdx.y * PMAX;  // this block's slice of output columns
+  const int rows = (int)min<int64_t>(64, mp.A - a0);
+  const TIn* in = static_cast<const TIn*>(mp.in);
+  const TM* M = static_cast<const TM*>(mp.M);
+  double acc[PK];
+#pragma unroll
+  for (int k = 0; k < PK; ++k) acc[k] = 0.0;
+  for (int64_t q0 = 0; q0 < mp.Q; q0 += 64) {
+    const int qn = (int)min<int64_t>(64, mp.Q - q0);
+    __syncthreads();
+    for (int e = tid; e < 64 * 64; e += 256) {
+      const int rr = e >> 6, qq = e & 63;
+      sX[rr][qq] = (rr < rows && qq < qn) ? to_double(in[(a0 + rr) * mp.Q + q0 + qq]) : 0.0;
+    }
+    for (int e = tid; e < 64 * PMAX; e += 256) {
+      const int qq = e / PMAX, p = e - qq * PMAX;
+      sM[qq][p] = (qq < qn && p0 + p < mp.P)
+                      ? to_double(M[(int64_t)(p0 + p) * mp.rs + (q0 + qq) * mp.cs]) : 0.0;
+    }
+    __syncthreads();
+    for (int qq = 0; qq < qn; ++qq) {
+      const double x = sX[row][qq];
+#pragma unroll
+      for (int k = 0; k < PK; ++k) acc[k] = fma(x, sM[qq][pg + 4 * k], acc[k]);
+    }
+  }
+  if (row < rows) {
+    TOut* out = static_cast<TOut*>(mp.out);
+#pragma unroll
+    for (int k = 0; k < PK; ++k) {
+      const int p = p0 + pg + 4 * k;
+      if (p < mp.P) {
+        const int64_t o = (a0 + row) * mp.P + p;
+        double v = acc[k];
+        if (mp.accumulate) v += to_double(out[o]);
+        out[o] = from_double<TOut>(v);
+      }
+    }
+  }
+}
+
+template <typename TIn, typename TOut, typename TM, int PMAX>
+__global__ __launch_bounds__(256) void mode_strided_kernel(const ModeProduct mp) {
+  // out[a][p][b] = sum_q in[a][q][b] M[p][q]; one (a, b) per thread
+  __shared__ double sM[64][PMAX + 1];
+  const int tid = threadIdx.x;
+  const int64_t g = (int64_t)blockIdx.x * 256 + tid;
+  const bool live = g < mp.A * mp.B;
+  const int64_t a = live ? g / mp.B : 0;
+  const int64_t bb = live ? g - a * mp.B : 0;
+  const int p0 = blockIdx.y * PMAX;  // this block's slice of output columns
+  const TIn* in = static_cast<const TIn*>(mp.in);
+  const TM* M = static_cast<const TM*>(mp.M);
+  double acc[PMAX];
+#pragma unroll
+  for (int k = 0; k < PMAX; ++k) acc[k] = 0.0;
+  for (int64_t q0 = 0; q0 < mp.Q; q0 += 64) {
+    const int qn = (int)min<int64_t>(64, mp.Q - q0);
+    __syncthreads();
+    for (int e = tid; e < 64 * PMAX; e += 256) {
+      const int qq = e / PMAX, p = e - qq * PMAX;
+      sM[qq][p] = (qq < qn && p0 + p < mp.P)
+                      ? to_double(M[(int64_t)(p0 + p) * mp.rs + (q0 + qq) * mp.cs]) : 0.0;
+    }
+    __syncthreads();
+    if (live) {
+      for (int qq = 0; qq < qn; ++qq) {
+        const double x = to_double(in[(a * mp.Q + q0 + qq) * mp.B + bb]);
+#pragma unroll
+        for (int k = 0; k < PMAX; ++k) acc[k] = fma(x, sM[qq][k], acc[k]);
+      }
+    }
+  }
+  if (live) {
+    TOut* out = static_cast<TOut*>(mp.out);
+#pragma unroll
+    for (int k = 0; k < PMAX; ++k) {
+      if (p0 + k < mp.P) {
+        const int64_t o = (a * mp.P + p0 + k) * mp.B + bb;
+        double v = acc[k];
+        if (mp.accumulate) v += to_double(out[o]);
+        out[o] = from_double<TOut>(v);
+      }
+    }
+  }
+}
+
+template <typename TIn, typename TOut, typename TM>
+hipError_t mode_product(const ModeProduct& mp, hipStream_t st) {
+  if (mp.A == 0 || mp.B == 0) return hipSuccess;
+  if (mp.P < 1) return hipSuccess;
+  const bool narrow = mp.P <= 16;
+  const unsigned pchunks = (unsigned)ceil_div(mp.P, narrow ? 16 : 64);
+  if (mp.B == 1) {
+    const dim3 grid((unsigned)ceil_div(mp.A, 64), pchunks);
+    if (narrow)
+      hipLaunchKernelGGL((mode_rows_kernel<TIn, TOut, TM, 16>), grid, dim3(256), 0, st, mp);
+    else
+      hipLaunchKernelGGL((mode_rows_kernel<TIn, TOut, TM, 64>), grid, dim3(256), 0, st, mp);
+  } else {
+    const dim3 grid((unsigned)ceil_div(mp.A * mp.B, 256), pchunks);
+    if (narrow)
+      hipLaunchKernelGGL((mode_strided_kernel<TIn, TOut, TM, 16>), grid, dim3(256), 0, st, mp);
+    else
+      hipLaunchKernelGGL((mode_strided_kernel<TIn, TOut, TM, 64>), grid, dim3(256), 0, st, mp);
+  }
+  return hipGetLastError();
+}
+
+template <typename TIn, typename TM>
+hipError_t by_out(const ModeProduct& mp, int out_dt, hipStream_t st) {
+  return out_dt == TK_F64 ? mode_product<TIn, double, TM>(mp, st)
+                          : mode_product<TIn, float, TM>(mp, st);
+}
+template <typename TM>
+hipError_t by_in(const ModeProduct& mp, int in_dt, int out_dt, hipStream_t st) {
+  switch (in_dt) {
+    case TK_F64: return by_out<double, TM>(mp, out_dt, st);
+    case TK_F32: return by_out<float, TM>(mp, out_dt, st);
+    case TK_BF16: return by_out<bf16, TM>(mp, out_dt, st);
+    case TK_F16: return by_out<f16, TM>(mp, out_dt, st);
+  }
+  return hipErrorInvalidValue;
+}
+
+// ------------------------------------------------------------------ fused residual
+constexpr int kResidBlocks = 2048;
+
+template <typename TX, typename TF>
+__global__ __launch_bounds__(256) void expand_residual_kernel(const ExpandResidual e) {
+  __shared__ double red[2][256];
+  const int tid = threadIdx.x;
+  const int64_t total = e.A * e.n;
+  const TF* F = static_cast<const TF*>(e.F);
+  const TX* X = static_cast<const TX*>(e.X);
+  TF* Xh = static_cast<TF*>(e.Xhat);
+  double r2 = 0.0, x2 = 0.0;
+  for (int64_t g = (int64_t)blockIdx.x * 256 + tid; g < total; g += (int64_t)gridDim.x * 256) {
+    const int64_t a = g / e.n, i = g - a * e.n;
+    const double* t = e.T + a * e.c;
+    const TF* f = F + i * e.c;
+    double v = 0.0;
+    for (int j = 0; j < e.c; ++j) v = fma(t[j], to_double(f[j]), v);
+    if (Xh) Xh[g] = from_double<TF>(v);
+    if (X) {
+      const double x = to_double(X[g]);
+      const double d = x - v;
+      r2 = fma(d, d, r2);
+      x2 = fma(x, x, x2);
+    }
+  }
+  if (!e.partials) return;
+  red[0][tid] = r2;
+  red[1][tid] = x2;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (tid < s) {
+      red[0][tid] += red[0][tid + s];
+      red[1][tid] += red[1][tid + s];
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    e.partials[2 * blockIdx.x] = red[0][0];
+    e.partials[2 * blockIdx.x + 1] = red[1][0];
+  }
+}
+
+__global__ __launch_bounds__(256) void final_sum_kernel(const double* partials, int nblocks,
+                                                        double* out) {
+  __shared__ double red[2][256];
+  const int tid = threadIdx.x;
+  double a = 0.0, b = 0.0;
+  for (int i = tid; i < nblocks; i += 256) {
+    a += partials[2 * i];
+    b += partials[2 * i + 1];
+  }
+  red[0][tid] = a;
+  red[1][tid] = b;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (tid < s) {
+      red[0][tid] += red[0][tid + s];
+      red[1][tid] += red[1][tid + s];
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    out[0] = red[0][0];
+    out[1] = red[1][0];
+  }
+}
+
+template <typename TX, typename TF>
+hipError_t expand_residual(const ExpandResidual& e, hipStream_t st) {
+  const int nb = (int)expand_residual_blocks(e.A * e.n);
+  hipLaunchKernelGGL((expand_residual_kernel<TX, TF>), dim3(nb), dim3(256), 0, st, e);
+  if (e.partials && e.resid2)
+    hipLaunchKernelGGL(final_sum_kernel, dim3(1), dim3(256), 0, st, e.partials, nb, e.resid2);
+  return hipGetLastError();
+}
+
+template <typename TF>
+hipError_t er_by_x(const ExpandResidual& e, int x_dt, hipStream_t st) {
+  switch (x_dt) {
+    case TK_F64: return expand_residual<double, TF>(e, st);
+    case TK_F32: return expand_residual<float, TF>(e, st);
+    case TK_BF16: return expand_residual<bf16, TF>(e, st);
+    case TK_F16: return expand_residual<f16, TF>(e, st);
+  }
+  return hipErrorInvalidValue;
+}
+
+template <typename TO>
+__global__ void convert_kernel(const double* in, TO* out, int64_t n) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g < n) out[g] = from_double<TO>(in[g]);
+}
+
+template <typename TI>
+__global__ void to_f64_kernel(const TI* in, double* out, int64_t n) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g < n) out[g] = to_double(in[g]);
+}
+
+}  // namespace
+
+int64_t expand_residual_blocks(int64_t total) {
+  return std::max<int64_t>(1, std::min<int64_t>(kResidBlocks, ceil_div(total, 256)));
+}
+
+hipError_t launch_mode_product(const ModeProduct& mp, int in_dt, int out_dt, int m_dt,
+                               hipStream_t st) {
+  return m_dt == TK_F64 ? by_in<double>(mp, in_dt, out_dt, st) : by_in<float>(mp, in_dt, out_dt, st);
+}
+
+hipError_t launch_expand_residual(const ExpandResidual& e, int x_dt, int f_dt, hipStream_t st) {
+  if (e.A * e.n == 0) return hipSuccess;
+  return f_dt == TK_F64 ? er_by_x<double>(e, x_dt, st) : er_by_x<float>(e, x_dt, st);
+}
+
+hipError_t launch_convert(const double* in, void* out, int out_dt, int64_t n, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  const dim3 grid((unsigned)ceil_div(n, 256));
+  if (out_dt == TK_F64)
+    hipLaunchKernelGGL((convert_kernel<double>), grid, dim3(256), 0, st, in,
+                       static_cast<double*>(out), n);
+  else
+    hipLaunchKernelGGL((convert_kernel<float>), grid, dim3(256), 0, st, in,
+                       static_cast<float*>(out), n);
+  return hipGetLastError();
+}
+
+hipError_t launch_to_f64(const void* in, int in_dt, double* out, int64_t n, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  const dim3 grid((unsigned)ceil_div(n, 256));
+  switch (in_dt) {
+    case TK_F64: hipLaunchKernelGGL((to_f64_kernel<double>), grid, dim3(256), 0, st, static_cast<const double*>(in), out, n); break;
+    case TK_F32: hipLaunchKernelGGL((to_f64_kernel<float>), grid, dim3(256), 0, st, static_cast<const float*>(in), out, n); break;
+    case TK_BF16: hipLaunchKernelGGL((to_f64_kernel<bf16>), grid, dim3(256), 0, st, static_cast<const bf16*>(in), out, n); break;
+    case TK_F16: hipLaunchKernelGGL((to_f64_kernel<f16>), grid, dim3(256), 0, st, static_cast<const f16*>(in), out, n); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace tk

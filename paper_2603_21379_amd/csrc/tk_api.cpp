@@ -1,0 +1,556 @@
+// Host layer of libtkmi: argument validation, workspace planning and the
+// orchestration of the kernels behind the C ABI declared in tkmi.h.
+//
+// Every entry point validates all arguments before touching the device, so
+// a failing call has no side effects, and a call with ws == NULL only
+// reports the workspace size.
+#include <stdarg.h>
+#include <stdio.h>
+
+#include <algorithm>
+#include <string>
+#include <vector>
+
+#include "tk_kernels.hpp"
+
+namespace tk {
+
+static thread_local std::string g_last_error;
+
+tk_status set_error(tk_status s, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return s;
+}
+void clear_error() { g_last_error.clear(); }
+
+namespace {
+
+bool valid_dtype(int dt) { return dt == TK_F64 || dt == TK_F32 || dt == TK_BF16 || dt == TK_F16; }
+
+tk_status check_tensor(const tk_tensor* X, const char* name, int64_t* N) {
+  if (!X) return set_error(TK_EINVAL, "%s: tensor descriptor is NULL", name);
+  if (X->order < 1 || X->order > TK_MAX_ORDER)
+    return set_error(TK_EINVAL, "%s: order %d outside [1, %d]", name, X->order, TK_MAX_ORDER);
+  if (!valid_dtype(X->dtype)) return set_error(TK_EINVAL, "%s: unknown dtype %d", name, X->dtype);
+  if (!X->data) return set_error(TK_EINVAL, "%s: data pointer is NULL", name);
+  int64_t n = 1;
+  for (int k = 0; k < X->order; ++k) {
+    if (X->dims[k] < 1) return set_error(TK_EINVAL, "%s: dims[%d] = %lld < 1", name, k, (long long)X->dims[k]);
+    if (n > INT64_MAX / X->dims[k]) return set_error(TK_EINVAL, "%s: element count overflows", name);
+    n *= X->dims[k];
+  }
+  *N = n;
+  return TK_OK;
+}
+
+int64_t prod(const int64_t* d, int lo, int hi) {
+  int64_t p = 1;
+  for (int k = lo; k < hi; ++k) p *= d[k];
+  return p;
+}
+
+tk_status check_sketch(const tk_sketch& s, int64_t nrows, int64_t ncols, const char* what, int k) {
+  if (s.reserved != 0) return set_error(TK_EINVAL, "%s %d: reserved field must be 0", what, k);
+  if (s.ell < 1 || s.ell > kMaxEll)
+    return set_error(s.ell > kMaxEll ? TK_EUNSUPPORTED : TK_EINVAL,
+                     "%s %d: ell = %d outside [1, %d]", what, k, s.ell, kMaxEll);
+  if (s.ell > nrows) return set_error(TK_EINVAL, "%s %d: ell = %d exceeds the %lld rows", what, k, s.ell, (long long)nrows);
+  if (s.s < s.ell || s.s > ncols)
+    return set_error(TK_EINVAL, "%s %d: s = %lld outside [ell = %d, ncols = %lld]", what, k,
+                     (long long)s.s, s.ell, (long long)ncols);
+  if (!s.idx && s.s != ncols)
+    return set_error(TK_EINVAL, "%s %d: idx is NULL (every column) but s = %lld != %lld", what, k,
+                     (long long)s.s, (long long)ncols);
+  if (!s.omega) return set_error(TK_EINVAL, "%s %d: omega is NULL", what, k);
+  return TK_OK;
+}
+
+// Fill one sketch unit and reserve its partial buffer.
+void plan_unit(Workspace& ws, SketchUnit& u, const void* X, int64_t A, int64_t n, int64_t B,
+               const tk_sketch& s, double* Z, void* Y, int64_t& blocks, int64_t& outs) {
+  u = SketchUnit{};
+  u.X = X;
+  u.A = A;
+  u.n = n;
+  u.B = B;
+  u.s = s.s;
+  u.idx = s.idx;
+  u.omega = s.omega;
+  u.ell = s.ell;
+  u.nchunks = (int32_t)ceil_div(s.s, kSketchCols);
+  u.rowblocks = (int32_t)ceil_div(n, kSketchRows);
+  u.partial = ws.take<double>((size_t)u.nchunks * n * s.ell);
+  u.Z = Z;
+  u.Y = Y;
+  u.block_begin = blocks;
+  blocks += (int64_t)u.nchunks * u.rowblocks;
+  outs += n * s.ell;
+}
+
+// Plan the QR (+ W step) workspace of one matrix.
+void plan_qr(Workspace& ws, QRMat& q, double* Z, int64_t m, int ell, const void* Y, int64_t s,
+             int r, void* U, int32_t* info) {
+  q = QRMat{};
+  q.Z = Z;
+  q.Y = Y;
+  q.U = U;
+  q.info = info;
+  q.m = m;
+  q.s = Y ? s : 0;
+  q.ell = ell;
+  q.r = Y ? r : 0;
+  q.nrc = (int32_t)ceil_div(m, kQRRowChunk);
+  q.ncc = Y ? (int32_t)ceil_div(s, kQRColChunk) : 0;
+  q.nrb = (int32_t)ceil_div(m, kQRRowBlock);
+  q.gpart = ws.take<double>((size_t)q.nrc * ell * ell);
+  q.R = ws.take<double>((size_t)ell * ell);
+  q.shifted = ws.take<int32_t>(1);
+  if (Y) {
+    q.mpart = ws.take<double>((size_t)q.nrc * ell * s);
+    q.cpart = ws.take<double>((size_t)q.ncc * ell * ell);
+    q.W = ws.take<double>((size_t)ell * r);
+    q.utmp = ws.take<double>((size_t)m * r);
+    q.amax_v = ws.take<double>((size_t)q.nrb * r);
+    q.amax_i = ws.take<int64_t>((size_t)q.nrb * r);
+  }
+}
+
+tk_status run_qr(std::vector<QRMat>& mats, int ydtype, int udtype, bool wstep, hipStream_t st) {
+  for (size_t g = 0; g < mats.size(); g += kQRMaxBatch) {
+    QRBatch b{};
+    b.count = (int32_t)std::min<size_t>(kQRMaxBatch, mats.size() - g);
+    for (int i = 0; i < b.count; ++i) b.m[i] = mats[g + i];
+    TK_HIP(launch_cholqr(b, st));
+    if (wstep) TK_HIP(launch_wstep(b, ydtype, udtype, st));
+  }
+  return TK_OK;
+}
+
+tk_status check_factors(int order, const int64_t* dims, const void* const* F, const int32_t* cols,
+                        const char* who) {
+  if (!F) return set_error(TK_EINVAL, "%s: factor array is NULL", who);
+  if (!cols) return set_error(TK_EINVAL, "%s: cols array is NULL", who);
+  for (int k = 0; k < order; ++k) {
+    if (!F[k]) return set_error(TK_EINVAL, "%s: F[%d] is NULL", who, k);
+    if (cols[k] < 1 || cols[k] > dims[k])
+      return set_error(TK_EINVAL, "%s: cols[%d] = %d outside [1, n_k = %lld]", who, k, cols[k],
+                       (long long)dims[k]);
+    if (cols[k] > kMaxCols)
+      return set_error(TK_EUNSUPPORTED, "%s: cols[%d] = %d exceeds %d", who, k, cols[k], kMaxCols);
+  }
+  return TK_OK;
+}
+
+// Chain of contractions G = X x_k F_k^T, last mode first.  Intermediates are FP64.
+struct CorePlan {
+  double* buf[2] = {nullptr, nullptr};
+};
+
+tk_status plan_core(Workspace& ws, int order, const int64_t* dims, const int32_t* cols,
+                    CorePlan& p) {
+  int64_t shape[TK_MAX_ORDER];
+  for (int k = 0; k < order; ++k) shape[k] = dims[k];
+  int64_t mx = 0;
+  for (int k = order - 1; k >= 1; --k) {
+    shape[k] = cols[k];
+    mx = std::max(mx, prod(shape, 0, order));
+  }
+  p.buf[0] = ws.take<double>((size_t)mx);
+  p.buf[1] = ws.take<double>((size_t)mx);
+  return TK_OK;
+}
+
+tk_status run_core(const void* X, int xdt, int order, const int64_t* dims,
+                   const void* const* F, const int32_t* cols, void* G, int fdt, const CorePlan& p,
+                   hipStream_t st) {
+  int64_t shape[TK_MAX_ORDER];
+  for (int k = 0; k < order; ++k) shape[k] = dims[k];
+  const void* cur = X;
+  int cur_dt = xdt;
+  for (int k = order - 1; k >= 0; --k) {
+    ModeProduct mp{};
+    mp.in = cur;
+    mp.A = prod(shape, 0, k);
+    mp.Q = shape[k];
+    mp.B = prod(shape, k + 1, order);
+    mp.P = cols[k];
+    mp.M = F[k];
+    mp.rs = 1;          // M[p][q] = F[q][p]
+    mp.cs = cols[k];
+    void* out = k == 0 ? G : (void*)p.buf[(order - 1 - k) & 1];
+    mp.out = out;
+    TK_HIP(launch_mode_product(mp, cur_dt, k == 0 ? fdt : TK_F64, fdt, st));
+    shape[k] = cols[k];
+    cur = out;
+    cur_dt = TK_F64;
+  }
+  return TK_OK;
+}
+
+hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
+}  // namespace
+}  // namespace tk
+
+using namespace tk;
+
+extern "C" {
+
+const char* tk_last_error(void) { return g_last_error.c_str(); }
+const char* tk_version(void) { return "tkmi 0.1 (gfx950)"; }
+
+tk_status tucker_sketch_all_modes(const tk_tensor* X, const tk_sketch* sk, double* const* Z,
+                                  void* const* Y, void* ws, size_t* ws_bytes, void* stream) {
+  clear_error();
+  int64_t N;
+  if (tk_status s = check_tensor(X, "tucker_sketch_all_modes", &N)) return s;
+  if (!sk || !Z) return set_error(TK_EINVAL, "tucker_sketch_all_modes: sk or Z is NULL");
+  if (!ws_bytes) return set_error(TK_EINVAL, "tucker_sketch_all_modes: ws_bytes is NULL");
+  const int d = X->order;
+  for (int k = 0; k < d; ++k) {
+    if (tk_status s = check_sketch(sk[k], X->dims[k], N / X->dims[k], "mode", k)) return s;
+    if (!Z[k]) return set_error(TK_EINVAL, "tucker_sketch_all_modes: Z[%d] is NULL", k);
+  }
+  Workspace w;
+  w.base = static_cast<char*>(ws);
+  SketchBatch b{};
+  b.count = d;
+  for (int k = 0; k < d; ++k)
+    plan_unit(w, b.u[k], X->data, prod(X->dims, 0, k), X->dims[k], prod(X->dims, k + 1, d), sk[k],
+              Z[k], Y ? Y[k] : nullptr, b.total_blocks, b.total_out);
+  if (!ws) {
+    *ws_bytes = w.off;
+    return TK_OK;
+  }
+  if (*ws_bytes < w.off)
+    return set_error(TK_EWORKSPACE, "tucker_sketch_all_modes: workspace %zu < required %zu",
+                     *ws_bytes, w.off);
+  TK_HIP(launch_sketch(X->dtype, b, as_stream(stream)));
+  return TK_OK;
+}
+
+tk_status tucker_qr(int32_t nmat, const int64_t* m, const int32_t* ell, double* const* Z,
+                    const void* const* Y, int32_t ydtype, const int64_t* s, const int32_t* r,
+                    void* const* U, int32_t udtype, int32_t* info, void* ws, size_t* ws_bytes,
+                    void* stream) {
+  clear_error();
+  if (nmat < 0) return set_error(TK_EINVAL, "tucker_qr: nmat < 0");
+  if (!ws_bytes) return set_error(TK_EINVAL, "tucker_qr: ws_bytes is NULL");
+  if (nmat > 0 && (!m || !ell || !Z)) return set_error(TK_EINVAL, "tucker_qr: m, ell or Z is NULL");
+  if (Y) {
+    if (!valid_dtype(ydtype)) return set_error(TK_EINVAL, "tucker_qr: unknown ydtype %d", ydtype);
+    if (udtype != TK_F64 && udtype != TK_F32)
+      return set_error(TK_EINVAL, "tucker_qr: udtype must be TK_F64 or TK_F32");
+    if (nmat > 0 && (!s || !r || !U)) return set_error(TK_EINVAL, "tucker_qr: s, r or U is NULL");
+  }
+  for (int i = 0; i < nmat; ++i) {
+    if (m[i] < 1) return set_error(TK_EINVAL, "tucker_qr: m[%d] < 1", i);
+    if (ell[i] < 1 || ell[i] > m[i])
+      return set_error(TK_EINVAL, "tucker_qr: ell[%d] = %d outside [1, m = %lld]", i, ell[i], (long long)m[i]);
+    if (ell[i] > kMaxEll) return set_error(TK_EUNSUPPORTED, "tucker_qr: ell[%d] = %d > %d", i, ell[i], kMaxEll);
+    if (!Z[i]) return set_error(TK_EINVAL, "tucker_qr: Z[%d] is NULL", i);
+    if (Y) {
+      if (!Y[i] || !U[i]) return set_error(TK_EINVAL, "tucker_qr: Y[%d] or U[%d] is NULL", i, i);
+      if (s[i] < 1) return set_error(TK_EINVAL, "tucker_qr: s[%d] < 1", i);
+      if (r[i] < 1 || r[i] > ell[i])
+        return set_error(TK_EINVAL, "tucker_qr: r[%d] = %d outside [1, ell = %d]", i, r[i], ell[i]);
+    }
+  }
+  Workspace w;
+  w.base = static_cast<char*>(ws);
+  std::vector<QRMat> mats(nmat);
+  for (int i = 0; i < nmat; ++i)
+    plan_qr(w, mats[i], Z[i], m[i], ell[i], Y ? Y[i] : nullptr, Y ? s[i] : 0, Y ? r[i] : 0,
+            Y ? U[i] : nullptr, info ? info + i : nullptr);
+  if (!ws) {
+    *ws_bytes = w.off;
+    return TK_OK;
+  }
+  if (*ws_bytes < w.off)
+    return set_error(TK_EWORKSPACE, "tucker_qr: workspace %zu < required %zu", *ws_bytes, w.off);
+  return run_qr(mats, ydtype, udtype, Y != nullptr, as_stream(stream));
+}
+
+tk_status tucker_core(const tk_tensor* X, const void* const* F, const int32_t* cols, void* G,
+                      void* ws, size_t* ws_bytes, void* stream) {
+  clear_error();
+  int64_t N;
+  if (tk_status s = check_tensor(X, "tucker_core", &N)) return s;
+  if (tk_status s = check_factors(X->order, X->dims, F, cols, "tucker_core")) return s;
+  if (!G) return set_error(TK_EINVAL, "tucker_core: G is NULL");
+  if (!ws_bytes) return set_error(TK_EINVAL, "tucker_core: ws_bytes is NULL");
+  Workspace w;
+  w.base = static_cast<char*>(ws);
+  CorePlan p;
+  plan_core(w, X->order, X->dims, cols, p);
+  if (!ws) {
+    *ws_bytes = w.off;
+    return TK_OK;
+  }
+  if (*ws_bytes < w.off)
+    return set_error(TK_EWORKSPACE, "tucker_core: workspace %zu < required %zu", *ws_bytes, w.off);
+  return run_core(X->data, X->dtype, X->order, X->dims, F, cols, G, factor_dtype(X->dtype), p,
+                  as_stream(stream));
+}
+
+tk_status tucker_reconstruct(int32_t order, const int64_t* dims, int32_t fdtype, const void* G,
+                             const void* const* F, const int32_t* cols, const tk_tensor* Xref,
+                             void* Xhat, double* resid2, void* ws, size_t* ws_bytes,
+                             void* stream) {
+  clear_error();
+  if (order < 1 || order > TK_MAX_ORDER) return set_error(TK_EINVAL, "tucker_reconstruct: bad order %d", order);
+  if (!dims) return set_error(TK_EINVAL, "tucker_reconstruct: dims is NULL");
+  for (int k = 0; k < order; ++k)
+    if (dims[k] < 1) return set_error(TK_EINVAL, "tucker_reconstruct: dims[%d] < 1", k);
+  if (fdtype != TK_F64 && fdtype != TK_F32)
+    return set_error(TK_EINVAL, "tucker_reconstruct: fdtype must be TK_F64 or TK_F32");
+  if (!G) return set_error(TK_EINVAL, "tucker_reconstruct: G is NULL");
+  if (tk_status s = check_factors(order, dims, F, cols, "tucker_reconstruct")) return s;
+  if (!Xhat && !resid2) return set_error(TK_EINVAL, "tucker_reconstruct: neither Xhat nor resid2 given");
+  if (resid2 && !Xref) return set_error(TK_EINVAL, "tucker_reconstruct: resid2 needs Xref");
+  if (!ws_bytes) return set_error(TK_EINVAL, "tucker_reconstruct: ws_bytes is NULL");
+  if (Xref) {
+    int64_t N;
+    if (tk_status s = check_tensor(Xref, "tucker_reconstruct(Xref)", &N)) return s;
+    if (Xref->order != order) return set_error(TK_EINVAL, "tucker_reconstruct: Xref order mismatch");
+    for (int k = 0; k < order; ++k)
+      if (Xref->dims[k] != dims[k]) return set_error(TK_EINVAL, "tucker_reconstruct: Xref dims[%d] mismatch", k);
+    if (factor_dtype(Xref->dtype) != fdtype)
+      return set_error(TK_EINVAL, "tucker_reconstruct: fdtype does not match Xref's factor dtype");
+  }
+  // expand modes 0 .. d-2 into FP64 intermediates, the last one fused with the residual
+  int64_t shape[TK_MAX_ORDER];
+  for (int k = 0; k < order; ++k) shape[k] = cols[k];
+  int64_t mx = prod(shape, 0, order);
+  for (int k = 0; k < order - 1; ++k) {
+    shape[k] = dims[k];
+    mx = std::max(mx, prod(shape, 0, order));
+  }
+  Workspace w;
+  w.base = static_cast<char*>(ws);
+  double* buf[2] = {w.take<double>((size_t)mx), w.take<double>((size_t)mx)};
+  const int64_t A_last = prod(dims, 0, order - 1);
+  const int64_t nb = expand_residual_blocks(A_last * dims[order - 1]);
+  double* partials = w.take<double>((size_t)2 * nb);
+  if (!ws) {
+    *ws_bytes = w.off;
+    return TK_OK;
+  }
+  if (*ws_bytes < w.off)
+    return set_error(TK_EWORKSPACE, "tucker_reconstruct: workspace %zu < required %zu", *ws_bytes, w.off);
+  hipStream_t st = as_stream(stream);
+  for (int k = 0; k < order; ++k) shape[k] = cols[k];
+  const void* cur = G;
+  int cur_dt = fdtype;
+  int which = 0;
+  for (int k = 0; k < order - 1; ++k) {
+    ModeProduct mp{};
+    mp.in = cur;
+    mp.A = prod(shape, 0, k);
+    mp.Q = shape[k];
+    mp.B = prod(shape, k + 1, order);
+    mp.P = (int32_t)dims[k];
+    mp.M = F[k];
+    mp.rs = cols[k];   // M[p][q] = F[p][q]
+    mp.cs = 1;
+    mp.out = buf[which];
+    TK_HIP(launch_mode_product(mp, cur_dt, TK_F64, fdtype, st));
+    shape[k] = dims[k];
+    cur = buf[which];
+    cur_dt = TK_F64;
+    which ^= 1;
+  }
+  if (order == 1 && fdtype != TK_F64) {
+    // the last expansion reads an FP64 intermediate: widen the c_0 core values
+    TK_HIP(launch_to_f64(G, fdtype, buf[0], cols[0], st));
+    cur = buf[0];
+  }
+  ExpandResidual e{};
+  e.T = static_cast<const double*>(cur);
+  e.F = F[order - 1];
+  e.X = Xref ? Xref->data : nullptr;
+  e.Xhat = Xhat;
+  e.partials = resid2 ? partials : nullptr;
+  e.resid2 = resid2;
+  e.A = A_last;
+  e.n = dims[order - 1];
+  e.c = cols[order - 1];
+  TK_HIP(launch_expand_residual(e, Xref ? Xref->dtype : fdtype, fdtype, st));
+  return TK_OK;
+}
+
+tk_status htucker_decompose(const tk_tensor* X, const tk_tree* tree, const int32_t* rank,
+                            const tk_sketch* sk, void* const* U, void* const* B, int32_t* info,
+                            void* ws, size_t* ws_bytes, void* stream) {
+  clear_error();
+  int64_t N;
+  if (tk_status s = check_tensor(X, "htucker_decompose", &N)) return s;
+  const int d = X->order;
+  if (d < 2) return set_error(TK_EINVAL, "htucker_decompose: order must be >= 2");
+  if (!tree || !rank || !sk || !U || !B || !ws_bytes)
+    return set_error(TK_EINVAL, "htucker_decompose: NULL argument");
+  const int nn = 2 * d - 1;
+  if (tree->num_nodes != nn)
+    return set_error(TK_EINVAL, "htucker_decompose: num_nodes %d != 2 order - 1", tree->num_nodes);
+  if (!tree->left || !tree->right || !tree->first_mode || !tree->num_modes)
+    return set_error(TK_EINVAL, "htucker_decompose: tree arrays are NULL");
+  // the expected balanced heap tree (left child = first ceil(|S|/2) modes)
+  {
+    std::vector<int> ef(1, 0), ec(1, d), el, er;
+    size_t head = 0;
+    std::vector<std::pair<int, int>> level{{0, d}};
+    el.assign(1, -1);
+    er.assign(1, -1);
+    while (head < ef.size()) {
+      // breadth-first, children appended in order
+      const size_t end = ef.size();
+      std::vector<std::pair<int, int>> kids;
+      for (size_t t = head; t < end; ++t) {
+        if (ec[t] > 1) {
+          const int cl = (ec[t] + 1) / 2;
+          el[t] = (int)(end + kids.size());
+          kids.push_back({ef[t], cl});
+          er[t] = (int)(end + kids.size());
+          kids.push_back({ef[t] + cl, ec[t] - cl});
+        }
+      }
+      head = end;
+      for (auto& kd : kids) {
+        ef.push_back(kd.first);
+        ec.push_back(kd.second);
+        el.push_back(-1);
+        er.push_back(-1);
+      }
+    }
+    if ((int)ef.size() != nn) return set_error(TK_EINVAL, "htucker_decompose: internal tree error");
+    for (int t = 0; t < nn; ++t)
+      if (tree->first_mode[t] != ef[t] || tree->num_modes[t] != ec[t] || tree->left[t] != el[t] ||
+          tree->right[t] != er[t])
+        return set_error(TK_EINVAL, "htucker_decompose: node %d differs from the balanced heap tree", t);
+  }
+  std::vector<int64_t> nS(nn), nc(nn), A(nn), Bv(nn);
+  for (int t = 0; t < nn; ++t) {
+    const int f = tree->first_mode[t], c = tree->num_modes[t];
+    A[t] = prod(X->dims, 0, f);
+    nS[t] = prod(X->dims, f, f + c);
+    Bv[t] = prod(X->dims, f + c, d);
+    nc[t] = N / nS[t];
+  }
+  for (int t = 1; t < nn; ++t) {
+    if (tk_status s = check_sketch(sk[t], nS[t], nc[t], "node", t)) return s;
+    if (rank[t] < 1 || rank[t] > sk[t].ell)
+      return set_error(TK_EINVAL, "htucker_decompose: rank[%d] = %d outside [1, ell = %d]", t, rank[t], sk[t].ell);
+    if (!U[t]) return set_error(TK_EINVAL, "htucker_decompose: U[%d] is NULL", t);
+    if (tree->left[t] >= 0 && !B[t]) return set_error(TK_EINVAL, "htucker_decompose: B[%d] is NULL", t);
+  }
+  if (!B[0]) return set_error(TK_EINVAL, "htucker_decompose: B[0] is NULL");
+  for (int t = 0; t < nn; ++t) {
+    if (tree->left[t] < 0) continue;
+    const int l = tree->left[t], r = tree->right[t];
+    if (rank[l] > kMaxCols || rank[r] > kMaxCols)
+      return set_error(TK_EUNSUPPORTED, "htucker_decompose: child rank above %d", kMaxCols);
+  }
+  const int fdt = factor_dtype(X->dtype);
+  Workspace w;
+  w.base = static_cast<char*>(ws);
+  // sketches of every non-root node
+  SketchBatch sb{};
+  sb.count = nn - 1;
+  std::vector<double*> Z(nn, nullptr);
+  std::vector<void*> Y(nn, nullptr);
+  const size_t xs = dtype_size(X->dtype);
+  for (int t = 1; t < nn; ++t) {
+    Z[t] = w.take<double>((size_t)nS[t] * sk[t].ell);
+    Y[t] = w.take<char>((size_t)nS[t] * sk[t].s * xs);
+  }
+  for (int t = 1; t < nn; ++t)
+    plan_unit(w, sb.u[t - 1], X->data, A[t], nS[t], Bv[t], sk[t], Z[t], Y[t], sb.total_blocks,
+              sb.total_out);
+  std::vector<QRMat> mats(nn - 1);
+  for (int t = 1; t < nn; ++t)
+    plan_qr(w, mats[t - 1], Z[t], nS[t], sk[t].ell, Y[t], sk[t].s, rank[t], U[t],
+            info ? info + t : nullptr);
+  // transfers of internal non-root nodes
+  std::vector<Transfer> tr;
+  for (int t = 1; t < nn; ++t) {
+    if (tree->left[t] < 0) continue;
+    const int l = tree->left[t], r = tree->right[t];
+    Transfer x{};
+    x.US = U[t];
+    x.Ul = U[l];
+    x.Ur = U[r];
+    x.Bout = B[t];
+    x.nl = nS[l];
+    x.nr = nS[r];
+    x.rS = rank[t];
+    x.rl = rank[l];
+    x.rr = rank[r];
+    x.V = w.take<double>((size_t)x.nl * x.rr * x.rS);
+    tr.push_back(x);
+  }
+  // root: X viewed as (n_l, n_r): B_R = U_l^T X U_r
+  const int L = tree->left[0], R = tree->right[0];
+  double* t1 = w.take<double>((size_t)nS[L] * rank[R]);
+  if (!ws) {
+    *ws_bytes = w.off;
+    return TK_OK;
+  }
+  if (*ws_bytes < w.off)
+    return set_error(TK_EWORKSPACE, "htucker_decompose: workspace %zu < required %zu", *ws_bytes, w.off);
+  hipStream_t st = as_stream(stream);
+  // an order <= 16 tree has at most 30 non-root nodes: a single sketch launch
+  TK_HIP(launch_sketch(X->dtype, sb, st));
+  if (tk_status s = run_qr(mats, X->dtype, fdt, true, st)) return s;
+  for (const Transfer& x : tr) TK_HIP(launch_transfer(x, fdt, st));
+  {
+    ModeProduct mp{};
+    mp.in = X->data;
+    mp.A = nS[L];
+    mp.Q = nS[R];
+    mp.B = 1;
+    mp.P = rank[R];
+    mp.M = U[R];
+    mp.rs = 1;
+    mp.cs = rank[R];
+    mp.out = t1;
+    TK_HIP(launch_mode_product(mp, X->dtype, TK_F64, fdt, st));
+    ModeProduct m2{};
+    m2.in = t1;
+    m2.A = 1;
+    m2.Q = nS[L];
+    m2.B = rank[R];
+    m2.P = rank[L];
+    m2.M = U[L];
+    m2.rs = 1;
+    m2.cs = rank[L];
+    m2.out = B[0];
+    TK_HIP(launch_mode_product(m2, TK_F64, fdt, fdt, st));
+  }
+  return TK_OK;
+}
+
+tk_status tucker_core_vjp(const tk_tensor* X, const void* const* F, const int32_t* cols,
+                          const void* Gbar, void* Xbar, void* const* Fbar, int32_t accumulate,
+                          void* ws, size_t* ws_bytes, void* stream) {
+  clear_error();
+  (void)X; (void)F; (void)cols; (void)Gbar; (void)Xbar; (void)Fbar; (void)accumulate;
+  (void)ws; (void)ws_bytes; (void)stream;
+  return set_error(TK_EUNSUPPORTED, "tucker_core_vjp: not built yet");
+}
+
+tk_status tucker_reconstruct_vjp(int32_t order, const int64_t* dims, int32_t fdtype,
+                                 const void* G, const void* const* F, const int32_t* cols,
+                                 const void* H, void* Gbar, void* const* Fbar, void* ws,
+                                 size_t* ws_bytes, void* stream) {
+  clear_error();
+  (void)order; (void)dims; (void)fdtype; (void)G; (void)F; (void)cols; (void)H; (void)Gbar;
+  (void)Fbar; (void)ws; (void)ws_bytes; (void)stream;
+  return set_error(TK_EUNSUPPORTED, "tucker_reconstruct_vjp: not built yet");
+}
+
+}  // extern "C"

@@ -1,0 +1,115 @@
+// Host-side launchers of the kernels (one translation unit per kernel family).
+#pragma once
+
+#include "tk_common.hpp"
+
+namespace tk {
+
+// ---------------------------------------------------------------- sampled sketches
+// One unit = one mode (or tree node) S of a tensor viewed as (A, n, B):
+// column j of the unfolding is the fiber X[a, :, b], (a, b) = divmod(j, B).
+struct SketchUnit {
+  const void* X;
+  int64_t A, n, B;
+  int64_t s;
+  const int64_t* idx;   // sorted column indices, or nullptr = every column
+  const void* omega;    // [s x ell], double for F64 tensors, float otherwise
+  double* partial;      // [nchunks][n][ell]
+  double* Z;            // [n][ell]
+  void* Y;              // [n][s] in the tensor dtype, or nullptr
+  int64_t block_begin;  // first block of this unit in the gather launch
+  int32_t ell;
+  int32_t nchunks;      // ceil(s / kSketchCols)
+  int32_t rowblocks;    // ceil(n / kSketchRows)
+  int32_t pad;
+};
+struct SketchBatch {
+  int32_t count;
+  int64_t total_blocks;
+  int64_t total_out;    // sum over units of n * ell (reduce launch)
+  SketchUnit u[kMaxUnits];
+};
+constexpr int kSketchRows = 64;
+constexpr int kSketchCols = 32;
+hipError_t launch_sketch(int dtype, const SketchBatch& b, hipStream_t st);
+
+// ---------------------------------------------------------------- CholeskyQR2 + W step
+struct QRMat {
+  double* Z;            // m x ell, becomes Q
+  const void* Y;        // m x s or nullptr
+  void* U;              // m x r output or nullptr
+  int32_t* info;        // element or nullptr
+  double* gpart;        // [nrc][ell][ell]
+  double* R;            // [ell][ell]
+  int32_t* shifted;     // per-matrix flag
+  double* mpart;        // [nrc][ell][s]
+  double* cpart;        // [ncc][ell][ell]
+  double* W;            // [ell][r]
+  double* utmp;         // [m][r]
+  double* amax_v;       // [nrb][r]
+  int64_t* amax_i;      // [nrb][r]
+  int64_t m, s;
+  int32_t ell, r;
+  int32_t nrc, ncc, nrb; // row chunks (Gram / Q^T Y), column chunks, row blocks (apply)
+  int32_t pad;
+};
+constexpr int kQRMaxBatch = 16;
+constexpr int kQRRowChunk = 256;
+constexpr int kQRColChunk = 64;
+constexpr int kQRRowBlock = 64;
+struct QRBatch {
+  int32_t count;
+  QRMat m[kQRMaxBatch];
+};
+hipError_t launch_cholqr(const QRBatch& b, hipStream_t st);
+hipError_t launch_wstep(const QRBatch& b, int ydtype, int udtype, hipStream_t st);
+
+// ---------------------------------------------------------------- generic mode products
+// out[a][p][b] = sum_q in[a][q][b] * M[p][q],  M[p][q] = Mp[p*rs + q*cs]
+struct ModeProduct {
+  const void* in;
+  void* out;
+  const void* M;        // factor dtype (double or float)
+  int64_t A, Q, B;
+  int32_t P;
+  int32_t rs, cs;
+  int32_t accumulate;   // out += instead of out =
+};
+// in_dt: dtype of `in`; out_dt, m_dt: TK_F64 or TK_F32
+hipError_t launch_mode_product(const ModeProduct& mp, int in_dt, int out_dt, int m_dt,
+                               hipStream_t st);
+
+// Last-mode expansion fused with the residual: xhat[a][i] = sum_j T[a][j] F[i][j]
+// (T is FP64 A x c, F is n x c in f_dt); optional write of xhat (f_dt) and
+// per-block partial sums of (x - xhat)^2 and x^2.
+struct ExpandResidual {
+  const double* T;
+  const void* F;
+  const void* X;        // reference or nullptr
+  void* Xhat;           // output or nullptr
+  double* partials;     // [nblocks][2] or nullptr
+  double* resid2;       // final [2] or nullptr
+  int64_t A, n;
+  int32_t c;
+  int32_t pad;
+};
+int64_t expand_residual_blocks(int64_t total);
+hipError_t launch_expand_residual(const ExpandResidual& e, int x_dt, int f_dt, hipStream_t st);
+
+// ---------------------------------------------------------------- H-Tucker transfers
+// B[i][j][k] = sum_{a,b} US[a*nr + b][i] Ul[a][j] Ur[b][k]
+struct Transfer {
+  const void* US; const void* Ul; const void* Ur;
+  void* Bout;
+  double* V;            // workspace [nl][rS][rr]
+  int64_t nl, nr;
+  int32_t rS, rl, rr;
+  int32_t pad;
+};
+hipError_t launch_transfer(const Transfer& t, int f_dt, hipStream_t st);
+
+// ---------------------------------------------------------------- conversions
+hipError_t launch_convert(const double* in, void* out, int out_dt, int64_t n, hipStream_t st);
+hipError_t launch_to_f64(const void* in, int in_dt, double* out, int64_t n, hipStream_t st);
+
+}  // namespace tk

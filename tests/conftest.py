@@ -21,3 +21,13 @@ def gpu_lib():
         pytest.skip("no GPU")
     from paper_2603_21379_amd import binding
     return binding.lib()
+
+
+@pytest.fixture(autouse=True)
+def _announce(request):
+    """Name the case on the real stderr (not captured) before it runs, so the
+    last line printed identifies the test if a GPU step never returns."""
+    if request.node.get_closest_marker("gpu"):
+        sys.__stderr__.write(f"\n[gpu-case] {request.node.nodeid}\n")
+        sys.__stderr__.flush()
+    yield

@@ -1,0 +1,176 @@
+"""The C-ABI library without a GPU: it loads, exports every function declared in
+include/tkmi.h, validates arguments before touching the device, and answers
+workspace-size queries.  No compute call is made here."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "tkmi.h")
+
+from paper_2603_21379_amd import binding as B  # noqa: E402
+
+FAKE = 0x10000  # a non-NULL address; never dereferenced by validation or size queries
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?\w+\s*\*?\s*(\w+)\s*\(", text, flags=re.M)))
+
+
+def test_library_exports_every_declared_function():
+    L = B.lib()
+    names = declared_functions()
+    assert "tucker_sketch_all_modes" in names and "htucker_decompose" in names
+    for n in names:
+        assert hasattr(L, n), n
+    assert set(B.EXPORTS) <= set(names)
+    assert B.version().startswith("tkmi")
+
+
+def _tensor(dims, dtype=B.TK_F32, data=FAKE):
+    t = B.TkTensor()
+    t.order = len(dims)
+    t.dtype = dtype
+    for k, n in enumerate(dims):
+        t.dims[k] = n
+    t.data = data
+    return t
+
+
+def _sk(s, ell, idx=FAKE, om=FAKE, reserved=0):
+    k = B.TkSketch()
+    k.s, k.ell, k.reserved, k.idx, k.omega = s, ell, reserved, idx, om
+    return k
+
+
+def _query(fn, *args):
+    n = C.c_size_t(0)
+    st = getattr(B.lib(), fn)(*args, None, C.byref(n), None)
+    return st, n.value, B.lib().tk_last_error().decode()
+
+
+def _ptrs(n):
+    return (C.c_void_p * n)(*([FAKE] * n))
+
+
+def test_sketch_validation_and_query():
+    X = _tensor((8, 9, 10))
+    sks = (B.TkSketch * 3)(_sk(20, 5), _sk(30, 5), _sk(40, 5))
+    st, n, _ = _query("tucker_sketch_all_modes", C.byref(X), sks, _ptrs(3), None)
+    assert st == 0 and n > 0
+    # ell > s
+    bad = (B.TkSketch * 3)(_sk(4, 5), _sk(30, 5), _sk(40, 5))
+    st, _, msg = _query("tucker_sketch_all_modes", C.byref(X), bad, _ptrs(3), None)
+    assert st == 1 and "mode 0" in msg
+    # s larger than the number of columns (9*10 = 90)
+    bad = (B.TkSketch * 3)(_sk(91, 5), _sk(30, 5), _sk(40, 5))
+    assert _query("tucker_sketch_all_modes", C.byref(X), bad, _ptrs(3), None)[0] == 1
+    # dense sketch must sample every column
+    bad = (B.TkSketch * 3)(_sk(50, 5, idx=None), _sk(30, 5), _sk(40, 5))
+    assert _query("tucker_sketch_all_modes", C.byref(X), bad, _ptrs(3), None)[0] == 1
+    ok = (B.TkSketch * 3)(_sk(90, 5, idx=None), _sk(30, 5), _sk(40, 5))
+    assert _query("tucker_sketch_all_modes", C.byref(X), ok, _ptrs(3), None)[0] == 0
+    # reserved field, NULL omega, ell beyond the rows, NULL data
+    assert _query("tucker_sketch_all_modes", C.byref(X),
+                  (B.TkSketch * 3)(_sk(20, 5, reserved=1), _sk(30, 5), _sk(40, 5)), _ptrs(3), None)[0] == 1
+    assert _query("tucker_sketch_all_modes", C.byref(X),
+                  (B.TkSketch * 3)(_sk(20, 5, om=None), _sk(30, 5), _sk(40, 5)), _ptrs(3), None)[0] == 1
+    assert _query("tucker_sketch_all_modes", C.byref(X),
+                  (B.TkSketch * 3)(_sk(20, 9), _sk(30, 5), _sk(40, 5)), _ptrs(3), None)[0] == 1
+    X0 = _tensor((8, 9, 10), data=None)
+    assert _query("tucker_sketch_all_modes", C.byref(X0), sks, _ptrs(3), None)[0] == 1
+    # ell above the one-wave solver limit
+    big = _tensor((100, 100))
+    assert _query("tucker_sketch_all_modes", C.byref(big),
+                  (B.TkSketch * 2)(_sk(100, 65), _sk(100, 5)), _ptrs(2), None)[0] == 5
+
+
+def test_workspace_too_small_is_rejected_before_launch():
+    X = _tensor((8, 9, 10))
+    sks = (B.TkSketch * 3)(_sk(20, 5), _sk(30, 5), _sk(40, 5))
+    n = C.c_size_t(16)
+    st = B.lib().tucker_sketch_all_modes(C.byref(X), sks, _ptrs(3), None, C.c_void_p(FAKE),
+                                          C.byref(n), None)
+    assert st == 2 and "workspace" in B.lib().tk_last_error().decode()
+
+
+def test_qr_validation():
+    m = (C.c_int64 * 2)(10, 20)
+    ell = (C.c_int32 * 2)(4, 25)
+    st, _, msg = _query("tucker_qr", 2, m, ell, _ptrs(2), None, 0, None, None, None, 0, None)
+    assert st == 1 and "ell[1]" in msg
+    ell = (C.c_int32 * 2)(4, 5)
+    st, n, _ = _query("tucker_qr", 2, m, ell, _ptrs(2), None, 0, None, None, None, 0, None)
+    assert st == 0 and n > 0
+    s = (C.c_int64 * 2)(30, 40)
+    r = (C.c_int32 * 2)(4, 6)
+    st, _, msg = _query("tucker_qr", 2, m, ell, _ptrs(2), _ptrs(2), B.TK_F32, s, r, _ptrs(2),
+                        B.TK_F32, None)
+    assert st == 1 and "r[1]" in msg
+    r = (C.c_int32 * 2)(4, 5)
+    assert _query("tucker_qr", 2, m, ell, _ptrs(2), _ptrs(2), B.TK_F32, s, r, _ptrs(2), B.TK_BF16,
+                  None)[0] == 1
+    assert _query("tucker_qr", 2, m, ell, _ptrs(2), _ptrs(2), B.TK_F32, s, r, _ptrs(2), B.TK_F32,
+                  None)[0] == 0
+    assert _query("tucker_qr", -1, m, ell, _ptrs(2), None, 0, None, None, None, 0, None)[0] == 1
+
+
+def test_core_and_reconstruct_validation():
+    X = _tensor((8, 9, 10))
+    cols = (C.c_int32 * 3)(3, 4, 5)
+    st, n, _ = _query("tucker_core", C.byref(X), _ptrs(3), cols, C.c_void_p(FAKE))
+    assert st == 0 and n > 0
+    bad = (C.c_int32 * 3)(3, 10, 5)
+    st, _, msg = _query("tucker_core", C.byref(X), _ptrs(3), bad, C.c_void_p(FAKE))
+    assert st == 1 and "cols[1]" in msg
+    F = _ptrs(3)
+    F[2] = None
+    assert _query("tucker_core", C.byref(X), F, cols, C.c_void_p(FAKE))[0] == 1
+    assert _query("tucker_core", C.byref(X), _ptrs(3), cols, None)[0] == 1
+    dims = (C.c_int64 * 3)(8, 9, 10)
+    # neither output requested
+    assert _query("tucker_reconstruct", 3, dims, B.TK_F32, C.c_void_p(FAKE), _ptrs(3), cols, None,
+                  None, None)[0] == 1
+    # residual without reference
+    assert _query("tucker_reconstruct", 3, dims, B.TK_F32, C.c_void_p(FAKE), _ptrs(3), cols, None,
+                  None, C.c_void_p(FAKE))[0] == 1
+    # factor dtype mismatch with the reference
+    X64 = _tensor((8, 9, 10), dtype=B.TK_F64)
+    assert _query("tucker_reconstruct", 3, dims, B.TK_F32, C.c_void_p(FAKE), _ptrs(3), cols,
+                  C.byref(X64), None, C.c_void_p(FAKE))[0] == 1
+    st, n, _ = _query("tucker_reconstruct", 3, dims, B.TK_F32, C.c_void_p(FAKE), _ptrs(3), cols,
+                      C.byref(X), None, C.c_void_p(FAKE))
+    assert st == 0 and n > 0
+
+
+def test_htucker_validation():
+    import synthgen
+    X = _tensor((4, 4, 4, 4))
+    tr = synthgen.balanced_tree(4)
+    td = B.tree_desc(tr)
+    nn = tr.num_nodes
+    rk = (C.c_int32 * nn)(*([0] + [2] * (nn - 1)))
+    sks = (B.TkSketch * nn)(*([_sk(1, 1)] + [_sk(8, 3)] * (nn - 1)))
+    st, n, msg = _query("htucker_decompose", C.byref(X), C.byref(td), rk, sks, _ptrs(nn), _ptrs(nn),
+                        None)
+    assert st == 0 and n > 0, msg
+    # a tree that is not the balanced heap tree
+    tr.left[0], tr.right[0] = tr.right[0], tr.left[0]
+    td2 = B.tree_desc(tr)
+    st, _, msg = _query("htucker_decompose", C.byref(X), C.byref(td2), rk, sks, _ptrs(nn), _ptrs(nn),
+                        None)
+    assert st == 1 and "balanced" in msg
+    # rank above ell
+    rk2 = (C.c_int32 * nn)(*([0] + [4] * (nn - 1)))
+    assert _query("htucker_decompose", C.byref(X), C.byref(td), rk2, sks, _ptrs(nn), _ptrs(nn),
+                  None)[0] == 1
+
+
+def test_status_codes_in_header_match_binding():
+    text = open(HEADER).read()
+    for code, name in B.STATUS.items():
+        assert re.search(rf"\b{name}\s*=\s*{code}\b", text), name

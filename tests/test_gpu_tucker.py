@@ -1,0 +1,183 @@
+"""GPU parity of the Sub-R-HOSVD path (sketch, CholeskyQR2 + W step, core,
+residual) against the FP64 oracle on the same seeded inputs and sketches.
+
+Tolerances (relative reconstruction error eps vs the oracle's):
+FP64 1e-10, FP32 1e-5, BF16/FP16 3e-3 (as |eps_gpu - eps_or| / eps_or).
+Factor comparisons go through projectors and canonical column signs.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synthgen
+from synthgen import configs
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"f64": 1e-10, "f32": 1e-5, "bf16": 3e-3, "f16": 3e-3}
+TORCH_DT = {"f64": torch.float64, "f32": torch.float32, "bf16": torch.bfloat16, "f16": torch.float16}
+
+
+def to_device(X, dtype):
+    if dtype == "bf16":
+        t = torch.from_numpy(X.view(np.int16)).cuda().view(torch.bfloat16)
+        return t
+    return torch.from_numpy(X).cuda()
+
+
+def run_case(dims, ranks, decay, noise, p, ss, dtype, cfg, dense=False, core_factor="U",
+             exact_ell=None):
+    from paper_2603_21379_amd import tucker as T
+    inp = synthgen.tucker_tensor(dims, ranks, decay, noise, cfg=cfg, dtype=dtype)
+    ells = exact_ell or synthgen.default_ell(dims, ranks, p)
+    fdt = synthgen.factor_dtype(dtype)
+    sk = synthgen.mode_sketches(dims, ells, ss, cfg=cfg, omega_dtype=fdt, dense=dense)
+    X64 = synthgen.to_f64(inp.X, dtype)
+    G_or, U_or, Q_or, Y_or, Z_or = oracle.sub_r_hosvd(X64, ranks, sk, core_factor=core_factor)
+    Xd = to_device(inp.X, dtype)
+    skd = T.mode_sketches_to_device(sk, dims, "cuda", TORCH_DT[fdt])
+    res = T.sub_r_hosvd(Xd, ranks, skd, core_factor=core_factor)
+    eps_gpu = T.rel_error(Xd, res.G, res.F)
+    torch.cuda.synchronize()
+    F_or = U_or if core_factor == "U" else Q_or
+    eps_or = oracle.rel_error(X64, G_or, F_or)
+    out = dict(inp=inp, X64=X64, sk=sk, G_or=G_or, U_or=U_or, Q_or=Q_or, Y_or=Y_or, Z_or=Z_or,
+               F_or=F_or, eps_or=eps_or, eps_gpu=eps_gpu,
+               G=res.G.double().cpu().numpy(), F=[f.double().cpu().numpy() for f in res.F],
+               Q=[q.cpu().numpy() for q in res.Q],
+               Y=[synthgen.to_f64(y.cpu().view(torch.int16).numpy().view(np.uint16), "bf16")
+                  if dtype == "bf16" else y.double().cpu().numpy() for y in res.Y],
+               info=res.info.cpu().numpy())
+    return out
+
+
+def check_common(o, dtype, ptol):
+    # the gather is a copy: bit-exact
+    for a, b in zip(o["Y"], o["Y_or"]):
+        np.testing.assert_array_equal(a, b)
+    # factors orthonormal at their storage precision
+    otol = 1e-12 if dtype == "f64" else 1e-5
+    for F in o["F"]:
+        assert np.max(np.abs(F.T @ F - np.eye(F.shape[1]))) < otol
+    for a, b in zip(o["F"], o["F_or"]):
+        assert oracle.projector_distance(a, b) < ptol
+    # core kernel alone: the oracle's core on the GPU's own factors
+    G_chk = oracle.core(o["X64"], o["F"])
+    scale = np.abs(G_chk).max()
+    ctol = 1e-12 if dtype == "f64" else 1e-6
+    np.testing.assert_allclose(o["G"], G_chk, rtol=0, atol=ctol * scale)
+    rel = abs(o["eps_gpu"] - o["eps_or"]) / o["eps_or"]
+    assert rel <= TOL[dtype], (o["eps_gpu"], o["eps_or"], rel)
+
+
+def test_c1_fp64_sampled():
+    c = configs.C1
+    o = run_case(c.dims, c.ranks, c.decay, c.noise, c.p, synthgen.default_s(c.dims), c.dtype,
+                 c.cfg_id)
+    check_common(o, "f64", 1e-10)
+    for z, zo in zip(o["Q"], o["Q_or"]):
+        np.testing.assert_allclose(z, zo, atol=1e-10)
+    for a, b in zip(o["F"], o["F_or"]):
+        np.testing.assert_allclose(a, b, atol=1e-9)
+    np.testing.assert_allclose(o["G"], o["G_or"], atol=1e-9 * np.abs(o["G_or"]).max())
+    assert (o["info"] == 0).all()
+
+
+def test_c1_fp64_dense_sketch():
+    c = configs.C1
+    o = run_case(c.dims, c.ranks, c.decay, c.noise, c.p, [0, 0, 0], c.dtype, c.cfg_id, dense=True)
+    check_common(o, "f64", 1e-10)
+
+
+def test_c1_exact_rank_shifted_qr():
+    """sigma = 0: rank(Z_k) = 8 < ell = 13, the Gram is singular, the shifted
+    first pass runs (info = 1) and the decomposition is exact."""
+    c = configs.C1
+    o = run_case(c.dims, c.ranks, c.decay, 0.0, c.p, synthgen.default_s(c.dims), c.dtype, 31)
+    assert o["eps_or"] < 1e-12
+    assert o["eps_gpu"] < 1e-12
+    assert (o["info"] == 1).all()
+    for F in o["F"]:
+        assert np.max(np.abs(F.T @ F - np.eye(F.shape[1]))) < 1e-12
+    for a, b in zip(o["F"], o["F_or"]):
+        assert oracle.projector_distance(a, b) < 1e-10
+
+
+def test_c1_q_core():
+    c = configs.C1
+    o = run_case(c.dims, c.ranks, c.decay, c.noise, c.p, synthgen.default_s(c.dims), c.dtype,
+                 c.cfg_id, core_factor="Q")
+    rel = abs(o["eps_gpu"] - o["eps_or"]) / o["eps_or"]
+    assert rel <= TOL["f64"]
+    for a, b in zip(o["F"], o["Q_or"]):
+        assert oracle.projector_distance(a, b) < 1e-10
+
+
+def test_c2_small_fp32():
+    c = configs.C2_SMALL
+    o = run_case(c.dims, c.ranks, c.decay, c.noise, c.p, synthgen.default_s(c.dims), c.dtype,
+                 c.cfg_id)
+    check_common(o, "f32", 1e-5)
+
+
+@pytest.mark.parametrize("dtype", ["bf16", "f16", "f32"])
+def test_c3_small_low_precision(dtype):
+    c = configs.C3_SMALL
+    o = run_case(c.dims, c.ranks, c.decay, c.noise, c.p, synthgen.default_s(c.dims), dtype,
+                 c.cfg_id)
+    check_common(o, dtype, 1e-4)
+
+
+def test_ragged_order2_and_order5():
+    # order 2: rows/cols not multiples of the tiles, s not a multiple of 32
+    o = run_case((131, 77), (5, 5), 0.6, 1e-3, 5, [77, 131], "f64", 41)
+    check_common(o, "f64", 1e-9)
+    o = run_case((7, 9, 5, 6, 11), (3, 2, 3, 3, 4), 0.7, 1e-2, 4, [37, 45, 29, 33, 55], "f32", 42)
+    check_common(o, "f32", 1e-4)
+
+
+def test_full_basis_gives_exact_reconstruction():
+    """ell_k = n_k and every fiber: Q_k is a full basis and X_hat = X for any X."""
+    o = run_case((6, 7, 8), (6, 7, 8), 0.9, 1.0, 0, [0, 0, 0], "f64", 43, dense=True,
+                 core_factor="Q", exact_ell=[6, 7, 8])
+    assert o["eps_gpu"] < 1e-13
+    assert o["eps_or"] < 1e-13
+
+
+def test_s_equals_ell_minimum_sample():
+    o = run_case((20, 18, 16), (3, 3, 3), 0.5, 1e-4, 4, [7, 7, 7], "f64", 44)
+    check_common(o, "f64", 1e-8)
+
+
+def test_reconstruct_materialised_matches_oracle():
+    from paper_2603_21379_amd import tucker as T
+    rng = np.random.default_rng(7)
+    dims, cols = (9, 70, 33), (4, 5, 6)
+    G = rng.standard_normal(cols)
+    F = [np.linalg.qr(rng.standard_normal((n, c)))[0] for n, c in zip(dims, cols)]
+    for dt in (torch.float64, torch.float32):
+        Gd = torch.from_numpy(G).to("cuda", dt)
+        Fd = [torch.from_numpy(f).to("cuda", dt) for f in F]
+        Xh = T.reconstruct(dims, Gd, Fd).double().cpu().numpy()
+        ref = oracle.reconstruct(synthgen.to_f64(np.asarray(Gd.cpu()), "f64"),
+                                 [np.asarray(f.double().cpu()) for f in Fd])
+        tol = 1e-13 if dt == torch.float64 else 1e-6
+        np.testing.assert_allclose(Xh, ref, atol=tol * np.abs(ref).max())
+
+
+def test_bitwise_repeatable():
+    from paper_2603_21379_amd import tucker as T
+    c = configs.C2_SMALL
+    inp = synthgen.tucker_tensor(c.dims, c.ranks, c.decay, c.noise, cfg=c.cfg_id, dtype="f32")
+    sk = synthgen.mode_sketches(c.dims, synthgen.default_ell(c.dims, c.ranks, c.p),
+                                synthgen.default_s(c.dims), cfg=c.cfg_id, omega_dtype="f32")
+    Xd = torch.from_numpy(inp.X).cuda()
+    skd = T.mode_sketches_to_device(sk, c.dims, "cuda", torch.float32)
+    a = T.sub_r_hosvd(Xd, c.ranks, skd)
+    b = T.sub_r_hosvd(Xd, c.ranks, skd)
+    assert torch.equal(a.G, b.G)
+    for x, y in zip(a.F, b.F):
+        assert torch.equal(x, y)
