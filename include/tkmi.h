@@ -109,9 +109,13 @@ tk_status tucker_sketch_all_modes(const tk_tensor* X, const tk_sketch* sk, doubl
 /* Thin QR of a batch of sketches and the rank truncation of Algorithm 1
  * (orthonormal basis step, then W_k = dominant r_k left singular vectors of
  * Q_k^T Y_k and U_k = Q_k W_k).  The QR is CholeskyQR2 with an FP64 Gram and
- * FP64 Cholesky; when a pivot of the first Gram is not safely positive the
- * first pass is shifted (shifted CholeskyQR3) and info[i] is set to 1.
- * Q_i is unique up to rounding when Z_i has full column rank (R_ii > 0).
+ * FP64 Cholesky.  When a Cholesky pivot is not safely positive that pass is
+ * shifted (shifted CholeskyQR, Fukaya et al. 2020) and two plain passes
+ * follow it, so an exactly rank-deficient Z_i still yields ell_i orthonormal
+ * columns (at most four passes).  info[i]: bit 0 = first pass shifted,
+ * bit 1 = a later pass shifted, bit 2 = a Cholesky failed even with the
+ * shift (the result is then not reliable).  Q_i is unique up to rounding
+ * when Z_i has full column rank (R_ii > 0).
  *   nmat     number of matrices.
  *   m, ell   host arrays [nmat]: rows and columns of Z_i (ell_i <= m_i).
  *   Z        host array [nmat] of device FP64 m_i x ell_i row-major, replaced
@@ -165,16 +169,18 @@ tk_status tucker_reconstruct(int32_t order, const int64_t* dims, int32_t fdtype,
  * B_S(i,j,k) = <U_S(:,i), U_Sl(:,j) kron U_Sr(:,k)> of every internal non-root
  * node (transfer-tensor equation of Section 4); and the root transfer
  * B_R(0,j,k) = <vec X, U_Rl(:,j) kron U_Rr(:,k)> (one full read of X).
- *   X       tensor (F64 or F32).
+ *   X       tensor (any dtype).
  *   tree    balanced tree over X's modes (num_nodes = 2 order - 1).
  *   rank    host int32 [num_nodes]: r_S for every node (rank[0] is ignored;
  *           the root rank is 1).
  *   sk      host array [num_nodes] of sketches (sk[0] ignored).
  *   U       host array [num_nodes] of device outputs, U[t] is n_S x r_S
- *           row-major in the factor dtype (U[0] ignored).
+ *           row-major FP64 (U[0] ignored).
  *   B       host array [num_nodes] of device outputs, B[t] is r_t x r_l x r_r
- *           (C-order) for internal nodes, 1 x r_l x r_r for the root, in the
- *           factor dtype; entries for leaves are ignored.
+ *           (C-order) for internal nodes, 1 x r_l x r_r for the root, FP64;
+ *           entries for leaves are ignored.  Bases and transfers are FP64 for
+ *           every tensor dtype (they are small, and their storage precision
+ *           would otherwise bound the accuracy of the format).
  *   info    device int32 [num_nodes] or NULL (as in tucker_qr, index = node).
  * Errors: TK_EINVAL (also for a tree that is not the balanced heap tree of
  * this order), TK_EWORKSPACE, TK_EDEVICE. */

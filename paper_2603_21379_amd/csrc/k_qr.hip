@@ -19,7 +19,7 @@ __global__ __launch_bounds__(256) void gram_partial_kernel(const QRBatch b, int 
   const QRMat& M = b.m[blockIdx.y];
   const int rc = blockIdx.x;
   if (rc >= M.nrc) return;
-  if (pass == 3 && *M.shifted == 0) return;
+  if (pass > 1 && M.state[0] == 0) return;
   __shared__ double sZ[64][kMaxEll + 1];
   const int ell = M.ell, tid = threadIdx.x;
   const int64_t r0 = (int64_t)rc * kQRRowChunk;
@@ -83,9 +83,14 @@ __device__ bool cholesky_upper(double (*G)[kMaxEll + 1], int n, int lane, double
   return ok != 0;
 }
 
+// state[0]: CholeskyQR passes still owed (a plain pass pays one, a shifted
+// pass leaves two owed); state[1]: whether this pass applies R^{-1}.
 __global__ __launch_bounds__(64) void chol_kernel(const QRBatch b, int pass) {
   const QRMat& M = b.m[blockIdx.x];
-  if (pass == 3 && *M.shifted == 0) return;
+  if (pass > 1 && M.state[0] == 0) {
+    if (threadIdx.x == 0) M.state[1] = 0;
+    return;
+  }
   __shared__ double G[kMaxEll][kMaxEll + 1];
   __shared__ double red[64];
   const int n = M.ell, lane = threadIdx.x;
@@ -142,10 +147,16 @@ __global__ __launch_bounds__(64) void chol_kernel(const QRBatch b, int pass) {
     M.R[e] = v;
   }
   if (lane == 0) {
-    if (pass == 1) *M.shifted = status != 0 ? 1 : 0;
+    const int owed = pass == 1 ? 2 : M.state[0];
+    M.state[0] = status != 0 ? 2 : owed - 1;
+    M.state[1] = 1;
     if (M.info) {
-      if (pass == 1) *M.info = status;
-      else if (status != 0) *M.info = *M.info | (status << 2);
+      // bit 0: first pass shifted; bit 1: a later pass shifted; bit 2: Cholesky
+      // failed even with the shift
+      int v = pass == 1 ? 0 : *M.info;
+      if (status != 0) v |= pass == 1 ? 1 : 2;
+      if (status == 2) v |= 4;
+      *M.info = v;
     }
   }
 }
@@ -155,7 +166,8 @@ __global__ __launch_bounds__(64) void apply_rinv_kernel(const QRBatch b, int pas
   const QRMat& M = b.m[blockIdx.y];
   const int rb = blockIdx.x;
   if (rb >= M.nrb) return;
-  if (pass == 3 && *M.shifted == 0) return;
+  if (M.state[1] == 0) return;
+  (void)pass;
   __shared__ double R[kMaxEll][kMaxEll + 1];
   __shared__ double sZ[kMaxEll][65];
   const int n = M.ell, lane = threadIdx.x;
@@ -426,7 +438,9 @@ int max_field(const QRBatch& b, int which) {
 hipError_t launch_cholqr(const QRBatch& b, hipStream_t st) {
   if (b.count == 0) return hipSuccess;
   const int nrc = max_field(b, 0), nrb = max_field(b, 2);
-  for (int pass = 1; pass <= 3; ++pass) {
+  // CholeskyQR2 needs two passes; every shifted pass owes two more plain ones,
+  // so an exactly rank-deficient sketch (shift, shift, plain, plain) needs four.
+  for (int pass = 1; pass <= kQRMaxPasses; ++pass) {
     hipLaunchKernelGGL(gram_partial_kernel, dim3(nrc, b.count), dim3(256), 0, st, b, pass);
     hipLaunchKernelGGL(chol_kernel, dim3(b.count), dim3(64), 0, st, b, pass);
     hipLaunchKernelGGL(apply_rinv_kernel, dim3(nrb, b.count), dim3(64), 0, st, b, pass);

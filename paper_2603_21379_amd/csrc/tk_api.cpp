@@ -93,24 +93,24 @@ void plan_unit(Workspace& ws, SketchUnit& u, const void* X, int64_t A, int64_t n
 }
 
 // Plan the QR (+ W step) workspace of one matrix.
-void plan_qr(Workspace& ws, QRMat& q, double* Z, int64_t m, int ell, const void* Y, int64_t s,
-             int r, void* U, int32_t* info) {
+void plan_qr(Workspace& ws, QRMat& q, double* Z, int64_t m, int ell, bool wstep, const void* Y,
+             int64_t s, int r, void* U, int32_t* info) {
   q = QRMat{};
   q.Z = Z;
   q.Y = Y;
   q.U = U;
   q.info = info;
   q.m = m;
-  q.s = Y ? s : 0;
+  q.s = wstep ? s : 0;
   q.ell = ell;
-  q.r = Y ? r : 0;
+  q.r = wstep ? r : 0;
   q.nrc = (int32_t)ceil_div(m, kQRRowChunk);
-  q.ncc = Y ? (int32_t)ceil_div(s, kQRColChunk) : 0;
+  q.ncc = wstep ? (int32_t)ceil_div(s, kQRColChunk) : 0;
   q.nrb = (int32_t)ceil_div(m, kQRRowBlock);
   q.gpart = ws.take<double>((size_t)q.nrc * ell * ell);
   q.R = ws.take<double>((size_t)ell * ell);
-  q.shifted = ws.take<int32_t>(1);
-  if (Y) {
+  q.state = ws.take<int32_t>(2);
+  if (wstep) {
     q.mpart = ws.take<double>((size_t)q.nrc * ell * s);
     q.cpart = ws.take<double>((size_t)q.ncc * ell * ell);
     q.W = ws.take<double>((size_t)ell * r);
@@ -265,8 +265,8 @@ tk_status tucker_qr(int32_t nmat, const int64_t* m, const int32_t* ell, double* 
   w.base = static_cast<char*>(ws);
   std::vector<QRMat> mats(nmat);
   for (int i = 0; i < nmat; ++i)
-    plan_qr(w, mats[i], Z[i], m[i], ell[i], Y ? Y[i] : nullptr, Y ? s[i] : 0, Y ? r[i] : 0,
-            Y ? U[i] : nullptr, info ? info + i : nullptr);
+    plan_qr(w, mats[i], Z[i], m[i], ell[i], Y != nullptr, Y ? Y[i] : nullptr, Y ? s[i] : 0,
+            Y ? r[i] : 0, Y ? U[i] : nullptr, info ? info + i : nullptr);
   if (!ws) {
     *ws_bytes = w.off;
     return TK_OK;
@@ -455,7 +455,9 @@ tk_status htucker_decompose(const tk_tensor* X, const tk_tree* tree, const int32
     if (rank[l] > kMaxCols || rank[r] > kMaxCols)
       return set_error(TK_EUNSUPPORTED, "htucker_decompose: child rank above %d", kMaxCols);
   }
-  const int fdt = factor_dtype(X->dtype);
+  // bases and transfer tensors are small: they are produced in FP64 for every
+  // tensor dtype, so storing them adds no error to the format
+  const int fdt = TK_F64;
   Workspace w;
   w.base = static_cast<char*>(ws);
   // sketches of every non-root node
@@ -473,7 +475,7 @@ tk_status htucker_decompose(const tk_tensor* X, const tk_tree* tree, const int32
               sb.total_out);
   std::vector<QRMat> mats(nn - 1);
   for (int t = 1; t < nn; ++t)
-    plan_qr(w, mats[t - 1], Z[t], nS[t], sk[t].ell, Y[t], sk[t].s, rank[t], U[t],
+    plan_qr(w, mats[t - 1], Z[t], nS[t], sk[t].ell, true, Y[t], sk[t].s, rank[t], U[t],
             info ? info + t : nullptr);
   // transfers of internal non-root nodes
   std::vector<Transfer> tr;

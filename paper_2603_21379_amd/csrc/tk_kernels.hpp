@@ -41,7 +41,7 @@ struct QRMat {
   int32_t* info;        // element or nullptr
   double* gpart;        // [nrc][ell][ell]
   double* R;            // [ell][ell]
-  int32_t* shifted;     // per-matrix flag
+  int32_t* state;       // [2] pass bookkeeping (passes owed, apply flag)
   double* mpart;        // [nrc][ell][s]
   double* cpart;        // [ncc][ell][ell]
   double* W;            // [ell][r]
@@ -54,6 +54,7 @@ struct QRMat {
   int32_t pad;
 };
 constexpr int kQRMaxBatch = 16;
+constexpr int kQRMaxPasses = 4;
 constexpr int kQRRowChunk = 256;
 constexpr int kQRColChunk = 64;
 constexpr int kQRRowBlock = 64;

@@ -88,7 +88,7 @@ class HTResult:
 def sub_r_rtl_ht(X: torch.Tensor, tree, ranks: dict, sk_dev: dict, ws=None) -> HTResult:
     """Algorithm 2 on the GPU.  ranks[t] and sk_dev[t] for every non-root node."""
     dims = list(X.shape)
-    fdt = B.factor_torch_dtype(X.dtype)
+    fdt = torch.float64  # H-Tucker bases and transfers are FP64 for every tensor dtype
     dev = X.device
     n = tree.num_nodes
     nS = {t: math.prod(dims[k] for k in tree.modes(t)) for t in range(n)}

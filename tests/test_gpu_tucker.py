@@ -78,11 +78,13 @@ def test_c1_fp64_sampled():
     o = run_case(c.dims, c.ranks, c.decay, c.noise, c.p, synthgen.default_s(c.dims), c.dtype,
                  c.cfg_id)
     check_common(o, "f64", 1e-10)
-    for z, zo in zip(o["Q"], o["Q_or"]):
-        np.testing.assert_allclose(z, zo, atol=1e-10)
+    # thin QR is unique (R_ii > 0); its columns are determined to ~u kappa(Z)
+    for z, zo, Z in zip(o["Q"], o["Q_or"], o["Z_or"]):
+        sv = np.linalg.svd(Z, compute_uv=False)
+        np.testing.assert_allclose(z, zo, rtol=0, atol=100 * 1.1e-16 * sv[0] / sv[-1])
     for a, b in zip(o["F"], o["F_or"]):
-        np.testing.assert_allclose(a, b, atol=1e-9)
-    np.testing.assert_allclose(o["G"], o["G_or"], atol=1e-9 * np.abs(o["G_or"]).max())
+        np.testing.assert_allclose(a, b, rtol=0, atol=1e-9)
+    np.testing.assert_allclose(o["G"], o["G_or"], rtol=0, atol=1e-9 * np.abs(o["G_or"]).max())
     assert (o["info"] == 0).all()
 
 
@@ -99,7 +101,8 @@ def test_c1_exact_rank_shifted_qr():
     o = run_case(c.dims, c.ranks, c.decay, 0.0, c.p, synthgen.default_s(c.dims), c.dtype, 31)
     assert o["eps_or"] < 1e-12
     assert o["eps_gpu"] < 1e-12
-    assert (o["info"] == 1).all()
+    # the first pass was shifted and no Cholesky failed
+    assert ((o["info"] & 1) == 1).all() and ((o["info"] & 4) == 0).all()
     for F in o["F"]:
         assert np.max(np.abs(F.T @ F - np.eye(F.shape[1]))) < 1e-12
     for a, b in zip(o["F"], o["F_or"]):
@@ -112,8 +115,10 @@ def test_c1_q_core():
                  c.cfg_id, core_factor="Q")
     rel = abs(o["eps_gpu"] - o["eps_or"]) / o["eps_or"]
     assert rel <= TOL["f64"]
-    for a, b in zip(o["F"], o["Q_or"]):
-        assert oracle.projector_distance(a, b) < 1e-10
+    # Range(Q_k) includes noise directions determined only to ~u kappa(Z_k)
+    for a, b, Z in zip(o["F"], o["Q_or"], o["Z_or"]):
+        sv = np.linalg.svd(Z, compute_uv=False)
+        assert oracle.projector_distance(a, b) < 100 * 1.1e-16 * sv[0] / sv[-1]
 
 
 def test_c2_small_fp32():
