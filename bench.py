@@ -1,0 +1,221 @@
+"""Benchmark of the randomized Tucker hot path on one MI355X.
+
+One step = one Sub-R-HOSVD of a resident tensor: the all-mode sampled
+sketch, the batched CholeskyQR2 + W step, and the core projection (the one
+full read of X).  Default workload: the FP32 256^4 tensor of multilinear
+rank 32 (decay 0.8, relative noise 1e-4), target ranks 32, p = 10,
+s_k = 10 n_k = 2560 sampled fibers per mode.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--config c2|c3-bf16|c3-f16|c3-f32|c1]
+
+Prints one JSON line.  `value` is tensor GB/s streamed per step:
+(sum_k s_k n_k + prod n_k) * bytes / step time.  `roofline` is the streaming
+pass of the core (its algorithmic bytes prod n_k * bytes per launch over its
+HIP-event-timed average duration).  `cpu_baseline` is the FP64 oracle on a
+bounded sample of the same workload on this host.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--config", default="c2")
+    ap.add_argument("--core", default="U", choices=["U", "Q"])
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
+    ap.add_argument("--cpu-slabs", type=int, default=4,
+                    help="mode-0 slabs of X the oracle core baseline processes")
+    return ap.parse_args()
+
+
+def workload(name):
+    from synthgen import configs
+    table = {"c1": (configs.C1, "f64"), "c2": (configs.C2, "f32"),
+             "c3-bf16": (configs.C3, "bf16"), "c3-f16": (configs.C3, "f16"),
+             "c3-f32": (configs.C3, "f32")}
+    if name not in table:
+        raise SystemExit(f"unknown config {name}")
+    return table[name]
+
+
+def log(msg):
+    sys.stderr.write(f"[bench] {msg}\n")
+    sys.stderr.flush()
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
+              "(the multi-GPU sharding is a design, not a build)", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import synthgen
+    from paper_2603_21379_amd import binding as B
+    from paper_2603_21379_amd import tucker as T
+
+    cfg, dtype = workload(args.config)
+    dims, ranks = cfg.dims, cfg.ranks
+    tdt = {"f64": torch.float64, "f32": torch.float32, "bf16": torch.bfloat16,
+           "f16": torch.float16}[dtype]
+    fdt = torch.float64 if dtype == "f64" else torch.float32
+    esize = synthgen.itemsize(dtype)
+    N = math.prod(dims)
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+
+    t0 = time.time()
+    log(f"generating {cfg.name} ({dtype}, {N * esize / 1e9:.2f} GB) on the host")
+    inp = synthgen.tucker_tensor(dims, ranks, cfg.decay, cfg.noise, cfg=cfg.cfg_id, dtype=dtype)
+    ells = synthgen.default_ell(dims, ranks, cfg.p)
+    ss = synthgen.default_s(dims, cfg.alpha)
+    omega_dt = synthgen.factor_dtype(dtype)
+    sk = synthgen.mode_sketches(dims, ells, ss, cfg=cfg.cfg_id, omega_dtype=omega_dt)
+    log(f"generated in {time.time() - t0:.1f}s; uploading")
+    Xh = inp.X.view(np.int16) if dtype == "bf16" else inp.X
+    X = torch.from_numpy(Xh).to(dev)
+    if dtype == "bf16":
+        X = X.view(torch.bfloat16)
+    skd = T.mode_sketches_to_device(sk, dims, dev, fdt)
+
+    d = len(dims)
+    cols = list(ranks) if args.core == "U" else list(ells)
+    Z = [torch.empty(n, e, dtype=torch.float64, device=dev) for n, e in zip(dims, ells)]
+    Y = [torch.empty(n, s, dtype=tdt, device=dev) for n, s in zip(dims, ss)]
+    F = [torch.empty(n, c, dtype=fdt, device=dev) for n, c in zip(dims, cols)]
+    G = torch.empty(cols, dtype=fdt, device=dev)
+    info = torch.zeros(d, dtype=torch.int32, device=dev)
+
+    # one workspace for the whole step, sized by the library's own queries
+    ws = torch.empty(1 << 20, dtype=torch.uint8, device=dev)
+
+    def step(wsb):
+        B.tucker_sketch_all_modes(X, skd, Z, Y, ws=wsb)
+        B.tucker_qr(Z, Y, r=cols, U=F, info=info, ws=wsb)
+        B.tucker_core(X, F, G, ws=wsb)
+
+    # size the workspace: the binding raises when it is smaller than what a
+    # call's size query returns, so grow it to the largest of the three calls
+    for _ in range(4):
+        try:
+            step(ws)
+            break
+        except ValueError as e:
+            need = int(str(e).split("required ")[1])
+            ws = torch.empty(need, dtype=torch.uint8, device=dev)
+    torch.cuda.synchronize()
+    log(f"workspace {ws.numel() / 1e9:.3f} GB; warmup {args.warmup}")
+    for _ in range(args.warmup):
+        step(ws)
+    torch.cuda.synchronize()
+
+    B.tk_profile_read(reset=True)
+    B.tk_profile_enable(True)
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for _ in range(args.steps):
+        step(ws)
+    torch.cuda.synchronize()
+    t_stop = time.perf_counter()
+    B.tk_profile_enable(False)
+    core_ms, launches = B.tk_profile_read(reset=True)
+    ms_per_step = (t_stop - t_start) * 1e3 / args.steps
+    log(f"timed {args.steps} steps: {ms_per_step:.3f} ms/step; streaming pass "
+        f"{core_ms / max(launches, 1):.3f} ms x {launches}")
+
+    b_sketch = sum(s * n for s, n in zip(ss, dims)) * esize
+    b_core = N * esize
+    value = (b_sketch + b_core) / (ms_per_step * 1e-3) / 1e9
+    core_avg_ms = core_ms / max(launches, 1)
+    achieved = b_core / (core_avg_ms * 1e-3) / 1e9
+
+    eps = T.rel_error(X, G, F, ws=ws)
+    info_h = info.cpu().tolist()
+    log(f"eps_gpu = {eps:.6e}, info = {info_h}")
+
+    result = {
+        "metric": "tensor GB/s streamed (sketch+core), frac of HBM roofline; rel err vs FP64 oracle",
+        "value": round(value, 2),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {"f64": "f64", "f32": "f32", "bf16": "bf16", "f16": "f16"}[dtype],
+        "data": "synthetic",
+        "config": {"workload": f"sub-r-hosvd {cfg.name}", "dims": list(dims),
+                   "ranks": list(ranks), "p": cfg.p, "s": ss, "core_factor": args.core,
+                   "decay": cfg.decay, "noise_rel": cfg.noise},
+        "frac_hbm_step": round(value / HBM_PEAK_GBS, 4),
+        "rel_err_gpu": eps,
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": None, "kernel": "core streaming pass",
+                     "avg_ms": round(core_avg_ms, 4)},
+    }
+    del Y, Z
+    torch.cuda.empty_cache()
+    if not args.no_cpu:
+        result["cpu_baseline"] = cpu_baseline(inp, sk, dims, ranks, cols, dtype, args, F)
+    print(json.dumps(result), flush=True)
+
+
+def cpu_baseline(inp, sk, dims, ranks, cols, dtype, args, F_gpu):
+    """The FP64 oracle on a bounded sample: every mode's sketch, QR and W step
+    at full size, and the core over the first `cpu_slabs` mode-0 slabs of X.
+    Reported as the oracle's own tensor GB/s on that sample."""
+    import numpy as np
+
+    import oracle
+    import synthgen
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    except Exception:  # noqa: BLE001
+        cores = len(os.sched_getaffinity(0))
+    esize = synthgen.itemsize(dtype)
+    to64 = (lambda a: synthgen.to_f64(a, dtype))
+    t0 = time.perf_counter()
+    Us = []
+    for k in range(len(dims)):
+        Y = oracle.gather_fibers(inp.X, k, sk[k].idx, to64=to64)
+        Zk = oracle.range_sketch(Y, sk[k].omega)
+        Q = oracle.orth(Zk)
+        _, U, _ = oracle.w_step(Q, Y, cols[k])
+        Us.append(U)
+    t1 = time.perf_counter()
+    slabs = min(args.cpu_slabs, dims[0])
+    part = oracle.core_streamed(inp.X[:slabs], [Us[0][:slabs]] + Us[1:], to64=to64, slab=1)
+    t2 = time.perf_counter()
+    b_sketch = sum(len(s.idx) * n for s, n in zip(sk, dims)) * esize
+    b_core = slabs * math.prod(dims[1:]) * esize
+    dist = max(oracle.projector_distance(f.double().cpu().numpy(), u) for f, u in zip(F_gpu, Us))
+    del part
+    return {"value": round((b_sketch + b_core) / (t2 - t0) / 1e9, 4), "unit": "GB/s",
+            "cores": int(cores), "kind": "oracle",
+            "sample": f"full sketch+QR+W of every mode, core over {slabs} of {dims[0]} mode-0 slabs",
+            "sketch_s": round(t1 - t0, 3), "core_s": round(t2 - t1, 3),
+            "max_projector_dist_gpu_vs_oracle": dist}
+
+
+if __name__ == "__main__":
+    main()

@@ -210,6 +210,16 @@ tk_status tucker_reconstruct_vjp(int32_t order, const int64_t* dims, int32_t fdt
                                  const void* H, void* Gbar, void* const* Fbar, void* ws,
                                  size_t* ws_bytes, void* stream);
 
+/* Profiling of the streaming pass.  While enabled, every tucker_core,
+ * tucker_reconstruct and htucker_decompose call brackets the kernel that
+ * streams X (the one full read of the tensor) with HIP events recorded on the
+ * call's stream.  tk_profile_read waits for the recorded events, writes the
+ * summed elapsed milliseconds and the number of bracketed launches, and
+ * clears the record when reset != 0.  Returns TK_OK or TK_EDEVICE.
+ * Not thread-safe: profile from one host thread at a time. */
+void tk_profile_enable(int32_t on);
+tk_status tk_profile_read(double* ms, int64_t* launches, int32_t reset);
+
 /* Message for the calling thread's last non-OK status ("" if none). */
 const char* tk_last_error(void);
 

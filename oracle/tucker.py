@@ -16,16 +16,18 @@ import numpy as np
 from .tensor import multi_ttm, unfold
 
 
-def gather_fibers(X: np.ndarray, k: int, idx: np.ndarray) -> np.ndarray:
+def gather_fibers(X: np.ndarray, k: int, idx: np.ndarray, to64=None) -> np.ndarray:
     """Y_k = X^(k) E_k: the columns idx of the mode-k unfolding, taken as
     mode-k fibers of X (Section 3.1).  Column j of X^(k) is the fiber
-    X[a, :, b] of X viewed as (n_{<k}, n_k, n_{>k}) with (a, b) = divmod(j, n_{>k})."""
+    X[a, :, b] of X viewed as (n_{<k}, n_k, n_{>k}) with (a, b) = divmod(j, n_{>k}).
+    `to64` upcasts stored values exactly (applied to the gathered fibers only)."""
+    to64 = to64 or (lambda v: np.asarray(v, dtype=np.float64))
     dims = X.shape
     A = int(np.prod(dims[:k], dtype=np.int64))
     B = int(np.prod(dims[k + 1:], dtype=np.int64))
-    X3 = np.asarray(X, dtype=np.float64).reshape(A, dims[k], B)
+    X3 = X.reshape(A, dims[k], B)
     a, b = np.divmod(np.asarray(idx, dtype=np.int64), B)
-    return X3[a, :, b].T.copy()
+    return to64(X3[a, :, b].T.copy())
 
 
 def range_sketch(Y: np.ndarray, omega: np.ndarray) -> np.ndarray:

@@ -53,7 +53,7 @@ _lock = threading.Lock()
 
 EXPORTS = ("tucker_sketch_all_modes", "tucker_qr", "tucker_core", "tucker_reconstruct",
            "htucker_decompose", "tucker_core_vjp", "tucker_reconstruct_vjp", "tk_last_error",
-           "tk_version")
+           "tk_version", "tk_profile_enable", "tk_profile_read")
 
 
 def lib():
@@ -69,6 +69,10 @@ def lib():
             sz = C.POINTER(C.c_size_t)
             i64p, i32p = C.POINTER(C.c_int64), C.POINTER(C.c_int32)
             L.tk_last_error.restype = C.c_char_p
+            L.tk_profile_enable.argtypes = [C.c_int32]
+            L.tk_profile_enable.restype = None
+            L.tk_profile_read.argtypes = [C.POINTER(C.c_double), C.POINTER(C.c_int64), C.c_int32]
+            L.tk_profile_read.restype = C.c_int
             L.tk_version.restype = C.c_char_p
             sig = {
                 "tucker_sketch_all_modes": [C.POINTER(TkTensor), C.POINTER(TkSketch), pp, pp, vp, sz, vp],
@@ -273,6 +277,17 @@ def tucker_reconstruct_vjp(dims, G, F, H, Gbar=None, Fbar=None, stream=None, ws=
     args = [d, dd, dtype_code(G.dtype), G.data_ptr(), ptr_array(F), cols, H.data_ptr(),
             ptr(Gbar), ptr_array(Fbar) if Fbar is not None else None]
     return _call("tucker_reconstruct_vjp", args, G.device, stream, ws)
+
+
+def tk_profile_enable(on: bool) -> None:
+    lib().tk_profile_enable(1 if on else 0)
+
+
+def tk_profile_read(reset: bool = True):
+    """(summed ms, launches) of the bracketed streaming passes."""
+    ms, n = C.c_double(0), C.c_int64(0)
+    _check("tk_profile_read", lib().tk_profile_read(C.byref(ms), C.byref(n), 1 if reset else 0))
+    return ms.value, n.value
 
 
 def version() -> str:

@@ -28,6 +28,25 @@ tk_status set_error(tk_status s, const char* fmt, ...) {
 }
 void clear_error() { g_last_error.clear(); }
 
+// ------------------------------------------------------------------ profiler
+static bool g_prof_on = false;
+static std::vector<hipEvent_t> g_prof_events;  // start/stop pairs, reused
+static size_t g_prof_used = 0;                 // events recorded since the last reset
+
+bool profiling() { return g_prof_on; }
+
+static hipError_t prof_record(hipStream_t st) {
+  if (g_prof_used == g_prof_events.size()) {
+    hipEvent_t e;
+    hipError_t r = hipEventCreate(&e);
+    if (r != hipSuccess) return r;
+    g_prof_events.push_back(e);
+  }
+  return hipEventRecord(g_prof_events[g_prof_used++], st);
+}
+hipError_t profile_begin(hipStream_t st) { return g_prof_on ? prof_record(st) : hipSuccess; }
+hipError_t profile_end(hipStream_t st) { return g_prof_on ? prof_record(st) : hipSuccess; }
+
 namespace {
 
 bool valid_dtype(int dt) { return dt == TK_F64 || dt == TK_F32 || dt == TK_BF16 || dt == TK_F16; }
@@ -184,7 +203,10 @@ tk_status run_core(const void* X, int xdt, int order, const int64_t* dims,
     mp.cs = cols[k];
     void* out = k == 0 ? G : (void*)p.buf[(order - 1 - k) & 1];
     mp.out = out;
+    const bool streaming = k == order - 1;  // the launch that reads X
+    if (streaming) TK_HIP(profile_begin(st));
     TK_HIP(launch_mode_product(mp, cur_dt, k == 0 ? fdt : TK_F64, fdt, st));
+    if (streaming) TK_HIP(profile_end(st));
     shape[k] = cols[k];
     cur = out;
     cur_dt = TK_F64;
@@ -202,6 +224,24 @@ using namespace tk;
 extern "C" {
 
 const char* tk_last_error(void) { return g_last_error.c_str(); }
+
+void tk_profile_enable(int32_t on) { g_prof_on = on != 0; }
+
+tk_status tk_profile_read(double* ms, int64_t* launches, int32_t reset) {
+  clear_error();
+  double total = 0.0;
+  const size_t pairs = g_prof_used / 2;
+  for (size_t i = 0; i < pairs; ++i) {
+    TK_HIP(hipEventSynchronize(g_prof_events[2 * i + 1]));
+    float t = 0.0f;
+    TK_HIP(hipEventElapsedTime(&t, g_prof_events[2 * i], g_prof_events[2 * i + 1]));
+    total += t;
+  }
+  if (ms) *ms = total;
+  if (launches) *launches = (int64_t)pairs;
+  if (reset) g_prof_used = 0;
+  return TK_OK;
+}
 const char* tk_version(void) { return "tkmi 0.1 (gfx950)"; }
 
 tk_status tucker_sketch_all_modes(const tk_tensor* X, const tk_sketch* sk, double* const* Z,
@@ -380,7 +420,9 @@ tk_status tucker_reconstruct(int32_t order, const int64_t* dims, int32_t fdtype,
   e.A = A_last;
   e.n = dims[order - 1];
   e.c = cols[order - 1];
+  TK_HIP(profile_begin(st));
   TK_HIP(launch_expand_residual(e, Xref ? Xref->dtype : fdtype, fdtype, st));
+  TK_HIP(profile_end(st));
   return TK_OK;
 }
 
@@ -520,7 +562,9 @@ tk_status htucker_decompose(const tk_tensor* X, const tk_tree* tree, const int32
     mp.rs = 1;
     mp.cs = rank[R];
     mp.out = t1;
+    TK_HIP(profile_begin(st));
     TK_HIP(launch_mode_product(mp, X->dtype, TK_F64, fdt, st));
+    TK_HIP(profile_end(st));
     ModeProduct m2{};
     m2.in = t1;
     m2.A = 1;

@@ -66,6 +66,11 @@ struct Workspace {
 
 inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
+// Streaming-pass profiler (tk_profile_enable / tk_profile_read).
+bool profiling();
+hipError_t profile_begin(hipStream_t st);  // record the start event of one bracket
+hipError_t profile_end(hipStream_t st);    // record its stop event
+
 }  // namespace tk
 
 #define TK_HIP(expr)                                                                  \
