@@ -145,7 +145,7 @@ def main():
     core_avg_ms = core_ms / max(launches, 1)
     achieved = b_core / (core_avg_ms * 1e-3) / 1e9
 
-    eps = T.rel_error(X, G, F, ws=ws)
+    eps = T.rel_error(X, G, F)
     info_h = info.cpu().tolist()
     log(f"eps_gpu = {eps:.6e}, info = {info_h}")
 

@@ -269,6 +269,13 @@ __global__ __launch_bounds__(256) void mgram_kernel(const QRBatch b) {
 
 // Cyclic Jacobi (parallel round-robin ordering) on the summed ell x ell Gram;
 // W = eigenvectors of the r largest eigenvalues, in descending order.
+// Lane j owns column j of the row updates and row j of the column updates, so
+// a round is three passes over the ell/2 disjoint rotations with no index
+// arithmetic.  A rotation is skipped once |a_pq| <= 4 u max(|a_pp|, |a_qq|):
+// the rotation it would apply is then below rounding level relative to the
+// pair's own scale (so a signal/noise pair is decoupled to ~u), while the
+// stricter test |a_pq| <= u sqrt(a_pp a_qq) can be unreachable in floating
+// point for strongly graded pairs.
 __global__ __launch_bounds__(64) void eig_kernel(const QRBatch b) {
   const QRMat& M = b.m[blockIdx.x];
   __shared__ double A[kMaxEll][kMaxEll + 1];
@@ -293,12 +300,16 @@ __global__ __launch_bounds__(64) void eig_kernel(const QRBatch b) {
       if (lane < half) {
         int p, q;
         if (lane == 0) { p = np - 1; q = round; }
-        else { p = (round + lane) % (np - 1); q = (round - lane + np - 1) % (np - 1); }
+        else {
+          p = round + lane; if (p >= np - 1) p -= np - 1;
+          q = round - lane; if (q < 0) q += np - 1;
+        }
         if (p > q) { const int t = p; p = q; q = t; }
         double c = 1.0, s = 0.0;
         if (q < n) {
           const double apq = A[p][q], app = A[p][p], aqq = A[q][q];
-          if (apq != 0.0 && fabs(apq) > 2.0 * kUnit * sqrt(fabs(app * aqq))) {
+          const double aa = fabs(apq);
+          if (aa > 4.0 * kUnit * fmax(fabs(app), fabs(aqq))) {
             const double th = (aqq - app) / (2.0 * apq);
             const double t = (th >= 0.0 ? 1.0 : -1.0) / (fabs(th) + sqrt(1.0 + th * th));
             c = 1.0 / sqrt(1.0 + t * t);
@@ -309,28 +320,34 @@ __global__ __launch_bounds__(64) void eig_kernel(const QRBatch b) {
         rc_[lane] = c; rs_[lane] = s; rp_[lane] = p; rq_[lane] = q;
       }
       __syncthreads();
-      for (int e = lane; e < half * np; e += 64) {   // rows: A <- J^T A
-        const int k = e / np, j = e - k * np;
-        const double c = rc_[k], s = rs_[k];
-        if (s != 0.0) {
-          const int p = rp_[k], q = rq_[k];
-          const double apj = A[p][j], aqj = A[q][j];
-          A[p][j] = c * apj - s * aqj;
-          A[q][j] = s * apj + c * aqj;
+      if (lane < np) {          // rows p, q of every pair: A <- J^T A
+        const int j = lane;
+        for (int k = 0; k < half; ++k) {
+          const double s = rs_[k];
+          if (s != 0.0) {
+            const double c = rc_[k];
+            const int p = rp_[k], q = rq_[k];
+            const double apj = A[p][j], aqj = A[q][j];
+            A[p][j] = c * apj - s * aqj;
+            A[q][j] = s * apj + c * aqj;
+          }
         }
       }
       __syncthreads();
-      for (int e = lane; e < half * np; e += 64) {   // columns: A <- A J, V <- V J
-        const int k = e / np, i = e - k * np;
-        const double c = rc_[k], s = rs_[k];
-        if (s != 0.0) {
-          const int p = rp_[k], q = rq_[k];
-          const double aip = A[i][p], aiq = A[i][q];
-          A[i][p] = c * aip - s * aiq;
-          A[i][q] = s * aip + c * aiq;
-          const double vip = V[i][p], viq = V[i][q];
-          V[i][p] = c * vip - s * viq;
-          V[i][q] = s * vip + c * viq;
+      if (lane < np) {          // columns p, q: A <- A J, V <- V J
+        const int i = lane;
+        for (int k = 0; k < half; ++k) {
+          const double s = rs_[k];
+          if (s != 0.0) {
+            const double c = rc_[k];
+            const int p = rp_[k], q = rq_[k];
+            const double aip = A[i][p], aiq = A[i][q];
+            A[i][p] = c * aip - s * aiq;
+            A[i][q] = s * aip + c * aiq;
+            const double vip = V[i][p], viq = V[i][q];
+            V[i][p] = c * vip - s * viq;
+            V[i][q] = s * vip + c * viq;
+          }
         }
       }
       __syncthreads();

@@ -98,8 +98,21 @@ __global__ __launch_bounds__(256) void mode_strided_kernel(const ModeProduct mp)
     }
     __syncthreads();
     if (live) {
-      for (int qq = 0; qq < qn; ++qq) {
-        const double x = to_double(in[(a * mp.Q + q0 + qq) * mp.B + bb]);
+      // loads of 8 rows are issued together so their latencies overlap
+      const TIn* src = in + (a * mp.Q + q0) * mp.B + bb;
+      int qq = 0;
+      for (; qq + 8 <= qn; qq += 8) {
+        double x[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) x[u] = to_double(src[(int64_t)(qq + u) * mp.B]);
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+#pragma unroll
+          for (int k = 0; k < PMAX; ++k) acc[k] = fma(x[u], sM[qq + u][k], acc[k]);
+        }
+      }
+      for (; qq < qn; ++qq) {
+        const double x = to_double(src[(int64_t)qq * mp.B]);
 #pragma unroll
         for (int k = 0; k < PMAX; ++k) acc[k] = fma(x, sM[qq][k], acc[k]);
       }
@@ -123,18 +136,22 @@ template <typename TIn, typename TOut, typename TM>
 hipError_t mode_product(const ModeProduct& mp, hipStream_t st) {
   if (mp.A == 0 || mp.B == 0) return hipSuccess;
   if (mp.P < 1) return hipSuccess;
-  const bool narrow = mp.P <= 16;
-  const unsigned pchunks = (unsigned)ceil_div(mp.P, narrow ? 16 : 64);
+  const int width = mp.P <= 16 ? 16 : mp.P <= 32 ? 32 : 64;
+  const unsigned pchunks = (unsigned)ceil_div(mp.P, width);
   if (mp.B == 1) {
     const dim3 grid((unsigned)ceil_div(mp.A, 64), pchunks);
-    if (narrow)
+    if (width == 16)
       hipLaunchKernelGGL((mode_rows_kernel<TIn, TOut, TM, 16>), grid, dim3(256), 0, st, mp);
+    else if (width == 32)
+      hipLaunchKernelGGL((mode_rows_kernel<TIn, TOut, TM, 32>), grid, dim3(256), 0, st, mp);
     else
       hipLaunchKernelGGL((mode_rows_kernel<TIn, TOut, TM, 64>), grid, dim3(256), 0, st, mp);
   } else {
     const dim3 grid((unsigned)ceil_div(mp.A * mp.B, 256), pchunks);
-    if (narrow)
+    if (width == 16)
       hipLaunchKernelGGL((mode_strided_kernel<TIn, TOut, TM, 16>), grid, dim3(256), 0, st, mp);
+    else if (width == 32)
+      hipLaunchKernelGGL((mode_strided_kernel<TIn, TOut, TM, 32>), grid, dim3(256), 0, st, mp);
     else
       hipLaunchKernelGGL((mode_strided_kernel<TIn, TOut, TM, 64>), grid, dim3(256), 0, st, mp);
   }

@@ -165,17 +165,27 @@ tk_status check_factors(int order, const int64_t* dims, const void* const* F, co
   return TK_OK;
 }
 
-// Chain of contractions G = X x_k F_k^T, last mode first.  Intermediates are FP64.
+// Chain of contractions G = X x_k F_k^T, last mode first.  Intermediates are
+// FP64, except the output of the fused FP32 streaming pass (FP32, A x c x c).
 struct CorePlan {
   double* buf[2] = {nullptr, nullptr};
+  float* t32 = nullptr;
+  bool fused = false;
 };
 
-tk_status plan_core(Workspace& ws, int order, const int64_t* dims, const int32_t* cols,
+tk_status plan_core(Workspace& ws, int xdt, int order, const int64_t* dims, const int32_t* cols,
                     CorePlan& p) {
   int64_t shape[TK_MAX_ORDER];
   for (int k = 0; k < order; ++k) shape[k] = dims[k];
+  p.fused = fused2_supported(xdt, order, dims, cols);
   int64_t mx = 0;
-  for (int k = order - 1; k >= 1; --k) {
+  const int first = p.fused ? order - 3 : order - 1;
+  if (p.fused) {
+    shape[order - 1] = cols[order - 1];
+    shape[order - 2] = cols[order - 2];
+    p.t32 = ws.take<float>((size_t)prod(shape, 0, order));
+  }
+  for (int k = first; k >= 1; --k) {
     shape[k] = cols[k];
     mx = std::max(mx, prod(shape, 0, order));
   }
@@ -191,7 +201,29 @@ tk_status run_core(const void* X, int xdt, int order, const int64_t* dims,
   for (int k = 0; k < order; ++k) shape[k] = dims[k];
   const void* cur = X;
   int cur_dt = xdt;
-  for (int k = order - 1; k >= 0; --k) {
+  int kstart = order - 1;
+  if (p.fused) {
+    // the two trailing modes in one MFMA pass over X
+    CoreFused2 f{};
+    f.X = static_cast<const float*>(X);
+    f.FI = static_cast<const float*>(F[order - 2]);
+    f.FJ = static_cast<const float*>(F[order - 1]);
+    f.T = p.t32;
+    f.A = prod(dims, 0, order - 2);
+    f.nI = (int32_t)dims[order - 2];
+    f.nJ = (int32_t)dims[order - 1];
+    f.cI = cols[order - 2];
+    f.cJ = cols[order - 1];
+    TK_HIP(profile_begin(st));
+    TK_HIP(launch_fused2_f32(f, st));
+    TK_HIP(profile_end(st));
+    shape[order - 1] = cols[order - 1];
+    shape[order - 2] = cols[order - 2];
+    cur = p.t32;
+    cur_dt = TK_F32;
+    kstart = order - 3;
+  }
+  for (int k = kstart; k >= 0; --k) {
     ModeProduct mp{};
     mp.in = cur;
     mp.A = prod(shape, 0, k);
@@ -201,9 +233,9 @@ tk_status run_core(const void* X, int xdt, int order, const int64_t* dims,
     mp.M = F[k];
     mp.rs = 1;          // M[p][q] = F[q][p]
     mp.cs = cols[k];
-    void* out = k == 0 ? G : (void*)p.buf[(order - 1 - k) & 1];
+    void* out = k == 0 ? G : (void*)p.buf[(kstart - k) & 1];
     mp.out = out;
-    const bool streaming = k == order - 1;  // the launch that reads X
+    const bool streaming = k == order - 1 && !p.fused;  // the launch that reads X
     if (streaming) TK_HIP(profile_begin(st));
     TK_HIP(launch_mode_product(mp, cur_dt, k == 0 ? fdt : TK_F64, fdt, st));
     if (streaming) TK_HIP(profile_end(st));
@@ -327,7 +359,7 @@ tk_status tucker_core(const tk_tensor* X, const void* const* F, const int32_t* c
   Workspace w;
   w.base = static_cast<char*>(ws);
   CorePlan p;
-  plan_core(w, X->order, X->dims, cols, p);
+  plan_core(w, X->dtype, X->order, X->dims, cols, p);
   if (!ws) {
     *ws_bytes = w.off;
     return TK_OK;

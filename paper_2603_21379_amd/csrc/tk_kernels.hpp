@@ -97,6 +97,21 @@ struct ExpandResidual {
 int64_t expand_residual_blocks(int64_t total);
 hipError_t launch_expand_residual(const ExpandResidual& e, int x_dt, int f_dt, hipStream_t st);
 
+// ---------------------------------------------------------------- FP32 fused streaming core
+// T[a] = F_I^T X[a] F_J for the A slabs X[a] (n_I x n_J) of an FP32 tensor.
+struct CoreFused2 {
+  const float* X;
+  const float* FI;     // n_I x c_I
+  const float* FJ;     // n_J x c_J
+  float* T;            // A x c_I x c_J
+  int64_t A;
+  int32_t nI, nJ, cI, cJ;
+  int32_t nwaves;      // set by the launcher: waves in the grid
+  int32_t pad;
+};
+bool fused2_supported(int dtype, int order, const int64_t* dims, const int32_t* cols);
+hipError_t launch_fused2_f32(const CoreFused2& p, hipStream_t st);
+
 // ---------------------------------------------------------------- H-Tucker transfers
 // B[i][j][k] = sum_{a,b} US[a*nr + b][i] Ul[a][j] Ur[b][k]
 struct Transfer {

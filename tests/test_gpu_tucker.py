@@ -186,3 +186,15 @@ def test_bitwise_repeatable():
     assert torch.equal(a.G, b.G)
     for x, y in zip(a.F, b.F):
         assert torch.equal(x, y)
+
+
+@pytest.mark.parametrize("dims,ranks", [
+    ((16, 20, 30, 132), (5, 6, 12, 20)),     # two column blocks, the second 4 wide
+    ((8, 40, 33, 96), (4, 7, 32, 32)),       # odd rows, one partial block, full 32 ranks
+    ((4, 64, 256, 256), (4, 16, 32, 32)),    # the 256^4 slab shape
+])
+def test_fp32_fused_streaming_core(dims, ranks):
+    """The FP32 MFMA streaming pass (two trailing modes per read of X) against
+    the oracle core on the same factors, and the end-to-end error gate."""
+    o = run_case(dims, ranks, 0.8, 1e-4, 6, synthgen.default_s(dims), "f32", 61)
+    check_common(o, "f32", 1e-5)
