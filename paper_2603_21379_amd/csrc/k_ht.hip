@@ -32,6 +32,7 @@ hipError_t launch_transfer(const Transfer& t, int f_dt, hipStream_t st) {
   mp.in = t.US;
   mp.out = t.V;
   mp.M = t.Ur;
+  mp.Mt = t.Mt;
   mp.A = t.nl;
   mp.Q = t.nr;
   mp.B = t.rS;

@@ -18,7 +18,7 @@ constexpr double kUnit = 1.1102230246251565e-16;  // 2^-53
 __global__ __launch_bounds__(256) void gram_partial_kernel(const QRBatch b, int pass) {
   const QRMat& M = b.m[blockIdx.y];
   const int rc = blockIdx.x;
-  if (rc >= M.nrc) return;
+  if (rc >= M.nrc || M.small) return;
   if (pass > 1 && M.state[0] == 0) return;
   __shared__ double sZ[64][kMaxEll + 1];
   const int ell = M.ell, tid = threadIdx.x;
@@ -87,6 +87,7 @@ __device__ bool cholesky_upper(double (*G)[kMaxEll + 1], int n, int lane, double
 // pass leaves two owed); state[1]: whether this pass applies R^{-1}.
 __global__ __launch_bounds__(64) void chol_kernel(const QRBatch b, int pass) {
   const QRMat& M = b.m[blockIdx.x];
+  if (M.small) return;
   if (pass > 1 && M.state[0] == 0) {
     if (threadIdx.x == 0) M.state[1] = 0;
     return;
@@ -165,7 +166,7 @@ __global__ __launch_bounds__(64) void chol_kernel(const QRBatch b, int pass) {
 __global__ __launch_bounds__(64) void apply_rinv_kernel(const QRBatch b, int pass) {
   const QRMat& M = b.m[blockIdx.y];
   const int rb = blockIdx.x;
-  if (rb >= M.nrb) return;
+  if (rb >= M.nrb || M.small) return;
   if (M.state[1] == 0) return;
   (void)pass;
   __shared__ double R[kMaxEll][kMaxEll + 1];
@@ -193,8 +194,216 @@ __global__ __launch_bounds__(64) void apply_rinv_kernel(const QRBatch b, int pas
   }
 }
 
+// ------------------------------------------------------------------ small matrices
+// Every CholeskyQR pass of one matrix in one 256-thread workgroup (m x ell <=
+// kQRSmallElems): Gram from 32-row chunks staged in LDS, Cholesky in LDS, and
+// Q = Z R^{-1} by forward substitution with each row held in registers.
+// Same passes, shift rule and info bits as the multi-kernel path.
+constexpr int kSmallChunk = 32;
+
+// Within one wavefront LDS operations complete in issue order, so lanes of
+// that wave only need the compiler kept from reordering across this point.
+#define TK_WAVE_SYNC()                          \
+  do {                                          \
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);    \
+    __builtin_amdgcn_wave_barrier();            \
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);    \
+  } while (0)
+
+// Upper Cholesky factor in place, by the 64 lanes of one wave (no barriers).
+__device__ bool cholesky_upper_wave(double (*G)[kMaxEll + 1], int n, int lane, double tol) {
+  for (int j = 0; j < n; ++j) {
+    const double piv = G[j][j];
+    if (!(piv > tol)) return false;  // uniform: every lane read the same pivot
+    const double rjj = sqrt(piv), inv = 1.0 / rjj;
+    TK_WAVE_SYNC();
+    for (int i = j + 1 + lane; i < n; i += 64) G[j][i] *= inv;
+    if (lane == 0) G[j][j] = rjj;
+    TK_WAVE_SYNC();
+    const int m = n - j - 1;
+    for (int e = lane; e < m * m; e += 64) {
+      const int p = j + 1 + e / m, q = j + 1 + e % m;
+      if (q >= p) G[p][q] -= G[j][p] * G[j][q];
+    }
+    TK_WAVE_SYNC();
+  }
+  return true;
+}
+
+// In-place inverse of the upper triangular R by one wave (as LAPACK's
+// unblocked trti2): column j of R^{-1} is -R^{-1}_{jj} R^{-1}(0:j, 0:j) R(0:j, j).
+__device__ void upper_inverse_wave(double (*R)[kMaxEll + 1], int n, int lane) {
+  for (int j = 0; j < n; ++j) {
+    const double rjj = 1.0 / R[j][j];
+    TK_WAVE_SYNC();
+    // four independent partial sums so the LDS reads pipeline
+    double x0 = 0.0, x1 = 0.0, x2 = 0.0, x3 = 0.0;
+    if (lane < j) {
+      int k = lane;
+      for (; k + 4 <= j; k += 4) {
+        x0 = fma(R[lane][k], R[k][j], x0);
+        x1 = fma(R[lane][k + 1], R[k + 1][j], x1);
+        x2 = fma(R[lane][k + 2], R[k + 2][j], x2);
+        x3 = fma(R[lane][k + 3], R[k + 3][j], x3);
+      }
+      for (; k < j; ++k) x0 = fma(R[lane][k], R[k][j], x0);
+    }
+    const double x = (x0 + x1) + (x2 + x3);
+    TK_WAVE_SYNC();
+    if (lane < j) R[lane][j] = -rjj * x;
+    if (lane == 0) R[j][j] = rjj;
+    TK_WAVE_SYNC();
+  }
+}
+
+// Q = Z R^{-1} in place, 32 rows at a time: the rows are staged in LDS
+// (coalesced, zero padded to 64 columns), thread t forms the 4 x 4 output
+// tile (rows 4 (t / 16), columns 4 (t % 16)) from LDS, then writes it.
+__device__ void apply_inverse_block(const QRMat& M, double (*Ri)[kMaxEll + 1],
+                                    double (*sZ)[kMaxEll + 1], int tid) {
+  const int n = M.ell;
+  const int ti = tid >> 4, tj = tid & 15;  // 8 row groups x 16 column groups
+  for (int64_t r0 = 0; r0 < M.m; r0 += kSmallChunk) {
+    const int rows = (int)min<int64_t>(kSmallChunk, M.m - r0);
+    for (int e = tid; e < kSmallChunk * kMaxEll; e += 256) {
+      const int rr = e / kMaxEll, j = e - rr * kMaxEll;
+      sZ[rr][j] = (rr < rows && j < n) ? M.Z[(r0 + rr) * n + j] : 0.0;
+    }
+    __syncthreads();
+    double acc[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) acc[a][c] = 0.0;
+    const int jmax = min(n, 4 * tj + 4);   // R^{-1} is upper triangular: k <= j
+#pragma unroll 4
+    for (int k = 0; k < jmax; ++k) {
+      double z[4], w[4];
+#pragma unroll
+      for (int a = 0; a < 4; ++a) z[a] = sZ[4 * ti + a][k];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) w[c] = (4 * tj + c < n) ? Ri[k][4 * tj + c] : 0.0;
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) acc[a][c] = fma(z[a], w[c], acc[a][c]);
+    }
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+      const int rr = 4 * ti + a;
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        const int j = 4 * tj + c;
+        if (rr < rows && j < n) M.Z[(r0 + rr) * n + j] = acc[a][c];
+      }
+    }
+    __syncthreads();
+  }
+}
+
+__global__ __launch_bounds__(256) void cholqr_small_kernel(const QRBatch b) {
+  const QRMat& M = b.m[blockIdx.x];
+  if (!M.small) return;
+  __shared__ double G[kMaxEll][kMaxEll + 1];
+  __shared__ double G0[kMaxEll][kMaxEll + 1];  // the unshifted Gram, kept for a shifted retry
+  __shared__ double sZ[kSmallChunk][kMaxEll + 1];
+  __shared__ double red[2];
+  __shared__ int ok;
+  const int n = M.ell, tid = threadIdx.x;
+  int owed = 2, info = 0;
+  for (int pass = 1; pass <= kQRMaxPasses && owed > 0; ++pass) {
+    // Gram: thread t owns the 4 x 4 tile (4 (t / 16), 4 (t % 16)) of G, so a
+    // row of the chunk costs 8 LDS reads for 16 FMAs
+    const int ti = tid >> 4, tj = tid & 15;
+    double acc[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) acc[a][c] = 0.0;
+    for (int64_t r0 = 0; r0 < M.m; r0 += kSmallChunk) {
+      const int rows = (int)min<int64_t>(kSmallChunk, M.m - r0);
+      __syncthreads();
+      for (int e = tid; e < kSmallChunk * kMaxEll; e += 256) {
+        const int rr = e / kMaxEll, j = e - rr * kMaxEll;
+        sZ[rr][j] = (rr < rows && j < n) ? M.Z[(r0 + rr) * n + j] : 0.0;
+      }
+      __syncthreads();
+#pragma unroll 4
+      for (int rr = 0; rr < rows; ++rr) {
+        double x[4], y[4];
+#pragma unroll
+        for (int a = 0; a < 4; ++a) x[a] = sZ[rr][4 * ti + a];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) y[c] = sZ[rr][4 * tj + c];
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+          for (int c = 0; c < 4; ++c) acc[a][c] = fma(x[a], y[c], acc[a][c]);
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        const int p = 4 * ti + a, q = 4 * tj + c;
+        if (p < n && q < n) G[p][q] = G0[p][q] = acc[a][c];
+      }
+    __syncthreads();
+    if (tid == 0) {
+      double mx = 0.0, tr = 0.0;
+      for (int j = 0; j < n; ++j) { mx = fmax(mx, G[j][j]); tr += G[j][j]; }
+      red[0] = mx;
+      red[1] = tr;
+    }
+    __syncthreads();
+    const double mx = red[0], tr = red[1];
+    // Cholesky (+ shifted retry) and the triangular inverse by wave 0
+    if (tid < 64) {
+      int st = 0;
+      bool good = mx > 0.0 && cholesky_upper_wave(G, n, tid, 1e-14 * mx);
+      if (!good) {
+        const double shift =
+            11.0 * ((double)M.m * n + (double)n * (n + 1)) * kUnit * fmax(tr, 1e-300);
+        TK_WAVE_SYNC();
+        for (int e = tid; e < n * n; e += 64)
+          G[e / n][e % n] = G0[e / n][e % n] + (e / n == e % n ? shift : 0.0);
+        TK_WAVE_SYNC();
+        st = 1;
+        good = cholesky_upper_wave(G, n, tid, 0.0);
+        if (!good) {
+          st = 2;
+          TK_WAVE_SYNC();
+          for (int j = tid; j < n; j += 64)
+            if (!(G[j][j] > 0.0)) G[j][j] = 1.0;  // keep the solve finite; flagged
+          TK_WAVE_SYNC();
+        }
+      }
+      // zero the strict lower triangle left over from the Gram
+      for (int e = tid; e < n * n; e += 64)
+        if (e / n > e % n) G[e / n][e % n] = 0.0;
+      TK_WAVE_SYNC();
+      upper_inverse_wave(G, n, tid);
+      if (tid == 0) ok = st;
+    }
+    __syncthreads();
+    const int status = ok;
+    apply_inverse_block(M, G, sZ, tid);
+    if (status != 0) info |= pass == 1 ? 1 : 2;
+    if (status == 2) info |= 4;
+    owed = status != 0 ? 2 : owed - 1;
+  }
+  if (tid == 0) {
+    if (M.info) *M.info = info;
+    M.state[0] = 0;
+    M.state[1] = 0;
+  }
+}
+
 // ------------------------------------------------------------------ W step
-// mpart[rc][p][t] = sum_{rows in rc} Q[row][p] Y[row][t], t in column chunk cc
+// mpart[rc][p][t] = sum_{rows in rc} Q[row][p] Y[row][t], t in column chunk cc.
+// Each thread owns a 4 x 4 register tile (p = 4 pr + i, t = 4 tc + j), so an
+// FMA costs half an LDS read instead of two.
 template <typename TY>
 __global__ __launch_bounds__(256) void qty_partial_kernel(const QRBatch b) {
   const QRMat& M = b.m[blockIdx.z];
@@ -203,42 +412,49 @@ __global__ __launch_bounds__(256) void qty_partial_kernel(const QRBatch b) {
   __shared__ double sQ[64][kMaxEll + 1];
   __shared__ double sY[64][kQRColChunk + 1];
   const int ell = M.ell, tid = threadIdx.x;
+  const int pr = tid >> 4, tc = tid & 15;   // 16 x 16 threads over 64 x 64 outputs
   const TY* Y = static_cast<const TY*>(M.Y);
   const int64_t t0 = (int64_t)cc * kQRColChunk;
   const int cols = (int)min<int64_t>(kQRColChunk, M.s - t0);
   const int64_t r0 = (int64_t)rc * kQRRowChunk;
   const int64_t r1 = min<int64_t>(M.m, r0 + kQRRowChunk);
-  double acc[16];
+  double acc[4][4];
 #pragma unroll
-  for (int q = 0; q < 16; ++q) acc[q] = 0.0;
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
   for (int64_t s0 = r0; s0 < r1; s0 += 64) {
     const int rows = (int)min<int64_t>(64, r1 - s0);
     __syncthreads();
-    for (int e = tid; e < 64 * ell; e += 256) {
-      const int rr = e / ell, j = e - rr * ell;
-      sQ[rr][j] = rr < rows ? M.Z[(s0 + rr) * ell + j] : 0.0;
+    for (int e = tid; e < 64 * kMaxEll; e += 256) {
+      const int rr = e / kMaxEll, j = e - rr * kMaxEll;
+      sQ[rr][j] = (rr < rows && j < ell) ? M.Z[(s0 + rr) * ell + j] : 0.0;
     }
     for (int e = tid; e < 64 * kQRColChunk; e += 256) {
       const int rr = e / kQRColChunk, t = e - rr * kQRColChunk;
       sY[rr][t] = (rr < rows && t < cols) ? to_double(Y[(s0 + rr) * M.s + t0 + t]) : 0.0;
     }
     __syncthreads();
+    for (int rr = 0; rr < rows; ++rr) {
+      double q[4], y[4];
 #pragma unroll
-    for (int q = 0; q < 16; ++q) {
-      const int e = tid + 256 * q;  // e = p * 64 + t
-      const int p = e >> 6, t = e & 63;
-      if (p < ell) {
-        double a = acc[q];
-        for (int rr = 0; rr < rows; ++rr) a = fma(sQ[rr][p], sY[rr][t], a);
-        acc[q] = a;
-      }
+      for (int i = 0; i < 4; ++i) q[i] = sQ[rr][4 * pr + i];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) y[j] = sY[rr][4 * tc + j];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = fma(q[i], y[j], acc[i][j]);
     }
   }
 #pragma unroll
-  for (int q = 0; q < 16; ++q) {
-    const int e = tid + 256 * q;
-    const int p = e >> 6, t = e & 63;
-    if (p < ell && t < cols) M.mpart[((int64_t)rc * ell + p) * M.s + t0 + t] = acc[q];
+  for (int i = 0; i < 4; ++i) {
+    const int p = 4 * pr + i;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int t = 4 * tc + j;
+      if (p < ell && t < cols) M.mpart[((int64_t)rc * ell + p) * M.s + t0 + t] = acc[i][j];
+    }
   }
 }
 
@@ -269,22 +485,30 @@ __global__ __launch_bounds__(256) void mgram_kernel(const QRBatch b) {
 
 // Cyclic Jacobi (parallel round-robin ordering) on the summed ell x ell Gram;
 // W = eigenvectors of the r largest eigenvalues, in descending order.
-// Lane j owns column j of the row updates and row j of the column updates, so
-// a round is three passes over the ell/2 disjoint rotations with no index
-// arithmetic.  A rotation is skipped once |a_pq| <= 4 u max(|a_pp|, |a_qq|):
-// the rotation it would apply is then below rounding level relative to the
-// pair's own scale (so a signal/noise pair is decoupled to ~u), while the
-// stricter test |a_pq| <= u sqrt(a_pp a_qq) can be unreachable in floating
-// point for strongly graded pairs.
-__global__ __launch_bounds__(64) void eig_kernel(const QRBatch b) {
+// One 256-thread workgroup per matrix: each round computes the ell/2
+// disjoint rotations, then applies them to rows (A <- J^T A) and to columns
+// (A <- A J, V <- V J); every thread owns a fixed set of (pair, index) items,
+// precomputed once, so a round is three barriers and a few FMAs per thread.
+// A rotation is skipped once |a_pq| <= 4 u max(|a_pp|, |a_qq|): the rotation
+// it would apply is then below rounding level relative to the pair's own
+// scale (a signal/noise pair is decoupled to ~u), whereas the stricter test
+// |a_pq| <= u sqrt(a_pp a_qq) can be unreachable in floating point for
+// strongly graded pairs.
+constexpr int kEigThreads = 256;
+constexpr int kEigItems = ((kMaxEll / 2) * (kMaxEll / 2) + kMaxEll * (kMaxEll / 2)) / kEigThreads;
+
+__global__ __launch_bounds__(kEigThreads) void eig_kernel(const QRBatch b) {
   const QRMat& M = b.m[blockIdx.x];
   __shared__ double A[kMaxEll][kMaxEll + 1];
   __shared__ double V[kMaxEll][kMaxEll + 1];
   __shared__ double rc_[kMaxEll / 2], rs_[kMaxEll / 2];
   __shared__ int rp_[kMaxEll / 2], rq_[kMaxEll / 2];
   __shared__ int rotations;
-  const int n = M.ell, np = n + (n & 1), half = np / 2, lane = threadIdx.x;
-  for (int e = lane; e < np * np; e += 64) {
+  const int n = M.ell, np = n + (n & 1), half = np / 2, tid = threadIdx.x;
+  // rotations stop below rounding level of the output precision (relative to
+  // the pair's own scale): FP64 bases need ~u, FP32 bases ~1e-12 suffices
+  const double tol = M.udtype == TK_F64 ? 4.0 * kUnit : 1e-12;
+  for (int e = tid; e < np * np; e += kEigThreads) {
     const int p = e / np, q = e - p * np;
     double v = 0.0;
     if (p < n && q < n)
@@ -292,24 +516,38 @@ __global__ __launch_bounds__(64) void eig_kernel(const QRBatch b) {
     A[p][q] = v;
     V[p][q] = p == q ? 1.0 : 0.0;
   }
+  // this thread's items: first the half x half 2x2 blocks of A (pair k1 rows,
+  // pair k2 columns: A <- J^T A J on the block), then the np x half column
+  // pairs of V (V <- V J); code = k1 * 64 + k2 + 1, or -(k * 64 + i) - 1
+  int item[kEigItems];
+  const int nblk = half * half, nitems = nblk + np * half;
+#pragma unroll
+  for (int t = 0; t < kEigItems; ++t) {
+    const int e = tid + kEigThreads * t;
+    if (e >= nitems) item[t] = 0;
+    else if (e < nblk) item[t] = (e / half) * 64 + (e % half) + 1;
+    else {
+      const int f = e - nblk;
+      item[t] = -(((f / np) * 64) + (f % np)) - 1;
+    }
+  }
   __syncthreads();
-  for (int sweep = 0; sweep < 40; ++sweep) {
-    if (lane == 0) rotations = 0;
+  for (int sweep = 0; sweep < 60; ++sweep) {
+    if (tid == 0) rotations = 0;
     __syncthreads();
     for (int round = 0; round < np - 1; ++round) {
-      if (lane < half) {
+      if (tid < half) {
         int p, q;
-        if (lane == 0) { p = np - 1; q = round; }
+        if (tid == 0) { p = np - 1; q = round; }
         else {
-          p = round + lane; if (p >= np - 1) p -= np - 1;
-          q = round - lane; if (q < 0) q += np - 1;
+          p = round + tid; if (p >= np - 1) p -= np - 1;
+          q = round - tid; if (q < 0) q += np - 1;
         }
         if (p > q) { const int t = p; p = q; q = t; }
         double c = 1.0, s = 0.0;
         if (q < n) {
           const double apq = A[p][q], app = A[p][p], aqq = A[q][q];
-          const double aa = fabs(apq);
-          if (aa > 4.0 * kUnit * fmax(fabs(app), fabs(aqq))) {
+          if (fabs(apq) > tol * fmax(fabs(app), fabs(aqq))) {
             const double th = (aqq - app) / (2.0 * apq);
             const double t = (th >= 0.0 ? 1.0 : -1.0) / (fabs(th) + sqrt(1.0 + th * th));
             c = 1.0 / sqrt(1.0 + t * t);
@@ -317,36 +555,37 @@ __global__ __launch_bounds__(64) void eig_kernel(const QRBatch b) {
             atomicAdd(&rotations, 1);
           }
         }
-        rc_[lane] = c; rs_[lane] = s; rp_[lane] = p; rq_[lane] = q;
+        rc_[tid] = c; rs_[tid] = s; rp_[tid] = p; rq_[tid] = q;
       }
       __syncthreads();
-      if (lane < np) {          // rows p, q of every pair: A <- J^T A
-        const int j = lane;
-        for (int k = 0; k < half; ++k) {
-          const double s = rs_[k];
-          if (s != 0.0) {
-            const double c = rc_[k];
-            const int p = rp_[k], q = rq_[k];
-            const double apj = A[p][j], aqj = A[q][j];
-            A[p][j] = c * apj - s * aqj;
-            A[q][j] = s * apj + c * aqj;
+#pragma unroll
+      for (int t = 0; t < kEigItems; ++t) {
+        const int code = item[t];
+        if (code > 0) {
+          const int k1 = (code - 1) >> 6, k2 = (code - 1) & 63;
+          const double s1 = rs_[k1], s2 = rs_[k2];
+          if (s1 != 0.0 || s2 != 0.0) {
+            const double c1 = rc_[k1], c2 = rc_[k2];
+            const int p1 = rp_[k1], q1 = rq_[k1], p2 = rp_[k2], q2 = rq_[k2];
+            const double a = A[p1][p2], bb = A[p1][q2], cc = A[q1][p2], dd = A[q1][q2];
+            // rows (J^T from the left), then columns (J from the right)
+            const double ra = c1 * a - s1 * cc, rb = c1 * bb - s1 * dd;
+            const double rc = s1 * a + c1 * cc, rd = s1 * bb + c1 * dd;
+            A[p1][p2] = c2 * ra - s2 * rb;
+            A[p1][q2] = s2 * ra + c2 * rb;
+            A[q1][p2] = c2 * rc - s2 * rd;
+            A[q1][q2] = s2 * rc + c2 * rd;
           }
-        }
-      }
-      __syncthreads();
-      if (lane < np) {          // columns p, q: A <- A J, V <- V J
-        const int i = lane;
-        for (int k = 0; k < half; ++k) {
-          const double s = rs_[k];
-          if (s != 0.0) {
-            const double c = rc_[k];
+        } else if (code < 0) {
+          const int f = -code - 1;
+          const int k = f >> 6, i = f & 63;
+          const double sv = rs_[k];
+          if (sv != 0.0) {
+            const double cv = rc_[k];
             const int p = rp_[k], q = rq_[k];
-            const double aip = A[i][p], aiq = A[i][q];
-            A[i][p] = c * aip - s * aiq;
-            A[i][q] = s * aip + c * aiq;
             const double vip = V[i][p], viq = V[i][q];
-            V[i][p] = c * vip - s * viq;
-            V[i][q] = s * vip + c * viq;
+            V[i][p] = cv * vip - sv * viq;
+            V[i][q] = sv * vip + cv * viq;
           }
         }
       }
@@ -357,15 +596,77 @@ __global__ __launch_bounds__(64) void eig_kernel(const QRBatch b) {
     if (done) break;
   }
   // rank of each eigenvalue in descending order (ties: lower index first)
-  for (int i = lane; i < n; i += 64) {
+  __shared__ int rank_of[kMaxEll];
+  for (int i = tid; i < n; i += kEigThreads) {
     const double li = A[i][i];
     int rank = 0;
     for (int j = 0; j < n; ++j) {
       const double lj = A[j][j];
       rank += (lj > li) || (lj == li && j < i);
     }
-    if (rank < M.r)
+    rank_of[i] = rank;
+    if (rank < M.r && !M.small)
       for (int k = 0; k < n; ++k) M.W[k * M.r + rank] = V[k][i];
+  }
+  if (!M.small) return;
+  __syncthreads();
+  // W into A (A[k][rank] = V[k][i]), then U = Q W with the column sign rule
+  for (int e = tid; e < n * n; e += kEigThreads) {
+    const int k = e / n, i = e - k * n;
+    if (rank_of[i] < M.r) A[k][rank_of[i]] = V[k][i];
+  }
+  __syncthreads();
+  const int r = M.r;
+  const int tpc = kEigThreads / r;            // threads per column
+  const int j = tid % r, slot = tid / r;      // column and this thread's row slot
+  const bool active = slot < tpc;
+  __shared__ double sQ[32][kMaxEll + 1];
+  double best = -1.0, bval = 0.0;
+  int64_t bidx = INT64_MAX;
+  const bool f64 = M.udtype == TK_F64;
+  for (int64_t r0 = 0; r0 < M.m; r0 += 32) {
+    const int rows = (int)min<int64_t>(32, M.m - r0);
+    for (int e = tid; e < rows * n; e += kEigThreads) sQ[e / n][e % n] = M.Z[r0 * n + e];
+    __syncthreads();
+    if (active) {
+      for (int rr = slot; rr < rows; rr += tpc) {
+        double v = 0.0;
+        for (int k = 0; k < n; ++k) v = fma(sQ[rr][k], A[k][j], v);
+        const int64_t row = r0 + rr;
+        if (fabs(v) > best) { best = fabs(v); bval = v; bidx = row; }  // rows ascend
+        if (f64) static_cast<double*>(M.U)[row * r + j] = v;
+        else static_cast<float*>(M.U)[row * r + j] = (float)v;
+      }
+    }
+    __syncthreads();
+  }
+  // per column: largest |u|, lowest row on ties
+  __shared__ double cand_v[kEigThreads], cand_a[kEigThreads];
+  __shared__ int64_t cand_i[kEigThreads];
+  __shared__ double sgn[kMaxEll];
+  cand_a[tid] = active ? best : -1.0;
+  cand_v[tid] = bval;
+  cand_i[tid] = bidx;
+  __syncthreads();
+  if (tid < r) {
+    double ba = -1.0, bv = 0.0;
+    int64_t bi = INT64_MAX;
+    for (int s2 = 0; s2 < tpc; ++s2) {
+      const int t = s2 * r + tid;
+      if (cand_a[t] > ba || (cand_a[t] == ba && cand_i[t] < bi)) {
+        ba = cand_a[t]; bv = cand_v[t]; bi = cand_i[t];
+      }
+    }
+    sgn[tid] = bv < 0.0 ? -1.0 : 1.0;
+  }
+  __syncthreads();
+  // flip the columns that need it (exact in either storage type); each thread
+  // rewrites only entries it wrote itself
+  if (active && sgn[j] < 0.0) {
+    for (int64_t row = slot; row < M.m; row += tpc) {
+      if (f64) { double* U = static_cast<double*>(M.U); U[row * r + j] = -U[row * r + j]; }
+      else { float* U = static_cast<float*>(M.U); U[row * r + j] = -U[row * r + j]; }
+    }
   }
 }
 
@@ -373,7 +674,7 @@ __global__ __launch_bounds__(64) void eig_kernel(const QRBatch b) {
 __global__ __launch_bounds__(64) void urows_kernel(const QRBatch b) {
   const QRMat& M = b.m[blockIdx.y];
   const int rb = blockIdx.x;
-  if (rb >= M.nrb) return;
+  if (rb >= M.nrb || M.small) return;
   __shared__ double sQ[kMaxEll][65];
   __shared__ double sW[kMaxEll][kMaxEll + 1];
   const int n = M.ell, r = M.r, lane = threadIdx.x;
@@ -412,7 +713,7 @@ template <typename TU>
 __global__ __launch_bounds__(64) void usign_kernel(const QRBatch b) {
   const QRMat& M = b.m[blockIdx.y];
   const int rb = blockIdx.x;
-  if (rb >= M.nrb) return;
+  if (rb >= M.nrb || M.small) return;
   __shared__ double sgn[kMaxEll];
   const int r = M.r, lane = threadIdx.x;
   for (int j = 0; j < r; ++j) {
@@ -455,6 +756,10 @@ int max_field(const QRBatch& b, int which) {
 hipError_t launch_cholqr(const QRBatch& b, hipStream_t st) {
   if (b.count == 0) return hipSuccess;
   const int nrc = max_field(b, 0), nrb = max_field(b, 2);
+  bool any_small = false, any_big = false;
+  for (int i = 0; i < b.count; ++i) (b.m[i].small ? any_small : any_big) = true;
+  if (any_small) hipLaunchKernelGGL(cholqr_small_kernel, dim3(b.count), dim3(256), 0, st, b);
+  if (!any_big) return hipGetLastError();
   // CholeskyQR2 needs two passes; every shifted pass owes two more plain ones,
   // so an exactly rank-deficient sketch (shift, shift, plain, plain) needs four.
   for (int pass = 1; pass <= kQRMaxPasses; ++pass) {
@@ -481,7 +786,10 @@ hipError_t launch_wstep(const QRBatch& b, int ydtype, int udtype, hipStream_t st
     default: return hipErrorInvalidValue;
   }
   hipLaunchKernelGGL(mgram_kernel, dim3(ncc, b.count), dim3(256), 0, st, b);
-  hipLaunchKernelGGL(eig_kernel, dim3(b.count), dim3(64), 0, st, b);
+  hipLaunchKernelGGL(eig_kernel, dim3(b.count), dim3(kEigThreads), 0, st, b);
+  bool any_big = false;
+  for (int i = 0; i < b.count; ++i) any_big |= !b.m[i].small;
+  if (!any_big) return hipGetLastError();
   hipLaunchKernelGGL(urows_kernel, dim3(nrb, b.count), dim3(64), 0, st, b);
   if (udtype == TK_F64)
     hipLaunchKernelGGL((usign_kernel<double>), dim3(nrb, b.count), dim3(64), 0, st, b);

@@ -23,19 +23,37 @@ template <typename T> __device__ __forceinline__ double ld(const void* p, int64_
   return to_double(static_cast<const T*>(p)[i]);
 }
 
-template <typename TIn, typename TOut, typename TM, int PMAX>
-__global__ __launch_bounds__(256) void mode_rows_kernel(const ModeProduct mp) {
-  // B == 1: out[a][p] = sum_q in[a][q] M[p][q]
+// M staged as a zero-padded FP64 table Mt[q][p] (ld = padded P): every read
+// of it in the inner loops is a fixed, contiguous, wave-uniform run, which
+// the compiler turns into scalar loads (no LDS traffic, no bounds checks).
+__global__ void stage_factor_kernel(const void* M, int m_dt, int64_t rs, int64_t cs, int P,
+                                    int64_t Q, int ld, double* Mt) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= Q * ld) return;
+  const int64_t q = g / ld;
+  const int p = (int)(g - q * ld);
+  double v = 0.0;
+  if (p < P) {
+    const int64_t i = p * rs + q * cs;
+    v = m_dt == TK_F64 ? static_cast<const double*>(M)[i] : (double)static_cast<const float*>(M)[i];
+  }
+  Mt[g] = v;
+}
+
+template <typename TIn, typename TOut, int PMAX>
+__global__ __launch_bounds__(256) void mode_rows_kernel(const ModeProduct mp, int ld) {
+  // B == 1: out[a][p] = sum_q in[a][q] M[p][q]; 64 rows per block, a
+  // 64 x 64 tile of `in` staged through LDS (coalesced), 4 p-groups
   __shared__ double sX[64][65];
-  __shared__ double sM[64][PMAX + 1];
   const int tid = threadIdx.x;
-  const int row = tid & 63, pg = tid >> 6;  // 4 p-groups
+  const int row = tid & 63;
+  const int pg = __builtin_amdgcn_readfirstlane(tid >> 6);  // one p-group per wave
   constexpr int PK = PMAX / 4;
   const int64_t a0 = (int64_t)blockIdx.x * 64;
-  const int p0 = blockIdx.y * PMAX;  // this block's slice of output columns
+  const int p0 = blockIdx.y * PMAX;
   const int rows = (int)min<int64_t>(64, mp.A - a0);
   const TIn* in = static_cast<const TIn*>(mp.in);
-  const TM* M = static_cast<const TM*>(mp.M);
+  const double* __restrict__ Mt = mp.Mt;
   double acc[PK];
 #pragma unroll
   for (int k = 0; k < PK; ++k) acc[k] = 0.0;
@@ -46,16 +64,12 @@ __global__ __launch_bounds__(256) void mode_rows_kernel(const ModeProduct mp) {
       const int rr = e >> 6, qq = e & 63;
       sX[rr][qq] = (rr < rows && qq < qn) ? to_double(in[(a0 + rr) * mp.Q + q0 + qq]) : 0.0;
     }
-    for (int e = tid; e < 64 * PMAX; e += 256) {
-      const int qq = e / PMAX, p = e - qq * PMAX;
-      sM[qq][p] = (qq < qn && p0 + p < mp.P)
-                      ? to_double(M[(int64_t)(p0 + p) * mp.rs + (q0 + qq) * mp.cs]) : 0.0;
-    }
     __syncthreads();
     for (int qq = 0; qq < qn; ++qq) {
       const double x = sX[row][qq];
+      const double* mq = Mt + (q0 + qq) * ld + p0;
 #pragma unroll
-      for (int k = 0; k < PK; ++k) acc[k] = fma(x, sM[qq][pg + 4 * k], acc[k]);
+      for (int k = 0; k < PK; ++k) acc[k] = fma(x, mq[pg + 4 * k], acc[k]);
     }
   }
   if (row < rows) {
@@ -73,58 +87,74 @@ __global__ __launch_bounds__(256) void mode_rows_kernel(const ModeProduct mp) {
   }
 }
 
-template <typename TIn, typename TOut, typename TM, int PMAX>
-__global__ __launch_bounds__(256) void mode_strided_kernel(const ModeProduct mp) {
-  // out[a][p][b] = sum_q in[a][q][b] M[p][q]; one (a, b) per thread
-  __shared__ double sM[64][PMAX + 1];
+template <typename TIn, typename TOut, int PMAX, int NB>
+__global__ __launch_bounds__(256) void mode_strided_kernel(const ModeProduct mp, int ld) {
+  // out[a][p][b] = sum_q in[a][q][b] M[p][q]; NB (a, b) points per thread,
+  // 256 apart, so each load instruction stays coalesced; M comes from the
+  // staged table with scalar loads.
   const int tid = threadIdx.x;
-  const int64_t g = (int64_t)blockIdx.x * 256 + tid;
-  const bool live = g < mp.A * mp.B;
-  const int64_t a = live ? g / mp.B : 0;
-  const int64_t bb = live ? g - a * mp.B : 0;
-  const int p0 = blockIdx.y * PMAX;  // this block's slice of output columns
-  const TIn* in = static_cast<const TIn*>(mp.in);
-  const TM* M = static_cast<const TM*>(mp.M);
-  double acc[PMAX];
+  const int64_t AB = mp.A * mp.B;
+  const int p0 = blockIdx.y * PMAX;
+  const TIn* __restrict__ in = static_cast<const TIn*>(mp.in);
+  const double* __restrict__ Mt = mp.Mt;
+  int64_t base[NB];
+  bool live[NB];
 #pragma unroll
-  for (int k = 0; k < PMAX; ++k) acc[k] = 0.0;
-  for (int64_t q0 = 0; q0 < mp.Q; q0 += 64) {
-    const int qn = (int)min<int64_t>(64, mp.Q - q0);
-    __syncthreads();
-    for (int e = tid; e < 64 * PMAX; e += 256) {
-      const int qq = e / PMAX, p = e - qq * PMAX;
-      sM[qq][p] = (qq < qn && p0 + p < mp.P)
-                      ? to_double(M[(int64_t)(p0 + p) * mp.rs + (q0 + qq) * mp.cs]) : 0.0;
-    }
-    __syncthreads();
-    if (live) {
-      // loads of 8 rows are issued together so their latencies overlap
-      const TIn* src = in + (a * mp.Q + q0) * mp.B + bb;
-      int qq = 0;
-      for (; qq + 8 <= qn; qq += 8) {
-        double x[8];
+  for (int u = 0; u < NB; ++u) {
+    const int64_t g = ((int64_t)blockIdx.x * NB + u) * 256 + tid;
+    live[u] = g < AB;
+    const int64_t a = live[u] ? g / mp.B : 0;
+    const int64_t bb = live[u] ? g - a * mp.B : 0;
+    base[u] = a * mp.Q * mp.B + bb;
+  }
+  double acc[NB][PMAX];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) x[u] = to_double(src[(int64_t)(qq + u) * mp.B]);
+  for (int u = 0; u < NB; ++u)
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
+    for (int k = 0; k < PMAX; ++k) acc[u][k] = 0.0;
+  int64_t q = 0;
+  for (; q + 4 <= mp.Q; q += 4) {
+    double x[4][NB];
 #pragma unroll
-          for (int k = 0; k < PMAX; ++k) acc[k] = fma(x[u], sM[qq + u][k], acc[k]);
-        }
-      }
-      for (; qq < qn; ++qq) {
-        const double x = to_double(src[(int64_t)qq * mp.B]);
+    for (int w = 0; w < 4; ++w)
 #pragma unroll
-        for (int k = 0; k < PMAX; ++k) acc[k] = fma(x, sM[qq][k], acc[k]);
+      for (int u = 0; u < NB; ++u)
+        x[w][u] = live[u] ? to_double(in[base[u] + (q + w) * mp.B]) : 0.0;
+#pragma unroll
+    for (int w = 0; w < 4; ++w) {
+      const double* mq = Mt + (q + w) * ld + p0;
+#pragma unroll
+      for (int k = 0; k < PMAX; ++k) {
+        const double m = mq[k];
+#pragma unroll
+        for (int u = 0; u < NB; ++u) acc[u][k] = fma(x[w][u], m, acc[u][k]);
       }
     }
   }
-  if (live) {
-    TOut* out = static_cast<TOut*>(mp.out);
+  for (; q < mp.Q; ++q) {
+    double x[NB];
+#pragma unroll
+    for (int u = 0; u < NB; ++u) x[u] = live[u] ? to_double(in[base[u] + q * mp.B]) : 0.0;
+    const double* mq = Mt + q * ld + p0;
 #pragma unroll
     for (int k = 0; k < PMAX; ++k) {
-      if (p0 + k < mp.P) {
+      const double m = mq[k];
+#pragma unroll
+      for (int u = 0; u < NB; ++u) acc[u][k] = fma(x[u], m, acc[u][k]);
+    }
+  }
+  TOut* out = static_cast<TOut*>(mp.out);
+  const int pn = min(PMAX, mp.P - p0);
+#pragma unroll
+  for (int u = 0; u < NB; ++u) {
+    if (!live[u]) continue;
+    const int64_t g = ((int64_t)blockIdx.x * NB + u) * 256 + tid;
+    const int64_t a = g / mp.B, bb = g - a * mp.B;
+#pragma unroll
+    for (int k = 0; k < PMAX; ++k) {
+      if (k < pn) {
         const int64_t o = (a * mp.P + p0 + k) * mp.B + bb;
-        double v = acc[k];
+        double v = acc[u][k];
         if (mp.accumulate) v += to_double(out[o]);
         out[o] = from_double<TOut>(v);
       }
@@ -132,46 +162,47 @@ __global__ __launch_bounds__(256) void mode_strided_kernel(const ModeProduct mp)
   }
 }
 
-template <typename TIn, typename TOut, typename TM>
-hipError_t mode_product(const ModeProduct& mp, hipStream_t st) {
-  if (mp.A == 0 || mp.B == 0) return hipSuccess;
-  if (mp.P < 1) return hipSuccess;
-  const int width = mp.P <= 16 ? 16 : mp.P <= 32 ? 32 : 64;
+int width_of(int P) { return P <= 16 ? 16 : P <= 32 ? 32 : 64; }
+
+template <typename TIn, typename TOut>
+hipError_t mode_product(const ModeProduct& mp, int m_dt, hipStream_t st) {
+  if (mp.A == 0 || mp.B == 0 || mp.P < 1) return hipSuccess;
+  const int width = width_of(mp.P);
   const unsigned pchunks = (unsigned)ceil_div(mp.P, width);
+  const int ld = (int)pchunks * width;
+  hipLaunchKernelGGL(stage_factor_kernel, dim3((unsigned)ceil_div(mp.Q * ld, 256)), dim3(256), 0,
+                     st, mp.M, m_dt, (int64_t)mp.rs, (int64_t)mp.cs, mp.P, mp.Q, ld, mp.Mt);
   if (mp.B == 1) {
     const dim3 grid((unsigned)ceil_div(mp.A, 64), pchunks);
     if (width == 16)
-      hipLaunchKernelGGL((mode_rows_kernel<TIn, TOut, TM, 16>), grid, dim3(256), 0, st, mp);
+      hipLaunchKernelGGL((mode_rows_kernel<TIn, TOut, 16>), grid, dim3(256), 0, st, mp, ld);
     else if (width == 32)
-      hipLaunchKernelGGL((mode_rows_kernel<TIn, TOut, TM, 32>), grid, dim3(256), 0, st, mp);
+      hipLaunchKernelGGL((mode_rows_kernel<TIn, TOut, 32>), grid, dim3(256), 0, st, mp, ld);
     else
-      hipLaunchKernelGGL((mode_rows_kernel<TIn, TOut, TM, 64>), grid, dim3(256), 0, st, mp);
+      hipLaunchKernelGGL((mode_rows_kernel<TIn, TOut, 64>), grid, dim3(256), 0, st, mp, ld);
   } else {
-    const dim3 grid((unsigned)ceil_div(mp.A * mp.B, 256), pchunks);
-    if (width == 16)
-      hipLaunchKernelGGL((mode_strided_kernel<TIn, TOut, TM, 16>), grid, dim3(256), 0, st, mp);
-    else if (width == 32)
-      hipLaunchKernelGGL((mode_strided_kernel<TIn, TOut, TM, 32>), grid, dim3(256), 0, st, mp);
-    else
-      hipLaunchKernelGGL((mode_strided_kernel<TIn, TOut, TM, 64>), grid, dim3(256), 0, st, mp);
+    // several points per thread when there are enough of them to keep every
+    // CU busy (64 accumulators per thread at most)
+    const bool wide = mp.A * mp.B >= (int64_t)256 * 4 * 1024;
+    const int nb = !wide ? 1 : width == 16 ? 4 : width == 32 ? 2 : 1;
+    const dim3 grid((unsigned)ceil_div(mp.A * mp.B, 256 * nb), pchunks);
+    if (width == 16) {
+      if (wide) hipLaunchKernelGGL((mode_strided_kernel<TIn, TOut, 16, 4>), grid, dim3(256), 0, st, mp, ld);
+      else hipLaunchKernelGGL((mode_strided_kernel<TIn, TOut, 16, 1>), grid, dim3(256), 0, st, mp, ld);
+    } else if (width == 32) {
+      if (wide) hipLaunchKernelGGL((mode_strided_kernel<TIn, TOut, 32, 2>), grid, dim3(256), 0, st, mp, ld);
+      else hipLaunchKernelGGL((mode_strided_kernel<TIn, TOut, 32, 1>), grid, dim3(256), 0, st, mp, ld);
+    } else {
+      hipLaunchKernelGGL((mode_strided_kernel<TIn, TOut, 64, 1>), grid, dim3(256), 0, st, mp, ld);
+    }
   }
   return hipGetLastError();
 }
 
-template <typename TIn, typename TM>
-hipError_t by_out(const ModeProduct& mp, int out_dt, hipStream_t st) {
-  return out_dt == TK_F64 ? mode_product<TIn, double, TM>(mp, st)
-                          : mode_product<TIn, float, TM>(mp, st);
-}
-template <typename TM>
-hipError_t by_in(const ModeProduct& mp, int in_dt, int out_dt, hipStream_t st) {
-  switch (in_dt) {
-    case TK_F64: return by_out<double, TM>(mp, out_dt, st);
-    case TK_F32: return by_out<float, TM>(mp, out_dt, st);
-    case TK_BF16: return by_out<bf16, TM>(mp, out_dt, st);
-    case TK_F16: return by_out<f16, TM>(mp, out_dt, st);
-  }
-  return hipErrorInvalidValue;
+template <typename TIn>
+hipError_t by_out(const ModeProduct& mp, int out_dt, int m_dt, hipStream_t st) {
+  return out_dt == TK_F64 ? mode_product<TIn, double>(mp, m_dt, st)
+                          : mode_product<TIn, float>(mp, m_dt, st);
 }
 
 // ------------------------------------------------------------------ fused residual
@@ -280,9 +311,21 @@ int64_t expand_residual_blocks(int64_t total) {
   return std::max<int64_t>(1, std::min<int64_t>(kResidBlocks, ceil_div(total, 256)));
 }
 
+int64_t mode_product_scratch(int64_t P, int64_t Q) {
+  const int w = width_of((int)std::min<int64_t>(P, 1 << 20));
+  return ceil_div(P, w) * w * Q;
+}
+
 hipError_t launch_mode_product(const ModeProduct& mp, int in_dt, int out_dt, int m_dt,
                                hipStream_t st) {
-  return m_dt == TK_F64 ? by_in<double>(mp, in_dt, out_dt, st) : by_in<float>(mp, in_dt, out_dt, st);
+  if (!mp.Mt) return hipErrorInvalidValue;
+  switch (in_dt) {
+    case TK_F64: return by_out<double>(mp, out_dt, m_dt, st);
+    case TK_F32: return by_out<float>(mp, out_dt, m_dt, st);
+    case TK_BF16: return by_out<bf16>(mp, out_dt, m_dt, st);
+    case TK_F16: return by_out<f16>(mp, out_dt, m_dt, st);
+  }
+  return hipErrorInvalidValue;
 }
 
 hipError_t launch_expand_residual(const ExpandResidual& e, int x_dt, int f_dt, hipStream_t st) {

@@ -126,6 +126,10 @@ void plan_qr(Workspace& ws, QRMat& q, double* Z, int64_t m, int ell, bool wstep,
   q.nrc = (int32_t)ceil_div(m, kQRRowChunk);
   q.ncc = wstep ? (int32_t)ceil_div(s, kQRColChunk) : 0;
   q.nrb = (int32_t)ceil_div(m, kQRRowBlock);
+  // the one-workgroup kernels: QR needs m ell <= kQRSmallElems; the fused U = Q W
+  // gives each of 256 / r threads per column at most 64 rows
+  q.small = (m <= kQRSmallRows && m * ell <= kQRSmallElems && (!wstep || m <= 64 * (256 / r)))
+                ? 1 : 0;
   q.gpart = ws.take<double>((size_t)q.nrc * ell * ell);
   q.R = ws.take<double>((size_t)ell * ell);
   q.state = ws.take<int32_t>(2);
@@ -143,7 +147,10 @@ tk_status run_qr(std::vector<QRMat>& mats, int ydtype, int udtype, bool wstep, h
   for (size_t g = 0; g < mats.size(); g += kQRMaxBatch) {
     QRBatch b{};
     b.count = (int32_t)std::min<size_t>(kQRMaxBatch, mats.size() - g);
-    for (int i = 0; i < b.count; ++i) b.m[i] = mats[g + i];
+    for (int i = 0; i < b.count; ++i) {
+      b.m[i] = mats[g + i];
+      b.m[i].udtype = udtype;
+    }
     TK_HIP(launch_cholqr(b, st));
     if (wstep) TK_HIP(launch_wstep(b, ydtype, udtype, st));
   }
@@ -170,6 +177,7 @@ tk_status check_factors(int order, const int64_t* dims, const void* const* F, co
 struct CorePlan {
   double* buf[2] = {nullptr, nullptr};
   float* t32 = nullptr;
+  double* mt = nullptr;   // staged factor table of the mode products
   bool fused = false;
 };
 
@@ -191,6 +199,9 @@ tk_status plan_core(Workspace& ws, int xdt, int order, const int64_t* dims, cons
   }
   p.buf[0] = ws.take<double>((size_t)mx);
   p.buf[1] = ws.take<double>((size_t)mx);
+  int64_t smax = 0;
+  for (int k = 0; k < order; ++k) smax = std::max(smax, mode_product_scratch(cols[k], dims[k]));
+  p.mt = ws.take<double>((size_t)smax);
   return TK_OK;
 }
 
@@ -231,6 +242,7 @@ tk_status run_core(const void* X, int xdt, int order, const int64_t* dims,
     mp.B = prod(shape, k + 1, order);
     mp.P = cols[k];
     mp.M = F[k];
+    mp.Mt = p.mt;
     mp.rs = 1;          // M[p][q] = F[q][p]
     mp.cs = cols[k];
     void* out = k == 0 ? G : (void*)p.buf[(kstart - k) & 1];
@@ -406,6 +418,9 @@ tk_status tucker_reconstruct(int32_t order, const int64_t* dims, int32_t fdtype,
   Workspace w;
   w.base = static_cast<char*>(ws);
   double* buf[2] = {w.take<double>((size_t)mx), w.take<double>((size_t)mx)};
+  int64_t smax = 0;
+  for (int k = 0; k < order; ++k) smax = std::max(smax, mode_product_scratch(dims[k], cols[k]));
+  double* mt = w.take<double>((size_t)smax);
   const int64_t A_last = prod(dims, 0, order - 1);
   const int64_t nb = expand_residual_blocks(A_last * dims[order - 1]);
   double* partials = w.take<double>((size_t)2 * nb);
@@ -428,6 +443,7 @@ tk_status tucker_reconstruct(int32_t order, const int64_t* dims, int32_t fdtype,
     mp.B = prod(shape, k + 1, order);
     mp.P = (int32_t)dims[k];
     mp.M = F[k];
+    mp.Mt = mt;
     mp.rs = cols[k];   // M[p][q] = F[p][q]
     mp.cs = 1;
     mp.out = buf[which];
@@ -567,11 +583,14 @@ tk_status htucker_decompose(const tk_tensor* X, const tk_tree* tree, const int32
     x.rl = rank[l];
     x.rr = rank[r];
     x.V = w.take<double>((size_t)x.nl * x.rr * x.rS);
+    x.Mt = w.take<double>((size_t)mode_product_scratch(x.rr, x.nr));
     tr.push_back(x);
   }
   // root: X viewed as (n_l, n_r): B_R = U_l^T X U_r
   const int L = tree->left[0], R = tree->right[0];
   double* t1 = w.take<double>((size_t)nS[L] * rank[R]);
+  double* mt_root = w.take<double>((size_t)std::max(mode_product_scratch(rank[R], nS[R]),
+                                                    mode_product_scratch(rank[L], nS[L])));
   if (!ws) {
     *ws_bytes = w.off;
     return TK_OK;
@@ -591,6 +610,7 @@ tk_status htucker_decompose(const tk_tensor* X, const tk_tree* tree, const int32
     mp.B = 1;
     mp.P = rank[R];
     mp.M = U[R];
+    mp.Mt = mt_root;
     mp.rs = 1;
     mp.cs = rank[R];
     mp.out = t1;
@@ -604,6 +624,7 @@ tk_status htucker_decompose(const tk_tensor* X, const tk_tree* tree, const int32
     m2.B = rank[R];
     m2.P = rank[L];
     m2.M = U[L];
+    m2.Mt = mt_root;
     m2.rs = 1;
     m2.cs = rank[L];
     m2.out = B[0];

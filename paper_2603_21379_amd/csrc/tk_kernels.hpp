@@ -51,8 +51,13 @@ struct QRMat {
   int64_t m, s;
   int32_t ell, r;
   int32_t nrc, ncc, nrb; // row chunks (Gram / Q^T Y), column chunks, row blocks (apply)
-  int32_t pad;
+  int32_t small;         // m x ell (and m x r) small enough for the one-workgroup kernels
+  int32_t udtype;        // TK_F64 or TK_F32
+  int32_t pad2;
 };
+// a matrix is handled by one workgroup when its rows times columns fit this
+constexpr int kQRSmallElems = 16384;
+constexpr int kQRSmallRows = 4096;
 constexpr int kQRMaxBatch = 16;
 constexpr int kQRMaxPasses = 4;
 constexpr int kQRRowChunk = 256;
@@ -71,11 +76,14 @@ struct ModeProduct {
   const void* in;
   void* out;
   const void* M;        // factor dtype (double or float)
+  double* Mt;           // scratch of mode_product_scratch(P, Q) doubles
   int64_t A, Q, B;
   int32_t P;
   int32_t rs, cs;
   int32_t accumulate;   // out += instead of out =
 };
+// doubles of scratch a mode product needs (M as a padded FP64 [Q][P'] table)
+int64_t mode_product_scratch(int64_t P, int64_t Q);
 // in_dt: dtype of `in`; out_dt, m_dt: TK_F64 or TK_F32
 hipError_t launch_mode_product(const ModeProduct& mp, int in_dt, int out_dt, int m_dt,
                                hipStream_t st);
@@ -118,6 +126,7 @@ struct Transfer {
   const void* US; const void* Ul; const void* Ur;
   void* Bout;
   double* V;            // workspace [nl][rS][rr]
+  double* Mt;           // workspace: mode_product_scratch(rr, nr) doubles
   int64_t nl, nr;
   int32_t rS, rl, rr;
   int32_t pad;
