@@ -120,6 +120,25 @@ struct CoreFused2 {
 bool fused2_supported(int dtype, int order, const int64_t* dims, const int32_t* cols);
 hipError_t launch_fused2_f32(const CoreFused2& p, hipStream_t st);
 
+// ---------------------------------------------------------------- FP32 fused streaming residual
+// sum (X[a] - F_I T[a] F_J^T)^2 and sum X[a]^2 over the A slabs of an FP32 tensor.
+struct ResidFused2 {
+  const float* X;
+  const float* T;      // A x c_I x c_J, the core expanded over the leading modes
+  const float* FI;     // n_I x c_I
+  const float* FJ;     // n_J x c_J
+  float* Xhat;         // optional output, prod(dims)
+  double* partials;    // [resid2_waves(A)][2]
+  double* resid2;      // [2] or nullptr
+  int64_t A;
+  int32_t nI, nJ, cI, cJ;
+  int32_t nwaves;      // set by the launcher
+  int32_t pad;
+};
+bool resid2_supported(int dtype, int order, const int64_t* dims, const int32_t* cols);
+int64_t resid2_waves(int64_t A);
+hipError_t launch_resid2_f32(const ResidFused2& p, hipStream_t st);
+
 // ---------------------------------------------------------------- H-Tucker transfers
 // B[i][j][k] = sum_{a,b} US[a*nr + b][i] Ul[a][j] Ur[b][k]
 struct Transfer {

@@ -198,3 +198,28 @@ def test_fp32_fused_streaming_core(dims, ranks):
     the oracle core on the same factors, and the end-to-end error gate."""
     o = run_case(dims, ranks, 0.8, 1e-4, 6, synthgen.default_s(dims), "f32", 61)
     check_common(o, "f32", 1e-5)
+
+
+@pytest.mark.parametrize("dims,cols", [((16, 20, 30, 132), (5, 6, 12, 20)),
+                                       ((300, 33, 96), (7, 32, 32))])
+def test_fp32_fused_residual_and_xhat(dims, cols):
+    """The FP32 MFMA residual pass: materialised X_hat and the FP64 sums
+    ||X - X_hat||^2, ||X||^2 against the oracle on the same core and factors."""
+    from paper_2603_21379_amd import binding as Bd
+    rng = np.random.default_rng(9)
+    X = rng.standard_normal(dims).astype(np.float32)
+    G = rng.standard_normal(cols).astype(np.float32)
+    F = [np.linalg.qr(rng.standard_normal((n, c)))[0].astype(np.float32) for n, c in zip(dims, cols)]
+    Xd = torch.from_numpy(X).cuda()
+    Gd = torch.from_numpy(G).cuda()
+    Fd = [torch.from_numpy(f).cuda() for f in F]
+    Xh = torch.empty(dims, dtype=torch.float32, device="cuda")
+    r2 = torch.zeros(2, dtype=torch.float64, device="cuda")
+    Bd.tucker_reconstruct(list(dims), Gd, Fd, Xref=Xd, Xhat=Xh, resid2=r2)
+    torch.cuda.synchronize()
+    ref = oracle.reconstruct(G.astype(np.float64), [f.astype(np.float64) for f in F])
+    np.testing.assert_allclose(Xh.cpu().numpy(), ref, rtol=0, atol=2e-6 * np.abs(ref).max())
+    X64 = X.astype(np.float64)
+    r2h = r2.cpu().numpy()
+    np.testing.assert_allclose(r2h[1], np.sum(X64 ** 2), rtol=1e-12)
+    np.testing.assert_allclose(r2h[0], np.sum((X64 - ref) ** 2), rtol=1e-6)
