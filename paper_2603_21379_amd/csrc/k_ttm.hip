@@ -223,7 +223,7 @@ __global__ __launch_bounds__(256) void expand_residual_kernel(const ExpandResidu
     const TF* f = F + i * e.c;
     double v = 0.0;
     for (int j = 0; j < e.c; ++j) v = fma(t[j], to_double(f[j]), v);
-    if (Xh) Xh[g] = from_double<TF>(v);
+    if (Xh) Xh[g] = from_double<TF>(e.accumulate ? v + to_double(Xh[g]) : v);
     if (X) {
       const double x = to_double(X[g]);
       const double d = x - v;

@@ -1,0 +1,106 @@
+// Unfolded products for the vector-Jacobian products of the core projection
+// and the reconstruction (derived from the TTM definition of Section 2.2):
+//   out[i][a] (+)= sum_{p,q} A[p][i][q] B[p][a][q]
+// i.e. A^(k) (B^(k))^T for two tensors that differ only in mode k (A has n_k
+// there, B has c_k), both viewed as (pre, ., post).
+//
+// The (p, q) range is split into `splits` ranges; block (i, split, chunk)
+// forms up to CMAX outputs (columns chunk*CMAX ..) of row i over its range with a fixed-order tree reduction
+// across the block, writes them as a partial, and a second kernel sums the
+// partials in index order (deterministic, no atomics).
+#include "tk_kernels.hpp"
+
+namespace tk {
+namespace {
+
+template <typename TA, typename TB, int CMAX>
+__global__ __launch_bounds__(256) void unfold_gemm_kernel(const UnfoldGemm g) {
+  __shared__ double red[256];
+  const int i = blockIdx.x, split = blockIdx.y, tid = threadIdx.x;
+  const int a0 = blockIdx.z * CMAX, cc = min(CMAX, g.c - a0);
+  const int64_t R = g.pre * g.post;
+  const int64_t per = (R + g.splits - 1) / g.splits;
+  const int64_t r0 = split * per, r1 = min(R, r0 + per);
+  const TA* A = static_cast<const TA*>(g.A);
+  const TB* B = static_cast<const TB*>(g.B);
+  double acc[CMAX];
+#pragma unroll
+  for (int a = 0; a < CMAX; ++a) acc[a] = 0.0;
+  for (int64_t r = r0 + tid; r < r1; r += 256) {
+    const int64_t p = r / g.post, q = r - p * g.post;
+    const double x = to_double(A[(p * g.n + i) * g.post + q]);
+    const TB* b = B + (p * g.c + a0) * g.post + q;
+#pragma unroll
+    for (int a = 0; a < CMAX; ++a)
+      if (a < cc) acc[a] = fma(x, to_double(b[(int64_t)a * g.post]), acc[a]);
+  }
+  double* out = g.partials + ((int64_t)split * g.n + i) * g.c + a0;
+#pragma unroll
+  for (int a = 0; a < CMAX; ++a) {
+    if (a >= cc) break;
+    red[tid] = acc[a];
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+      if (tid < s) red[tid] += red[tid + s];
+      __syncthreads();
+    }
+    if (tid == 0) out[a] = red[0];
+    __syncthreads();
+  }
+}
+
+template <typename TO>
+__global__ void unfold_sum_kernel(const UnfoldGemm g) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t nc = (int64_t)g.n * g.c;
+  if (e >= nc) return;
+  double v = 0.0;
+  for (int s = 0; s < g.splits; ++s) v += g.partials[s * nc + e];
+  TO* out = static_cast<TO*>(g.out);
+  if (g.accumulate) v += to_double(out[e]);
+  out[e] = from_double<TO>(v);
+}
+
+template <typename TA, typename TB>
+hipError_t run(const UnfoldGemm& g, int out_dt, hipStream_t st) {
+  const dim3 grid((unsigned)g.n, (unsigned)g.splits);
+  if (g.c <= 16) hipLaunchKernelGGL((unfold_gemm_kernel<TA, TB, 16>), grid, dim3(256), 0, st, g);
+  else if (g.c <= 32) hipLaunchKernelGGL((unfold_gemm_kernel<TA, TB, 32>), grid, dim3(256), 0, st, g);
+  else
+    hipLaunchKernelGGL((unfold_gemm_kernel<TA, TB, 64>),
+                       dim3((unsigned)g.n, (unsigned)g.splits, (unsigned)ceil_div(g.c, 64)), dim3(256),
+                       0, st, g);
+  const dim3 g2((unsigned)ceil_div((int64_t)g.n * g.c, 256));
+  if (out_dt == TK_F64) hipLaunchKernelGGL((unfold_sum_kernel<double>), g2, dim3(256), 0, st, g);
+  else hipLaunchKernelGGL((unfold_sum_kernel<float>), g2, dim3(256), 0, st, g);
+  return hipGetLastError();
+}
+
+template <typename TA>
+hipError_t by_b(const UnfoldGemm& g, int b_dt, int out_dt, hipStream_t st) {
+  switch (b_dt) {
+    case TK_F64: return run<TA, double>(g, out_dt, st);
+    case TK_F32: return run<TA, float>(g, out_dt, st);
+  }
+  return hipErrorInvalidValue;
+}
+
+}  // namespace
+
+int32_t unfold_gemm_splits(int64_t n, int64_t pre_post) {
+  // enough blocks to cover the chip, each with at least 64K products
+  int64_t s = ceil_div(1024, std::max<int64_t>(1, n));
+  s = std::min<int64_t>(s, std::max<int64_t>(1, pre_post / 65536));
+  return (int32_t)std::max<int64_t>(1, std::min<int64_t>(s, 256));
+}
+
+hipError_t launch_unfold_gemm(const UnfoldGemm& g, int a_dt, int b_dt, int out_dt, hipStream_t st) {
+  if (g.n == 0 || g.c == 0) return hipSuccess;
+  switch (a_dt) {
+    case TK_F64: return by_b<double>(g, b_dt, out_dt, st);
+    case TK_F32: return by_b<float>(g, b_dt, out_dt, st);
+  }
+  return hipErrorInvalidValue;
+}
+
+}  // namespace tk

@@ -260,6 +260,193 @@ tk_status run_core(const void* X, int xdt, int order, const int64_t* dims,
 
 hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
 
+// ------------------------------------------------------------------ VJP chains
+// Buffers shared by the chains of the VJPs: two FP64 ping-pong intermediates
+// large enough for every chain, the staged factor table, the partials of
+// the unfolded products and of the last expansion.
+struct VjpPlan {
+  double* buf[2] = {nullptr, nullptr};
+  double* mt = nullptr;
+  double* upart = nullptr;
+  double* epart = nullptr;
+};
+
+void plan_vjp(Workspace& ws, int d, const int64_t* dims, const int32_t* cols, VjpPlan& vp) {
+  int64_t mx = 1;
+  int64_t shape[TK_MAX_ORDER];
+  // contractions of X in every mode but k (last mode first)
+  for (int k = 0; k < d; ++k) {
+    for (int j = 0; j < d; ++j) shape[j] = dims[j];
+    for (int j = d - 1; j >= 0; --j) {
+      if (j == k) continue;
+      shape[j] = cols[j];
+      mx = std::max(mx, prod(shape, 0, d));
+    }
+  }
+  // expansions of a core in every mode but k, and in every mode but the last
+  for (int k = -1; k < d; ++k) {
+    for (int j = 0; j < d; ++j) shape[j] = cols[j];
+    mx = std::max(mx, prod(shape, 0, d));
+    for (int j = 0; j < d; ++j) {
+      if (j == k || (k < 0 && j == d - 1)) continue;
+      shape[j] = dims[j];
+      mx = std::max(mx, prod(shape, 0, d));
+    }
+  }
+  vp.buf[0] = ws.take<double>((size_t)mx);
+  vp.buf[1] = ws.take<double>((size_t)mx);
+  int64_t smax = 0, umax = 0;
+  for (int k = 0; k < d; ++k) {
+    smax = std::max(smax, mode_product_scratch(cols[k], dims[k]));
+    smax = std::max(smax, mode_product_scratch(dims[k], cols[k]));
+    int64_t rest = 1;
+    for (int j = 0; j < d; ++j)
+      if (j != k) rest *= std::max<int64_t>(dims[j], cols[j]);
+    umax = std::max(umax, (int64_t)unfold_gemm_splits(dims[k], rest) * dims[k] * cols[k]);
+  }
+  vp.mt = ws.take<double>((size_t)smax);
+  vp.upart = ws.take<double>((size_t)umax);
+  vp.epart = ws.take<double>((size_t)2 * expand_residual_blocks(prod(dims, 0, d)));
+}
+
+// X x_{j != k} F_j^T: result in FP64 (or X itself when order is 1)
+tk_status contract_all_but(const void* X, int xdt, int d, const int64_t* dims, const void* const* F,
+                           const int32_t* cols, int k, const VjpPlan& vp, hipStream_t st,
+                           const void** out, int* out_dt) {
+  int64_t shape[TK_MAX_ORDER];
+  for (int j = 0; j < d; ++j) shape[j] = dims[j];
+  const void* cur = X;
+  int cur_dt = xdt;
+  int which = 0;
+  for (int j = d - 1; j >= 0; --j) {
+    if (j == k) continue;
+    ModeProduct mp{};
+    mp.in = cur;
+    mp.A = prod(shape, 0, j);
+    mp.Q = shape[j];
+    mp.B = prod(shape, j + 1, d);
+    mp.P = cols[j];
+    mp.M = F[j];
+    mp.Mt = vp.mt;
+    mp.rs = 1;
+    mp.cs = cols[j];
+    mp.out = vp.buf[which];
+    TK_HIP(launch_mode_product(mp, cur_dt, TK_F64, factor_dtype(xdt), st));
+    shape[j] = cols[j];
+    cur = vp.buf[which];
+    cur_dt = TK_F64;
+    which ^= 1;
+  }
+  *out = cur;
+  *out_dt = cur_dt;
+  return TK_OK;
+}
+
+// G x_{j != k} F_j: result in FP64 (or G itself when order is 1)
+tk_status expand_all_but(const void* G, int fdt, int d, const int64_t* dims, const void* const* F,
+                         const int32_t* cols, int k, const VjpPlan& vp, hipStream_t st,
+                         const void** out, int* out_dt) {
+  int64_t shape[TK_MAX_ORDER];
+  for (int j = 0; j < d; ++j) shape[j] = cols[j];
+  const void* cur = G;
+  int cur_dt = fdt;
+  int which = 0;
+  for (int j = 0; j < d; ++j) {
+    if (j == k) continue;
+    ModeProduct mp{};
+    mp.in = cur;
+    mp.A = prod(shape, 0, j);
+    mp.Q = shape[j];
+    mp.B = prod(shape, j + 1, d);
+    mp.P = (int32_t)dims[j];
+    mp.M = F[j];
+    mp.Mt = vp.mt;
+    mp.rs = cols[j];
+    mp.cs = 1;
+    mp.out = vp.buf[which];
+    TK_HIP(launch_mode_product(mp, cur_dt, TK_F64, fdt, st));
+    shape[j] = dims[j];
+    cur = vp.buf[which];
+    cur_dt = TK_F64;
+    which ^= 1;
+  }
+  *out = cur;
+  *out_dt = cur_dt;
+  return TK_OK;
+}
+
+// out (+)= Gc x_1 F_1 .. x_d F_d (prod(dims) entries, fdt)
+tk_status expand_full(const void* Gc, int fdt, int d, const int64_t* dims, const void* const* F,
+                      const int32_t* cols, void* out, bool accumulate, const VjpPlan& vp,
+                      hipStream_t st) {
+  int64_t shape[TK_MAX_ORDER];
+  for (int j = 0; j < d; ++j) shape[j] = cols[j];
+  const void* cur = Gc;
+  int cur_dt = fdt;
+  int which = 0;
+  for (int j = 0; j < d - 1; ++j) {
+    ModeProduct mp{};
+    mp.in = cur;
+    mp.A = prod(shape, 0, j);
+    mp.Q = shape[j];
+    mp.B = prod(shape, j + 1, d);
+    mp.P = (int32_t)dims[j];
+    mp.M = F[j];
+    mp.Mt = vp.mt;
+    mp.rs = cols[j];
+    mp.cs = 1;
+    mp.out = vp.buf[which];
+    TK_HIP(launch_mode_product(mp, cur_dt, TK_F64, fdt, st));
+    shape[j] = dims[j];
+    cur = vp.buf[which];
+    cur_dt = TK_F64;
+    which ^= 1;
+  }
+  if (cur_dt != TK_F64) {
+    TK_HIP(launch_to_f64(cur, cur_dt, vp.buf[which], prod(shape, 0, d), st));
+    cur = vp.buf[which];
+  }
+  ExpandResidual e{};
+  e.T = static_cast<const double*>(cur);
+  e.F = F[d - 1];
+  e.X = nullptr;
+  e.Xhat = out;
+  e.partials = nullptr;
+  e.resid2 = nullptr;
+  e.A = prod(dims, 0, d - 1);
+  e.n = dims[d - 1];
+  e.c = cols[d - 1];
+  e.accumulate = accumulate ? 1 : 0;
+  TK_HIP(launch_expand_residual(e, fdt, fdt, st));
+  return TK_OK;
+}
+
+// out[i][a] (+)= sum A[.., i, ..] B[.., a, ..] over all modes but k; A has
+// dims[k] at mode k and B cols[k] (a_is_big: A's other modes are cols, else dims)
+tk_status unfold_product(const void* A, int adt, const void* B, int bdt, int d, const int64_t* dims,
+                         const int32_t* cols, int k, bool a_is_big, void* out, int out_dt,
+                         bool accumulate, const VjpPlan& vp, hipStream_t st) {
+  int64_t pre = 1, post = 1;
+  for (int j = 0; j < d; ++j) {
+    if (j == k) continue;
+    const int64_t e = a_is_big ? cols[j] : dims[j];
+    (j < k ? pre : post) *= e;
+  }
+  UnfoldGemm g{};
+  g.A = A;
+  g.B = B;
+  g.out = out;
+  g.partials = vp.upart;
+  g.pre = pre;
+  g.post = post;
+  g.n = (int32_t)dims[k];
+  g.c = cols[k];
+  g.splits = unfold_gemm_splits(dims[k], pre * post);
+  g.accumulate = accumulate ? 1 : 0;
+  TK_HIP(launch_unfold_gemm(g, adt, bdt, out_dt, st));
+  return TK_OK;
+}
+
 }  // namespace
 }  // namespace tk
 
@@ -704,9 +891,40 @@ tk_status tucker_core_vjp(const tk_tensor* X, const void* const* F, const int32_
                           const void* Gbar, void* Xbar, void* const* Fbar, int32_t accumulate,
                           void* ws, size_t* ws_bytes, void* stream) {
   clear_error();
-  (void)X; (void)F; (void)cols; (void)Gbar; (void)Xbar; (void)Fbar; (void)accumulate;
-  (void)ws; (void)ws_bytes; (void)stream;
-  return set_error(TK_EUNSUPPORTED, "tucker_core_vjp: not built yet");
+  int64_t N;
+  if (tk_status s = check_tensor(X, "tucker_core_vjp", &N)) return s;
+  if (X->dtype != TK_F64 && X->dtype != TK_F32)
+    return set_error(TK_EUNSUPPORTED, "tucker_core_vjp: tensor dtype must be F64 or F32");
+  if (tk_status s = check_factors(X->order, X->dims, F, cols, "tucker_core_vjp")) return s;
+  if (!Gbar) return set_error(TK_EINVAL, "tucker_core_vjp: Gbar is NULL");
+  if (!ws_bytes) return set_error(TK_EINVAL, "tucker_core_vjp: ws_bytes is NULL");
+  const int d = X->order;
+  const int fdt = factor_dtype(X->dtype);
+  Workspace w;
+  w.base = static_cast<char*>(ws);
+  VjpPlan vp;
+  plan_vjp(w, d, X->dims, cols, vp);
+  if (!ws) {
+    *ws_bytes = w.off;
+    return TK_OK;
+  }
+  if (*ws_bytes < w.off)
+    return set_error(TK_EWORKSPACE, "tucker_core_vjp: workspace %zu < required %zu", *ws_bytes, w.off);
+  hipStream_t st = as_stream(stream);
+  // Xbar (+)= Gbar x_1 F_1 .. x_d F_d
+  if (Xbar)
+    if (tk_status s = expand_full(Gbar, fdt, d, X->dims, F, cols, Xbar, accumulate != 0, vp, st)) return s;
+  // Fbar_k (+)= (X x_{j!=k} F_j^T)^(k) (Gbar^(k))^T
+  if (Fbar)
+    for (int k = 0; k < d; ++k) {
+      if (!Fbar[k]) continue;
+      const void* P = nullptr;
+      int pdt = 0;
+      if (tk_status s = contract_all_but(X->data, X->dtype, d, X->dims, F, cols, k, vp, st, &P, &pdt)) return s;
+      if (tk_status s = unfold_product(P, pdt, Gbar, fdt, d, X->dims, cols, k, true, Fbar[k], fdt,
+                                       accumulate != 0, vp, st)) return s;
+    }
+  return TK_OK;
 }
 
 tk_status tucker_reconstruct_vjp(int32_t order, const int64_t* dims, int32_t fdtype,
@@ -714,9 +932,42 @@ tk_status tucker_reconstruct_vjp(int32_t order, const int64_t* dims, int32_t fdt
                                  const void* H, void* Gbar, void* const* Fbar, void* ws,
                                  size_t* ws_bytes, void* stream) {
   clear_error();
-  (void)order; (void)dims; (void)fdtype; (void)G; (void)F; (void)cols; (void)H; (void)Gbar;
-  (void)Fbar; (void)ws; (void)ws_bytes; (void)stream;
-  return set_error(TK_EUNSUPPORTED, "tucker_reconstruct_vjp: not built yet");
+  if (order < 1 || order > TK_MAX_ORDER) return set_error(TK_EINVAL, "tucker_reconstruct_vjp: bad order %d", order);
+  if (!dims) return set_error(TK_EINVAL, "tucker_reconstruct_vjp: dims is NULL");
+  for (int k = 0; k < order; ++k)
+    if (dims[k] < 1) return set_error(TK_EINVAL, "tucker_reconstruct_vjp: dims[%d] < 1", k);
+  if (fdtype != TK_F64 && fdtype != TK_F32)
+    return set_error(TK_EINVAL, "tucker_reconstruct_vjp: fdtype must be TK_F64 or TK_F32");
+  if (!G || !H) return set_error(TK_EINVAL, "tucker_reconstruct_vjp: G or H is NULL");
+  if (tk_status s = check_factors(order, dims, F, cols, "tucker_reconstruct_vjp")) return s;
+  if (!ws_bytes) return set_error(TK_EINVAL, "tucker_reconstruct_vjp: ws_bytes is NULL");
+  Workspace w;
+  w.base = static_cast<char*>(ws);
+  VjpPlan vp;
+  plan_vjp(w, order, dims, cols, vp);
+  CorePlan cp;
+  plan_core(w, fdtype, order, dims, cols, cp);
+  if (!ws) {
+    *ws_bytes = w.off;
+    return TK_OK;
+  }
+  if (*ws_bytes < w.off)
+    return set_error(TK_EWORKSPACE, "tucker_reconstruct_vjp: workspace %zu < required %zu", *ws_bytes, w.off);
+  hipStream_t st = as_stream(stream);
+  // Gbar = H x_1 F_1^T .. x_d F_d^T (the core projection of H)
+  if (Gbar)
+    if (tk_status s = run_core(H, fdtype, order, dims, F, cols, Gbar, fdtype, cp, st)) return s;
+  // Fbar_k = H^(k) ((G x_{j!=k} F_j)^(k))^T
+  if (Fbar)
+    for (int k = 0; k < order; ++k) {
+      if (!Fbar[k]) continue;
+      const void* E = nullptr;
+      int edt = 0;
+      if (tk_status s = expand_all_but(G, fdtype, order, dims, F, cols, k, vp, st, &E, &edt)) return s;
+      if (tk_status s = unfold_product(H, fdtype, E, edt, order, dims, cols, k, false, Fbar[k], fdtype,
+                                       false, vp, st)) return s;
+    }
+  return TK_OK;
 }
 
 }  // extern "C"

@@ -100,7 +100,7 @@ struct ExpandResidual {
   double* resid2;       // final [2] or nullptr
   int64_t A, n;
   int32_t c;
-  int32_t pad;
+  int32_t accumulate;   // Xhat += instead of Xhat =
 };
 int64_t expand_residual_blocks(int64_t total);
 hipError_t launch_expand_residual(const ExpandResidual& e, int x_dt, int f_dt, hipStream_t st);
@@ -151,6 +151,22 @@ struct Transfer {
   int32_t pad;
 };
 hipError_t launch_transfer(const Transfer& t, int f_dt, hipStream_t st);
+
+// ---------------------------------------------------------------- unfolded products (VJPs)
+// out[i][a] (+)= sum_{p,q} A[p][i][q] B[p][a][q]: A is (pre, n, post), B is
+// (pre, c, post); the mode-k unfolding product A^(k) (B^(k))^T.
+struct UnfoldGemm {
+  const void* A;        // a_dt
+  const void* B;        // b_dt
+  void* out;            // n x c, out_dt
+  double* partials;     // [splits][n][c]
+  int64_t pre, post;
+  int32_t n, c;
+  int32_t splits;       // partial sums over ranges of (p, q), summed in order
+  int32_t accumulate;
+};
+int32_t unfold_gemm_splits(int64_t n, int64_t pre_post);
+hipError_t launch_unfold_gemm(const UnfoldGemm& g, int a_dt, int b_dt, int out_dt, hipStream_t st);
 
 // ---------------------------------------------------------------- conversions
 hipError_t launch_convert(const double* in, void* out, int out_dt, int64_t n, hipStream_t st);

@@ -1,0 +1,101 @@
+"""GPU parity of the hand-written backward (core and reconstruction VJPs
+behind torch.autograd) against the oracle's closed-form gradients, which the
+CPU tests pin to finite differences and to PyTorch's CPU autograd."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+
+def _grads_gpu(X, Fs, dtype):
+    from paper_2603_21379_amd import autograd as AG
+    Xd = torch.tensor(X, dtype=dtype, device="cuda", requires_grad=True)
+    Fd = [torch.tensor(f, dtype=dtype, device="cuda", requires_grad=True) for f in Fs]
+    L = AG.projection_loss(Xd, Fd)
+    L.backward()
+    torch.cuda.synchronize()
+    return float(L.detach()), Xd.grad.double().cpu().numpy(), [f.grad.double().cpu().numpy() for f in Fd]
+
+
+@pytest.mark.parametrize("dims,cols", [((4,) * 8, (3,) * 8), ((6, 5, 7), (2, 3, 4)),
+                                       ((9, 70, 33, 5), (4, 5, 6, 3)), ((80, 6, 5), (64, 3, 2))])
+def test_loss_gradients_match_oracle_fp64(dims, cols):
+    rng = np.random.default_rng(1)
+    X = rng.standard_normal(dims)
+    Fs = [np.linalg.qr(rng.standard_normal((n, c)))[0] for n, c in zip(dims, cols)]
+    L0, dX0, dF0 = oracle.loss_and_grads(X, Fs)
+    L, dX, dF = _grads_gpu(X, Fs, torch.float64)
+    assert abs(L - L0) <= 1e-12 * abs(L0)
+    np.testing.assert_allclose(dX, dX0, rtol=0, atol=1e-11 * np.abs(dX0).max())
+    for a, b in zip(dF, dF0):
+        np.testing.assert_allclose(a, b, rtol=0, atol=1e-11 * np.abs(b).max())
+
+
+def test_loss_gradients_match_oracle_fp32():
+    dims, cols = (16, 20, 30, 132), (5, 6, 12, 20)
+    rng = np.random.default_rng(2)
+    X = rng.standard_normal(dims).astype(np.float32)
+    Fs = [np.linalg.qr(rng.standard_normal((n, c)))[0].astype(np.float32)
+          for n, c in zip(dims, cols)]
+    L0, dX0, dF0 = oracle.loss_and_grads(X.astype(np.float64), [f.astype(np.float64) for f in Fs])
+    L, dX, dF = _grads_gpu(X, Fs, torch.float32)
+    assert abs(L - L0) <= 1e-4 * abs(L0)
+    np.testing.assert_allclose(dX, dX0, rtol=0, atol=1e-5 * np.abs(dX0).max())
+    for a, b in zip(dF, dF0):
+        np.testing.assert_allclose(a, b, rtol=0, atol=1e-4 * np.abs(b).max())
+
+
+def test_gpu_directional_derivative_fd_4pow8():
+    """Central differences of the GPU loss itself (FP64) along random directions."""
+    from paper_2603_21379_amd import autograd as AG
+    rng = np.random.default_rng(3)
+    dims, cols = (4,) * 8, (3,) * 8
+    X = rng.standard_normal(dims)
+    Fs = [np.linalg.qr(rng.standard_normal((n, c)))[0] for n, c in zip(dims, cols)]
+    _, dX, dF = _grads_gpu(X, Fs, torch.float64)
+
+    def loss(Xn, Fn):
+        with torch.no_grad():
+            return float(AG.projection_loss(torch.tensor(Xn, device="cuda"),
+                                            [torch.tensor(f, device="cuda") for f in Fn]))
+    h = 1e-4
+    for _ in range(4):
+        VX = rng.standard_normal(dims)
+        VF = [rng.standard_normal(f.shape) for f in Fs]
+
+        def cd(step):
+            return (loss(X + step * VX, [f + step * v for f, v in zip(Fs, VF)])
+                    - loss(X - step * VX, [f - step * v for f, v in zip(Fs, VF)])) / (2 * step)
+        fd = (4 * cd(h / 2) - cd(h)) / 3
+        an = float(np.sum(dX * VX) + sum(np.sum(a * v) for a, v in zip(dF, VF)))
+        assert abs(fd - an) <= 1e-7 * max(1.0, abs(an))
+
+
+def test_core_vjp_accumulate_and_partial_outputs():
+    from paper_2603_21379_amd import binding as B
+    rng = np.random.default_rng(4)
+    dims, cols = (7, 8, 9), (3, 2, 4)
+    X = torch.tensor(rng.standard_normal(dims), device="cuda")
+    F = [torch.tensor(rng.standard_normal((n, c)), device="cuda") for n, c in zip(dims, cols)]
+    Gb = torch.tensor(rng.standard_normal(cols), device="cuda")
+    Xbar = torch.ones(dims, dtype=torch.float64, device="cuda")
+    Fbar = [None, torch.zeros(8, 2, dtype=torch.float64, device="cuda"), None]
+    B.tucker_core_vjp(X, F, Gb, Xbar=Xbar, Fbar=Fbar, accumulate=True)
+    Xn = X.cpu().numpy()
+    Fn = [f.cpu().numpy() for f in F]
+    Xb0, Fb0 = oracle.core_vjp(Xn, Fn, Gb.cpu().numpy())
+    np.testing.assert_allclose(Xbar.cpu().numpy(), 1.0 + Xb0, atol=1e-12)
+    np.testing.assert_allclose(Fbar[1].cpu().numpy(), Fb0[1], atol=1e-11 * np.abs(Fb0[1]).max())
+
+
+def test_core_vjp_rejects_rank_above_64():
+    from paper_2603_21379_amd import binding as B
+    dims, cols = (80, 6, 5), (70, 3, 2)
+    X = torch.zeros(dims, dtype=torch.float64, device="cuda")
+    F = [torch.zeros(n, c, dtype=torch.float64, device="cuda") for n, c in zip(dims, cols)]
+    Gb = torch.zeros(cols, dtype=torch.float64, device="cuda")
+    with pytest.raises(B.TkError, match="exceeds 64"):
+        B.tucker_core_vjp(X, F, Gb, Xbar=torch.empty_like(X))
