@@ -37,9 +37,51 @@ def parse():
     ap.add_argument("--config", default="c2")
     ap.add_argument("--core", default="U", choices=["U", "Q"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
-    ap.add_argument("--cpu-slabs", type=int, default=4,
+    ap.add_argument("--cpu-slabs", type=int, default=12,
                     help="mode-0 slabs of X the oracle core baseline processes")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain device copy of known size (for scaling the "
+                         "FETCH_SIZE / WRITE_SIZE counters of the streaming pass)")
     return ap.parse_args()
+
+
+# HBM bytes per launch of the streaming pass, from rocprofv3 FETCH_SIZE and
+# WRITE_SIZE runs scaled by a plain copy of known size; valid only for the
+# kernel source it was taken on
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "core_stream_f32_256x4_traffic.txt")
+KERNEL_SRC = os.path.join(ROOT, "paper_2603_21379_amd", "csrc", "k_core_f32.hip")
+
+
+def measured_traffic(workload_name):
+    import hashlib
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    kv = {}
+    with open(TRAFFIC_FILE) as f:
+        for line in f:
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                kv[k.strip()] = v.strip()
+    with open(KERNEL_SRC, "rb") as f:
+        sha = hashlib.sha256(f.read()).hexdigest()
+    if kv.get("kernel_source_sha256") != sha or kv.get("workload") != workload_name:
+        return None
+    try:
+        return float(kv["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def copy_calibration():
+    import torch
+    nbytes = 4 << 30
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda:0")
+    dst = torch.empty_like(src)
+    for _ in range(5):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": nbytes, "copy_bytes_written": nbytes, "launches": 5}),
+          flush=True)
 
 
 def workload(name):
@@ -59,6 +101,9 @@ def log(msg):
 
 def main():
     args = parse()
+    if args.copy_calibration:
+        copy_calibration()
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
               "(the multi-GPU sharding is a design, not a build)", file=sys.stderr)
@@ -127,16 +172,26 @@ def main():
 
     B.tk_profile_read(reset=True)
     B.tk_profile_enable(True)
+    # events on the stream the library launches on (torch's current stream)
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(args.steps)]
     torch.cuda.synchronize()
     t_start = time.perf_counter()
-    for _ in range(args.steps):
-        step(ws)
+    for i in range(args.steps):
+        ev[i][0].record()
+        B.tucker_sketch_all_modes(X, skd, Z, Y, ws=ws)
+        ev[i][1].record()
+        B.tucker_qr(Z, Y, r=cols, U=F, info=info, ws=ws)
+        ev[i][2].record()
+        B.tucker_core(X, F, G, ws=ws)
+        ev[i][3].record()
     torch.cuda.synchronize()
     t_stop = time.perf_counter()
     B.tk_profile_enable(False)
     core_ms, launches = B.tk_profile_read(reset=True)
     ms_per_step = (t_stop - t_start) * 1e3 / args.steps
-    log(f"timed {args.steps} steps: {ms_per_step:.3f} ms/step; streaming pass "
+    stage = [sum(e[j].elapsed_time(e[j + 1]) for e in ev) / args.steps for j in range(3)]
+    log(f"timed {args.steps} steps: {ms_per_step:.3f} ms/step (sketch {stage[0]:.3f}, "
+        f"qr+w {stage[1]:.3f}, core {stage[2]:.3f}); streaming pass "
         f"{core_ms / max(launches, 1):.3f} ms x {launches}")
 
     b_sketch = sum(s * n for s, n in zip(ss, dims)) * esize
@@ -144,6 +199,10 @@ def main():
     value = (b_sketch + b_core) / (ms_per_step * 1e-3) / 1e9
     core_avg_ms = core_ms / max(launches, 1)
     achieved = b_core / (core_avg_ms * 1e-3) / 1e9
+
+    sketch_core_gbs = (b_sketch + b_core) / ((stage[0] + stage[2]) * 1e-3) / 1e9
+    flops_core = core_flops(dims, cols)
+    traffic = measured_traffic(cfg.name)
 
     eps = T.rel_error(X, G, F)
     info_h = info.cpu().tolist()
@@ -166,17 +225,33 @@ def main():
                    "ranks": list(ranks), "p": cfg.p, "s": ss, "core_factor": args.core,
                    "decay": cfg.decay, "noise_rel": cfg.noise},
         "frac_hbm_step": round(value / HBM_PEAK_GBS, 4),
+        "sketch_core": {"gbs": round(sketch_core_gbs, 1),
+                        "frac_hbm": round(sketch_core_gbs / HBM_PEAK_GBS, 4),
+                        "ms_sketch": round(stage[0], 4), "ms_qr_w": round(stage[1], 4),
+                        "ms_core": round(stage[2], 4)},
+        "core_tflops": round(flops_core / (stage[2] * 1e-3) / 1e12, 2),
         "rel_err_gpu": eps,
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": None, "kernel": "core streaming pass",
-                     "avg_ms": round(core_avg_ms, 4)},
+                     "traffic": traffic, "kernel": "core streaming pass",
+                     "avg_ms": round(core_avg_ms, 4),
+                     "bytes_per_launch": b_core},
     }
     del Y, Z
     torch.cuda.empty_cache()
     if not args.no_cpu:
         result["cpu_baseline"] = cpu_baseline(inp, sk, dims, ranks, cols, dtype, args, F)
     print(json.dumps(result), flush=True)
+
+
+def core_flops(dims, cols):
+    """Algorithmic flops of the core projection contracting the last mode
+    first: sum over k of 2 * prod(cols[k:]) * prod(dims[:k+1])."""
+    d = len(dims)
+    total = 0
+    for k in range(d - 1, -1, -1):
+        total += 2 * math.prod(dims[:k + 1]) * math.prod(cols[k:])
+    return total
 
 
 def cpu_baseline(inp, sk, dims, ranks, cols, dtype, args, F_gpu):
