@@ -1,0 +1,124 @@
+// Contraction of one leading or middle mode of an FP32 tensor on MFMA (the
+// TTM of Section 2.2 with F^T):
+//   out[a][p][b] = sum_q F[q][p] in[a][q][b]      (p < P <= 32)
+// used for the modes that remain after the streaming pass of the core, where
+// `in` is the partial core (much smaller than X but still hundreds of MB for
+// large tensors).
+//
+// One wavefront owns a unit (a, 128 consecutive b) and walks q two rows at a
+// time with v_mfma_f32_32x32x2f32: the A operand is F^T from LDS (lane l
+// gives F[q + l/32][p = l%32]), the B operand comes from one float4 per lane,
+// in[a][q + l/32][b0 + 4 (l%32) .. +3], whose component c is the B tile of
+// the four accumulators for columns b = b0 + 4 n + c.  Rows past Q read zero
+// through the buffer range check; columns past B only feed output columns
+// that are not stored.
+#include "tk_kernels.hpp"
+
+namespace tk {
+namespace {
+
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+constexpr int kCols = 128;
+constexpr int kWaves = 4;
+constexpr int kKB = 8;        // row pairs per load batch
+constexpr int kRsrcWord3 = 0x00020000;
+
+__device__ __forceinline__ floatx16 mfma32(float a, float b, floatx16 c) {
+  return __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, c, 0, 0, 0);
+}
+
+template <typename TOut>
+__global__ __launch_bounds__(256) void mode_mfma_f32_kernel(const ModeMfma m) {
+  extern __shared__ float sF[];   // [Qp][32], zero padded
+  const int Qp = (int)((m.Q + 2 * kKB - 1) / (2 * kKB)) * 2 * kKB;
+  for (int e = threadIdx.x; e < Qp * 32; e += blockDim.x) {
+    const int q = e >> 5, p = e & 31;
+    sF[e] = (q < m.Q && p < m.P) ? m.F[(int64_t)q * m.P + p] : 0.0f;
+  }
+  __syncthreads();
+
+  const int lane = threadIdx.x & 63, kh = lane >> 5, l32 = lane & 31;
+  const int64_t nBb = (m.B + kCols - 1) / kCols;
+  const int64_t unit = (int64_t)blockIdx.x * kWaves + (threadIdx.x >> 6);
+  if (unit >= m.A * nBb) return;  // no barrier follows
+  const int64_t a = unit / nBb;
+  const int64_t b0 = (unit - a * nBb) * kCols;
+  const int64_t slab = m.Q * m.B;
+  const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+      const_cast<float*>(m.in + a * slab), (short)0, (int)(slab * 4), kRsrcWord3);
+  const int64_t b = b0 + 4 * l32;
+  const bool colok = b < m.B;
+  const uint32_t rowb = (uint32_t)(m.B * 4);
+
+  auto load = [&](int q0, floatx4 (&buf)[kKB]) {
+#pragma unroll
+    for (int u = 0; u < kKB; ++u) {
+      const int q = q0 + 2 * u + kh;
+      const uint32_t off = (colok && q < m.Q) ? (uint32_t)q * rowb + (uint32_t)(b * 4) : 0x80000000u;
+      buf[u] = __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, 0);
+    }
+  };
+  floatx16 acc[4];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) acc[c] = floatx16{};
+  auto compute = [&](int q0, const floatx4 (&buf)[kKB]) {
+    const float* f = sF + (q0 + kh) * 32 + l32;
+#pragma unroll
+    for (int u = 0; u < kKB; ++u) {
+      const float fv = f[u * 64];
+      acc[0] = mfma32(fv, buf[u][0], acc[0]);
+      acc[1] = mfma32(fv, buf[u][1], acc[1]);
+      acc[2] = mfma32(fv, buf[u][2], acc[2]);
+      acc[3] = mfma32(fv, buf[u][3], acc[3]);
+    }
+  };
+  floatx4 bufA[kKB], bufB[kKB];
+  load(0, bufA);
+  for (int q0 = 0; q0 < Qp; q0 += 4 * kKB) {
+    const bool second = q0 + 2 * kKB < Qp;
+    if (second) load(q0 + 2 * kKB, bufB);
+    __builtin_amdgcn_sched_barrier(0);
+    compute(q0, bufA);
+    if (!second) break;
+    if (q0 + 4 * kKB < Qp) load(q0 + 4 * kKB, bufA);
+    __builtin_amdgcn_sched_barrier(0);
+    compute(q0 + 2 * kKB, bufB);
+  }
+  // acc[c] register v: p = 8 (v/4) + 4 kh + v%4, column b + c
+  TOut* out = static_cast<TOut*>(m.out) + a * (int64_t)m.P * m.B;
+  if (!colok) return;
+  const int ncol = (int)min<int64_t>(4, m.B - b);
+#pragma unroll
+  for (int v = 0; v < 16; ++v) {
+    const int p = 8 * (v >> 2) + 4 * kh + (v & 3);
+    if (p >= m.P) continue;
+    TOut* o = out + (int64_t)p * m.B + b;
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+      if (c < ncol) o[c] = (TOut)acc[c][v];
+  }
+}
+
+}  // namespace
+
+bool mode_mfma_supported(int64_t Q, int64_t B, int32_t P) {
+  // F^T staged in LDS (at most 64 KB); one (Q x B) slab addressed in 31 bits
+  return P >= 1 && P <= 32 && Q >= 1 && Q <= 512 && B >= 1 && Q * B * 4 < (int64_t(1) << 31);
+}
+
+hipError_t launch_mode_mfma_f32(const ModeMfma& m, int out_dt, hipStream_t st) {
+  if (m.A * m.B == 0) return hipSuccess;
+  const int64_t Qp = (m.Q + 2 * kKB - 1) / (2 * kKB) * 2 * kKB;
+  const size_t lds = (size_t)Qp * 32 * sizeof(float);
+  const int64_t units = m.A * ((m.B + kCols - 1) / kCols);
+  const dim3 grid((unsigned)ceil_div(units, kWaves));
+  if (out_dt == TK_F64)
+    hipLaunchKernelGGL((mode_mfma_f32_kernel<double>), grid, dim3(256), lds, st, m);
+  else
+    hipLaunchKernelGGL((mode_mfma_f32_kernel<float>), grid, dim3(256), lds, st, m);
+  return hipGetLastError();
+}
+
+}  // namespace tk

@@ -172,25 +172,44 @@ tk_status check_factors(int order, const int64_t* dims, const void* const* F, co
   return TK_OK;
 }
 
-// Chain of contractions G = X x_k F_k^T, last mode first.  Intermediates are
-// FP64, except the output of the fused FP32 streaming pass (FP32, A x c x c).
+// Chain of contractions G = X x_k F_k^T, last mode first.  The streaming
+// pass contracts the two (or three) trailing modes in one read of X when a
+// fused kernel covers the shape; the rest runs on the partial core.
+// Intermediates are FP64, except the FP32 partial cores of the fused passes
+// and their MFMA successors.
+enum CoreKind { kCoreGeneric = 0, kCoreFused2 = 1, kCoreSlab2 = 2, kCoreSlab3 = 3 };
 struct CorePlan {
   double* buf[2] = {nullptr, nullptr};
   float* t32 = nullptr;
   double* mt = nullptr;   // staged factor table of the mode products
-  bool fused = false;
+  int kind = kCoreGeneric;
+  int fused_modes = 0;
 };
+
+int core_kind(int xdt, int order, const int64_t* dims, const int32_t* cols) {
+  if (fused2_supported(xdt, order, dims, cols)) return kCoreFused2;
+  if (order < 3) return kCoreGeneric;
+  const int64_t nI = dims[order - 2], nJ = dims[order - 1];
+  if (!slab_supported(xdt, nI, nJ, cols[order - 2], cols[order - 1])) return kCoreGeneric;
+  const int64_t A = prod(dims, 0, order - 2);
+  if (A >= (int64_t(1) << 31)) return kCoreGeneric;
+  // accumulate the third mode in registers when that still leaves work for
+  // every wave of the grid (it shrinks the partial core n_H / c_H times)
+  if (order >= 4 && cols[order - 3] <= 16 && dims[order - 3] <= 512 && A / dims[order - 3] >= 2048)
+    return kCoreSlab3;
+  return kCoreSlab2;
+}
 
 tk_status plan_core(Workspace& ws, int xdt, int order, const int64_t* dims, const int32_t* cols,
                     CorePlan& p) {
   int64_t shape[TK_MAX_ORDER];
   for (int k = 0; k < order; ++k) shape[k] = dims[k];
-  p.fused = fused2_supported(xdt, order, dims, cols);
+  p.kind = core_kind(xdt, order, dims, cols);
+  p.fused_modes = p.kind == kCoreGeneric ? 0 : p.kind == kCoreSlab3 ? 3 : 2;
   int64_t mx = 0;
-  const int first = p.fused ? order - 3 : order - 1;
-  if (p.fused) {
-    shape[order - 1] = cols[order - 1];
-    shape[order - 2] = cols[order - 2];
+  const int first = p.fused_modes ? order - 1 - p.fused_modes : order - 1;
+  if (p.fused_modes) {
+    for (int k = order - p.fused_modes; k < order; ++k) shape[k] = cols[k];
     p.t32 = ws.take<float>((size_t)prod(shape, 0, order));
   }
   for (int k = first; k >= 1; --k) {
@@ -213,7 +232,7 @@ tk_status run_core(const void* X, int xdt, int order, const int64_t* dims,
   const void* cur = X;
   int cur_dt = xdt;
   int kstart = order - 1;
-  if (p.fused) {
+  if (p.kind == kCoreFused2) {
     // the two trailing modes in one MFMA pass over X
     CoreFused2 f{};
     f.X = static_cast<const float*>(X);
@@ -228,13 +247,50 @@ tk_status run_core(const void* X, int xdt, int order, const int64_t* dims,
     TK_HIP(profile_begin(st));
     TK_HIP(launch_fused2_f32(f, st));
     TK_HIP(profile_end(st));
-    shape[order - 1] = cols[order - 1];
-    shape[order - 2] = cols[order - 2];
+  } else if (p.kind == kCoreSlab2 || p.kind == kCoreSlab3) {
+    // two or three trailing modes in one MFMA pass over X (16x16 tiles)
+    const bool h3 = p.kind == kCoreSlab3;
+    CoreSlab f{};
+    f.X = X;
+    f.FH = h3 ? static_cast<const float*>(F[order - 3]) : nullptr;
+    f.FI = static_cast<const float*>(F[order - 2]);
+    f.FJ = static_cast<const float*>(F[order - 1]);
+    f.T = p.t32;
+    f.items = prod(dims, 0, order - (h3 ? 3 : 2));
+    f.nH = h3 ? (int32_t)dims[order - 3] : 1;
+    f.nI = (int32_t)dims[order - 2];
+    f.nJ = (int32_t)dims[order - 1];
+    f.cH = h3 ? cols[order - 3] : 1;
+    f.cI = cols[order - 2];
+    f.cJ = cols[order - 1];
+    TK_HIP(profile_begin(st));
+    TK_HIP(launch_core_slab(f, xdt, st));
+    TK_HIP(profile_end(st));
+  }
+  if (p.fused_modes) {
+    for (int k = order - p.fused_modes; k < order; ++k) shape[k] = cols[k];
     cur = p.t32;
     cur_dt = TK_F32;
-    kstart = order - 3;
+    kstart = order - 1 - p.fused_modes;
   }
   for (int k = kstart; k >= 0; --k) {
+    if (cur_dt == TK_F32 && fdt == TK_F32 &&
+        mode_mfma_supported(shape[k], prod(shape, k + 1, order), cols[k])) {
+      // FP32 partial core: MFMA contraction, FP32 intermediates
+      ModeMfma mm{};
+      mm.in = static_cast<const float*>(cur);
+      mm.F = static_cast<const float*>(F[k]);
+      mm.A = prod(shape, 0, k);
+      mm.Q = shape[k];
+      mm.B = prod(shape, k + 1, order);
+      mm.P = cols[k];
+      void* out = k == 0 ? G : (void*)p.buf[(kstart - k) & 1];
+      mm.out = out;
+      TK_HIP(launch_mode_mfma_f32(mm, TK_F32, st));
+      shape[k] = cols[k];
+      cur = out;
+      continue;
+    }
     ModeProduct mp{};
     mp.in = cur;
     mp.A = prod(shape, 0, k);
@@ -247,7 +303,7 @@ tk_status run_core(const void* X, int xdt, int order, const int64_t* dims,
     mp.cs = cols[k];
     void* out = k == 0 ? G : (void*)p.buf[(kstart - k) & 1];
     mp.out = out;
-    const bool streaming = k == order - 1 && !p.fused;  // the launch that reads X
+    const bool streaming = k == order - 1 && !p.fused_modes;  // the launch that reads X
     if (streaming) TK_HIP(profile_begin(st));
     TK_HIP(launch_mode_product(mp, cur_dt, k == 0 ? fdt : TK_F64, fdt, st));
     if (streaming) TK_HIP(profile_end(st));

@@ -120,6 +120,37 @@ struct CoreFused2 {
 bool fused2_supported(int dtype, int order, const int64_t* dims, const int32_t* cols);
 hipError_t launch_fused2_f32(const CoreFused2& p, hipStream_t st);
 
+// ---------------------------------------------------------------- small-mode streaming core
+// T[a] = F_I^T X[a] F_J for the slabs X[a] (n_I x n_J) of an FP32, BF16 or
+// FP16 tensor, or (FH != nullptr) T3[r] = sum_h F_H[h] (x) F_I^T X[r,h] F_J.
+struct CoreSlab {
+  const void* X;
+  const float* FH;      // nH x cH, or nullptr
+  const float* FI;      // nI x cI
+  const float* FJ;      // nJ x cJ
+  float* T;             // (items, [cH,] cI, cJ)
+  int64_t items;        // slabs, or runs of nH slabs
+  int32_t nH, nI, nJ;
+  int32_t cH, cI, cJ;
+  int32_t nwaves;       // set by the launcher
+  int32_t pad;
+};
+bool slab_supported(int dtype, int64_t nI, int64_t nJ, int32_t cI, int32_t cJ);
+hipError_t launch_core_slab(const CoreSlab& p, int xdt, hipStream_t st);
+
+// ---------------------------------------------------------------- FP32 MFMA mode contraction
+// out[a][p][b] = sum_q F[q][p] in[a][q][b] for an FP32 (A, Q, B) tensor, P <= 32.
+struct ModeMfma {
+  const float* in;
+  const float* F;       // Q x P row-major
+  void* out;            // (A, P, B), FP32 or FP64
+  int64_t A, Q, B;
+  int32_t P;
+  int32_t pad;
+};
+bool mode_mfma_supported(int64_t Q, int64_t B, int32_t P);
+hipError_t launch_mode_mfma_f32(const ModeMfma& m, int out_dt, hipStream_t st);
+
 // ---------------------------------------------------------------- FP32 fused streaming residual
 // sum (X[a] - F_I T[a] F_J^T)^2 and sum X[a]^2 over the A slabs of an FP32 tensor.
 struct ResidFused2 {

@@ -95,6 +95,28 @@ def _threads() -> int:
     return max(1, min(16, len(os.sched_getaffinity(0))))
 
 
+def _single_blas(fn):
+    """Run a generator with one BLAS thread.
+
+    A multi-threaded BLAS may split a product differently from run to run
+    (or with the thread count), which changes the last bits of the result;
+    the generators parallelise over slabs themselves instead, so the same
+    seed gives the same bytes on every run."""
+    import functools
+
+    @functools.wraps(fn)
+    def wrapped(*a, **kw):
+        from threadpoolctl import threadpool_limits
+        with threadpool_limits(limits=1, user_api="blas"):
+            return fn(*a, **kw)
+    return wrapped
+
+
+def _parallel_slabs(fn, count: int, threads: int | None):
+    with ThreadPoolExecutor(threads or _threads()) as ex:
+        list(ex.map(fn, range(count)))
+
+
 # ---------------------------------------------------------------- Tucker tensors
 @dataclass
 class TuckerInput:
@@ -108,6 +130,7 @@ class TuckerInput:
     noise: float             # relative noise level
 
 
+@_single_blas
 def tucker_tensor(dims, ranks, decay: float, noise: float, cfg: int, dtype: str = "f64",
                   run: int = 0, threads: int | None = None) -> TuckerInput:
     """Low-rank Tucker tensor plus relative Gaussian noise.
@@ -141,8 +164,7 @@ def tucker_tensor(dims, ranks, decay: float, noise: float, cfg: int, dtype: str 
             t = t + noise * g.standard_normal(t.shape)
         X[i0] = to_storage(t, dtype)
 
-    with ThreadPoolExecutor(threads or _threads()) as ex:
-        list(ex.map(slab, range(dims[0])))
+    _parallel_slabs(slab, dims[0], threads)
     return TuckerInput(dims, ranks, dtype, X, core, factors, scale, noise)
 
 
@@ -275,6 +297,7 @@ class HTInput:
     noise: float
 
 
+@_single_blas
 def ht_tensor(n: int, order: int, rank: int, noise: float, cfg: int, dtype: str = "f32",
               run: int = 0, threads: int | None = None) -> HTInput:
     """Tensor of hierarchical rank `rank` on the balanced tree, plus noise.
@@ -333,8 +356,7 @@ def ht_tensor(n: int, order: int, rank: int, noise: float, cfg: int, dtype: str 
             t = t + noise * _rng(cfg, _NOISE, run, i0).standard_normal(t.shape)
         X[i0] = to_storage(t, dtype).reshape(dims[1:])
 
-    with ThreadPoolExecutor(threads or _threads()) as ex:
-        list(ex.map(slab, range(n)))
+    _parallel_slabs(slab, n, threads)
     return HTInput(dims, X, dtype, tr, leaf, trans, root, scale, noise)
 
 
