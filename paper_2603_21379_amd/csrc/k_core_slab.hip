@@ -32,6 +32,8 @@
 // factor rows.  Waves are persistent over work items (slabs, or runs of n_H
 // slabs when the third mode is accumulated), with NBUF units of loads in
 // flight.
+#include <stdlib.h>
+
 #include <type_traits>
 
 #include "tk_kernels.hpp"
@@ -99,22 +101,10 @@ __device__ __forceinline__ floatx4 mma_f32(float a, float b, floatx4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
 
-struct Cur {
-  int item;  // work item, or -1 past the end
-  int h;     // slab within the item
-  int t;     // 16-row tile
-};
-__device__ __forceinline__ Cur uni(Cur c) {
-  c.item = __builtin_amdgcn_readfirstlane(c.item);
-  c.h = __builtin_amdgcn_readfirstlane(c.h);
-  c.t = __builtin_amdgcn_readfirstlane(c.t);
-  return c;
-}
-
 // TX: float, bf16 or f16.  NK: column chunks of stage 1 (32 columns for
 // 16-bit, 16 for FP32), NT: row tiles (16 rows), both upper bounds of the
 // runtime sizes.  H3: accumulate the third trailing mode.
-template <typename TX, int NK, int NT, bool H3, int NBUF>
+template <typename TX, int NK, int NT, int TG, bool H3, int NBUF>
 __global__ __launch_bounds__(256, 2) void core_slab_kernel(const CoreSlab p) {
   constexpr bool kF32 = sizeof(TX) == 4;
   constexpr int kChunk = kF32 ? 16 : 32;      // columns per chunk
@@ -205,162 +195,177 @@ __global__ __launch_bounds__(256, 2) void core_slab_kernel(const CoreSlab p) {
     }
   }
 
-  const int64_t slab_elems = (int64_t)p.nI * p.nJ;
   const int nH = H3 ? p.nH : 1;
-  auto load_unit = [&](Cur c, uintx4 (&buf)[NK]) {
-    c = uni(c);
-    const bool live = c.item >= 0;
-    const int64_t slab = live ? (int64_t)c.item * nH + c.h : 0;
-    const TX* base = static_cast<const TX*>(p.X) + slab * slab_elems;
+  const uint32_t slab_bytes = (uint32_t)p.nI * (uint32_t)p.nJ * (uint32_t)sizeof(TX);
+  // lane part of every load offset (row l16 of a tile, column kPer g); tiles
+  // add 16 rows, chunks an immediate; rows past n_I fall past the slab
+  const uint32_t lane_off = (uint32_t)(l16 * p.nJ + kPer * g) * (uint32_t)sizeof(TX);
+  const uint32_t tile_bytes = (uint32_t)(16 * p.nJ) * (uint32_t)sizeof(TX);
+  const char* Xb = static_cast<const char*>(p.X);
+
+  // one unit = TG tiles (group grp) of slab (item, h); item = -1 past the end
+  const int nG = (nT + TG - 1) / TG;
+  auto load_unit = [&](int item, int h, int grp, uintx4 (&buf)[TG][NK]) {
+    item = __builtin_amdgcn_readfirstlane(item);
+    h = __builtin_amdgcn_readfirstlane(h);
+    grp = __builtin_amdgcn_readfirstlane(grp);
+    const bool live = item >= 0;
+    const int64_t slab = live ? (int64_t)item * nH + h : 0;
     const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
-        const_cast<TX*>(base), (short)0, live ? (int)(slab_elems * sizeof(TX)) : 0, kRsrcWord3);
-    const int i = 16 * c.t + l16;
-    const uint32_t row = i < p.nI ? (uint32_t)(i * p.nJ + kPer * g) * (uint32_t)sizeof(TX) : 0x80000000u;
+        const_cast<char*>(Xb + slab * slab_bytes), (short)0, live ? (int)slab_bytes : 0, kRsrcWord3);
 #pragma unroll
-    for (int kc = 0; kc < NK; ++kc) {
-      if (kc < nK)
-        buf[kc] = __builtin_bit_cast(
-            uintx4, __builtin_amdgcn_raw_buffer_load_b128(
-                        rs, row + (row == 0x80000000u ? 0u : (uint32_t)(kc * kChunk * sizeof(TX))), 0, 2));
+    for (int tt = 0; tt < TG; ++tt) {
+      const int t = grp * TG + tt;
+      if (t >= nT) continue;
+      const uint32_t off = lane_off + t * tile_bytes;
+#pragma unroll
+      for (int kc = 0; kc < NK; ++kc)
+        if (kc < nK)
+          buf[tt][kc] = __builtin_bit_cast(
+              uintx4, __builtin_amdgcn_raw_buffer_load_b128(rs, off + kc * kChunk * (int)sizeof(TX), 0, 2));
     }
-  };
-  auto advance = [&](Cur c) {
-    c = uni(c);
-    if (c.item < 0) return c;
-    if (++c.t >= nT) {
-      c.t = 0;
-      if (++c.h >= nH) {
-        c.h = 0;
-        c.item = c.item + nwaves < items ? c.item + nwaves : -1;
-      }
-    }
-    return uni(c);
   };
 
-  floatx4 accE = floatx4{}, tacc = floatx4{};
   floatx4 acc3[H3 ? kMaxC : 1];
 #pragma unroll
   for (int q = 0; q < (H3 ? kMaxC : 1); ++q) acc3[q] = floatx4{};
 
-  auto compute = [&](Cur c, uintx4 (&buf)[NK]) {
-    c = uni(c);
-    floatx4 acc = floatx4{};
+  floatx4 tacc = floatx4{};
+  auto compute_unit = [&](int item, int h, int grp, uintx4 (&buf)[TG][NK]) {
+    floatx4 accE = floatx4{};
 #pragma unroll
-    for (int kc = 0; kc < NK; ++kc) {
-      if (kc >= nK) continue;
-      uintx4 x = buf[kc];
-      if (kc == nK - 1) x &= lastmask;
+    for (int tt = 0; tt < TG; ++tt) {
+      const int t = grp * TG + tt;
+      if (t >= nT) continue;
+      floatx4 acc = floatx4{};
+#pragma unroll
+      for (int kc = 0; kc < NK; ++kc) {
+        if (kc >= nK) continue;
+        uintx4 x = buf[tt][kc];
+        if (kc == nK - 1) x &= lastmask;
+        if constexpr (kF32) {
+          const floatx4 xf = __builtin_bit_cast(floatx4, x);
+#pragma unroll
+          for (int cc = 0; cc < 4; ++cc) acc = mma_f32(xf[cc], fj32[kc][cc], acc);
+        } else {
+          typedef Lp<typename std::conditional<kF32, bf16, TX>::type> L;
+          const typename L::vec xv = __builtin_bit_cast(typename L::vec, x);
+          acc = L::mma(xv, fjh[kc], acc);
+          acc = L::mma(xv, fjl[kc], acc);
+        }
+      }
       if constexpr (kF32) {
-        const floatx4 xf = __builtin_bit_cast(floatx4, x);
+        const float* a = sA + t * 256 + lane;
 #pragma unroll
-        for (int cc = 0; cc < 4; ++cc) acc = mma_f32(xf[cc], fj32[kc][cc], acc);
+        for (int v = 0; v < 4; ++v) tacc = mma_f32(a[v * 64], acc[v], tacc);
       } else {
-        typedef typename Lp<typename std::conditional<kF32, bf16, TX>::type>::vec V;
-        const V xv = __builtin_bit_cast(V, x);
-        acc = Lp<typename std::conditional<kF32, bf16, TX>::type>::mma(xv, fjh[kc], acc);
-        acc = Lp<typename std::conditional<kF32, bf16, TX>::type>::mma(xv, fjl[kc], acc);
-      }
-    }
-    if constexpr (kF32) {
-      const float* a = sA + c.t * 256 + lane;
+        // tiles pair up into one K = 32 step (an odd last tile pairs with zero)
+        const bool even = (tt & 1) == 0;
+        if (even && t + 1 < nT) {
+          accE = acc;
+        } else {
+          float d[8];
 #pragma unroll
-      for (int v = 0; v < 4; ++v) tacc = mma_f32(a[v * 64], acc[v], tacc);
-    } else {
-      const bool even = (c.t & 1) == 0;
-      if (even && c.t + 1 < nT) {
-        accE = acc;
-      } else {
-        float d[8];
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          d[v] = even ? acc[v] : accE[v];
-          d[4 + v] = even ? 0.0f : acc[v];
-        }
-        bf16x8 dh, dl;
-        split_bf16(d, dh, dl);
-        const int tp = c.t >> 1;
-        const bf16x8 ah = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uintx4*>(sAh + (tp * 64 + lane) * 4));
-        const bf16x8 al = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uintx4*>(sAl + (tp * 64 + lane) * 4));
-        tacc = mma_bf16(ah, dh, tacc);
-        tacc = mma_bf16(al, dh, tacc);
-        tacc = mma_bf16(ah, dl, tacc);
-      }
-    }
-    if (c.t == nT - 1) {
-      // slab complete: lane holds T[j' = 4 g + v][j = l16]; stores go to a
-      // uniform base plus one of four lane offsets
-      if (H3) {
-        const floatx4* fh = reinterpret_cast<const floatx4*>(sFH + c.h * kMaxC);
-#pragma unroll
-        for (int q4 = 0; q4 < kMaxC / 4; ++q4) {
-          if (4 * q4 >= p.cH) continue;
-          const floatx4 w = fh[q4];
-#pragma unroll
-          for (int r = 0; r < 4; ++r) acc3[4 * q4 + r] += w[r] * tacc;
-        }
-        if (c.h == nH - 1) {
-          const int cIJ = p.cI * p.cJ;
-          const __amdgpu_buffer_rsrc_t ro = __builtin_amdgcn_make_buffer_rsrc(
-              p.T + (int64_t)c.item * p.cH * cIJ, (short)0, p.cH * cIJ * 4, kRsrcWord3);
-          // lanes outside (c_I, c_J) store past the range, which discards them
-          uint32_t off[4];
-#pragma unroll
-          for (int v = 0; v < 4; ++v)
-            off[v] = (4 * g + v < p.cI && l16 < p.cJ) ? (uint32_t)(((4 * g + v) * p.cJ + l16) * 4) : 0x80000000u;
-#pragma unroll
-          for (int q = 0; q < kMaxC; ++q) {
-            if (q < p.cH) {
-#pragma unroll
-              for (int v = 0; v < 4; ++v)
-                __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(acc3[q][v]), ro, off[v], q * cIJ * 4, 0);
-            }
-            acc3[q] = floatx4{};
+          for (int v = 0; v < 4; ++v) {
+            d[v] = even ? acc[v] : accE[v];
+            d[4 + v] = even ? 0.0f : acc[v];
           }
-        }
-      } else {
-        const __amdgpu_buffer_rsrc_t ro = __builtin_amdgcn_make_buffer_rsrc(
-            p.T + (int64_t)c.item * p.cI * p.cJ, (short)0, p.cI * p.cJ * 4, kRsrcWord3);
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int jp = 4 * g + v;
-          const uint32_t off = (jp < p.cI && l16 < p.cJ) ? (uint32_t)((jp * p.cJ + l16) * 4) : 0x80000000u;
-          __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(tacc[v]), ro, off, 0, 0);
+          bf16x8 dh, dl;
+          split_bf16(d, dh, dl);
+          const int tp = t >> 1;
+          const bf16x8 ah = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uintx4*>(sAh + (tp * 64 + lane) * 4));
+          const bf16x8 al = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uintx4*>(sAl + (tp * 64 + lane) * 4));
+          tacc = mma_bf16(ah, dh, tacc);
+          tacc = mma_bf16(al, dh, tacc);
+          tacc = mma_bf16(ah, dl, tacc);
         }
       }
-      tacc = floatx4{};
     }
+    if (grp != nG - 1) return;
+    // slab complete: lane holds T[j' = 4 g + v][j = l16]; lanes outside
+    // (c_I, c_J) store past the range, which discards them
+    uint32_t off[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
+      off[v] = (4 * g + v < p.cI && l16 < p.cJ) ? (uint32_t)(((4 * g + v) * p.cJ + l16) * 4) : 0x80000000u;
+    if (H3) {
+      const floatx4* fh = reinterpret_cast<const floatx4*>(sFH + h * kMaxC);
+#pragma unroll
+      for (int q4 = 0; q4 < kMaxC / 4; ++q4) {
+        if (4 * q4 >= p.cH) continue;
+        const floatx4 w = fh[q4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) acc3[4 * q4 + r] += w[r] * tacc;
+      }
+      if (h == nH - 1) {
+        const int cIJ = p.cI * p.cJ;
+        const __amdgpu_buffer_rsrc_t ro = __builtin_amdgcn_make_buffer_rsrc(
+            p.T + (int64_t)item * p.cH * cIJ, (short)0, p.cH * cIJ * 4, kRsrcWord3);
+#pragma unroll
+        for (int q = 0; q < kMaxC; ++q) {
+          if (q < p.cH) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v)
+              __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(acc3[q][v]), ro, off[v], q * cIJ * 4, 0);
+          }
+          acc3[q] = floatx4{};
+        }
+      }
+    } else {
+      const __amdgpu_buffer_rsrc_t ro = __builtin_amdgcn_make_buffer_rsrc(
+          p.T + (int64_t)item * p.cI * p.cJ, (short)0, p.cI * p.cJ * 4, kRsrcWord3);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(tacc[v]), ro, off[v], 0, 0);
+    }
+    tacc = floatx4{};
   };
 
-  uintx4 buf[NBUF][NK];
-  Cur cc[NBUF];
-  cc[0] = Cur{gwave, 0, 0};
-  load_unit(cc[0], buf[0]);
-  Cur last = cc[0];
+  // NBUF units of loads rotate through the buffers: step s multiplies
+  // buffer s after issuing the load of the unit NBUF - 1 ahead
+  uintx4 buf[NBUF][TG][NK];
+  int ci[NBUF], chh[NBUF], cg[NBUF];
+  int li = gwave, lh = 0, lg = 0;
+  auto advance = [&]() {
+    if (li < 0) return;
+    if (++lg >= nG) {
+      lg = 0;
+      if (++lh >= nH) {
+        lh = 0;
+        li = li + nwaves < items ? li + nwaves : -1;
+      }
+    }
+  };
+  ci[0] = li;
+  chh[0] = lh;
+  cg[0] = lg;
+  load_unit(li, lh, lg, buf[0]);
 #pragma unroll
   for (int s = 1; s < NBUF - 1; ++s) {
-    last = advance(last);
-    cc[s] = last;
-    load_unit(cc[s], buf[s]);
+    advance();
+    ci[s] = li;
+    chh[s] = lh;
+    cg[s] = lg;
+    load_unit(li, lh, lg, buf[s]);
   }
   while (true) {
 #pragma unroll
     for (int s = 0; s < NBUF; ++s) {
       const int lb = (s + NBUF - 1) % NBUF;
-      last = advance(last);
-      cc[lb] = last;
-      load_unit(cc[lb], buf[lb]);
+      advance();
+      ci[lb] = li;
+      chh[lb] = lh;
+      cg[lb] = lg;
+      load_unit(li, lh, lg, buf[lb]);
       __builtin_amdgcn_sched_barrier(0);
-      if (cc[s].item < 0) return;
-      compute(cc[s], buf[s]);
+      if (ci[s] < 0) return;
+      compute_unit(ci[s], chh[s], cg[s], buf[s]);
     }
   }
 }
 
-template <typename TX, int NK, int NT, bool H3>
+template <typename TX, int NK, int NT, int TG, bool H3, int NBUF>
 hipError_t launch_variant(CoreSlab p, size_t lds, hipStream_t st) {
-  // the widest FP32 tiling keeps its accumulators in registers with two buffers
-  constexpr int kNbuf = (H3 && sizeof(TX) == 4 && NK >= 8) ? 2 : 3;
-  auto kern = core_slab_kernel<TX, NK, NT, H3, kNbuf>;
+  auto kern = core_slab_kernel<TX, NK, NT, TG, H3, NBUF>;
   // as many resident waves as the registers allow, persistent over the items
   int per_cu = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 256, lds) != hipSuccess || per_cu < 1)
@@ -375,10 +380,29 @@ hipError_t launch_variant(CoreSlab p, size_t lds, hipStream_t st) {
   return hipGetLastError();
 }
 
+// Units of loads in the register pipeline (2 or 3): 0 = default (2).
+static int slab_nbuf() {
+  static int env = [] {
+    const char* e = getenv("TKMI_SLAB_NBUF");
+    return e ? atoi(e) : 0;
+  }();
+  return env;
+}
+
+// TG tiles per unit keep one unit's loads at 32-48 registers
+template <typename TX, int NK, int NT, bool H3>
+hipError_t launch_depth(const CoreSlab& p, size_t lds, hipStream_t st) {
+  constexpr int kTG0 = 12 / NK < 1 ? 1 : 12 / NK;
+  constexpr int kTG1 = kTG0 > NT ? NT : kTG0;
+  constexpr int TG = sizeof(TX) == 4 ? kTG1 : (kTG1 < 2 ? 2 : kTG1 & ~1);
+  if (slab_nbuf() == 3) return launch_variant<TX, NK, NT, TG, H3, 3>(p, lds, st);
+  return launch_variant<TX, NK, NT, TG, H3, 2>(p, lds, st);
+}
+
 template <typename TX, int NK, int NT>
 hipError_t launch_typed(const CoreSlab& p, bool h3, size_t lds, hipStream_t st) {
-  if (h3) return launch_variant<TX, NK, NT, true>(p, lds + (size_t)p.nH * kMaxC * sizeof(float), st);
-  return launch_variant<TX, NK, NT, false>(p, lds, st);
+  if (h3) return launch_depth<TX, NK, NT, true>(p, lds + (size_t)p.nH * kMaxC * sizeof(float), st);
+  return launch_depth<TX, NK, NT, false>(p, lds, st);
 }
 
 template <typename TX>
@@ -398,6 +422,7 @@ hipError_t launch_by_size(const CoreSlab& p, bool h3, hipStream_t st) {
     return launch_typed<TX, 8, 8>(p, h3, lds(8), st);
   } else {
     if (nT <= 2 && nK <= 1) return launch_typed<TX, 1, 2>(p, h3, lds(2), st);
+    if (nT <= 3 && nK <= 2) return launch_typed<TX, 2, 3>(p, h3, lds(3), st);
     if (nT <= 4 && nK <= 2) return launch_typed<TX, 2, 4>(p, h3, lds(4), st);
     return launch_typed<TX, 4, 8>(p, h3, lds(8), st);
   }

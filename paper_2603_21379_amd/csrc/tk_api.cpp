@@ -11,6 +11,8 @@
 #include <string>
 #include <vector>
 
+#include <stdlib.h>
+
 #include "tk_kernels.hpp"
 
 namespace tk {
@@ -195,7 +197,12 @@ int core_kind(int xdt, int order, const int64_t* dims, const int32_t* cols) {
   if (A >= (int64_t(1) << 31)) return kCoreGeneric;
   // accumulate the third mode in registers when that still leaves work for
   // every wave of the grid (it shrinks the partial core n_H / c_H times)
-  if (order >= 4 && cols[order - 3] <= 16 && dims[order - 3] <= 512 && A / dims[order - 3] >= 2048)
+  static const bool h3_off = [] {
+    const char* e = getenv("TKMI_SLAB_H3");
+    return e && atoi(e) == 0;
+  }();
+  if (!h3_off && order >= 4 && cols[order - 3] <= 16 && dims[order - 3] <= 512 &&
+      A / dims[order - 3] >= 2048)
     return kCoreSlab3;
   return kCoreSlab2;
 }
