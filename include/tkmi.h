@@ -210,6 +210,45 @@ tk_status tucker_reconstruct_vjp(int32_t order, const int64_t* dims, int32_t fdt
                                  const void* H, void* Gbar, void* const* Fbar, void* ws,
                                  size_t* ws_bytes, void* stream);
 
+/* Batching form of Sub-R-HOSVD (Algorithm 1 for many independent tensors at
+ * once): every mode of every tensor is sketched, orthonormalised, truncated
+ * and projected by one fixed sequence of persistent launches (sketch, QR,
+ * W step, streaming core pass, remaining modes), whatever the orders and
+ * sizes of the tensors.  A plan holds the descriptor tables in the caller's
+ * workspace; running it allocates nothing, does not synchronise and records
+ * no memset, so a run can be captured in a HIP graph and replayed.
+ *
+ * tucker_batch_plan_create
+ *   count   number of tensors (>= 1).
+ *   X       host array [count] of FP32 tensors of order >= 3, the two
+ *           trailing modes at most 96, at most 2^29 entries each.
+ *   ranks   host int32 [sum of orders]: r_k of every mode, tensor by tensor
+ *           (1 <= r_k <= ell_k; r_k <= 16 for the two trailing modes and
+ *           <= 32 for the others).
+ *   sk      host array [sum of orders] of sketches, as in
+ *           tucker_sketch_all_modes (omega FP32).
+ *   U       host array [sum of orders] of device outputs, n_k x r_k FP32
+ *           row-major (U_k = Q_k W_k, sign rule as in tucker_qr).
+ *   G       host array [count] of device outputs, r_1 x .. x r_d FP32.
+ *   info    device int32 [sum of orders] or NULL (as in tucker_qr).
+ *   ws      caller workspace; NULL is a size query (nothing else happens).
+ *   stream  stream for the table upload (the call waits for it).
+ *   plan    receives the plan (host object; valid while ws, the tensors,
+ *           sketches and outputs stay allocated).
+ * tucker_batch_run enqueues one run on `stream`.
+ * tucker_batch_autotune runs the plan once, then times the streaming pass
+ *   for each tile grouping, load-pipeline depth and chunk size and keeps
+ *   the fastest; it synchronises (do not call it while capturing).  A text
+ *   report is written to `report` (may be NULL).
+ * Errors: TK_EINVAL, TK_EUNSUPPORTED, TK_EWORKSPACE, TK_EDEVICE. */
+typedef struct tk_batch_plan tk_batch_plan;
+tk_status tucker_batch_plan_create(int32_t count, const tk_tensor* X, const int32_t* ranks,
+                                   const tk_sketch* sk, void* const* U, void* const* G, int32_t* info,
+                                   void* ws, size_t* ws_bytes, void* stream, tk_batch_plan** plan);
+tk_status tucker_batch_run(const tk_batch_plan* plan, void* stream);
+tk_status tucker_batch_autotune(tk_batch_plan* plan, void* stream, char* report, size_t report_bytes);
+void tucker_batch_plan_destroy(tk_batch_plan* plan);
+
 /* Profiling of the streaming pass.  While enabled, every tucker_core,
  * tucker_reconstruct and htucker_decompose call brackets the kernel that
  * streams X (the one full read of the tensor) with HIP events recorded on the

@@ -53,7 +53,8 @@ _lock = threading.Lock()
 
 EXPORTS = ("tucker_sketch_all_modes", "tucker_qr", "tucker_core", "tucker_reconstruct",
            "htucker_decompose", "tucker_core_vjp", "tucker_reconstruct_vjp", "tk_last_error",
-           "tk_version", "tk_profile_enable", "tk_profile_read")
+           "tk_version", "tk_profile_enable", "tk_profile_read", "tucker_batch_plan_create",
+           "tucker_batch_run", "tucker_batch_autotune", "tucker_batch_plan_destroy")
 
 
 def lib():
@@ -87,6 +88,12 @@ def lib():
                 "tucker_reconstruct_vjp": [C.c_int32, i64p, C.c_int32, vp, pp, i32p, vp, vp, pp, vp,
                                            sz, vp],
             }
+            sig["tucker_batch_plan_create"] = [C.c_int32, C.POINTER(TkTensor), i32p, C.POINTER(TkSketch),
+                                               pp, pp, vp, vp, sz, vp, C.POINTER(C.c_void_p)]
+            sig["tucker_batch_run"] = [vp, vp]
+            sig["tucker_batch_autotune"] = [vp, vp, C.c_char_p, C.c_size_t]
+            L.tucker_batch_plan_destroy.argtypes = [vp]
+            L.tucker_batch_plan_destroy.restype = None
             for name, args in sig.items():
                 f = getattr(L, name)
                 f.argtypes = args
@@ -277,6 +284,55 @@ def tucker_reconstruct_vjp(dims, G, F, H, Gbar=None, Fbar=None, stream=None, ws=
     args = [d, dd, dtype_code(G.dtype), G.data_ptr(), ptr_array(F), cols, H.data_ptr(),
             ptr(Gbar), ptr_array(Fbar) if Fbar is not None else None]
     return _call("tucker_reconstruct_vjp", args, G.device, stream, ws)
+
+
+class BatchPlan:
+    """Owner of a tucker_batch_plan: keeps the workspace, the descriptor
+    arrays and the tensors they point to alive while the plan exists."""
+
+    def __init__(self, X, ranks, sketches, U, G, info=None, stream=None):
+        n = len(X)
+        self._keep = (list(X), list(U), list(G), info, [t for sk in sketches for t in sk if t is not None])
+        xd = (TkTensor * n)()
+        for i, x in enumerate(X):
+            xd[i] = tensor_desc(x)
+        flat_r = [int(r) for rr in ranks for r in rr]
+        rk = (C.c_int32 * len(flat_r))(*flat_r)
+        sk = sketch_descs(sketches)
+        Up, Gp = ptr_array(U), ptr_array(G)
+        self._args = (xd, rk, sk, Up, Gp)
+        f = lib().tucker_batch_plan_create
+        nbytes = C.c_size_t(0)
+        _check("tucker_batch_plan_create",
+               f(n, xd, rk, sk, Up, Gp, ptr(info), None, C.byref(nbytes), _stream(stream), None))
+        dev = X[0].device
+        self.ws = torch.empty(max(int(nbytes.value), 256), dtype=torch.uint8, device=dev)
+        h = C.c_void_p()
+        n2 = C.c_size_t(self.ws.numel())
+        _check("tucker_batch_plan_create",
+               f(n, xd, rk, sk, Up, Gp, ptr(info), C.c_void_p(self.ws.data_ptr()), C.byref(n2),
+                 _stream(stream), C.byref(h)))
+        self.handle = h
+        self.ws_bytes = int(nbytes.value)
+
+    def run(self, stream=None):
+        _check("tucker_batch_run", lib().tucker_batch_run(self.handle, _stream(stream)))
+
+    def autotune(self, stream=None) -> str:
+        buf = C.create_string_buffer(4096)
+        _check("tucker_batch_autotune", lib().tucker_batch_autotune(self.handle, _stream(stream), buf, 4096))
+        return buf.value.decode()
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().tucker_batch_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:  # noqa: BLE001
+            pass
 
 
 def tk_profile_enable(on: bool) -> None:

@@ -1,0 +1,292 @@
+// Batching form of the core projection (Algorithm 1, core step) for many
+// FP32 tensors of uneven order and size in one launch per step.
+//
+// batch_slab_kernel: the streaming pass of every tensor, T[a] = F_I^T X[a] F_J
+//   for the slabs X[a] of its two trailing modes (n <= 96, ranks <= 16), on
+//   v_mfma_f32_16x16x4f32 exactly as the single-tensor small-mode pass.  The
+//   work is a list of chunks (tensor, slab range) assigned to waves on the
+//   host by longest-processing-time first, so the waves finish together and
+//   the schedule is fixed (no counters to reset between graph replays).  A
+//   wave keeps its tensor's F_J in registers and F_I^T in its own LDS region,
+//   reloading both when its next chunk belongs to another tensor.
+//
+// batch_mode_kernel: one remaining mode of every tensor that still has one,
+//   out[a][p][b] = sum_q F[q][p] in[a][q][b], as the single-tensor MFMA mode
+//   contraction; each descriptor's units are padded to whole workgroups so a
+//   workgroup shares one F^T table.
+#include "tk_kernels.hpp"
+
+namespace tk {
+namespace {
+
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+typedef unsigned int uintx4 __attribute__((ext_vector_type(4)));
+
+constexpr int kWaves = 4;
+constexpr int kRsrcWord3 = 0x00020000;
+constexpr int NK = 6;      // 16-column chunks (n_J <= 96)
+constexpr int NT = 6;      // 16-row tiles (n_I <= 96)
+
+__device__ __forceinline__ floatx4 mma_f32(float a, float b, floatx4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+template <int TG, int NBUF>
+__global__ __launch_bounds__(256, 2) void batch_slab_kernel(const BatchSlab bs) {
+  extern __shared__ float lds[];
+  const int lane = threadIdx.x & 63, g = lane >> 4, l16 = lane & 15;
+  const int wv = threadIdx.x >> 6;
+  float* sA = lds + wv * (NT * 256);   // this wave's F_I^T table [t][v][lane]
+  const int gwave = __builtin_amdgcn_readfirstlane((int)blockIdx.x * kWaves + wv);
+  if (gwave >= bs.nwaves) return;
+  const int c_begin = bs.wave_begin[gwave], c_end = bs.wave_begin[gwave + 1];
+
+  int cur_tensor = -1;
+  float fj[NK][4];
+  uintx4 lastmask;
+  BatchTensor td{};
+  int nT = 0, nK = 0;
+  uint32_t lane_off = 0, tile_bytes = 0, slab_bytes = 0;
+
+  for (int ci = c_begin; ci < c_end; ++ci) {
+    const BatchChunk ch = bs.chunks[bs.wave_chunks[ci]];
+    const int tid = __builtin_amdgcn_readfirstlane(ch.tensor);
+    if (tid != cur_tensor) {
+      cur_tensor = tid;
+      td = bs.tensors[tid];
+      nT = (td.nI + 15) / 16;
+      nK = (td.nJ + 15) / 16;
+#pragma unroll
+      for (int kc = 0; kc < NK; ++kc)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          const int b = 16 * kc + 4 * g + c;
+          fj[kc][c] = (b < td.nJ && l16 < td.cJ) ? td.FJ[b * td.cJ + l16] : 0.0f;
+        }
+      const int valid = td.nJ - ((nK - 1) * 16 + 4 * g);
+#pragma unroll
+      for (int w = 0; w < 4; ++w) lastmask[w] = w < valid ? 0xFFFFFFFFu : 0u;
+      // the wave's own table: ordered LDS accesses of one wave need no barrier
+#pragma unroll
+      for (int t = 0; t < NT; ++t)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int i = 16 * t + 4 * g + v;
+          sA[t * 256 + v * 64 + lane] = (i < td.nI && l16 < td.cI) ? td.FI[i * td.cI + l16] : 0.0f;
+        }
+      __builtin_amdgcn_wave_barrier();
+      lane_off = (uint32_t)(l16 * td.nJ + 4 * g) * 4u;
+      tile_bytes = (uint32_t)(16 * td.nJ) * 4u;
+      slab_bytes = (uint32_t)td.nI * (uint32_t)td.nJ * 4u;
+    }
+    const int nG = (nT + TG - 1) / TG;
+    const char* Xb = reinterpret_cast<const char*>(td.X);
+
+    auto load_unit = [&](int64_t a, int grp, uintx4 (&buf)[TG][NK]) {
+      const bool live = a >= 0;
+      const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+          const_cast<char*>(Xb + (live ? a : 0) * (int64_t)slab_bytes), (short)0, live ? (int)slab_bytes : 0,
+          kRsrcWord3);
+#pragma unroll
+      for (int tt = 0; tt < TG; ++tt) {
+        const int t = grp * TG + tt;
+        if (t >= nT) continue;
+        const uint32_t off = lane_off + t * tile_bytes;
+#pragma unroll
+        for (int kc = 0; kc < NK; ++kc)
+          if (kc < nK)
+            buf[tt][kc] = __builtin_bit_cast(uintx4, __builtin_amdgcn_raw_buffer_load_b128(rs, off + kc * 64, 0, 2));
+      }
+    };
+    floatx4 tacc = floatx4{};
+    auto compute_unit = [&](int64_t a, int grp, uintx4 (&buf)[TG][NK]) {
+#pragma unroll
+      for (int tt = 0; tt < TG; ++tt) {
+        const int t = grp * TG + tt;
+        if (t >= nT) continue;
+        floatx4 acc = floatx4{};
+#pragma unroll
+        for (int kc = 0; kc < NK; ++kc) {
+          if (kc >= nK) continue;
+          uintx4 x = buf[tt][kc];
+          if (kc == nK - 1) x &= lastmask;
+          const floatx4 xf = __builtin_bit_cast(floatx4, x);
+#pragma unroll
+          for (int c = 0; c < 4; ++c) acc = mma_f32(xf[c], fj[kc][c], acc);
+        }
+        const float* A = sA + t * 256 + lane;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) tacc = mma_f32(A[v * 64], acc[v], tacc);
+      }
+      if (grp != nG - 1) return;
+      const __amdgpu_buffer_rsrc_t ro = __builtin_amdgcn_make_buffer_rsrc(
+          td.T + a * td.cI * td.cJ, (short)0, td.cI * td.cJ * 4, kRsrcWord3);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int jp = 4 * g + v;
+        const uint32_t off = (jp < td.cI && l16 < td.cJ) ? (uint32_t)((jp * td.cJ + l16) * 4) : 0x80000000u;
+        __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(tacc[v]), ro, off, 0, 0);
+      }
+      tacc = floatx4{};
+    };
+
+    // units (slab a, tile group) of this chunk through NBUF rotating buffers
+    uintx4 buf[NBUF][TG][NK];
+    int64_t ua[NBUF];
+    int ug[NBUF];
+    int64_t la = ch.a0;
+    int lg = 0;
+    auto advance = [&]() {
+      if (la < 0) return;
+      if (++lg >= nG) {
+        lg = 0;
+        la = la + 1 < ch.a1 ? la + 1 : -1;
+      }
+    };
+    ua[0] = la;
+    ug[0] = lg;
+    load_unit(la, lg, buf[0]);
+#pragma unroll
+    for (int s = 1; s < NBUF - 1; ++s) {
+      advance();
+      ua[s] = la;
+      ug[s] = lg;
+      load_unit(la, lg, buf[s]);
+    }
+    bool done = false;
+    while (!done) {
+#pragma unroll
+      for (int s = 0; s < NBUF; ++s) {
+        const int lb = (s + NBUF - 1) % NBUF;
+        advance();
+        ua[lb] = la;
+        ug[lb] = lg;
+        load_unit(la, lg, buf[lb]);
+        __builtin_amdgcn_sched_barrier(0);
+        if (ua[s] < 0) {
+          done = true;
+          break;
+        }
+        compute_unit(ua[s], ug[s], buf[s]);
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------- remaining modes
+constexpr int kCols = 128;
+constexpr int kKB = 8;
+
+__device__ __forceinline__ floatx16 mfma32(float a, float b, floatx16 c) {
+  return __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, c, 0, 0, 0);
+}
+
+__global__ __launch_bounds__(256) void batch_mode_kernel(const BatchMode bm) {
+  extern __shared__ float sF[];   // [Qp][32]
+  const int64_t u0 = (int64_t)blockIdx.x * kWaves;
+  // descriptor of this workgroup (unit ranges are padded to whole workgroups)
+  int lo = 0, hi = bm.count - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (bm.descs[mid].unit_begin <= u0) lo = mid; else hi = mid - 1;
+  }
+  const BatchModeDesc m = bm.descs[lo];
+  const int Qp = (int)((m.Q + 2 * kKB - 1) / (2 * kKB)) * 2 * kKB;
+  for (int e = threadIdx.x; e < Qp * 32; e += blockDim.x) {
+    const int q = e >> 5, p = e & 31;
+    sF[e] = (q < m.Q && p < m.P) ? m.F[(int64_t)q * m.P + p] : 0.0f;
+  }
+  __syncthreads();
+
+  const int lane = threadIdx.x & 63, kh = lane >> 5, l32 = lane & 31;
+  const int64_t nBb = (m.B + kCols - 1) / kCols;
+  const int64_t unit = u0 + (threadIdx.x >> 6) - m.unit_begin;
+  if (unit >= m.A * nBb) return;  // no barrier follows
+  const int64_t a = unit / nBb;
+  const int64_t b0 = (unit - a * nBb) * kCols;
+  const int64_t slab = m.Q * m.B;
+  const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+      const_cast<float*>(m.in + a * slab), (short)0, (int)(slab * 4), kRsrcWord3);
+  const int64_t b = b0 + 4 * l32;
+  const bool colok = b < m.B;
+  const uint32_t rowb = (uint32_t)(m.B * 4);
+  floatx16 acc[4];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) acc[c] = floatx16{};
+  for (int q0 = 0; q0 < Qp; q0 += 2 * kKB) {
+    floatx4 buf[kKB];
+#pragma unroll
+    for (int u = 0; u < kKB; ++u) {
+      const int q = q0 + 2 * u + kh;
+      const uint32_t off = (colok && q < m.Q) ? (uint32_t)q * rowb + (uint32_t)(b * 4) : 0x80000000u;
+      buf[u] = __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, 0);
+    }
+    const float* f = sF + (q0 + kh) * 32 + l32;
+#pragma unroll
+    for (int u = 0; u < kKB; ++u) {
+      const float fv = f[u * 64];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) acc[c] = mfma32(fv, buf[u][c], acc[c]);
+    }
+  }
+  if (!colok) return;
+  float* out = m.out + a * (int64_t)m.P * m.B;
+  const int ncol = (int)min<int64_t>(4, m.B - b);
+#pragma unroll
+  for (int v = 0; v < 16; ++v) {
+    const int p = 8 * (v >> 2) + 4 * kh + (v & 3);
+    if (p >= m.P) continue;
+    float* o = out + (int64_t)p * m.B + b;
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+      if (c < ncol) o[c] = acc[c][v];
+  }
+}
+
+}  // namespace
+
+size_t batch_slab_lds_bytes() { return (size_t)kWaves * NT * 256 * sizeof(float); }
+
+int batch_slab_waves(int tg, int nbuf) {
+  int per_cu = 0;
+  const size_t lds = batch_slab_lds_bytes();
+  hipError_t e = hipErrorInvalidValue;
+  if (tg == 1 && nbuf == 2) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batch_slab_kernel<1, 2>, 256, lds);
+  if (tg == 2 && nbuf == 2) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batch_slab_kernel<2, 2>, 256, lds);
+  if (tg == 1 && nbuf == 3) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batch_slab_kernel<1, 3>, 256, lds);
+  if (e != hipSuccess || per_cu < 1) per_cu = 1;
+  int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
+    cus = 256;
+  return per_cu * cus * kWaves;
+}
+
+hipError_t launch_batch_slab(const BatchSlab& bs, int tg, int nbuf, hipStream_t st) {
+  if (bs.nwaves <= 0) return hipSuccess;
+  const dim3 grid((unsigned)ceil_div(bs.nwaves, kWaves));
+  const size_t lds = batch_slab_lds_bytes();
+  if (tg == 1 && nbuf == 2) hipLaunchKernelGGL((batch_slab_kernel<1, 2>), grid, dim3(256), lds, st, bs);
+  else if (tg == 2 && nbuf == 2) hipLaunchKernelGGL((batch_slab_kernel<2, 2>), grid, dim3(256), lds, st, bs);
+  else if (tg == 1 && nbuf == 3) hipLaunchKernelGGL((batch_slab_kernel<1, 3>), grid, dim3(256), lds, st, bs);
+  else return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+int64_t batch_mode_units(int64_t A, int64_t B) {
+  return ceil_div(A * ceil_div(B, kCols), kWaves) * kWaves;
+}
+
+size_t batch_mode_lds_bytes(int64_t Qmax) {
+  return (size_t)((Qmax + 2 * kKB - 1) / (2 * kKB) * 2 * kKB) * 32 * sizeof(float);
+}
+
+hipError_t launch_batch_mode(const BatchMode& bm, int64_t total_units, int64_t Qmax, hipStream_t st) {
+  if (total_units == 0 || bm.count == 0) return hipSuccess;
+  hipLaunchKernelGGL(batch_mode_kernel, dim3((unsigned)(total_units / kWaves)), dim3(256),
+                     batch_mode_lds_bytes(Qmax), st, bm);
+  return hipGetLastError();
+}
+
+}  // namespace tk

@@ -15,8 +15,9 @@ constexpr double kUnit = 1.1102230246251565e-16;  // 2^-53
 
 // ------------------------------------------------------------------ Gram partials
 // gpart[rc] = Z[rows of rc]^T Z[rows of rc]
-__global__ __launch_bounds__(256) void gram_partial_kernel(const QRBatch b, int pass) {
-  const QRMat& M = b.m[blockIdx.y];
+template <typename S>
+__global__ __launch_bounds__(256) void gram_partial_kernel(const S b, int pass) {
+  const QRMat& M = b.get(blockIdx.y);
   const int rc = blockIdx.x;
   if (rc >= M.nrc || M.small) return;
   if (pass > 1 && M.state[0] == 0) return;
@@ -85,8 +86,9 @@ __device__ bool cholesky_upper(double (*G)[kMaxEll + 1], int n, int lane, double
 
 // state[0]: CholeskyQR passes still owed (a plain pass pays one, a shifted
 // pass leaves two owed); state[1]: whether this pass applies R^{-1}.
-__global__ __launch_bounds__(64) void chol_kernel(const QRBatch b, int pass) {
-  const QRMat& M = b.m[blockIdx.x];
+template <typename S>
+__global__ __launch_bounds__(64) void chol_kernel(const S b, int pass) {
+  const QRMat& M = b.get(blockIdx.x);
   if (M.small) return;
   if (pass > 1 && M.state[0] == 0) {
     if (threadIdx.x == 0) M.state[1] = 0;
@@ -163,8 +165,9 @@ __global__ __launch_bounds__(64) void chol_kernel(const QRBatch b, int pass) {
 }
 
 // Q = Z R^{-1} row by row (forward substitution on q R = z), in place.
-__global__ __launch_bounds__(64) void apply_rinv_kernel(const QRBatch b, int pass) {
-  const QRMat& M = b.m[blockIdx.y];
+template <typename S>
+__global__ __launch_bounds__(64) void apply_rinv_kernel(const S b, int pass) {
+  const QRMat& M = b.get(blockIdx.y);
   const int rb = blockIdx.x;
   if (rb >= M.nrb || M.small) return;
   if (M.state[1] == 0) return;
@@ -301,8 +304,9 @@ __device__ void apply_inverse_block(const QRMat& M, double (*Ri)[kMaxEll + 1],
   }
 }
 
-__global__ __launch_bounds__(256) void cholqr_small_kernel(const QRBatch b) {
-  const QRMat& M = b.m[blockIdx.x];
+template <typename S>
+__global__ __launch_bounds__(256) void cholqr_small_kernel(const S b) {
+  const QRMat& M = b.get(blockIdx.x);
   if (!M.small) return;
   __shared__ double G[kMaxEll][kMaxEll + 1];
   __shared__ double G0[kMaxEll][kMaxEll + 1];  // the unshifted Gram, kept for a shifted retry
@@ -404,9 +408,9 @@ __global__ __launch_bounds__(256) void cholqr_small_kernel(const QRBatch b) {
 // mpart[rc][p][t] = sum_{rows in rc} Q[row][p] Y[row][t], t in column chunk cc.
 // Each thread owns a 4 x 4 register tile (p = 4 pr + i, t = 4 tc + j), so an
 // FMA costs half an LDS read instead of two.
-template <typename TY>
-__global__ __launch_bounds__(256) void qty_partial_kernel(const QRBatch b) {
-  const QRMat& M = b.m[blockIdx.z];
+template <typename TY, typename S>
+__global__ __launch_bounds__(256) void qty_partial_kernel(const S b) {
+  const QRMat& M = b.get(blockIdx.z);
   const int rc = blockIdx.x, cc = blockIdx.y;
   if (rc >= M.nrc || cc >= M.ncc) return;
   __shared__ double sQ[64][kMaxEll + 1];
@@ -459,8 +463,9 @@ __global__ __launch_bounds__(256) void qty_partial_kernel(const QRBatch b) {
 }
 
 // cpart[cc] = M_cc M_cc^T with M_cc = sum_rc mpart[rc][:, cc]
-__global__ __launch_bounds__(256) void mgram_kernel(const QRBatch b) {
-  const QRMat& M = b.m[blockIdx.y];
+template <typename S>
+__global__ __launch_bounds__(256) void mgram_kernel(const S b) {
+  const QRMat& M = b.get(blockIdx.y);
   const int cc = blockIdx.x;
   if (cc >= M.ncc) return;
   __shared__ double sM[kMaxEll][kQRColChunk + 1];
@@ -497,8 +502,9 @@ __global__ __launch_bounds__(256) void mgram_kernel(const QRBatch b) {
 constexpr int kEigThreads = 256;
 constexpr int kEigItems = ((kMaxEll / 2) * (kMaxEll / 2) + kMaxEll * (kMaxEll / 2)) / kEigThreads;
 
-__global__ __launch_bounds__(kEigThreads) void eig_kernel(const QRBatch b) {
-  const QRMat& M = b.m[blockIdx.x];
+template <typename S>
+__global__ __launch_bounds__(kEigThreads) void eig_kernel(const S b) {
+  const QRMat& M = b.get(blockIdx.x);
   __shared__ double A[kMaxEll][kMaxEll + 1];
   __shared__ double V[kMaxEll][kMaxEll + 1];
   __shared__ double rc_[kMaxEll / 2], rs_[kMaxEll / 2];
@@ -671,8 +677,9 @@ __global__ __launch_bounds__(kEigThreads) void eig_kernel(const QRBatch b) {
 }
 
 // utmp = Q W for a block of 64 rows, plus per-block column argmax of |u|.
-__global__ __launch_bounds__(64) void urows_kernel(const QRBatch b) {
-  const QRMat& M = b.m[blockIdx.y];
+template <typename S>
+__global__ __launch_bounds__(64) void urows_kernel(const S b) {
+  const QRMat& M = b.get(blockIdx.y);
   const int rb = blockIdx.x;
   if (rb >= M.nrb || M.small) return;
   __shared__ double sQ[kMaxEll][65];
@@ -709,9 +716,9 @@ __global__ __launch_bounds__(64) void urows_kernel(const QRBatch b) {
   }
 }
 
-template <typename TU>
-__global__ __launch_bounds__(64) void usign_kernel(const QRBatch b) {
-  const QRMat& M = b.m[blockIdx.y];
+template <typename TU, typename S>
+__global__ __launch_bounds__(64) void usign_kernel(const S b) {
+  const QRMat& M = b.get(blockIdx.y);
   const int rb = blockIdx.x;
   if (rb >= M.nrb || M.small) return;
   __shared__ double sgn[kMaxEll];
@@ -742,60 +749,71 @@ __global__ __launch_bounds__(64) void usign_kernel(const QRBatch b) {
   }
 }
 
-int max_field(const QRBatch& b, int which) {
+int max_field(const QRMat* m, int count, int which) {
   int v = 0;
-  for (int i = 0; i < b.count; ++i) {
-    const QRMat& M = b.m[i];
-    v = max(v, which == 0 ? M.nrc : which == 1 ? M.ncc : M.nrb);
-  }
+  for (int i = 0; i < count; ++i) v = max(v, which == 0 ? m[i].nrc : which == 1 ? m[i].ncc : m[i].nrb);
   return v;
 }
 
-}  // namespace
-
-hipError_t launch_cholqr(const QRBatch& b, hipStream_t st) {
-  if (b.count == 0) return hipSuccess;
-  const int nrc = max_field(b, 0), nrb = max_field(b, 2);
+// `src` gives the kernels the matrix descriptors (kernel arguments or a
+// device table); `host` is the same table on the host, for the grid sizes
+template <typename S>
+hipError_t cholqr_impl(const S& src, const QRMat* host, int count, hipStream_t st) {
+  if (count == 0) return hipSuccess;
+  const int nrc = max_field(host, count, 0), nrb = max_field(host, count, 2);
   bool any_small = false, any_big = false;
-  for (int i = 0; i < b.count; ++i) (b.m[i].small ? any_small : any_big) = true;
-  if (any_small) hipLaunchKernelGGL(cholqr_small_kernel, dim3(b.count), dim3(256), 0, st, b);
+  for (int i = 0; i < count; ++i) (host[i].small ? any_small : any_big) = true;
+  if (any_small) hipLaunchKernelGGL(cholqr_small_kernel<S>, dim3(count), dim3(256), 0, st, src);
   if (!any_big) return hipGetLastError();
   // CholeskyQR2 needs two passes; every shifted pass owes two more plain ones,
   // so an exactly rank-deficient sketch (shift, shift, plain, plain) needs four.
   for (int pass = 1; pass <= kQRMaxPasses; ++pass) {
-    hipLaunchKernelGGL(gram_partial_kernel, dim3(nrc, b.count), dim3(256), 0, st, b, pass);
-    hipLaunchKernelGGL(chol_kernel, dim3(b.count), dim3(64), 0, st, b, pass);
-    hipLaunchKernelGGL(apply_rinv_kernel, dim3(nrb, b.count), dim3(64), 0, st, b, pass);
+    hipLaunchKernelGGL(gram_partial_kernel<S>, dim3(nrc, count), dim3(256), 0, st, src, pass);
+    hipLaunchKernelGGL(chol_kernel<S>, dim3(count), dim3(64), 0, st, src, pass);
+    hipLaunchKernelGGL(apply_rinv_kernel<S>, dim3(nrb, count), dim3(64), 0, st, src, pass);
   }
   return hipGetLastError();
 }
 
-template <typename TY>
-static void launch_qty(const QRBatch& b, int nrc, int ncc, hipStream_t st) {
-  hipLaunchKernelGGL((qty_partial_kernel<TY>), dim3(nrc, ncc, b.count), dim3(256), 0, st, b);
-}
-
-hipError_t launch_wstep(const QRBatch& b, int ydtype, int udtype, hipStream_t st) {
-  if (b.count == 0) return hipSuccess;
-  const int nrc = max_field(b, 0), ncc = max_field(b, 1), nrb = max_field(b, 2);
+template <typename S>
+hipError_t wstep_impl(const S& src, const QRMat* host, int count, int ydtype, int udtype, hipStream_t st) {
+  if (count == 0) return hipSuccess;
+  const int nrc = max_field(host, count, 0), ncc = max_field(host, count, 1), nrb = max_field(host, count, 2);
+  const dim3 gq(nrc, ncc, count);
   switch (ydtype) {
-    case TK_F64: launch_qty<double>(b, nrc, ncc, st); break;
-    case TK_F32: launch_qty<float>(b, nrc, ncc, st); break;
-    case TK_BF16: launch_qty<bf16>(b, nrc, ncc, st); break;
-    case TK_F16: launch_qty<f16>(b, nrc, ncc, st); break;
+    case TK_F64: hipLaunchKernelGGL((qty_partial_kernel<double, S>), gq, dim3(256), 0, st, src); break;
+    case TK_F32: hipLaunchKernelGGL((qty_partial_kernel<float, S>), gq, dim3(256), 0, st, src); break;
+    case TK_BF16: hipLaunchKernelGGL((qty_partial_kernel<bf16, S>), gq, dim3(256), 0, st, src); break;
+    case TK_F16: hipLaunchKernelGGL((qty_partial_kernel<f16, S>), gq, dim3(256), 0, st, src); break;
     default: return hipErrorInvalidValue;
   }
-  hipLaunchKernelGGL(mgram_kernel, dim3(ncc, b.count), dim3(256), 0, st, b);
-  hipLaunchKernelGGL(eig_kernel, dim3(b.count), dim3(kEigThreads), 0, st, b);
+  hipLaunchKernelGGL(mgram_kernel<S>, dim3(ncc, count), dim3(256), 0, st, src);
+  hipLaunchKernelGGL(eig_kernel<S>, dim3(count), dim3(kEigThreads), 0, st, src);
   bool any_big = false;
-  for (int i = 0; i < b.count; ++i) any_big |= !b.m[i].small;
+  for (int i = 0; i < count; ++i) any_big |= !host[i].small;
   if (!any_big) return hipGetLastError();
-  hipLaunchKernelGGL(urows_kernel, dim3(nrb, b.count), dim3(64), 0, st, b);
+  hipLaunchKernelGGL(urows_kernel<S>, dim3(nrb, count), dim3(64), 0, st, src);
   if (udtype == TK_F64)
-    hipLaunchKernelGGL((usign_kernel<double>), dim3(nrb, b.count), dim3(64), 0, st, b);
+    hipLaunchKernelGGL((usign_kernel<double, S>), dim3(nrb, count), dim3(64), 0, st, src);
   else
-    hipLaunchKernelGGL((usign_kernel<float>), dim3(nrb, b.count), dim3(64), 0, st, b);
+    hipLaunchKernelGGL((usign_kernel<float, S>), dim3(nrb, count), dim3(64), 0, st, src);
   return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_cholqr(const QRBatch& b, hipStream_t st) { return cholqr_impl(b, b.m, b.count, st); }
+
+hipError_t launch_wstep(const QRBatch& b, int ydtype, int udtype, hipStream_t st) {
+  return wstep_impl(b, b.m, b.count, ydtype, udtype, st);
+}
+
+hipError_t launch_cholqr_list(const QRList& dev, const QRMat* host, hipStream_t st) {
+  return cholqr_impl(dev, host, dev.count, st);
+}
+
+hipError_t launch_wstep_list(const QRList& dev, const QRMat* host, int ydtype, int udtype, hipStream_t st) {
+  return wstep_impl(dev, host, dev.count, ydtype, udtype, st);
 }
 
 }  // namespace tk

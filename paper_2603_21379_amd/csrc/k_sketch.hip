@@ -13,18 +13,12 @@
 namespace tk {
 namespace {
 
-__device__ __forceinline__ int find_unit(const SketchBatch& b, int64_t blk) {
-  int u = 0;
-  while (u + 1 < b.count && b.u[u + 1].block_begin <= blk) ++u;
-  return u;
-}
-
-template <typename TX, typename TO>
-__global__ __launch_bounds__(256) void sketch_gather_kernel(const SketchBatch b) {
+template <typename TX, typename TO, typename S>
+__global__ __launch_bounds__(256) void sketch_gather_kernel(const S b) {
   __shared__ double sY[kSketchRows][kSketchCols + 1];
   __shared__ double sO[kSketchCols][64 + 1];
   const int64_t blk = blockIdx.x;
-  const SketchUnit& U = b.u[find_unit(b, blk)];
+  const SketchUnit& U = b.get(b.find_block(blk));
   const int64_t lb = blk - U.block_begin;
   const int64_t chunk = lb / U.rowblocks;
   const int64_t rb = lb - chunk * U.rowblocks;
@@ -83,38 +77,31 @@ __global__ __launch_bounds__(256) void sketch_gather_kernel(const SketchBatch b)
   }
 }
 
-__global__ __launch_bounds__(256) void sketch_reduce_kernel(const SketchBatch b) {
+template <typename S>
+__global__ __launch_bounds__(256) void sketch_reduce_kernel(const S b) {
   const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= b.total_out) return;
-  int64_t base = 0;
-  int u = 0;
-  for (; u < b.count; ++u) {
-    const int64_t cnt = b.u[u].n * b.u[u].ell;
-    if (g < base + cnt) break;
-    base += cnt;
-  }
-  const SketchUnit& U = b.u[u];
-  const int64_t e = g - base;
+  const SketchUnit& U = b.get(b.find_out(g));
+  const int64_t e = g - U.out_begin;
   const int64_t plane = U.n * U.ell;
   double acc = 0.0;
   for (int c = 0; c < U.nchunks; ++c) acc += U.partial[c * plane + e];
   U.Z[e] = acc;
 }
 
-template <typename TX, typename TO>
-hipError_t run(const SketchBatch& b, hipStream_t st) {
+template <typename TX, typename TO, typename S>
+hipError_t run(const S& b, hipStream_t st) {
   if (b.total_blocks > 0)
-    hipLaunchKernelGGL((sketch_gather_kernel<TX, TO>), dim3((unsigned)b.total_blocks), dim3(256), 0,
+    hipLaunchKernelGGL((sketch_gather_kernel<TX, TO, S>), dim3((unsigned)b.total_blocks), dim3(256), 0,
                        st, b);
   if (b.total_out > 0)
-    hipLaunchKernelGGL(sketch_reduce_kernel, dim3((unsigned)ceil_div(b.total_out, 256)), dim3(256),
+    hipLaunchKernelGGL(sketch_reduce_kernel<S>, dim3((unsigned)ceil_div(b.total_out, 256)), dim3(256),
                        0, st, b);
   return hipGetLastError();
 }
 
-}  // namespace
-
-hipError_t launch_sketch(int dtype, const SketchBatch& b, hipStream_t st) {
+template <typename S>
+hipError_t dispatch(int dtype, const S& b, hipStream_t st) {
   switch (dtype) {
     case TK_F64: return run<double, double>(b, st);
     case TK_F32: return run<float, float>(b, st);
@@ -123,5 +110,11 @@ hipError_t launch_sketch(int dtype, const SketchBatch& b, hipStream_t st) {
   }
   return hipErrorInvalidValue;
 }
+
+}  // namespace
+
+hipError_t launch_sketch(int dtype, const SketchBatch& b, hipStream_t st) { return dispatch(dtype, b, st); }
+
+hipError_t launch_sketch_list(int dtype, const SketchList& b, hipStream_t st) { return dispatch(dtype, b, st); }
 
 }  // namespace tk

@@ -6,6 +6,7 @@
 // reports the workspace size.
 #include <stdarg.h>
 #include <stdio.h>
+#include <string.h>
 
 #include <algorithm>
 #include <string>
@@ -109,6 +110,7 @@ void plan_unit(Workspace& ws, SketchUnit& u, const void* X, int64_t A, int64_t n
   u.Z = Z;
   u.Y = Y;
   u.block_begin = blocks;
+  u.out_begin = outs;
   blocks += (int64_t)u.nchunks * u.rowblocks;
   outs += n * s.ell;
 }
@@ -508,6 +510,275 @@ tk_status unfold_product(const void* A, int adt, const void* B, int bdt, int d, 
   g.accumulate = accumulate ? 1 : 0;
   TK_HIP(launch_unfold_gemm(g, adt, bdt, out_dt, st));
   return TK_OK;
+}
+
+
+// ------------------------------------------------------------------ batching form
+// All tensors and modes of a batch: the descriptor tables are built once on
+// the host and kept in the workspace; a run is a fixed launch sequence
+// (sketch, QR, W step, streaming core, remaining modes) with no allocation,
+// no host synchronisation and no memset, so it can be captured in a graph.
+constexpr int kBatchWaveCap = 16384;              // schedule capacity (waves)
+constexpr int64_t kBatchChunkMin = 128 << 10;    // smallest chunk the tuner tries (bytes)
+
+struct BatchPlanData {
+  int count = 0;
+  std::vector<SketchUnit> units;
+  std::vector<QRMat> qr;
+  std::vector<BatchTensor> tensors;
+  std::vector<std::vector<BatchModeDesc>> steps;
+  std::vector<int64_t> step_units, step_qmax;
+  SketchUnit* d_units = nullptr;
+  QRMat* d_qr = nullptr;
+  BatchTensor* d_tensors = nullptr;
+  BatchChunk* d_chunks = nullptr;
+  int32_t* d_wave_begin = nullptr;
+  int32_t* d_wave_chunks = nullptr;
+  size_t chunk_cap = 0;
+  std::vector<BatchModeDesc*> d_steps;
+  SketchList sl{};
+  BatchSlab bs{};
+  int tg = 1, nbuf = 2;
+  int64_t chunk_bytes = 512 << 10;
+};
+
+int64_t batch_chunk_slabs(const BatchTensor& t, int64_t chunk_bytes) {
+  const int64_t sb = (int64_t)t.nI * t.nJ * 4;
+  return std::max<int64_t>(1, chunk_bytes / sb);
+}
+
+// Chunks of every tensor, assigned to waves longest first onto the least
+// loaded wave; each wave's list is then ordered by tensor.
+void batch_schedule(const std::vector<BatchTensor>& ts, int64_t chunk_bytes, int nwaves,
+                    std::vector<BatchChunk>& chunks, std::vector<int32_t>& wb, std::vector<int32_t>& wc) {
+  chunks.clear();
+  std::vector<int64_t> cost;
+  for (int t = 0; t < (int)ts.size(); ++t) {
+    const int64_t S = batch_chunk_slabs(ts[t], chunk_bytes);
+    const int64_t tile_work = ceil_div(ts[t].nI, 16) * ceil_div(ts[t].nJ, 16);
+    for (int64_t a0 = 0; a0 < ts[t].A; a0 += S) {
+      BatchChunk c{};
+      c.tensor = t;
+      c.a0 = a0;
+      c.a1 = std::min(ts[t].A, a0 + S);
+      chunks.push_back(c);
+      cost.push_back((c.a1 - c.a0) * tile_work + 4);   // + per-chunk start-up
+    }
+  }
+  std::vector<int32_t> order(chunks.size());
+  for (size_t i = 0; i < order.size(); ++i) order[i] = (int32_t)i;
+  std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return cost[a] > cost[b]; });
+  nwaves = std::max(1, std::min<int>(nwaves, (int)chunks.size()));
+  std::vector<std::pair<int64_t, int32_t>> heap;   // (load, wave), min-heap
+  for (int w = 0; w < nwaves; ++w) heap.push_back({0, w});
+  auto cmp = [](const std::pair<int64_t, int32_t>& a, const std::pair<int64_t, int32_t>& b) {
+    return a.first != b.first ? a.first > b.first : a.second > b.second;
+  };
+  std::make_heap(heap.begin(), heap.end(), cmp);
+  std::vector<std::vector<int32_t>> lists(nwaves);
+  for (int32_t c : order) {
+    std::pop_heap(heap.begin(), heap.end(), cmp);
+    auto& top = heap.back();
+    lists[top.second].push_back(c);
+    top.first += cost[c];
+    std::push_heap(heap.begin(), heap.end(), cmp);
+  }
+  wb.assign(nwaves + 1, 0);
+  wc.clear();
+  for (int w = 0; w < nwaves; ++w) {
+    std::sort(lists[w].begin(), lists[w].end(), [&](int32_t a, int32_t b) {
+      return chunks[a].tensor != chunks[b].tensor ? chunks[a].tensor < chunks[b].tensor : chunks[a].a0 < chunks[b].a0;
+    });
+    wb[w] = (int32_t)wc.size();
+    wc.insert(wc.end(), lists[w].begin(), lists[w].end());
+  }
+  wb[nwaves] = (int32_t)wc.size();
+}
+
+tk_status plan_batch(Workspace& ws, int count, const tk_tensor* X, const int32_t* ranks,
+                     const tk_sketch* sk, void* const* U, void* const* G, int32_t* info, BatchPlanData& P) {
+  if (count < 1) return set_error(TK_EINVAL, "tucker_batch_plan_create: count = %d < 1", count);
+  if (!X || !ranks || !sk || !U || !G)
+    return set_error(TK_EINVAL, "tucker_batch_plan_create: a descriptor array is NULL");
+  P = BatchPlanData{};
+  P.count = count;
+  int m0 = 0, max_order = 0;
+  int64_t blocks = 0, outs = 0;
+  for (int t = 0; t < count; ++t) {
+    int64_t N;
+    if (tk_status s = check_tensor(&X[t], "tucker_batch_plan_create", &N)) return s;
+    const tk_tensor& x = X[t];
+    const int d = x.order;
+    if (x.dtype != TK_F32)
+      return set_error(TK_EUNSUPPORTED, "tucker_batch_plan_create: tensor %d: the batch form takes FP32 tensors", t);
+    if (d < 3) return set_error(TK_EUNSUPPORTED, "tucker_batch_plan_create: tensor %d: order %d < 3", t, d);
+    if (x.dims[d - 2] > kBatchMaxN || x.dims[d - 1] > kBatchMaxN)
+      return set_error(TK_EUNSUPPORTED, "tucker_batch_plan_create: tensor %d: trailing modes exceed %d", t, kBatchMaxN);
+    if (N * 4 >= (int64_t(1) << 31))
+      return set_error(TK_EUNSUPPORTED, "tucker_batch_plan_create: tensor %d: more than 2^29 entries", t);
+    if (!G[t]) return set_error(TK_EINVAL, "tucker_batch_plan_create: G[%d] is NULL", t);
+    for (int k = 0; k < d; ++k) {
+      const int r = ranks[m0 + k];
+      const tk_sketch& s = sk[m0 + k];
+      const int64_t ncols = N / x.dims[k];
+      if (tk_status e = check_sketch(s, x.dims[k], ncols, "tucker_batch_plan_create: sketch", m0 + k)) return e;
+      if (r < 1 || r > s.ell)
+        return set_error(TK_EINVAL, "tucker_batch_plan_create: rank %d of mode %d outside [1, ell = %d]", r, m0 + k, s.ell);
+      const int rmax = k >= d - 2 ? kBatchMaxC : 32;
+      if (r > rmax)
+        return set_error(TK_EUNSUPPORTED, "tucker_batch_plan_create: rank %d of mode %d exceeds %d", r, m0 + k, rmax);
+      if (!U[m0 + k]) return set_error(TK_EINVAL, "tucker_batch_plan_create: U[%d] is NULL", m0 + k);
+    }
+    m0 += d;
+    max_order = std::max(max_order, d);
+  }
+  // sketches and their QR / W step
+  m0 = 0;
+  for (int t = 0; t < count; ++t) {
+    const tk_tensor& x = X[t];
+    const int d = x.order;
+    for (int k = 0; k < d; ++k) {
+      const tk_sketch& s = sk[m0 + k];
+      const int64_t n = x.dims[k];
+      double* Z = ws.take<double>((size_t)n * s.ell);
+      float* Y = ws.take<float>((size_t)n * s.s);
+      SketchUnit u;
+      plan_unit(ws, u, x.data, prod(x.dims, 0, k), n, prod(x.dims, k + 1, d), s, Z, Y, blocks, outs);
+      P.units.push_back(u);
+      QRMat q;
+      plan_qr(ws, q, Z, n, s.ell, true, Y, s.s, ranks[m0 + k], U[m0 + k], info ? info + m0 + k : nullptr);
+      q.udtype = TK_F32;
+      P.qr.push_back(q);
+    }
+    m0 += d;
+  }
+  // core: streaming pass per tensor, then the remaining modes step by step
+  P.steps.assign(max_order - 2, {});
+  m0 = 0;
+  for (int t = 0; t < count; ++t) {
+    const tk_tensor& x = X[t];
+    const int d = x.order;
+    const int32_t* c = ranks + m0;
+    BatchTensor bt{};
+    bt.X = static_cast<const float*>(x.data);
+    bt.FI = static_cast<const float*>(U[m0 + d - 2]);
+    bt.FJ = static_cast<const float*>(U[m0 + d - 1]);
+    bt.A = prod(x.dims, 0, d - 2);
+    bt.nI = (int32_t)x.dims[d - 2];
+    bt.nJ = (int32_t)x.dims[d - 1];
+    bt.cI = c[d - 2];
+    bt.cJ = c[d - 1];
+    bt.T = ws.take<float>((size_t)bt.A * bt.cI * bt.cJ);
+    int64_t shape[TK_MAX_ORDER];
+    for (int k = 0; k < d; ++k) shape[k] = x.dims[k];
+    shape[d - 2] = c[d - 2];
+    shape[d - 1] = c[d - 1];
+    int64_t mx = 1;
+    {
+      int64_t sh[TK_MAX_ORDER];
+      for (int k = 0; k < d; ++k) sh[k] = shape[k];
+      for (int k = d - 3; k >= 1; --k) {
+        sh[k] = c[k];
+        mx = std::max(mx, prod(sh, 0, d));
+      }
+    }
+    float* buf[2] = {ws.take<float>((size_t)mx), ws.take<float>((size_t)mx)};
+    const float* cur = bt.T;
+    for (int s = 0; s < d - 2; ++s) {
+      const int k = d - 3 - s;
+      BatchModeDesc md{};
+      md.in = cur;
+      md.F = static_cast<const float*>(U[m0 + k]);
+      md.A = prod(shape, 0, k);
+      md.Q = shape[k];
+      md.B = prod(shape, k + 1, d);
+      md.P = c[k];
+      md.out = k == 0 ? static_cast<float*>(G[t]) : buf[s & 1];
+      P.steps[s].push_back(md);
+      shape[k] = c[k];
+      cur = md.out;
+    }
+    P.tensors.push_back(bt);
+    m0 += d;
+  }
+  P.step_units.assign(P.steps.size(), 0);
+  P.step_qmax.assign(P.steps.size(), 1);
+  for (size_t s = 0; s < P.steps.size(); ++s)
+    for (auto& md : P.steps[s]) {
+      md.unit_begin = P.step_units[s];
+      P.step_units[s] += batch_mode_units(md.A, md.B);
+      P.step_qmax[s] = std::max(P.step_qmax[s], md.Q);
+    }
+  // device tables
+  P.chunk_cap = 0;
+  for (auto& bt : P.tensors) P.chunk_cap += (size_t)ceil_div(bt.A, batch_chunk_slabs(bt, kBatchChunkMin));
+  P.d_units = ws.take<SketchUnit>(P.units.size());
+  P.d_qr = ws.take<QRMat>(P.qr.size());
+  P.d_tensors = ws.take<BatchTensor>(P.tensors.size());
+  P.d_chunks = ws.take<BatchChunk>(P.chunk_cap);
+  P.d_wave_begin = ws.take<int32_t>(kBatchWaveCap + 1);
+  P.d_wave_chunks = ws.take<int32_t>(P.chunk_cap);
+  for (auto& st : P.steps) P.d_steps.push_back(ws.take<BatchModeDesc>(st.size()));
+  P.sl.u = P.d_units;
+  P.sl.count = (int32_t)P.units.size();
+  P.sl.total_blocks = blocks;
+  P.sl.total_out = outs;
+  return TK_OK;
+}
+
+// schedule of the streaming pass for a variant and chunk size (synchronous upload)
+tk_status batch_set_schedule(BatchPlanData& P, int tg, int nbuf, int64_t chunk_bytes, hipStream_t st) {
+  std::vector<BatchChunk> chunks;
+  std::vector<int32_t> wb, wc;
+  const int waves = std::min(kBatchWaveCap, batch_slab_waves(tg, nbuf));
+  batch_schedule(P.tensors, std::max(chunk_bytes, kBatchChunkMin), waves, chunks, wb, wc);
+  if (chunks.size() > P.chunk_cap) return set_error(TK_EINVAL, "batch schedule exceeds its table");
+  TK_HIP(hipMemcpyAsync(P.d_chunks, chunks.data(), chunks.size() * sizeof(BatchChunk), hipMemcpyHostToDevice, st));
+  TK_HIP(hipMemcpyAsync(P.d_wave_begin, wb.data(), wb.size() * sizeof(int32_t), hipMemcpyHostToDevice, st));
+  TK_HIP(hipMemcpyAsync(P.d_wave_chunks, wc.data(), wc.size() * sizeof(int32_t), hipMemcpyHostToDevice, st));
+  TK_HIP(hipStreamSynchronize(st));
+  P.tg = tg;
+  P.nbuf = nbuf;
+  P.chunk_bytes = chunk_bytes;
+  P.bs.tensors = P.d_tensors;
+  P.bs.chunks = P.d_chunks;
+  P.bs.wave_begin = P.d_wave_begin;
+  P.bs.wave_chunks = P.d_wave_chunks;
+  P.bs.nwaves = (int32_t)(wb.size() - 1);
+  return TK_OK;
+}
+
+tk_status batch_upload(BatchPlanData& P, hipStream_t st) {
+  TK_HIP(hipMemcpyAsync(P.d_units, P.units.data(), P.units.size() * sizeof(SketchUnit), hipMemcpyHostToDevice, st));
+  TK_HIP(hipMemcpyAsync(P.d_qr, P.qr.data(), P.qr.size() * sizeof(QRMat), hipMemcpyHostToDevice, st));
+  TK_HIP(hipMemcpyAsync(P.d_tensors, P.tensors.data(), P.tensors.size() * sizeof(BatchTensor), hipMemcpyHostToDevice, st));
+  for (size_t s = 0; s < P.steps.size(); ++s)
+    TK_HIP(hipMemcpyAsync(P.d_steps[s], P.steps[s].data(), P.steps[s].size() * sizeof(BatchModeDesc),
+                          hipMemcpyHostToDevice, st));
+  return batch_set_schedule(P, P.tg, P.nbuf, P.chunk_bytes, st);
+}
+
+tk_status batch_core(const BatchPlanData& P, hipStream_t st) {
+  TK_HIP(profile_begin(st));
+  TK_HIP(launch_batch_slab(P.bs, P.tg, P.nbuf, st));
+  TK_HIP(profile_end(st));
+  for (size_t s = 0; s < P.steps.size(); ++s) {
+    BatchMode bm{};
+    bm.descs = P.d_steps[s];
+    bm.count = (int32_t)P.steps[s].size();
+    TK_HIP(launch_batch_mode(bm, P.step_units[s], P.step_qmax[s], st));
+  }
+  return TK_OK;
+}
+
+tk_status batch_run(const BatchPlanData& P, hipStream_t st) {
+  TK_HIP(launch_sketch_list(TK_F32, P.sl, st));
+  QRList ql{};
+  ql.m = P.d_qr;
+  ql.count = (int32_t)P.qr.size();
+  TK_HIP(launch_cholqr_list(ql, P.qr.data(), st));
+  TK_HIP(launch_wstep_list(ql, P.qr.data(), TK_F32, TK_F32, st));
+  return batch_core(P, st);
 }
 
 }  // namespace
@@ -1032,5 +1303,103 @@ tk_status tucker_reconstruct_vjp(int32_t order, const int64_t* dims, int32_t fdt
     }
   return TK_OK;
 }
+
+
+struct tk_batch_plan {
+  tk::BatchPlanData data;
+  int device = 0;
+};
+
+tk_status tucker_batch_plan_create(int32_t count, const tk_tensor* X, const int32_t* ranks,
+                                   const tk_sketch* sk, void* const* U, void* const* G, int32_t* info,
+                                   void* ws, size_t* ws_bytes, void* stream, tk_batch_plan** plan) {
+  clear_error();
+  if (!ws_bytes) return set_error(TK_EINVAL, "tucker_batch_plan_create: ws_bytes is NULL");
+  Workspace w;
+  w.base = static_cast<char*>(ws);
+  BatchPlanData P;
+  if (tk_status s = plan_batch(w, count, X, ranks, sk, U, G, info, P)) return s;
+  if (!ws) {
+    *ws_bytes = w.off;
+    return TK_OK;
+  }
+  if (*ws_bytes < w.off)
+    return set_error(TK_EWORKSPACE, "tucker_batch_plan_create: workspace %zu < required %zu", *ws_bytes, w.off);
+  if (!plan) return set_error(TK_EINVAL, "tucker_batch_plan_create: plan is NULL");
+  int dev = 0;
+  TK_HIP(hipGetDevice(&dev));
+  tk_batch_plan* p = new tk_batch_plan();
+  p->data = std::move(P);
+  p->device = dev;
+  if (tk_status s = batch_upload(p->data, as_stream(stream))) {
+    delete p;
+    return s;
+  }
+  *plan = p;
+  return TK_OK;
+}
+
+tk_status tucker_batch_run(const tk_batch_plan* plan, void* stream) {
+  clear_error();
+  if (!plan) return set_error(TK_EINVAL, "tucker_batch_run: plan is NULL");
+  return batch_run(plan->data, as_stream(stream));
+}
+
+tk_status tucker_batch_autotune(tk_batch_plan* plan, void* stream, char* report, size_t report_bytes) {
+  clear_error();
+  if (!plan) return set_error(TK_EINVAL, "tucker_batch_autotune: plan is NULL");
+  BatchPlanData& P = plan->data;
+  hipStream_t st = as_stream(stream);
+  // factors for the timed passes
+  if (tk_status s = batch_run(P, st)) return s;
+  const int variants[3][2] = {{1, 2}, {2, 2}, {1, 3}};
+  const int64_t chunk_sizes[3] = {kBatchChunkMin, 512 << 10, 2 << 20};
+  hipEvent_t e0, e1;
+  TK_HIP(hipEventCreate(&e0));
+  TK_HIP(hipEventCreate(&e1));
+  std::string rep;
+  float best = 1e30f;
+  int bv = 0, bc = 1;
+  tk_status status = TK_OK;
+  for (int v = 0; v < 3 && status == TK_OK; ++v)
+    for (int c = 0; c < 3 && status == TK_OK; ++c) {
+      if ((status = batch_set_schedule(P, variants[v][0], variants[v][1], chunk_sizes[c], st))) break;
+      if ((status = batch_core(P, st))) break;   // warm-up
+      if (hipEventRecord(e0, st) != hipSuccess) { status = set_error(TK_EDEVICE, "event record failed"); break; }
+      for (int r = 0; r < 3 && status == TK_OK; ++r) status = batch_core(P, st);
+      if (status) break;
+      float ms = 0.0f;
+      if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+          hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+        status = set_error(TK_EDEVICE, "event timing failed");
+        break;
+      }
+      ms /= 3.0f;
+      char line[160];
+      snprintf(line, sizeof(line), "tiles/unit %d, buffers %d, chunk %lld KB: %.4f ms\n", variants[v][0],
+               variants[v][1], (long long)(chunk_sizes[c] >> 10), ms);
+      rep += line;
+      if (ms < best) {
+        best = ms;
+        bv = v;
+        bc = c;
+      }
+    }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  if (status) return status;
+  if (tk_status s = batch_set_schedule(P, variants[bv][0], variants[bv][1], chunk_sizes[bc], st)) return s;
+  char line[160];
+  snprintf(line, sizeof(line), "chosen: tiles/unit %d, buffers %d, chunk %lld KB\n", variants[bv][0],
+           variants[bv][1], (long long)(chunk_sizes[bc] >> 10));
+  rep += line;
+  if (report && report_bytes) {
+    strncpy(report, rep.c_str(), report_bytes - 1);
+    report[report_bytes - 1] = 0;
+  }
+  return TK_OK;
+}
+
+void tucker_batch_plan_destroy(tk_batch_plan* plan) { delete plan; }
 
 }  // extern "C"

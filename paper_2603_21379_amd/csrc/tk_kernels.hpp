@@ -18,6 +18,7 @@ struct SketchUnit {
   double* Z;            // [n][ell]
   void* Y;              // [n][s] in the tensor dtype, or nullptr
   int64_t block_begin;  // first block of this unit in the gather launch
+  int64_t out_begin;    // first entry of this unit in the reduce launch
   int32_t ell;
   int32_t nchunks;      // ceil(s / kSketchCols)
   int32_t rowblocks;    // ceil(n / kSketchRows)
@@ -28,10 +29,47 @@ struct SketchBatch {
   int64_t total_blocks;
   int64_t total_out;    // sum over units of n * ell (reduce launch)
   SketchUnit u[kMaxUnits];
+  __device__ const SketchUnit& get(int i) const { return u[i]; }
+  __device__ int find_block(int64_t blk) const {
+    int i = 0;
+    while (i + 1 < count && u[i + 1].block_begin <= blk) ++i;
+    return i;
+  }
+  __device__ int find_out(int64_t g) const {
+    int i = 0;
+    while (i + 1 < count && u[i + 1].out_begin <= g) ++i;
+    return i;
+  }
+};
+// the same units in a device table (any number), found by binary search
+struct SketchList {
+  const SketchUnit* u;
+  int32_t count;
+  int32_t pad;
+  int64_t total_blocks;
+  int64_t total_out;
+  __device__ const SketchUnit& get(int i) const { return u[i]; }
+  __device__ int find_block(int64_t blk) const {
+    int lo = 0, hi = count - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (u[mid].block_begin <= blk) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+  }
+  __device__ int find_out(int64_t g) const {
+    int lo = 0, hi = count - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (u[mid].out_begin <= g) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+  }
 };
 constexpr int kSketchRows = 64;
 constexpr int kSketchCols = 32;
 hipError_t launch_sketch(int dtype, const SketchBatch& b, hipStream_t st);
+hipError_t launch_sketch_list(int dtype, const SketchList& b, hipStream_t st);
 
 // ---------------------------------------------------------------- CholeskyQR2 + W step
 struct QRMat {
@@ -66,9 +104,20 @@ constexpr int kQRRowBlock = 64;
 struct QRBatch {
   int32_t count;
   QRMat m[kQRMaxBatch];
+  __device__ const QRMat& get(int i) const { return m[i]; }
+};
+// the same descriptors in a device table (batches of any size)
+struct QRList {
+  const QRMat* m;
+  int32_t count;
+  int32_t pad;
+  __device__ const QRMat& get(int i) const { return m[i]; }
 };
 hipError_t launch_cholqr(const QRBatch& b, hipStream_t st);
 hipError_t launch_wstep(const QRBatch& b, int ydtype, int udtype, hipStream_t st);
+// host: the table `dev.m` points to, as a host copy (grid sizes, path choice)
+hipError_t launch_cholqr_list(const QRList& dev, const QRMat* host, hipStream_t st);
+hipError_t launch_wstep_list(const QRList& dev, const QRMat* host, int ydtype, int udtype, hipStream_t st);
 
 // ---------------------------------------------------------------- generic mode products
 // out[a][p][b] = sum_q in[a][q][b] * M[p][q],  M[p][q] = Mp[p*rs + q*cs]
@@ -137,6 +186,54 @@ struct CoreSlab {
 };
 bool slab_supported(int dtype, int64_t nI, int64_t nJ, int32_t cI, int32_t cJ);
 hipError_t launch_core_slab(const CoreSlab& p, int xdt, hipStream_t st);
+
+// ---------------------------------------------------------------- batching form
+// Streaming pass of many FP32 tensors (two trailing modes, n <= 96, c <= 16).
+struct BatchTensor {
+  const float* X;
+  const float* FI;      // nI x cI
+  const float* FJ;      // nJ x cJ
+  float* T;             // (A, cI, cJ)
+  int64_t A;            // slabs
+  int32_t nI, nJ, cI, cJ;
+};
+struct BatchChunk {
+  int32_t tensor;
+  int32_t pad;
+  int64_t a0, a1;       // slabs [a0, a1) of the tensor
+};
+struct BatchSlab {
+  const BatchTensor* tensors;
+  const BatchChunk* chunks;
+  const int32_t* wave_begin;   // [nwaves + 1]: chunk list of each wave (CSR)
+  const int32_t* wave_chunks;
+  int32_t nwaves;
+  int32_t pad;
+};
+constexpr int kBatchMaxN = 96;
+constexpr int kBatchMaxC = 16;
+size_t batch_slab_lds_bytes();
+int batch_slab_waves(int tg, int nbuf);   // resident waves of a variant
+hipError_t launch_batch_slab(const BatchSlab& bs, int tg, int nbuf, hipStream_t st);
+
+// One remaining mode of many tensors: out[a][p][b] = sum_q F[q][p] in[a][q][b].
+struct BatchModeDesc {
+  const float* in;
+  const float* F;       // Q x P
+  float* out;           // (A, P, B)
+  int64_t A, Q, B;
+  int64_t unit_begin;   // first unit (multiple of 4) of this descriptor
+  int32_t P;
+  int32_t pad;
+};
+struct BatchMode {
+  const BatchModeDesc* descs;
+  int32_t count;
+  int32_t pad;
+};
+int64_t batch_mode_units(int64_t A, int64_t B);   // padded to whole workgroups
+size_t batch_mode_lds_bytes(int64_t Qmax);
+hipError_t launch_batch_mode(const BatchMode& bm, int64_t total_units, int64_t Qmax, hipStream_t st);
 
 // ---------------------------------------------------------------- FP32 MFMA mode contraction
 // out[a][p][b] = sum_q F[q][p] in[a][q][b] for an FP32 (A, Q, B) tensor, P <= 32.

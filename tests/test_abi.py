@@ -174,3 +174,35 @@ def test_status_codes_in_header_match_binding():
     text = open(HEADER).read()
     for code, name in B.STATUS.items():
         assert re.search(rf"\b{name}\s*=\s*{code}\b", text), name
+
+
+def test_batch_plan_validation_and_query():
+    L = B.lib()
+    f = L.tucker_batch_plan_create
+    dims = (20, 30, 40)
+    X = (B.TkTensor * 1)()
+    X[0] = _tensor(dims)
+    ranks = (C.c_int32 * 3)(3, 4, 5)
+    sk = (B.TkSketch * 3)()
+    for k, n in enumerate(dims):
+        sk[k].s = 10 * n
+        sk[k].ell = ranks[k] + 5
+        sk[k].idx = FAKE
+        sk[k].omega = FAKE
+    U = (C.c_void_p * 3)(FAKE, FAKE, FAKE)
+    G = (C.c_void_p * 1)(FAKE)
+    n = C.c_size_t(0)
+    assert f(1, X, ranks, sk, U, G, None, None, C.byref(n), None, None) == 0
+    assert n.value > 0
+    # FP64 tensors, order 2 and wide trailing modes are outside the batch form
+    X[0] = _tensor(dims, dtype=B.TK_F64)
+    assert f(1, X, ranks, sk, U, G, None, None, C.byref(n), None, None) == 5
+    X[0] = _tensor((20, 300, 40))
+    assert f(1, X, ranks, sk, U, G, None, None, C.byref(n), None, None) == 5
+    X[0] = _tensor(dims)
+    ranks[2] = 11    # above ell
+    assert f(1, X, ranks, sk, U, G, None, None, C.byref(n), None, None) == 1
+    ranks[2] = 5
+    G[0] = None
+    assert f(1, X, ranks, sk, U, G, None, None, C.byref(n), None, None) == 1
+    assert f(0, X, ranks, sk, U, G, None, None, C.byref(n), None, None) == 1
