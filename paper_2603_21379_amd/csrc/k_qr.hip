@@ -220,14 +220,18 @@ __device__ bool cholesky_upper_wave(double (*G)[kMaxEll + 1], int n, int lane, d
     if (!(piv > tol)) return false;  // uniform: every lane read the same pivot
     const double rjj = sqrt(piv), inv = 1.0 / rjj;
     TK_WAVE_SYNC();
-    for (int i = j + 1 + lane; i < n; i += 64) G[j][i] *= inv;
+    // lane q owns column q (n <= 64): scale row j, then the trailing update
+    // of its column, rows j < p <= q (row p's multiplier is a broadcast)
+    const int q = lane;
+    double gjq = 0.0;
+    if (q > j && q < n) {
+      gjq = G[j][q] * inv;
+      G[j][q] = gjq;
+    }
     if (lane == 0) G[j][j] = rjj;
     TK_WAVE_SYNC();
-    const int m = n - j - 1;
-    for (int e = lane; e < m * m; e += 64) {
-      const int p = j + 1 + e / m, q = j + 1 + e % m;
-      if (q >= p) G[p][q] -= G[j][p] * G[j][q];
-    }
+    if (q > j && q < n)
+      for (int p = j + 1; p <= q; ++p) G[p][q] -= G[j][p] * gjq;
     TK_WAVE_SYNC();
   }
   return true;
@@ -500,7 +504,6 @@ __global__ __launch_bounds__(256) void mgram_kernel(const S b) {
 // |a_pq| <= u sqrt(a_pp a_qq) can be unreachable in floating point for
 // strongly graded pairs.
 constexpr int kEigThreads = 256;
-constexpr int kEigItems = ((kMaxEll / 2) * (kMaxEll / 2) + kMaxEll * (kMaxEll / 2)) / kEigThreads;
 
 template <typename S>
 __global__ __launch_bounds__(kEigThreads) void eig_kernel(const S b) {
@@ -509,7 +512,7 @@ __global__ __launch_bounds__(kEigThreads) void eig_kernel(const S b) {
   __shared__ double V[kMaxEll][kMaxEll + 1];
   __shared__ double rc_[kMaxEll / 2], rs_[kMaxEll / 2];
   __shared__ int rp_[kMaxEll / 2], rq_[kMaxEll / 2];
-  __shared__ int rotations;
+  __shared__ int rotations;   // any rotation in this sweep (written by wave 0)
   const int n = M.ell, np = n + (n & 1), half = np / 2, tid = threadIdx.x;
   // rotations stop below rounding level of the output precision (relative to
   // the pair's own scale): FP64 bases need ~u, FP32 bases ~1e-12 suffices
@@ -522,26 +525,30 @@ __global__ __launch_bounds__(kEigThreads) void eig_kernel(const S b) {
     A[p][q] = v;
     V[p][q] = p == q ? 1.0 : 0.0;
   }
-  // this thread's items: first the half x half 2x2 blocks of A (pair k1 rows,
-  // pair k2 columns: A <- J^T A J on the block), then the np x half column
-  // pairs of V (V <- V J); code = k1 * 64 + k2 + 1, or -(k * 64 + i) - 1
-  int item[kEigItems];
-  const int nblk = half * half, nitems = nblk + np * half;
+  // this thread's items, in two loops of one kind each so a wave never runs
+  // both kinds: the half x half 2x2 blocks of A (pair k1 rows, pair k2
+  // columns: A <- J^T A J on the block) and the np x half column pairs of V
+  // (V <- V J); codes k1 * 64 + k2 and k * 64 + i, or -1 past the end
+  constexpr int kItemsA = (kMaxEll / 2) * (kMaxEll / 2) / kEigThreads;
+  constexpr int kItemsV = kMaxEll * (kMaxEll / 2) / kEigThreads;
+  int itemA[kItemsA], itemV[kItemsV];
+  const int nblk = half * half, nv = np * half;
 #pragma unroll
-  for (int t = 0; t < kEigItems; ++t) {
+  for (int t = 0; t < kItemsA; ++t) {
     const int e = tid + kEigThreads * t;
-    if (e >= nitems) item[t] = 0;
-    else if (e < nblk) item[t] = (e / half) * 64 + (e % half) + 1;
-    else {
-      const int f = e - nblk;
-      item[t] = -(((f / np) * 64) + (f % np)) - 1;
-    }
+    itemA[t] = e < nblk ? (e / half) * 64 + (e % half) : -1;
+  }
+#pragma unroll
+  for (int t = 0; t < kItemsV; ++t) {
+    const int e = tid + kEigThreads * t;
+    itemV[t] = e < nv ? (e / np) * 64 + (e % np) : -1;
   }
   __syncthreads();
   for (int sweep = 0; sweep < 60; ++sweep) {
     if (tid == 0) rotations = 0;
     __syncthreads();
     for (int round = 0; round < np - 1; ++round) {
+      bool rot = false;
       if (tid < half) {
         int p, q;
         if (tid == 0) { p = np - 1; q = round; }
@@ -558,41 +565,47 @@ __global__ __launch_bounds__(kEigThreads) void eig_kernel(const S b) {
             const double t = (th >= 0.0 ? 1.0 : -1.0) / (fabs(th) + sqrt(1.0 + th * th));
             c = 1.0 / sqrt(1.0 + t * t);
             s = t * c;
-            atomicAdd(&rotations, 1);
+            rot = true;
           }
         }
         rc_[tid] = c; rs_[tid] = s; rp_[tid] = p; rq_[tid] = q;
       }
+      if (tid < 64) {   // half <= 32: every rotation of the round is in wave 0
+        const bool any = __any(rot);
+        if (tid == 0 && any) rotations = 1;
+      }
       __syncthreads();
 #pragma unroll
-      for (int t = 0; t < kEigItems; ++t) {
-        const int code = item[t];
-        if (code > 0) {
-          const int k1 = (code - 1) >> 6, k2 = (code - 1) & 63;
-          const double s1 = rs_[k1], s2 = rs_[k2];
-          if (s1 != 0.0 || s2 != 0.0) {
-            const double c1 = rc_[k1], c2 = rc_[k2];
-            const int p1 = rp_[k1], q1 = rq_[k1], p2 = rp_[k2], q2 = rq_[k2];
-            const double a = A[p1][p2], bb = A[p1][q2], cc = A[q1][p2], dd = A[q1][q2];
-            // rows (J^T from the left), then columns (J from the right)
-            const double ra = c1 * a - s1 * cc, rb = c1 * bb - s1 * dd;
-            const double rc = s1 * a + c1 * cc, rd = s1 * bb + c1 * dd;
-            A[p1][p2] = c2 * ra - s2 * rb;
-            A[p1][q2] = s2 * ra + c2 * rb;
-            A[q1][p2] = c2 * rc - s2 * rd;
-            A[q1][q2] = s2 * rc + c2 * rd;
-          }
-        } else if (code < 0) {
-          const int f = -code - 1;
-          const int k = f >> 6, i = f & 63;
-          const double sv = rs_[k];
-          if (sv != 0.0) {
-            const double cv = rc_[k];
-            const int p = rp_[k], q = rq_[k];
-            const double vip = V[i][p], viq = V[i][q];
-            V[i][p] = cv * vip - sv * viq;
-            V[i][q] = sv * vip + cv * viq;
-          }
+      for (int t = 0; t < kItemsA; ++t) {
+        const int code = itemA[t];
+        if (code < 0) break;
+        const int k1 = code >> 6, k2 = code & 63;
+        const double s1 = rs_[k1], s2 = rs_[k2];
+        if (s1 != 0.0 || s2 != 0.0) {
+          const double c1 = rc_[k1], c2 = rc_[k2];
+          const int p1 = rp_[k1], q1 = rq_[k1], p2 = rp_[k2], q2 = rq_[k2];
+          const double a = A[p1][p2], bb = A[p1][q2], cc = A[q1][p2], dd = A[q1][q2];
+          // rows (J^T from the left), then columns (J from the right)
+          const double ra = c1 * a - s1 * cc, rb = c1 * bb - s1 * dd;
+          const double rc = s1 * a + c1 * cc, rd = s1 * bb + c1 * dd;
+          A[p1][p2] = c2 * ra - s2 * rb;
+          A[p1][q2] = s2 * ra + c2 * rb;
+          A[q1][p2] = c2 * rc - s2 * rd;
+          A[q1][q2] = s2 * rc + c2 * rd;
+        }
+      }
+#pragma unroll
+      for (int t = 0; t < kItemsV; ++t) {
+        const int code = itemV[t];
+        if (code < 0) break;
+        const int k = code >> 6, i = code & 63;
+        const double sv = rs_[k];
+        if (sv != 0.0) {
+          const double cv = rc_[k];
+          const int p = rp_[k], q = rq_[k];
+          const double vip = V[i][p], viq = V[i][q];
+          V[i][p] = cv * vip - sv * viq;
+          V[i][q] = sv * vip + cv * viq;
         }
       }
       __syncthreads();

@@ -17,34 +17,60 @@ template <typename TX, typename TO, typename S>
 __global__ __launch_bounds__(256) void sketch_gather_kernel(const S b) {
   __shared__ double sY[kSketchRows][kSketchCols + 1];
   __shared__ double sO[kSketchCols][64 + 1];
+  __shared__ int64_t sFib[kSketchCols];   // offset of element 0 of each fiber, or -1
   const int64_t blk = blockIdx.x;
   const SketchUnit& U = b.get(b.find_block(blk));
   const int64_t lb = blk - U.block_begin;
   const int64_t chunk = lb / U.rowblocks;
   const int64_t rb = lb - chunk * U.rowblocks;
   const int64_t i0 = rb * kSketchRows, t0 = chunk * kSketchCols;
-  const TX* X = static_cast<const TX*>(U.X);
-  TX* Y = static_cast<TX*>(U.Y);
+  const TX* __restrict__ X = static_cast<const TX*>(U.X);
+  TX* __restrict__ Y = static_cast<TX*>(U.Y);
   const int tid = threadIdx.x;
   const bool rows_fast = (U.B == 1);  // fibers contiguous: walk along the fiber
-
-  for (int e = tid; e < kSketchRows * kSketchCols; e += blockDim.x) {
-    int i, t;
-    if (rows_fast) { i = e % kSketchRows; t = e / kSketchRows; }
-    else { t = e % kSketchCols; i = e / kSketchCols; }
-    const int64_t gi = i0 + i, gt = t0 + t;
-    double v = 0.0;
-    if (gi < U.n && gt < U.s) {
+  // the block's fibers: column j of the unfolding is X[a, :, b], (a, b) = divmod(j, B)
+  if (tid < kSketchCols) {
+    const int64_t gt = t0 + tid;
+    int64_t off = -1;
+    if (gt < U.s) {
       const int64_t j = U.idx ? U.idx[gt] : gt;
       if (j >= 0 && j < U.A * U.B) {  // a column index outside the unfolding reads nothing
         const int64_t a = j / U.B;
-        const int64_t bb = j - a * U.B;
-        const TX x = X[(a * U.n + gi) * U.B + bb];
-        v = to_double(x);
-        if (Y) Y[gi * U.s + gt] = x;
+        off = a * U.n * U.B + (j - a * U.B);
       } else {
-        v = __builtin_nan("");
+        off = -2;
       }
+    }
+    sFib[tid] = off;
+  }
+  __syncthreads();
+  // every load of the tile first, then the stores
+  constexpr int kPer = kSketchRows * kSketchCols / 256;
+  TX xv[kPer];
+  bool ok[kPer];
+#pragma unroll
+  for (int q = 0; q < kPer; ++q) {
+    const int e = tid + 256 * q;
+    int i, t;
+    if (rows_fast) { i = e % kSketchRows; t = e / kSketchRows; }
+    else { t = e % kSketchCols; i = e / kSketchCols; }
+    const int64_t gi = i0 + i, f = sFib[t];
+    ok[q] = gi < U.n && f >= 0;
+    xv[q] = ok[q] ? X[f + gi * U.B] : TX{};
+  }
+#pragma unroll
+  for (int q = 0; q < kPer; ++q) {
+    const int e = tid + 256 * q;
+    int i, t;
+    if (rows_fast) { i = e % kSketchRows; t = e / kSketchRows; }
+    else { t = e % kSketchCols; i = e / kSketchCols; }
+    const int64_t gi = i0 + i, f = sFib[t];
+    double v = 0.0;
+    if (ok[q]) {
+      v = to_double(xv[q]);
+      if (Y) Y[gi * U.s + t0 + t] = xv[q];
+    } else if (gi < U.n && f == -2) {
+      v = __builtin_nan("");
     }
     sY[i][t] = v;
   }

@@ -519,7 +519,7 @@ tk_status unfold_product(const void* A, int adt, const void* B, int bdt, int d, 
 // (sketch, QR, W step, streaming core, remaining modes) with no allocation,
 // no host synchronisation and no memset, so it can be captured in a graph.
 constexpr int kBatchWaveCap = 16384;              // schedule capacity (waves)
-constexpr int64_t kBatchChunkMin = 128 << 10;    // smallest chunk the tuner tries (bytes)
+constexpr int64_t kBatchChunkMin = 32 << 10;     // smallest chunk the tuner tries (bytes)
 
 struct BatchPlanData {
   int count = 0;
@@ -529,6 +529,8 @@ struct BatchPlanData {
   std::vector<std::vector<BatchModeDesc>> steps;
   std::vector<int64_t> step_units, step_qmax;
   SketchUnit* d_units = nullptr;
+  int32_t* d_block_unit = nullptr;
+  std::vector<int32_t> block_unit;
   QRMat* d_qr = nullptr;
   BatchTensor* d_tensors = nullptr;
   BatchChunk* d_chunks = nullptr;
@@ -713,6 +715,7 @@ tk_status plan_batch(Workspace& ws, int count, const tk_tensor* X, const int32_t
   P.chunk_cap = 0;
   for (auto& bt : P.tensors) P.chunk_cap += (size_t)ceil_div(bt.A, batch_chunk_slabs(bt, kBatchChunkMin));
   P.d_units = ws.take<SketchUnit>(P.units.size());
+  P.d_block_unit = ws.take<int32_t>((size_t)std::max<int64_t>(blocks, 1));
   P.d_qr = ws.take<QRMat>(P.qr.size());
   P.d_tensors = ws.take<BatchTensor>(P.tensors.size());
   P.d_chunks = ws.take<BatchChunk>(P.chunk_cap);
@@ -720,6 +723,7 @@ tk_status plan_batch(Workspace& ws, int count, const tk_tensor* X, const int32_t
   P.d_wave_chunks = ws.take<int32_t>(P.chunk_cap);
   for (auto& st : P.steps) P.d_steps.push_back(ws.take<BatchModeDesc>(st.size()));
   P.sl.u = P.d_units;
+  P.sl.block_unit = P.d_block_unit;
   P.sl.count = (int32_t)P.units.size();
   P.sl.total_blocks = blocks;
   P.sl.total_out = outs;
@@ -750,6 +754,14 @@ tk_status batch_set_schedule(BatchPlanData& P, int tg, int nbuf, int64_t chunk_b
 
 tk_status batch_upload(BatchPlanData& P, hipStream_t st) {
   TK_HIP(hipMemcpyAsync(P.d_units, P.units.data(), P.units.size() * sizeof(SketchUnit), hipMemcpyHostToDevice, st));
+  P.block_unit.assign((size_t)P.sl.total_blocks, 0);
+  for (size_t i = 0; i < P.units.size(); ++i) {
+    const int64_t end = i + 1 < P.units.size() ? P.units[i + 1].block_begin : P.sl.total_blocks;
+    for (int64_t bk = P.units[i].block_begin; bk < end; ++bk) P.block_unit[bk] = (int32_t)i;
+  }
+  if (!P.block_unit.empty())
+    TK_HIP(hipMemcpyAsync(P.d_block_unit, P.block_unit.data(), P.block_unit.size() * sizeof(int32_t),
+                          hipMemcpyHostToDevice, st));
   TK_HIP(hipMemcpyAsync(P.d_qr, P.qr.data(), P.qr.size() * sizeof(QRMat), hipMemcpyHostToDevice, st));
   TK_HIP(hipMemcpyAsync(P.d_tensors, P.tensors.data(), P.tensors.size() * sizeof(BatchTensor), hipMemcpyHostToDevice, st));
   for (size_t s = 0; s < P.steps.size(); ++s)
@@ -1353,7 +1365,7 @@ tk_status tucker_batch_autotune(tk_batch_plan* plan, void* stream, char* report,
   // factors for the timed passes
   if (tk_status s = batch_run(P, st)) return s;
   const int variants[3][2] = {{1, 2}, {2, 2}, {1, 3}};
-  const int64_t chunk_sizes[3] = {kBatchChunkMin, 512 << 10, 2 << 20};
+  const int64_t chunk_sizes[3] = {kBatchChunkMin, 128 << 10, 512 << 10};
   hipEvent_t e0, e1;
   TK_HIP(hipEventCreate(&e0));
   TK_HIP(hipEventCreate(&e1));

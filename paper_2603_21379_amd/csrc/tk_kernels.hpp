@@ -44,19 +44,13 @@ struct SketchBatch {
 // the same units in a device table (any number), found by binary search
 struct SketchList {
   const SketchUnit* u;
+  const int32_t* block_unit;   // unit of every gather block
   int32_t count;
   int32_t pad;
   int64_t total_blocks;
   int64_t total_out;
   __device__ const SketchUnit& get(int i) const { return u[i]; }
-  __device__ int find_block(int64_t blk) const {
-    int lo = 0, hi = count - 1;
-    while (lo < hi) {
-      const int mid = (lo + hi + 1) >> 1;
-      if (u[mid].block_begin <= blk) lo = mid; else hi = mid - 1;
-    }
-    return lo;
-  }
+  __device__ int find_block(int64_t blk) const { return block_unit[blk]; }
   __device__ int find_out(int64_t g) const {
     int lo = 0, hi = count - 1;
     while (lo < hi) {
