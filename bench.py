@@ -8,6 +8,10 @@ s_k = 10 n_k = 2560 sampled fibers per mode.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--config c2|c3-bf16|c3-f16|c3-f32|c1|c4]
 
+c5 is Sub-R-RtL-HT on the FP32 18^8 tensor (balanced tree, node ranks 12,
+p = 4, w_S = min(20 n, n_notS) sampled columns per node): node sketches,
+QR + W per node, transfer tensors and the root contraction.
+
 c4 is the batching form: 512 FP32 tensors of order 3-5 (n_k in [16, 96],
 at most 2^24 entries each, ranks in [4, 16], p = 5), every mode of every
 tensor in one plan run, captured in a HIP graph and replayed.
@@ -114,6 +118,9 @@ def main():
         sys.exit(2)
     if args.config == "c4":
         bench_batch(args)
+        return
+    if args.config == "c5":
+        bench_ht(args)
         return
     import numpy as np
     import torch
@@ -339,6 +346,74 @@ def bench_batch(args):
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
                      "kernel": "batched streaming pass", "avg_ms": round(core_avg, 4),
                      "bytes_per_launch": b_core},
+    }
+    print(json.dumps(result), flush=True)
+
+
+def bench_ht(args):
+    """One step = one htucker_decompose of a resident 18^8 FP32 tensor."""
+    import numpy as np
+    import torch
+
+    import synthgen
+    from synthgen import configs
+    from paper_2603_21379_amd import binding as B
+    from paper_2603_21379_amd import tucker as T
+
+    c = configs.C5
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    t0 = time.time()
+    log(f"generating {c.name} on the host")
+    inp = synthgen.ht_tensor(c.n, c.order, c.rank, c.noise, cfg=c.cfg_id, dtype=c.dtype)
+    tr, dims = inp.tree, inp.dims
+    N = math.prod(dims)
+    ranks, ells, ws = {}, {}, {}
+    for t in range(1, tr.num_nodes):
+        nS = math.prod(dims[k] for k in tr.modes(t))
+        ells[t] = min(c.rank + c.p, nS, N // nS)
+        ranks[t] = min(c.rank, ells[t])
+        ws[t] = min(c.w_alpha * c.n, N // nS)
+    sk = synthgen.node_sketches(dims, tr, ells, ws, cfg=c.cfg_id, omega_dtype="f32")
+    X = torch.from_numpy(inp.X).to(dev)
+    del inp
+    pairs = [(sk[t], N // math.prod(dims[k] for k in tr.modes(t))) for t in range(1, tr.num_nodes)]
+    dsk = T.upload_sketches(pairs, dev, torch.float32)
+    skd = {t: dsk[t - 1] for t in range(1, tr.num_nodes)}
+    log(f"generated and uploaded in {time.time() - t0:.1f}s ({N * 4 / 1e9:.1f} GB)")
+    res = T.sub_r_rtl_ht(X, tr, ranks, skd)
+    torch.cuda.synchronize()
+    for _ in range(args.warmup):
+        T.sub_r_rtl_ht(X, tr, ranks, skd)
+    torch.cuda.synchronize()
+    B.tk_profile_read(reset=True)
+    B.tk_profile_enable(True)
+    t_start = time.perf_counter()
+    for _ in range(args.steps):
+        res = T.sub_r_rtl_ht(X, tr, ranks, skd)
+    torch.cuda.synchronize()
+    ms_per_step = (time.perf_counter() - t_start) * 1e3 / args.steps
+    B.tk_profile_enable(False)
+    root_ms, launches = B.tk_profile_read(reset=True)
+    root_avg = root_ms / max(launches, 1)
+    b_sketch = sum(ws[t] * math.prod(dims[k] for k in tr.modes(t)) for t in ws) * 4
+    b_root = N * 4
+    value = (b_sketch + b_root) / (ms_per_step * 1e-3) / 1e9
+    achieved = b_root / (root_avg * 1e-3) / 1e9
+    log(f"timed {args.steps} steps: {ms_per_step:.3f} ms/step; root pass {root_avg:.3f} ms; "
+        f"info {res.info.cpu().tolist()}")
+    result = {
+        "metric": "tensor GB/s streamed (sketch+core), frac of HBM roofline; rel err vs FP64 oracle",
+        "value": round(value, 2), "unit": "GB/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"sub-r-rtl-ht {c.name}", "n": c.n, "order": c.order,
+                   "node_rank": c.rank, "p": c.p, "w_alpha": c.w_alpha, "noise_rel": c.noise},
+        "frac_hbm_step": round(value / HBM_PEAK_GBS, 4),
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "kernel": "root contraction pass", "avg_ms": round(root_avg, 4),
+                     "bytes_per_launch": b_root},
     }
     print(json.dumps(result), flush=True)
 

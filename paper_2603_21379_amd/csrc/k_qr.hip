@@ -412,11 +412,20 @@ __global__ __launch_bounds__(256) void cholqr_small_kernel(const S b) {
 // mpart[rc][p][t] = sum_{rows in rc} Q[row][p] Y[row][t], t in column chunk cc.
 // Each thread owns a 4 x 4 register tile (p = 4 pr + i, t = 4 tc + j), so an
 // FMA costs half an LDS read instead of two.
+// Blocks form one flat list over the matrices (qty_begin: prefix of nrc * ncc),
+// so a batch of very different shapes launches no empty blocks.
 template <typename TY, typename S>
-__global__ __launch_bounds__(256) void qty_partial_kernel(const S b) {
-  const QRMat& M = b.get(blockIdx.z);
-  const int rc = blockIdx.x, cc = blockIdx.y;
-  if (rc >= M.nrc || cc >= M.ncc) return;
+__global__ __launch_bounds__(256) void qty_partial_kernel(const S b, int count) {
+  const int64_t blk = blockIdx.x;
+  int lo = 0, hi = count - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (b.get(mid).qty_begin <= blk) lo = mid; else hi = mid - 1;
+  }
+  const QRMat& M = b.get(lo);
+  const int64_t lb = blk - M.qty_begin;
+  const int rc = (int)(lb / M.ncc), cc = (int)(lb - (int64_t)rc * M.ncc);
+  if (rc >= M.nrc) return;
   __shared__ double sQ[64][kMaxEll + 1];
   __shared__ double sY[64][kQRColChunk + 1];
   const int ell = M.ell, tid = threadIdx.x;
@@ -791,13 +800,15 @@ hipError_t cholqr_impl(const S& src, const QRMat* host, int count, hipStream_t s
 template <typename S>
 hipError_t wstep_impl(const S& src, const QRMat* host, int count, int ydtype, int udtype, hipStream_t st) {
   if (count == 0) return hipSuccess;
-  const int nrc = max_field(host, count, 0), ncc = max_field(host, count, 1), nrb = max_field(host, count, 2);
-  const dim3 gq(nrc, ncc, count);
+  const int ncc = max_field(host, count, 1), nrb = max_field(host, count, 2);
+  int64_t qty_blocks = 0;
+  for (int i = 0; i < count; ++i) qty_blocks = host[i].qty_begin + (int64_t)host[i].nrc * host[i].ncc;
+  const dim3 gq((unsigned)qty_blocks);
   switch (ydtype) {
-    case TK_F64: hipLaunchKernelGGL((qty_partial_kernel<double, S>), gq, dim3(256), 0, st, src); break;
-    case TK_F32: hipLaunchKernelGGL((qty_partial_kernel<float, S>), gq, dim3(256), 0, st, src); break;
-    case TK_BF16: hipLaunchKernelGGL((qty_partial_kernel<bf16, S>), gq, dim3(256), 0, st, src); break;
-    case TK_F16: hipLaunchKernelGGL((qty_partial_kernel<f16, S>), gq, dim3(256), 0, st, src); break;
+    case TK_F64: hipLaunchKernelGGL((qty_partial_kernel<double, S>), gq, dim3(256), 0, st, src, count); break;
+    case TK_F32: hipLaunchKernelGGL((qty_partial_kernel<float, S>), gq, dim3(256), 0, st, src, count); break;
+    case TK_BF16: hipLaunchKernelGGL((qty_partial_kernel<bf16, S>), gq, dim3(256), 0, st, src, count); break;
+    case TK_F16: hipLaunchKernelGGL((qty_partial_kernel<f16, S>), gq, dim3(256), 0, st, src, count); break;
     default: return hipErrorInvalidValue;
   }
   hipLaunchKernelGGL(mgram_kernel<S>, dim3(ncc, count), dim3(256), 0, st, src);

@@ -20,9 +20,11 @@ __global__ __launch_bounds__(256) void sketch_gather_kernel(const S b) {
   __shared__ int64_t sFib[kSketchCols];   // offset of element 0 of each fiber, or -1
   const int64_t blk = blockIdx.x;
   const SketchUnit& U = b.get(b.find_block(blk));
+  // fiber chunks vary fastest: blocks running together share rows, which
+  // keeps the pages they touch few when fibers are strided (B > 1)
   const int64_t lb = blk - U.block_begin;
-  const int64_t chunk = lb / U.rowblocks;
-  const int64_t rb = lb - chunk * U.rowblocks;
+  const int64_t rb = lb / U.nchunks;
+  const int64_t chunk = lb - rb * U.nchunks;
   const int64_t i0 = rb * kSketchRows, t0 = chunk * kSketchCols;
   const TX* __restrict__ X = static_cast<const TX*>(U.X);
   TX* __restrict__ Y = static_cast<TX*>(U.Y);

@@ -151,9 +151,12 @@ tk_status run_qr(std::vector<QRMat>& mats, int ydtype, int udtype, bool wstep, h
   for (size_t g = 0; g < mats.size(); g += kQRMaxBatch) {
     QRBatch b{};
     b.count = (int32_t)std::min<size_t>(kQRMaxBatch, mats.size() - g);
+    int64_t qb = 0;
     for (int i = 0; i < b.count; ++i) {
       b.m[i] = mats[g + i];
       b.m[i].udtype = udtype;
+      b.m[i].qty_begin = qb;
+      qb += (int64_t)b.m[i].nrc * b.m[i].ncc;
     }
     TK_HIP(launch_cholqr(b, st));
     if (wstep) TK_HIP(launch_wstep(b, ydtype, udtype, st));
@@ -703,6 +706,13 @@ tk_status plan_batch(Workspace& ws, int count, const tk_tensor* X, const int32_t
     P.tensors.push_back(bt);
     m0 += d;
   }
+  {
+    int64_t qb = 0;
+    for (auto& q : P.qr) {
+      q.qty_begin = qb;
+      qb += (int64_t)q.nrc * q.ncc;
+    }
+  }
   P.step_units.assign(P.steps.size(), 0);
   P.step_qmax.assign(P.steps.size(), 1);
   for (size_t s = 0; s < P.steps.size(); ++s)
@@ -1188,9 +1198,12 @@ tk_status htucker_decompose(const tk_tensor* X, const tk_tree* tree, const int32
   }
   // root: X viewed as (n_l, n_r): B_R = U_l^T X U_r
   const int L = tree->left[0], R = tree->right[0];
-  double* t1 = w.take<double>((size_t)nS[L] * rank[R]);
-  double* mt_root = w.take<double>((size_t)std::max(mode_product_scratch(rank[R], nS[R]),
-                                                    mode_product_scratch(rank[L], nS[L])));
+  const bool root_fused = root_pass_supported(X->dtype, nS[L], nS[R], rank[L], rank[R]);
+  double* t1 = root_fused ? nullptr : w.take<double>((size_t)nS[L] * rank[R]);
+  double* mt_root = root_fused ? nullptr
+                               : w.take<double>((size_t)std::max(mode_product_scratch(rank[R], nS[R]),
+                                                                 mode_product_scratch(rank[L], nS[L])));
+  double* root_part = root_fused ? w.take<double>((size_t)root_pass_blocks(nS[L], nS[R]) * 256) : nullptr;
   if (!ws) {
     *ws_bytes = w.off;
     return TK_OK;
@@ -1202,7 +1215,19 @@ tk_status htucker_decompose(const tk_tensor* X, const tk_tree* tree, const int32
   TK_HIP(launch_sketch(X->dtype, sb, st));
   if (tk_status s = run_qr(mats, X->dtype, fdt, true, st)) return s;
   for (const Transfer& x : tr) TK_HIP(launch_transfer(x, fdt, st));
-  {
+  if (root_fused) {
+    RootPass rp{};
+    rp.X = static_cast<const float*>(X->data);
+    rp.UL = static_cast<const double*>(U[L]);
+    rp.UR = static_cast<const double*>(U[R]);
+    rp.partials = root_part;
+    rp.out = static_cast<double*>(B[0]);
+    rp.nL = nS[L];
+    rp.nR = nS[R];
+    rp.rL = rank[L];
+    rp.rR = rank[R];
+    TK_HIP(launch_root_pass(rp, st));
+  } else {
     ModeProduct mp{};
     mp.in = X->data;
     mp.A = nS[L];

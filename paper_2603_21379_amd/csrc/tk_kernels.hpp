@@ -83,6 +83,7 @@ struct QRMat {
   int64_t m, s;
   int32_t ell, r;
   int32_t nrc, ncc, nrb; // row chunks (Gram / Q^T Y), column chunks, row blocks (apply)
+  int64_t qty_begin;     // first block of this matrix in the Q^T Y launch
   int32_t small;         // m x ell (and m x r) small enough for the one-workgroup kernels
   int32_t udtype;        // TK_F64 or TK_F32
   int32_t pad2;
@@ -273,6 +274,24 @@ struct Transfer {
   int32_t pad;
 };
 hipError_t launch_transfer(const Transfer& t, int f_dt, hipStream_t st);
+
+// ---------------------------------------------------------------- H-Tucker root pass
+// B_R[j][k] = sum_{a,b} UL[a][j] X[a][b] UR[b][k] for an FP32 X (nL x nR), FP64 bases.
+struct RootPass {
+  const float* X;
+  const double* UL;     // nL x rL
+  const double* UR;     // nR x rR
+  double* partials;     // [root_pass_blocks(nL, nR)][16][16]
+  double* out;          // rL x rR
+  int64_t nL, nR;
+  int32_t rL, rR;
+  int32_t nblocks;      // set by the launcher
+  int32_t qsplit;       // column splits per row block, set by the launcher
+};
+bool root_pass_supported(int dtype, int64_t nL, int64_t nR, int rL, int rR);
+int64_t root_pass_blocks(int64_t nL, int64_t nR);
+// brackets the streaming kernel with the profiler's events
+hipError_t launch_root_pass(const RootPass& p, hipStream_t st);
 
 // ---------------------------------------------------------------- unfolded products (VJPs)
 // out[i][a] (+)= sum_{p,q} A[p][i][q] B[p][a][q]: A is (pre, n, post), B is

@@ -23,7 +23,7 @@ def _setup(n, order, rank, p, walpha, noise, dtype, cfg):
         nS = math.prod(dims[k] for k in tr.modes(t))
         ells[t] = min(rank + p, nS, N // nS)
         ranks[t] = min(rank, ells[t])
-        ws[t] = min(walpha * nS, N // nS)
+        ws[t] = min(walpha * n, N // nS)
     fdt = synthgen.factor_dtype(dtype)
     sk = synthgen.node_sketches(dims, tr, ells, ws, cfg=cfg, omega_dtype=fdt)
     return inp, ranks, sk
