@@ -20,7 +20,7 @@ theory: the paper gives no bound for it).
 """
 from .tensor import unfold, fold, unfold_set, ttm, multi_ttm  # noqa: F401
 from .tucker import (gather_fibers, range_sketch, orth, w_step, sub_r_hosvd,  # noqa: F401
-                     core, core_streamed, reconstruct, rel_error, mode_errors,
+                     core, core_streamed, core_chunked, reconstruct, rel_error, mode_errors,
                      projector_distance, canonical_signs)
 from .htucker import (sub_r_rtl_ht, transfer_tensor, root_transfer, ht_full, ht_bases,  # noqa: F401
                       ht_rel_error, gather_node, kron_cols)

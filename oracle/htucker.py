@@ -27,13 +27,15 @@ def _node_dims(dims, tree, t):
     return A, nS, B
 
 
-def gather_node(X: np.ndarray, tree, t: int, idx: np.ndarray) -> np.ndarray:
+def gather_node(X: np.ndarray, tree, t: int, idx: np.ndarray, to64=None) -> np.ndarray:
     """Y_S = X^(S) E_S for a node S of contiguous modes: column j of X^(S) is
-    X[a, :, b] of X viewed as (n_before, n_S, n_after), (a, b) = divmod(j, n_after)."""
+    X[a, :, b] of X viewed as (n_before, n_S, n_after), (a, b) = divmod(j, n_after).
+    The sampled fibers are taken first and then upcast exactly (`to64`)."""
+    to64 = to64 or (lambda v: np.asarray(v, dtype=np.float64))
     A, nS, B = _node_dims(X.shape, tree, t)
-    X3 = np.asarray(X, dtype=np.float64).reshape(A, nS, B)
+    X3 = X.reshape(A, nS, B)
     a, b = np.divmod(np.asarray(idx, dtype=np.int64), B)
-    return X3[a, :, b].T.copy()
+    return to64(X3[a, :, b].T.copy())
 
 
 def kron_cols(V: np.ndarray, W: np.ndarray) -> np.ndarray:

@@ -100,6 +100,22 @@ def core_streamed(X: np.ndarray, Fs, to64=None, slab: int = 1) -> np.ndarray:
     return G
 
 
+def core_chunked(X: np.ndarray, Fs, to64=None, rows: int = 1 << 16) -> np.ndarray:
+    """Same core, contracting the last mode first: X viewed as the
+    (N / n_d) x n_d matrix times F_d (a matrix product over chunks of rows,
+    each upcast exactly with `to64`), then the other modes of the much
+    smaller result.  For tensors whose FP64 copy does not fit in memory."""
+    to64 = to64 or (lambda a: np.asarray(a, dtype=np.float64))
+    dims = X.shape
+    Fd = np.asarray(Fs[-1], dtype=np.float64)
+    M = X.reshape(-1, dims[-1])
+    T = np.empty((M.shape[0], Fd.shape[1]))
+    for r0 in range(0, M.shape[0], rows):
+        T[r0:r0 + rows] = to64(M[r0:r0 + rows]) @ Fd
+    T = T.reshape(dims[:-1] + (Fd.shape[1],))
+    return multi_ttm(T, [F.T for F in Fs[:-1]] + [np.eye(Fd.shape[1])])
+
+
 def reconstruct(G: np.ndarray, Fs) -> np.ndarray:
     """X_hat = (F_1, .., F_d) G (Tucker format, Section 3)."""
     return multi_ttm(G, Fs)
@@ -133,6 +149,15 @@ def mode_errors(X: np.ndarray, Fs):
 
 
 def projector_distance(F1: np.ndarray, F2: np.ndarray) -> float:
-    """||F1 F1^T - F2 F2^T||_F / sqrt(2 c): sign- and rotation-invariant."""
-    P = F1 @ F1.T - F2 @ F2.T
-    return float(np.linalg.norm(P) / math.sqrt(2 * F1.shape[1]))
+    """||F1 F1^T - F2 F2^T||_F / sqrt(2 c): sign- and rotation-invariant.
+
+    For n > 8192 rows the n x n difference is not formed: for bases with
+    orthonormal columns and the same c, ||F1 F1^T - F2 F2^T||_F^2 =
+    2 ||F1 - F2 (F2^T F1)||_F^2 (twice the sum of the squared sines of the
+    principal angles), a residual that is computed directly."""
+    n, c = F1.shape
+    if n <= 8192:
+        P = F1 @ F1.T - F2 @ F2.T
+        return float(np.linalg.norm(P) / math.sqrt(2 * c))
+    R = F1 - F2 @ (F2.T @ F1)
+    return float(np.linalg.norm(R) / math.sqrt(c))

@@ -247,3 +247,29 @@ def test_projector_distance_invariances():
     assert oracle.projector_distance(Q, -Q) < 1e-14
     Q2, _ = np.linalg.qr(rng.standard_normal((20, 4)))
     assert oracle.projector_distance(Q, Q2) > 0.1
+
+
+def test_chunked_core_matches_plain_core():
+    """The last-mode-first chunked core (row chunks not dividing the rows,
+    one chunk, order 3 and 5) equals the plain multi-TTM core."""
+    rng = np.random.default_rng(31)
+    for dims, cols, rows in [((7, 9, 11), (3, 4, 5), 5), ((4, 5, 3, 6, 8), (2, 3, 3, 4, 5), 17),
+                             ((6, 5, 4), (2, 2, 2), 1 << 20)]:
+        X = rng.standard_normal(dims).astype(np.float32)
+        Fs = [rng.standard_normal((n, c)) for n, c in zip(dims, cols)]
+        ref = oracle.core(X.astype(np.float64), Fs)
+        got = oracle.core_chunked(X, Fs, rows=rows)
+        np.testing.assert_allclose(got, ref, rtol=1e-12, atol=1e-12 * np.abs(ref).max())
+
+
+def test_projector_distance_large_n_form_matches_dense():
+    """The principal-angle form used above 8192 rows equals the dense
+    projector difference (orthonormal bases of equal dimension)."""
+    rng = np.random.default_rng(32)
+    n, c = 8200, 5
+    A = np.linalg.qr(rng.standard_normal((n, c)))[0]
+    for eps in (1e-3, 1e-7):
+        Bm = np.linalg.qr(A + eps * rng.standard_normal((n, c)))[0]
+        P = A @ A.T - Bm @ Bm.T
+        dense = np.linalg.norm(P) / math.sqrt(2 * c)
+        assert abs(oracle.projector_distance(A, Bm) - dense) <= 1e-6 * dense
