@@ -56,21 +56,36 @@ def parse():
 # HBM bytes per launch of the streaming pass, from rocprofv3 FETCH_SIZE and
 # WRITE_SIZE runs scaled by a plain copy of known size; valid only for the
 # kernel source it was taken on
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "core_stream_f32_256x4_traffic.txt")
-KERNEL_SRC = os.path.join(ROOT, "paper_2603_21379_amd", "csrc", "k_core_f32.hip")
+# HBM traffic summaries of the FP32 streaming pass, one per kernel form: the
+# BF16-piece form (default) and the FP32-MFMA form (TKMI_CORE_X6=0)
+TRAFFIC = {
+    "x6": (os.path.join(ROOT, "profiles", "core_stream_x6_256x4_traffic.txt"),
+           os.path.join(ROOT, "paper_2603_21379_amd", "csrc", "k_core_x6.hip")),
+    "f32": (os.path.join(ROOT, "profiles", "core_stream_f32_256x4_traffic.txt"),
+            os.path.join(ROOT, "paper_2603_21379_amd", "csrc", "k_core_f32.hip")),
+}
+
+
+def core_form():
+    e = os.environ.get("TKMI_CORE_X6")
+    return "f32" if (e is not None and e.strip() == "0") else "x6"
 
 
 def measured_traffic(workload_name):
+    """HBM bytes per launch from the committed counter summary of the kernel
+    form that runs, or None when the summary is missing or the kernel source
+    changed since the counters were taken."""
     import hashlib
-    if not os.path.exists(TRAFFIC_FILE):
+    path, src = TRAFFIC[core_form()]
+    if not os.path.exists(path):
         return None
     kv = {}
-    with open(TRAFFIC_FILE) as f:
+    with open(path) as f:
         for line in f:
             if ":" in line and not line.startswith("#"):
                 k, v = line.split(":", 1)
                 kv[k.strip()] = v.strip()
-    with open(KERNEL_SRC, "rb") as f:
+    with open(src, "rb") as f:
         sha = hashlib.sha256(f.read()).hexdigest()
     if kv.get("kernel_source_sha256") != sha or kv.get("workload") != workload_name:
         return None

@@ -88,15 +88,18 @@ __global__ __launch_bounds__(256, 2) void batch_slab_kernel(const BatchSlab bs) 
       const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
           const_cast<char*>(Xb + (live ? a : 0) * (int64_t)slab_bytes), (short)0, live ? (int)slab_bytes : 0,
           kRsrcWord3);
+      // the same TG NK loads in every unit (tiles past n_T and chunks past
+      // n_K read zero from past the range): the waits before the multiplies
+      // then count loads instead of waiting for all of them
 #pragma unroll
       for (int tt = 0; tt < TG; ++tt) {
         const int t = grp * TG + tt;
-        if (t >= nT) continue;
         const uint32_t off = lane_off + t * tile_bytes;
 #pragma unroll
-        for (int kc = 0; kc < NK; ++kc)
-          if (kc < nK)
-            buf[tt][kc] = __builtin_bit_cast(uintx4, __builtin_amdgcn_raw_buffer_load_b128(rs, off + kc * 64, 0, 2));
+        for (int kc = 0; kc < NK; ++kc) {
+          const uint32_t o = (t < nT && kc < nK) ? off + kc * 64 : 0x80000000u;
+          buf[tt][kc] = __builtin_bit_cast(uintx4, __builtin_amdgcn_raw_buffer_load_b128(rs, o, 0, 2));
+        }
       }
     };
     floatx4 tacc = floatx4{};
@@ -154,8 +157,11 @@ __global__ __launch_bounds__(256, 2) void batch_slab_kernel(const BatchSlab bs) 
       ug[s] = lg;
       load_unit(la, lg, buf[s]);
     }
-    bool done = false;
-    while (!done) {
+    // full groups of NBUF units with no exit test inside (one there would
+    // leave loads of skipped units pending at the loop head and force a wait
+    // for every load in flight); the tail multiplies the units in flight
+    int left = (int)(ch.a1 - ch.a0) * nG;
+    for (; left >= NBUF; left -= NBUF) {
 #pragma unroll
       for (int s = 0; s < NBUF; ++s) {
         const int lb = (s + NBUF - 1) % NBUF;
@@ -164,13 +170,12 @@ __global__ __launch_bounds__(256, 2) void batch_slab_kernel(const BatchSlab bs) 
         ug[lb] = lg;
         load_unit(la, lg, buf[lb]);
         __builtin_amdgcn_sched_barrier(0);
-        if (ua[s] < 0) {
-          done = true;
-          break;
-        }
         compute_unit(ua[s], ug[s], buf[s]);
       }
     }
+#pragma unroll
+    for (int s = 0; s < NBUF - 1; ++s)
+      if (s < left) compute_unit(ua[s], ug[s], buf[s]);
   }
 }
 

@@ -164,6 +164,12 @@ __global__ __launch_bounds__(256, MINB) void fused2_f32_kernel(const CoreFused2 
 
   // Step t multiplies buffer t % NBUF after issuing the load of step
   // t + NBUF - 1 into buffer (t - 1) % NBUF, which step t - 1 has finished.
+  // The wave's batches (its slabs gwave, gwave + nwaves, ... times nH nB) run
+  // in full groups of NBUF steps with no exit test inside (an exit test there
+  // would leave loads of skipped steps pending at the loop head and force a
+  // wait for every load in flight); the tail multiplies the batches already
+  // in flight.
+  const int steps = ((A32 - 1 - gwave) / nwaves + 1) * nH * nB;
   floatx4 buf[NBUF][KB];
   Cursor cc[NBUF];
   cc[0] = Cursor{gwave, 0, 0};
@@ -175,7 +181,8 @@ __global__ __launch_bounds__(256, MINB) void fused2_f32_kernel(const CoreFused2 
     cc[s] = last;
     load_batch(cc[s], buf[s]);
   }
-  while (true) {
+  int left = steps;
+  for (; left >= NBUF; left -= NBUF) {
 #pragma unroll
     for (int s = 0; s < NBUF; ++s) {
       const int lb = (s + NBUF - 1) % NBUF;
@@ -185,10 +192,12 @@ __global__ __launch_bounds__(256, MINB) void fused2_f32_kernel(const CoreFused2 
       // keep these loads ahead of the multiplies below: without the barrier
       // the scheduler sinks them past the MFMAs and nothing is in flight
       __builtin_amdgcn_sched_barrier(0);
-      if (cc[s].slab < 0) return;
       compute(cc[s], buf[s]);
     }
   }
+#pragma unroll
+  for (int s = 0; s < NBUF - 1; ++s)
+    if (s < left) compute(cc[s], buf[s]);
 }
 
 }  // namespace

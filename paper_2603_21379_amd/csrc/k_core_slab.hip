@@ -213,16 +213,18 @@ __global__ __launch_bounds__(256, 2) void core_slab_kernel(const CoreSlab p) {
     const int64_t slab = live ? (int64_t)item * nH + h : 0;
     const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
         const_cast<char*>(Xb + slab * slab_bytes), (short)0, live ? (int)slab_bytes : 0, kRsrcWord3);
+    // every unit issues the same TG NK loads (tiles past n_T and chunks past
+    // n_K read zero from past the range), so the waits before the multiplies
+    // count loads instead of waiting for all of them
 #pragma unroll
     for (int tt = 0; tt < TG; ++tt) {
       const int t = grp * TG + tt;
-      if (t >= nT) continue;
       const uint32_t off = lane_off + t * tile_bytes;
 #pragma unroll
-      for (int kc = 0; kc < NK; ++kc)
-        if (kc < nK)
-          buf[tt][kc] = __builtin_bit_cast(
-              uintx4, __builtin_amdgcn_raw_buffer_load_b128(rs, off + kc * kChunk * (int)sizeof(TX), 0, 2));
+      for (int kc = 0; kc < NK; ++kc) {
+        const uint32_t o = (t < nT && kc < nK) ? off + kc * kChunk * (uint32_t)sizeof(TX) : 0x80000000u;
+        buf[tt][kc] = __builtin_bit_cast(uintx4, __builtin_amdgcn_raw_buffer_load_b128(rs, o, 0, 2));
+      }
     }
   };
 
@@ -347,7 +349,12 @@ __global__ __launch_bounds__(256, 2) void core_slab_kernel(const CoreSlab p) {
     cg[s] = lg;
     load_unit(li, lh, lg, buf[s]);
   }
-  while (true) {
+  // the wave's units (items gwave, gwave + nwaves, ... times nH nG) run in
+  // full groups of NBUF with no exit test inside (one there would leave the
+  // loads of skipped units pending at the loop head and force a wait for
+  // every load in flight); the tail multiplies the units already in flight
+  int left = ((items - 1 - gwave) / nwaves + 1) * nH * nG;
+  for (; left >= NBUF; left -= NBUF) {
 #pragma unroll
     for (int s = 0; s < NBUF; ++s) {
       const int lb = (s + NBUF - 1) % NBUF;
@@ -357,10 +364,12 @@ __global__ __launch_bounds__(256, 2) void core_slab_kernel(const CoreSlab p) {
       cg[lb] = lg;
       load_unit(li, lh, lg, buf[lb]);
       __builtin_amdgcn_sched_barrier(0);
-      if (ci[s] < 0) return;
       compute_unit(ci[s], chh[s], cg[s], buf[s]);
     }
   }
+#pragma unroll
+  for (int s = 0; s < NBUF - 1; ++s)
+    if (s < left) compute_unit(ci[s], chh[s], cg[s], buf[s]);
 }
 
 template <typename TX, int NK, int NT, int TG, bool H3, int NBUF>

@@ -256,8 +256,9 @@ tk_status run_core(const void* X, int xdt, int order, const int64_t* dims,
     f.nJ = (int32_t)dims[order - 1];
     f.cI = cols[order - 2];
     f.cJ = cols[order - 1];
+    const bool x6 = fused2x6_enabled() && fused2x6_supported(xdt, order, dims, cols);
     TK_HIP(profile_begin(st));
-    TK_HIP(launch_fused2_f32(f, st));
+    TK_HIP(x6 ? launch_fused2x6(f, st) : launch_fused2_f32(f, st));
     TK_HIP(profile_end(st));
   } else if (p.kind == kCoreSlab2 || p.kind == kCoreSlab3) {
     // two or three trailing modes in one MFMA pass over X (16x16 tiles)
