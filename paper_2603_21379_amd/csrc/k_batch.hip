@@ -40,7 +40,7 @@ __global__ __launch_bounds__(256, 2) void batch_slab_kernel(const BatchSlab bs) 
   float* sA = lds + wv * (NT * 256);   // this wave's F_I^T table [t][v][lane]
   const int gwave = __builtin_amdgcn_readfirstlane((int)blockIdx.x * kWaves + wv);
   if (gwave >= bs.nwaves) return;
-  const int c_begin = bs.wave_begin[gwave], c_end = bs.wave_begin[gwave + 1];
+  const int c_begin = wave_uniform(bs.wave_begin[gwave]), c_end = wave_uniform(bs.wave_begin[gwave + 1]);
 
   int cur_tensor = -1;
   float fj[NK][4];
@@ -50,11 +50,11 @@ __global__ __launch_bounds__(256, 2) void batch_slab_kernel(const BatchSlab bs) 
   uint32_t lane_off = 0, tile_bytes = 0, slab_bytes = 0;
 
   for (int ci = c_begin; ci < c_end; ++ci) {
-    const BatchChunk ch = bs.chunks[bs.wave_chunks[ci]];
-    const int tid = __builtin_amdgcn_readfirstlane(ch.tensor);
+    const BatchChunk ch = wave_uniform(bs.chunks[wave_uniform(bs.wave_chunks[ci])]);
+    const int tid = ch.tensor;
     if (tid != cur_tensor) {
       cur_tensor = tid;
-      td = bs.tensors[tid];
+      td = wave_uniform(bs.tensors[tid]);
       nT = (td.nI + 15) / 16;
       nK = (td.nJ + 15) / 16;
 #pragma unroll
@@ -129,7 +129,7 @@ __global__ __launch_bounds__(256, 2) void batch_slab_kernel(const BatchSlab bs) 
       for (int v = 0; v < 4; ++v) {
         const int jp = 4 * g + v;
         const uint32_t off = (jp < td.cI && l16 < td.cJ) ? (uint32_t)((jp * td.cJ + l16) * 4) : 0x80000000u;
-        __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(tacc[v]), ro, off, 0, 0);
+        __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(tacc[v]), ro, off, 0, kOutStorePolicy);
       }
       tacc = floatx4{};
     };
@@ -196,7 +196,7 @@ __global__ __launch_bounds__(256) void batch_mode_kernel(const BatchMode bm) {
     const int mid = (lo + hi + 1) >> 1;
     if (bm.descs[mid].unit_begin <= u0) lo = mid; else hi = mid - 1;
   }
-  const BatchModeDesc m = bm.descs[lo];
+  const BatchModeDesc m = wave_uniform(bm.descs[wave_uniform(lo)]);
   const int Qp = (int)((m.Q + 2 * kKB - 1) / (2 * kKB)) * 2 * kKB;
   for (int e = threadIdx.x; e < Qp * 32; e += blockDim.x) {
     const int q = e >> 5, p = e & 31;
@@ -206,7 +206,7 @@ __global__ __launch_bounds__(256) void batch_mode_kernel(const BatchMode bm) {
 
   const int lane = threadIdx.x & 63, kh = lane >> 5, l32 = lane & 31;
   const int64_t nBb = (m.B + kCols - 1) / kCols;
-  const int64_t unit = u0 + (threadIdx.x >> 6) - m.unit_begin;
+  const int64_t unit = wave_uniform(u0 + (threadIdx.x >> 6) - m.unit_begin);
   if (unit >= m.A * nBb) return;  // no barrier follows
   const int64_t a = unit / nBb;
   const int64_t b0 = (unit - a * nBb) * kCols;
@@ -219,14 +219,15 @@ __global__ __launch_bounds__(256) void batch_mode_kernel(const BatchMode bm) {
   floatx16 acc[4];
 #pragma unroll
   for (int c = 0; c < 4; ++c) acc[c] = floatx16{};
-  for (int q0 = 0; q0 < Qp; q0 += 2 * kKB) {
-    floatx4 buf[kKB];
+  auto load = [&](int q0, floatx4 (&buf)[kKB]) {
 #pragma unroll
     for (int u = 0; u < kKB; ++u) {
       const int q = q0 + 2 * u + kh;
       const uint32_t off = (colok && q < m.Q) ? (uint32_t)q * rowb + (uint32_t)(b * 4) : 0x80000000u;
       buf[u] = __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, 0);
     }
+  };
+  auto compute = [&](int q0, const floatx4 (&buf)[kKB]) {
     const float* f = sF + (q0 + kh) * 32 + l32;
 #pragma unroll
     for (int u = 0; u < kKB; ++u) {
@@ -234,7 +235,22 @@ __global__ __launch_bounds__(256) void batch_mode_kernel(const BatchMode bm) {
 #pragma unroll
       for (int c = 0; c < 4; ++c) acc[c] = mfma32(fv, buf[u][c], acc[c]);
     }
+  };
+  // double buffered as the single-tensor mode contraction (loads past Q read
+  // zero, so every step issues the next batch before multiplying)
+  const int nb = Qp / (2 * kKB);
+  floatx4 bufA[kKB], bufB[kKB];
+  load(0, bufA);
+  int bq = 0;
+  for (; bq + 2 <= nb; bq += 2) {
+    load((bq + 1) * 2 * kKB, bufB);
+    __builtin_amdgcn_sched_barrier(0);
+    compute(bq * 2 * kKB, bufA);
+    load((bq + 2) * 2 * kKB, bufA);
+    __builtin_amdgcn_sched_barrier(0);
+    compute((bq + 1) * 2 * kKB, bufB);
   }
+  if (bq < nb) compute(bq * 2 * kKB, bufA);
   if (!colok) return;
   float* out = m.out + a * (int64_t)m.P * m.B;
   const int ncol = (int)min<int64_t>(4, m.B - b);

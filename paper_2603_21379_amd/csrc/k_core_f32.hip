@@ -151,11 +151,13 @@ __global__ __launch_bounds__(256, MINB) void fused2_f32_kernel(const CoreFused2 
       }
       if (c.h == nH - 1) {
         // slab complete: T[a][j][j'] with j' = l32, j = 8 (v/4) + 4 kh + v%4
-        float* T = p.T + (int64_t)c.slab * p.cI * p.cJ;
+        const __amdgpu_buffer_rsrc_t ro = __builtin_amdgcn_make_buffer_rsrc(
+            p.T + (int64_t)c.slab * p.cI * p.cJ, (short)0, p.cI * p.cJ * 4, kRsrcWord3);
 #pragma unroll
         for (int v = 0; v < 16; ++v) {
           const int j = 8 * (v >> 2) + 4 * kh + (v & 3);
-          if (j < p.cI && l32 < p.cJ) T[j * p.cJ + l32] = tacc[v];
+          const uint32_t off = (j < p.cI && l32 < p.cJ) ? (uint32_t)((j * p.cJ + l32) * 4) : 0x80000000u;
+          __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(tacc[v]), ro, off, 0, kOutStorePolicy);
         }
         tacc = floatx16{};
       }

@@ -300,7 +300,8 @@ __global__ __launch_bounds__(256, 2) void core_slab_kernel(const CoreSlab p) {
         for (int r = 0; r < 4; ++r) acc3[4 * q4 + r] += w[r] * tacc;
       }
       if (h == nH - 1) {
-        const int cIJ = p.cI * p.cJ;
+        // uniform: the plane stride is the scalar offset of the stores
+        const int cIJ = __builtin_amdgcn_readfirstlane(p.cI * p.cJ);
         const __amdgpu_buffer_rsrc_t ro = __builtin_amdgcn_make_buffer_rsrc(
             p.T + (int64_t)item * p.cH * cIJ, (short)0, p.cH * cIJ * 4, kRsrcWord3);
 #pragma unroll
@@ -308,7 +309,7 @@ __global__ __launch_bounds__(256, 2) void core_slab_kernel(const CoreSlab p) {
           if (q < p.cH) {
 #pragma unroll
             for (int v = 0; v < 4; ++v)
-              __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(acc3[q][v]), ro, off[v], q * cIJ * 4, 0);
+              __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(acc3[q][v]), ro, off[v], q * cIJ * 4, kOutStorePolicy);
           }
           acc3[q] = floatx4{};
         }
@@ -317,7 +318,7 @@ __global__ __launch_bounds__(256, 2) void core_slab_kernel(const CoreSlab p) {
       const __amdgpu_buffer_rsrc_t ro = __builtin_amdgcn_make_buffer_rsrc(
           p.T + (int64_t)item * p.cI * p.cJ, (short)0, p.cI * p.cJ * 4, kRsrcWord3);
 #pragma unroll
-      for (int v = 0; v < 4; ++v) __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(tacc[v]), ro, off[v], 0, 0);
+      for (int v = 0; v < 4; ++v) __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(tacc[v]), ro, off[v], 0, kOutStorePolicy);
     }
     tacc = floatx4{};
   };

@@ -199,7 +199,7 @@ __global__ __launch_bounds__(256, 2) void fused2x6_kernel(const CoreFused2 p) {
     for (int v = 0; v < 16; ++v) {
       const int j = 8 * (v >> 2) + 4 * kh + (v & 3);
       const uint32_t off = (j < p.cI && l32 < p.cJ) ? (uint32_t)((j * p.cJ + l32) * 4) : 0x80000000u;
-      __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(tacc[v]), ro, off, 0, 0);
+      __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(tacc[v]), ro, off, 0, kOutStorePolicy);
     }
     tacc = floatx16{};
   };

@@ -41,7 +41,7 @@ __global__ __launch_bounds__(256) void mode_mfma_f32_kernel(const ModeMfma m) {
 
   const int lane = threadIdx.x & 63, kh = lane >> 5, l32 = lane & 31;
   const int64_t nBb = (m.B + kCols - 1) / kCols;
-  const int64_t unit = (int64_t)blockIdx.x * kWaves + (threadIdx.x >> 6);
+  const int64_t unit = wave_uniform((int64_t)blockIdx.x * kWaves + (threadIdx.x >> 6));
   if (unit >= m.A * nBb) return;  // no barrier follows
   const int64_t a = unit / nBb;
   const int64_t b0 = (unit - a * nBb) * kCols;
@@ -74,18 +74,22 @@ __global__ __launch_bounds__(256) void mode_mfma_f32_kernel(const ModeMfma m) {
       acc[3] = mfma32(fv, buf[u][3], acc[3]);
     }
   };
+  // batches of kKB row pairs, double buffered: every step issues the next
+  // batch's loads (past Q they read zero) before multiplying the current one,
+  // so the waits count loads and one batch stays in flight
+  const int nb = Qp / (2 * kKB);
   floatx4 bufA[kKB], bufB[kKB];
   load(0, bufA);
-  for (int q0 = 0; q0 < Qp; q0 += 4 * kKB) {
-    const bool second = q0 + 2 * kKB < Qp;
-    if (second) load(q0 + 2 * kKB, bufB);
+  int bq = 0;
+  for (; bq + 2 <= nb; bq += 2) {
+    load((bq + 1) * 2 * kKB, bufB);
     __builtin_amdgcn_sched_barrier(0);
-    compute(q0, bufA);
-    if (!second) break;
-    if (q0 + 4 * kKB < Qp) load(q0 + 4 * kKB, bufA);
+    compute(bq * 2 * kKB, bufA);
+    load((bq + 2) * 2 * kKB, bufA);
     __builtin_amdgcn_sched_barrier(0);
-    compute(q0 + 2 * kKB, bufB);
+    compute((bq + 1) * 2 * kKB, bufB);
   }
+  if (bq < nb) compute(bq * 2 * kKB, bufA);
   // acc[c] register v: p = 8 (v/4) + 4 kh + v%4, column b + c
   TOut* out = static_cast<TOut*>(m.out) + a * (int64_t)m.P * m.B;
   if (!colok) return;

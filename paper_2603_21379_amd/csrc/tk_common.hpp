@@ -42,6 +42,28 @@ inline size_t dtype_size(int dt) {
   }
 }
 
+// A value every lane of a wave holds (read from one address), passed word by
+// word through v_readfirstlane so the compiler keeps it in scalar registers.
+// Buffer descriptors and scalar offsets built from it then stay uniform;
+// otherwise every buffer access is wrapped in a loop over distinct values.
+template <typename T>
+__device__ __forceinline__ T wave_uniform(const T& v) {
+  static_assert(sizeof(T) % 4 == 0, "word-sized fields only");
+  T out;
+  const int* src = reinterpret_cast<const int*>(&v);
+  int* dst = reinterpret_cast<int*>(&out);
+#pragma unroll
+  for (int i = 0; i < (int)(sizeof(T) / 4); ++i) dst[i] = __builtin_amdgcn_readfirstlane(src[i]);
+  return out;
+}
+
+// Cache policy (sc0 | sc1) of the small per-slab output stores of the
+// streaming kernels: written through rather than held dirty in L2, so the
+// write-back does not interleave with the read stream of X (measured on the
+// 256^4 FP32 pass: ~0.17 ms of the ~0.5 ms the stores cost with the default
+// policy).
+constexpr int kOutStorePolicy = 0x11;
+
 // ------------------------------------------------------------------ limits
 constexpr int kMaxEll = 64;       // sketch width handled by the one-wave Jacobi solver
 constexpr int kMaxCols = 64;      // factor columns per mode in the core / reconstruct
