@@ -263,31 +263,27 @@ __device__ void upper_inverse_wave(double (*R)[kMaxEll + 1], int n, int lane) {
   }
 }
 
-// Q = Z R^{-1} in place, 32 rows at a time: the rows are staged in LDS
-// (coalesced, zero padded to 64 columns), thread t forms the 4 x 4 output
-// tile (rows 4 (t / 16), columns 4 (t % 16)) from LDS, then writes it.
-__device__ void apply_inverse_block(const QRMat& M, double (*Ri)[kMaxEll + 1],
-                                    double (*sZ)[kMaxEll + 1], int tid) {
-  const int n = M.ell;
-  const int ti = tid >> 4, tj = tid & 15;  // 8 row groups x 16 column groups
-  for (int64_t r0 = 0; r0 < M.m; r0 += kSmallChunk) {
-    const int rows = (int)min<int64_t>(kSmallChunk, M.m - r0);
-    for (int e = tid; e < kSmallChunk * kMaxEll; e += 256) {
-      const int rr = e / kMaxEll, j = e - rr * kMaxEll;
-      sZ[rr][j] = (rr < rows && j < n) ? M.Z[(r0 + rr) * n + j] : 0.0;
-    }
-    __syncthreads();
+// Q = Z R^{-1} in place on the LDS copy of Z, 64 rows at a time: thread t
+// forms the 4 x 4 output tile (rows 4 (t / 16), columns 4 (t % 16)) in
+// registers; the chunk is overwritten once every thread has read its rows.
+__device__ void apply_inverse_lds(double* sZ, int64_t m, int n, const double (*Ri)[kMaxEll + 1],
+                                  int tid) {
+  const int ti = tid >> 4, tj = tid & 15;
+  const int jmax = min(n, 4 * tj + 4);   // R^{-1} is upper triangular: k <= j
+  for (int64_t r0 = 0; r0 < m; r0 += 64) {
     double acc[4][4];
 #pragma unroll
     for (int a = 0; a < 4; ++a)
 #pragma unroll
       for (int c = 0; c < 4; ++c) acc[a][c] = 0.0;
-    const int jmax = min(n, 4 * tj + 4);   // R^{-1} is upper triangular: k <= j
+    int64_t rows[4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) rows[a] = min<int64_t>(r0 + 4 * ti + a, m - 1);
 #pragma unroll 4
     for (int k = 0; k < jmax; ++k) {
       double z[4], w[4];
 #pragma unroll
-      for (int a = 0; a < 4; ++a) z[a] = sZ[4 * ti + a][k];
+      for (int a = 0; a < 4; ++a) z[a] = sZ[rows[a] * n + k];
 #pragma unroll
       for (int c = 0; c < 4; ++c) w[c] = (4 * tj + c < n) ? Ri[k][4 * tj + c] : 0.0;
 #pragma unroll
@@ -295,13 +291,14 @@ __device__ void apply_inverse_block(const QRMat& M, double (*Ri)[kMaxEll + 1],
 #pragma unroll
         for (int c = 0; c < 4; ++c) acc[a][c] = fma(z[a], w[c], acc[a][c]);
     }
+    __syncthreads();   // every read of this chunk is done
 #pragma unroll
     for (int a = 0; a < 4; ++a) {
-      const int rr = 4 * ti + a;
+      const int64_t row = r0 + 4 * ti + a;
 #pragma unroll
       for (int c = 0; c < 4; ++c) {
         const int j = 4 * tj + c;
-        if (rr < rows && j < n) M.Z[(r0 + rr) * n + j] = acc[a][c];
+        if (row < m && j < n) sZ[row * n + j] = acc[a][c];
       }
     }
     __syncthreads();
@@ -312,50 +309,52 @@ template <typename S>
 __global__ __launch_bounds__(256) void cholqr_small_kernel(const S b) {
   const QRMat& M = b.get(blockIdx.x);
   if (!M.small) return;
+  // Z stays in LDS for every pass (row stride ell): one coalesced read at the
+  // start, one write of Q at the end, no global latency inside the passes
+  extern __shared__ double sZ[];
   __shared__ double G[kMaxEll][kMaxEll + 1];
-  __shared__ double G0[kMaxEll][kMaxEll + 1];  // the unshifted Gram, kept for a shifted retry
-  __shared__ double sZ[kSmallChunk][kMaxEll + 1];
   __shared__ double red[2];
   __shared__ int ok;
   const int n = M.ell, tid = threadIdx.x;
+  const int64_t mn = M.m * n;
+  for (int64_t e = tid; e < mn; e += 256) sZ[e] = M.Z[e];
+  __syncthreads();
+  const int ti = tid >> 4, tj = tid & 15;
   int owed = 2, info = 0;
   for (int pass = 1; pass <= kQRMaxPasses && owed > 0; ++pass) {
     // Gram: thread t owns the 4 x 4 tile (4 (t / 16), 4 (t % 16)) of G, so a
-    // row of the chunk costs 8 LDS reads for 16 FMAs
-    const int ti = tid >> 4, tj = tid & 15;
+    // row costs 8 LDS reads for 16 FMAs; the tile stays in registers for a
+    // shifted retry
     double acc[4][4];
 #pragma unroll
     for (int a = 0; a < 4; ++a)
 #pragma unroll
       for (int c = 0; c < 4; ++c) acc[a][c] = 0.0;
-    for (int64_t r0 = 0; r0 < M.m; r0 += kSmallChunk) {
-      const int rows = (int)min<int64_t>(kSmallChunk, M.m - r0);
-      __syncthreads();
-      for (int e = tid; e < kSmallChunk * kMaxEll; e += 256) {
-        const int rr = e / kMaxEll, j = e - rr * kMaxEll;
-        sZ[rr][j] = (rr < rows && j < n) ? M.Z[(r0 + rr) * n + j] : 0.0;
-      }
-      __syncthreads();
-#pragma unroll 4
-      for (int rr = 0; rr < rows; ++rr) {
-        double x[4], y[4];
+    int ca[4], cc[4];
 #pragma unroll
-        for (int a = 0; a < 4; ++a) x[a] = sZ[rr][4 * ti + a];
-#pragma unroll
-        for (int c = 0; c < 4; ++c) y[c] = sZ[rr][4 * tj + c];
-#pragma unroll
-        for (int a = 0; a < 4; ++a)
-#pragma unroll
-          for (int c = 0; c < 4; ++c) acc[a][c] = fma(x[a], y[c], acc[a][c]);
-      }
+    for (int a = 0; a < 4; ++a) {
+      ca[a] = min(4 * ti + a, n - 1);
+      cc[a] = min(4 * tj + a, n - 1);
     }
-    __syncthreads();
+#pragma unroll 4
+    for (int64_t r = 0; r < M.m; ++r) {
+      const double* zr = sZ + r * n;
+      double x[4], y[4];
+#pragma unroll
+      for (int a = 0; a < 4; ++a) x[a] = zr[ca[a]];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) y[c] = zr[cc[c]];
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) acc[a][c] = fma(x[a], y[c], acc[a][c]);
+    }
 #pragma unroll
     for (int a = 0; a < 4; ++a)
 #pragma unroll
       for (int c = 0; c < 4; ++c) {
         const int p = 4 * ti + a, q = 4 * tj + c;
-        if (p < n && q < n) G[p][q] = G0[p][q] = acc[a][c];
+        if (p < n && q < n) G[p][q] = acc[a][c];
       }
     __syncthreads();
     if (tid == 0) {
@@ -366,41 +365,50 @@ __global__ __launch_bounds__(256) void cholqr_small_kernel(const S b) {
     }
     __syncthreads();
     const double mx = red[0], tr = red[1];
-    // Cholesky (+ shifted retry) and the triangular inverse by wave 0
+    // Cholesky by wave 0; on failure every thread rewrites its tile of the
+    // Gram with the shift and wave 0 factors again
     if (tid < 64) {
-      int st = 0;
-      bool good = mx > 0.0 && cholesky_upper_wave(G, n, tid, 1e-14 * mx);
-      if (!good) {
-        const double shift =
-            11.0 * ((double)M.m * n + (double)n * (n + 1)) * kUnit * fmax(tr, 1e-300);
-        TK_WAVE_SYNC();
-        for (int e = tid; e < n * n; e += 64)
-          G[e / n][e % n] = G0[e / n][e % n] + (e / n == e % n ? shift : 0.0);
-        TK_WAVE_SYNC();
-        st = 1;
-        good = cholesky_upper_wave(G, n, tid, 0.0);
+      const bool good = mx > 0.0 && cholesky_upper_wave(G, n, tid, 1e-14 * mx);
+      if (tid == 0) ok = good ? 0 : 1;
+    }
+    __syncthreads();
+    if (ok != 0) {
+      const double shift = 11.0 * ((double)M.m * n + (double)n * (n + 1)) * kUnit * fmax(tr, 1e-300);
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          const int p = 4 * ti + a, q = 4 * tj + c;
+          if (p < n && q < n) G[p][q] = acc[a][c] + (p == q ? shift : 0.0);
+        }
+      __syncthreads();
+      if (tid < 64) {
+        const bool good = cholesky_upper_wave(G, n, tid, 0.0);
         if (!good) {
-          st = 2;
           TK_WAVE_SYNC();
           for (int j = tid; j < n; j += 64)
             if (!(G[j][j] > 0.0)) G[j][j] = 1.0;  // keep the solve finite; flagged
-          TK_WAVE_SYNC();
         }
+        if (tid == 0) ok = good ? 1 : 2;
       }
-      // zero the strict lower triangle left over from the Gram
+    }
+    // the triangular inverse by wave 0 (zero the strict lower triangle left
+    // over from the Gram first)
+    if (tid < 64) {
+      TK_WAVE_SYNC();
       for (int e = tid; e < n * n; e += 64)
         if (e / n > e % n) G[e / n][e % n] = 0.0;
       TK_WAVE_SYNC();
       upper_inverse_wave(G, n, tid);
-      if (tid == 0) ok = st;
     }
     __syncthreads();
     const int status = ok;
-    apply_inverse_block(M, G, sZ, tid);
+    apply_inverse_lds(sZ, M.m, n, G, tid);
     if (status != 0) info |= pass == 1 ? 1 : 2;
     if (status == 2) info |= 4;
     owed = status != 0 ? 2 : owed - 1;
   }
+  for (int64_t e = tid; e < mn; e += 256) M.Z[e] = sZ[e];
   if (tid == 0) {
     if (M.info) *M.info = info;
     M.state[0] = 0;
@@ -526,13 +534,38 @@ __global__ __launch_bounds__(kEigThreads) void eig_kernel(const S b) {
   // rotations stop below rounding level of the output precision (relative to
   // the pair's own scale): FP64 bases need ~u, FP32 bases ~1e-12 suffices
   const double tol = M.udtype == TK_F64 ? 4.0 * kUnit : 1e-12;
-  for (int e = tid; e < np * np; e += kEigThreads) {
-    const int p = e / np, q = e - p * np;
-    double v = 0.0;
-    if (p < n && q < n)
-      for (int c = 0; c < M.ncc; ++c) v += M.cpart[(int64_t)c * n * n + p * n + q];
-    A[p][q] = v;
-    V[p][q] = p == q ? 1.0 : 0.0;
+  // summed Gram: every thread's elements over groups of four column chunks,
+  // all loads of a group in flight together (each element still sums the
+  // chunks in index order)
+  {
+    constexpr int kE = kMaxEll * kMaxEll / kEigThreads;
+    double v[kE];
+#pragma unroll
+    for (int k = 0; k < kE; ++k) v[k] = 0.0;
+    for (int c0 = 0; c0 < M.ncc; c0 += 4) {
+      double t[kE][4];
+#pragma unroll
+      for (int k = 0; k < kE; ++k) {
+        const int e = tid + kEigThreads * k, p = e / np, q = e - (e / np) * np;
+        const bool live = e < np * np && p < n && q < n;
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+          t[k][u] = (live && c0 + u < M.ncc) ? M.cpart[(int64_t)(c0 + u) * n * n + p * n + q] : 0.0;
+      }
+#pragma unroll
+      for (int k = 0; k < kE; ++k)
+#pragma unroll
+        for (int u = 0; u < 4; ++u) v[k] += t[k][u];
+    }
+#pragma unroll
+    for (int k = 0; k < kE; ++k) {
+      const int e = tid + kEigThreads * k;
+      if (e < np * np) {
+        const int p = e / np, q = e - p * np;
+        A[p][q] = v[k];
+        V[p][q] = p == q ? 1.0 : 0.0;
+      }
+    }
   }
   // this thread's items, in two loops of one kind each so a wave never runs
   // both kinds: the half x half 2x2 blocks of A (pair k1 rows, pair k2
@@ -652,9 +685,27 @@ __global__ __launch_bounds__(kEigThreads) void eig_kernel(const S b) {
   double best = -1.0, bval = 0.0;
   int64_t bidx = INT64_MAX;
   const bool f64 = M.udtype == TK_F64;
+  // rows of Q in chunks of 32, the next chunk's loads in flight (registers)
+  // while the current one is multiplied
+  constexpr int kPre = 32 * kMaxEll / kEigThreads;
+  double pre[kPre];
+  auto fetch = [&](int64_t r0) {
+    const int rows = (int)min<int64_t>(32, M.m - r0);
+#pragma unroll
+    for (int u = 0; u < kPre; ++u) {
+      const int e = tid + kEigThreads * u;
+      pre[u] = (r0 < M.m && e < rows * n) ? M.Z[r0 * n + e] : 0.0;
+    }
+  };
+  fetch(0);
   for (int64_t r0 = 0; r0 < M.m; r0 += 32) {
     const int rows = (int)min<int64_t>(32, M.m - r0);
-    for (int e = tid; e < rows * n; e += kEigThreads) sQ[e / n][e % n] = M.Z[r0 * n + e];
+#pragma unroll
+    for (int u = 0; u < kPre; ++u) {
+      const int e = tid + kEigThreads * u;
+      if (e < rows * n) sQ[e / n][e % n] = pre[u];
+    }
+    fetch(r0 + 32);
     __syncthreads();
     if (active) {
       for (int rr = slot; rr < rows; rr += tpc) {
@@ -785,7 +836,12 @@ hipError_t cholqr_impl(const S& src, const QRMat* host, int count, hipStream_t s
   const int nrc = max_field(host, count, 0), nrb = max_field(host, count, 2);
   bool any_small = false, any_big = false;
   for (int i = 0; i < count; ++i) (host[i].small ? any_small : any_big) = true;
-  if (any_small) hipLaunchKernelGGL(cholqr_small_kernel<S>, dim3(count), dim3(256), 0, st, src);
+  if (any_small) {
+    int64_t lds = 0;
+    for (int i = 0; i < count; ++i)
+      if (host[i].small) lds = std::max<int64_t>(lds, host[i].m * host[i].ell * (int64_t)sizeof(double));
+    hipLaunchKernelGGL(cholqr_small_kernel<S>, dim3(count), dim3(256), (size_t)lds, st, src);
+  }
   if (!any_big) return hipGetLastError();
   // CholeskyQR2 needs two passes; every shifted pass owes two more plain ones,
   // so an exactly rank-deficient sketch (shift, shift, plain, plain) needs four.

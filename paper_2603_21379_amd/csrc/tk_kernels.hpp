@@ -89,7 +89,8 @@ struct QRMat {
   int32_t pad2;
 };
 // a matrix is handled by one workgroup when its rows times columns fit this
-constexpr int kQRSmallElems = 16384;
+// (the FP64 copy of Z, 120 KB, and the Gram share the workgroup's LDS)
+constexpr int kQRSmallElems = 15360;
 constexpr int kQRSmallRows = 4096;
 constexpr int kQRMaxBatch = 16;
 constexpr int kQRMaxPasses = 4;
