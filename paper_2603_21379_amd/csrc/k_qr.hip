@@ -603,9 +603,14 @@ __global__ __launch_bounds__(kEigThreads) void eig_kernel(const S b) {
         if (q < n) {
           const double apq = A[p][q], app = A[p][p], aqq = A[q][q];
           if (fabs(apq) > tol * fmax(fabs(app), fabs(aqq))) {
-            const double th = (aqq - app) / (2.0 * apq);
-            const double t = (th >= 0.0 ? 1.0 : -1.0) / (fabs(th) + sqrt(1.0 + th * th));
-            c = 1.0 / sqrt(1.0 + t * t);
+            // t = tan of the rotation angle, the root of t^2 + 2 theta t - 1
+            // of smaller magnitude, theta = (a_qq - a_pp) / (2 a_pq):
+            // t = 2 a_pq / (d + sign(d) sqrt(d^2 + 4 a_pq^2)), d = a_qq - a_pp
+            // (one square root and one division); c = 1 / sqrt(1 + t^2)
+            const double d = aqq - app;
+            const double root = sqrt(fma(d, d, 4.0 * apq * apq));
+            const double t = (2.0 * apq) / (d >= 0.0 ? d + root : d - root);
+            c = 1.0 / sqrt(fma(t, t, 1.0));
             s = t * c;
             rot = true;
           }
