@@ -9,7 +9,7 @@
 // exactly; v_mfma_f64_16x16x4f64 accumulates in FP64.
 //
 // A workgroup owns 256 rows (four waves of four 16-row tiles) and walks the
-// columns in chunks of 64: the chunk of U_r (64 x 16, FP64) is staged in LDS
+// columns in chunks of 32: the chunk of U_r (32 x 16, FP64) is staged in LDS
 // once for the workgroup, each lane loads float4s of X (rows 16 t + l%16,
 // columns 16 s + 4 (l/16) .. +3; component c is the A operand of one K = 4
 // step, K <-> column 16 s + 4 k + c), and the B operand (a row of U_r) is
@@ -18,7 +18,11 @@
 // 16x16 MFMA result, register v of lane l holds row l/16 + 4 v, column l%16,
 // so step v of that product takes K <-> rows k + 4 v of the tile.  The four
 // waves' 16 x 16 partials are added in a fixed order and one per workgroup is
-// written; a second kernel sums them in workgroup order.
+// written; two more kernels sum them in fixed order (segments of workgroups,
+// then the segments).  U_r of the next chunk is loaded into registers while
+// the current chunk is multiplied and every step issues the same loads, so
+// the waits count loads; 32-column chunks keep the kernel at two waves per
+// SIMD.
 #include "tk_kernels.hpp"
 
 namespace tk {
@@ -28,7 +32,8 @@ typedef double doublex4 __attribute__((ext_vector_type(4)));
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 
 constexpr int kRows = 256;        // rows per workgroup
-constexpr int kChunk = 64;        // columns per chunk
+constexpr int kChunk = 32;        // columns per chunk
+constexpr int kS = kChunk / 16;   // float4 column groups per lane and chunk
 constexpr int kRsrcWord3 = 0x00020000;
 
 __device__ __forceinline__ doublex4 mma64(double a, double b, doublex4 c) {
@@ -52,22 +57,37 @@ __global__ __launch_bounds__(256) void root_pass_kernel(const RootPass p) {
   const int c0 = qs * per;
   const int nchunks = max(0, min(allchunks, c0 + per) - c0);
 
-  auto stage_u = [&](int ck, int slot) {
-    for (int e = tid; e < kChunk * 16; e += 256) {
-      const int q = e >> 4, k = e & 15;
+  // U_r rows of chunk ck (32 x 16 FP64, two per thread), loaded into
+  // registers one chunk ahead and written to LDS slot ck % 2 after the
+  // previous multiply; rows past n_r and chunks past the end read zero
+  constexpr int kUPer = kChunk * 16 / 256;
+  auto load_u = [&](int ck, double (&u)[kUPer]) {
+#pragma unroll
+    for (int w = 0; w < kUPer; ++w) {
+      const int e = tid + 256 * w, q = e >> 4, k = e & 15;
       const int64_t b = (int64_t)(c0 + ck) * kChunk + q;
-      sU[slot][q][k] = (b < p.nR && k < p.rR) ? p.UR[b * p.rR + k] : 0.0;
+      u[w] = (ck < nchunks && b < p.nR && k < p.rR) ? p.UR[b * p.rR + k] : 0.0;
     }
   };
-  // X of one chunk for this wave: 4 tiles x 4 column groups of float4
-  auto load_x = [&](int ck, floatx4 (&buf)[4][4]) {
+  auto store_u = [&](int slot, const double (&u)[kUPer]) {
+#pragma unroll
+    for (int w = 0; w < kUPer; ++w) {
+      const int e = tid + 256 * w;
+      sU[slot][e >> 4][e & 15] = u[w];
+    }
+  };
+  // X of one chunk for this wave: 4 tiles x 4 column groups of float4; chunks
+  // past the end read zero (every step issues the same loads, so the waits
+  // count loads)
+  auto load_x = [&](int ck, floatx4 (&buf)[4][kS]) {
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
       const int64_t r = (int64_t)wv * 64 + 16 * t + l16;
 #pragma unroll
-      for (int s = 0; s < 4; ++s) {
+      for (int s = 0; s < kS; ++s) {
         const int64_t b = (int64_t)(c0 + ck) * kChunk + 16 * s + 4 * g;
-        const uint32_t off = (r < rows && b < p.nR) ? (uint32_t)((r * p.nR + b) * 4) : 0x80000000u;
+        const uint32_t off =
+            (ck < nchunks && r < rows && b < p.nR) ? (uint32_t)((r * p.nR + b) * 4) : 0x80000000u;
         buf[t][s] = __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, 0);
       }
     }
@@ -77,14 +97,9 @@ __global__ __launch_bounds__(256) void root_pass_kernel(const RootPass p) {
   doublex4 acc[4];
 #pragma unroll
   for (int t = 0; t < 4; ++t) acc[t] = doublex4{};
-  floatx4 bufA[4][4], bufB[4][4];
-  if (nchunks > 0) {
-    stage_u(0, 0);
-    load_x(0, bufA);
-  }
-  auto compute = [&](int slot, const floatx4 (&buf)[4][4]) {
+  auto compute = [&](int slot, const floatx4 (&buf)[4][kS]) {
 #pragma unroll
-    for (int s = 0; s < 4; ++s)
+    for (int s = 0; s < kS; ++s)
 #pragma unroll
       for (int c = 0; c < 4; ++c) {
         const double u = sU[slot][16 * s + 4 * g + c][l16];
@@ -92,24 +107,31 @@ __global__ __launch_bounds__(256) void root_pass_kernel(const RootPass p) {
         for (int t = 0; t < 4; ++t) acc[t] = mma64((double)buf[t][s][c], u, acc[t]);
       }
   };
-  for (int ck = 0; ck < nchunks; ck += 2) {
-    __syncthreads();   // chunk ck staged; the other slot is free
-    const bool second = ck + 1 < nchunks;
-    if (second) {
-      stage_u(ck + 1, 1);
-      load_x(ck + 1, bufB);
-    }
+  // step ck: issue U_r(ck + 1) and X(ck + 1), multiply chunk ck, then put
+  // U_r(ck + 1) into the other LDS slot (its last readers, step ck - 1, are
+  // past the barrier that ended that step)
+  double u[kUPer];
+  floatx4 bufA[4][kS], bufB[4][kS];
+  load_u(0, u);
+  load_x(0, bufA);
+  store_u(0, u);
+  __syncthreads();
+  int ck = 0;
+  for (; ck + 2 <= nchunks; ck += 2) {
+    load_u(ck + 1, u);
+    load_x(ck + 1, bufB);
     __builtin_amdgcn_sched_barrier(0);
     compute(0, bufA);
-    if (!second) break;
-    __syncthreads();   // chunk ck + 1 staged; slot 0 is free
-    if (ck + 2 < nchunks) {
-      stage_u(ck + 2, 0);
-      load_x(ck + 2, bufA);
-    }
+    store_u(1, u);
+    __syncthreads();
+    load_u(ck + 2, u);
+    load_x(ck + 2, bufA);
     __builtin_amdgcn_sched_barrier(0);
     compute(1, bufB);
+    store_u(0, u);
+    __syncthreads();
   }
+  if (ck < nchunks) compute(0, bufA);
   // U_l^T T over this wave's 64 rows: A = U_l[row][j] (lane: j = l%16, k = l/16)
   doublex4 part = doublex4{};
 #pragma unroll
@@ -131,12 +153,38 @@ __global__ __launch_bounds__(256) void root_pass_kernel(const RootPass p) {
   }
 }
 
+// The workgroup partials are summed in two fixed-order levels: kSumSeg
+// segments of consecutive workgroups (eight loads in flight per thread), then
+// the segment sums.  A single workgroup walking every partial in turn took
+// 0.77 ms at 18^8 (2048 dependent loads per thread).
+constexpr int kSumSeg = 64;
+
+__global__ __launch_bounds__(256) void root_sum_seg_kernel(const RootPass p) {
+  const int e = threadIdx.x, g = blockIdx.x;
+  const int per = (p.nblocks + kSumSeg - 1) / kSumSeg;
+  const int b0 = g * per, b1 = min(p.nblocks, b0 + per);
+  double s = 0.0;
+  int b = b0;
+  for (; b + 8 <= b1; b += 8) {
+    double t[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) t[u] = p.partials[(int64_t)(b + u) * 256 + e];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) s += t[u];
+  }
+  for (; b < b1; ++b) s += p.partials[(int64_t)b * 256 + e];
+  p.partials[((int64_t)p.nblocks + g) * 256 + e] = s;
+}
+
 __global__ __launch_bounds__(256) void root_sum_kernel(const RootPass p) {
   const int e = threadIdx.x, j = e >> 4, k = e & 15;
-  if (j >= p.rL || k >= p.rR) return;
+  double t[kSumSeg];
+#pragma unroll
+  for (int g = 0; g < kSumSeg; ++g) t[g] = p.partials[((int64_t)p.nblocks + g) * 256 + e];
   double s = 0.0;
-  for (int b = 0; b < p.nblocks; ++b) s += p.partials[(int64_t)b * 256 + e];
-  p.out[j * p.rR + k] = s;
+#pragma unroll
+  for (int g = 0; g < kSumSeg; ++g) s += t[g];
+  if (j < p.rL && k < p.rR) p.out[j * p.rR + k] = s;
 }
 
 }  // namespace
@@ -154,6 +202,9 @@ static int root_qsplit(int64_t nL, int64_t nR) {
 
 int64_t root_pass_blocks(int64_t nL, int64_t nR) { return ceil_div(nL, kRows) * root_qsplit(nL, nR); }
 
+// doubles of the partials buffer: the workgroup partials and the segment sums
+int64_t root_pass_partials(int64_t nL, int64_t nR) { return (root_pass_blocks(nL, nR) + kSumSeg) * 256; }
+
 hipError_t launch_root_pass(const RootPass& pin, hipStream_t st) {
   RootPass p = pin;
   p.qsplit = root_qsplit(p.nL, p.nR);
@@ -162,6 +213,7 @@ hipError_t launch_root_pass(const RootPass& pin, hipStream_t st) {
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(root_pass_kernel, dim3((unsigned)p.nblocks), dim3(256), 0, st, p);
   if ((e = profile_end(st)) != hipSuccess) return e;
+  hipLaunchKernelGGL(root_sum_seg_kernel, dim3(kSumSeg), dim3(256), 0, st, p);
   hipLaunchKernelGGL(root_sum_kernel, dim3(1), dim3(256), 0, st, p);
   return hipGetLastError();
 }

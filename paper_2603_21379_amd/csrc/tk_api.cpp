@@ -1204,7 +1204,7 @@ tk_status htucker_decompose(const tk_tensor* X, const tk_tree* tree, const int32
   double* mt_root = root_fused ? nullptr
                                : w.take<double>((size_t)std::max(mode_product_scratch(rank[R], nS[R]),
                                                                  mode_product_scratch(rank[L], nS[L])));
-  double* root_part = root_fused ? w.take<double>((size_t)root_pass_blocks(nS[L], nS[R]) * 256) : nullptr;
+  double* root_part = root_fused ? w.take<double>((size_t)root_pass_partials(nS[L], nS[R])) : nullptr;
   if (!ws) {
     *ws_bytes = w.off;
     return TK_OK;

@@ -287,7 +287,7 @@ struct RootPass {
   const float* X;
   const double* UL;     // nL x rL
   const double* UR;     // nR x rR
-  double* partials;     // [root_pass_blocks(nL, nR)][16][16]
+  double* partials;     // root_pass_partials(nL, nR) doubles: workgroup partials, then segment sums
   double* out;          // rL x rR
   int64_t nL, nR;
   int32_t rL, rR;
@@ -296,6 +296,7 @@ struct RootPass {
 };
 bool root_pass_supported(int dtype, int64_t nL, int64_t nR, int rL, int rR);
 int64_t root_pass_blocks(int64_t nL, int64_t nR);
+int64_t root_pass_partials(int64_t nL, int64_t nR);   // doubles of RootPass::partials
 // brackets the streaming kernel with the profiler's events
 hipError_t launch_root_pass(const RootPass& p, hipStream_t st);
 
