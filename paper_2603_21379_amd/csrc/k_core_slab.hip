@@ -304,14 +304,46 @@ __global__ __launch_bounds__(256, 2) void core_slab_kernel(const CoreSlab p) {
         const int cIJ = __builtin_amdgcn_readfirstlane(p.cI * p.cJ);
         const __amdgpu_buffer_rsrc_t ro = __builtin_amdgcn_make_buffer_rsrc(
             p.T + (int64_t)item * p.cH * cIJ, (short)0, p.cH * cIJ * 4, kRsrcWord3);
+        if ((cIJ & 3) == 0) {
+          // the item's c_H x c_I x c_J block is contiguous: stage up to 1024
+          // values of it in this wave's LDS block and write them as 16-byte
+          // pieces (four stores per 1024 values instead of four per plane)
+          float* so = sFH + p.nH * kMaxC + (threadIdx.x >> 6) * 1024;
+          const int G = __builtin_amdgcn_readfirstlane(1024 / cIJ);
+          for (int q0 = 0; q0 < p.cH; q0 += G) {
 #pragma unroll
-        for (int q = 0; q < kMaxC; ++q) {
-          if (q < p.cH) {
+            for (int q = 0; q < kMaxC; ++q) {
+              if (q < q0 || q >= q0 + G || q >= p.cH) continue;
 #pragma unroll
-            for (int v = 0; v < 4; ++v)
-              __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(acc3[q][v]), ro, off[v], q * cIJ * 4, kOutStorePolicy);
+              for (int v = 0; v < 4; ++v)
+                if (off[v] != 0x80000000u) so[(q - q0) * cIJ + (off[v] >> 2)] = acc3[q][v];
+            }
+            // ordered LDS accesses of one wave: the reads below see the writes
+            __builtin_amdgcn_wave_barrier();
+            __atomic_signal_fence(__ATOMIC_SEQ_CST);
+            const int nf = min(G, p.cH - q0) * cIJ;
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+              const int f = (u * 64 + lane) * 4;
+              const floatx4 w = *reinterpret_cast<const floatx4*>(so + f);
+              const uint32_t o = f < nf ? (uint32_t)((q0 * cIJ + f) * 4) : 0x80000000u;
+              __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(uintx4, w), ro, o, 0, kOutStorePolicy);
+            }
+            __atomic_signal_fence(__ATOMIC_SEQ_CST);
+            __builtin_amdgcn_wave_barrier();
           }
-          acc3[q] = floatx4{};
+#pragma unroll
+          for (int q = 0; q < kMaxC; ++q) acc3[q] = floatx4{};
+        } else {
+#pragma unroll
+          for (int q = 0; q < kMaxC; ++q) {
+            if (q < p.cH) {
+#pragma unroll
+              for (int v = 0; v < 4; ++v)
+                __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(acc3[q][v]), ro, off[v], q * cIJ * 4, kOutStorePolicy);
+            }
+            acc3[q] = floatx4{};
+          }
         }
       }
     } else {
@@ -411,7 +443,8 @@ hipError_t launch_depth(const CoreSlab& p, size_t lds, hipStream_t st) {
 
 template <typename TX, int NK, int NT>
 hipError_t launch_typed(const CoreSlab& p, bool h3, size_t lds, hipStream_t st) {
-  if (h3) return launch_depth<TX, NK, NT, true>(p, lds + (size_t)p.nH * kMaxC * sizeof(float), st);
+  // three modes: F_H and a 4 KB output staging block per wave
+  if (h3) return launch_depth<TX, NK, NT, true>(p, lds + (size_t)p.nH * kMaxC * sizeof(float) + kWaves * 1024 * sizeof(float), st);
   return launch_depth<TX, NK, NT, false>(p, lds, st);
 }
 
