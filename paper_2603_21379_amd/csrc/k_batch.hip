@@ -103,6 +103,34 @@ __global__ __launch_bounds__(256, 2) void batch_slab_kernel(const BatchSlab bs) 
       }
     };
     floatx4 tacc = floatx4{};
+    // Output staging: the partial cores of consecutive slabs are contiguous
+    // (T + a c_I c_J), so runs of them collect in this wave's 4 KB LDS block
+    // and are written as 16-byte pieces (four stores per 1024 values instead
+    // of four per slab).  Needs c_I c_J divisible by 4 (16-byte alignment).
+    const int cIJ = td.cI * td.cJ;
+    const bool staged = (cIJ & 3) == 0;
+    float* so = lds + kWaves * (NT * 256) + wv * 1024;
+    int64_t sa0 = 0;
+    int sn = 0;
+    auto flush = [&]() {
+      if (sn == 0) return;
+      // ordered LDS accesses of one wave: the reads below see the writes
+      __builtin_amdgcn_wave_barrier();
+      __atomic_signal_fence(__ATOMIC_SEQ_CST);
+      const int nf = sn * cIJ;
+      const __amdgpu_buffer_rsrc_t ro = __builtin_amdgcn_make_buffer_rsrc(
+          td.T + sa0 * cIJ, (short)0, nf * 4, kRsrcWord3);
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int f = (u * 64 + lane) * 4;
+        const floatx4 w = *reinterpret_cast<const floatx4*>(so + f);
+        const uint32_t o = f < nf ? (uint32_t)(f * 4) : 0x80000000u;
+        __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(uintx4, w), ro, o, 0, kOutStorePolicy);
+      }
+      __atomic_signal_fence(__ATOMIC_SEQ_CST);
+      __builtin_amdgcn_wave_barrier();
+      sn = 0;
+    };
     auto compute_unit = [&](int64_t a, int grp, uintx4 (&buf)[TG][NK]) {
 #pragma unroll
       for (int tt = 0; tt < TG; ++tt) {
@@ -123,13 +151,26 @@ __global__ __launch_bounds__(256, 2) void batch_slab_kernel(const BatchSlab bs) 
         for (int v = 0; v < 4; ++v) tacc = mma_f32(A[v * 64], acc[v], tacc);
       }
       if (grp != nG - 1) return;
-      const __amdgpu_buffer_rsrc_t ro = __builtin_amdgcn_make_buffer_rsrc(
-          td.T + a * td.cI * td.cJ, (short)0, td.cI * td.cJ * 4, kRsrcWord3);
+      if (staged) {
+        // slab complete: its c_I x c_J block goes to this wave's LDS block
+        // after the previous slabs of the run; a full block is written out
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int jp = 4 * g + v;
-        const uint32_t off = (jp < td.cI && l16 < td.cJ) ? (uint32_t)((jp * td.cJ + l16) * 4) : 0x80000000u;
-        __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(tacc[v]), ro, off, 0, kOutStorePolicy);
+        for (int v = 0; v < 4; ++v) {
+          const int jp = 4 * g + v;
+          if (jp < td.cI && l16 < td.cJ) so[sn * cIJ + jp * td.cJ + l16] = tacc[v];
+        }
+        if (sn == 0) sa0 = a;
+        sn = sn + 1;
+        if ((sn + 1) * cIJ > 1024) flush();
+      } else {
+        const __amdgpu_buffer_rsrc_t ro = __builtin_amdgcn_make_buffer_rsrc(
+            td.T + a * td.cI * td.cJ, (short)0, td.cI * td.cJ * 4, kRsrcWord3);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int jp = 4 * g + v;
+          const uint32_t off = (jp < td.cI && l16 < td.cJ) ? (uint32_t)((jp * td.cJ + l16) * 4) : 0x80000000u;
+          __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(tacc[v]), ro, off, 0, kOutStorePolicy);
+        }
       }
       tacc = floatx4{};
     };
@@ -176,6 +217,7 @@ __global__ __launch_bounds__(256, 2) void batch_slab_kernel(const BatchSlab bs) 
 #pragma unroll
     for (int s = 0; s < NBUF - 1; ++s)
       if (s < left) compute_unit(ua[s], ug[s], buf[s]);
+    flush();
   }
 }
 
@@ -267,7 +309,8 @@ __global__ __launch_bounds__(256) void batch_mode_kernel(const BatchMode bm) {
 
 }  // namespace
 
-size_t batch_slab_lds_bytes() { return (size_t)kWaves * NT * 256 * sizeof(float); }
+// per wave: the F_I^T table and a 1024-value output staging block
+size_t batch_slab_lds_bytes() { return (size_t)kWaves * (NT * 256 + 1024) * sizeof(float); }
 
 int batch_slab_waves(int tg, int nbuf) {
   int per_cu = 0;
