@@ -259,6 +259,17 @@ void tucker_batch_plan_destroy(tk_batch_plan* plan);
 void tk_profile_enable(int32_t on);
 tk_status tk_profile_read(double* ms, int64_t* launches, int32_t reset);
 
+/* Measurement helper, not a step of the method: the read-only streaming
+ * reference against which the streaming passes are compared.  Reads
+ * floor(bytes / 16) float4s of the device buffer x once (each 16-byte-per-lane
+ * load one contiguous 1 KB piece, persistent waves, two workgroups per CU) and
+ * writes one checksum per workgroup to partials (device, FP64).  npartials
+ * must be at least tk_stream_read_blocks().  Asynchronous on `stream`.
+ * Returns TK_EINVAL (null buffer, negative size, partials too small) or
+ * TK_EDEVICE. */
+int32_t tk_stream_read_blocks(void);
+tk_status tk_stream_read(const void* x, int64_t bytes, double* partials, int32_t npartials, void* stream);
+
 /* Message for the calling thread's last non-OK status ("" if none). */
 const char* tk_last_error(void);
 

@@ -54,7 +54,8 @@ _lock = threading.Lock()
 EXPORTS = ("tucker_sketch_all_modes", "tucker_qr", "tucker_core", "tucker_reconstruct",
            "htucker_decompose", "tucker_core_vjp", "tucker_reconstruct_vjp", "tk_last_error",
            "tk_version", "tk_profile_enable", "tk_profile_read", "tucker_batch_plan_create",
-           "tucker_batch_run", "tucker_batch_autotune", "tucker_batch_plan_destroy")
+           "tucker_batch_run", "tucker_batch_autotune", "tucker_batch_plan_destroy",
+           "tk_stream_read_blocks", "tk_stream_read")
 
 
 def lib():
@@ -75,6 +76,10 @@ def lib():
             L.tk_profile_read.argtypes = [C.POINTER(C.c_double), C.POINTER(C.c_int64), C.c_int32]
             L.tk_profile_read.restype = C.c_int
             L.tk_version.restype = C.c_char_p
+            L.tk_stream_read_blocks.argtypes = []
+            L.tk_stream_read_blocks.restype = C.c_int32
+            L.tk_stream_read.argtypes = [vp, C.c_int64, vp, C.c_int32, vp]
+            L.tk_stream_read.restype = C.c_int
             sig = {
                 "tucker_sketch_all_modes": [C.POINTER(TkTensor), C.POINTER(TkSketch), pp, pp, vp, sz, vp],
                 "tucker_qr": [C.c_int32, i64p, i32p, pp, pp, C.c_int32, i64p, i32p, pp, C.c_int32,
@@ -344,6 +349,17 @@ def tk_profile_read(reset: bool = True):
     ms, n = C.c_double(0), C.c_int64(0)
     _check("tk_profile_read", lib().tk_profile_read(C.byref(ms), C.byref(n), 1 if reset else 0))
     return ms.value, n.value
+
+
+def stream_read_blocks() -> int:
+    return int(lib().tk_stream_read_blocks())
+
+
+def stream_read(x, partials, stream=None):
+    """Read-only streaming reference over the bytes of tensor x (measurement)."""
+    _check("tk_stream_read", lib().tk_stream_read(
+        C.c_void_p(x.data_ptr()), x.numel() * x.element_size(), C.c_void_p(partials.data_ptr()),
+        partials.numel(), _stream(stream)))
 
 
 def version() -> str:

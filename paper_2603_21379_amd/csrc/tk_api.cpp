@@ -832,6 +832,18 @@ tk_status tk_profile_read(double* ms, int64_t* launches, int32_t reset) {
 }
 const char* tk_version(void) { return "tkmi 0.1 (gfx950)"; }
 
+int32_t tk_stream_read_blocks(void) { return (int32_t)stream_read_blocks(); }
+
+tk_status tk_stream_read(const void* x, int64_t bytes, double* partials, int32_t npartials, void* stream) {
+  clear_error();
+  if (!x || !partials || bytes < 0) return set_error(TK_EINVAL, "tk_stream_read: null buffer or negative size");
+  const int32_t blocks = (int32_t)stream_read_blocks();
+  if (npartials < blocks)
+    return set_error(TK_EINVAL, "tk_stream_read: partials holds %d values, needs %d", npartials, blocks);
+  TK_HIP(launch_stream_read(x, bytes, partials, blocks, as_stream(stream)));
+  return TK_OK;
+}
+
 tk_status tucker_sketch_all_modes(const tk_tensor* X, const tk_sketch* sk, double* const* Z,
                                   void* const* Y, void* ws, size_t* ws_bytes, void* stream) {
   clear_error();

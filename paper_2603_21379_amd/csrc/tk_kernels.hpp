@@ -320,4 +320,8 @@ hipError_t launch_unfold_gemm(const UnfoldGemm& g, int a_dt, int b_dt, int out_d
 hipError_t launch_convert(const double* in, void* out, int out_dt, int64_t n, hipStream_t st);
 hipError_t launch_to_f64(const void* in, int in_dt, double* out, int64_t n, hipStream_t st);
 
+// ---------------------------------------------------------------- measurement
+int stream_read_blocks();
+hipError_t launch_stream_read(const void* x, int64_t bytes, double* partials, int32_t blocks, hipStream_t st);
+
 }  // namespace tk
