@@ -9,10 +9,14 @@
 // Per slab and 128-column block b0 (one wave, persistent over slabs):
 //  stage 1  P = T[a] F_J^T on v_mfma_f32_32x32x2f32: M = j (rows of T), K = j',
 //           four N tiles whose column n stands for b = b0 + 4 n + c;
-//  stage 2  X_hat = F_I P: for every 32-row tile of i, register v of a P
-//           accumulator holds rows j = 8 (v/4) + 4 (l/32) + v%4 for column n,
-//           which is the B operand of a K = 2 step over the row pair
-//           {j, j + 4}, so P feeds stage 2 without moving; F_I comes from LDS.
+//  stage 2  X_hat = F_I P on v_mfma_f32_32x32x16_bf16 at FP32 accuracy: P and
+//           F_I are split into three BF16 pieces (x = h + m + l exactly) and
+//           the six piece products of rank sum <= 4 are accumulated in FP32
+//           (the three dropped are ~2^-27 relative).  Register v of a P
+//           accumulator holds row j = 8 (v/4) + 4 (l/32) + v%4 for column n;
+//           K step ks takes registers 8 ks .. 8 ks + 7 as its K slots and the
+//           F_I pieces in LDS follow the same j order, so P feeds stage 2
+//           without moving between lanes.
 //  The output tiles of components c = 2 q, 2 q + 1 line up with a float2 of X
 //  per lane (X[a][i][b0 + 4 n + 2 q .. +1]), loaded coalesced and compared in
 //  FP64.  The next (row tile, component pair) of X is loaded while the
@@ -23,7 +27,11 @@ namespace tk {
 namespace {
 
 typedef float floatx16 __attribute__((ext_vector_type(16)));
+typedef float floatx4 __attribute__((ext_vector_type(4)));
 typedef float floatx2 __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef unsigned int uintx4 __attribute__((ext_vector_type(4)));
 
 constexpr int kCols = 128;
 constexpr int kWaves = 4;
@@ -32,16 +40,58 @@ constexpr int kRsrcWord3 = 0x00020000;
 __device__ __forceinline__ floatx16 mfma32(float a, float b, floatx16 c) {
   return __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, c, 0, 0, 0);
 }
+__device__ __forceinline__ floatx16 mma_bf16(bf16x8 a, bf16x8 b, floatx16 c) {
+  return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
+}
+
+// x (8 FP32 values) -> BF16 pieces h, m, l with x = h + m + l exactly:
+// h = rne(x), m = rne(x - h), l = rne(x - h - m), each difference exact in FP32
+__device__ __forceinline__ void split3(const float (&x)[8], bf16x8& h, bf16x8& m, bf16x8& l) {
+  uintx4 hh, mm, ll;
+#pragma unroll
+  for (int w = 0; w < 4; ++w) {
+    const floatx2 v = {x[2 * w], x[2 * w + 1]};
+    const uint32_t hb = __builtin_bit_cast(uint32_t, __builtin_convertvector(v, bf16x2));
+    const floatx2 r1 = {v[0] - __uint_as_float(hb << 16), v[1] - __uint_as_float(hb & 0xFFFF0000u)};
+    const uint32_t mb = __builtin_bit_cast(uint32_t, __builtin_convertvector(r1, bf16x2));
+    const floatx2 r2 = {r1[0] - __uint_as_float(mb << 16), r1[1] - __uint_as_float(mb & 0xFFFF0000u)};
+    hh[w] = hb;
+    mm[w] = mb;
+    ll[w] = __builtin_bit_cast(uint32_t, __builtin_convertvector(r2, bf16x2));
+  }
+  h = __builtin_bit_cast(bf16x8, hh);
+  m = __builtin_bit_cast(bf16x8, mm);
+  l = __builtin_bit_cast(bf16x8, ll);
+}
 
 __global__ __launch_bounds__(256, 1) void resid2_f32_kernel(const ResidFused2 p) {
   extern __shared__ float lds[];
   const int nIt = (p.nI + 31) / 32;             // 32-row tiles of i
   const int nH = (p.nJ + kCols - 1) / kCols;    // 128-column blocks
-  float* sFI = lds;                              // [nIt * 32][32], zero padded
-  float* sFJ = lds + nIt * 32 * 32;              // [nH * 128][32], zero padded
-  for (int e = threadIdx.x; e < nIt * 32 * 32; e += blockDim.x) {
-    const int i = e >> 5, j = e & 31;
-    sFI[e] = (i < p.nI && j < p.cI) ? p.FI[i * p.cI + j] : 0.0f;
+  // F_I as the A operand of stage 2 in BF16 pieces: sFIp[it][ks][piece][lane]
+  // (BF16x8) = F_I[32 it + l%32][j] for the K slots 8 (l/32) + v of step ks,
+  // j = 8 (2 ks + v/4) + 4 (l/32) + v%4 (the order the stage-1 accumulator
+  // holds j in, so P needs no exchange between lanes)
+  uint32_t* sFIp = reinterpret_cast<uint32_t*>(lds);
+  float* sFJ = lds + nIt * 2 * 3 * 64 * 4;       // [nH * 128][32], zero padded
+  for (int e = threadIdx.x; e < nIt * 2 * 64; e += blockDim.x) {
+    const int it = e >> 7, ks = (e >> 6) & 1, ln = e & 63, g = ln >> 5, i = it * 32 + (ln & 31);
+    float x[8];
+#pragma unroll
+    for (int v = 0; v < 8; ++v) {
+      const int j = 8 * (2 * ks + (v >> 2)) + 4 * g + (v & 3);
+      x[v] = (i < p.nI && j < p.cI) ? p.FI[i * p.cI + j] : 0.0f;
+    }
+    bf16x8 h, m, l;
+    split3(x, h, m, l);
+    const uintx4 uh = __builtin_bit_cast(uintx4, h), um = __builtin_bit_cast(uintx4, m),
+                 ul = __builtin_bit_cast(uintx4, l);
+#pragma unroll
+    for (int w = 0; w < 4; ++w) {
+      sFIp[((((it * 2 + ks) * 3) + 0) * 64 + ln) * 4 + w] = uh[w];
+      sFIp[((((it * 2 + ks) * 3) + 1) * 64 + ln) * 4 + w] = um[w];
+      sFIp[((((it * 2 + ks) * 3) + 2) * 64 + ln) * 4 + w] = ul[w];
+    }
   }
   for (int e = threadIdx.x; e < nH * kCols * 32; e += blockDim.x) {
     const int b = e >> 5, j = e & 31;
@@ -57,8 +107,23 @@ __global__ __launch_bounds__(256, 1) void resid2_f32_kernel(const ResidFused2 p)
   const uint32_t slab_bytes = (uint32_t)(nIJ * 4);
   double r2 = 0.0, x2 = 0.0;
 
+  // the A operand of stage 1, T[a][j = l32][j' = 2 k + kh] (k = 0..15), is
+  // loaded one slab ahead so the multiplies never wait on it
+  auto load_t = [&](int slab, float (&t)[16]) {
+    const float* Ta = p.T + (int64_t)min(slab, A32 - 1) * p.cI * p.cJ;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+      const int jp = 2 * k + kh;
+      t[k] = (slab < A32 && l32 < p.cI && jp < p.cJ) ? Ta[l32 * p.cJ + jp] : 0.0f;
+    }
+  };
+  float tnext[16];
+  load_t(gwave, tnext);
   for (int slab = gwave; slab < A32; slab += nwaves) {
-    const float* Ta = p.T + (int64_t)slab * p.cI * p.cJ;
+    float tcur[16];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) tcur[k] = tnext[k];
+    load_t(slab + nwaves, tnext);
     const float* base = p.X + (int64_t)slab * nIJ;
     const __amdgpu_buffer_rsrc_t rs =
         __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(base), (short)0, (int)slab_bytes, kRsrcWord3);
@@ -76,16 +141,6 @@ __global__ __launch_bounds__(256, 1) void resid2_f32_kernel(const ResidFused2 p)
       // tiles live instead of four; stage 1 costs the same either way
 #pragma unroll 1
       for (int q = 0; q < 2; ++q) {
-        // stage 1: P_c[j][n] = sum_j' T[a][j][j'] F_J[b0 + 4 n + c][j'], c = 2 q + {0, 1}
-        floatx16 P0 = floatx16{}, P1 = floatx16{};
-#pragma unroll 4
-        for (int k = 0; k < 16; ++k) {
-          // A = T[a][j = l32][j' = 2 k + kh] (4 KB per slab, cache resident)
-          const int jp = 2 * k + kh;
-          const float t = (l32 < p.cI && jp < p.cJ) ? Ta[l32 * p.cJ + jp] : 0.0f;
-          P0 = mfma32(t, sFJ[(b + 2 * q) * 32 + jp], P0);
-          P1 = mfma32(t, sFJ[(b + 2 * q + 1) * 32 + jp], P1);
-        }
         auto load_unit = [&](int it, floatx2 (&buf)[16]) {
           // lanes past the column tail point far outside the range: they read zero
 #pragma unroll
@@ -96,15 +151,56 @@ __global__ __launch_bounds__(256, 1) void resid2_f32_kernel(const ResidFused2 p)
             buf[v] = __builtin_amdgcn_raw_buffer_load_b64(rs, off, 0, 2);
           }
         };
+        // the first row tile of X is in flight during stage 1
+        floatx2 bufA[16], bufB[16];
+        load_unit(0, bufA);
+        // stage 1: P_c[j][n] = sum_j' T[a][j][j'] F_J[b0 + 4 n + c][j'], c = 2 q + {0, 1}
+        floatx16 P0 = floatx16{}, P1 = floatx16{};
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+          // A = T[a][j = l32][j' = 2 k + kh]
+          const int jp = 2 * k + kh;
+          P0 = mfma32(tcur[k], sFJ[(b + 2 * q) * 32 + jp], P0);
+          P1 = mfma32(tcur[k], sFJ[(b + 2 * q + 1) * 32 + jp], P1);
+        }
+        // P in BF16 pieces as the B operand of stage 2: step ks takes the
+        // accumulator registers 8 ks .. 8 ks + 7 (j = 8 (v/4) + 4 kh + v%4)
+        bf16x8 ph0[2][3], ph1[2][3];
+#pragma unroll
+        for (int ks = 0; ks < 2; ++ks) {
+          float x0[8], x1[8];
+#pragma unroll
+          for (int v = 0; v < 8; ++v) {
+            x0[v] = P0[8 * ks + v];
+            x1[v] = P1[8 * ks + v];
+          }
+          split3(x0, ph0[ks][0], ph0[ks][1], ph0[ks][2]);
+          split3(x1, ph1[ks][0], ph1[ks][1], ph1[ks][2]);
+        }
         auto unit = [&](int it, const floatx2 (&xb)[16]) {
+          // stage 2: X_hat tile = F_I P from six BF16 piece products per K
+          // step (hh, hm, mh, hl, mm, lh; the dropped ones are ~2^-27
+          // relative), each exact in the FP32 accumulator
           floatx16 o0 = floatx16{}, o1 = floatx16{};
 #pragma unroll
-          for (int v = 0; v < 16; ++v) {
-            // K pair {j, j + 4}, j = 8 (v/4) + v%4; A = F_I[it*32 + l32][j + 4 kh]
-            const int j = 8 * (v >> 2) + 4 * kh + (v & 3);
-            const float f = sFI[(it * 32 + l32) * 32 + j];
-            o0 = mfma32(f, P0[v], o0);
-            o1 = mfma32(f, P1[v], o1);
+          for (int ks = 0; ks < 2; ++ks) {
+            const uint32_t* fa = sFIp + (((it * 2 + ks) * 3) * 64 + lane) * 4;
+            bf16x8 a[3];
+#pragma unroll
+            for (int pc = 0; pc < 3; ++pc)
+              a[pc] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uintx4*>(fa + pc * 64 * 4));
+            o0 = mma_bf16(a[0], ph0[ks][0], o0);
+            o1 = mma_bf16(a[0], ph1[ks][0], o1);
+            o0 = mma_bf16(a[0], ph0[ks][1], o0);
+            o1 = mma_bf16(a[0], ph1[ks][1], o1);
+            o0 = mma_bf16(a[1], ph0[ks][0], o0);
+            o1 = mma_bf16(a[1], ph1[ks][0], o1);
+            o0 = mma_bf16(a[0], ph0[ks][2], o0);
+            o1 = mma_bf16(a[0], ph1[ks][2], o1);
+            o0 = mma_bf16(a[1], ph0[ks][1], o0);
+            o1 = mma_bf16(a[1], ph1[ks][1], o1);
+            o0 = mma_bf16(a[2], ph0[ks][0], o0);
+            o1 = mma_bf16(a[2], ph1[ks][0], o1);
           }
 #pragma unroll
           for (int v = 0; v < 16; ++v) {
@@ -123,19 +219,20 @@ __global__ __launch_bounds__(256, 1) void resid2_f32_kernel(const ResidFused2 p)
             }
           }
         };
-        // stage 2 over row tiles with the next tile of X in flight
-        floatx2 bufA[16], bufB[16];
-        load_unit(0, bufA);
+        // stage 2 over row tiles with the next tile of X in flight; every
+        // step issues the next tile's loads (past n_I they read zero), so the
+        // waits count loads instead of waiting for all of them
+        int it = 0;
 #pragma unroll 1
-        for (int it = 0; it < nIt; it += 2) {
-          if (it + 1 < nIt) load_unit(it + 1, bufB);
+        for (; it + 2 <= nIt; it += 2) {
+          load_unit(it + 1, bufB);
           __builtin_amdgcn_sched_barrier(0);
           unit(it, bufA);
-          if (it + 1 >= nIt) break;
-          if (it + 2 < nIt) load_unit(it + 2, bufA);
+          load_unit(it + 2, bufA);
           __builtin_amdgcn_sched_barrier(0);
           unit(it + 1, bufB);
         }
+        if (it < nIt) unit(it, bufA);
       }
     }
   }
@@ -177,7 +274,8 @@ __global__ __launch_bounds__(256) void resid_sum_kernel(const double* partials, 
 }  // namespace
 
 size_t resid2_lds_bytes(int nI, int nJ) {
-  return (size_t)(((nI + 31) / 32) * 32 + ((nJ + kCols - 1) / kCols) * kCols) * 32 * sizeof(float);
+  // F_I pieces (6 KB per 32-row tile) and F_J in FP32
+  return (size_t)((nI + 31) / 32) * 2 * 3 * 64 * 16 + (size_t)((nJ + kCols - 1) / kCols) * kCols * 32 * sizeof(float);
 }
 
 bool resid2_supported(int dtype, int order, const int64_t* dims, const int32_t* cols) {
@@ -187,11 +285,12 @@ bool resid2_supported(int dtype, int order, const int64_t* dims, const int32_t* 
   for (int k = 0; k < order - 2; ++k) A *= dims[k];
   if (nI > 1024 || nJ > 1024 || A >= (int64_t(1) << 31)) return false;
   return nJ % 4 == 0 && nJ >= 64 && cols[order - 2] <= 32 && cols[order - 1] <= 32 && A >= 256 &&
-         resid2_lds_bytes((int)nI, (int)nJ) <= 64 * 1024;
+         resid2_lds_bytes((int)nI, (int)nJ) <= 128 * 1024;
 }
 
 int64_t resid2_waves(int64_t A) {
-  return std::max<int64_t>(1, std::min<int64_t>(ceil_div(A, kWaves), 1024)) * kWaves;
+  // one workgroup per CU on 256 CUs: every wave resident, persistent over slabs
+  return std::max<int64_t>(1, std::min<int64_t>(ceil_div(A, kWaves), 256)) * kWaves;
 }
 
 hipError_t launch_resid2_f32(const ResidFused2& pin, hipStream_t st) {
