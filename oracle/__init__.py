@@ -25,5 +25,6 @@ from .tucker import (gather_fibers, range_sketch, orth, w_step, sub_r_hosvd,  # 
 from .htucker import (sub_r_rtl_ht, transfer_tensor, root_transfer, ht_full, ht_bases,  # noqa: F401
                       ht_rel_error, gather_node, kron_cols)
 from .grads import core_vjp, reconstruct_vjp, loss_and_grads  # noqa: F401
+from .sampling import philox4x64_10, draw_indices, draw_omega, box_muller  # noqa: F401
 from .brute import (t_hosvd, rtl_ht, unfolding_tail, lower_bound_sq, rhosvd_factor,  # noqa: F401
                     rangefinder_factor, thm34_factor, sampling_event, ht_tails_sq)
