@@ -113,6 +113,22 @@ def streaming_ceiling(X, reps=5):
     return X.numel() * X.element_size() / (ms * 1e-3) / 1e9
 
 
+def device_draw_ms(ncols, ss, ells, fdt, reps=5):
+    """Time of the seeded device-side draw of the same sketch shapes
+    (indices and Omega for every mode), in ms."""
+    import torch
+    from paper_2603_21379_amd import binding as B
+    B.draw_sketches(ncols, ss, ells, 1, omega_dtype=fdt)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for r in range(reps):
+        B.draw_sketches(ncols, ss, ells, 2 + r, omega_dtype=fdt)
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
 def copy_calibration():
     import torch
     nbytes = 4 << 30
@@ -178,13 +194,19 @@ def main():
     ells = synthgen.default_ell(dims, ranks, cfg.p)
     ss = synthgen.default_s(dims, cfg.alpha)
     omega_dt = synthgen.factor_dtype(dtype)
+    t_sk = time.perf_counter()
     sk = synthgen.mode_sketches(dims, ells, ss, cfg=cfg.cfg_id, omega_dtype=omega_dt)
+    ms_host_sketch = (time.perf_counter() - t_sk) * 1e3
     log(f"generated in {time.time() - t0:.1f}s; uploading")
     Xh = inp.X.view(np.int16) if dtype == "bf16" else inp.X
     X = torch.from_numpy(Xh).to(dev)
     if dtype == "bf16":
         X = X.view(torch.bfloat16)
+    torch.cuda.synchronize()
+    t_up = time.perf_counter()
     skd = T.mode_sketches_to_device(sk, dims, dev, fdt)
+    torch.cuda.synchronize()
+    ms_upload_sketch = (time.perf_counter() - t_up) * 1e3
 
     d = len(dims)
     cols = list(ranks) if args.core == "U" else list(ells)
@@ -267,6 +289,9 @@ def main():
     log(f"eps_gpu = {eps:.6e}, info = {info_h}; residual pass {ms_resid:.3f} ms")
     ceiling = streaming_ceiling(X)
     log(f"read-only streaming reference over X: {ceiling:.1f} GB/s")
+    ms_device_draw = device_draw_ms([N // n for n in dims], ss, ells, fdt)
+    log(f"sketch operands: device draw {ms_device_draw:.3f} ms; host generation "
+        f"{ms_host_sketch:.1f} ms + upload {ms_upload_sketch:.2f} ms")
 
     result = {
         "metric": "tensor GB/s streamed (sketch+core), frac of HBM roofline; rel err vs FP64 oracle",
@@ -300,6 +325,9 @@ def main():
                      "frac_of_ceiling": round(achieved / ceiling, 4)},
         "sketch_core_frac_of_ceiling": round(sketch_core_gbs / ceiling, 4),
         "ms_resid": round(ms_resid, 4),
+        "sketch_draw": {"ms_device": round(ms_device_draw, 4),
+                        "ms_host_generate": round(ms_host_sketch, 2),
+                        "ms_upload": round(ms_upload_sketch, 3)},
         "resid_gbs": round(b_core / (ms_resid * 1e-3) / 1e9, 1),
     }
     del Y, Z

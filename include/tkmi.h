@@ -6,8 +6,8 @@
  * Sub-R-RtL-HT (Algorithm 2: [{U_k}, {B_S}] = Sub-R-RtL-HT(X, T, r, w, p)) of
  * "A practical mode-parallel implementation of the (H-)Tucker decomposition
  * via randomization".  The random quantities of those algorithms (the fiber
- * samples E_k and the Gaussian matrices Omega_k) are drawn by the caller and
- * passed in.
+ * samples E_k and the Gaussian matrices Omega_k) are passed in: drawn by the
+ * caller, or on the device by tucker_draw_sketches from a seeded stream.
  *
  * Conventions shared by every entry point
  *  - Layout: dense tensors are C-ordered (last mode fastest).  The column
@@ -248,6 +248,26 @@ tk_status tucker_batch_plan_create(int32_t count, const tk_tensor* X, const int3
 tk_status tucker_batch_run(const tk_batch_plan* plan, void* stream);
 tk_status tucker_batch_autotune(tk_batch_plan* plan, void* stream, char* report, size_t report_bytes);
 void tucker_batch_plan_destroy(tk_batch_plan* plan);
+
+/* Seeded device-side draw of sampled sketches (the sampling of Algorithm 1,
+ * Section 3.1: column indices uniform without repetition and a Gaussian
+ * test matrix), so no host generation or upload is needed.  For each unit
+ * k < nunits (nunits <= 32):
+ *   idx[k]   device int64[s[k]]: s[k] distinct indices of [0, ncols[k]),
+ *            sorted ascending (Floyd's algorithm);
+ *   omega[k] device [s[k]][ell[k]] row-major, omega_dtype TK_F32 or TK_F64:
+ *            standard normals (Box-Muller, computed in FP64);
+ * both from Philox4x64-10 keyed by (seed, k): index step i uses word 0 of the
+ * block at counter (i, 0, 0, 0) and takes t = floor(w (j + 1) / 2^64) for
+ * j = ncols - s + i (t if not yet chosen, else j); Omega[t][e] uses words 0
+ * and 1 of the block at counter (t ell + e, 1, 0, 0) as
+ * u1 = ((w0 >> 11) + 1) 2^-53, u2 = (w1 >> 11) 2^-53, sqrt(-2 ln u1) cos(2 pi u2).
+ * Asynchronous on `stream`; the caller owns idx and omega.
+ * Errors: TK_EINVAL (nunits outside [1, 32], s > ncols, s > 4096, ell < 1,
+ * NULL buffers for s > 0, other omega dtypes), TK_EDEVICE. */
+tk_status tucker_draw_sketches(int32_t nunits, const int64_t* ncols, const int32_t* s, const int32_t* ell,
+                               uint64_t seed, int64_t* const* idx, void* const* omega, int32_t omega_dtype,
+                               void* stream);
 
 /* Profiling of the streaming pass.  While enabled, every tucker_core,
  * tucker_reconstruct and htucker_decompose call brackets the kernel that

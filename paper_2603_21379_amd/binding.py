@@ -55,7 +55,7 @@ EXPORTS = ("tucker_sketch_all_modes", "tucker_qr", "tucker_core", "tucker_recons
            "htucker_decompose", "tucker_core_vjp", "tucker_reconstruct_vjp", "tk_last_error",
            "tk_version", "tk_profile_enable", "tk_profile_read", "tucker_batch_plan_create",
            "tucker_batch_run", "tucker_batch_autotune", "tucker_batch_plan_destroy",
-           "tk_stream_read_blocks", "tk_stream_read")
+           "tk_stream_read_blocks", "tk_stream_read", "tucker_draw_sketches")
 
 
 def lib():
@@ -80,6 +80,9 @@ def lib():
             L.tk_stream_read_blocks.restype = C.c_int32
             L.tk_stream_read.argtypes = [vp, C.c_int64, vp, C.c_int32, vp]
             L.tk_stream_read.restype = C.c_int
+            L.tucker_draw_sketches.argtypes = [C.c_int32, i64p, i32p, i32p, C.c_uint64, pp, pp,
+                                               C.c_int32, vp]
+            L.tucker_draw_sketches.restype = C.c_int
             sig = {
                 "tucker_sketch_all_modes": [C.POINTER(TkTensor), C.POINTER(TkSketch), pp, pp, vp, sz, vp],
                 "tucker_qr": [C.c_int32, i64p, i32p, pp, pp, C.c_int32, i64p, i32p, pp, C.c_int32,
@@ -349,6 +352,23 @@ def tk_profile_read(reset: bool = True):
     ms, n = C.c_double(0), C.c_int64(0)
     _check("tk_profile_read", lib().tk_profile_read(C.byref(ms), C.byref(n), 1 if reset else 0))
     return ms.value, n.value
+
+
+def draw_sketches(ncols, s, ell, seed, omega_dtype=None, device="cuda", stream=None):
+    """Seeded device-side draw (tucker_draw_sketches): per unit k, the sorted
+    int64 indices (s[k]) and the Gaussian Omega (s[k] x ell[k]); lists of
+    device tensors."""
+    omega_dtype = omega_dtype or torch.float32
+    n = len(ncols)
+    idx = [torch.empty(int(sk), dtype=torch.int64, device=device) for sk in s]
+    om = [torch.empty(int(sk), int(ek), dtype=omega_dtype, device=device) for sk, ek in zip(s, ell)]
+    odt = {torch.float32: 1, torch.float64: 0}[omega_dtype]
+    _check("tucker_draw_sketches", lib().tucker_draw_sketches(
+        n, (C.c_int64 * n)(*[int(v) for v in ncols]), (C.c_int32 * n)(*[int(v) for v in s]),
+        (C.c_int32 * n)(*[int(v) for v in ell]), C.c_uint64(int(seed) & ((1 << 64) - 1)),
+        (C.c_void_p * n)(*[t.data_ptr() for t in idx]), (C.c_void_p * n)(*[t.data_ptr() for t in om]),
+        odt, _stream(stream)))
+    return idx, om
 
 
 def stream_read_blocks() -> int:

@@ -832,6 +832,35 @@ tk_status tk_profile_read(double* ms, int64_t* launches, int32_t reset) {
 }
 const char* tk_version(void) { return "tkmi 0.1 (gfx950)"; }
 
+tk_status tucker_draw_sketches(int32_t nunits, const int64_t* ncols, const int32_t* s, const int32_t* ell,
+                               uint64_t seed, int64_t* const* idx, void* const* omega, int32_t omega_dtype,
+                               void* stream) {
+  clear_error();
+  if (nunits < 1 || nunits > kMaxUnits)
+    return set_error(TK_EINVAL, "tucker_draw_sketches: nunits %d outside [1, %d]", nunits, kMaxUnits);
+  if (!ncols || !s || !ell || !idx || !omega)
+    return set_error(TK_EINVAL, "tucker_draw_sketches: NULL array argument");
+  if (omega_dtype != TK_F32 && omega_dtype != TK_F64)
+    return set_error(TK_EINVAL, "tucker_draw_sketches: omega_dtype must be TK_F32 or TK_F64");
+  DrawBatch b{};
+  b.count = nunits;
+  b.seed = seed;
+  b.omega_dtype = omega_dtype;
+  int smax = 1;
+  for (int k = 0; k < nunits; ++k) {
+    if (ncols[k] < 1 || s[k] < 0 || s[k] > ncols[k] || s[k] > kDrawMaxS || ell[k] < 1)
+      return set_error(TK_EINVAL, "tucker_draw_sketches: unit %d: need 0 <= s <= min(ncols, %d), ell >= 1 "
+                       "(ncols %lld, s %d, ell %d)", k, kDrawMaxS, (long long)ncols[k], s[k], ell[k]);
+    if (s[k] > 0 && (!idx[k] || !omega[k]))
+      return set_error(TK_EINVAL, "tucker_draw_sketches: unit %d: idx or omega is NULL", k);
+    b.u[k] = DrawUnit{ncols[k], idx[k], omega[k], s[k], ell[k]};
+    b.omega_begin[k + 1] = b.omega_begin[k] + (int64_t)s[k] * ell[k];
+    smax = std::max(smax, (int)s[k]);
+  }
+  TK_HIP(launch_draw(b, smax, as_stream(stream)));
+  return TK_OK;
+}
+
 int32_t tk_stream_read_blocks(void) { return (int32_t)stream_read_blocks(); }
 
 tk_status tk_stream_read(const void* x, int64_t bytes, double* partials, int32_t npartials, void* stream) {

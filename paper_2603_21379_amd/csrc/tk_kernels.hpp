@@ -324,4 +324,22 @@ hipError_t launch_to_f64(const void* in, int in_dt, double* out, int64_t n, hipS
 int stream_read_blocks();
 hipError_t launch_stream_read(const void* x, int64_t bytes, double* partials, int32_t blocks, hipStream_t st);
 
+// ---------------------------------------------------------------- seeded sketch draw
+constexpr int kDrawMaxS = 4096;   // fibers per sketch (LDS hash set and sort)
+struct DrawUnit {
+  int64_t ncols;        // columns of the unfolding
+  int64_t* idx;         // [s] out: sorted distinct indices
+  void* omega;          // [s][ell] out: Gaussian test matrix
+  int32_t s, ell;
+};
+struct DrawBatch {
+  DrawUnit u[kMaxUnits];
+  int64_t omega_begin[kMaxUnits + 1];   // prefix of s ell
+  uint64_t seed;
+  int32_t count;
+  int32_t omega_dtype;
+};
+size_t draw_indices_lds_bytes(int smax);
+hipError_t launch_draw(const DrawBatch& b, int smax, hipStream_t st);
+
 }  // namespace tk
