@@ -5,11 +5,16 @@
 //
 // Stream: Philox4x64-10 (Salmon, Moraes, Dror, Shaw, SC 2011) keyed by
 // (seed, unit), unit = the sketch's position in the call.
-// * indices: Floyd's algorithm.  Step i = 0..s-1 considers j = N - s + i,
-//   draws t = high 64 bits of w (j + 1), w = word 0 of the block at counter
-//   (i, 0, 0, 0), and takes t if it is new, else j.  The draws are made by
-//   all threads at once; one thread then walks the steps against a hash set
-//   in LDS, and the workgroup sorts the result (bitonic, in LDS).
+// * indices: Floyd's algorithm.  Step i = 0..s-1 considers j_i = N - s + i,
+//   draws t_i = high 64 bits of w (j_i + 1), w = word 0 of the block at
+//   counter (i, 0, 0, 0), and takes t_i if it is new, else j_i.  The walk is
+//   resolved in parallel: after step i-1 the chosen set is every earlier
+//   draw t_k together with j_k for each earlier step k that was rejected, so
+//   step i is rejected exactly when t_i repeats an earlier draw or equals j_k
+//   of a rejected step k < i (k = t_i - (N - s)).  Repeats are found by
+//   sorting the pairs (t_i, i); the second condition is a chain to a strictly
+//   earlier step, resolved by pointer jumping in ceil(log2 s) rounds; the
+//   chosen values are then sorted (bitonic sorts in LDS, 1024 threads).
 // * Omega[t][e]: the block at counter (t ell + e, 1, 0, 0) gives
 //   u1 = ((w0 >> 11) + 1) 2^-53, u2 = (w1 >> 11) 2^-53 and the normal
 //   sqrt(-2 ln u1) cos(2 pi u2) (FP64, stored as FP32 or FP64).
@@ -20,8 +25,7 @@ namespace {
 
 constexpr uint64_t kM0 = 0xD2E7470EE14C6C93ull, kM1 = 0xCA5A826395121157ull;
 constexpr uint64_t kW0 = 0x9E3779B97F4A7C15ull, kW1 = 0xBB67AE8584CAA73Bull;
-constexpr int kHashBits = 13;               // 8192-slot table for s <= 4096
-constexpr int64_t kEmpty = -1;
+constexpr int kDrawThreads = 1024;
 
 struct Block4 {
   uint64_t w[4];
@@ -44,66 +48,96 @@ __device__ __forceinline__ Block4 philox4x64_10(uint64_t c0, uint64_t c1, uint64
   return Block4{{c0, c1, c2, c3}};
 }
 
-__global__ __launch_bounds__(256) void draw_indices_kernel(const DrawBatch b) {
-  extern __shared__ int64_t dl[];
-  const DrawUnit& U = b.u[blockIdx.x];
-  const int s = U.s, tid = threadIdx.x;
-  if (s == 0) return;
-  int P = 1;
-  while (P < s) P <<= 1;
-  int64_t* sel = dl;                 // [P]: draws, then the chosen set, then sorted
-  int64_t* tab = dl + P;             // [1 << kHashBits]: hash set of chosen indices
-  const uint64_t key0 = b.seed, key1 = (uint64_t)blockIdx.x;
-  for (int i = tid; i < P; i += 256) {
-    if (i < s) {
-      const uint64_t w = philox4x64_10((uint64_t)i, 0, 0, 0, key0, key1).w[0];
-      const uint64_t j = (uint64_t)(U.ncols - s + i);
-      sel[i] = (int64_t)__umul64hi(w, j + 1);   // uniform on [0, j]
-    } else {
-      sel[i] = INT64_MAX;                       // padding sorts last
-    }
-  }
-  for (int i = tid; i < (1 << kHashBits); i += 256) tab[i] = kEmpty;
-  __syncthreads();
-  if (tid == 0) {
-    // Floyd: take t unless already chosen, then take j (never chosen before)
-    for (int i = 0; i < s; ++i) {
-      const int64_t t = sel[i];
-      uint32_t h = (uint32_t)(((uint64_t)t * kW0) >> (64 - kHashBits));
-      bool found = false;
-      while (tab[h] != kEmpty) {
-        if (tab[h] == t) { found = true; break; }
-        h = (h + 1) & ((1u << kHashBits) - 1);
-      }
-      int64_t v = t;
-      if (found) {
-        v = U.ncols - s + i;
-        h = (uint32_t)(((uint64_t)v * kW0) >> (64 - kHashBits));
-        while (tab[h] != kEmpty) h = (h + 1) & ((1u << kHashBits) - 1);
-      }
-      tab[h] = v;
-      sel[i] = v;
-    }
-  }
-  __syncthreads();
-  // bitonic sort of sel[0..P) ascending
-  for (int k = 2; k <= P; k <<= 1) {
+// Ascending bitonic sort of n = 2^m keys (with an optional payload that
+// breaks ties), by the whole workgroup.
+template <bool kPayload>
+__device__ void bitonic_sort(int64_t* key, int32_t* pay, int n) {
+  const int half = n >> 1;
+  for (int k = 2; k <= n; k <<= 1) {
     for (int jj = k >> 1; jj > 0; jj >>= 1) {
-      for (int i = tid; i < P; i += 256) {
-        const int l = i ^ jj;
-        if (l > i) {
-          const int64_t a = sel[i], c = sel[l];
-          const bool up = (i & k) == 0;
-          if ((a > c) == up) {
-            sel[i] = c;
-            sel[l] = a;
+      for (int q = threadIdx.x; q < half; q += kDrawThreads) {
+        const int i = 2 * jj * (q / jj) + q % jj, l = i + jj;
+        const int64_t a = key[i], c = key[l];
+        bool gt = a > c;
+        if (kPayload) gt = gt || (a == c && pay[i] > pay[l]);
+        if (gt == ((i & k) == 0)) {
+          key[i] = c;
+          key[l] = a;
+          if (kPayload) {
+            const int32_t t = pay[i];
+            pay[i] = pay[l];
+            pay[l] = t;
           }
         }
       }
       __syncthreads();
     }
   }
-  for (int i = tid; i < s; i += 256) U.idx[i] = sel[i];
+}
+
+__global__ __launch_bounds__(kDrawThreads) void draw_indices_kernel(const DrawBatch b) {
+  extern __shared__ int64_t dl[];
+  const DrawUnit& U = b.u[blockIdx.x];
+  const int s = U.s, tid = threadIdx.x;
+  if (s == 0) return;
+  int P = 1;
+  while (P < s) P <<= 1;
+  int64_t* key = dl;                                        // [P] draws, then the chosen set
+  int32_t* pos = reinterpret_cast<int32_t*>(dl + P);        // [P] step of each draw
+  int32_t* link = pos + P;                                  // [P] by step: rejected << 16 | (k + 1)
+  const int64_t j0 = U.ncols - s;                           // j_i = j0 + i
+  const uint64_t key0 = b.seed, key1 = (uint64_t)blockIdx.x;
+  for (int i = tid; i < P; i += kDrawThreads) {
+    if (i < s) {
+      const uint64_t w = philox4x64_10((uint64_t)i, 0, 0, 0, key0, key1).w[0];
+      key[i] = (int64_t)__umul64hi(w, (uint64_t)(j0 + i) + 1);   // uniform on [0, j_i]
+    } else {
+      key[i] = INT64_MAX;                                        // padding sorts last
+    }
+    pos[i] = i;
+  }
+  __syncthreads();
+  bitonic_sort<true>(key, pos, P);
+  // a draw repeats an earlier one iff its predecessor in (t, i) order has the
+  // same t; the chain link goes to the step whose j_k equals t_i, if earlier
+  for (int p = tid; p < s; p += kDrawThreads) {
+    const int64_t t = key[p];
+    const int i = pos[p];
+    const int rep = (p > 0 && key[p - 1] == t) ? 1 : 0;
+    const int k = (t >= j0 && t - j0 < i) ? (int)(t - j0) : -1;
+    link[i] = (rep << 16) | (k + 1);
+  }
+  __syncthreads();
+  for (int span = 1; span < s; span <<= 1) {
+    int32_t nv[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int i = tid + r * kDrawThreads;
+      if (i < s) {
+        int32_t v = link[i];
+        const int k = (v & 0xFFFF) - 1;
+        if (k >= 0) {
+          const int32_t w = link[k];
+          v = ((v | w) & 0x10000) | (w & 0xFFFF);
+        }
+        nv[r] = v;
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int i = tid + r * kDrawThreads;
+      if (i < s) link[i] = nv[r];
+    }
+    __syncthreads();
+  }
+  for (int p = tid; p < s; p += kDrawThreads) {
+    const int i = pos[p];
+    if (link[i] >> 16) key[p] = j0 + i;
+  }
+  __syncthreads();
+  bitonic_sort<false>(key, nullptr, P);
+  for (int i = tid; i < s; i += kDrawThreads) U.idx[i] = key[i];
 }
 
 template <typename TO>
@@ -126,12 +160,12 @@ __global__ __launch_bounds__(256) void draw_omega_kernel(const DrawBatch b) {
 size_t draw_indices_lds_bytes(int smax) {
   int P = 1;
   while (P < smax) P <<= 1;
-  return ((size_t)P + ((size_t)1 << kHashBits)) * sizeof(int64_t);
+  return (size_t)P * (sizeof(int64_t) + 2 * sizeof(int32_t));
 }
 
 hipError_t launch_draw(const DrawBatch& b, int smax, hipStream_t st) {
   if (b.count == 0) return hipSuccess;
-  hipLaunchKernelGGL(draw_indices_kernel, dim3(b.count), dim3(256), draw_indices_lds_bytes(smax), st, b);
+  hipLaunchKernelGGL(draw_indices_kernel, dim3(b.count), dim3(kDrawThreads), draw_indices_lds_bytes(smax), st, b);
   const int64_t n = b.omega_begin[b.count];
   if (n > 0) {
     const dim3 grid((unsigned)ceil_div(n, 256));

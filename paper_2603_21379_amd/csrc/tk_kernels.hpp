@@ -325,7 +325,7 @@ int stream_read_blocks();
 hipError_t launch_stream_read(const void* x, int64_t bytes, double* partials, int32_t blocks, hipStream_t st);
 
 // ---------------------------------------------------------------- seeded sketch draw
-constexpr int kDrawMaxS = 4096;   // fibers per sketch (LDS hash set and sort)
+constexpr int kDrawMaxS = 4096;   // fibers per sketch (LDS sort of at most 4096 keys)
 struct DrawUnit {
   int64_t ncols;        // columns of the unfolding
   int64_t* idx;         // [s] out: sorted distinct indices

@@ -43,6 +43,20 @@ def test_draw_matches_oracle_stream(dtype):
                                        rtol=2.0 ** -23, atol=1e-30)
 
 
+@pytest.mark.parametrize("case", range(4))
+def test_draw_indices_dense_collisions(case):
+    # small column ranges with s close to ncols: most steps collide and the
+    # rejected steps chain into each other; also the full and nearly full draw
+    # at the size limit
+    rng = np.random.default_rng(1000 + case)
+    ncols = [int(n) for n in rng.integers(1, 80, size=30)] + [4096, 4097]
+    s = [int(rng.integers(max(0, n - 8), n + 1)) for n in ncols[:30]] + [4096, 4096]
+    seed = int(rng.integers(0, 2 ** 63))
+    idx, _ = _draw(ncols, s, [1] * len(ncols), seed, torch.float64)
+    for k in range(len(ncols)):
+        np.testing.assert_array_equal(idx[k], oracle.draw_indices(ncols[k], s[k], seed, k))
+
+
 def test_draw_rejects_bad_sizes():
     from paper_2603_21379_amd import binding as B
     with pytest.raises(B.TkError):
