@@ -23,7 +23,7 @@ from .tucker import (gather_fibers, range_sketch, orth, w_step, sub_r_hosvd,  # 
                      core, core_streamed, core_chunked, reconstruct, rel_error, mode_errors,
                      projector_distance, canonical_signs)
 from .htucker import (sub_r_rtl_ht, transfer_tensor, root_transfer, ht_full, ht_bases,  # noqa: F401
-                      ht_rel_error, gather_node, kron_cols)
+                      ht_rel_error, gather_node, kron_cols, ht_full_vjp)
 from .grads import core_vjp, reconstruct_vjp, loss_and_grads  # noqa: F401
 from .sampling import philox4x64_10, draw_indices, draw_omega, box_muller  # noqa: F401
 from .brute import (t_hosvd, rtl_ht, unfolding_tail, lower_bound_sq, rhosvd_factor,  # noqa: F401

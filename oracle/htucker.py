@@ -109,3 +109,43 @@ def ht_rel_error(X: np.ndarray, tree, U: dict, B: dict) -> float:
     leaves = {t: U[t] for t in U if tree.is_leaf(t)}
     Xh = ht_full(X.shape, tree, leaves, B)
     return float(math.sqrt(np.sum((X - Xh) ** 2) / np.sum(X ** 2)))
+
+
+def ht_full_vjp(dims, tree, leaf_bases: dict, B: dict, H: np.ndarray):
+    """Vector-Jacobian product of the H-Tucker format's full tensor (ht_full)
+    with respect to its parameters, the leaf bases and the transfer tensors.
+
+    The paper does not differentiate the format; this is the chain rule
+    through its two defining relations (Section 4): at the root
+    X^(Rl) = U_Rl B_R U_Rr^T, so with H^(Rl) the adjoint viewed the same way
+        B_R_bar = U_Rl^T H U_Rr,  U_Rl_bar = H U_Rr B_R^T,  U_Rr_bar = H^T U_Rl B_R,
+    and at an internal node U_S = (U_Sl kron U_Sr) (B_S^(1))^T (nestedness), so
+    with K = U_Sl kron U_Sr (columns (j, k) C-order)
+        B_S_bar^(1) = U_S_bar^T K,  K_bar = U_S_bar B_S^(1),
+        U_Sl_bar[a, j] = sum_{b,k} K_bar[(a,b), (j,k)] U_Sr[b, k],
+        U_Sr_bar[b, k] = sum_{a,j} K_bar[(a,b), (j,k)] U_Sl[a, j],
+    applied from the root's children down to the leaves (each node's basis
+    feeds only its parent, so every adjoint has one term).  Returns
+    (B_bar for every internal node including the root 0, U_bar for the leaves),
+    FP64."""
+    nb = ht_bases(tree, leaf_bases, B)
+    L, R = tree.left[0], tree.right[0]
+    Hm = np.asarray(H, dtype=np.float64).reshape(nb[L].shape[0], nb[R].shape[0])
+    BR = B[0][0]
+    Bbar = {0: (nb[L].T @ Hm @ nb[R])[None]}
+    Ubar = {L: Hm @ nb[R] @ BR.T, R: Hm.T @ nb[L] @ BR}
+    order = sorted(range(1, tree.num_nodes), key=lambda t: tree.level[t])   # parents first
+    for t in order:
+        if tree.is_leaf(t):
+            continue
+        l, r = tree.left[t], tree.right[t]
+        Ul, Ur = nb[l], nb[r]
+        rS, rl, rr = B[t].shape
+        K = kron_cols(Ul, Ur)
+        B1 = B[t].reshape(rS, rl * rr)
+        Bbar[t] = (Ubar[t].T @ K).reshape(rS, rl, rr)
+        Kbar = (Ubar[t] @ B1).reshape(Ul.shape[0], Ur.shape[0], rl, rr)
+        Ubar[l] = np.einsum("abjk,bk->aj", Kbar, Ur)
+        Ubar[r] = np.einsum("abjk,aj->bk", Kbar, Ul)
+    return Bbar, {t: Ubar[t] for t in Ubar if tree.is_leaf(t)}
+

@@ -360,6 +360,29 @@ def ht_tensor(n: int, order: int, rank: int, noise: float, cfg: int, dtype: str 
     return HTInput(dims, X, dtype, tr, leaf, trans, root, scale, noise)
 
 
+def inverse_norm_tensor(n: int, order: int, dtype: str = "f32", threads: int | None = None) -> np.ndarray:
+    """X(i_1, .., i_d) = (i_1^2 + .. + i_d^2)^(-1/2) for i_j = 1..n: the function
+    1 / ||x|| sampled on the uniform grid over [1, n]^d (the H-Tucker serial
+    tests, Section 4.2.1).  Sums of squares are exact integers; each value is
+    computed in FP64 and rounded once to the storage dtype."""
+    if order < 2 or n < 1:
+        raise ValueError("need order >= 2 and n >= 1")
+    dims = (n,) * order
+    X = np.empty(dims, dtype={"f64": np.float64, "f32": np.float32, "f16": np.float16,
+                              "bf16": np.uint16}[dtype])
+    sq = np.arange(1, n + 1, dtype=np.int64) ** 2
+    rest = sq                                   # sums over modes 2..d, C-order
+    for _ in range(order - 2):
+        rest = (rest[:, None] + sq[None, :]).reshape(-1)
+
+    def slab(i0):
+        t = 1.0 / np.sqrt((sq[i0] + rest).astype(np.float64))
+        X[i0] = to_storage(t, dtype).reshape(dims[1:])
+
+    _parallel_slabs(slab, n, threads)
+    return X
+
+
 def node_sketches(dims, tree: DimTree, ells: dict, ws: dict, cfg: int, omega_dtype: str,
                   run: int = 0):
     """Sketch operands for every non-root node S: w_S sampled columns of X^(S)."""

@@ -233,3 +233,83 @@ def test_bf16_rounding_matches_torch():
     ours = synthgen.to_f64(synthgen.to_storage(x, "bf16"), "bf16")
     ref = torch.from_numpy(x).to(torch.bfloat16).to(torch.float64).numpy()
     np.testing.assert_array_equal(ours, ref)
+
+
+# ------------------------------------------------------------------ H-Tucker format VJP
+def _ht_params(rng, dims, ranks):
+    """Random (not orthonormal) leaf bases and transfer tensors on the
+    balanced tree; ranks[t] for every non-root node."""
+    tr = synthgen.balanced_tree(len(dims))
+    U, B = {}, {}
+    for t in range(1, tr.num_nodes):
+        if tr.is_leaf(t):
+            U[t] = rng.standard_normal((dims[tr.first[t]], ranks[t]))
+    for t in range(tr.num_nodes):
+        if not tr.is_leaf(t):
+            rt = 1 if t == 0 else ranks[t]
+            B[t] = rng.standard_normal((rt, ranks[tr.left[t]], ranks[tr.right[t]]))
+    return tr, U, B
+
+
+@pytest.mark.parametrize("dims", [(3, 2, 3, 2), (2, 3, 2, 2, 3)])
+def test_ht_full_vjp_every_entry_fd(dims):
+    """<H, ht_full(theta)> is affine in every single entry of every leaf basis
+    and transfer tensor (the format is multilinear in its parameters, each
+    used once), so central differences are exact up to rounding."""
+    rng = np.random.default_rng(11 + len(dims))
+    tr = synthgen.balanced_tree(len(dims))
+    ranks = {t: 2 for t in range(1, tr.num_nodes)}
+    tr, U, B = _ht_params(rng, dims, ranks)
+    H = rng.standard_normal(dims)
+    Bbar, Ubar = oracle.ht_full_vjp(dims, tr, U, B, H)
+    assert set(Bbar) == set(B) and set(Ubar) == set(U)
+
+    def L(U_, B_):
+        return float(np.sum(H * oracle.ht_full(dims, tr, U_, B_)))
+
+    h = 1e-3
+    for t in B:
+        for i in np.ndindex(B[t].shape):
+            Bp = {k: v.copy() for k, v in B.items()}
+            Bm = {k: v.copy() for k, v in B.items()}
+            Bp[t][i] += h
+            Bm[t][i] -= h
+            fd = (L(U, Bp) - L(U, Bm)) / (2 * h)
+            assert abs(fd - Bbar[t][i]) <= 1e-9 * max(1.0, abs(fd)), (t, i)
+    for t in U:
+        for i in np.ndindex(U[t].shape):
+            Up = {k: v.copy() for k, v in U.items()}
+            Um = {k: v.copy() for k, v in U.items()}
+            Up[t][i] += h
+            Um[t][i] -= h
+            fd = (L(Up, B) - L(Um, B)) / (2 * h)
+            assert abs(fd - Ubar[t][i]) <= 1e-9 * max(1.0, abs(fd)), (t, i)
+
+
+def test_ht_full_vjp_order2_is_matrix_product_rule():
+    """Order 2: the format is U_1 B_R U_2^T; its adjoints are the textbook
+    ones of a product of three matrices."""
+    rng = np.random.default_rng(5)
+    tr, U, B = _ht_params(rng, (4, 5), {1: 3, 2: 2})
+    H = rng.standard_normal((4, 5))
+    Bbar, Ubar = oracle.ht_full_vjp((4, 5), tr, U, B, H)
+    U1, U2, BR = U[1], U[2], B[0][0]
+    np.testing.assert_allclose(oracle.ht_full((4, 5), tr, U, B), U1 @ BR @ U2.T, rtol=1e-14)
+    np.testing.assert_allclose(Bbar[0][0], U1.T @ H @ U2, rtol=1e-13)
+    np.testing.assert_allclose(Ubar[1], H @ U2 @ BR.T, rtol=1e-13)
+    np.testing.assert_allclose(Ubar[2], H.T @ U1 @ BR, rtol=1e-13)
+
+
+# ------------------------------------------------------------------ closed-form HT workload
+def test_inverse_norm_workload_values():
+    """X(i) = (sum_j i_j^2)^(-1/2) on the 1-based grid: hand-evaluated corners
+    and symmetry under permutation of the modes."""
+    X = synthgen.inverse_norm_tensor(15, 4, "f64")
+    assert X.shape == (15,) * 4
+    assert X[0, 0, 0, 0] == 0.5                              # 1 / sqrt(4)
+    assert X[14, 14, 14, 14] == 1.0 / 30.0                   # 1 / sqrt(4 * 225)
+    assert X[1, 0, 0, 0] == 1.0 / math.sqrt(7.0)            # 4 + 1 + 1 + 1
+    assert X[2, 1, 0, 0] == 1.0 / math.sqrt(15.0)           # 9 + 4 + 1 + 1
+    np.testing.assert_array_equal(X, X.transpose(2, 0, 3, 1))
+    X5 = synthgen.inverse_norm_tensor(3, 5, "f32")
+    assert X5.dtype == np.float32 and X5[2, 2, 2, 2, 2] == np.float32(1.0 / math.sqrt(45.0))
