@@ -188,6 +188,56 @@ tk_status htucker_decompose(const tk_tensor* X, const tk_tree* tree, const int32
                             const tk_sketch* sk, void* const* U, void* const* B, int32_t* info,
                             void* ws, size_t* ws_bytes, void* stream);
 
+/* Full tensor of an H-Tucker format and its residual (Section 4: the root
+ * relation X^(Rl) = U_Rl B_R U_Rr^T and the nestedness U_S = (U_Sl kron U_Sr)
+ * (B_S^(1))^T of the bases of internal nodes).  The nested bases of the
+ * internal non-root nodes are formed from the leaves upwards; the root
+ * expansion xhat[a][b] = sum_k (U_Rl B_R)[a][k] U_Rr[b][k] over the
+ * n_Rl x n_Rr matricisation is one streaming pass, fused with the residual.
+ *   order, dims  n_1 .. n_d (order >= 2).
+ *   tree    the balanced heap tree of this order (as for htucker_decompose).
+ *   rank    host int32 [num_nodes]: r_t of every node (rank[0] ignored).
+ *   U       host array [num_nodes]: U[t] for every leaf t is n_t x r_t
+ *           row-major FP64 (device); other entries ignored.
+ *   B       host array [num_nodes]: B[t] for every internal node is
+ *           r_t x r_l x r_r (C-order) FP64 (device), the root's 1 x r_l x r_r;
+ *           entries of leaves ignored.  The format is the output layout of
+ *           htucker_decompose (its leaf bases and transfer tensors).
+ *   Xref    NULL or a reference tensor of the same dims (any dtype).
+ *   Xhat    NULL or a device output of prod(dims) entries in xhat_dtype
+ *           (TK_F32 or TK_F64); computed in FP64.
+ *   resid2  NULL or device double[2]: ||Xref - Xhat||_F^2 and ||Xref||_F^2
+ *           (FP64 sums in a fixed order; requires Xref).
+ * At least one of Xhat and resid2 must be non-NULL.  The rank of the root's
+ * right child is at most 64.
+ * Errors: TK_EINVAL, TK_EUNSUPPORTED (that rank above 64), TK_EWORKSPACE,
+ * TK_EDEVICE. */
+tk_status htucker_reconstruct(int32_t order, const int64_t* dims, const tk_tree* tree, const int32_t* rank,
+                              const void* const* U, const void* const* B, const tk_tensor* Xref,
+                              void* Xhat, int32_t xhat_dtype, double* resid2, void* ws, size_t* ws_bytes,
+                              void* stream);
+
+/* Vector-Jacobian product of the H-Tucker format's full tensor with respect
+ * to its parameters (the differentiation form of the format; chain rule
+ * through the two relations above): given H = dL/dXhat (prod(dims) entries,
+ * h_dtype TK_F32 or TK_F64),
+ *   root:      Bbar_R = U_Rl^T H U_Rr,  Ubar_Rl = H U_Rr B_R^T,
+ *              Ubar_Rr = H^T U_Rl B_R   (H viewed as n_Rl x n_Rr);
+ *   internal:  with K = U_l kron U_r,  Bbar_S^(1) = Ubar_S^T K and
+ *              Ubar_l, Ubar_r the contractions of Ubar_S B_S^(1) with U_r, U_l;
+ * from the root's children down to the leaves.
+ *   Bbar    host array [num_nodes] of device FP64 outputs shaped like B
+ *           (every internal node, root included; leaf entries ignored).
+ *   Ubar    host array [num_nodes] of device FP64 outputs shaped like U
+ *           (every leaf; other entries ignored).
+ * Other arguments as for htucker_reconstruct.  H is read twice (one
+ * one-sided contraction and one unfolded product).
+ * Errors: TK_EINVAL, TK_EUNSUPPORTED, TK_EWORKSPACE, TK_EDEVICE. */
+tk_status htucker_reconstruct_vjp(int32_t order, const int64_t* dims, const tk_tree* tree,
+                                  const int32_t* rank, const void* const* U, const void* const* B,
+                                  const void* H, int32_t h_dtype, void* const* Bbar, void* const* Ubar,
+                                  void* ws, size_t* ws_bytes, void* stream);
+
 /* Vector-Jacobian product of the core projection G = X x_k F_k^T (the
  * differentiation form of the method; follows from the TTM definition of
  * Section 2.2): given Gbar (c_1 x .. x c_d),

@@ -55,7 +55,8 @@ EXPORTS = ("tucker_sketch_all_modes", "tucker_qr", "tucker_core", "tucker_recons
            "htucker_decompose", "tucker_core_vjp", "tucker_reconstruct_vjp", "tk_last_error",
            "tk_version", "tk_profile_enable", "tk_profile_read", "tucker_batch_plan_create",
            "tucker_batch_run", "tucker_batch_autotune", "tucker_batch_plan_destroy",
-           "tk_stream_read_blocks", "tk_stream_read", "tucker_draw_sketches")
+           "tk_stream_read_blocks", "tk_stream_read", "tucker_draw_sketches",
+           "htucker_reconstruct", "htucker_reconstruct_vjp")
 
 
 def lib():
@@ -92,6 +93,10 @@ def lib():
                                        vp, vp, vp, sz, vp],
                 "htucker_decompose": [C.POINTER(TkTensor), C.POINTER(TkTree), i32p, C.POINTER(TkSketch),
                                       pp, pp, vp, vp, sz, vp],
+                "htucker_reconstruct": [C.c_int32, i64p, C.POINTER(TkTree), i32p, pp, pp,
+                                        C.POINTER(TkTensor), vp, C.c_int32, vp, vp, sz, vp],
+                "htucker_reconstruct_vjp": [C.c_int32, i64p, C.POINTER(TkTree), i32p, pp, pp, vp,
+                                            C.c_int32, pp, pp, vp, sz, vp],
                 "tucker_core_vjp": [C.POINTER(TkTensor), pp, i32p, vp, vp, pp, C.c_int32, vp, sz, vp],
                 "tucker_reconstruct_vjp": [C.c_int32, i64p, C.c_int32, vp, pp, i32p, vp, vp, pp, vp,
                                            sz, vp],
@@ -275,6 +280,35 @@ def htucker_decompose(X, tree, ranks, sketches, U, B, info=None, stream=None, ws
         sk[t].omega = om.data_ptr()
     args = [C.byref(xd), C.byref(td), rk, sk, ptr_array(U), ptr_array(B), ptr(info)]
     return _call("htucker_decompose", args, X.device, stream, ws)
+
+
+def _ht_common(dims, tree, ranks):
+    d = len(dims)
+    n = tree.num_nodes
+    return d, (C.c_int64 * d)(*dims), tree_desc(tree), (C.c_int32 * n)(*[int(r) if r else 0 for r in ranks])
+
+
+def htucker_reconstruct(dims, tree, ranks, U, B, Xref=None, Xhat=None, resid2=None, stream=None,
+                        ws=None):
+    """Full tensor of an H-Tucker format (Xhat, FP32 or FP64) and/or its
+    residual against Xref (resid2: FP64 [2]).  U, B, ranks: lists indexed by
+    node; the leaf entries of U and the internal entries of B (root 0
+    included) are used, all FP64 device tensors."""
+    d, dd, td, rk = _ht_common(dims, tree, ranks)
+    xr = tensor_desc(Xref) if Xref is not None else None
+    args = [d, dd, C.byref(td), rk, ptr_array(U), ptr_array(B), C.byref(xr) if xr is not None else None,
+            ptr(Xhat), dtype_code(Xhat.dtype) if Xhat is not None else 0, ptr(resid2)]
+    dev = B[0].device
+    return _call("htucker_reconstruct", args, dev, stream, ws)
+
+
+def htucker_reconstruct_vjp(dims, tree, ranks, U, B, H, Bbar, Ubar, stream=None, ws=None):
+    """Given H = dL/dXhat (FP32 or FP64, dims), writes dL/dB_t into Bbar[t]
+    (internal nodes, root included) and dL/dU_t into Ubar[t] (leaves), FP64."""
+    d, dd, td, rk = _ht_common(dims, tree, ranks)
+    args = [d, dd, C.byref(td), rk, ptr_array(U), ptr_array(B), H.data_ptr(), dtype_code(H.dtype),
+            ptr_array(Bbar), ptr_array(Ubar)]
+    return _call("htucker_reconstruct_vjp", args, H.device, stream, ws)
 
 
 def tucker_core_vjp(X, F, Gbar, Xbar=None, Fbar=None, accumulate=False, stream=None, ws=None):

@@ -1,0 +1,220 @@
+// Full tensor of an H-Tucker format and its residual (Section 4: root
+// relation and nestedness of the bases).
+//
+// The root relation gives X^(Rl) = U_Rl B_R U_Rr^T for the nested bases of the
+// root's two children, so with T = U_Rl B_R (n_l x r_r, small) every entry is
+//     xhat[a][b] = sum_k T[a][k] U_Rr[b][k],
+// a rank-r_r expansion of the n_l x n_r matricisation.  ht_expand_kernel
+// streams it once: a workgroup owns a tile of columns b and a range of rows a;
+// each lane keeps U_Rr[b][:] of its columns in registers, each row's T[a][:]
+// is wave-uniform (scalar loads), so an entry costs r_r FP64 FMAs and the
+// only HBM traffic is the reference tensor (and the output, if written).
+// The residual ||X - Xhat||^2 and ||X||^2 are accumulated in FP64 per lane,
+// reduced per workgroup and summed in a fixed order.
+#include "tk_kernels.hpp"
+
+namespace tk {
+namespace {
+
+struct None {};
+
+template <typename T> struct IsNone { static constexpr bool value = false; };
+template <> struct IsNone<None> { static constexpr bool value = true; };
+
+// C[j][k][i] = B[i][j][k] (to_core != 0) or B[i][j][k] = C[j][k][i]
+__global__ __launch_bounds__(256) void permute_transfer_kernel(const double* in, double* out, int rS,
+                                                               int rl, int rr, int to_core) {
+  const int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t total = (int64_t)rS * rl * rr;
+  if (g >= total) return;
+  const int64_t jk = g % ((int64_t)rl * rr);
+  const int64_t i = g / ((int64_t)rl * rr);
+  const int64_t c = jk * rS + i;   // (j rr + k) rS + i
+  if (to_core)
+    out[c] = in[g];
+  else
+    out[g] = in[c];
+}
+
+// T[a][k] = sum_j UL[a][j] BR[j][k] for k < rr; 0 for rr <= k < rpad
+__global__ __launch_bounds__(256) void ht_rowmat_kernel(const double* UL, const double* BR, double* T,
+                                                        int64_t nL, int rl, int rr, int rpad) {
+  const int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (g >= nL * rpad) return;
+  const int64_t a = g / rpad;
+  const int k = (int)(g - a * rpad);
+  double v = 0.0;
+  if (k < rr)
+    for (int j = 0; j < rl; ++j) v = fma(UL[a * rl + j], BR[j * rr + k], v);
+  T[g] = v;
+}
+
+template <typename TX, typename TO, int R>
+__global__ __launch_bounds__(256) void ht_expand_kernel(const HTExpand p) {
+  constexpr int C = 64 / R;          // columns per lane
+  constexpr int kRows = 4;           // rows whose loads are issued together
+  constexpr bool kX = !IsNone<TX>::value, kO = !IsNone<TO>::value;
+  __shared__ double red[2][4];
+  const int tid = threadIdx.x;
+  const int64_t tile = blockIdx.x % p.ntile, grp = blockIdx.x / p.ntile;
+  const int64_t a0 = grp * p.rows_per_group;
+  const int64_t a1 = min(a0 + p.rows_per_group, p.nL);
+  int64_t col[C];
+  bool ok[C];
+  double ur[C][R];
+#pragma unroll
+  for (int c = 0; c < C; ++c) {
+    const int64_t b = tile * (256 * C) + tid + 256 * c;
+    ok[c] = b < p.nR;
+    col[c] = ok[c] ? b : 0;          // in-range address for the idle columns
+#pragma unroll
+    for (int k = 0; k < R; ++k) ur[c][k] = (ok[c] && k < p.rr) ? p.UR[col[c] * p.rr + k] : 0.0;
+  }
+  const TX* X = static_cast<const TX*>(p.X);
+  TO* Xh = static_cast<TO*>(p.Xh);
+  double r2 = 0.0, x2 = 0.0;
+  for (int64_t a = a0; a < a1; a += kRows) {
+    double xv[kRows][C];
+    if constexpr (kX) {
+#pragma unroll
+      for (int u = 0; u < kRows; ++u) {
+        const int64_t row = min(a + u, a1 - 1);
+#pragma unroll
+        for (int c = 0; c < C; ++c) xv[u][c] = to_double(X[row * p.nR + col[c]]);
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < kRows; ++u) {
+      const bool live = a + u < a1;
+      const int64_t row = min(a + u, a1 - 1);
+      const double* t = p.T + row * R;
+      double tk[R];
+#pragma unroll
+      for (int k = 0; k < R; ++k) tk[k] = t[k];
+#pragma unroll
+      for (int c = 0; c < C; ++c) {
+        double xh = 0.0;
+#pragma unroll
+        for (int k = 0; k < R; ++k) xh = fma(tk[k], ur[c][k], xh);
+        if constexpr (kX) {
+          const double x = (live && ok[c]) ? xv[u][c] : 0.0;
+          const double d = (live && ok[c]) ? x - xh : 0.0;
+          r2 = fma(d, d, r2);
+          x2 = fma(x, x, x2);
+        }
+        if constexpr (kO) {
+          if (live && ok[c]) Xh[row * p.nR + col[c]] = from_double<TO>(xh);
+        }
+      }
+    }
+  }
+  if (!p.partials) return;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    r2 += __shfl_xor(r2, off);
+    x2 += __shfl_xor(x2, off);
+  }
+  if ((tid & 63) == 0) {
+    red[0][tid >> 6] = r2;
+    red[1][tid >> 6] = x2;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    p.partials[2 * blockIdx.x] = (red[0][0] + red[0][1]) + (red[0][2] + red[0][3]);
+    p.partials[2 * blockIdx.x + 1] = (red[1][0] + red[1][1]) + (red[1][2] + red[1][3]);
+  }
+}
+
+// out[0..1] = sums of the workgroup partials, in a fixed order
+__global__ __launch_bounds__(256) void ht_sum_kernel(const double* partials, int64_t nblocks, double* out) {
+  __shared__ double red[2][256];
+  const int tid = threadIdx.x;
+  double s0 = 0.0, s1 = 0.0;
+  for (int64_t i = tid; i < nblocks; i += 256) {
+    s0 += partials[2 * i];
+    s1 += partials[2 * i + 1];
+  }
+  red[0][tid] = s0;
+  red[1][tid] = s1;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (tid < s) {
+      red[0][tid] += red[0][tid + s];
+      red[1][tid] += red[1][tid + s];
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    out[0] = red[0][0];
+    out[1] = red[1][0];
+  }
+}
+
+template <typename TX, typename TO>
+hipError_t expand_by_r(const HTExpand& p, hipStream_t st) {
+  const dim3 grid((unsigned)(p.ntile * p.groups));
+  if (p.rpad == 16)
+    hipLaunchKernelGGL((ht_expand_kernel<TX, TO, 16>), grid, dim3(256), 0, st, p);
+  else
+    hipLaunchKernelGGL((ht_expand_kernel<TX, TO, 64>), grid, dim3(256), 0, st, p);
+  return hipGetLastError();
+}
+
+template <typename TX>
+hipError_t expand_by_out(const HTExpand& p, int out_dt, hipStream_t st) {
+  switch (out_dt) {
+    case -1: return expand_by_r<TX, None>(p, st);
+    case TK_F64: return expand_by_r<TX, double>(p, st);
+    case TK_F32: return expand_by_r<TX, float>(p, st);
+  }
+  return hipErrorInvalidValue;
+}
+
+}  // namespace
+
+int ht_expand_rpad(int rr) { return rr <= 16 ? 16 : (rr <= 64 ? 64 : 0); }
+
+void ht_expand_grid(HTExpand& p) {
+  const int C = 64 / p.rpad;
+  p.ntile = ceil_div(p.nR, 256 * C);
+  int64_t groups = std::max<int64_t>(1, std::min<int64_t>(p.nL, ceil_div(4096, p.ntile)));
+  p.rows_per_group = ceil_div(p.nL, groups);
+  p.groups = ceil_div(p.nL, p.rows_per_group);
+}
+
+hipError_t launch_ht_rowmat(const double* UL, const double* BR, double* T, int64_t nL, int rl, int rr,
+                            int rpad, hipStream_t st) {
+  const int64_t n = nL * rpad;
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(ht_rowmat_kernel, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, st, UL, BR, T,
+                     nL, rl, rr, rpad);
+  return hipGetLastError();
+}
+
+hipError_t launch_permute_transfer(const double* in, double* out, int rS, int rl, int rr, bool to_core,
+                                   hipStream_t st) {
+  const int64_t n = (int64_t)rS * rl * rr;
+  hipLaunchKernelGGL(permute_transfer_kernel, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, st, in, out,
+                     rS, rl, rr, to_core ? 1 : 0);
+  return hipGetLastError();
+}
+
+hipError_t launch_ht_expand(const HTExpand& p, int x_dt, int out_dt, hipStream_t st) {
+  if (p.rpad != 16 && p.rpad != 64) return hipErrorInvalidValue;
+  hipError_t e = hipErrorInvalidValue;
+  switch (x_dt) {
+    case -1: e = out_dt == -1 ? hipErrorInvalidValue : expand_by_out<None>(p, out_dt, st); break;
+    case TK_F64: e = expand_by_out<double>(p, out_dt, st); break;
+    case TK_F32: e = expand_by_out<float>(p, out_dt, st); break;
+    case TK_BF16: e = expand_by_out<bf16>(p, out_dt, st); break;
+    case TK_F16: e = expand_by_out<f16>(p, out_dt, st); break;
+  }
+  if (e != hipSuccess) return e;
+  if (p.partials && p.resid2) {
+    hipLaunchKernelGGL(ht_sum_kernel, dim3(1), dim3(256), 0, st, p.partials, p.ntile * p.groups, p.resid2);
+    e = hipGetLastError();
+  }
+  return e;
+}
+
+}  // namespace tk

@@ -1126,26 +1126,18 @@ tk_status tucker_reconstruct(int32_t order, const int64_t* dims, int32_t fdtype,
   return TK_OK;
 }
 
-tk_status htucker_decompose(const tk_tensor* X, const tk_tree* tree, const int32_t* rank,
-                            const tk_sketch* sk, void* const* U, void* const* B, int32_t* info,
-                            void* ws, size_t* ws_bytes, void* stream) {
-  clear_error();
-  int64_t N;
-  if (tk_status s = check_tensor(X, "htucker_decompose", &N)) return s;
-  const int d = X->order;
-  if (d < 2) return set_error(TK_EINVAL, "htucker_decompose: order must be >= 2");
-  if (!tree || !rank || !sk || !U || !B || !ws_bytes)
-    return set_error(TK_EINVAL, "htucker_decompose: NULL argument");
+// The tree must be the balanced heap tree of this order (left child = first
+// ceil(|S|/2) modes of S), the one every H-Tucker entry point is built for.
+tk_status check_ht_tree(const tk_tree* tree, int d, const char* name) {
   const int nn = 2 * d - 1;
   if (tree->num_nodes != nn)
-    return set_error(TK_EINVAL, "htucker_decompose: num_nodes %d != 2 order - 1", tree->num_nodes);
+    return set_error(TK_EINVAL, "%s: num_nodes %d != 2 order - 1", name, tree->num_nodes);
   if (!tree->left || !tree->right || !tree->first_mode || !tree->num_modes)
-    return set_error(TK_EINVAL, "htucker_decompose: tree arrays are NULL");
+    return set_error(TK_EINVAL, "%s: tree arrays are NULL", name);
   // the expected balanced heap tree (left child = first ceil(|S|/2) modes)
   {
     std::vector<int> ef(1, 0), ec(1, d), el, er;
     size_t head = 0;
-    std::vector<std::pair<int, int>> level{{0, d}};
     el.assign(1, -1);
     er.assign(1, -1);
     while (head < ef.size()) {
@@ -1169,12 +1161,27 @@ tk_status htucker_decompose(const tk_tensor* X, const tk_tree* tree, const int32
         er.push_back(-1);
       }
     }
-    if ((int)ef.size() != nn) return set_error(TK_EINVAL, "htucker_decompose: internal tree error");
+    if ((int)ef.size() != nn) return set_error(TK_EINVAL, "%s: internal tree error", name);
     for (int t = 0; t < nn; ++t)
       if (tree->first_mode[t] != ef[t] || tree->num_modes[t] != ec[t] || tree->left[t] != el[t] ||
           tree->right[t] != er[t])
-        return set_error(TK_EINVAL, "htucker_decompose: node %d differs from the balanced heap tree", t);
+        return set_error(TK_EINVAL, "%s: node %d differs from the balanced heap tree", name, t);
   }
+  return TK_OK;
+}
+
+tk_status htucker_decompose(const tk_tensor* X, const tk_tree* tree, const int32_t* rank,
+                            const tk_sketch* sk, void* const* U, void* const* B, int32_t* info,
+                            void* ws, size_t* ws_bytes, void* stream) {
+  clear_error();
+  int64_t N;
+  if (tk_status s = check_tensor(X, "htucker_decompose", &N)) return s;
+  const int d = X->order;
+  if (d < 2) return set_error(TK_EINVAL, "htucker_decompose: order must be >= 2");
+  if (!tree || !rank || !sk || !U || !B || !ws_bytes)
+    return set_error(TK_EINVAL, "htucker_decompose: NULL argument");
+  const int nn = 2 * d - 1;
+  if (tk_status s = check_ht_tree(tree, d, "htucker_decompose")) return s;
   std::vector<int64_t> nS(nn), nc(nn), A(nn), Bv(nn);
   for (int t = 0; t < nn; ++t) {
     const int f = tree->first_mode[t], c = tree->num_modes[t];
@@ -1296,6 +1303,277 @@ tk_status htucker_decompose(const tk_tensor* X, const tk_tree* tree, const int32
     m2.cs = rank[L];
     m2.out = B[0];
     TK_HIP(launch_mode_product(m2, TK_F64, fdt, fdt, st));
+  }
+  return TK_OK;
+}
+
+// ------------------------------------------------------------------ H-Tucker format
+// Shared checks and plan of the format's entry points: node sizes, the nested
+// bases of every internal non-root node (U_S = C_S x_0 U_Sl x_1 U_Sr with
+// C_S[j][k][i] = B_S[i][j][k], nestedness of Section 4) and their buffers.
+struct HTFormat {
+  int d = 0, nn = 0, L = 0, R = 0;
+  std::vector<int64_t> nS;
+  std::vector<double*> NB;      // nested bases (internal non-root nodes)
+  double* C = nullptr;          // permuted transfer tensor
+  double* E = nullptr;          // C x_0 U_l (and other n_l x r_r x r_S intermediates)
+  double* Mt = nullptr;         // mode-product factor table
+  int64_t mt_need = 0;
+};
+
+tk_status check_ht_format(int32_t order, const int64_t* dims, const tk_tree* tree, const int32_t* rank,
+                          const void* const* U, const void* const* B, const char* name, HTFormat& f) {
+  if (order < 2 || order > TK_MAX_ORDER)
+    return set_error(TK_EINVAL, "%s: order %d outside [2, %d]", name, order, TK_MAX_ORDER);
+  if (!dims || !tree || !rank || !U || !B) return set_error(TK_EINVAL, "%s: NULL argument", name);
+  for (int k = 0; k < order; ++k)
+    if (dims[k] < 1) return set_error(TK_EINVAL, "%s: dims[%d] < 1", name, k);
+  if (tk_status s = check_ht_tree(tree, order, name)) return s;
+  f.d = order;
+  f.nn = 2 * order - 1;
+  f.L = tree->left[0];
+  f.R = tree->right[0];
+  f.nS.assign(f.nn, 0);
+  for (int t = 0; t < f.nn; ++t)
+    f.nS[t] = prod(dims, tree->first_mode[t], tree->first_mode[t] + tree->num_modes[t]);
+  for (int t = 1; t < f.nn; ++t) {
+    if (rank[t] < 1) return set_error(TK_EINVAL, "%s: rank[%d] = %d < 1", name, t, rank[t]);
+    if (tree->left[t] < 0 && !U[t]) return set_error(TK_EINVAL, "%s: U[%d] (leaf) is NULL", name, t);
+    if (tree->left[t] >= 0 && !B[t]) return set_error(TK_EINVAL, "%s: B[%d] is NULL", name, t);
+  }
+  if (!B[0]) return set_error(TK_EINVAL, "%s: B[0] is NULL", name);
+  if (!ht_expand_rpad(rank[f.R]))
+    return set_error(TK_EUNSUPPORTED, "%s: rank of the root's right child %d above 64", name, rank[f.R]);
+  return TK_OK;
+}
+
+void plan_ht_format(Workspace& w, const tk_tree* tree, const int32_t* rank, HTFormat& f) {
+  f.NB.assign(f.nn, nullptr);
+  int64_t cmax = 1, emax = 1;
+  for (int t = 1; t < f.nn; ++t) {
+    if (tree->left[t] < 0) continue;
+    const int l = tree->left[t], r = tree->right[t];
+    f.NB[t] = w.take<double>((size_t)f.nS[t] * rank[t]);
+    cmax = std::max<int64_t>(cmax, (int64_t)rank[t] * rank[l] * rank[r]);
+    emax = std::max<int64_t>(emax, f.nS[l] * rank[r] * rank[t]);
+    f.mt_need = std::max(f.mt_need, mode_product_scratch(f.nS[l], rank[l]));
+    f.mt_need = std::max(f.mt_need, mode_product_scratch(f.nS[r], rank[r]));
+  }
+  f.C = w.take<double>((size_t)cmax);
+  f.E = w.take<double>((size_t)emax);
+}
+
+const double* ht_basis(const tk_tree* tree, const void* const* U, const HTFormat& f, int t) {
+  return tree->left[t] < 0 ? static_cast<const double*>(U[t]) : f.NB[t];
+}
+
+// nested bases of every internal non-root node, children before parents
+// (heap order: a child's index exceeds its parent's)
+tk_status run_ht_bases(const tk_tree* tree, const int32_t* rank, const void* const* U,
+                       const void* const* B, const HTFormat& f, hipStream_t st) {
+  for (int t = f.nn - 1; t >= 1; --t) {
+    if (tree->left[t] < 0) continue;
+    const int l = tree->left[t], r = tree->right[t];
+    TK_HIP(launch_permute_transfer(static_cast<const double*>(B[t]), f.C, rank[t], rank[l], rank[r], true, st));
+    ModeProduct m1{};   // E = C x_0 U_l: (n_l, r_r, r_S)
+    m1.in = f.C;
+    m1.A = 1;
+    m1.Q = rank[l];
+    m1.B = (int64_t)rank[r] * rank[t];
+    m1.P = (int32_t)f.nS[l];
+    m1.M = ht_basis(tree, U, f, l);
+    m1.Mt = f.Mt;
+    m1.rs = rank[l];
+    m1.cs = 1;
+    m1.out = f.E;
+    TK_HIP(launch_mode_product(m1, TK_F64, TK_F64, TK_F64, st));
+    ModeProduct m2{};   // U_S = E x_1 U_r: (n_l, n_r, r_S) = U_S[(a n_r + b)][i]
+    m2.in = f.E;
+    m2.A = f.nS[l];
+    m2.Q = rank[r];
+    m2.B = rank[t];
+    m2.P = (int32_t)f.nS[r];
+    m2.M = ht_basis(tree, U, f, r);
+    m2.Mt = f.Mt;
+    m2.rs = rank[r];
+    m2.cs = 1;
+    m2.out = f.NB[t];
+    TK_HIP(launch_mode_product(m2, TK_F64, TK_F64, TK_F64, st));
+  }
+  return TK_OK;
+}
+
+tk_status htucker_reconstruct(int32_t order, const int64_t* dims, const tk_tree* tree, const int32_t* rank,
+                              const void* const* U, const void* const* B, const tk_tensor* Xref,
+                              void* Xhat, int32_t xhat_dtype, double* resid2, void* ws, size_t* ws_bytes,
+                              void* stream) {
+  clear_error();
+  const char* nm = "htucker_reconstruct";
+  HTFormat f;
+  if (tk_status s = check_ht_format(order, dims, tree, rank, U, B, nm, f)) return s;
+  if (!ws_bytes) return set_error(TK_EINVAL, "%s: ws_bytes is NULL", nm);
+  if (!Xhat && !resid2) return set_error(TK_EINVAL, "%s: Xhat and resid2 are both NULL", nm);
+  if (resid2 && !Xref) return set_error(TK_EINVAL, "%s: resid2 needs Xref", nm);
+  if (Xhat && xhat_dtype != TK_F32 && xhat_dtype != TK_F64)
+    return set_error(TK_EINVAL, "%s: xhat_dtype must be TK_F32 or TK_F64", nm);
+  if (Xref) {
+    int64_t N;
+    if (tk_status s = check_tensor(Xref, nm, &N)) return s;
+    if (Xref->order != order) return set_error(TK_EINVAL, "%s: Xref order %d != %d", nm, Xref->order, order);
+    for (int k = 0; k < order; ++k)
+      if (Xref->dims[k] != dims[k]) return set_error(TK_EINVAL, "%s: Xref dims[%d] differs", nm, k);
+  }
+  Workspace w;
+  w.base = static_cast<char*>(ws);
+  plan_ht_format(w, tree, rank, f);
+  const int L = f.L, R = f.R;
+  HTExpand e{};
+  e.nL = f.nS[L];
+  e.nR = f.nS[R];
+  e.rr = rank[R];
+  e.rpad = ht_expand_rpad(rank[R]);
+  ht_expand_grid(e);
+  double* T = w.take<double>((size_t)e.nL * e.rpad);
+  double* part = resid2 ? w.take<double>((size_t)2 * e.ntile * e.groups) : nullptr;
+  f.Mt = w.take<double>((size_t)std::max<int64_t>(1, f.mt_need));
+  if (!ws) {
+    *ws_bytes = w.off;
+    return TK_OK;
+  }
+  if (*ws_bytes < w.off) return set_error(TK_EWORKSPACE, "%s: workspace %zu < required %zu", nm, *ws_bytes, w.off);
+  hipStream_t st = as_stream(stream);
+  if (tk_status s = run_ht_bases(tree, rank, U, B, f, st)) return s;
+  // root: T = U_Rl B_R, then xhat = T U_Rr^T streamed against the reference
+  TK_HIP(launch_ht_rowmat(ht_basis(tree, U, f, L), static_cast<const double*>(B[0]), T, e.nL, rank[L],
+                          rank[R], e.rpad, st));
+  e.T = T;
+  e.UR = ht_basis(tree, U, f, R);
+  e.X = Xref ? Xref->data : nullptr;
+  e.Xh = Xhat;
+  e.partials = part;
+  e.resid2 = resid2;
+  TK_HIP(profile_begin(st));
+  TK_HIP(launch_ht_expand(e, Xref ? Xref->dtype : -1, Xhat ? xhat_dtype : -1, st));
+  TK_HIP(profile_end(st));
+  return TK_OK;
+}
+
+tk_status htucker_reconstruct_vjp(int32_t order, const int64_t* dims, const tk_tree* tree,
+                                  const int32_t* rank, const void* const* U, const void* const* B,
+                                  const void* H, int32_t h_dtype, void* const* Bbar, void* const* Ubar,
+                                  void* ws, size_t* ws_bytes, void* stream) {
+  clear_error();
+  const char* nm = "htucker_reconstruct_vjp";
+  HTFormat f;
+  if (tk_status s = check_ht_format(order, dims, tree, rank, U, B, nm, f)) return s;
+  if (!ws_bytes || !H || !Bbar || !Ubar) return set_error(TK_EINVAL, "%s: NULL argument", nm);
+  if (h_dtype != TK_F32 && h_dtype != TK_F64) return set_error(TK_EINVAL, "%s: h_dtype must be TK_F32 or TK_F64", nm);
+  for (int t = 0; t < f.nn; ++t) {
+    if (tree->left[t] >= 0 && !Bbar[t]) return set_error(TK_EINVAL, "%s: Bbar[%d] is NULL", nm, t);
+    if (t > 0 && tree->left[t] < 0 && !Ubar[t]) return set_error(TK_EINVAL, "%s: Ubar[%d] is NULL", nm, t);
+  }
+  Workspace w;
+  w.base = static_cast<char*>(ws);
+  plan_ht_format(w, tree, rank, f);
+  const int L = f.L, R = f.R;
+  const int rl0 = rank[L], rr0 = rank[R];
+  const int64_t nL = f.nS[L], nR = f.nS[R];
+  // adjoints of the internal non-root bases; leaves write to Ubar
+  std::vector<double*> UB(f.nn, nullptr);
+  int64_t e2 = 1, up = 1;
+  int64_t mt = f.mt_need;
+  for (int t = 1; t < f.nn; ++t) {
+    if (tree->left[t] < 0) continue;
+    UB[t] = w.take<double>((size_t)f.nS[t] * rank[t]);
+    const int l = tree->left[t], r = tree->right[t];
+    const int64_t nl = f.nS[l], nr = f.nS[r];
+    e2 = std::max<int64_t>(e2, (int64_t)rank[l] * nr * rank[t]);
+    up = std::max<int64_t>(up, (int64_t)unfold_gemm_splits(nl, nr * rank[t]) * nl * rank[l]);
+    up = std::max<int64_t>(up, (int64_t)unfold_gemm_splits(nr, nl * rank[t]) * nr * rank[r]);
+    mt = std::max(mt, mode_product_scratch(rank[r], nr));
+    mt = std::max(mt, mode_product_scratch(rank[l], nl));
+  }
+  up = std::max<int64_t>(up, (int64_t)unfold_gemm_splits(nR, nL) * nR * rr0);
+  mt = std::max(mt, mode_product_scratch(rr0, nR));
+  mt = std::max(mt, mode_product_scratch(rl0, nL));
+  mt = std::max(mt, mode_product_scratch(rl0, rr0));
+  mt = std::max(mt, mode_product_scratch(nL, rl0));
+  double* E2 = w.take<double>((size_t)e2);
+  int64_t cb = 1;
+  for (int t = 1; t < f.nn; ++t)
+    if (tree->left[t] >= 0) cb = std::max<int64_t>(cb, (int64_t)rank[t] * rank[tree->left[t]] * rank[tree->right[t]]);
+  double* Cbar2 = w.take<double>((size_t)cb);
+  double* P1 = w.take<double>((size_t)nL * rr0);
+  double* W = w.take<double>((size_t)nL * rr0);
+  double* upart = w.take<double>((size_t)up);
+  f.Mt = w.take<double>((size_t)std::max<int64_t>(1, mt));
+  if (!ws) {
+    *ws_bytes = w.off;
+    return TK_OK;
+  }
+  if (*ws_bytes < w.off) return set_error(TK_EWORKSPACE, "%s: workspace %zu < required %zu", nm, *ws_bytes, w.off);
+  hipStream_t st = as_stream(stream);
+  if (tk_status s = run_ht_bases(tree, rank, U, B, f, st)) return s;
+  auto adj = [&](int t) -> double* { return tree->left[t] < 0 ? static_cast<double*>(Ubar[t]) : UB[t]; };
+  auto mode = [&](const void* in, int in_dt, int64_t A, int64_t Q, int64_t Bn, int64_t P, const void* M,
+                  int rs, int cs, void* out) -> hipError_t {
+    ModeProduct m{};
+    m.in = in;
+    m.A = A;
+    m.Q = Q;
+    m.B = Bn;
+    m.P = (int32_t)P;
+    m.M = M;
+    m.Mt = f.Mt;
+    m.rs = rs;
+    m.cs = cs;
+    m.out = out;
+    return launch_mode_product(m, in_dt, TK_F64, TK_F64, st);
+  };
+  auto ugemm = [&](const void* A, int adt, const void* Bm, int64_t pre, int64_t n, int64_t c, int64_t post,
+                   void* out) -> hipError_t {
+    UnfoldGemm g{};
+    g.A = A;
+    g.B = Bm;
+    g.out = out;
+    g.partials = upart;
+    g.pre = pre;
+    g.post = post;
+    g.n = (int32_t)n;
+    g.c = (int32_t)c;
+    g.splits = unfold_gemm_splits(n, pre * post);
+    g.accumulate = 0;
+    return launch_unfold_gemm(g, adt, TK_F64, TK_F64, st);
+  };
+  const double* UL = ht_basis(tree, U, f, L);
+  const double* UR = ht_basis(tree, U, f, R);
+  // root, H viewed as n_l x n_r: P1 = H U_Rr; B_R_bar = U_Rl^T P1; U_Rl_bar = P1 B_R^T;
+  // U_Rr_bar = H^T (U_Rl B_R)
+  TK_HIP(mode(H, h_dtype, nL, nR, 1, rr0, UR, 1, rr0, P1));
+  TK_HIP(mode(P1, TK_F64, 1, nL, rr0, rl0, UL, 1, rl0, Bbar[0]));
+  TK_HIP(mode(P1, TK_F64, nL, rr0, 1, rl0, B[0], rr0, 1, adj(L)));
+  TK_HIP(mode(B[0], TK_F64, 1, rl0, rr0, nL, UL, rl0, 1, W));
+  TK_HIP(ugemm(H, h_dtype, W, nL, nR, rr0, 1, adj(R)));
+  // internal nodes, parents before children: with H' = U_S_bar as (n_l, n_r, r_S)
+  // and C = B_S permuted to (r_l, r_r, r_S):
+  //   C_bar = H' x_0 U_l^T x_1 U_r^T,  U_l_bar = H'^(0) (C x_1 U_r)^(0)T,
+  //   U_r_bar = H'^(1) (C x_0 U_l)^(1)T
+  for (int t = 1; t < f.nn; ++t) {
+    if (tree->left[t] < 0) continue;
+    const int l = tree->left[t], r = tree->right[t];
+    const int rS = rank[t], rl = rank[l], rr = rank[r];
+    const int64_t nl = f.nS[l], nr = f.nS[r];
+    const double* Ul = ht_basis(tree, U, f, l);
+    const double* Ur = ht_basis(tree, U, f, r);
+    const double* Hs = UB[t];
+    TK_HIP(launch_permute_transfer(static_cast<const double*>(B[t]), f.C, rS, rl, rr, true, st));
+    TK_HIP(mode(Hs, TK_F64, nl, nr, rS, rr, Ur, 1, rr, f.E));            // (n_l, r_r, r_S)
+    TK_HIP(mode(f.E, TK_F64, 1, nl, (int64_t)rr * rS, rl, Ul, 1, rl, Cbar2));   // (r_l, r_r, r_S)
+    TK_HIP(launch_permute_transfer(Cbar2, static_cast<double*>(Bbar[t]), rS, rl, rr, false, st));
+    TK_HIP(mode(f.C, TK_F64, rl, rr, rS, nr, Ur, rr, 1, E2));            // (r_l, n_r, r_S)
+    TK_HIP(ugemm(Hs, TK_F64, E2, 1, nl, rl, nr * rS, adj(l)));
+    TK_HIP(mode(f.C, TK_F64, 1, rl, (int64_t)rr * rS, nl, Ul, rl, 1, f.E));   // (n_l, r_r, r_S)
+    TK_HIP(ugemm(Hs, TK_F64, f.E, nl, nr, rr, rS, adj(r)));
   }
   return TK_OK;
 }

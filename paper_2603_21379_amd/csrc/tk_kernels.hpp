@@ -300,6 +300,30 @@ int64_t root_pass_partials(int64_t nL, int64_t nR);   // doubles of RootPass::pa
 // brackets the streaming kernel with the profiler's events
 hipError_t launch_root_pass(const RootPass& p, hipStream_t st);
 
+// ---------------------------------------------------------------- H-Tucker full tensor
+// xhat[a][b] = sum_k T[a][k] UR[b][k] over the n_l x n_r matricisation, with
+// T = U_Rl B_R padded to rpad columns; optional reference X (partials of
+// ||X - xhat||^2 and ||X||^2) and optional output Xh.
+struct HTExpand {
+  const double* T;      // nL x rpad (columns rr.. rpad-1 zero)
+  const double* UR;     // nR x rr
+  const void* X;        // reference (x_dt) or nullptr
+  void* Xh;             // output (out_dt) or nullptr
+  double* partials;     // [ntile * groups][2] or nullptr
+  double* resid2;       // final [2] or nullptr
+  int64_t nL, nR;
+  int32_t rr, rpad;     // rpad = ht_expand_rpad(rr)
+  int64_t ntile, groups, rows_per_group;   // set by ht_expand_grid
+};
+int ht_expand_rpad(int rr);           // 16 or 64; 0 = rank above 64
+void ht_expand_grid(HTExpand& p);     // fills ntile, groups, rows_per_group
+hipError_t launch_ht_expand(const HTExpand& p, int x_dt, int out_dt, hipStream_t st);   // dt -1 = absent
+hipError_t launch_ht_rowmat(const double* UL, const double* BR, double* T, int64_t nL, int rl, int rr,
+                            int rpad, hipStream_t st);
+// C[j][k][i] = B[i][j][k] (to_core) or the inverse permutation
+hipError_t launch_permute_transfer(const double* in, double* out, int rS, int rl, int rr, bool to_core,
+                                   hipStream_t st);
+
 // ---------------------------------------------------------------- unfolded products (VJPs)
 // out[i][a] (+)= sum_{p,q} A[p][i][q] B[p][a][q]: A is (pre, n, post), B is
 // (pre, c, post); the mode-k unfolding product A^(k) (B^(k))^T.

@@ -104,3 +104,38 @@ def sub_r_rtl_ht(X: torch.Tensor, tree, ranks: dict, sk_dev: dict, ws=None) -> H
     B.htucker_decompose(X, tree, rk, sk, U, Bt, info=info, ws=ws)
     return HTResult({t: U[t] for t in range(1, n)},
                     {t: Bt[t] for t in range(n) if Bt[t] is not None}, info)
+
+
+def _ht_lists(tree, ranks, U: dict, Bd: dict):
+    n = tree.num_nodes
+    Ul = [U[t].contiguous() if tree.is_leaf(t) else None for t in range(n)]
+    Bl = [Bd[t].contiguous() if not tree.is_leaf(t) else None for t in range(n)]
+    return [0] + [int(ranks[t]) for t in range(1, n)], Ul, Bl
+
+
+def ht_reconstruct(dims, tree, ranks: dict, U: dict, Bd: dict, Xref=None, out_dtype=None, ws=None):
+    """Full tensor of an H-Tucker format (leaf bases U, transfers Bd, FP64 on
+    the device) in out_dtype, and/or [||Xref - Xhat||^2, ||Xref||^2]."""
+    rk, Ul, Bl = _ht_lists(tree, ranks, U, Bd)
+    dev = Bl[0].device
+    Xhat = torch.empty(tuple(dims), dtype=out_dtype, device=dev) if out_dtype is not None else None
+    r2 = torch.empty(2, dtype=torch.float64, device=dev) if Xref is not None else None
+    B.htucker_reconstruct(list(dims), tree, rk, Ul, Bl, Xref=Xref, Xhat=Xhat, resid2=r2, ws=ws)
+    return Xhat, r2
+
+
+def ht_rel_error(X, tree, ranks: dict, U: dict, Bd: dict, ws=None) -> float:
+    _, r2 = ht_reconstruct(list(X.shape), tree, ranks, U, Bd, Xref=X, ws=ws)
+    v = r2.cpu()
+    return float(math.sqrt(v[0] / v[1]))
+
+
+def ht_reconstruct_vjp(dims, tree, ranks: dict, U: dict, Bd: dict, H, ws=None):
+    """(dL/dB_t for internal nodes, dL/dU_t for leaves) given H = dL/dXhat."""
+    rk, Ul, Bl = _ht_lists(tree, ranks, U, Bd)
+    Bbar = [torch.empty_like(b) if b is not None else None for b in Bl]
+    Ubar = [torch.empty_like(u) if u is not None else None for u in Ul]
+    B.htucker_reconstruct_vjp(list(dims), tree, rk, Ul, Bl, H.contiguous(), Bbar, Ubar, ws=ws)
+    n = tree.num_nodes
+    return ({t: Bbar[t] for t in range(n) if Bbar[t] is not None},
+            {t: Ubar[t] for t in range(n) if Ubar[t] is not None})
