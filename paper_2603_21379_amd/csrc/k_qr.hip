@@ -514,7 +514,11 @@ __global__ __launch_bounds__(256) void mgram_kernel(const S b) {
 // One 256-thread workgroup per matrix: each round computes the ell/2
 // disjoint rotations, then applies them to rows (A <- J^T A) and to columns
 // (A <- A J, V <- V J); every thread owns a fixed set of (pair, index) items,
-// precomputed once, so a round is three barriers and a few FMAs per thread.
+// precomputed once.  The pairs of a round follow the fixed round-robin
+// schedule, so every wave computes all of the round's rotations itself (no
+// wave waits for another's parameters) and every thread derives its items'
+// indices arithmetically; a round is two barriers, one batch of LDS loads
+// per thread and the stores of the entries a rotation changes.
 // A rotation is skipped once |a_pq| <= 4 u max(|a_pp|, |a_qq|): the rotation
 // it would apply is then below rounding level relative to the pair's own
 // scale (a signal/noise pair is decoupled to ~u), whereas the stricter test
@@ -522,14 +526,15 @@ __global__ __launch_bounds__(256) void mgram_kernel(const S b) {
 // strongly graded pairs.
 constexpr int kEigThreads = 256;
 
-template <typename S>
+// IA, IV: A-block and V-pair items per thread, sized by the launcher for the
+// widest sketch of the batch so the per-round loads are straight-line code
+template <typename S, int IA, int IV>
 __global__ __launch_bounds__(kEigThreads) void eig_kernel(const S b) {
   const QRMat& M = b.get(blockIdx.x);
   __shared__ double A[kMaxEll][kMaxEll + 1];
   __shared__ double V[kMaxEll][kMaxEll + 1];
-  __shared__ double rc_[kMaxEll / 2], rs_[kMaxEll / 2];
-  __shared__ int rp_[kMaxEll / 2], rq_[kMaxEll / 2];
-  __shared__ int rotations;   // any rotation in this sweep (written by wave 0)
+  // (c, s) of the current round's rotations, one copy per wave
+  __shared__ double2 rot_cs[kEigThreads / 64][kMaxEll / 2];
   const int n = M.ell, np = n + (n & 1), half = np / 2, tid = threadIdx.x;
   // rotations stop below rounding level of the output precision (relative to
   // the pair's own scale): FP64 bases need ~u, FP32 bases ~1e-12 suffices
@@ -571,14 +576,13 @@ __global__ __launch_bounds__(kEigThreads) void eig_kernel(const S b) {
   // both kinds: the half x half 2x2 blocks of A (pair k1 rows, pair k2
   // columns: A <- J^T A J on the block) and the np x half column pairs of V
   // (V <- V J); codes k1 * 64 + k2 and k * 64 + i, or -1 past the end
-  constexpr int kItemsA = (kMaxEll / 2) * (kMaxEll / 2) / kEigThreads;
-  constexpr int kItemsV = kMaxEll * (kMaxEll / 2) / kEigThreads;
+  constexpr int kItemsA = IA, kItemsV = IV;
   int itemA[kItemsA], itemV[kItemsV];
   const int nblk = half * half, nv = np * half;
 #pragma unroll
   for (int t = 0; t < kItemsA; ++t) {
     const int e = tid + kEigThreads * t;
-    itemA[t] = e < nblk ? (e / half) * 64 + (e % half) : -1;
+    itemA[t] = e < nblk ? (e / half) * 64 + (e % half) : -1;   // -1: none (loads a dummy)
   }
 #pragma unroll
   for (int t = 0; t < kItemsV; ++t) {
@@ -586,20 +590,30 @@ __global__ __launch_bounds__(kEigThreads) void eig_kernel(const S b) {
     itemV[t] = e < nv ? (e / np) * 64 + (e % np) : -1;
   }
   __syncthreads();
+  const int wave = tid >> 6, lane = tid & 63;
+  // the pair (p < q) of rotation k in a round: fixed by the round-robin
+  // ordering, so every thread computes it instead of reading it
+  // (selects only: a branch here would split every item's loads)
+  auto pair_of = [&](int k, int round, int& p, int& q) {
+    const int m = np - 1;
+    int a = round + k, c = round - k;
+    a = a >= m ? a - m : a;
+    c = c < 0 ? c + m : c;
+    a = k == 0 ? m : a;
+    c = k == 0 ? round : c;
+    p = min(a, c);
+    q = max(a, c);
+  };
   for (int sweep = 0; sweep < 60; ++sweep) {
-    if (tid == 0) rotations = 0;
-    __syncthreads();
+    bool rotated = false;   // any rotation in this sweep (wave-uniform, equal in every wave)
     for (int round = 0; round < np - 1; ++round) {
-      bool rot = false;
-      if (tid < half) {
+      // every wave computes the round's ell/2 disjoint rotations (lane k:
+      // rotation k), so no wave waits for another's parameters
+      bool rot_now = false;
+      if (lane < half) {
         int p, q;
-        if (tid == 0) { p = np - 1; q = round; }
-        else {
-          p = round + tid; if (p >= np - 1) p -= np - 1;
-          q = round - tid; if (q < 0) q += np - 1;
-        }
-        if (p > q) { const int t = p; p = q; q = t; }
-        double c = 1.0, s = 0.0;
+        pair_of(lane, round, p, q);
+        double c = 1.0, sn = 0.0;
         if (q < n) {
           const double apq = A[p][q], app = A[p][p], aqq = A[q][q];
           if (fabs(apq) > tol * fmax(fabs(app), fabs(aqq))) {
@@ -611,55 +625,72 @@ __global__ __launch_bounds__(kEigThreads) void eig_kernel(const S b) {
             const double root = sqrt(fma(d, d, 4.0 * apq * apq));
             const double t = (2.0 * apq) / (d >= 0.0 ? d + root : d - root);
             c = 1.0 / sqrt(fma(t, t, 1.0));
-            s = t * c;
-            rot = true;
+            sn = t * c;
+            rot_now = true;
           }
         }
-        rc_[tid] = c; rs_[tid] = s; rp_[tid] = p; rq_[tid] = q;
+        rot_cs[wave][lane] = make_double2(c, sn);
       }
-      if (tid < 64) {   // half <= 32: every rotation of the round is in wave 0
-        const bool any = __any(rot);
-        if (tid == 0 && any) rotations = 1;
-      }
-      __syncthreads();
+      // identical in every wave, so every wave takes the same branch
+      const bool round_rot = __any(rot_now);
+      rotated |= round_rot;
+      __syncthreads();   // every read of A for the rotations is done
+      if (!round_rot) continue;
+      // every load of this thread's items first (straight-line: an absent
+      // item loads the entries of block (0, 0)), then the updates; an item
+      // whose rotations are both the identity stores nothing
+      double blk[kItemsA][4], vv[kItemsV][2];
+      double2 r1[kItemsA], r2[kItemsA], rv[kItemsV];
+      int ia[kItemsA][4], iv[kItemsV][3];
 #pragma unroll
       for (int t = 0; t < kItemsA; ++t) {
-        const int code = itemA[t];
-        if (code < 0) break;
+        const int code = itemA[t] < 0 ? 0 : itemA[t];
         const int k1 = code >> 6, k2 = code & 63;
-        const double s1 = rs_[k1], s2 = rs_[k2];
-        if (s1 != 0.0 || s2 != 0.0) {
-          const double c1 = rc_[k1], c2 = rc_[k2];
-          const int p1 = rp_[k1], q1 = rq_[k1], p2 = rp_[k2], q2 = rq_[k2];
-          const double a = A[p1][p2], bb = A[p1][q2], cc = A[q1][p2], dd = A[q1][q2];
+        pair_of(k1, round, ia[t][0], ia[t][1]);
+        pair_of(k2, round, ia[t][2], ia[t][3]);
+        r1[t] = rot_cs[wave][k1];
+        r2[t] = rot_cs[wave][k2];
+        blk[t][0] = A[ia[t][0]][ia[t][2]];
+        blk[t][1] = A[ia[t][0]][ia[t][3]];
+        blk[t][2] = A[ia[t][1]][ia[t][2]];
+        blk[t][3] = A[ia[t][1]][ia[t][3]];
+      }
+#pragma unroll
+      for (int t = 0; t < kItemsV; ++t) {
+        const int code = itemV[t] < 0 ? 0 : itemV[t];
+        const int k = code >> 6;
+        iv[t][0] = code & 63;
+        pair_of(k, round, iv[t][1], iv[t][2]);
+        rv[t] = rot_cs[wave][k];
+        vv[t][0] = V[iv[t][0]][iv[t][1]];
+        vv[t][1] = V[iv[t][0]][iv[t][2]];
+      }
+#pragma unroll
+      for (int t = 0; t < kItemsA; ++t) {
+        if (itemA[t] >= 0 && (r1[t].y != 0.0 || r2[t].y != 0.0)) {
+          const double c1 = r1[t].x, s1 = r1[t].y, c2 = r2[t].x, s2 = r2[t].y;
+          const double a = blk[t][0], bb = blk[t][1], cc = blk[t][2], dd = blk[t][3];
           // rows (J^T from the left), then columns (J from the right)
           const double ra = c1 * a - s1 * cc, rb = c1 * bb - s1 * dd;
           const double rc = s1 * a + c1 * cc, rd = s1 * bb + c1 * dd;
-          A[p1][p2] = c2 * ra - s2 * rb;
-          A[p1][q2] = s2 * ra + c2 * rb;
-          A[q1][p2] = c2 * rc - s2 * rd;
-          A[q1][q2] = s2 * rc + c2 * rd;
+          A[ia[t][0]][ia[t][2]] = c2 * ra - s2 * rb;
+          A[ia[t][0]][ia[t][3]] = s2 * ra + c2 * rb;
+          A[ia[t][1]][ia[t][2]] = c2 * rc - s2 * rd;
+          A[ia[t][1]][ia[t][3]] = s2 * rc + c2 * rd;
         }
       }
 #pragma unroll
       for (int t = 0; t < kItemsV; ++t) {
-        const int code = itemV[t];
-        if (code < 0) break;
-        const int k = code >> 6, i = code & 63;
-        const double sv = rs_[k];
-        if (sv != 0.0) {
-          const double cv = rc_[k];
-          const int p = rp_[k], q = rq_[k];
-          const double vip = V[i][p], viq = V[i][q];
-          V[i][p] = cv * vip - sv * viq;
-          V[i][q] = sv * vip + cv * viq;
+        if (itemV[t] >= 0 && rv[t].y != 0.0) {
+          const double cv = rv[t].x, sv = rv[t].y;
+          const double vip = vv[t][0], viq = vv[t][1];
+          V[iv[t][0]][iv[t][1]] = cv * vip - sv * viq;
+          V[iv[t][0]][iv[t][2]] = sv * vip + cv * viq;
         }
       }
       __syncthreads();
     }
-    const int done = rotations == 0;
-    __syncthreads();
-    if (done) break;
+    if (!rotated) break;
   }
   // rank of each eigenvalue in descending order (ties: lower index first)
   __shared__ int rank_of[kMaxEll];
@@ -746,10 +777,26 @@ __global__ __launch_bounds__(kEigThreads) void eig_kernel(const S b) {
   __syncthreads();
   // flip the columns that need it (exact in either storage type); each thread
   // rewrites only entries it wrote itself
+  // (eight loads in flight, then the eight stores)
   if (active && sgn[j] < 0.0) {
-    for (int64_t row = slot; row < M.m; row += tpc) {
-      if (f64) { double* U = static_cast<double*>(M.U); U[row * r + j] = -U[row * r + j]; }
-      else { float* U = static_cast<float*>(M.U); U[row * r + j] = -U[row * r + j]; }
+    constexpr int kB = 8;
+    for (int64_t row0 = slot; row0 < M.m; row0 += (int64_t)kB * tpc) {
+      double u[kB];
+#pragma unroll
+      for (int q = 0; q < kB; ++q) {
+        const int64_t row = row0 + (int64_t)q * tpc;
+        if (row < M.m)
+          u[q] = f64 ? static_cast<const double*>(M.U)[row * r + j]
+                     : (double)static_cast<const float*>(M.U)[row * r + j];
+      }
+#pragma unroll
+      for (int q = 0; q < kB; ++q) {
+        const int64_t row = row0 + (int64_t)q * tpc;
+        if (row < M.m) {
+          if (f64) static_cast<double*>(M.U)[row * r + j] = -u[q];
+          else static_cast<float*>(M.U)[row * r + j] = (float)-u[q];
+        }
+      }
     }
   }
 }
@@ -873,7 +920,20 @@ hipError_t wstep_impl(const S& src, const QRMat* host, int count, int ydtype, in
     default: return hipErrorInvalidValue;
   }
   hipLaunchKernelGGL(mgram_kernel<S>, dim3(ncc, count), dim3(256), 0, st, src);
-  hipLaunchKernelGGL(eig_kernel<S>, dim3(count), dim3(kEigThreads), 0, st, src);
+  // items per thread for the widest sketch: half^2 A blocks and np * half V pairs
+  int ellmax = 1;
+  for (int i = 0; i < count; ++i) ellmax = std::max(ellmax, host[i].ell);
+  const int np = ellmax + (ellmax & 1), half = np / 2;
+  const int ia = (int)ceil_div((int64_t)half * half, kEigThreads);
+  const int iv = (int)ceil_div((int64_t)np * half, kEigThreads);
+  if (ia <= 1 && iv <= 2)
+    hipLaunchKernelGGL((eig_kernel<S, 1, 2>), dim3(count), dim3(kEigThreads), 0, st, src);
+  else if (ia <= 2 && iv <= 4)
+    hipLaunchKernelGGL((eig_kernel<S, 2, 4>), dim3(count), dim3(kEigThreads), 0, st, src);
+  else if (ia <= 3 && iv <= 6)
+    hipLaunchKernelGGL((eig_kernel<S, 3, 6>), dim3(count), dim3(kEigThreads), 0, st, src);
+  else
+    hipLaunchKernelGGL((eig_kernel<S, 4, 8>), dim3(count), dim3(kEigThreads), 0, st, src);
   bool any_big = false;
   for (int i = 0; i < count; ++i) any_big |= !host[i].small;
   if (!any_big) return hipGetLastError();
