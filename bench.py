@@ -6,11 +6,13 @@ full read of X).  Default workload: the FP32 256^4 tensor of multilinear
 rank 32 (decay 0.8, relative noise 1e-4), target ranks 32, p = 10,
 s_k = 10 n_k = 2560 sampled fibers per mode.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--config c2|c3-bf16|c3-f16|c3-f32|c1|c4]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--config c2|c3-bf16|c3-f16|c3-f32|c1|c4|c5|c6]
 
 c5 is Sub-R-RtL-HT on the FP32 18^8 tensor (balanced tree, node ranks 12,
 p = 4, w_S = min(20 n, n_notS) sampled columns per node): node sketches,
-QR + W per node, transfer tensors and the root contraction.
+QR + W per node, transfer tensors and the root contraction.  c6 is the same
+on the closed-form tensor 1/||x|| over [1, 15]^8 in FP32 (node ranks 7).
+Both also time the format's residual pass (htucker_reconstruct).
 
 c4 is the batching form: 512 FP32 tensors of order 3-5 (n_k in [16, 96],
 at most 2^24 entries each, ranks in [4, 16], p = 5), every mode of every
@@ -168,7 +170,7 @@ def main():
     if args.config == "c4":
         bench_batch(args)
         return
-    if args.config == "c5":
+    if args.config in ("c5", "c6"):
         bench_ht(args)
         return
     import numpy as np
@@ -430,7 +432,8 @@ def bench_batch(args):
 
 
 def bench_ht(args):
-    """One step = one htucker_decompose of a resident 18^8 FP32 tensor."""
+    """One step = one htucker_decompose of a resident FP32 tensor (18^8
+    hierarchical rank 12, or the closed-form 15^8)."""
     import numpy as np
     import torch
 
@@ -439,13 +442,18 @@ def bench_ht(args):
     from paper_2603_21379_amd import binding as B
     from paper_2603_21379_amd import tucker as T
 
-    c = configs.C5
+    c = configs.C6 if args.config == "c6" else configs.C5
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     t0 = time.time()
     log(f"generating {c.name} on the host")
-    inp = synthgen.ht_tensor(c.n, c.order, c.rank, c.noise, cfg=c.cfg_id, dtype=c.dtype)
-    tr, dims = inp.tree, inp.dims
+    if args.config == "c6":
+        Xh = synthgen.inverse_norm_tensor(c.n, c.order, c.dtype)
+        tr, dims = synthgen.balanced_tree(c.order), Xh.shape
+    else:
+        inp = synthgen.ht_tensor(c.n, c.order, c.rank, c.noise, cfg=c.cfg_id, dtype=c.dtype)
+        tr, dims, Xh = inp.tree, inp.dims, inp.X
+        del inp
     N = math.prod(dims)
     ranks, ells, ws = {}, {}, {}
     for t in range(1, tr.num_nodes):
@@ -454,8 +462,8 @@ def bench_ht(args):
         ranks[t] = min(c.rank, ells[t])
         ws[t] = min(c.w_alpha * c.n, N // nS)
     sk = synthgen.node_sketches(dims, tr, ells, ws, cfg=c.cfg_id, omega_dtype="f32")
-    X = torch.from_numpy(inp.X).to(dev)
-    del inp
+    X = torch.from_numpy(Xh).to(dev)
+    del Xh
     pairs = [(sk[t], N // math.prod(dims[k] for k in tr.modes(t))) for t in range(1, tr.num_nodes)]
     dsk = T.upload_sketches(pairs, dev, torch.float32)
     skd = {t: dsk[t - 1] for t in range(1, tr.num_nodes)}
@@ -481,6 +489,20 @@ def bench_ht(args):
     achieved = b_root / (root_avg * 1e-3) / 1e9
     log(f"timed {args.steps} steps: {ms_per_step:.3f} ms/step; root pass {root_avg:.3f} ms; "
         f"info {res.info.cpu().tolist()}")
+    # the format's residual: nested bases, then one streaming pass over X
+    leaves = {t: res.U[t] for t in res.U if tr.is_leaf(t)}
+    T.ht_reconstruct(dims, tr, ranks, leaves, res.B, Xref=X)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(3):
+        _, r2 = T.ht_reconstruct(dims, tr, ranks, leaves, res.B, Xref=X)
+    e1.record()
+    torch.cuda.synchronize()
+    ms_resid = e0.elapsed_time(e1) / 3
+    r2 = r2.cpu().tolist()
+    eps = math.sqrt(r2[0] / r2[1])
+    log(f"residual pass {ms_resid:.3f} ms ({N * 4 / ms_resid / 1e6:.1f} GB/s); rel err {eps:.4e}")
     result = {
         "metric": "tensor GB/s streamed (sketch+core), frac of HBM roofline; rel err vs FP64 oracle",
         "value": round(value, 2), "unit": "GB/s", "n_gpus": 1, "steps": args.steps,
@@ -489,6 +511,8 @@ def bench_ht(args):
         "config": {"workload": f"sub-r-rtl-ht {c.name}", "n": c.n, "order": c.order,
                    "node_rank": c.rank, "p": c.p, "w_alpha": c.w_alpha, "noise_rel": c.noise},
         "frac_hbm_step": round(value / HBM_PEAK_GBS, 4),
+        "rel_error": eps, "ms_resid": round(ms_resid, 4),
+        "resid_gbs": round(N * 4 / ms_resid / 1e6, 1),
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
                      "kernel": "root contraction pass", "avg_ms": round(root_avg, 4),

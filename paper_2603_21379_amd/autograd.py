@@ -1,4 +1,5 @@
-"""torch.autograd.Functions for the core projection and the reconstruction.
+"""torch.autograd.Functions for the core projection, the reconstruction and
+the full tensor of an H-Tucker format.
 
 Forward and backward both run in libtkmi's kernels: the backward passes
 call the hand-written vector-Jacobian products (tucker_core_vjp,
@@ -78,3 +79,54 @@ def projection_loss(X, F):
     """||X - R(C(X, F), F)||_F^2 with both maps differentiable."""
     Xh = tucker_reconstruct(tucker_core(X, F), F)
     return ((X - Xh) ** 2).sum()
+
+
+class HTuckerFull(torch.autograd.Function):
+    """Full tensor of an H-Tucker format (root relation and nested bases,
+    Section 4) from its leaf bases and transfer tensors; gradients flow to
+    every leaf basis and every transfer tensor."""
+
+    @staticmethod
+    def forward(ctx, spec, out_dtype, *params):
+        dims, tree, ranks, leaves, internal = spec
+        U = {t: p.contiguous() for t, p in zip(leaves, params[:len(leaves)])}
+        Bd = {t: p.contiguous() for t, p in zip(internal, params[len(leaves):])}
+        rk = [0] + [int(ranks[t]) for t in range(1, tree.num_nodes)]
+        n = tree.num_nodes
+        Ul = [U.get(t) for t in range(n)]
+        Bl = [Bd.get(t) for t in range(n)]
+        Xhat = torch.empty(tuple(dims), dtype=out_dtype, device=params[0].device)
+        B.htucker_reconstruct(list(dims), tree, rk, Ul, Bl, Xhat=Xhat)
+        ctx.spec = spec
+        ctx.save_for_backward(*params)
+        return Xhat
+
+    @staticmethod
+    def backward(ctx, H):
+        dims, tree, ranks, leaves, internal = ctx.spec
+        params = ctx.saved_tensors
+        n = tree.num_nodes
+        Ul = [None] * n
+        Bl = [None] * n
+        for t, p in zip(leaves, params[:len(leaves)]):
+            Ul[t] = p
+        for t, p in zip(internal, params[len(leaves):]):
+            Bl[t] = p
+        rk = [0] + [int(ranks[t]) for t in range(1, n)]
+        Bbar = [torch.empty_like(b) if b is not None else None for b in Bl]
+        Ubar = [torch.empty_like(u) if u is not None else None for u in Ul]
+        Hc = H.contiguous()
+        if Hc.dtype not in (torch.float32, torch.float64):
+            Hc = Hc.double()
+        B.htucker_reconstruct_vjp(list(dims), tree, rk, Ul, Bl, Hc, Bbar, Ubar)
+        return (None, None, *[Ubar[t] for t in leaves], *[Bbar[t] for t in internal])
+
+
+def htucker_full(dims, tree, ranks, U: dict, Bd: dict, out_dtype=torch.float64):
+    """Differentiable full tensor of the format (leaf bases U[t], transfer
+    tensors Bd[t] for internal nodes including the root 0, FP64)."""
+    leaves = [t for t in range(1, tree.num_nodes) if tree.is_leaf(t)]
+    internal = [t for t in range(tree.num_nodes) if not tree.is_leaf(t)]
+    spec = (tuple(dims), tree, dict(ranks), leaves, internal)
+    return HTuckerFull.apply(spec, out_dtype, *[U[t] for t in leaves], *[Bd[t] for t in internal])
+

@@ -49,6 +49,9 @@ class HTConfig:
 
 C5 = HTConfig("c5_ht_fp32_18^8", 5, 18, 8, 12, 1e-5, 4, 20, "f32")
 C5_SMALL = HTConfig("c5_ht_fp32_6^8", 5, 6, 8, 4, 1e-5, 4, 20, "f32")
+# closed-form 1/||x|| on [1, 15]^8 (H-Tucker serial tests, Section 4.2.1): rank 7,
+# w_S = min(20 n, n_notS) fibers per node as in the parallel tests (Section 4.2.2)
+C6 = HTConfig("c6_inverse_norm_fp32_15^8", 6, 15, 8, 7, 0.0, 4, 20, "f32")
 
 C4_COUNT = 512
 C4_CFG_ID = 4

@@ -175,3 +175,26 @@ def test_ht_reconstruct_rejects_bad_arguments():
     with pytest.raises(B.TkError):     # Xref of other dims
         T.ht_reconstruct(dims, tr, ranks, Ud, Bd, Xref=torch.zeros(4, 5, 4, dtype=torch.float64,
                                                                     device="cuda"))
+
+
+def test_htucker_full_autograd_matches_oracle():
+    """loss = <W, Xhat> + ||Xhat||^2 / 2 through torch.autograd: the
+    gradients reaching every leaf basis and transfer tensor are the oracle's
+    VJP at H = dloss/dXhat."""
+    from paper_2603_21379_amd import autograd as A
+    dims, rule, seed = CASES[1]
+    tr, ranks, U, Bt = _format(dims, rule, seed)
+    Wt = np.random.default_rng(7).standard_normal(dims)
+    Ud = {t: torch.from_numpy(v).cuda().requires_grad_() for t, v in U.items()}
+    Bd = {t: torch.from_numpy(v).cuda().requires_grad_() for t, v in Bt.items()}
+    Xh = A.htucker_full(dims, tr, ranks, Ud, Bd)
+    loss = (torch.from_numpy(Wt).cuda() * Xh).sum() + 0.5 * (Xh * Xh).sum()
+    loss.backward()
+    H = Wt + oracle.ht_full(dims, tr, U, Bt)
+    Bbar_or, Ubar_or = oracle.ht_full_vjp(dims, tr, U, Bt, H)
+    for t in Bbar_or:
+        np.testing.assert_allclose(Bd[t].grad.cpu().numpy(), Bbar_or[t], rtol=1e-10,
+                                   atol=1e-11 * np.abs(Bbar_or[t]).max())
+    for t in Ubar_or:
+        np.testing.assert_allclose(Ud[t].grad.cpu().numpy(), Ubar_or[t], rtol=1e-10,
+                                   atol=1e-11 * np.abs(Ubar_or[t]).max())
