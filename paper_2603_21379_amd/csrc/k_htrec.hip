@@ -7,10 +7,14 @@
 // a rank-r_r expansion of the n_l x n_r matricisation.  ht_expand_kernel
 // streams it once: a workgroup owns a tile of columns b and a range of rows a;
 // each lane keeps U_Rr[b][:] of its columns in registers, each row's T[a][:]
-// is wave-uniform (scalar loads), so an entry costs r_r FP64 FMAs and the
-// only HBM traffic is the reference tensor (and the output, if written).
+// is wave-uniform (scalar loads), so an entry costs r_r FP64 FMAs (r_r padded
+// to 8, 12, 16, 32 or 64) and the only HBM traffic is the reference tensor
+// (and the output, if written).  The next group of rows is loaded while the
+// current one is multiplied.
 // The residual ||X - Xhat||^2 and ||X||^2 are accumulated in FP64 per lane,
 // reduced per workgroup and summed in a fixed order.
+#include <type_traits>
+
 #include "tk_kernels.hpp"
 
 namespace tk {
@@ -52,8 +56,10 @@ __global__ __launch_bounds__(256) void ht_rowmat_kernel(const double* UL, const 
 template <typename TX, typename TO, int R>
 __global__ __launch_bounds__(256) void ht_expand_kernel(const HTExpand p) {
   constexpr int C = 64 / R;          // columns per lane
-  constexpr int kRows = 4;           // rows whose loads are issued together
+  constexpr int kRows = 4;           // rows per group; the next group's loads are in
+                                     // flight while this group is multiplied
   constexpr bool kX = !IsNone<TX>::value, kO = !IsNone<TO>::value;
+  using TL = typename std::conditional<kX, TX, float>::type;
   __shared__ double red[2][4];
   const int tid = threadIdx.x;
   const int64_t tile = blockIdx.x % p.ntile, grp = blockIdx.x / p.ntile;
@@ -70,19 +76,21 @@ __global__ __launch_bounds__(256) void ht_expand_kernel(const HTExpand p) {
 #pragma unroll
     for (int k = 0; k < R; ++k) ur[c][k] = (ok[c] && k < p.rr) ? p.UR[col[c] * p.rr + k] : 0.0;
   }
-  const TX* X = static_cast<const TX*>(p.X);
+  const TL* X = static_cast<const TL*>(p.X);
   TO* Xh = static_cast<TO*>(p.Xh);
   double r2 = 0.0, x2 = 0.0;
-  for (int64_t a = a0; a < a1; a += kRows) {
-    double xv[kRows][C];
+  // rows past a1 - 1 load row a1 - 1 again (always in range) and add nothing
+  auto load = [&](int64_t a, TL (&buf)[kRows][C]) {
     if constexpr (kX) {
 #pragma unroll
       for (int u = 0; u < kRows; ++u) {
         const int64_t row = min(a + u, a1 - 1);
 #pragma unroll
-        for (int c = 0; c < C; ++c) xv[u][c] = to_double(X[row * p.nR + col[c]]);
+        for (int c = 0; c < C; ++c) buf[u][c] = X[row * p.nR + col[c]];
       }
     }
+  };
+  auto multiply = [&](int64_t a, const TL (&buf)[kRows][C]) {
 #pragma unroll
     for (int u = 0; u < kRows; ++u) {
       const bool live = a + u < a1;
@@ -97,7 +105,7 @@ __global__ __launch_bounds__(256) void ht_expand_kernel(const HTExpand p) {
 #pragma unroll
         for (int k = 0; k < R; ++k) xh = fma(tk[k], ur[c][k], xh);
         if constexpr (kX) {
-          const double x = (live && ok[c]) ? xv[u][c] : 0.0;
+          const double x = (live && ok[c]) ? to_double(buf[u][c]) : 0.0;
           const double d = (live && ok[c]) ? x - xh : 0.0;
           r2 = fma(d, d, r2);
           x2 = fma(x, x, x2);
@@ -107,6 +115,25 @@ __global__ __launch_bounds__(256) void ht_expand_kernel(const HTExpand p) {
         }
       }
     }
+  };
+  // groups in pairs (ping-pong buffers); a pair past the end multiplies rows
+  // that are not live and adds nothing
+  // (the scheduling fences keep each prefetch ahead of the multiply that
+  // precedes its use; without them the loads sink below it and the wave waits
+  // for every load in flight)
+  TL bA[kRows][C], bB[kRows][C];
+  load(a0, bA);
+  const int pairs = (int)((a1 - a0 + 2 * kRows - 1) / (2 * kRows));
+  int64_t a = a0;
+  for (int it = 0; it < pairs; ++it, a += 2 * kRows) {
+    load(a + kRows, bB);
+    __builtin_amdgcn_sched_barrier(0);
+    multiply(a, bA);
+    __builtin_amdgcn_sched_barrier(0);
+    load(a + 2 * kRows, bA);
+    __builtin_amdgcn_sched_barrier(0);
+    multiply(a + kRows, bB);
+    __builtin_amdgcn_sched_barrier(0);
   }
   if (!p.partials) return;
 #pragma unroll
@@ -153,10 +180,13 @@ __global__ __launch_bounds__(256) void ht_sum_kernel(const double* partials, int
 template <typename TX, typename TO>
 hipError_t expand_by_r(const HTExpand& p, hipStream_t st) {
   const dim3 grid((unsigned)(p.ntile * p.groups));
-  if (p.rpad == 16)
-    hipLaunchKernelGGL((ht_expand_kernel<TX, TO, 16>), grid, dim3(256), 0, st, p);
-  else
-    hipLaunchKernelGGL((ht_expand_kernel<TX, TO, 64>), grid, dim3(256), 0, st, p);
+  switch (p.rpad) {
+    case 8: hipLaunchKernelGGL((ht_expand_kernel<TX, TO, 8>), grid, dim3(256), 0, st, p); break;
+    case 12: hipLaunchKernelGGL((ht_expand_kernel<TX, TO, 12>), grid, dim3(256), 0, st, p); break;
+    case 16: hipLaunchKernelGGL((ht_expand_kernel<TX, TO, 16>), grid, dim3(256), 0, st, p); break;
+    case 32: hipLaunchKernelGGL((ht_expand_kernel<TX, TO, 32>), grid, dim3(256), 0, st, p); break;
+    default: hipLaunchKernelGGL((ht_expand_kernel<TX, TO, 64>), grid, dim3(256), 0, st, p); break;
+  }
   return hipGetLastError();
 }
 
@@ -172,7 +202,9 @@ hipError_t expand_by_out(const HTExpand& p, int out_dt, hipStream_t st) {
 
 }  // namespace
 
-int ht_expand_rpad(int rr) { return rr <= 16 ? 16 : (rr <= 64 ? 64 : 0); }
+int ht_expand_rpad(int rr) {
+  return rr <= 8 ? 8 : rr <= 12 ? 12 : rr <= 16 ? 16 : rr <= 32 ? 32 : rr <= 64 ? 64 : 0;
+}
 
 void ht_expand_grid(HTExpand& p) {
   const int C = 64 / p.rpad;
@@ -200,7 +232,8 @@ hipError_t launch_permute_transfer(const double* in, double* out, int rS, int rl
 }
 
 hipError_t launch_ht_expand(const HTExpand& p, int x_dt, int out_dt, hipStream_t st) {
-  if (p.rpad != 16 && p.rpad != 64) return hipErrorInvalidValue;
+  if (p.rpad != 8 && p.rpad != 12 && p.rpad != 16 && p.rpad != 32 && p.rpad != 64)
+    return hipErrorInvalidValue;
   hipError_t e = hipErrorInvalidValue;
   switch (x_dt) {
     case -1: e = out_dt == -1 ? hipErrorInvalidValue : expand_by_out<None>(p, out_dt, st); break;

@@ -315,7 +315,7 @@ struct HTExpand {
   int32_t rr, rpad;     // rpad = ht_expand_rpad(rr)
   int64_t ntile, groups, rows_per_group;   // set by ht_expand_grid
 };
-int ht_expand_rpad(int rr);           // 16 or 64; 0 = rank above 64
+int ht_expand_rpad(int rr);           // 8, 12, 16, 32 or 64; 0 = rank above 64
 void ht_expand_grid(HTExpand& p);     // fills ntile, groups, rows_per_group
 hipError_t launch_ht_expand(const HTExpand& p, int x_dt, int out_dt, hipStream_t st);   // dt -1 = absent
 hipError_t launch_ht_rowmat(const double* UL, const double* BR, double* T, int64_t nL, int rl, int rr,

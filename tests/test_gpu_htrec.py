@@ -45,6 +45,10 @@ CASES = [
     ((3, 4, 2, 3, 5, 2), lambda t, tr: 2, 3),
     ((9, 8, 7, 6), lambda t, tr: 20 if t == 2 else 4, 4),
     ((37, 1500), lambda t, tr: 5, 5),
+    # the root's right child at ranks 12, 14 and 40 (padded to 12, 16 and 64)
+    ((6, 7, 5, 8), lambda t, tr: 12 if t == 2 else 3, 6),
+    ((5, 6, 4, 9, 3), lambda t, tr: 14 if t == 2 else 3, 7),
+    ((9, 4, 7, 50), lambda t, tr: 40 if t == 2 else 4, 8),
 ]
 
 
