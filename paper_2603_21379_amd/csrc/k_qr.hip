@@ -604,8 +604,29 @@ __global__ __launch_bounds__(kEigThreads) void eig_kernel(const S b) {
     p = min(a, c);
     q = max(a, c);
   };
+  // Pairs of two indices that currently rank below the r largest diagonal
+  // entries are not rotated: such a rotation only mixes directions that are
+  // dropped, so it changes neither the kept eigenvectors nor their decoupling.
+  // Once no other pair rotates, a Gershgorin bound checks that the unreduced
+  // block of those indices lies below every kept diagonal entry (so the kept
+  // ones are the r largest eigenvalues); if it does not, full sweeps resume.
+  bool skip_dropped = M.r < n;
   for (int sweep = 0; sweep < 60; ++sweep) {
     bool rotated = false;   // any rotation in this sweep (wave-uniform, equal in every wave)
+    uint64_t dropped = 0;   // indices ranked r or later by diagonal (ties: lower index first)
+    if (skip_dropped) {
+      bool d = false;
+      if (lane < n) {
+        const double di = A[lane][lane];
+        int rk = 0;
+        for (int j = 0; j < n; ++j) {
+          const double dj = A[j][j];
+          rk += (dj > di) || (dj == di && j < lane);
+        }
+        d = rk >= M.r;
+      }
+      dropped = __ballot(d);
+    }
     for (int round = 0; round < np - 1; ++round) {
       // every wave computes the round's ell/2 disjoint rotations (lane k:
       // rotation k), so no wave waits for another's parameters
@@ -614,7 +635,7 @@ __global__ __launch_bounds__(kEigThreads) void eig_kernel(const S b) {
         int p, q;
         pair_of(lane, round, p, q);
         double c = 1.0, sn = 0.0;
-        if (q < n) {
+        if (q < n && !(((dropped >> p) & 1) && ((dropped >> q) & 1))) {
           const double apq = A[p][q], app = A[p][p], aqq = A[q][q];
           if (fabs(apq) > tol * fmax(fabs(app), fabs(aqq))) {
             // t = tan of the rotation angle, the root of t^2 + 2 theta t - 1
@@ -690,7 +711,28 @@ __global__ __launch_bounds__(kEigThreads) void eig_kernel(const S b) {
       }
       __syncthreads();
     }
-    if (!rotated) break;
+    if (!rotated) {
+      if (dropped == 0) break;
+      double top_min = INFINITY, drop_max = -INFINITY;
+      if (lane < n) {
+        const double di = A[lane][lane];
+        if ((dropped >> lane) & 1) {
+          double rad = 0.0;
+          for (int j = 0; j < n; ++j)
+            if (j != lane && ((dropped >> j) & 1)) rad += fabs(A[lane][j]);
+          drop_max = di + rad;
+        } else {
+          top_min = di;
+        }
+      }
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) {
+        top_min = fmin(top_min, __shfl_xor(top_min, off));
+        drop_max = fmax(drop_max, __shfl_xor(drop_max, off));
+      }
+      if (drop_max < top_min) break;
+      skip_dropped = false;
+    }
   }
   // rank of each eigenvalue in descending order (ties: lower index first)
   __shared__ int rank_of[kMaxEll];
