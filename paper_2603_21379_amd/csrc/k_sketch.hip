@@ -8,6 +8,8 @@
 // of Omega_S in FP64.  Per-chunk partial products go to the workspace and a
 // second kernel sums them in a fixed order, so Z_S = Y_S Omega_S is
 // deterministic.
+#include <type_traits>
+
 #include "tk_kernels.hpp"
 
 namespace tk {
@@ -19,7 +21,10 @@ __global__ __launch_bounds__(256) void sketch_gather_kernel(const S b) {
   __shared__ double sO[kSketchCols][64 + 1];
   __shared__ int64_t sFib[kSketchCols];   // offset of element 0 of each fiber, or -1
   const int64_t blk = blockIdx.x;
-  const SketchUnit& U = b.get(b.find_block(blk));
+  // the unit's descriptor in registers: read through a reference into a device
+  // table, every field would be reloaded after each store of the kernel (the
+  // stores may alias the table), thousands of extra loads per block
+  const SketchUnit U = wave_uniform(b.get(b.find_block(blk)));
   // fiber chunks vary fastest: blocks running together share rows, which
   // keeps the pages they touch few when fibers are strided (B > 1)
   const int64_t lb = blk - U.block_begin;
@@ -78,6 +83,31 @@ __global__ __launch_bounds__(256) void sketch_gather_kernel(const S b) {
   }
   const TO* Om = static_cast<const TO*>(U.omega);
   const int row = tid >> 2, lane4 = tid & 3;
+  const int64_t gi = i0 + row;
+  // thread (row, lane4) forms columns lane4 + 4 q of the 64-column chunk; only
+  // the accumulators the sketch width needs are formed (QN of 16), and rows
+  // past n skip the products (a wave of such rows skips them entirely)
+  auto tile = [&](int e0, auto qn) {
+    constexpr int QN = decltype(qn)::value;
+    double acc[QN];
+#pragma unroll
+    for (int q = 0; q < QN; ++q) acc[q] = 0.0;
+    if (gi < U.n) {
+      // (unrolled by two only: a full unroll hoists every load of the 32
+      // steps and spills to scratch)
+#pragma unroll 2
+      for (int t = 0; t < kSketchCols; ++t) {
+        const double y = sY[row][t];
+#pragma unroll
+        for (int q = 0; q < QN; ++q) acc[q] = fma(y, sO[t][lane4 + 4 * q], acc[q]);
+      }
+#pragma unroll
+      for (int q = 0; q < QN; ++q) {
+        const int jj = e0 + lane4 + 4 * q;
+        if (jj < U.ell) U.partial[(chunk * U.n + gi) * U.ell + jj] = acc[q];
+      }
+    }
+  };
   for (int e0 = 0; e0 < U.ell; e0 += 64) {
     __syncthreads();
     for (int e = tid; e < kSketchCols * 64; e += blockDim.x) {
@@ -86,22 +116,11 @@ __global__ __launch_bounds__(256) void sketch_gather_kernel(const S b) {
       sO[t][jj] = (gt < U.s && e0 + jj < U.ell) ? to_double(Om[gt * U.ell + e0 + jj]) : 0.0;
     }
     __syncthreads();
-    double acc[16];
-#pragma unroll
-    for (int q = 0; q < 16; ++q) acc[q] = 0.0;
-    for (int t = 0; t < kSketchCols; ++t) {
-      const double y = sY[row][t];
-#pragma unroll
-      for (int q = 0; q < 16; ++q) acc[q] = fma(y, sO[t][lane4 + 4 * q], acc[q]);
-    }
-    const int64_t gi = i0 + row;
-    if (gi < U.n) {
-#pragma unroll
-      for (int q = 0; q < 16; ++q) {
-        const int jj = e0 + lane4 + 4 * q;
-        if (jj < U.ell) U.partial[(chunk * U.n + gi) * U.ell + jj] = acc[q];
-      }
-    }
+    const int width = U.ell - e0 < 64 ? U.ell - e0 : 64;
+    if (width <= 16) tile(e0, std::integral_constant<int, 4>{});
+    else if (width <= 32) tile(e0, std::integral_constant<int, 8>{});
+    else if (width <= 48) tile(e0, std::integral_constant<int, 12>{});
+    else tile(e0, std::integral_constant<int, 16>{});
   }
 }
 
@@ -109,7 +128,7 @@ template <typename S>
 __global__ __launch_bounds__(256) void sketch_reduce_kernel(const S b) {
   const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= b.total_out) return;
-  const SketchUnit& U = b.get(b.find_out(g));
+  const SketchUnit U = b.get(b.find_out(g));   // by value: fields loaded once
   const int64_t e = g - U.out_begin;
   const int64_t plane = U.n * U.ell;
   double acc = 0.0;
