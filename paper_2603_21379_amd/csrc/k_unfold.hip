@@ -5,9 +5,10 @@
 // there, B has c_k), both viewed as (pre, ., post).
 //
 // The (p, q) range is split into `splits` ranges; block (i, split, chunk)
-// forms up to CMAX outputs (columns chunk*CMAX ..) of row i over its range with a fixed-order tree reduction
-// across the block, writes them as a partial, and a second kernel sums the
-// partials in index order (deterministic, no atomics).
+// forms up to CMAX outputs (columns chunk*CMAX ..) of row i over its range,
+// reduces them across the block in a fixed order, writes them as a partial,
+// and a second kernel sums the partials in index order (deterministic, no
+// atomics).
 #include "tk_kernels.hpp"
 
 namespace tk {
@@ -15,7 +16,7 @@ namespace {
 
 template <typename TA, typename TB, int CMAX>
 __global__ __launch_bounds__(256) void unfold_gemm_kernel(const UnfoldGemm g) {
-  __shared__ double red[256];
+  __shared__ double red[4 * CMAX];
   const int i = blockIdx.x, split = blockIdx.y, tid = threadIdx.x;
   const int a0 = blockIdx.z * CMAX, cc = min(CMAX, g.c - a0);
   const int64_t R = g.pre * g.post;
@@ -34,19 +35,21 @@ __global__ __launch_bounds__(256) void unfold_gemm_kernel(const UnfoldGemm g) {
     for (int a = 0; a < CMAX; ++a)
       if (a < cc) acc[a] = fma(x, to_double(b[(int64_t)a * g.post]), acc[a]);
   }
-  double* out = g.partials + ((int64_t)split * g.n + i) * g.c + a0;
+  // every accumulator reduced across the wave (fixed butterfly order), then
+  // the four waves' sums in a fixed order; acc stays in registers (a loop
+  // over a with barriers inside would index it dynamically)
 #pragma unroll
   for (int a = 0; a < CMAX; ++a) {
-    if (a >= cc) break;
-    red[tid] = acc[a];
-    __syncthreads();
-    for (int s = 128; s > 0; s >>= 1) {
-      if (tid < s) red[tid] += red[tid + s];
-      __syncthreads();
-    }
-    if (tid == 0) out[a] = red[0];
-    __syncthreads();
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) acc[a] += __shfl_xor(acc[a], off);
   }
+  if ((tid & 63) == 0) {
+#pragma unroll
+    for (int a = 0; a < CMAX; ++a) red[(tid >> 6) * CMAX + a] = acc[a];
+  }
+  __syncthreads();
+  double* out = g.partials + ((int64_t)split * g.n + i) * g.c + a0;
+  if (tid < cc) out[tid] = (red[tid] + red[CMAX + tid]) + (red[2 * CMAX + tid] + red[3 * CMAX + tid]);
 }
 
 template <typename TO>
