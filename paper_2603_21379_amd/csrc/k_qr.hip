@@ -528,13 +528,13 @@ constexpr int kEigThreads = 256;
 
 // IA, IV: A-block and V-pair items per thread, sized by the launcher for the
 // widest sketch of the batch so the per-round loads are straight-line code
-template <typename S, int IA, int IV>
+template <typename S, int IA, int IV, int E>
 __global__ __launch_bounds__(kEigThreads) void eig_kernel(const S b) {
   const QRMat& M = b.get(blockIdx.x);
-  __shared__ double A[kMaxEll][kMaxEll + 1];
-  __shared__ double V[kMaxEll][kMaxEll + 1];
+  __shared__ double A[E][E + 1];
+  __shared__ double V[E][E + 1];
   // (c, s) of the current round's rotations, one copy per wave
-  __shared__ double2 rot_cs[kEigThreads / 64][kMaxEll / 2];
+  __shared__ double2 rot_cs[kEigThreads / 64][E / 2];
   const int n = M.ell, np = n + (n & 1), half = np / 2, tid = threadIdx.x;
   // rotations stop below rounding level of the output precision (relative to
   // the pair's own scale): FP64 bases need ~u, FP32 bases ~1e-12 suffices
@@ -543,7 +543,7 @@ __global__ __launch_bounds__(kEigThreads) void eig_kernel(const S b) {
   // all loads of a group in flight together (each element still sums the
   // chunks in index order)
   {
-    constexpr int kE = kMaxEll * kMaxEll / kEigThreads;
+    constexpr int kE = E * E / kEigThreads;
     double v[kE];
 #pragma unroll
     for (int k = 0; k < kE; ++k) v[k] = 0.0;
@@ -735,7 +735,7 @@ __global__ __launch_bounds__(kEigThreads) void eig_kernel(const S b) {
     }
   }
   // rank of each eigenvalue in descending order (ties: lower index first)
-  __shared__ int rank_of[kMaxEll];
+  __shared__ int rank_of[E];
   for (int i = tid; i < n; i += kEigThreads) {
     const double li = A[i][i];
     int rank = 0;
@@ -759,13 +759,13 @@ __global__ __launch_bounds__(kEigThreads) void eig_kernel(const S b) {
   const int tpc = kEigThreads / r;            // threads per column
   const int j = tid % r, slot = tid / r;      // column and this thread's row slot
   const bool active = slot < tpc;
-  __shared__ double sQ[32][kMaxEll + 1];
+  __shared__ double sQ[32][E + 1];
   double best = -1.0, bval = 0.0;
   int64_t bidx = INT64_MAX;
   const bool f64 = M.udtype == TK_F64;
   // rows of Q in chunks of 32, the next chunk's loads in flight (registers)
   // while the current one is multiplied
-  constexpr int kPre = 32 * kMaxEll / kEigThreads;
+  constexpr int kPre = 32 * E / kEigThreads;
   double pre[kPre];
   auto fetch = [&](int64_t r0) {
     const int rows = (int)min<int64_t>(32, M.m - r0);
@@ -800,7 +800,7 @@ __global__ __launch_bounds__(kEigThreads) void eig_kernel(const S b) {
   // per column: largest |u|, lowest row on ties
   __shared__ double cand_v[kEigThreads], cand_a[kEigThreads];
   __shared__ int64_t cand_i[kEigThreads];
-  __shared__ double sgn[kMaxEll];
+  __shared__ double sgn[E];
   cand_a[tid] = active ? best : -1.0;
   cand_v[tid] = bval;
   cand_i[tid] = bidx;
@@ -968,14 +968,16 @@ hipError_t wstep_impl(const S& src, const QRMat* host, int count, int ydtype, in
   const int np = ellmax + (ellmax & 1), half = np / 2;
   const int ia = (int)ceil_div((int64_t)half * half, kEigThreads);
   const int iv = (int)ceil_div((int64_t)np * half, kEigThreads);
-  if (ia <= 1 && iv <= 2)
-    hipLaunchKernelGGL((eig_kernel<S, 1, 2>), dim3(count), dim3(kEigThreads), 0, st, src);
+  // LDS sized for the widest sketch too (E = 32 or 64): narrow sketches then
+  // fit several workgroups per CU, which a batch of many matrices needs
+  if (np <= 32)
+    hipLaunchKernelGGL((eig_kernel<S, 1, 2, 32>), dim3(count), dim3(kEigThreads), 0, st, src);
   else if (ia <= 2 && iv <= 4)
-    hipLaunchKernelGGL((eig_kernel<S, 2, 4>), dim3(count), dim3(kEigThreads), 0, st, src);
+    hipLaunchKernelGGL((eig_kernel<S, 2, 4, 64>), dim3(count), dim3(kEigThreads), 0, st, src);
   else if (ia <= 3 && iv <= 6)
-    hipLaunchKernelGGL((eig_kernel<S, 3, 6>), dim3(count), dim3(kEigThreads), 0, st, src);
+    hipLaunchKernelGGL((eig_kernel<S, 3, 6, 64>), dim3(count), dim3(kEigThreads), 0, st, src);
   else
-    hipLaunchKernelGGL((eig_kernel<S, 4, 8>), dim3(count), dim3(kEigThreads), 0, st, src);
+    hipLaunchKernelGGL((eig_kernel<S, 4, 8, 64>), dim3(count), dim3(kEigThreads), 0, st, src);
   bool any_big = false;
   for (int i = 0; i < count; ++i) any_big |= !host[i].small;
   if (!any_big) return hipGetLastError();
