@@ -248,6 +248,57 @@ __global__ __launch_bounds__(256) void expand_residual_kernel(const ExpandResidu
   }
 }
 
+// The same for a short last mode (n <= 256): thread (r, i) of a block owns
+// column i of rows r, r + RP, ... (RP = 256 / n rows per step), so F[i][:]
+// stays in registers, the lanes of a wave share one or two rows of T (cached
+// loads) and no element index is divided.  Same partials as above.
+template <typename TX, typename TF, int CB>
+__global__ __launch_bounds__(256) void expand_residual_rows_kernel(const ExpandResidual e) {
+  __shared__ double red[2][4];
+  const int tid = threadIdx.x;
+  const int n = (int)e.n, RP = 256 / n;
+  const int r = tid / n, i = tid - r * n;
+  const bool on = r < RP;
+  const TF* F = static_cast<const TF*>(e.F);
+  const TX* X = static_cast<const TX*>(e.X);
+  TF* Xh = static_cast<TF*>(e.Xhat);
+  double f[CB];
+#pragma unroll
+  for (int k = 0; k < CB; ++k) f[k] = (on && k < e.c) ? to_double(F[(int64_t)i * e.c + k]) : 0.0;
+  double r2 = 0.0, x2 = 0.0;
+  if (on) {
+    for (int64_t a = (int64_t)blockIdx.x * RP + r; a < e.A; a += (int64_t)gridDim.x * RP) {
+      const double* t = e.T + a * e.c;
+      double v = 0.0;
+#pragma unroll
+      for (int k = 0; k < CB; ++k) v = fma(k < e.c ? t[k] : 0.0, f[k], v);
+      const int64_t g = a * n + i;
+      if (Xh) Xh[g] = from_double<TF>(e.accumulate ? v + to_double(Xh[g]) : v);
+      if (X) {
+        const double x = to_double(X[g]);
+        const double d = x - v;
+        r2 = fma(d, d, r2);
+        x2 = fma(x, x, x2);
+      }
+    }
+  }
+  if (!e.partials) return;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    r2 += __shfl_xor(r2, off);
+    x2 += __shfl_xor(x2, off);
+  }
+  if ((tid & 63) == 0) {
+    red[0][tid >> 6] = r2;
+    red[1][tid >> 6] = x2;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    e.partials[2 * blockIdx.x] = (red[0][0] + red[0][1]) + (red[0][2] + red[0][3]);
+    e.partials[2 * blockIdx.x + 1] = (red[1][0] + red[1][1]) + (red[1][2] + red[1][3]);
+  }
+}
+
 __global__ __launch_bounds__(256) void final_sum_kernel(const double* partials, int nblocks,
                                                         double* out) {
   __shared__ double red[2][256];
@@ -276,7 +327,16 @@ __global__ __launch_bounds__(256) void final_sum_kernel(const double* partials, 
 template <typename TX, typename TF>
 hipError_t expand_residual(const ExpandResidual& e, hipStream_t st) {
   const int nb = (int)expand_residual_blocks(e.A * e.n);
-  hipLaunchKernelGGL((expand_residual_kernel<TX, TF>), dim3(nb), dim3(256), 0, st, e);
+  if (e.n <= 256 && e.c <= 64) {
+    if (e.c <= 16)
+      hipLaunchKernelGGL((expand_residual_rows_kernel<TX, TF, 16>), dim3(nb), dim3(256), 0, st, e);
+    else if (e.c <= 32)
+      hipLaunchKernelGGL((expand_residual_rows_kernel<TX, TF, 32>), dim3(nb), dim3(256), 0, st, e);
+    else
+      hipLaunchKernelGGL((expand_residual_rows_kernel<TX, TF, 64>), dim3(nb), dim3(256), 0, st, e);
+  } else {
+    hipLaunchKernelGGL((expand_residual_kernel<TX, TF>), dim3(nb), dim3(256), 0, st, e);
+  }
   if (e.partials && e.resid2)
     hipLaunchKernelGGL(final_sum_kernel, dim3(1), dim3(256), 0, st, e.partials, nb, e.resid2);
   return hipGetLastError();
