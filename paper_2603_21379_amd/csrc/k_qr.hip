@@ -214,24 +214,33 @@ constexpr int kSmallChunk = 32;
   } while (0)
 
 // Upper Cholesky factor in place, by the 64 lanes of one wave (no barriers).
+// Left-looking: lane q owns column q and step j forms
+//   R[j][q] = (G[j][q] - sum_{k<j} R[k][j] R[k][q]) / R[j][j]   (q >= j),
+// reading only rows k < j, which are final; the dot products keep four
+// partial sums so their loads pipeline, and each step stores one entry per
+// lane.  The lower triangle is not touched (the Gram is reloaded from
+// registers for a shifted retry).
 __device__ bool cholesky_upper_wave(double (*G)[kMaxEll + 1], int n, int lane, double tol) {
+  const int q = lane;
+  const bool mine = q < n;
   for (int j = 0; j < n; ++j) {
-    const double piv = G[j][j];
-    if (!(piv > tol)) return false;  // uniform: every lane read the same pivot
-    const double rjj = sqrt(piv), inv = 1.0 / rjj;
-    TK_WAVE_SYNC();
-    // lane q owns column q (n <= 64): scale row j, then the trailing update
-    // of its column, rows j < p <= q (row p's multiplier is a broadcast)
-    const int q = lane;
-    double gjq = 0.0;
-    if (q > j && q < n) {
-      gjq = G[j][q] * inv;
-      G[j][q] = gjq;
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    if (mine && q >= j) {
+      int k = 0;
+      for (; k + 4 <= j; k += 4) {
+        s0 = fma(G[k][j], G[k][q], s0);
+        s1 = fma(G[k + 1][j], G[k + 1][q], s1);
+        s2 = fma(G[k + 2][j], G[k + 2][q], s2);
+        s3 = fma(G[k + 3][j], G[k + 3][q], s3);
+      }
+      for (; k < j; ++k) s0 = fma(G[k][j], G[k][q], s0);
     }
-    if (lane == 0) G[j][j] = rjj;
-    TK_WAVE_SYNC();
-    if (q > j && q < n)
-      for (int p = j + 1; p <= q; ++p) G[p][q] -= G[j][p] * gjq;
+    const double val = (mine && q >= j) ? G[j][q] - ((s0 + s1) + (s2 + s3)) : 0.0;
+    const double piv = __shfl(val, j);
+    if (!(piv > tol)) return false;  // uniform: every lane holds lane j's pivot
+    const double rjj = sqrt(piv), inv = 1.0 / rjj;
+    if (mine && q > j) G[j][q] = val * inv;
+    if (q == j) G[j][j] = rjj;
     TK_WAVE_SYNC();
   }
   return true;
