@@ -6,12 +6,14 @@ full read of X).  Default workload: the FP32 256^4 tensor of multilinear
 rank 32 (decay 0.8, relative noise 1e-4), target ranks 32, p = 10,
 s_k = 10 n_k = 2560 sampled fibers per mode.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--config c2|c3-bf16|c3-f16|c3-f32|c1|c4|c5|c6]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--config c2|c3-bf16|c3-f16|c3-f32|c1|c4|c5|c6|c7]
 
 c5 is Sub-R-RtL-HT on the FP32 18^8 tensor (balanced tree, node ranks 12,
 p = 4, w_S = min(20 n, n_notS) sampled columns per node): node sketches,
 QR + W per node, transfer tensors and the root contraction.  c6 is the same
-on the closed-form tensor 1/||x|| over [1, 15]^8 in FP32 (node ranks 7).
+on the closed-form tensor 1/||x|| over [1, 15]^8 in FP32 (node ranks 7); c7
+the same with the serial tests' rule w_S = min(2^(d-2) n_S, n_notS), which
+samples the root's two children densely.
 Both also time the format's residual pass (htucker_reconstruct).
 
 c4 is the batching form: 512 FP32 tensors of order 3-5 (n_k in [16, 96],
@@ -170,7 +172,7 @@ def main():
     if args.config == "c4":
         bench_batch(args)
         return
-    if args.config in ("c5", "c6"):
+    if args.config in ("c5", "c6", "c7"):
         bench_ht(args)
         return
     import numpy as np
@@ -442,12 +444,12 @@ def bench_ht(args):
     from paper_2603_21379_amd import binding as B
     from paper_2603_21379_amd import tucker as T
 
-    c = configs.C6 if args.config == "c6" else configs.C5
+    c = {"c5": configs.C5, "c6": configs.C6, "c7": configs.C7}[args.config]
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     t0 = time.time()
     log(f"generating {c.name} on the host")
-    if args.config == "c6":
+    if args.config in ("c6", "c7"):
         Xh = synthgen.inverse_norm_tensor(c.n, c.order, c.dtype)
         tr, dims = synthgen.balanced_tree(c.order), Xh.shape
     else:
@@ -460,7 +462,13 @@ def bench_ht(args):
         nS = math.prod(dims[k] for k in tr.modes(t))
         ells[t] = min(c.rank + c.p, nS, N // nS)
         ranks[t] = min(c.rank, ells[t])
-        ws[t] = min(c.w_alpha * c.n, N // nS)
+        if c.sample_rule == "nS":
+            ws[t] = min(c.w_alpha ** (c.order - 2) * nS, N // nS)
+        else:
+            ws[t] = min(c.w_alpha * c.n, N // nS)
+    dense = [t for t in ws if ws[t] == N // math.prod(dims[k] for k in tr.modes(t))]
+    if dense:
+        log(f"dense nodes (every column sampled): {dense}")
     sk = synthgen.node_sketches(dims, tr, ells, ws, cfg=c.cfg_id, omega_dtype="f32")
     X = torch.from_numpy(Xh).to(dev)
     del Xh
@@ -483,7 +491,10 @@ def bench_ht(args):
     B.tk_profile_enable(False)
     root_ms, launches = B.tk_profile_read(reset=True)
     root_avg = root_ms / max(launches, 1)
-    b_sketch = sum(ws[t] * math.prod(dims[k] for k in tr.modes(t)) for t in ws) * 4
+    # a dense node reads X twice (its sketch and its W step); a sampled one
+    # its gathered fibers
+    b_sketch = sum(2 * N if t in dense else ws[t] * math.prod(dims[k] for k in tr.modes(t))
+                   for t in ws) * 4
     b_root = N * 4
     value = (b_sketch + b_root) / (ms_per_step * 1e-3) / 1e9
     achieved = b_root / (root_avg * 1e-3) / 1e9
@@ -509,7 +520,8 @@ def bench_ht(args):
         "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": f"sub-r-rtl-ht {c.name}", "n": c.n, "order": c.order,
-                   "node_rank": c.rank, "p": c.p, "w_alpha": c.w_alpha, "noise_rel": c.noise},
+                   "node_rank": c.rank, "p": c.p, "w_alpha": c.w_alpha, "noise_rel": c.noise,
+                   "sample_rule": c.sample_rule, "dense_nodes": dense},
         "frac_hbm_step": round(value / HBM_PEAK_GBS, 4),
         "rel_error": eps, "ms_resid": round(ms_resid, 4),
         "resid_gbs": round(N * 4 / ms_resid / 1e6, 1),

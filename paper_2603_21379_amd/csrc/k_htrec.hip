@@ -40,6 +40,27 @@ __global__ __launch_bounds__(256) void permute_transfer_kernel(const double* in,
     out[g] = in[c];
 }
 
+// out[a][e][b] = om[(a B + b) ell + e]: the Gaussian of a dense node sketch in
+// the (pre, ell, post) layout of an unfolded product
+template <typename T>
+__global__ __launch_bounds__(256) void omega_unfold_kernel(const T* om, T* out, int64_t A, int64_t B, int ell) {
+  const int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t total = A * B * ell;
+  if (g >= total) return;
+  const int64_t b = g % B, ae = g / B;
+  const int64_t e = ae % ell, a = ae / ell;
+  out[g] = om[(a * B + b) * ell + e];
+}
+
+// out[c][r] = in[r][c] for an rows x cols FP64 matrix
+__global__ __launch_bounds__(256) void transpose_f64_kernel(const double* in, double* out, int64_t rows,
+                                                            int64_t cols) {
+  const int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (g >= rows * cols) return;
+  const int64_t r = g / cols, c = g - r * cols;
+  out[c * rows + r] = in[g];
+}
+
 // T[a][k] = sum_j UL[a][j] BR[j][k] for k < rr; 0 for rr <= k < rpad
 __global__ __launch_bounds__(256) void ht_rowmat_kernel(const double* UL, const double* BR, double* T,
                                                         int64_t nL, int rl, int rr, int rpad) {
@@ -220,6 +241,30 @@ hipError_t launch_ht_rowmat(const double* UL, const double* BR, double* T, int64
   if (n == 0) return hipSuccess;
   hipLaunchKernelGGL(ht_rowmat_kernel, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, st, UL, BR, T,
                      nL, rl, rr, rpad);
+  return hipGetLastError();
+}
+
+hipError_t launch_transpose_f64(const double* in, double* out, int64_t rows, int64_t cols, hipStream_t st) {
+  const int64_t n = rows * cols;
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(transpose_f64_kernel, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, st, in, out, rows,
+                     cols);
+  return hipGetLastError();
+}
+
+hipError_t launch_omega_to_unfolded(const void* om, void* out, int dt, int64_t A, int64_t B, int ell,
+                                    hipStream_t st) {
+  const int64_t n = A * B * ell;
+  if (n == 0) return hipSuccess;
+  const dim3 grid((unsigned)ceil_div(n, 256));
+  if (dt == TK_F64)
+    hipLaunchKernelGGL(omega_unfold_kernel<double>, grid, dim3(256), 0, st, static_cast<const double*>(om),
+                       static_cast<double*>(out), A, B, ell);
+  else if (dt == TK_F32)
+    hipLaunchKernelGGL(omega_unfold_kernel<float>, grid, dim3(256), 0, st, static_cast<const float*>(om),
+                       static_cast<float*>(out), A, B, ell);
+  else
+    return hipErrorInvalidValue;
   return hipGetLastError();
 }
 

@@ -956,21 +956,26 @@ hipError_t cholqr_impl(const S& src, const QRMat* host, int count, hipStream_t s
   return hipGetLastError();
 }
 
+// gram_given: every matrix's cpart already holds the Gram of Q^T Y (ncc = 1),
+// so the Q^T Y and Gram kernels are skipped
 template <typename S>
-hipError_t wstep_impl(const S& src, const QRMat* host, int count, int ydtype, int udtype, hipStream_t st) {
+hipError_t wstep_impl(const S& src, const QRMat* host, int count, int ydtype, int udtype, hipStream_t st,
+                      bool gram_given = false) {
   if (count == 0) return hipSuccess;
   const int ncc = max_field(host, count, 1), nrb = max_field(host, count, 2);
   int64_t qty_blocks = 0;
   for (int i = 0; i < count; ++i) qty_blocks = host[i].qty_begin + (int64_t)host[i].nrc * host[i].ncc;
-  const dim3 gq((unsigned)qty_blocks);
-  switch (ydtype) {
-    case TK_F64: hipLaunchKernelGGL((qty_partial_kernel<double, S>), gq, dim3(256), 0, st, src, count); break;
-    case TK_F32: hipLaunchKernelGGL((qty_partial_kernel<float, S>), gq, dim3(256), 0, st, src, count); break;
-    case TK_BF16: hipLaunchKernelGGL((qty_partial_kernel<bf16, S>), gq, dim3(256), 0, st, src, count); break;
-    case TK_F16: hipLaunchKernelGGL((qty_partial_kernel<f16, S>), gq, dim3(256), 0, st, src, count); break;
-    default: return hipErrorInvalidValue;
+  if (!gram_given) {
+    const dim3 gq((unsigned)qty_blocks);
+    switch (ydtype) {
+      case TK_F64: hipLaunchKernelGGL((qty_partial_kernel<double, S>), gq, dim3(256), 0, st, src, count); break;
+      case TK_F32: hipLaunchKernelGGL((qty_partial_kernel<float, S>), gq, dim3(256), 0, st, src, count); break;
+      case TK_BF16: hipLaunchKernelGGL((qty_partial_kernel<bf16, S>), gq, dim3(256), 0, st, src, count); break;
+      case TK_F16: hipLaunchKernelGGL((qty_partial_kernel<f16, S>), gq, dim3(256), 0, st, src, count); break;
+      default: return hipErrorInvalidValue;
+    }
+    hipLaunchKernelGGL(mgram_kernel<S>, dim3(ncc, count), dim3(256), 0, st, src);
   }
-  hipLaunchKernelGGL(mgram_kernel<S>, dim3(ncc, count), dim3(256), 0, st, src);
   // items per thread for the widest sketch: half^2 A blocks and np * half V pairs
   int ellmax = 1;
   for (int i = 0; i < count; ++i) ellmax = std::max(ellmax, host[i].ell);
@@ -1004,6 +1009,10 @@ hipError_t launch_cholqr(const QRBatch& b, hipStream_t st) { return cholqr_impl(
 
 hipError_t launch_wstep(const QRBatch& b, int ydtype, int udtype, hipStream_t st) {
   return wstep_impl(b, b.m, b.count, ydtype, udtype, st);
+}
+
+hipError_t launch_wstep_gram(const QRBatch& b, int udtype, hipStream_t st) {
+  return wstep_impl(b, b.m, b.count, TK_F64, udtype, st, true);
 }
 
 hipError_t launch_cholqr_list(const QRList& dev, const QRMat* host, hipStream_t st) {

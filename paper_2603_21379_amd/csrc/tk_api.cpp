@@ -164,6 +164,25 @@ tk_status run_qr(std::vector<QRMat>& mats, int ydtype, int udtype, bool wstep, h
   return TK_OK;
 }
 
+// The W step alone (CholeskyQR already done); gram: the matrices' cpart
+// holds the Gram of Q^T Y (ncc = 1)
+tk_status run_wstep(std::vector<QRMat>& mats, int ydtype, int udtype, bool gram, hipStream_t st) {
+  for (size_t g = 0; g < mats.size(); g += kQRMaxBatch) {
+    QRBatch b{};
+    b.count = (int32_t)std::min<size_t>(kQRMaxBatch, mats.size() - g);
+    int64_t qb = 0;
+    for (int i = 0; i < b.count; ++i) {
+      b.m[i] = mats[g + i];
+      b.m[i].udtype = udtype;
+      b.m[i].qty_begin = qb;
+      qb += (int64_t)b.m[i].nrc * b.m[i].ncc;
+    }
+    if (gram) TK_HIP(launch_wstep_gram(b, udtype, st));
+    else TK_HIP(launch_wstep(b, ydtype, udtype, st));
+  }
+  return TK_OK;
+}
+
 tk_status check_factors(int order, const int64_t* dims, const void* const* F, const int32_t* cols,
                         const char* who) {
   if (!F) return set_error(TK_EINVAL, "%s: factor array is NULL", who);
@@ -1209,23 +1228,49 @@ tk_status htucker_decompose(const tk_tensor* X, const tk_tree* tree, const int32
   const int fdt = TK_F64;
   Workspace w;
   w.base = static_cast<char*>(ws);
+  // A dense node (every column sampled: idx NULL, s = n_notS) whose modes
+  // are a prefix or a suffix of X's (the root's children) is sketched and
+  // W-stepped by products with X itself: Z = X^(S) Omega and M = Q^T X^(S)
+  // are mode products along X's first or last dimension, and the W step
+  // starts from the Gram M M^T, so no copy of the unfolding is formed.
+  // Other nodes gather their sampled columns.
+  const bool xf = X->dtype == TK_F64 || X->dtype == TK_F32;
+  std::vector<char> dense(nn, 0);
+  for (int t = 1; t < nn; ++t)
+    dense[t] = xf && sk[t].idx == nullptr && sk[t].s == nc[t] && (A[t] == 1 || Bv[t] == 1) && nc[t] > 1;
+  const int odt = X->dtype == TK_F64 ? TK_F64 : TK_F32;   // Omega's dtype (the factor dtype)
   // sketches of every non-root node
   SketchBatch sb{};
-  sb.count = nn - 1;
   std::vector<double*> Z(nn, nullptr);
   std::vector<void*> Y(nn, nullptr);
   const size_t xs = dtype_size(X->dtype);
   for (int t = 1; t < nn; ++t) {
     Z[t] = w.take<double>((size_t)nS[t] * sk[t].ell);
-    Y[t] = w.take<char>((size_t)nS[t] * sk[t].s * xs);
+    if (!dense[t]) Y[t] = w.take<char>((size_t)nS[t] * sk[t].s * xs);
   }
   for (int t = 1; t < nn; ++t)
-    plan_unit(w, sb.u[t - 1], X->data, A[t], nS[t], Bv[t], sk[t], Z[t], Y[t], sb.total_blocks,
-              sb.total_out);
+    if (!dense[t])
+      plan_unit(w, sb.u[sb.count++], X->data, A[t], nS[t], Bv[t], sk[t], Z[t], Y[t], sb.total_blocks,
+                sb.total_out);
   std::vector<QRMat> mats(nn - 1);
   for (int t = 1; t < nn; ++t)
-    plan_qr(w, mats[t - 1], Z[t], nS[t], sk[t].ell, true, Y[t], sk[t].s, rank[t], U[t],
-            info ? info + t : nullptr);
+    plan_qr(w, mats[t - 1], Z[t], nS[t], sk[t].ell, true, Y[t], dense[t] ? kQRColChunk : sk[t].s, rank[t],
+            U[t], info ? info + t : nullptr);
+  // dense nodes: M (n_notS x ell values), a transposed copy, the unfolded
+  // product's partials and the mode products' factor table
+  std::vector<double*> Md(nn, nullptr), Mt(nn, nullptr);
+  int64_t dmt = 1, dup = 1;
+  for (int t = 1; t < nn; ++t) {
+    if (!dense[t]) continue;
+    const int ell = sk[t].ell;
+    Md[t] = w.take<double>((size_t)nc[t] * ell);
+    Mt[t] = w.take<double>((size_t)std::max<int64_t>(nc[t], nS[t]) * ell);
+    dmt = std::max(dmt, mode_product_scratch(ell, nc[t]));
+    dmt = std::max(dmt, mode_product_scratch(ell, nS[t]));
+    dup = std::max<int64_t>(dup, (int64_t)unfold_gemm_splits(ell, nc[t]) * ell * ell);
+  }
+  double* dense_mt = w.take<double>((size_t)dmt);
+  double* dense_up = w.take<double>((size_t)dup);
   // transfers of internal non-root nodes
   std::vector<Transfer> tr;
   for (int t = 1; t < nn; ++t) {
@@ -1261,8 +1306,63 @@ tk_status htucker_decompose(const tk_tensor* X, const tk_tree* tree, const int32
     return set_error(TK_EWORKSPACE, "htucker_decompose: workspace %zu < required %zu", *ws_bytes, w.off);
   hipStream_t st = as_stream(stream);
   // an order <= 16 tree has at most 30 non-root nodes: a single sketch launch
-  TK_HIP(launch_sketch(X->dtype, sb, st));
-  if (tk_status s = run_qr(mats, X->dtype, fdt, true, st)) return s;
+  if (sb.count > 0) TK_HIP(launch_sketch(X->dtype, sb, st));
+  auto mode_x = [&](int64_t Aa, int64_t Qq, int64_t Bb, int P, const void* Mm, int m_dt, double* out,
+                    const void* in, int in_dt) -> hipError_t {
+    ModeProduct mp{};
+    mp.in = in;
+    mp.A = Aa;
+    mp.Q = Qq;
+    mp.B = Bb;
+    mp.P = P;
+    mp.M = Mm;
+    mp.Mt = dense_mt;
+    mp.rs = 1;
+    mp.cs = P;           // M[p][q] = Mm[q * P + p]: an (Qq x P) row-major matrix used transposed
+    mp.out = out;
+    return launch_mode_product(mp, in_dt, TK_F64, m_dt, st);
+  };
+  for (int t = 1; t < nn; ++t) {
+    if (!dense[t]) continue;
+    const int ell = sk[t].ell;
+    if (A[t] == 1) {     // prefix: X^(S) is X viewed n_S x n_notS, Z = X Omega
+      TK_HIP(mode_x(nS[t], nc[t], 1, ell, sk[t].omega, odt, Z[t], X->data, X->dtype));
+    } else {             // suffix: X^(S) = (X viewed n_notS x n_S)^T, Z^T = Omega^T X
+      TK_HIP(mode_x(1, nc[t], nS[t], ell, sk[t].omega, odt, Mt[t], X->data, X->dtype));
+      TK_HIP(launch_transpose_f64(Mt[t], Z[t], ell, nS[t], st));
+    }
+  }
+  // CholeskyQR of every node; then the W step of the sampled nodes from their
+  // gathered columns and of the dense ones from the Gram of Q^T X^(S)
+  if (tk_status s = run_qr(mats, X->dtype, fdt, false, st)) return s;
+  std::vector<QRMat> sparse_m, dense_m;
+  for (int t = 1; t < nn; ++t) (dense[t] ? dense_m : sparse_m).push_back(mats[t - 1]);
+  if (tk_status s = run_wstep(sparse_m, X->dtype, fdt, false, st)) return s;
+  for (int t = 1; t < nn; ++t) {
+    if (!dense[t]) continue;
+    const int ell = sk[t].ell;
+    const QRMat& q = mats[t - 1];
+    UnfoldGemm g{};
+    if (A[t] == 1) {     // M = Q^T X^(S): ell x n_notS
+      TK_HIP(mode_x(1, nS[t], nc[t], ell, q.Z, TK_F64, Md[t], X->data, X->dtype));
+      g.pre = 1;
+      g.post = nc[t];
+    } else {             // M^T = X_(n_notS x n_S) Q: n_notS x ell
+      TK_HIP(mode_x(nc[t], nS[t], 1, ell, q.Z, TK_F64, Md[t], X->data, X->dtype));
+      g.pre = nc[t];
+      g.post = 1;
+    }
+    g.A = Md[t];
+    g.B = Md[t];
+    g.out = q.cpart;
+    g.partials = dense_up;
+    g.n = ell;
+    g.c = ell;
+    g.splits = unfold_gemm_splits(ell, nc[t]);
+    g.accumulate = 0;
+    TK_HIP(launch_unfold_gemm(g, TK_F64, TK_F64, TK_F64, st));
+  }
+  if (tk_status s = run_wstep(dense_m, X->dtype, fdt, true, st)) return s;
   for (const Transfer& x : tr) TK_HIP(launch_transfer(x, fdt, st));
   if (root_fused) {
     RootPass rp{};

@@ -111,6 +111,8 @@ struct QRList {
 };
 hipError_t launch_cholqr(const QRBatch& b, hipStream_t st);
 hipError_t launch_wstep(const QRBatch& b, int ydtype, int udtype, hipStream_t st);
+// the W step from a given Gram of Q^T Y (cpart, ncc = 1): eigenvectors and U only
+hipError_t launch_wstep_gram(const QRBatch& b, int udtype, hipStream_t st);
 // host: the table `dev.m` points to, as a host copy (grid sizes, path choice)
 hipError_t launch_cholqr_list(const QRList& dev, const QRMat* host, hipStream_t st);
 hipError_t launch_wstep_list(const QRList& dev, const QRMat* host, int ydtype, int udtype, hipStream_t st);
@@ -320,6 +322,11 @@ void ht_expand_grid(HTExpand& p);     // fills ntile, groups, rows_per_group
 hipError_t launch_ht_expand(const HTExpand& p, int x_dt, int out_dt, hipStream_t st);   // dt -1 = absent
 hipError_t launch_ht_rowmat(const double* UL, const double* BR, double* T, int64_t nL, int rl, int rr,
                             int rpad, hipStream_t st);
+// out[c][r] = in[r][c] (rows x cols, FP64)
+hipError_t launch_transpose_f64(const double* in, double* out, int64_t rows, int64_t cols, hipStream_t st);
+// Omega of a dense node sketch, [(a B + b)][e] -> [a][e][b] (dtype TK_F32 or TK_F64)
+hipError_t launch_omega_to_unfolded(const void* om, void* out, int dt, int64_t A, int64_t B, int ell,
+                                    hipStream_t st);
 // C[j][k][i] = B[i][j][k] (to_core) or the inverse permutation
 hipError_t launch_permute_transfer(const double* in, double* out, int rS, int rl, int rr, bool to_core,
                                    hipStream_t st);

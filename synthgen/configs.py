@@ -45,6 +45,9 @@ class HTConfig:
     p: int
     w_alpha: int        # w_S = min(w_alpha * n, n_{not in S})
     dtype: str
+    # "n": the rule above (parallel tests, Section 4.2.2); "nS": w_S =
+    # min(w_alpha^(d-2) n_S, n_{not in S}) (serial tests, Section 4.2.1)
+    sample_rule: str = "n"
 
 
 C5 = HTConfig("c5_ht_fp32_18^8", 5, 18, 8, 12, 1e-5, 4, 20, "f32")
@@ -52,6 +55,9 @@ C5_SMALL = HTConfig("c5_ht_fp32_6^8", 5, 6, 8, 4, 1e-5, 4, 20, "f32")
 # closed-form 1/||x|| on [1, 15]^8 (H-Tucker serial tests, Section 4.2.1): rank 7,
 # w_S = min(20 n, n_notS) fibers per node as in the parallel tests (Section 4.2.2)
 C6 = HTConfig("c6_inverse_norm_fp32_15^8", 6, 15, 8, 7, 0.0, 4, 20, "f32")
+# the same tensor with the serial tests' rule at alpha = 2: the root's two
+# children (n_S = 15^4 = n_notS) are sampled densely
+C7 = HTConfig("c7_inverse_norm_fp32_15^8_serial_rule", 7, 15, 8, 7, 0.0, 4, 2, "f32", "nS")
 
 C4_COUNT = 512
 C4_CFG_ID = 4

@@ -1,0 +1,70 @@
+"""GPU parity of Sub-R-RtL-HT when the sampling rule of the serial H-Tucker
+tests, w_S = min(alpha^(d-2) n_S, n_notS) fibers per node (Section 4.2.1),
+makes the root's children dense (every column sampled).  The library then
+sketches those nodes and runs their W step by products with X itself (no
+copy of the unfolding); the oracle samples every column explicitly.  Orders 4
+(two dense 2-mode children), 5 (a dense prefix, a sampled suffix) and 6 (a
+dense prefix and a dense suffix), on the closed-form 1/||x|| tensor."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synthgen
+
+pytestmark = pytest.mark.gpu
+
+
+def _run(order, dtype, n=10, rank=5, p=3, alpha=2):
+    from paper_2603_21379_amd import tucker as T
+    X = synthgen.inverse_norm_tensor(n, order, dtype)
+    dims = X.shape
+    tr = synthgen.balanced_tree(order)
+    N = math.prod(dims)
+    ranks, ells, ws, dense = {}, {}, {}, []
+    for t in range(1, tr.num_nodes):
+        nS = math.prod(dims[k] for k in tr.modes(t))
+        ells[t] = min(rank + p, nS, N // nS)
+        ranks[t] = min(rank, ells[t])
+        ws[t] = min(alpha ** (order - 2) * nS, N // nS)
+        if ws[t] == N // nS:
+            dense.append(t)
+    fdt = synthgen.factor_dtype(dtype)
+    sk = synthgen.node_sketches(dims, tr, ells, ws, cfg=70 + order, omega_dtype=fdt)
+    tdt = torch.float64 if dtype == "f64" else torch.float32
+    up = T.upload_sketches([(sk[t], N // math.prod(dims[k] for k in tr.modes(t)))
+                            for t in range(1, tr.num_nodes)], "cuda", tdt)
+    skd = {t: up[t - 1] for t in range(1, tr.num_nodes)}
+    assert all(skd[t][0] is None for t in dense)
+    res = T.sub_r_rtl_ht(torch.from_numpy(X).cuda(), tr, ranks, skd)
+    torch.cuda.synchronize()
+    X64 = synthgen.to_f64(X, dtype)
+    U_or, B_or, _ = oracle.sub_r_rtl_ht(X64, tr, ranks, sk)
+    U = {t: u.cpu().numpy() for t, u in res.U.items()}
+    Bg = {t: b.cpu().numpy() for t, b in res.B.items()}
+    return tr, dense, U, Bg, U_or, B_or, X64, res.info.cpu().numpy()
+
+
+@pytest.mark.parametrize("order,expect", [(4, [1, 2]), (5, [1]), (6, [1, 2])])
+def test_dense_root_children_f64(order, expect):
+    tr, dense, U, Bg, U_or, B_or, X64, info = _run(order, "f64")
+    assert dense == expect
+    for t in U_or:
+        assert oracle.projector_distance(U[t], U_or[t]) < 1e-9, t
+    for t in B_or:
+        np.testing.assert_allclose(Bg[t], B_or[t], atol=1e-9 * max(1.0, np.abs(B_or[t]).max()))
+    eps_or = oracle.ht_rel_error(X64, tr, U_or, B_or)
+    eps = oracle.ht_rel_error(X64, tr, U, Bg)
+    assert abs(eps - eps_or) <= 1e-8 * eps_or
+
+
+def test_dense_root_children_f32():
+    tr, dense, U, Bg, U_or, B_or, X64, info = _run(6, "f32")
+    assert dense == [1, 2]
+    eps_or = oracle.ht_rel_error(X64, tr, U_or, B_or)
+    eps = oracle.ht_rel_error(X64, tr, U, Bg)
+    assert abs(eps - eps_or) <= 1e-4 * eps_or
+    for t in U_or:
+        assert oracle.projector_distance(U[t], U_or[t]) < 1e-5, t
