@@ -14,6 +14,8 @@
 // is coalesced.  The last expansion of a reconstruction is fused with the
 // squared residual against the reference tensor (FP64 partial sums per
 // block, then a fixed-order final sum).
+#include <algorithm>
+
 #include "tk_kernels.hpp"
 
 namespace tk {
@@ -43,28 +45,45 @@ __global__ void stage_factor_kernel(const void* M, int m_dt, int64_t rs, int64_t
 template <typename TIn, typename TOut, int PMAX>
 __global__ __launch_bounds__(256) void mode_rows_kernel(const ModeProduct mp, int ld) {
   // B == 1: out[a][p] = sum_q in[a][q] M[p][q]; 64 rows per block, a
-  // 64 x 64 tile of `in` staged through LDS (coalesced), 4 p-groups
+  // 64 x 64 tile of `in` staged through LDS (coalesced), the next tile's
+  // loads in flight while this one is multiplied; 4 p-groups, one per wave,
+  // each reading the staged factor table with wave-uniform (scalar) loads
   __shared__ double sX[64][65];
   const int tid = threadIdx.x;
   const int row = tid & 63;
   const int pg = __builtin_amdgcn_readfirstlane(tid >> 6);  // one p-group per wave
   constexpr int PK = PMAX / 4;
+  constexpr int kXE = 64 * 64 / 256;
   const int64_t a0 = (int64_t)blockIdx.x * 64;
   const int p0 = blockIdx.y * PMAX;
   const int rows = (int)min<int64_t>(64, mp.A - a0);
   const TIn* in = static_cast<const TIn*>(mp.in);
   const double* __restrict__ Mt = mp.Mt;
+  double xr[kXE];
+  // the tile at q0 (rows past the matrix and q past Q read as zero; a q0
+  // past Q loads nothing that is used)
+  auto load = [&](int64_t q0) {
+    const int64_t qn = min<int64_t>(64, mp.Q - q0);
+#pragma unroll
+    for (int u = 0; u < kXE; ++u) {
+      const int e = tid + 256 * u, rr = e >> 6, qq = e & 63;
+      xr[u] = (rr < rows && qq < qn) ? to_double(in[(a0 + rr) * mp.Q + q0 + qq]) : 0.0;
+    }
+  };
   double acc[PK];
 #pragma unroll
   for (int k = 0; k < PK; ++k) acc[k] = 0.0;
+  load(0);
   for (int64_t q0 = 0; q0 < mp.Q; q0 += 64) {
-    const int qn = (int)min<int64_t>(64, mp.Q - q0);
-    __syncthreads();
-    for (int e = tid; e < 64 * 64; e += 256) {
-      const int rr = e >> 6, qq = e & 63;
-      sX[rr][qq] = (rr < rows && qq < qn) ? to_double(in[(a0 + rr) * mp.Q + q0 + qq]) : 0.0;
+    __syncthreads();   // the previous tile's products are done
+#pragma unroll
+    for (int u = 0; u < kXE; ++u) {
+      const int e = tid + 256 * u;
+      sX[e >> 6][e & 63] = xr[u];
     }
     __syncthreads();
+    load(q0 + 64);
+    const int qn = (int)min<int64_t>(64, mp.Q - q0);
     for (int qq = 0; qq < qn; ++qq) {
       const double x = sX[row][qq];
       const double* mq = Mt + (q0 + qq) * ld + p0;
@@ -91,7 +110,8 @@ template <typename TIn, typename TOut, int PMAX, int NB>
 __global__ __launch_bounds__(256) void mode_strided_kernel(const ModeProduct mp, int ld) {
   // out[a][p][b] = sum_q in[a][q][b] M[p][q]; NB (a, b) points per thread,
   // 256 apart, so each load instruction stays coalesced; M comes from the
-  // staged table with scalar loads.
+  // staged table with scalar loads.  With gridDim.z > 1, block z sums the
+  // z-th range of q into its own partial output.
   const int tid = threadIdx.x;
   const int64_t AB = mp.A * mp.B;
   const int p0 = blockIdx.y * PMAX;
@@ -112,8 +132,10 @@ __global__ __launch_bounds__(256) void mode_strided_kernel(const ModeProduct mp,
   for (int u = 0; u < NB; ++u)
 #pragma unroll
     for (int k = 0; k < PMAX; ++k) acc[u][k] = 0.0;
-  int64_t q = 0;
-  for (; q + 4 <= mp.Q; q += 4) {
+  const int64_t qper = (mp.Q + gridDim.z - 1) / gridDim.z;
+  const int64_t qb = (int64_t)blockIdx.z * qper, qe = min(mp.Q, qb + qper);
+  int64_t q = qb;
+  for (; q + 4 <= qe; q += 4) {
     double x[4][NB];
 #pragma unroll
     for (int w = 0; w < 4; ++w)
@@ -131,7 +153,7 @@ __global__ __launch_bounds__(256) void mode_strided_kernel(const ModeProduct mp,
       }
     }
   }
-  for (; q < mp.Q; ++q) {
+  for (; q < qe; ++q) {
     double x[NB];
 #pragma unroll
     for (int u = 0; u < NB; ++u) x[u] = live[u] ? to_double(in[base[u] + q * mp.B]) : 0.0;
@@ -145,6 +167,8 @@ __global__ __launch_bounds__(256) void mode_strided_kernel(const ModeProduct mp,
   }
   TOut* out = static_cast<TOut*>(mp.out);
   const int pn = min(PMAX, mp.P - p0);
+  const bool split = gridDim.z > 1;
+  double* part = split ? mp.part + (int64_t)blockIdx.z * mp.A * mp.P * mp.B : nullptr;
 #pragma unroll
   for (int u = 0; u < NB; ++u) {
     if (!live[u]) continue;
@@ -154,12 +178,29 @@ __global__ __launch_bounds__(256) void mode_strided_kernel(const ModeProduct mp,
     for (int k = 0; k < PMAX; ++k) {
       if (k < pn) {
         const int64_t o = (a * mp.P + p0 + k) * mp.B + bb;
-        double v = acc[u][k];
-        if (mp.accumulate) v += to_double(out[o]);
-        out[o] = from_double<TOut>(v);
+        if (split) {
+          part[o] = acc[u][k];
+        } else {
+          double v = acc[u][k];
+          if (mp.accumulate) v += to_double(out[o]);
+          out[o] = from_double<TOut>(v);
+        }
       }
     }
   }
+}
+
+// out (+)= the sum of the q-range partials, in split order
+template <typename TOut>
+__global__ __launch_bounds__(256) void mode_split_sum_kernel(const ModeProduct mp, int splits) {
+  const int64_t o = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t n = mp.A * mp.P * mp.B;
+  if (o >= n) return;
+  double v = 0.0;
+  for (int z = 0; z < splits; ++z) v += mp.part[(int64_t)z * n + o];
+  TOut* out = static_cast<TOut*>(mp.out);
+  if (mp.accumulate) v += to_double(out[o]);
+  out[o] = from_double<TOut>(v);
 }
 
 int width_of(int P) { return P <= 16 ? 16 : P <= 32 ? 32 : 64; }
@@ -185,7 +226,14 @@ hipError_t mode_product(const ModeProduct& mp, int m_dt, hipStream_t st) {
     // CU busy (64 accumulators per thread at most)
     const bool wide = mp.A * mp.B >= (int64_t)256 * 4 * 1024;
     const int nb = !wide ? 1 : width == 16 ? 4 : width == 32 ? 2 : 1;
-    const dim3 grid((unsigned)ceil_div(mp.A * mp.B, 256 * nb), pchunks);
+    // few output points and a long contraction: split q so that about 2048
+    // blocks run (when the caller gave room for the partials)
+    const int64_t pts_blocks = ceil_div(mp.A * mp.B, 256 * nb) * pchunks;
+    int splits = 1;
+    if (mp.part && mp.qsplit_max > 1 && pts_blocks < 1024)
+      splits = (int)std::max<int64_t>(1, std::min<int64_t>({(int64_t)mp.qsplit_max, ceil_div(2048, pts_blocks),
+                                                            mp.Q / 256}));
+    const dim3 grid((unsigned)ceil_div(mp.A * mp.B, 256 * nb), pchunks, (unsigned)splits);
     if (width == 16) {
       if (wide) hipLaunchKernelGGL((mode_strided_kernel<TIn, TOut, 16, 4>), grid, dim3(256), 0, st, mp, ld);
       else hipLaunchKernelGGL((mode_strided_kernel<TIn, TOut, 16, 1>), grid, dim3(256), 0, st, mp, ld);
@@ -195,6 +243,9 @@ hipError_t mode_product(const ModeProduct& mp, int m_dt, hipStream_t st) {
     } else {
       hipLaunchKernelGGL((mode_strided_kernel<TIn, TOut, 64, 1>), grid, dim3(256), 0, st, mp, ld);
     }
+    if (splits > 1)
+      hipLaunchKernelGGL((mode_split_sum_kernel<TOut>), dim3((unsigned)ceil_div(mp.A * mp.P * mp.B, 256)),
+                         dim3(256), 0, st, mp, splits);
   }
   return hipGetLastError();
 }

@@ -1271,6 +1271,12 @@ tk_status htucker_decompose(const tk_tensor* X, const tk_tree* tree, const int32
   }
   double* dense_mt = w.take<double>((size_t)dmt);
   double* dense_up = w.take<double>((size_t)dup);
+  // partials of the first-dimension mode products (q split over up to 16 blocks)
+  constexpr int kDenseSplit = 16;
+  int64_t dpart = 1;
+  for (int t = 1; t < nn; ++t)
+    if (dense[t]) dpart = std::max<int64_t>(dpart, (int64_t)kDenseSplit * sk[t].ell * std::max(nc[t], nS[t]));
+  double* dense_part = dpart > 1 ? w.take<double>((size_t)dpart) : nullptr;
   // transfers of internal non-root nodes
   std::vector<Transfer> tr;
   for (int t = 1; t < nn; ++t) {
@@ -1320,6 +1326,8 @@ tk_status htucker_decompose(const tk_tensor* X, const tk_tree* tree, const int32
     mp.rs = 1;
     mp.cs = P;           // M[p][q] = Mm[q * P + p]: an (Qq x P) row-major matrix used transposed
     mp.out = out;
+    mp.part = dense_part;
+    mp.qsplit_max = kDenseSplit;
     return launch_mode_product(mp, in_dt, TK_F64, m_dt, st);
   };
   for (int t = 1; t < nn; ++t) {

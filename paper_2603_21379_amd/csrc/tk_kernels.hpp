@@ -128,6 +128,11 @@ struct ModeProduct {
   int32_t P;
   int32_t rs, cs;
   int32_t accumulate;   // out += instead of out =
+  // optional: when B > 1 and there are few output points, the contraction
+  // range may be split over up to qsplit_max blocks whose partial sums go to
+  // `part` (qsplit_max * A * P * B doubles) and are summed in split order
+  int32_t qsplit_max;
+  double* part;
 };
 // doubles of scratch a mode product needs (M as a padded FP64 [Q][P'] table)
 int64_t mode_product_scratch(int64_t P, int64_t Q);
