@@ -46,8 +46,9 @@ template <typename TIn, typename TOut, int PMAX>
 __global__ __launch_bounds__(256) void mode_rows_kernel(const ModeProduct mp, int ld) {
   // B == 1: out[a][p] = sum_q in[a][q] M[p][q]; 64 rows per block, a
   // 64 x 64 tile of `in` staged through LDS (coalesced), the next tile's
-  // loads in flight while this one is multiplied; 4 p-groups, one per wave,
-  // each reading the staged factor table with wave-uniform (scalar) loads
+  // loads in flight while this one is multiplied; 4 p-groups of PMAX / 4
+  // consecutive p, one per wave, each reading its entries of the staged
+  // factor table with wave-uniform (scalar) loads
   __shared__ double sX[64][65];
   const int tid = threadIdx.x;
   const int row = tid & 63;
@@ -84,18 +85,19 @@ __global__ __launch_bounds__(256) void mode_rows_kernel(const ModeProduct mp, in
     __syncthreads();
     load(q0 + 64);
     const int qn = (int)min<int64_t>(64, mp.Q - q0);
+#pragma unroll 4
     for (int qq = 0; qq < qn; ++qq) {
       const double x = sX[row][qq];
-      const double* mq = Mt + (q0 + qq) * ld + p0;
+      const double* mq = Mt + (q0 + qq) * ld + p0 + pg * PK;   // this wave's PK contiguous entries
 #pragma unroll
-      for (int k = 0; k < PK; ++k) acc[k] = fma(x, mq[pg + 4 * k], acc[k]);
+      for (int k = 0; k < PK; ++k) acc[k] = fma(x, mq[k], acc[k]);
     }
   }
   if (row < rows) {
     TOut* out = static_cast<TOut*>(mp.out);
 #pragma unroll
     for (int k = 0; k < PK; ++k) {
-      const int p = p0 + pg + 4 * k;
+      const int p = p0 + pg * PK + k;
       if (p < mp.P) {
         const int64_t o = (a0 + row) * mp.P + p;
         double v = acc[k];
