@@ -133,6 +133,32 @@ def device_draw_ms(ncols, ss, ells, fdt, reps=5):
     return e0.elapsed_time(e1) / reps
 
 
+def backward_ms(X, F, G):
+    """A7 on the resident tensor: the core VJP (factor gradients for a given
+    core adjoint, X recontracted) and the reconstruction VJP (X standing in
+    for the adjoint of Xhat), each timed with events after a sizing call.
+    FP32/FP64 tensors only (the backward entry points' dtypes)."""
+    import torch
+    from paper_2603_21379_amd import binding as B
+    if X.dtype not in (torch.float32, torch.float64):
+        return None
+    Fb = [torch.empty_like(f) for f in F]
+    Gb = torch.empty_like(G)
+    dims = list(X.shape)
+    out = {}
+    for name, fn in (("ms_core_vjp", lambda: B.tucker_core_vjp(X, F, G, Fbar=Fb)),
+                     ("ms_reconstruct_vjp", lambda: B.tucker_reconstruct_vjp(dims, G, F, X, Gbar=Gb, Fbar=Fb))):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        fn()
+        e1.record()
+        torch.cuda.synchronize()
+        out[name] = round(e0.elapsed_time(e1), 3)
+    return out
+
+
 def copy_calibration():
     import torch
     nbytes = 4 << 30
@@ -294,6 +320,10 @@ def main():
     ceiling = streaming_ceiling(X)
     log(f"read-only streaming reference over X: {ceiling:.1f} GB/s")
     ms_device_draw = device_draw_ms([N // n for n in dims], ss, ells, fdt)
+    back = backward_ms(X, F, G)
+    if back:
+        log(f"backward (A7): core VJP {back['ms_core_vjp']:.2f} ms, reconstruction VJP "
+            f"{back['ms_reconstruct_vjp']:.2f} ms")
     log(f"sketch operands: device draw {ms_device_draw:.3f} ms; host generation "
         f"{ms_host_sketch:.1f} ms + upload {ms_upload_sketch:.2f} ms")
 
@@ -329,6 +359,7 @@ def main():
                      "frac_of_ceiling": round(achieved / ceiling, 4)},
         "sketch_core_frac_of_ceiling": round(sketch_core_gbs / ceiling, 4),
         "ms_resid": round(ms_resid, 4),
+        "backward": back,
         "sketch_draw": {"ms_device": round(ms_device_draw, 4),
                         "ms_host_generate": round(ms_host_sketch, 2),
                         "ms_upload": round(ms_upload_sketch, 3)},

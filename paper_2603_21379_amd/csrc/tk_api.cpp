@@ -1756,14 +1756,17 @@ tk_status tucker_reconstruct_vjp(int32_t order, const int64_t* dims, int32_t fdt
   // Gbar = H x_1 F_1^T .. x_d F_d^T (the core projection of H)
   if (Gbar)
     if (tk_status s = run_core(H, fdtype, order, dims, F, cols, Gbar, fdtype, cp, st)) return s;
-  // Fbar_k = H^(k) ((G x_{j!=k} F_j)^(k))^T
+  // Fbar_k = H^(k) ((G x_{j!=k} F_j)^(k))^T = (H x_{j!=k} F_j^T)^(k) (G^(k))^T:
+  // contracting H first reads it once per mode through core-sized
+  // intermediates (expanding G first would form an H-sized one per mode and
+  // reread it for every row of Fbar_k)
   if (Fbar)
     for (int k = 0; k < order; ++k) {
       if (!Fbar[k]) continue;
-      const void* E = nullptr;
-      int edt = 0;
-      if (tk_status s = expand_all_but(G, fdtype, order, dims, F, cols, k, vp, st, &E, &edt)) return s;
-      if (tk_status s = unfold_product(H, fdtype, E, edt, order, dims, cols, k, false, Fbar[k], fdtype,
+      const void* P = nullptr;
+      int pdt = 0;
+      if (tk_status s = contract_all_but(H, fdtype, order, dims, F, cols, k, vp, st, &P, &pdt)) return s;
+      if (tk_status s = unfold_product(P, pdt, G, fdtype, order, dims, cols, k, true, Fbar[k], fdtype,
                                        false, vp, st)) return s;
     }
   return TK_OK;
