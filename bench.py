@@ -545,6 +545,16 @@ def bench_ht(args):
     r2 = r2.cpu().tolist()
     eps = math.sqrt(r2[0] / r2[1])
     log(f"residual pass {ms_resid:.3f} ms ({N * 4 / ms_resid / 1e6:.1f} GB/s); rel err {eps:.4e}")
+    # the format's VJP (gradients of the leaf bases and transfer tensors), X
+    # standing in for the adjoint of the full tensor
+    T.ht_reconstruct_vjp(dims, tr, ranks, leaves, res.B, X)
+    torch.cuda.synchronize()
+    e0.record()
+    T.ht_reconstruct_vjp(dims, tr, ranks, leaves, res.B, X)
+    e1.record()
+    torch.cuda.synchronize()
+    ms_vjp = e0.elapsed_time(e1)
+    log(f"format VJP {ms_vjp:.3f} ms")
     result = {
         "metric": "tensor GB/s streamed (sketch+core), frac of HBM roofline; rel err vs FP64 oracle",
         "value": round(value, 2), "unit": "GB/s", "n_gpus": 1, "steps": args.steps,
@@ -554,7 +564,7 @@ def bench_ht(args):
                    "node_rank": c.rank, "p": c.p, "w_alpha": c.w_alpha, "noise_rel": c.noise,
                    "sample_rule": c.sample_rule, "dense_nodes": dense},
         "frac_hbm_step": round(value / HBM_PEAK_GBS, 4),
-        "rel_error": eps, "ms_resid": round(ms_resid, 4),
+        "rel_error": eps, "ms_resid": round(ms_resid, 4), "ms_format_vjp": round(ms_vjp, 3),
         "resid_gbs": round(N * 4 / ms_resid / 1e6, 1),
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,

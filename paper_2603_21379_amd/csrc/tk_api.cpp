@@ -1601,7 +1601,6 @@ tk_status htucker_reconstruct_vjp(int32_t order, const int64_t* dims, const tk_t
     mt = std::max(mt, mode_product_scratch(rank[r], nr));
     mt = std::max(mt, mode_product_scratch(rank[l], nl));
   }
-  up = std::max<int64_t>(up, (int64_t)unfold_gemm_splits(nR, nL) * nR * rr0);
   mt = std::max(mt, mode_product_scratch(rr0, nR));
   mt = std::max(mt, mode_product_scratch(rl0, nL));
   mt = std::max(mt, mode_product_scratch(rl0, rr0));
@@ -1612,7 +1611,11 @@ tk_status htucker_reconstruct_vjp(int32_t order, const int64_t* dims, const tk_t
     if (tree->left[t] >= 0) cb = std::max<int64_t>(cb, (int64_t)rank[t] * rank[tree->left[t]] * rank[tree->right[t]]);
   double* Cbar2 = w.take<double>((size_t)cb);
   double* P1 = w.take<double>((size_t)nL * rr0);
-  double* W = w.take<double>((size_t)nL * rr0);
+  double* Qp = w.take<double>((size_t)rl0 * nR);
+  double* W2 = w.take<double>((size_t)rr0 * nR);
+  constexpr int kRootSplit = 16;
+  double* rpart = w.take<double>((size_t)kRootSplit * rl0 * nR);
+  mt = std::max(mt, mode_product_scratch(rr0, rl0));
   double* upart = w.take<double>((size_t)up);
   f.Mt = w.take<double>((size_t)std::max<int64_t>(1, mt));
   if (!ws) {
@@ -1624,8 +1627,10 @@ tk_status htucker_reconstruct_vjp(int32_t order, const int64_t* dims, const tk_t
   if (tk_status s = run_ht_bases(tree, rank, U, B, f, st)) return s;
   auto adj = [&](int t) -> double* { return tree->left[t] < 0 ? static_cast<double*>(Ubar[t]) : UB[t]; };
   auto mode = [&](const void* in, int in_dt, int64_t A, int64_t Q, int64_t Bn, int64_t P, const void* M,
-                  int rs, int cs, void* out) -> hipError_t {
+                  int rs, int cs, void* out, double* part = nullptr) -> hipError_t {
     ModeProduct m{};
+    m.part = part;
+    m.qsplit_max = part ? kRootSplit : 0;
     m.in = in;
     m.A = A;
     m.Q = Q;
@@ -1656,12 +1661,15 @@ tk_status htucker_reconstruct_vjp(int32_t order, const int64_t* dims, const tk_t
   const double* UL = ht_basis(tree, U, f, L);
   const double* UR = ht_basis(tree, U, f, R);
   // root, H viewed as n_l x n_r: P1 = H U_Rr; B_R_bar = U_Rl^T P1; U_Rl_bar = P1 B_R^T;
-  // U_Rr_bar = H^T (U_Rl B_R)
+  // U_Rr_bar = H^T U_Rl B_R, contracting H first: Q' = U_Rl^T H (a
+  // first-dimension product, its contraction split over blocks), then
+  // (B_R^T Q')^T; each reads H once
   TK_HIP(mode(H, h_dtype, nL, nR, 1, rr0, UR, 1, rr0, P1));
   TK_HIP(mode(P1, TK_F64, 1, nL, rr0, rl0, UL, 1, rl0, Bbar[0]));
   TK_HIP(mode(P1, TK_F64, nL, rr0, 1, rl0, B[0], rr0, 1, adj(L)));
-  TK_HIP(mode(B[0], TK_F64, 1, rl0, rr0, nL, UL, rl0, 1, W));
-  TK_HIP(ugemm(H, h_dtype, W, nL, nR, rr0, 1, adj(R)));
+  TK_HIP(mode(H, h_dtype, 1, nL, nR, rl0, UL, 1, rl0, Qp, rpart));       // r_l x n_r
+  TK_HIP(mode(Qp, TK_F64, 1, rl0, nR, rr0, B[0], 1, rr0, W2));           // r_r x n_r
+  TK_HIP(launch_transpose_f64(W2, static_cast<double*>(adj(R)), rr0, nR, st));
   // internal nodes, parents before children: with H' = U_S_bar as (n_l, n_r, r_S)
   // and C = B_S permuted to (r_l, r_r, r_S):
   //   C_bar = H' x_0 U_l^T x_1 U_r^T,  U_l_bar = H'^(0) (C x_1 U_r)^(0)T,
