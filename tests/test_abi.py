@@ -206,3 +206,113 @@ def test_batch_plan_validation_and_query():
     G[0] = None
     assert f(1, X, ranks, sk, U, G, None, None, C.byref(n), None, None) == 1
     assert f(0, X, ranks, sk, U, G, None, None, C.byref(n), None, None) == 1
+
+
+def _ht_args(dims, rank_of):
+    import synthgen
+    tr = synthgen.balanced_tree(len(dims))
+    nn = tr.num_nodes
+    td = B.tree_desc(tr)
+    rk = (C.c_int32 * nn)(*([0] + [rank_of(t) for t in range(1, nn)]))
+    dd = (C.c_int64 * len(dims))(*dims)
+    return tr, td, rk, dd, nn
+
+
+def test_htucker_reconstruct_validation_and_query():
+    dims = (5, 6, 4, 7)
+    tr, td, rk, dd, nn = _ht_args(dims, lambda t: 2)
+    X = _tensor(dims)
+    ok = _query("htucker_reconstruct", 4, dd, C.byref(td), rk, _ptrs(nn), _ptrs(nn), C.byref(X),
+                C.c_void_p(FAKE), B.TK_F32, C.c_void_p(FAKE))
+    assert ok[0] == 0 and ok[1] > 0, ok[2]
+    # neither output; a residual without a reference; an output dtype other than F32/F64
+    assert _query("htucker_reconstruct", 4, dd, C.byref(td), rk, _ptrs(nn), _ptrs(nn), C.byref(X),
+                  None, 0, None)[0] == 1
+    assert _query("htucker_reconstruct", 4, dd, C.byref(td), rk, _ptrs(nn), _ptrs(nn), None,
+                  None, 0, C.c_void_p(FAKE))[0] == 1
+    assert _query("htucker_reconstruct", 4, dd, C.byref(td), rk, _ptrs(nn), _ptrs(nn), None,
+                  C.c_void_p(FAKE), B.TK_BF16, None)[0] == 1
+    # a reference of other dims
+    X2 = _tensor((5, 6, 4, 8))
+    assert _query("htucker_reconstruct", 4, dd, C.byref(td), rk, _ptrs(nn), _ptrs(nn), C.byref(X2),
+                  None, 0, C.c_void_p(FAKE))[0] == 1
+    # a missing leaf basis
+    U = _ptrs(nn)
+    U[nn - 1] = None
+    st, _, msg = _query("htucker_reconstruct", 4, dd, C.byref(td), rk, U, _ptrs(nn), None,
+                        C.c_void_p(FAKE), B.TK_F64, None)
+    assert st == 1 and "leaf" in msg
+    # the rank of the root's right child above 64
+    rk2 = (C.c_int32 * nn)(*rk)
+    rk2[tr.right[0]] = 65
+    assert _query("htucker_reconstruct", 4, dd, C.byref(td), rk2, _ptrs(nn), _ptrs(nn), None,
+                  C.c_void_p(FAKE), B.TK_F64, None)[0] == 5
+    # a tree that is not the balanced heap tree
+    tr.left[0], tr.right[0] = tr.right[0], tr.left[0]
+    td2 = B.tree_desc(tr)
+    st, _, msg = _query("htucker_reconstruct", 4, dd, C.byref(td2), rk, _ptrs(nn), _ptrs(nn), None,
+                        C.c_void_p(FAKE), B.TK_F64, None)
+    assert st == 1 and "balanced" in msg
+
+
+def test_htucker_reconstruct_vjp_validation_and_query():
+    dims = (5, 6, 4, 7, 3)
+    tr, td, rk, dd, nn = _ht_args(dims, lambda t: 3)
+    ok = _query("htucker_reconstruct_vjp", 5, dd, C.byref(td), rk, _ptrs(nn), _ptrs(nn),
+                C.c_void_p(FAKE), B.TK_F32, _ptrs(nn), _ptrs(nn))
+    assert ok[0] == 0 and ok[1] > 0, ok[2]
+    assert _query("htucker_reconstruct_vjp", 5, dd, C.byref(td), rk, _ptrs(nn), _ptrs(nn),
+                  C.c_void_p(FAKE), B.TK_F16, _ptrs(nn), _ptrs(nn))[0] == 1
+    assert _query("htucker_reconstruct_vjp", 5, dd, C.byref(td), rk, _ptrs(nn), _ptrs(nn),
+                  None, B.TK_F32, _ptrs(nn), _ptrs(nn))[0] == 1
+    Bb = _ptrs(nn)
+    Bb[0] = None
+    st, _, msg = _query("htucker_reconstruct_vjp", 5, dd, C.byref(td), rk, _ptrs(nn), _ptrs(nn),
+                        C.c_void_p(FAKE), B.TK_F32, Bb, _ptrs(nn))
+    assert st == 1 and "Bbar[0]" in msg
+
+
+def test_htucker_dense_root_children_need_no_unfolding_copy():
+    """Every column of the root's children sampled (idx NULL): the workspace
+    holds no copy of those unfoldings, so it is far smaller than the same
+    call with the columns listed explicitly (which gathers them)."""
+    import synthgen
+    dims = (30, 30, 30, 30)
+    tr = synthgen.balanced_tree(4)
+    nn = tr.num_nodes
+    td = B.tree_desc(tr)
+    X = _tensor(dims)
+    rk = (C.c_int32 * nn)(*([0] + [3] * (nn - 1)))
+    ncols = {t: 30 ** 4 // 30 ** tr.count[t] for t in range(1, nn)}
+
+    def sketches(dense_idx):
+        return (B.TkSketch * nn)(*([_sk(1, 1)] + [
+            _sk(ncols[t], 5, idx=dense_idx) if t in (1, 2) else _sk(60, 5) for t in range(1, nn)]))
+    st_d, n_dense, msg = _query("htucker_decompose", C.byref(X), C.byref(td), rk, sketches(None),
+                                _ptrs(nn), _ptrs(nn), None)
+    st_g, n_gather, _ = _query("htucker_decompose", C.byref(X), C.byref(td), rk, sketches(FAKE),
+                               _ptrs(nn), _ptrs(nn), None)
+    assert st_d == 0 and st_g == 0, msg
+    # the gathered form stores the two 900 x 900 FP32 unfoldings; the dense
+    # form's own buffers (products with X, split partials) are much smaller
+    assert n_gather - n_dense >= 2 * 900 * 900 * 4 * 0.8
+
+
+def test_draw_sketches_rejects_bad_arguments_before_launch():
+    L = B.lib()
+    i64 = lambda *v: (C.c_int64 * len(v))(*v)  # noqa: E731
+    i32 = lambda *v: (C.c_int32 * len(v))(*v)  # noqa: E731
+    pp = (C.c_void_p * 1)(FAKE)
+    ip = C.cast(pp, C.POINTER(C.c_void_p))
+    cases = [
+        (0, i64(10), i32(5), i32(2), B.TK_F64),        # no units
+        (1, i64(10), i32(11), i32(2), B.TK_F64),       # s > ncols
+        (1, i64(10 ** 6), i32(4097), i32(2), B.TK_F64),  # s above the draw limit
+        (1, i64(10), i32(5), i32(0), B.TK_F64),        # ell < 1
+        (1, i64(10), i32(5), i32(2), B.TK_BF16),       # Omega dtype
+    ]
+    for n, nc, s, ell, dt in cases:
+        assert L.tucker_draw_sketches(n, nc, s, ell, 1, pp, pp, dt, None) == 1
+    null = (C.c_void_p * 1)(None)
+    assert L.tucker_draw_sketches(1, i64(10), i32(5), i32(2), 1, null, pp, B.TK_F64, None) == 1
+    del ip
