@@ -175,7 +175,7 @@ def workload(name):
     from synthgen import configs
     table = {"c1": (configs.C1, "f64"), "c2": (configs.C2, "f32"),
              "c3-bf16": (configs.C3, "bf16"), "c3-f16": (configs.C3, "f16"),
-             "c3-f32": (configs.C3, "f32")}
+             "c3-f32": (configs.C3, "f32"), "c8": (configs.C8, "f32")}
     if name not in table:
         raise SystemExit(f"unknown config {name}")
     return table[name]

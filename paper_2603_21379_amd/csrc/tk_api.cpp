@@ -76,11 +76,14 @@ int64_t prod(const int64_t* d, int lo, int hi) {
   return p;
 }
 
-tk_status check_sketch(const tk_sketch& s, int64_t nrows, int64_t ncols, const char* what, int k) {
+// maxell: kWideMaxEll for the sketches of tucker_sketch_all_modes (their QR
+// has a wide path), kMaxEll elsewhere
+tk_status check_sketch(const tk_sketch& s, int64_t nrows, int64_t ncols, const char* what, int k,
+                       int maxell = kMaxEll) {
   if (s.reserved != 0) return set_error(TK_EINVAL, "%s %d: reserved field must be 0", what, k);
-  if (s.ell < 1 || s.ell > kMaxEll)
-    return set_error(s.ell > kMaxEll ? TK_EUNSUPPORTED : TK_EINVAL,
-                     "%s %d: ell = %d outside [1, %d]", what, k, s.ell, kMaxEll);
+  if (s.ell < 1 || s.ell > maxell)
+    return set_error(s.ell > maxell ? TK_EUNSUPPORTED : TK_EINVAL,
+                     "%s %d: ell = %d outside [1, %d]", what, k, s.ell, maxell);
   if (s.ell > nrows) return set_error(TK_EINVAL, "%s %d: ell = %d exceeds the %lld rows", what, k, s.ell, (long long)nrows);
   if (s.s < s.ell || s.s > ncols)
     return set_error(TK_EINVAL, "%s %d: s = %lld outside [ell = %d, ncols = %lld]", what, k,
@@ -144,6 +147,35 @@ void plan_qr(Workspace& ws, QRMat& q, double* Z, int64_t m, int ell, bool wstep,
     q.utmp = ws.take<double>((size_t)m * r);
     q.amax_v = ws.take<double>((size_t)q.nrb * r);
     q.amax_i = ws.take<int64_t>((size_t)q.nrb * r);
+  }
+}
+
+// Plan the wide-path QR (+ W step) workspace of one matrix (ell > kMaxEll).
+void plan_wide(Workspace& ws, WideQR& q, double* Z, int64_t m, int ell, bool wstep, const void* Y,
+               int64_t s, int r, void* U, int32_t* info) {
+  q = WideQR{};
+  q.Z = Z;
+  q.Y = Y;
+  q.U = U;
+  q.info = info;
+  q.m = m;
+  q.s = wstep ? s : 0;
+  q.ell = ell;
+  q.r = wstep ? r : 0;
+  q.np = ell + (ell & 1);
+  q.gsplit = (int32_t)ceil_div(m, kWideRowChunk);
+  q.gpart = ws.take<double>((size_t)q.gsplit * ell * ell);
+  q.R = ws.take<double>((size_t)ell * ell);
+  q.state = ws.take<int32_t>(3 + kWideMaxSweeps);
+  if (wstep) {
+    const int64_t np = q.np;
+    q.csplit = (int32_t)ceil_div(s, kWideRowChunk);
+    q.Mt = ws.take<double>((size_t)s * ell);
+    q.cpart = ws.take<double>((size_t)q.csplit * ell * ell);
+    q.Ap = ws.take<double>((size_t)(np * (np + 1) / 2));
+    q.V = ws.take<double>((size_t)(np * np));
+    q.rot = ws.take<double>((size_t)((np - 1) * (np / 2) * 2));
+    q.W = ws.take<double>((size_t)ell * r);
   }
 }
 
@@ -901,7 +933,7 @@ tk_status tucker_sketch_all_modes(const tk_tensor* X, const tk_sketch* sk, doubl
   if (!ws_bytes) return set_error(TK_EINVAL, "tucker_sketch_all_modes: ws_bytes is NULL");
   const int d = X->order;
   for (int k = 0; k < d; ++k) {
-    if (tk_status s = check_sketch(sk[k], X->dims[k], N / X->dims[k], "mode", k)) return s;
+    if (tk_status s = check_sketch(sk[k], X->dims[k], N / X->dims[k], "mode", k, kWideMaxEll)) return s;
     if (!Z[k]) return set_error(TK_EINVAL, "tucker_sketch_all_modes: Z[%d] is NULL", k);
   }
   Workspace w;
@@ -940,7 +972,8 @@ tk_status tucker_qr(int32_t nmat, const int64_t* m, const int32_t* ell, double* 
     if (m[i] < 1) return set_error(TK_EINVAL, "tucker_qr: m[%d] < 1", i);
     if (ell[i] < 1 || ell[i] > m[i])
       return set_error(TK_EINVAL, "tucker_qr: ell[%d] = %d outside [1, m = %lld]", i, ell[i], (long long)m[i]);
-    if (ell[i] > kMaxEll) return set_error(TK_EUNSUPPORTED, "tucker_qr: ell[%d] = %d > %d", i, ell[i], kMaxEll);
+    if (ell[i] > kWideMaxEll)
+      return set_error(TK_EUNSUPPORTED, "tucker_qr: ell[%d] = %d > %d", i, ell[i], kWideMaxEll);
     if (!Z[i]) return set_error(TK_EINVAL, "tucker_qr: Z[%d] is NULL", i);
     if (Y) {
       if (!Y[i] || !U[i]) return set_error(TK_EINVAL, "tucker_qr: Y[%d] or U[%d] is NULL", i, i);
@@ -951,17 +984,33 @@ tk_status tucker_qr(int32_t nmat, const int64_t* m, const int32_t* ell, double* 
   }
   Workspace w;
   w.base = static_cast<char*>(ws);
-  std::vector<QRMat> mats(nmat);
-  for (int i = 0; i < nmat; ++i)
-    plan_qr(w, mats[i], Z[i], m[i], ell[i], Y != nullptr, Y ? Y[i] : nullptr, Y ? s[i] : 0,
-            Y ? r[i] : 0, Y ? U[i] : nullptr, info ? info + i : nullptr);
+  // sketches up to kMaxEll wide share the batched one-workgroup kernels; wider
+  // ones take the wide path, one matrix at a time
+  std::vector<QRMat> mats;
+  std::vector<WideQR> wide;
+  for (int i = 0; i < nmat; ++i) {
+    if (ell[i] > kMaxEll) {
+      wide.emplace_back();
+      plan_wide(w, wide.back(), Z[i], m[i], ell[i], Y != nullptr, Y ? Y[i] : nullptr, Y ? s[i] : 0,
+                Y ? r[i] : 0, Y ? U[i] : nullptr, info ? info + i : nullptr);
+    } else {
+      mats.emplace_back();
+      plan_qr(w, mats.back(), Z[i], m[i], ell[i], Y != nullptr, Y ? Y[i] : nullptr, Y ? s[i] : 0,
+              Y ? r[i] : 0, Y ? U[i] : nullptr, info ? info + i : nullptr);
+    }
+  }
   if (!ws) {
     *ws_bytes = w.off;
     return TK_OK;
   }
   if (*ws_bytes < w.off)
     return set_error(TK_EWORKSPACE, "tucker_qr: workspace %zu < required %zu", *ws_bytes, w.off);
-  return run_qr(mats, ydtype, udtype, Y != nullptr, as_stream(stream));
+  if (tk_status e = run_qr(mats, ydtype, udtype, Y != nullptr, as_stream(stream))) return e;
+  for (WideQR& q : wide) {
+    q.udtype = udtype;
+    TK_HIP(launch_qr_wide(q, ydtype, Y != nullptr, as_stream(stream)));
+  }
+  return TK_OK;
 }
 
 tk_status tucker_core(const tk_tensor* X, const void* const* F, const int32_t* cols, void* G,
@@ -1220,8 +1269,8 @@ tk_status htucker_decompose(const tk_tensor* X, const tk_tree* tree, const int32
   for (int t = 0; t < nn; ++t) {
     if (tree->left[t] < 0) continue;
     const int l = tree->left[t], r = tree->right[t];
-    if (rank[l] > kMaxCols || rank[r] > kMaxCols)
-      return set_error(TK_EUNSUPPORTED, "htucker_decompose: child rank above %d", kMaxCols);
+    if (rank[l] > kMaxEll || rank[r] > kMaxEll)
+      return set_error(TK_EUNSUPPORTED, "htucker_decompose: child rank above %d", kMaxEll);
   }
   // bases and transfer tensors are small: they are produced in FP64 for every
   // tensor dtype, so storing them adds no error to the format

@@ -66,7 +66,7 @@ constexpr int kOutStorePolicy = 0x11;
 
 // ------------------------------------------------------------------ limits
 constexpr int kMaxEll = 64;       // sketch width handled by the one-wave Jacobi solver
-constexpr int kMaxCols = 64;      // factor columns per mode in the core / reconstruct
+constexpr int kMaxCols = 192;     // factor columns per mode in the core / reconstruct
 constexpr int kMaxUnits = 32;     // sketch units (modes or tree nodes) per launch
 
 // ------------------------------------------------------------------ host error state

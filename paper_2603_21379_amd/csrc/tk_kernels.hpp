@@ -109,6 +109,32 @@ struct QRList {
   int32_t pad;
   __device__ const QRMat& get(int i) const { return m[i]; }
 };
+// Thin QR and W step for sketch widths kMaxEll < ell <= kWideMaxEll: one
+// matrix per launch sequence, its ell x ell matrices in global workspace and
+// (packed) in LDS.
+constexpr int kWideMaxEll = 192;     // packed FP64 triangle of 192 x 192 in LDS (148 KB)
+constexpr int kWideMaxSweeps = 24;   // Jacobi sweeps launched (converged ones exit at once)
+constexpr int kWideRowChunk = 1024;  // rows per partial of the Gram products
+struct WideQR {
+  double* Z;            // m x ell, becomes Q
+  const void* Y;        // m x s or nullptr
+  void* U;              // m x r output or nullptr
+  int32_t* info;        // element or nullptr
+  double* gpart;        // [gsplit][ell][ell] partial Grams of Z
+  double* R;            // [ell][ell]
+  int32_t* state;       // [3 + kWideMaxSweeps] passes owed, apply flag, converged, rotations per sweep
+  double* Mt;           // [s][ell] = (Q^T Y)^T
+  double* cpart;        // [csplit][ell][ell] partial Grams of M
+  double* Ap;           // packed upper triangle of the np x np Jacobi matrix
+  double* V;            // [np][np] eigenvectors (columns)
+  double* rot;          // [np - 1][np / 2][2] (c, s) of the current sweep
+  double* W;            // [ell][r]
+  int64_t m, s;
+  int32_t ell, r, np;   // np = ell rounded up to even
+  int32_t gsplit, csplit;
+  int32_t udtype;
+};
+hipError_t launch_qr_wide(const WideQR& w, int ydtype, bool wstep, hipStream_t st);
 hipError_t launch_cholqr(const QRBatch& b, hipStream_t st);
 hipError_t launch_wstep(const QRBatch& b, int ydtype, int udtype, hipStream_t st);
 // the W step from a given Gram of Q^T Y (cpart, ncc = 1): eigenvectors and U only

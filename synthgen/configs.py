@@ -61,3 +61,14 @@ C7 = HTConfig("c7_inverse_norm_fp32_15^8_serial_rule", 7, 15, 8, 7, 0.0, 4, 2, "
 
 C4_COUNT = 512
 C4_CFG_ID = 4
+
+# uneven modes with the shape of the paper's meteorological tensor (Section
+# 4.1.2) and its truncation ranks; synthetic values.  The core decays slowly
+# (0.97 per index) so that the 150th direction of the last mode stays far
+# above the noise; ell = min(r + p, n) caps the first mode at n_1 = 5 and
+# widens the last to 160
+C8 = TuckerConfig("c8_uneven_fp32_5x10x12x112x80x270", 8, (5, 10, 12, 112, 80, 270),
+                  (5, 8, 10, 28, 50, 150), 0.97, 1e-4, 10, 10, "f32")
+# oracle-sized stand-in: the same caps, a last mode of ell = 90
+C8_SMALL = TuckerConfig("c8_uneven_fp32_5x6x8x20x16x96", 8, (5, 6, 8, 20, 16, 96),
+                        (5, 6, 8, 12, 12, 80), 0.97, 1e-4, 10, 10, "f32")

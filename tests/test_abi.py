@@ -83,10 +83,13 @@ def test_sketch_validation_and_query():
                   (B.TkSketch * 3)(_sk(20, 9), _sk(30, 5), _sk(40, 5)), _ptrs(3), None)[0] == 1
     X0 = _tensor((8, 9, 10), data=None)
     assert _query("tucker_sketch_all_modes", C.byref(X0), sks, _ptrs(3), None)[0] == 1
-    # ell above the one-wave solver limit
+    # widths above 64 take the wide QR path (up to 192); beyond it: unsupported
     big = _tensor((100, 100))
     assert _query("tucker_sketch_all_modes", C.byref(big),
-                  (B.TkSketch * 2)(_sk(100, 65), _sk(100, 5)), _ptrs(2), None)[0] == 5
+                  (B.TkSketch * 2)(_sk(100, 65), _sk(100, 5)), _ptrs(2), None)[0] == 0
+    huge = _tensor((200, 200))
+    assert _query("tucker_sketch_all_modes", C.byref(huge),
+                  (B.TkSketch * 2)(_sk(200, 193), _sk(100, 5)), _ptrs(2), None)[0] == 5
 
 
 def test_workspace_too_small_is_rejected_before_launch():
@@ -117,6 +120,20 @@ def test_qr_validation():
     assert _query("tucker_qr", 2, m, ell, _ptrs(2), _ptrs(2), B.TK_F32, s, r, _ptrs(2), B.TK_F32,
                   None)[0] == 0
     assert _query("tucker_qr", -1, m, ell, _ptrs(2), None, 0, None, None, None, 0, None)[0] == 1
+    # a wide sketch (ell = 160 of 270 rows, s = 2700) next to a narrow one: the
+    # wide plan holds its own Gram partials, M^T (s x ell), the Jacobi matrix,
+    # V and the rotations of a sweep on top of the narrow plan
+    m = (C.c_int64 * 2)(270, 20)
+    s = (C.c_int64 * 2)(2700, 40)
+    r = (C.c_int32 * 2)(150, 5)
+    ell = (C.c_int32 * 2)(160, 5)
+    st, n_wide, _ = _query("tucker_qr", 2, m, ell, _ptrs(2), _ptrs(2), B.TK_F32, s, r, _ptrs(2),
+                           B.TK_F32, None)
+    assert st == 0 and n_wide > 8 * (2700 * 160 + 3 * 160 * 160)
+    ell = (C.c_int32 * 2)(193, 5)
+    st, _, msg = _query("tucker_qr", 2, m, ell, _ptrs(2), _ptrs(2), B.TK_F32, s, r, _ptrs(2),
+                        B.TK_F32, None)
+    assert st == 5 and "ell[0]" in msg
 
 
 def test_core_and_reconstruct_validation():
