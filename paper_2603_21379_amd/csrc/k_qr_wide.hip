@@ -207,9 +207,18 @@ __global__ __launch_bounds__(64) void wide_apply_kernel(const WideQR w) {
       for (int jj = 0; jj < jc; ++jj) {
         const int j = j0 + jj;
         const double* rc = Rt + jj * n;
-        double v = sZ[j * 65 + lane];
-        for (int k = 0; k < j; ++k) v = fma(-sZ[k * 65 + lane], rc[k], v);
-        sZ[j * 65 + lane] = v / rc[j];
+        // four partial sums (k mod 4), combined in a fixed order: the loads
+        // of a step do not wait on the previous step's sum
+        double v0 = sZ[j * 65 + lane], v1 = 0.0, v2 = 0.0, v3 = 0.0;
+        int k = 0;
+        for (; k + 4 <= j; k += 4) {
+          v0 = fma(-sZ[k * 65 + lane], rc[k], v0);
+          v1 = fma(-sZ[(k + 1) * 65 + lane], rc[k + 1], v1);
+          v2 = fma(-sZ[(k + 2) * 65 + lane], rc[k + 2], v2);
+          v3 = fma(-sZ[(k + 3) * 65 + lane], rc[k + 3], v3);
+        }
+        for (; k < j; ++k) v0 = fma(-sZ[k * 65 + lane], rc[k], v0);
+        sZ[j * 65 + lane] = ((v0 + v1) + (v2 + v3)) / rc[j];
       }
     }
   }
@@ -226,19 +235,25 @@ __global__ __launch_bounds__(64) void wide_apply_kernel(const WideQR w) {
 // (p, q), p < q, is J with J_pp = J_qq = c, J_pq = s, J_qp = -s; A <- J^T A J
 // zeroes a_pq.  It is skipped once |a_pq| <= tol max(|a_pp|, |a_qq|) (the
 // rotation is then below rounding level relative to the pair's own scale).
+// Every thread owns a fixed set of (pair a, pair b), a <= b, items, the same
+// in every round; a round's pairs and rotations sit in LDS.
 // state[2]: converged; state[3 + k]: rotations of sweep k.
-__global__ __launch_bounds__(1024) void wide_sweep_kernel(const WideQR w, int sweep, double tol) {
+constexpr int kSweepThreads = 1024;
+constexpr int kSweepItems = (kWideMaxEll / 2 * (kWideMaxEll / 2 + 1) / 2 + kSweepThreads - 1) / kSweepThreads;
+__global__ __launch_bounds__(kSweepThreads) void wide_sweep_kernel(const WideQR w, int sweep, double tol) {
   extern __shared__ double A[];
   __shared__ double rc[kWideMaxEll / 2], rs[kWideMaxEll / 2], rt[kWideMaxEll / 2];
-  __shared__ int ract[kWideMaxEll / 2];
+  __shared__ int ract[kWideMaxEll / 2], sp[kWideMaxEll / 2], sq[kWideMaxEll / 2];
+  __shared__ int rowoff[kWideMaxEll];   // pk(x, y) = rowoff[x] + y for x <= y
   __shared__ int count;
-  const int n = w.ell, np = w.np, half = np / 2, tid = threadIdx.x, nt = blockDim.x;
+  const int n = w.ell, np = w.np, half = np / 2, tid = threadIdx.x;
+  if (sweep > 0 && w.state[2]) return;
+  for (int x = tid; x < np; x += kSweepThreads) rowoff[x] = (int)pk(x, 0, np);
   if (sweep == 0) {
-    __syncthreads();
     if (tid == 0) w.state[2] = 0;
-    for (int k = tid; k < kWideMaxSweeps; k += nt) w.state[3 + k] = 0;
+    for (int k = tid; k < kWideMaxSweeps; k += kSweepThreads) w.state[3 + k] = 0;
     const int64_t nn = (int64_t)n * n;
-    for (int64_t e = tid; e < (int64_t)np * np; e += nt) {
+    for (int64_t e = tid; e < (int64_t)np * np; e += kSweepThreads) {
       const int p = (int)(e / np), q = (int)(e - (int64_t)p * np);
       if (q < p) continue;
       double v = 0.0;
@@ -247,17 +262,29 @@ __global__ __launch_bounds__(1024) void wide_sweep_kernel(const WideQR w, int sw
       A[pk(p, q, np)] = v;
     }
   } else {
-    if (w.state[2]) return;
     const int64_t tot = (int64_t)np * (np + 1) / 2;
-    for (int64_t e = tid; e < tot; e += nt) A[e] = w.Ap[e];
+    for (int64_t e = tid; e < tot; e += kSweepThreads) A[e] = w.Ap[e];
+  }
+  // this thread's items: (a, b) with a <= b, triangular index tid + 1024 j
+  int item[kSweepItems];
+  const int T = half * (half + 1) / 2;
+#pragma unroll
+  for (int j = 0; j < kSweepItems; ++j) {
+    int e = tid + kSweepThreads * j, a = 0;
+    item[j] = -1;
+    if (e < T) {
+      while (e >= half - a) { e -= half - a; ++a; }
+      item[j] = a | ((a + e) << 8);
+    }
   }
   if (tid == 0) count = 0;
   __syncthreads();
+  auto at = [&](int x, int y) -> double& { return x <= y ? A[rowoff[x] + y] : A[rowoff[y] + x]; };
   for (int t = 0; t < np - 1; ++t) {
     if (tid < half) {
       int p, q;
       pair_of(t, tid, np, p, q);
-      const double app = A[pk(p, p, np)], aqq = A[pk(q, q, np)], apq = A[pk(p, q, np)];
+      const double app = A[rowoff[p] + p], aqq = A[rowoff[q] + q], apq = A[rowoff[p] + q];
       double c = 1.0, s = 0.0, tn = 0.0;
       const bool act = fabs(apq) > tol * fmax(fabs(app), fabs(aqq));
       if (act) {
@@ -271,42 +298,46 @@ __global__ __launch_bounds__(1024) void wide_sweep_kernel(const WideQR w, int sw
       rs[tid] = s;
       rt[tid] = tn;
       ract[tid] = act;
+      sp[tid] = p;
+      sq[tid] = q;
       double* ro = w.rot + 2 * ((int64_t)t * half + tid);
       ro[0] = c;
       ro[1] = s;
     }
     __syncthreads();
-    for (int e = tid; e < half * half; e += nt) {
-      const int a = e / half, b = e - a * half;
-      if (a > b || (!ract[a] && !ract[b])) continue;
-      int pa, qa;
-      pair_of(t, a, np, pa, qa);
+#pragma unroll
+    for (int j = 0; j < kSweepItems; ++j) {
+      if (item[j] < 0) continue;
+      const int a = item[j] & 255, b = item[j] >> 8;
+      if (!ract[a] && !ract[b]) continue;
+      const int pa = sp[a], qa = sq[a];
       if (a == b) {
-        const int64_t ipq = pk(pa, qa, np);
+        const int ipq = rowoff[pa] + qa;
         const double apq = A[ipq];
-        A[pk(pa, pa, np)] -= rt[a] * apq;
-        A[pk(qa, qa, np)] += rt[a] * apq;
+        A[rowoff[pa] + pa] -= rt[a] * apq;
+        A[rowoff[qa] + qa] += rt[a] * apq;
         A[ipq] = 0.0;
         continue;
       }
-      int pb, qb;
-      pair_of(t, b, np, pb, qb);
-      const int64_t i00 = pks(pa, pb, np), i01 = pks(pa, qb, np);
-      const int64_t i10 = pks(qa, pb, np), i11 = pks(qa, qb, np);
-      const double x00 = A[i00], x01 = A[i01], x10 = A[i10], x11 = A[i11];
+      const int pb = sp[b], qb = sq[b];
+      double& r00 = at(pa, pb);
+      double& r01 = at(pa, qb);
+      double& r10 = at(qa, pb);
+      double& r11 = at(qa, qb);
+      const double x00 = r00, x01 = r01, x10 = r10, x11 = r11;
       const double ca = rc[a], sa = rs[a], cb = rc[b], sb = rs[b];
       // right factor J_b on the columns, then J_a^T on the rows
       const double y00 = cb * x00 - sb * x01, y01 = sb * x00 + cb * x01;
       const double y10 = cb * x10 - sb * x11, y11 = sb * x10 + cb * x11;
-      A[i00] = ca * y00 - sa * y10;
-      A[i10] = sa * y00 + ca * y10;
-      A[i01] = ca * y01 - sa * y11;
-      A[i11] = sa * y01 + ca * y11;
+      r00 = ca * y00 - sa * y10;
+      r10 = sa * y00 + ca * y10;
+      r01 = ca * y01 - sa * y11;
+      r11 = sa * y01 + ca * y11;
     }
     __syncthreads();
   }
   const int64_t tot = (int64_t)np * (np + 1) / 2;
-  for (int64_t e = tid; e < tot; e += nt) w.Ap[e] = A[e];
+  for (int64_t e = tid; e < tot; e += kSweepThreads) w.Ap[e] = A[e];
   if (tid == 0) {
     w.state[3 + sweep] = count;
     if (count == 0) w.state[2] = 1;
@@ -315,7 +346,9 @@ __global__ __launch_bounds__(1024) void wide_sweep_kernel(const WideQR w, int sw
 
 // V <- V J for every rotation of a sweep, one row of V per workgroup (the
 // rotations of a round touch disjoint pairs of a row).  Sweep 0 starts from
-// the identity.
+// the identity.  The next round's (c, s) loads are issued before the current
+// round's rotations.
+constexpr int kVrotPairs = (kWideMaxEll / 2 + 63) / 64;
 __global__ __launch_bounds__(64) void wide_vrot_kernel(const WideQR w, int sweep) {
   __shared__ double row[kWideMaxEll];
   const int np = w.np, half = np / 2, lane = threadIdx.x, i = blockIdx.x;
@@ -324,17 +357,33 @@ __global__ __launch_bounds__(64) void wide_vrot_kernel(const WideQR w, int sweep
   double* vr = w.V + (int64_t)i * np;
   for (int j = lane; j < np; j += 64) row[j] = sweep == 0 ? (j == i ? 1.0 : 0.0) : vr[j];
   if (rotate) {
-    for (int t = 0; t < np - 1; ++t) {
-      __syncthreads();
-      for (int k = lane; k < half; k += 64) {
-        int p, q;
-        pair_of(t, k, np, p, q);
-        const double* ro = w.rot + 2 * ((int64_t)t * half + k);
-        const double c = ro[0], s = ro[1];
-        const double vp = row[p], vq = row[q];
-        row[p] = c * vp - s * vq;
-        row[q] = s * vp + c * vq;
+    double2 cur[kVrotPairs], nxt[kVrotPairs];
+    auto fetch = [&](int t, double2 (&d)[kVrotPairs]) {
+#pragma unroll
+      for (int u = 0; u < kVrotPairs; ++u) {
+        const int k = lane + 64 * u;
+        d[u] = (t < np - 1 && k < half)
+                   ? *reinterpret_cast<const double2*>(w.rot + 2 * ((int64_t)t * half + k))
+                   : make_double2(1.0, 0.0);
       }
+    };
+    fetch(0, cur);
+    for (int t = 0; t < np - 1; ++t) {
+      fetch(t + 1, nxt);
+      __syncthreads();
+#pragma unroll
+      for (int u = 0; u < kVrotPairs; ++u) {
+        const int k = lane + 64 * u;
+        if (k < half) {
+          int p, q;
+          pair_of(t, k, np, p, q);
+          const double vp = row[p], vq = row[q];
+          row[p] = cur[u].x * vp - cur[u].y * vq;
+          row[q] = cur[u].y * vp + cur[u].x * vq;
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < kVrotPairs; ++u) cur[u] = nxt[u];
     }
   }
   __syncthreads();
@@ -431,7 +480,7 @@ hipError_t launch_qr_wide(const WideQR& w, int ydtype, bool wstep, hipStream_t s
   // the pair's own scale): FP64 bases need ~u, FP32 bases ~1e-12 suffices
   const double tol = w.udtype == TK_F64 ? 4.0 * kUnit : 1e-12;
   for (int sweep = 0; sweep < kWideMaxSweeps; ++sweep) {
-    hipLaunchKernelGGL(wide_sweep_kernel, dim3(1), dim3(1024), wide_sweep_lds(w.np), st, w, sweep, tol);
+    hipLaunchKernelGGL(wide_sweep_kernel, dim3(1), dim3(kSweepThreads), wide_sweep_lds(w.np), st, w, sweep, tol);
     hipLaunchKernelGGL(wide_vrot_kernel, dim3((unsigned)w.np), dim3(64), 0, st, w, sweep);
   }
   hipLaunchKernelGGL(wide_select_kernel, dim3(1), dim3(256), 0, st, w);

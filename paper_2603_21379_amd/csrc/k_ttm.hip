@@ -216,13 +216,21 @@ hipError_t mode_product(const ModeProduct& mp, int m_dt, hipStream_t st) {
   hipLaunchKernelGGL(stage_factor_kernel, dim3((unsigned)ceil_div(mp.Q * ld, 256)), dim3(256), 0,
                      st, mp.M, m_dt, (int64_t)mp.rs, (int64_t)mp.cs, mp.P, mp.Q, ld, mp.Mt);
   if (mp.B == 1) {
-    const dim3 grid((unsigned)ceil_div(mp.A, 64), pchunks);
-    if (width == 16)
+    // up to 192 columns in one block, so each row of `in` is read once (for
+    // 64 < P <= 192 the table's ld, a multiple of 64, is exactly 128 or 192);
+    // wider products keep 64-column blocks, whose reads stay inside ld
+    const int wr = mp.P <= 64 ? width : mp.P <= 128 ? 128 : mp.P <= 192 ? 192 : 64;
+    const dim3 grid((unsigned)ceil_div(mp.A, 64), (unsigned)ceil_div(mp.P, wr));
+    if (wr == 16)
       hipLaunchKernelGGL((mode_rows_kernel<TIn, TOut, 16>), grid, dim3(256), 0, st, mp, ld);
-    else if (width == 32)
+    else if (wr == 32)
       hipLaunchKernelGGL((mode_rows_kernel<TIn, TOut, 32>), grid, dim3(256), 0, st, mp, ld);
-    else
+    else if (wr == 64)
       hipLaunchKernelGGL((mode_rows_kernel<TIn, TOut, 64>), grid, dim3(256), 0, st, mp, ld);
+    else if (wr == 128)
+      hipLaunchKernelGGL((mode_rows_kernel<TIn, TOut, 128>), grid, dim3(256), 0, st, mp, ld);
+    else
+      hipLaunchKernelGGL((mode_rows_kernel<TIn, TOut, 192>), grid, dim3(256), 0, st, mp, ld);
   } else {
     // several points per thread when there are enough of them to keep every
     // CU busy (64 accumulators per thread at most)

@@ -242,7 +242,27 @@ struct CorePlan {
   double* mt = nullptr;   // staged factor table of the mode products
   int kind = kCoreGeneric;
   int fused_modes = 0;
+  // modes in contraction order (after the fused ones): the generic chain takes
+  // the largest reduction n_k / c_k first (ties: the later mode first), so
+  // the pass that reads X is the cheapest and every later one reads less
+  int order[TK_MAX_ORDER] = {};
+  int nsteps = 0;
 };
+
+void chain_order(const int64_t* dims, const int32_t* cols, int first, CorePlan& p) {
+  bool used[TK_MAX_ORDER] = {};
+  p.nsteps = 0;
+  for (int step = 0; step <= first; ++step) {
+    int best = -1;
+    for (int k = first; k >= 0; --k) {
+      if (used[k]) continue;
+      // n_k / c_k > n_b / c_b, compared exactly in integers
+      if (best < 0 || dims[k] * (int64_t)cols[best] > dims[best] * (int64_t)cols[k]) best = k;
+    }
+    used[best] = true;
+    p.order[p.nsteps++] = best;
+  }
+}
 
 int core_kind(int xdt, int order, const int64_t* dims, const int32_t* cols) {
   if (fused2_supported(xdt, order, dims, cols)) return kCoreFused2;
@@ -275,8 +295,14 @@ tk_status plan_core(Workspace& ws, int xdt, int order, const int64_t* dims, cons
     for (int k = order - p.fused_modes; k < order; ++k) shape[k] = cols[k];
     p.t32 = ws.take<float>((size_t)prod(shape, 0, order));
   }
-  for (int k = first; k >= 1; --k) {
-    shape[k] = cols[k];
+  if (p.kind == kCoreGeneric) {
+    chain_order(dims, cols, first, p);
+  } else {
+    p.nsteps = 0;
+    for (int k = first; k >= 0; --k) p.order[p.nsteps++] = k;
+  }
+  for (int i = 0; i + 1 < p.nsteps; ++i) {
+    shape[p.order[i]] = cols[p.order[i]];
     mx = std::max(mx, prod(shape, 0, order));
   }
   p.buf[0] = ws.take<double>((size_t)mx);
@@ -294,7 +320,6 @@ tk_status run_core(const void* X, int xdt, int order, const int64_t* dims,
   for (int k = 0; k < order; ++k) shape[k] = dims[k];
   const void* cur = X;
   int cur_dt = xdt;
-  int kstart = order - 1;
   if (p.kind == kCoreFused2) {
     // the two trailing modes in one MFMA pass over X
     CoreFused2 f{};
@@ -335,9 +360,12 @@ tk_status run_core(const void* X, int xdt, int order, const int64_t* dims,
     for (int k = order - p.fused_modes; k < order; ++k) shape[k] = cols[k];
     cur = p.t32;
     cur_dt = TK_F32;
-    kstart = order - 1 - p.fused_modes;
   }
-  for (int k = kstart; k >= 0; --k) {
+  for (int i = 0; i < p.nsteps; ++i) {
+    const int k = p.order[i];
+    const bool last = i + 1 == p.nsteps;
+    // the launch that reads X (no fused pass before it)
+    const bool streaming = i == 0 && !p.fused_modes;
     if (cur_dt == TK_F32 && fdt == TK_F32 &&
         mode_mfma_supported(shape[k], prod(shape, k + 1, order), cols[k])) {
       // FP32 partial core: MFMA contraction, FP32 intermediates
@@ -348,9 +376,11 @@ tk_status run_core(const void* X, int xdt, int order, const int64_t* dims,
       mm.Q = shape[k];
       mm.B = prod(shape, k + 1, order);
       mm.P = cols[k];
-      void* out = k == 0 ? G : (void*)p.buf[(kstart - k) & 1];
+      void* out = last ? G : (void*)p.buf[i & 1];
       mm.out = out;
+      if (streaming) TK_HIP(profile_begin(st));
       TK_HIP(launch_mode_mfma_f32(mm, TK_F32, st));
+      if (streaming) TK_HIP(profile_end(st));
       shape[k] = cols[k];
       cur = out;
       continue;
@@ -365,11 +395,10 @@ tk_status run_core(const void* X, int xdt, int order, const int64_t* dims,
     mp.Mt = p.mt;
     mp.rs = 1;          // M[p][q] = F[q][p]
     mp.cs = cols[k];
-    void* out = k == 0 ? G : (void*)p.buf[(kstart - k) & 1];
+    void* out = last ? G : (void*)p.buf[i & 1];
     mp.out = out;
-    const bool streaming = k == order - 1 && !p.fused_modes;  // the launch that reads X
     if (streaming) TK_HIP(profile_begin(st));
-    TK_HIP(launch_mode_product(mp, cur_dt, k == 0 ? fdt : TK_F64, fdt, st));
+    TK_HIP(launch_mode_product(mp, cur_dt, last ? fdt : TK_F64, fdt, st));
     if (streaming) TK_HIP(profile_end(st));
     shape[k] = cols[k];
     cur = out;
