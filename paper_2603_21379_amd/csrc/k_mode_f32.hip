@@ -132,6 +132,100 @@ __global__ __launch_bounds__(256) void mode_mfma_f32_kernel(const ModeMfma m) {
   }
 }
 
+// The last mode (B = 1) on MFMA, for up to 192 factor columns:
+//   out[a][p] = sum_q in[a][q] F[q][p].
+// A block keeps a slice of up to 96 columns of F (every q, zero padded) in
+// LDS, read once, and is persistent over row tiles: each of its 8 waves forms
+// a 32-row x 32-column tile per 32-column group with v_mfma_f32_32x32x2f32,
+// the A operand from `in` (lane l: row a0 + l%32) and the B operand from the
+// LDS slice (lane l: column p0 + l%32), so an accumulator register holds 32
+// consecutive columns of one row and the stores are coalesced.  Per 32-q step
+// a lane reads 16 consecutive q of its row (four 16-byte buffer loads; the
+// half-waves take q0..q0+15 and q0+16..q0+31, which pairs the two k rows of
+// the MFMA with the same q in both operands); the next step's loads are in
+// flight while the current one is multiplied.  Rows past A read zero through
+// the buffer range check; q past Q (the next row's values) is dropped.
+constexpr int kLastWaves = 8;
+constexpr int kLastQC = 32;     // q per step
+constexpr int kLastMaxPT = 3;   // 32-column groups per block (96 columns)
+constexpr int kLastLdf = 32 * kLastMaxPT + 2;  // LDS row stride: half-waves on disjoint banks
+
+template <typename TOut>
+__global__ __launch_bounds__(64 * kLastWaves) void mode_last_mfma_kernel(const ModeMfma m) {
+  extern __shared__ float sL[];   // [Qp][kLastLdf]
+  const int tid = threadIdx.x;
+  const int p0 = blockIdx.y * 32 * kLastMaxPT;
+  const int npt = min(kLastMaxPT, (int)((m.P - p0 + 31) / 32));
+  const int nsteps = (int)((m.Q + kLastQC - 1) / kLastQC);
+  const int Qp = nsteps * kLastQC;
+  for (int e = tid; e < Qp * 32 * kLastMaxPT; e += 64 * kLastWaves) {
+    const int q = e / (32 * kLastMaxPT), pp = e - q * (32 * kLastMaxPT);
+    const int p = p0 + pp;
+    sL[q * kLastLdf + pp] = (q < m.Q && p < m.P) ? m.F[(int64_t)q * m.P + p] : 0.0f;
+  }
+  __syncthreads();
+  const int lane = tid & 63, kh = lane >> 5, l32 = lane & 31;
+  const int wave = tid >> 6;
+  const int64_t tiles = (m.A + 31) / 32;
+  // the host checks A Q 4 < 2^31
+  const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+      const_cast<float*>(m.in), (short)0, (int)(m.A * m.Q * 4), kRsrcWord3);
+  TOut* out = static_cast<TOut*>(m.out);
+  for (int64_t tile = (int64_t)blockIdx.x * kLastWaves + wave; tile < tiles;
+       tile += (int64_t)gridDim.x * kLastWaves) {
+    const int64_t row = tile * 32 + l32;
+    const bool rok = row < m.A;
+    auto load = [&](int step, floatx4 (&b)[4]) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int q = step * kLastQC + 16 * kh + 4 * u;
+        const uint32_t off = (rok && step < nsteps) ? (uint32_t)((row * m.Q + q) * 4) : 0x80000000u;
+        b[u] = __builtin_bit_cast(floatx4, __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, 0));
+      }
+    };
+    floatx16 acc[kLastMaxPT];
+#pragma unroll
+    for (int t = 0; t < kLastMaxPT; ++t) acc[t] = floatx16{};
+    auto compute = [&](int step, const floatx4 (&b)[4]) {
+      const bool tail = (step + 1) * kLastQC > m.Q;   // wave-uniform
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          const int ql = step * kLastQC + 16 * kh + 4 * u + c;
+          float xv = b[u][c];
+          if (tail && ql >= m.Q) xv = 0.0f;
+          const float* fr = sL + ql * kLastLdf + l32;
+#pragma unroll
+          for (int t = 0; t < kLastMaxPT; ++t)
+            if (t < npt) acc[t] = mfma32(xv, fr[32 * t], acc[t]);
+        }
+      }
+    };
+    floatx4 bufA[4], bufB[4];
+    load(0, bufA);
+    for (int s = 0; s < nsteps; s += 2) {
+      load(s + 1, bufB);
+      __builtin_amdgcn_sched_barrier(0);
+      compute(s, bufA);
+      load(s + 2, bufA);
+      __builtin_amdgcn_sched_barrier(0);
+      if (s + 1 < nsteps) compute(s + 1, bufB);
+    }
+    // acc[t] register v: row tile*32 + 8 (v/4) + 4 kh + v%4, column p0 + 32 t + l32
+#pragma unroll
+    for (int t = 0; t < kLastMaxPT; ++t) {
+      const int p = p0 + 32 * t + l32;
+      if (t >= npt || p >= m.P) continue;
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        const int64_t r = tile * 32 + 8 * (v >> 2) + 4 * kh + (v & 3);
+        if (r < m.A) out[r * m.P + p] = (TOut)acc[t][v];
+      }
+    }
+  }
+}
+
 }  // namespace
 
 bool mode_mfma_supported(int64_t Q, int64_t B, int32_t P) {
@@ -160,6 +254,31 @@ hipError_t launch_mode_mfma_f32(const ModeMfma& m, int out_dt, hipStream_t st) {
   if (u4 >= want) return launch_mode_vec<4>(m, out_dt, lds, st);
   if (u2 >= want) return launch_mode_vec<2>(m, out_dt, lds, st);
   return launch_mode_vec<1>(m, out_dt, lds, st);
+}
+
+}  // namespace tk
+
+namespace tk {
+
+bool mode_last_mfma_supported(int64_t A, int64_t Q, int32_t P) {
+  // the F slice of every q in LDS (at most 150.5 KB); one buffer range for `in`
+  return P >= 1 && P <= 192 && Q >= 1 && Q <= 384 && A >= 1 && A * Q * 4 < (int64_t(1) << 31);
+}
+
+hipError_t launch_mode_last_mfma_f32(const ModeMfma& m, int out_dt, hipStream_t st) {
+  if (m.A == 0) return hipSuccess;
+  const int groups = (m.P + 32 * kLastMaxPT - 1) / (32 * kLastMaxPT);
+  const int64_t Qp = (m.Q + kLastQC - 1) / kLastQC * kLastQC;
+  const size_t lds = (size_t)Qp * kLastLdf * sizeof(float);
+  // one resident block per CU (the slice takes most of the LDS), persistent
+  const int64_t tiles = (m.A + 31) / 32;
+  const int64_t per_group = std::max<int64_t>(1, std::min<int64_t>(ceil_div(tiles, kLastWaves), 256 / groups));
+  const dim3 grid((unsigned)per_group, (unsigned)groups);
+  if (out_dt == TK_F64)
+    hipLaunchKernelGGL((mode_last_mfma_kernel<double>), grid, dim3(64 * kLastWaves), lds, st, m);
+  else
+    hipLaunchKernelGGL((mode_last_mfma_kernel<float>), grid, dim3(64 * kLastWaves), lds, st, m);
+  return hipGetLastError();
 }
 
 }  // namespace tk

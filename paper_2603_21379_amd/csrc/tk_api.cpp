@@ -385,6 +385,25 @@ tk_status run_core(const void* X, int xdt, int order, const int64_t* dims,
       cur = out;
       continue;
     }
+    if (cur_dt == TK_F32 && fdt == TK_F32 && prod(shape, k + 1, order) == 1 &&
+        mode_last_mfma_supported(prod(shape, 0, k), shape[k], cols[k])) {
+      // the last mode of an FP32 partial core (or of X): MFMA, FP32 out
+      ModeMfma mm{};
+      mm.in = static_cast<const float*>(cur);
+      mm.F = static_cast<const float*>(F[k]);
+      mm.A = prod(shape, 0, k);
+      mm.Q = shape[k];
+      mm.B = 1;
+      mm.P = cols[k];
+      void* out = last ? G : (void*)p.buf[i & 1];
+      mm.out = out;
+      if (streaming) TK_HIP(profile_begin(st));
+      TK_HIP(launch_mode_last_mfma_f32(mm, TK_F32, st));
+      if (streaming) TK_HIP(profile_end(st));
+      shape[k] = cols[k];
+      cur = out;
+      continue;
+    }
     ModeProduct mp{};
     mp.in = cur;
     mp.A = prod(shape, 0, k);

@@ -281,6 +281,9 @@ struct ModeMfma {
 };
 bool mode_mfma_supported(int64_t Q, int64_t B, int32_t P);
 hipError_t launch_mode_mfma_f32(const ModeMfma& m, int out_dt, hipStream_t st);
+// the last mode (B = 1), up to 192 columns: out[a][p] = sum_q in[a][q] F[q][p]
+bool mode_last_mfma_supported(int64_t A, int64_t Q, int32_t P);
+hipError_t launch_mode_last_mfma_f32(const ModeMfma& m, int out_dt, hipStream_t st);
 
 // ---------------------------------------------------------------- FP32 fused streaming residual
 // sum (X[a] - F_I T[a] F_J^T)^2 and sum X[a]^2 over the A slabs of an FP32 tensor.

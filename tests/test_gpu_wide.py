@@ -78,3 +78,23 @@ def test_wide_bitwise_repeatable():
     for fa, fb in zip(a.F, b.F):
         assert torch.equal(fa, fb)
     assert torch.equal(a.G, b.G)
+
+
+@pytest.mark.parametrize("dims,cols", [
+    # the last mode has the largest reduction (300 -> 100): it is contracted
+    # first, on the last-mode MFMA kernel (two column groups of 96 and 4,
+    # q tail of 12, 3000 rows), then the two leading modes
+    ((50, 60, 300), (40, 50, 100)),
+    # 150 columns (two groups, the second partial), Q = 270 as in the uneven
+    # shape, rows not a multiple of 32
+    ((7, 11, 270), (6, 9, 150)),
+    # the uneven stand-in's chain: 20 -> 12 and 16 -> 12 on the middle-mode
+    # MFMA kernel, then 96 -> 80 on the last-mode kernel
+    ((5, 6, 8, 20, 16, 96), (5, 6, 8, 12, 12, 80)),
+])
+def test_wide_factor_core_fp32(dims, cols):
+    """FP32 core with factors wider than 64 columns against the FP64 oracle
+    (the order of the contractions and their kernels are the library's)."""
+    from test_gpu_tucker import _core_direct
+    G, ref = _core_direct(dims, cols, "f32", 72)
+    np.testing.assert_allclose(G, ref, rtol=0, atol=2e-6 * np.abs(ref).max())
