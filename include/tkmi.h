@@ -102,7 +102,8 @@ typedef struct {
  *          NULL): Y[k] receives Y_k (n_k x s_k, row-major, X's dtype), the
  *          input of the W step of tucker_qr.
  * Errors: TK_EINVAL for a bad descriptor, ell > s, s > ncols, a non-zero
- * reserved field or NULL required pointers; TK_EWORKSPACE; TK_EDEVICE. */
+ * reserved field or NULL required pointers; TK_EUNSUPPORTED for ell > 192;
+ * TK_EWORKSPACE; TK_EDEVICE. */
 tk_status tucker_sketch_all_modes(const tk_tensor* X, const tk_sketch* sk, double* const* Z,
                                   void* const* Y, void* ws, size_t* ws_bytes, void* stream);
 
@@ -129,7 +130,10 @@ tk_status tucker_sketch_all_modes(const tk_tensor* X, const tk_sketch* sk, doubl
  *            (first on ties) is made positive.  With r_i = ell_i the columns
  *            of U_i span Range(Q_i).
  *   info     device int32 [nmat] (may be NULL).
- * Errors: TK_EINVAL, TK_EWORKSPACE, TK_EDEVICE. */
+ * Widths up to 64 run as one batch (one workgroup per matrix); wider ones,
+ * up to 192, one matrix at a time with the same arithmetic rules (their
+ * ell x ell matrices packed in LDS and in the workspace).
+ * Errors: TK_EINVAL, TK_EUNSUPPORTED (ell_i > 192), TK_EWORKSPACE, TK_EDEVICE. */
 tk_status tucker_qr(int32_t nmat, const int64_t* m, const int32_t* ell, double* const* Z,
                     const void* const* Y, int32_t ydtype, const int64_t* s, const int32_t* r,
                     void* const* U, int32_t udtype, int32_t* info, void* ws, size_t* ws_bytes,
@@ -139,12 +143,13 @@ tk_status tucker_qr(int32_t nmat, const int64_t* m, const int32_t* ell, double* 
  * The one full read of X.
  *   F      host array [order] of device n_k x c_k row-major factors in the
  *          factor dtype.
- *   cols   host array [order]: c_k (1 <= c_k <= n_k).
+ *   cols   host array [order]: c_k (1 <= c_k <= n_k, c_k <= 192).
  *   G      device output c_1 x ... x c_d (C-order), factor dtype.
  * Accumulation: FP64 for F64 tensors; FP32 MFMA with FP64 combination of
  * partial sums for F32; BF16/F16 MFMA with FP32 accumulation for BF16/F16
- * tensors (factors enter as a hi+lo pair).
- * Errors: TK_EINVAL, TK_EWORKSPACE, TK_EDEVICE. */
+ * tensors (factors enter as a hi+lo pair).  Modes that no fused pass covers
+ * are contracted one at a time, the largest reduction n_k / c_k first.
+ * Errors: TK_EINVAL, TK_EUNSUPPORTED (c_k > 192), TK_EWORKSPACE, TK_EDEVICE. */
 tk_status tucker_core(const tk_tensor* X, const void* const* F, const int32_t* cols, void* G,
                       void* ws, size_t* ws_bytes, void* stream);
 
