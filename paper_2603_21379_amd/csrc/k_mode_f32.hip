@@ -132,8 +132,10 @@ __global__ __launch_bounds__(256) void mode_mfma_f32_kernel(const ModeMfma m) {
   }
 }
 
-// The last mode (B = 1) on MFMA, for up to 192 factor columns:
-//   out[a][p] = sum_q in[a][q] F[q][p].
+// The last mode (B = 1) on MFMA:
+//   out[a][p] = sum_q in[a][q] F[q][p]
+// (a contraction by F_k with P = c_k, or with ftrans an expansion by F_k,
+// F[q][p] = F_k[p][q] and P = n_k).
 // A block keeps a slice of up to 96 columns of F (every q, zero padded) in
 // LDS, read once, and is persistent over row tiles: each of its 8 waves forms
 // a 32-row x 32-column tile per 32-column group with v_mfma_f32_32x32x2f32,
@@ -161,13 +163,15 @@ __global__ __launch_bounds__(64 * kLastWaves) void mode_last_mfma_kernel(const M
   for (int e = tid; e < Qp * 32 * kLastMaxPT; e += 64 * kLastWaves) {
     const int q = e / (32 * kLastMaxPT), pp = e - q * (32 * kLastMaxPT);
     const int p = p0 + pp;
-    sL[q * kLastLdf + pp] = (q < m.Q && p < m.P) ? m.F[(int64_t)q * m.P + p] : 0.0f;
+    float f = 0.0f;
+    if (q < m.Q && p < m.P) f = m.ftrans ? m.F[(int64_t)p * m.Q + q] : m.F[(int64_t)q * m.P + p];
+    sL[q * kLastLdf + pp] = f;
   }
   __syncthreads();
   const int lane = tid & 63, kh = lane >> 5, l32 = lane & 31;
   const int wave = tid >> 6;
   const int64_t tiles = (m.A + 31) / 32;
-  // the host checks A Q 4 < 2^31
+  // the launcher keeps A Q 4 below 2^31
   const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
       const_cast<float*>(m.in), (short)0, (int)(m.A * m.Q * 4), kRsrcWord3);
   TOut* out = static_cast<TOut*>(m.out);
@@ -262,7 +266,85 @@ namespace tk {
 
 bool mode_last_mfma_supported(int64_t A, int64_t Q, int32_t P) {
   // the F slice of every q in LDS (at most 150.5 KB); one buffer range for `in`
-  return P >= 1 && P <= 192 && Q >= 1 && Q <= 384 && A >= 1 && A * Q * 4 < (int64_t(1) << 31);
+  // (the launcher splits the rows so that each launch's input stays within 2^31 bytes)
+  return P >= 1 && P <= 4096 && Q >= 1 && Q <= 384 && A >= 1;
+}
+
+namespace {
+constexpr int kPairBlocks = 2048;
+
+__global__ __launch_bounds__(256) void resid_pair_kernel(const float* __restrict__ X,
+                                                         const float* __restrict__ Xh, int64_t n,
+                                                         double* __restrict__ partials) {
+  __shared__ double red[2][4];
+  const int tid = threadIdx.x;
+  double r2 = 0.0, x2 = 0.0;
+  const int64_t n4 = n / 4;
+  const float4* X4 = reinterpret_cast<const float4*>(X);
+  const float4* H4 = reinterpret_cast<const float4*>(Xh);
+  for (int64_t g = (int64_t)blockIdx.x * 256 + tid; g < n4; g += (int64_t)gridDim.x * 256) {
+    const float4 x = X4[g], h = H4[g];
+    const double d0 = (double)x.x - h.x, d1 = (double)x.y - h.y, d2 = (double)x.z - h.z,
+                 d3 = (double)x.w - h.w;
+    r2 = fma(d0, d0, fma(d1, d1, fma(d2, d2, fma(d3, d3, r2))));
+    x2 = fma((double)x.x, x.x, fma((double)x.y, x.y, fma((double)x.z, x.z, fma((double)x.w, x.w, x2))));
+  }
+  if (blockIdx.x == 0 && tid < (int)(n - 4 * n4)) {
+    const double x = X[4 * n4 + tid], d = x - (double)Xh[4 * n4 + tid];
+    r2 = fma(d, d, r2);
+    x2 = fma(x, x, x2);
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    r2 += __shfl_xor(r2, off);
+    x2 += __shfl_xor(x2, off);
+  }
+  if ((tid & 63) == 0) {
+    red[0][tid >> 6] = r2;
+    red[1][tid >> 6] = x2;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    partials[2 * blockIdx.x] = (red[0][0] + red[0][1]) + (red[0][2] + red[0][3]);
+    partials[2 * blockIdx.x + 1] = (red[1][0] + red[1][1]) + (red[1][2] + red[1][3]);
+  }
+}
+
+__global__ __launch_bounds__(256) void pair_sum_kernel(const double* partials, int nb, double* out) {
+  __shared__ double red[2][256];
+  const int tid = threadIdx.x;
+  double a = 0.0, b = 0.0;
+  for (int i = tid; i < nb; i += 256) {
+    a += partials[2 * i];
+    b += partials[2 * i + 1];
+  }
+  red[0][tid] = a;
+  red[1][tid] = b;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (tid < s) {
+      red[0][tid] += red[0][tid + s];
+      red[1][tid] += red[1][tid + s];
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    out[0] = red[0][0];
+    out[1] = red[1][0];
+  }
+}
+}  // namespace
+
+int64_t resid_pair_blocks(int64_t n) {
+  return std::max<int64_t>(1, std::min<int64_t>(kPairBlocks, ceil_div(n / 4, 256)));
+}
+
+hipError_t launch_resid_pair_f32(const float* X, const float* Xh, int64_t n, double* partials,
+                                 double* resid2, hipStream_t st) {
+  const int nb = (int)resid_pair_blocks(n);
+  hipLaunchKernelGGL(resid_pair_kernel, dim3(nb), dim3(256), 0, st, X, Xh, n, partials);
+  hipLaunchKernelGGL(pair_sum_kernel, dim3(1), dim3(256), 0, st, partials, nb, resid2);
+  return hipGetLastError();
 }
 
 hipError_t launch_mode_last_mfma_f32(const ModeMfma& m, int out_dt, hipStream_t st) {
@@ -270,14 +352,24 @@ hipError_t launch_mode_last_mfma_f32(const ModeMfma& m, int out_dt, hipStream_t 
   const int groups = (m.P + 32 * kLastMaxPT - 1) / (32 * kLastMaxPT);
   const int64_t Qp = (m.Q + kLastQC - 1) / kLastQC * kLastQC;
   const size_t lds = (size_t)Qp * kLastLdf * sizeof(float);
-  // one resident block per CU (the slice takes most of the LDS), persistent
-  const int64_t tiles = (m.A + 31) / 32;
-  const int64_t per_group = std::max<int64_t>(1, std::min<int64_t>(ceil_div(tiles, kLastWaves), 256 / groups));
-  const dim3 grid((unsigned)per_group, (unsigned)groups);
-  if (out_dt == TK_F64)
-    hipLaunchKernelGGL((mode_last_mfma_kernel<double>), grid, dim3(64 * kLastWaves), lds, st, m);
-  else
-    hipLaunchKernelGGL((mode_last_mfma_kernel<float>), grid, dim3(64 * kLastWaves), lds, st, m);
+  // rows per launch: the input's byte offsets (buffer range) stay below 2^31
+  const int64_t chunk = ((int64_t(1) << 31) - 1) / (m.Q * 4) / 32 * 32;
+  for (int64_t a0 = 0; a0 < m.A; a0 += chunk) {
+    ModeMfma c = m;
+    c.A = std::min<int64_t>(chunk, m.A - a0);
+    c.in = m.in + a0 * m.Q;
+    c.out = out_dt == TK_F64 ? (void*)(static_cast<double*>(m.out) + a0 * m.P)
+                             : (void*)(static_cast<float*>(m.out) + a0 * m.P);
+    // one resident block per CU (the slice takes most of the LDS), persistent
+    const int64_t tiles = (c.A + 31) / 32;
+    const int64_t per_group =
+        std::max<int64_t>(1, std::min<int64_t>(ceil_div(tiles, kLastWaves), 256 / groups));
+    const dim3 grid((unsigned)per_group, (unsigned)groups);
+    if (out_dt == TK_F64)
+      hipLaunchKernelGGL((mode_last_mfma_kernel<double>), grid, dim3(64 * kLastWaves), lds, st, c);
+    else
+      hipLaunchKernelGGL((mode_last_mfma_kernel<float>), grid, dim3(64 * kLastWaves), lds, st, c);
+  }
   return hipGetLastError();
 }
 

@@ -1175,6 +1175,75 @@ tk_status tucker_reconstruct(int32_t order, const int64_t* dims, int32_t fdtype,
     TK_HIP(profile_end(st));
     return TK_OK;
   }
+  // FP32, last factor wider than 64 columns: expand modes 0 .. d-2 (the last
+  // of them into FP32), the last mode on MFMA into X_hat (or a workspace
+  // copy), then the residual over (X, X_hat) in one streaming pass
+  const int64_t A_l = prod(dims, 0, order - 1);
+  const bool mlast = fdtype == TK_F32 && order >= 2 && cols[order - 1] > 64 &&
+                     (!Xref || Xref->dtype == TK_F32) &&
+                     mode_last_mfma_supported(A_l, cols[order - 1], (int32_t)dims[order - 1]);
+  if (mlast) {
+    int64_t shape[TK_MAX_ORDER];
+    for (int k = 0; k < order; ++k) shape[k] = cols[k];
+    int64_t mx = 1;
+    for (int k = 0; k + 2 < order; ++k) {   // FP64 outputs: every expansion but mode d-2's
+      shape[k] = dims[k];
+      mx = std::max(mx, prod(shape, 0, order));
+    }
+    const int64_t N = prod(dims, 0, order);
+    Workspace w;
+    w.base = static_cast<char*>(ws);
+    double* buf[2] = {w.take<double>((size_t)mx), w.take<double>((size_t)mx)};
+    float* T32 = w.take<float>((size_t)(A_l * cols[order - 1]));
+    float* Xh32 = Xhat ? static_cast<float*>(Xhat) : w.take<float>((size_t)N);
+    int64_t smax = 0;
+    for (int k = 0; k < order; ++k) smax = std::max(smax, mode_product_scratch(dims[k], cols[k]));
+    double* mt = w.take<double>((size_t)smax);
+    double* partials = w.take<double>((size_t)2 * resid_pair_blocks(N));
+    if (!ws) {
+      *ws_bytes = w.off;
+      return TK_OK;
+    }
+    if (*ws_bytes < w.off)
+      return set_error(TK_EWORKSPACE, "tucker_reconstruct: workspace %zu < required %zu", *ws_bytes, w.off);
+    hipStream_t st = as_stream(stream);
+    for (int k = 0; k < order; ++k) shape[k] = cols[k];
+    const void* cur = G;
+    int cur_dt = fdtype;
+    for (int k = 0; k + 1 < order; ++k) {
+      const bool to32 = k + 2 == order;
+      ModeProduct mp{};
+      mp.in = cur;
+      mp.A = prod(shape, 0, k);
+      mp.Q = shape[k];
+      mp.B = prod(shape, k + 1, order);
+      mp.P = (int32_t)dims[k];
+      mp.M = F[k];
+      mp.Mt = mt;
+      mp.rs = cols[k];   // M[p][q] = F[p][q]
+      mp.cs = 1;
+      mp.out = to32 ? (void*)T32 : (void*)buf[k & 1];
+      TK_HIP(launch_mode_product(mp, cur_dt, to32 ? TK_F32 : TK_F64, fdtype, st));
+      shape[k] = dims[k];
+      cur = mp.out;
+      cur_dt = to32 ? TK_F32 : TK_F64;
+    }
+    ModeMfma mm{};
+    mm.in = T32;
+    mm.F = static_cast<const float*>(F[order - 1]);
+    mm.A = A_l;
+    mm.Q = cols[order - 1];
+    mm.B = 1;
+    mm.P = (int32_t)dims[order - 1];
+    mm.ftrans = 1;
+    mm.out = Xh32;
+    TK_HIP(profile_begin(st));
+    TK_HIP(launch_mode_last_mfma_f32(mm, TK_F32, st));
+    if (resid2)
+      TK_HIP(launch_resid_pair_f32(static_cast<const float*>(Xref->data), Xh32, N, partials, resid2, st));
+    TK_HIP(profile_end(st));
+    return TK_OK;
+  }
   // expand modes 0 .. d-2 into FP64 intermediates, the last one fused with the residual
   int64_t shape[TK_MAX_ORDER];
   for (int k = 0; k < order; ++k) shape[k] = cols[k];

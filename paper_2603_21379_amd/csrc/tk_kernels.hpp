@@ -277,13 +277,18 @@ struct ModeMfma {
   void* out;            // (A, P, B), FP32 or FP64
   int64_t A, Q, B;
   int32_t P;
-  int32_t pad;
+  int32_t ftrans;       // last-mode kernel: F is P x Q row-major (an expansion by F_k)
 };
 bool mode_mfma_supported(int64_t Q, int64_t B, int32_t P);
 hipError_t launch_mode_mfma_f32(const ModeMfma& m, int out_dt, hipStream_t st);
 // the last mode (B = 1), up to 192 columns: out[a][p] = sum_q in[a][q] F[q][p]
 bool mode_last_mfma_supported(int64_t A, int64_t Q, int32_t P);
 hipError_t launch_mode_last_mfma_f32(const ModeMfma& m, int out_dt, hipStream_t st);
+// sum (X - Xh)^2 and sum X^2 over n FP32 entries into resid2[2] (FP64, fixed
+// order); partials holds 2 resid_pair_blocks(n) doubles
+int64_t resid_pair_blocks(int64_t n);
+hipError_t launch_resid_pair_f32(const float* X, const float* Xh, int64_t n, double* partials,
+                                 double* resid2, hipStream_t st);
 
 // ---------------------------------------------------------------- FP32 fused streaming residual
 // sum (X[a] - F_I T[a] F_J^T)^2 and sum X[a]^2 over the A slabs of an FP32 tensor.

@@ -21,7 +21,8 @@ def _grads_gpu(X, Fs, dtype):
 
 
 @pytest.mark.parametrize("dims,cols", [((4,) * 8, (3,) * 8), ((6, 5, 7), (2, 3, 4)),
-                                       ((9, 70, 33, 5), (4, 5, 6, 3)), ((80, 6, 5), (64, 3, 2))])
+                                       ((9, 70, 33, 5), (4, 5, 6, 3)), ((80, 6, 5), (64, 3, 2)),
+                                       ((80, 6, 5), (70, 3, 2))])
 def test_loss_gradients_match_oracle_fp64(dims, cols):
     rng = np.random.default_rng(1)
     X = rng.standard_normal(dims)
@@ -91,11 +92,11 @@ def test_core_vjp_accumulate_and_partial_outputs():
     np.testing.assert_allclose(Fbar[1].cpu().numpy(), Fb0[1], atol=1e-11 * np.abs(Fb0[1]).max())
 
 
-def test_core_vjp_rejects_rank_above_64():
+def test_core_vjp_rejects_rank_above_192():
     from paper_2603_21379_amd import binding as B
-    dims, cols = (80, 6, 5), (70, 3, 2)
+    dims, cols = (200, 6, 5), (193, 3, 2)
     X = torch.zeros(dims, dtype=torch.float64, device="cuda")
     F = [torch.zeros(n, c, dtype=torch.float64, device="cuda") for n, c in zip(dims, cols)]
     Gb = torch.zeros(cols, dtype=torch.float64, device="cuda")
-    with pytest.raises(B.TkError, match="exceeds 64"):
+    with pytest.raises(B.TkError, match="exceeds 192"):
         B.tucker_core_vjp(X, F, Gb, Xbar=torch.empty_like(X))

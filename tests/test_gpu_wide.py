@@ -98,3 +98,27 @@ def test_wide_factor_core_fp32(dims, cols):
     from test_gpu_tucker import _core_direct
     G, ref = _core_direct(dims, cols, "f32", 72)
     np.testing.assert_allclose(G, ref, rtol=0, atol=2e-6 * np.abs(ref).max())
+
+
+@pytest.mark.parametrize("dims,cols", [
+    ((7, 11, 270), (6, 9, 150)),      # three column groups of the expansion, q tail of 22
+    ((3, 5, 4, 100), (3, 4, 4, 65)),  # the narrowest wide last mode, 60 rows
+])
+def test_wide_last_mode_reconstruct_and_residual_fp32(dims, cols):
+    """FP32 reconstruction with a last factor wider than 64 columns (expanded
+    on MFMA): X_hat against the oracle, and the streamed residual against the
+    FP64 sums over the stored values."""
+    from paper_2603_21379_amd import tucker as T
+    rng = np.random.default_rng(9)
+    G = rng.standard_normal(cols).astype(np.float32)
+    F = [np.linalg.qr(rng.standard_normal((n, c)))[0].astype(np.float32) for n, c in zip(dims, cols)]
+    Gd = torch.from_numpy(G).cuda()
+    Fd = [torch.from_numpy(f).cuda() for f in F]
+    Xh = T.reconstruct(dims, Gd, Fd).double().cpu().numpy()
+    ref = oracle.reconstruct(G.astype(np.float64), [f.astype(np.float64) for f in F])
+    np.testing.assert_allclose(Xh, ref, rtol=0, atol=1e-6 * np.abs(ref).max())
+    X = (ref + 0.01 * rng.standard_normal(dims)).astype(np.float32)
+    r2 = T.residual(torch.from_numpy(X).cuda(), Gd, Fd).cpu().numpy()
+    X64 = X.astype(np.float64)
+    np.testing.assert_allclose(r2[1], np.sum(X64 ** 2), rtol=1e-12)
+    np.testing.assert_allclose(r2[0], np.sum((X64 - ref) ** 2), rtol=1e-4)
