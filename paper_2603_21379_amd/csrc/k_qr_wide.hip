@@ -244,6 +244,7 @@ __global__ __launch_bounds__(kSweepThreads) void wide_sweep_kernel(const WideQR 
   extern __shared__ double A[];
   __shared__ double rc[kWideMaxEll / 2], rs[kWideMaxEll / 2], rt[kWideMaxEll / 2];
   __shared__ int ract[kWideMaxEll / 2], sp[kWideMaxEll / 2], sq[kWideMaxEll / 2];
+  __shared__ int op[kWideMaxEll / 2], oq[kWideMaxEll / 2];   // rowoff of the pair's p and q
   __shared__ int rowoff[kWideMaxEll];   // pk(x, y) = rowoff[x] + y for x <= y
   __shared__ int count;
   const int n = w.ell, np = w.np, half = np / 2, tid = threadIdx.x;
@@ -279,7 +280,6 @@ __global__ __launch_bounds__(kSweepThreads) void wide_sweep_kernel(const WideQR 
   }
   if (tid == 0) count = 0;
   __syncthreads();
-  auto at = [&](int x, int y) -> double& { return x <= y ? A[rowoff[x] + y] : A[rowoff[y] + x]; };
   for (int t = 0; t < np - 1; ++t) {
     if (tid < half) {
       int p, q;
@@ -300,6 +300,8 @@ __global__ __launch_bounds__(kSweepThreads) void wide_sweep_kernel(const WideQR 
       ract[tid] = act;
       sp[tid] = p;
       sq[tid] = q;
+      op[tid] = rowoff[p];
+      oq[tid] = rowoff[q];
       double* ro = w.rot + 2 * ((int64_t)t * half + tid);
       ro[0] = c;
       ro[1] = s;
@@ -310,20 +312,21 @@ __global__ __launch_bounds__(kSweepThreads) void wide_sweep_kernel(const WideQR 
       if (item[j] < 0) continue;
       const int a = item[j] & 255, b = item[j] >> 8;
       if (!ract[a] && !ract[b]) continue;
-      const int pa = sp[a], qa = sq[a];
+      // every address from the pair tables directly (no second LDS lookup)
+      const int pa = sp[a], qa = sq[a], opa = op[a], oqa = oq[a];
       if (a == b) {
-        const int ipq = rowoff[pa] + qa;
+        const int ipq = opa + qa;
         const double apq = A[ipq];
-        A[rowoff[pa] + pa] -= rt[a] * apq;
-        A[rowoff[qa] + qa] += rt[a] * apq;
+        A[opa + pa] -= rt[a] * apq;
+        A[oqa + qa] += rt[a] * apq;
         A[ipq] = 0.0;
         continue;
       }
-      const int pb = sp[b], qb = sq[b];
-      double& r00 = at(pa, pb);
-      double& r01 = at(pa, qb);
-      double& r10 = at(qa, pb);
-      double& r11 = at(qa, qb);
+      const int pb = sp[b], qb = sq[b], opb = op[b], oqb = oq[b];
+      double& r00 = A[pa <= pb ? opa + pb : opb + pa];
+      double& r01 = A[pa <= qb ? opa + qb : oqb + pa];
+      double& r10 = A[qa <= pb ? oqa + pb : opb + qa];
+      double& r11 = A[qa <= qb ? oqa + qb : oqb + qa];
       const double x00 = r00, x01 = r01, x10 = r10, x11 = r11;
       const double ca = rc[a], sa = rs[a], cb = rc[b], sb = rs[b];
       // right factor J_b on the columns, then J_a^T on the rows

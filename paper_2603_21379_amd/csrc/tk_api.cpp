@@ -9,6 +9,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -177,6 +178,30 @@ void plan_wide(Workspace& ws, WideQR& q, double* Z, int64_t m, int ell, bool wst
     q.rot = ws.take<double>((size_t)((np - 1) * (np / 2) * 2));
     q.W = ws.take<double>((size_t)ell * r);
   }
+}
+
+// A second stream per device (default priority) and its fork / join events,
+// created on first use and kept for the process: the wide QR path, mostly
+// single-workgroup launches, overlaps the batched narrow matrices on it.
+struct SideStream {
+  hipStream_t st = nullptr;
+  hipEvent_t fork = nullptr, join = nullptr;
+};
+tk_status side_stream(SideStream** out) {
+  static std::mutex mu;
+  static SideStream per_dev[64];
+  int dev = 0;
+  TK_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= 64) return set_error(TK_EUNSUPPORTED, "device index %d above 63", dev);
+  std::lock_guard<std::mutex> lock(mu);
+  SideStream& s = per_dev[dev];
+  if (!s.st) {
+    TK_HIP(hipStreamCreateWithFlags(&s.st, hipStreamNonBlocking));
+    TK_HIP(hipEventCreateWithFlags(&s.fork, hipEventDisableTiming));
+    TK_HIP(hipEventCreateWithFlags(&s.join, hipEventDisableTiming));
+  }
+  *out = &s;
+  return TK_OK;
 }
 
 tk_status run_qr(std::vector<QRMat>& mats, int ydtype, int udtype, bool wstep, hipStream_t st) {
@@ -1053,10 +1078,26 @@ tk_status tucker_qr(int32_t nmat, const int64_t* m, const int32_t* ell, double* 
   }
   if (*ws_bytes < w.off)
     return set_error(TK_EWORKSPACE, "tucker_qr: workspace %zu < required %zu", *ws_bytes, w.off);
-  if (tk_status e = run_qr(mats, ydtype, udtype, Y != nullptr, as_stream(stream))) return e;
+  hipStream_t st = as_stream(stream);
+  // wide matrices next to narrow ones: the wide path runs on the side stream,
+  // forked from and joined back into the caller's stream (the two touch
+  // disjoint workspace, inputs and outputs)
+  SideStream* side = nullptr;
+  if (!wide.empty() && !mats.empty())
+    if (tk_status e = side_stream(&side)) return e;
+  hipStream_t wst = side ? side->st : st;
+  if (side) {
+    TK_HIP(hipEventRecord(side->fork, st));
+    TK_HIP(hipStreamWaitEvent(wst, side->fork, 0));
+  }
   for (WideQR& q : wide) {
     q.udtype = udtype;
-    TK_HIP(launch_qr_wide(q, ydtype, Y != nullptr, as_stream(stream)));
+    TK_HIP(launch_qr_wide(q, ydtype, Y != nullptr, wst));
+  }
+  if (tk_status e = run_qr(mats, ydtype, udtype, Y != nullptr, st)) return e;
+  if (side) {
+    TK_HIP(hipEventRecord(side->join, wst));
+    TK_HIP(hipStreamWaitEvent(st, side->join, 0));
   }
   return TK_OK;
 }
