@@ -464,15 +464,33 @@ struct VjpPlan {
   double* epart = nullptr;
 };
 
+// Order of the contractions of X in every mode but k: the largest reduction
+// n_j / c_j first (ties: the later mode first), as in the core chain.
+int contract_order(int d, const int64_t* dims, const int32_t* cols, int k, int* order) {
+  bool used[TK_MAX_ORDER] = {};
+  int n = 0;
+  for (int step = 0; step < d - (k >= 0 ? 1 : 0); ++step) {
+    int best = -1;
+    for (int j = d - 1; j >= 0; --j) {
+      if (j == k || used[j]) continue;
+      if (best < 0 || dims[j] * (int64_t)cols[best] > dims[best] * (int64_t)cols[j]) best = j;
+    }
+    used[best] = true;
+    order[n++] = best;
+  }
+  return n;
+}
+
 void plan_vjp(Workspace& ws, int d, const int64_t* dims, const int32_t* cols, VjpPlan& vp) {
   int64_t mx = 1;
   int64_t shape[TK_MAX_ORDER];
-  // contractions of X in every mode but k (last mode first)
+  // contractions of X in every mode but k
   for (int k = 0; k < d; ++k) {
     for (int j = 0; j < d; ++j) shape[j] = dims[j];
-    for (int j = d - 1; j >= 0; --j) {
-      if (j == k) continue;
-      shape[j] = cols[j];
+    int order[TK_MAX_ORDER];
+    const int n = contract_order(d, dims, cols, k, order);
+    for (int i = 0; i < n; ++i) {
+      shape[order[i]] = cols[order[i]];
       mx = std::max(mx, prod(shape, 0, d));
     }
   }
@@ -511,8 +529,10 @@ tk_status contract_all_but(const void* X, int xdt, int d, const int64_t* dims, c
   const void* cur = X;
   int cur_dt = xdt;
   int which = 0;
-  for (int j = d - 1; j >= 0; --j) {
-    if (j == k) continue;
+  int order[TK_MAX_ORDER];
+  const int nsteps = contract_order(d, dims, cols, k, order);
+  for (int i = 0; i < nsteps; ++i) {
+    const int j = order[i];
     ModeProduct mp{};
     mp.in = cur;
     mp.A = prod(shape, 0, j);
