@@ -6,7 +6,11 @@ full read of X).  Default workload: the FP32 256^4 tensor of multilinear
 rank 32 (decay 0.8, relative noise 1e-4), target ranks 32, p = 10,
 s_k = 10 n_k = 2560 sampled fibers per mode.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--config c2|c3-bf16|c3-f16|c3-f32|c1|c4|c5|c6|c7]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--config c2|c3-bf16|c3-f16|c3-f32|c1|c4|c5|c6|c7|c8]
+
+c8 is the same step on an FP32 tensor of uneven modes 5x10x12x112x80x270
+with ranks (5, 8, 10, 28, 50, 150), p = 10, s_k = min(10 n_k, n_notk): the
+last mode's sketch is 160 wide (the wide QR / W-step path).
 
 c5 is Sub-R-RtL-HT on the FP32 18^8 tensor (balanced tree, node ranks 12,
 p = 4, w_S = min(20 n, n_notS) sampled columns per node): node sketches,

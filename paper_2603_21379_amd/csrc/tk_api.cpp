@@ -513,7 +513,7 @@ void plan_vjp(Workspace& ws, int d, const int64_t* dims, const int32_t* cols, Vj
     int64_t rest = 1;
     for (int j = 0; j < d; ++j)
       if (j != k) rest *= std::max<int64_t>(dims[j], cols[j]);
-    umax = std::max(umax, (int64_t)unfold_gemm_splits(dims[k], rest) * dims[k] * cols[k]);
+    umax = std::max(umax, (int64_t)unfold_gemm_splits(dims[k], cols[k], rest) * dims[k] * cols[k]);
   }
   vp.mt = ws.take<double>((size_t)smax);
   vp.upart = ws.take<double>((size_t)umax);
@@ -654,7 +654,7 @@ tk_status unfold_product(const void* A, int adt, const void* B, int bdt, int d, 
   g.post = post;
   g.n = (int32_t)dims[k];
   g.c = cols[k];
-  g.splits = unfold_gemm_splits(dims[k], pre * post);
+  g.splits = unfold_gemm_splits(dims[k], cols[k], pre * post);
   g.accumulate = accumulate ? 1 : 0;
   TK_HIP(launch_unfold_gemm(g, adt, bdt, out_dt, st));
   return TK_OK;
@@ -1494,7 +1494,7 @@ tk_status htucker_decompose(const tk_tensor* X, const tk_tree* tree, const int32
     Mt[t] = w.take<double>((size_t)std::max<int64_t>(nc[t], nS[t]) * ell);
     dmt = std::max(dmt, mode_product_scratch(ell, nc[t]));
     dmt = std::max(dmt, mode_product_scratch(ell, nS[t]));
-    dup = std::max<int64_t>(dup, (int64_t)unfold_gemm_splits(ell, nc[t]) * ell * ell);
+    dup = std::max<int64_t>(dup, (int64_t)unfold_gemm_splits(ell, ell, nc[t]) * ell * ell);
   }
   double* dense_mt = w.take<double>((size_t)dmt);
   double* dense_up = w.take<double>((size_t)dup);
@@ -1593,7 +1593,7 @@ tk_status htucker_decompose(const tk_tensor* X, const tk_tree* tree, const int32
     g.partials = dense_up;
     g.n = ell;
     g.c = ell;
-    g.splits = unfold_gemm_splits(ell, nc[t]);
+    g.splits = unfold_gemm_splits(ell, ell, nc[t]);
     g.accumulate = 0;
     TK_HIP(launch_unfold_gemm(g, TK_F64, TK_F64, TK_F64, st));
   }
@@ -1823,8 +1823,8 @@ tk_status htucker_reconstruct_vjp(int32_t order, const int64_t* dims, const tk_t
     const int l = tree->left[t], r = tree->right[t];
     const int64_t nl = f.nS[l], nr = f.nS[r];
     e2 = std::max<int64_t>(e2, (int64_t)rank[l] * nr * rank[t]);
-    up = std::max<int64_t>(up, (int64_t)unfold_gemm_splits(nl, nr * rank[t]) * nl * rank[l]);
-    up = std::max<int64_t>(up, (int64_t)unfold_gemm_splits(nr, nl * rank[t]) * nr * rank[r]);
+    up = std::max<int64_t>(up, (int64_t)unfold_gemm_splits(nl, rank[l], nr * rank[t]) * nl * rank[l]);
+    up = std::max<int64_t>(up, (int64_t)unfold_gemm_splits(nr, rank[r], nl * rank[t]) * nr * rank[r]);
     mt = std::max(mt, mode_product_scratch(rank[r], nr));
     mt = std::max(mt, mode_product_scratch(rank[l], nl));
   }
@@ -1881,7 +1881,7 @@ tk_status htucker_reconstruct_vjp(int32_t order, const int64_t* dims, const tk_t
     g.post = post;
     g.n = (int32_t)n;
     g.c = (int32_t)c;
-    g.splits = unfold_gemm_splits(n, pre * post);
+    g.splits = unfold_gemm_splits(n, c, pre * post);
     g.accumulate = 0;
     return launch_unfold_gemm(g, adt, TK_F64, TK_F64, st);
   };

@@ -383,7 +383,7 @@ struct UnfoldGemm {
   int32_t splits;       // partial sums over ranges of (p, q), summed in order
   int32_t accumulate;
 };
-int32_t unfold_gemm_splits(int64_t n, int64_t pre_post);
+int32_t unfold_gemm_splits(int64_t n, int64_t c, int64_t pre_post);
 hipError_t launch_unfold_gemm(const UnfoldGemm& g, int a_dt, int b_dt, int out_dt, hipStream_t st);
 
 // ---------------------------------------------------------------- conversions

@@ -22,7 +22,7 @@ def _grads_gpu(X, Fs, dtype):
 
 @pytest.mark.parametrize("dims,cols", [((4,) * 8, (3,) * 8), ((6, 5, 7), (2, 3, 4)),
                                        ((9, 70, 33, 5), (4, 5, 6, 3)), ((80, 6, 5), (64, 3, 2)),
-                                       ((80, 6, 5), (70, 3, 2))])
+                                       ((80, 6, 5), (70, 3, 2)), ((5, 6, 80), (2, 3, 70))])
 def test_loss_gradients_match_oracle_fp64(dims, cols):
     rng = np.random.default_rng(1)
     X = rng.standard_normal(dims)
