@@ -52,7 +52,7 @@ __global__ __launch_bounds__(256) void unfold_gemm_kernel(const UnfoldGemm g) {
   if (tid < cc) out[tid] = (red[tid] + red[CMAX + tid]) + (red[2 * CMAX + tid] + red[3 * CMAX + tid]);
 }
 
-// The same product for wide outputs (n >= 64, c > 64), where re-reading B for
+// The same product for wide outputs (n >= 64, c > 32), where re-reading B for
 // every row i would dominate: 64 x 64 output tiles, (p, q) in chunks of 16
 // staged through LDS (A as [k][i], B as [k][a]), 4 x 4 outputs per thread,
 // the (p, q) range split over blocks into the same fixed-order partials.
@@ -127,7 +127,7 @@ __global__ __launch_bounds__(256) void unfold_tiled_kernel(const UnfoldGemm g) {
   }
 }
 
-bool tiled(int64_t n, int64_t c) { return n >= 64 && c > 64; }
+bool tiled(int64_t n, int64_t c) { return n >= 64 && c > 32; }
 
 template <typename TO>
 __global__ void unfold_sum_kernel(const UnfoldGemm g) {
@@ -172,9 +172,15 @@ hipError_t by_b(const UnfoldGemm& g, int b_dt, int out_dt, hipStream_t st) {
 }  // namespace
 
 int32_t unfold_gemm_splits(int64_t n, int64_t c, int64_t pre_post) {
-  // the tiled form: about 16K (p, q) per block (non-decreasing in pre_post,
-  // so a plan sized with a larger pre_post holds the partials)
-  if (tiled(n, c)) return (int32_t)std::max<int64_t>(1, std::min<int64_t>(256, ceil_div(pre_post, 16384)));
+  // the tiled form: about 16K (p, q) per block, and at least about 512 blocks
+  // while every split keeps 16 (p, q); non-decreasing in pre_post, so a plan
+  // sized with a larger pre_post holds the partials
+  if (tiled(n, c)) {
+    const int64_t tiles = ceil_div(n, 64) * ceil_div(c, 64);
+    int64_t sp = std::max<int64_t>(ceil_div(pre_post, 16384), ceil_div(512, tiles));
+    sp = std::min<int64_t>(sp, std::max<int64_t>(1, pre_post / 16));
+    return (int32_t)std::max<int64_t>(1, std::min<int64_t>(256, sp));
+  }
   // enough blocks to cover the chip, each with at least 64K products
   int64_t s = ceil_div(1024, std::max<int64_t>(1, n));
   s = std::min<int64_t>(s, std::max<int64_t>(1, pre_post / 65536));
