@@ -71,6 +71,9 @@ TRAFFIC = {
            os.path.join(ROOT, "paper_2603_21379_amd", "csrc", "k_core_x6.hip")),
     "f32": (os.path.join(ROOT, "profiles", "core_stream_f32_256x4_traffic.txt"),
             os.path.join(ROOT, "paper_2603_21379_amd", "csrc", "k_core_f32.hip")),
+    # the uneven shape's pass over X: the middle-mode MFMA contraction (112 -> 28)
+    "uneven": (os.path.join(ROOT, "profiles", "core_pass_mode_mfma_uneven_5x10x12x112x80x270_traffic.txt"),
+               os.path.join(ROOT, "paper_2603_21379_amd", "csrc", "k_mode_f32.hip")),
 }
 
 
@@ -84,7 +87,7 @@ def measured_traffic(workload_name):
     form that runs, or None when the summary is missing or the kernel source
     changed since the counters were taken."""
     import hashlib
-    path, src = TRAFFIC[core_form()]
+    path, src = TRAFFIC["uneven" if workload_name.startswith("c8_") else core_form()]
     if not os.path.exists(path):
         return None
     kv = {}
