@@ -45,6 +45,12 @@ extern "C" {
 
 #define TK_MAX_ORDER 16
 
+/* Bits of the device `info` words of tucker_qr and htucker_decompose. */
+#define TK_INFO_SHIFT_FIRST 1        /* the first CholeskyQR pass was shifted */
+#define TK_INFO_SHIFT_LATER 2        /* a later CholeskyQR pass was shifted */
+#define TK_INFO_CHOL_FAILED 4        /* a Cholesky failed even with the shift */
+#define TK_INFO_EIG_NOT_CONVERGED 8  /* the W step's eigensolver ran out of sweeps */
+
 typedef enum { TK_F64 = 0, TK_F32 = 1, TK_BF16 = 2, TK_F16 = 3 } tk_dtype;
 
 typedef enum {
@@ -115,7 +121,9 @@ tk_status tucker_sketch_all_modes(const tk_tensor* X, const tk_sketch* sk, doubl
  * follow it, so an exactly rank-deficient Z_i still yields ell_i orthonormal
  * columns (at most four passes).  info[i]: bit 0 = first pass shifted,
  * bit 1 = a later pass shifted, bit 2 = a Cholesky failed even with the
- * shift (the result is then not reliable).  Q_i is unique up to rounding
+ * shift (the result is then not reliable), bit 3 = the W step's Jacobi
+ * eigensolver used up its sweeps with rotations still above the stopping
+ * test (W_i may then be inaccurate).  Q_i is unique up to rounding
  * when Z_i has full column rank (R_ii > 0).
  *   nmat     number of matrices.
  *   m, ell   host arrays [nmat]: rows and columns of Z_i (ell_i <= m_i).
@@ -132,7 +140,11 @@ tk_status tucker_sketch_all_modes(const tk_tensor* X, const tk_sketch* sk, doubl
  *   info     device int32 [nmat] (may be NULL).
  * Widths up to 64 run as one batch (one workgroup per matrix); wider ones,
  * up to 192, one matrix at a time with the same arithmetic rules (their
- * ell x ell matrices packed in LDS and in the workspace).
+ * ell x ell matrices packed in LDS and in the workspace).  When a call has
+ * both, the wide ones run on a library-owned second stream of the current
+ * device, forked from and joined back into `stream` within the call; calls
+ * from several host threads take turns on it (serialised by a lock around
+ * the enqueue), so they stay correct but their wide matrices do not overlap.
  * Errors: TK_EINVAL, TK_EUNSUPPORTED (ell_i > 192), TK_EWORKSPACE, TK_EDEVICE. */
 tk_status tucker_qr(int32_t nmat, const int64_t* m, const int32_t* ell, double* const* Z,
                     const void* const* Y, int32_t ydtype, const int64_t* s, const int32_t* r,

@@ -21,9 +21,10 @@ theory: the paper gives no bound for it).
 from .tensor import unfold, fold, unfold_set, ttm, multi_ttm  # noqa: F401
 from .tucker import (gather_fibers, range_sketch, orth, w_step, sub_r_hosvd,  # noqa: F401
                      core, core_streamed, core_chunked, reconstruct, rel_error, mode_errors,
-                     projector_distance, canonical_signs)
+                     projector_distance, canonical_signs, sq_norm, rel_error_orthonormal)
 from .htucker import (sub_r_rtl_ht, transfer_tensor, root_transfer, ht_full, ht_bases,  # noqa: F401
-                      ht_rel_error, gather_node, kron_cols, ht_full_vjp)
+                      ht_rel_error, gather_node, kron_cols, ht_full_vjp,
+                      ht_residuals_streamed)
 from .grads import core_vjp, reconstruct_vjp, loss_and_grads  # noqa: F401
 from .sampling import philox4x64_10, draw_indices, draw_omega, box_muller  # noqa: F401
 from .brute import (t_hosvd, rtl_ht, unfolding_tail, lower_bound_sq, rhosvd_factor,  # noqa: F401

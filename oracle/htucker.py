@@ -111,6 +111,32 @@ def ht_rel_error(X: np.ndarray, tree, U: dict, B: dict) -> float:
     return float(math.sqrt(np.sum((X - Xh) ** 2) / np.sum(X ** 2)))
 
 
+def ht_residuals_streamed(X: np.ndarray, tree, formats, to64=None, rows: int = 512):
+    """Squared residuals ||X - X_hat_f||_F^2 of several H-Tucker formats
+    f = (leaf bases, transfers) and ||X||_F^2, in one pass over row blocks of
+    the root matricisation X^(Rl) (Section 4, root relation): a block of rows
+    of X_hat_f^(Rl) is (U_Rl^nest[rows] B_R) (U_Rr^nest)^T with nested bases
+    from `ht_bases`.  Blocks are upcast exactly with `to64`.  Returns
+    (list of squared residuals, squared norm)."""
+    to64 = to64 or (lambda a: np.asarray(a, dtype=np.float64))
+    L, R = tree.left[0], tree.right[0]
+    parts = []
+    for U, B in formats:
+        nb = ht_bases(tree, {t: U[t] for t in U if tree.is_leaf(t)}, B)
+        parts.append((nb[L] @ B[0][0], nb[R]))
+    nl = parts[0][0].shape[0]
+    Xm = X.reshape(nl, -1)
+    r2 = [0.0] * len(formats)
+    n2 = 0.0
+    for r0 in range(0, nl, rows):
+        xb = to64(Xm[r0:r0 + rows])
+        n2 += float(np.sum(xb * xb))
+        for f, (Tl, Vr) in enumerate(parts):
+            d = xb - Tl[r0:r0 + rows] @ Vr.T
+            r2[f] += float(np.sum(d * d))
+    return r2, n2
+
+
 def ht_full_vjp(dims, tree, leaf_bases: dict, B: dict, H: np.ndarray):
     """Vector-Jacobian product of the H-Tucker format's full tensor (ht_full)
     with respect to its parameters, the leaf bases and the transfer tensors.

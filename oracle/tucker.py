@@ -137,6 +137,32 @@ def rel_error(X: np.ndarray, G: np.ndarray, Fs, to64=None, slab: int | None = No
     return math.sqrt(num / den)
 
 
+def sq_norm(X: np.ndarray, to64=None, rows: int = 1 << 22) -> float:
+    """||X||_F^2 in FP64, summed over chunks of the flattened tensor (each
+    chunk upcast exactly with `to64`)."""
+    to64 = to64 or (lambda a: np.asarray(a, dtype=np.float64))
+    v = X.reshape(-1)
+    total = 0.0
+    for i in range(0, v.shape[0], rows):
+        c = to64(v[i:i + rows])
+        total += float(np.dot(c, c))
+    return total
+
+
+def rel_error_orthonormal(G: np.ndarray, normX2: float) -> float:
+    """||X - (F_1..F_d) G||_F / ||X||_F for G = (F_1^T..F_d^T) X with every
+    F_k orthonormal (Tucker format, Section 3): X_hat is then the orthogonal
+    projection of X onto the product of the factor ranges, so
+    ||X - X_hat||^2 = ||X||^2 - ||G||^2.  The subtraction cancels about
+    log10(1 / eps^2) digits: with FP64 sums the result carries a relative
+    error of about 1e-15 / eps^2, so it is refused below eps = 1e-4."""
+    g2 = float(np.sum(np.asarray(G, dtype=np.float64) ** 2))
+    e2 = 1.0 - g2 / normX2
+    if e2 < 1e-8:
+        raise ValueError(f"relative error {max(e2, 0.0) ** 0.5:.2e} < 1e-4: use rel_error")
+    return math.sqrt(e2)
+
+
 def mode_errors(X: np.ndarray, Fs):
     """eps_k = ||X^(k) - F_k F_k^T X^(k)||_F / ||X||_F for every mode."""
     X = np.asarray(X, dtype=np.float64)

@@ -21,6 +21,9 @@ TK_F64, TK_F32, TK_BF16, TK_F16 = 0, 1, 2, 3
 TK_MAX_ORDER = 16
 STATUS = {0: "TK_OK", 1: "TK_EINVAL", 2: "TK_EWORKSPACE", 3: "TK_ENOTPD", 4: "TK_EDEVICE",
           5: "TK_EUNSUPPORTED"}
+# bits of the device info words (tucker_qr, htucker_decompose)
+INFO_BITS = {1: "TK_INFO_SHIFT_FIRST", 2: "TK_INFO_SHIFT_LATER", 4: "TK_INFO_CHOL_FAILED",
+             8: "TK_INFO_EIG_NOT_CONVERGED"}
 
 _DT = {torch.float64: TK_F64, torch.float32: TK_F32, torch.bfloat16: TK_BF16,
        torch.float16: TK_F16}

@@ -534,6 +534,7 @@ __global__ __launch_bounds__(256) void mgram_kernel(const S b) {
 // |a_pq| <= u sqrt(a_pp a_qq) can be unreachable in floating point for
 // strongly graded pairs.
 constexpr int kEigThreads = 256;
+constexpr int kEigMaxSweeps = 60;
 
 // IA, IV: A-block and V-pair items per thread, sized by the launcher for the
 // widest sketch of the batch so the per-round loads are straight-line code
@@ -620,7 +621,8 @@ __global__ __launch_bounds__(kEigThreads) void eig_kernel(const S b) {
   // block of those indices lies below every kept diagonal entry (so the kept
   // ones are the r largest eigenvalues); if it does not, full sweeps resume.
   bool skip_dropped = M.r < n;
-  for (int sweep = 0; sweep < 60; ++sweep) {
+  bool converged = false;
+  for (int sweep = 0; sweep < kEigMaxSweeps; ++sweep) {
     bool rotated = false;   // any rotation in this sweep (wave-uniform, equal in every wave)
     uint64_t dropped = 0;   // indices ranked r or later by diagonal (ties: lower index first)
     if (skip_dropped) {
@@ -721,6 +723,7 @@ __global__ __launch_bounds__(kEigThreads) void eig_kernel(const S b) {
       __syncthreads();
     }
     if (!rotated) {
+      converged = true;
       if (dropped == 0) break;
       double top_min = INFINITY, drop_max = -INFINITY;
       if (lane < n) {
@@ -740,9 +743,12 @@ __global__ __launch_bounds__(kEigThreads) void eig_kernel(const S b) {
         drop_max = fmax(drop_max, __shfl_xor(drop_max, off));
       }
       if (drop_max < top_min) break;
+      converged = false;
       skip_dropped = false;
     }
   }
+  // sweeps exhausted with rotations still firing: W may be inaccurate
+  if (!converged && tid == 0 && M.info) *M.info |= 8;
   // rank of each eigenvalue in descending order (ties: lower index first)
   __shared__ int rank_of[E];
   for (int i = tid; i < n; i += kEigThreads) {

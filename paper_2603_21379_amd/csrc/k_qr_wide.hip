@@ -396,6 +396,8 @@ __global__ __launch_bounds__(64) void wide_vrot_kernel(const WideQR w, int sweep
 // W = eigenvectors of the r largest eigenvalues, descending (ties: lower index first)
 __global__ __launch_bounds__(256) void wide_select_kernel(const WideQR w) {
   const int n = w.ell, np = w.np;
+  // no sweep ended without a rotation: W may be inaccurate (info bit 3)
+  if (threadIdx.x == 0 && !w.state[2] && w.info) *w.info |= 8;
   for (int i = threadIdx.x; i < n; i += blockDim.x) {
     const double li = w.Ap[pk(i, i, np)];
     int rank = 0;

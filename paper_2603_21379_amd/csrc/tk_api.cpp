@@ -183,9 +183,12 @@ void plan_wide(Workspace& ws, WideQR& q, double* Z, int64_t m, int ell, bool wst
 // A second stream per device (default priority) and its fork / join events,
 // created on first use and kept for the process: the wide QR path, mostly
 // single-workgroup launches, overlaps the batched narrow matrices on it.
+// Callers hold `mu` from the fork record through the join record, so calls
+// from several host threads never interleave their uses of the two events.
 struct SideStream {
   hipStream_t st = nullptr;
   hipEvent_t fork = nullptr, join = nullptr;
+  std::mutex mu;
 };
 tk_status side_stream(SideStream** out) {
   static std::mutex mu;
@@ -1105,20 +1108,31 @@ tk_status tucker_qr(int32_t nmat, const int64_t* m, const int32_t* ell, double* 
   SideStream* side = nullptr;
   if (!wide.empty() && !mats.empty())
     if (tk_status e = side_stream(&side)) return e;
-  hipStream_t wst = side ? side->st : st;
-  if (side) {
-    TK_HIP(hipEventRecord(side->fork, st));
-    TK_HIP(hipStreamWaitEvent(wst, side->fork, 0));
+  if (!side) {
+    for (WideQR& q : wide) {
+      q.udtype = udtype;
+      TK_HIP(launch_qr_wide(q, ydtype, Y != nullptr, st));
+    }
+    return run_qr(mats, ydtype, udtype, Y != nullptr, st);
   }
+  std::lock_guard<std::mutex> lock(side->mu);
+  TK_HIP(hipEventRecord(side->fork, st));
+  TK_HIP(hipStreamWaitEvent(side->st, side->fork, 0));
+  tk_status e = TK_OK;
   for (WideQR& q : wide) {
     q.udtype = udtype;
-    TK_HIP(launch_qr_wide(q, ydtype, Y != nullptr, wst));
+    if (hipError_t he = launch_qr_wide(q, ydtype, Y != nullptr, side->st)) {
+      e = set_error(TK_EDEVICE, "tucker_qr: wide QR launch failed: %s", hipGetErrorString(he));
+      break;
+    }
   }
-  if (tk_status e = run_qr(mats, ydtype, udtype, Y != nullptr, st)) return e;
-  if (side) {
-    TK_HIP(hipEventRecord(side->join, wst));
-    TK_HIP(hipStreamWaitEvent(st, side->join, 0));
-  }
+  if (e == TK_OK) e = run_qr(mats, ydtype, udtype, Y != nullptr, st);
+  // joined on every path, so the caller's stream (possibly capturing) is
+  // never left forked
+  const hipError_t j1 = hipEventRecord(side->join, side->st);
+  const hipError_t j2 = j1 == hipSuccess ? hipStreamWaitEvent(st, side->join, 0) : j1;
+  if (e != TK_OK) return e;
+  TK_HIP(j2);
   return TK_OK;
 }
 
@@ -2088,8 +2102,8 @@ tk_status tucker_batch_autotune(tk_batch_plan* plan, void* stream, char* report,
         bc = c;
       }
     }
-  hipEventDestroy(e0);
-  hipEventDestroy(e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
   if (status) return status;
   if (tk_status s = batch_set_schedule(P, variants[bv][0], variants[bv][1], chunk_sizes[bc], st)) return s;
   char line[160];

@@ -63,7 +63,7 @@ C4_COUNT = 512
 C4_CFG_ID = 4
 
 # uneven modes with the shape of the paper's meteorological tensor (Section
-# 4.1.2) and its truncation ranks; synthetic values.  The core decays slowly
+# 3.3.2) and its truncation ranks; synthetic values.  The core decays slowly
 # (0.97 per index) so that the 150th direction of the last mode stays far
 # above the noise; ell = min(r + p, n) caps the first mode at n_1 = 5 and
 # widens the last to 160

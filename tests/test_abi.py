@@ -193,6 +193,15 @@ def test_status_codes_in_header_match_binding():
         assert re.search(rf"\b{name}\s*=\s*{code}\b", text), name
 
 
+def test_info_bits_in_header_match_binding():
+    """Every bit of the device info words, the eigensolver's non-convergence
+    bit included, is defined in the header with the binding's value."""
+    text = open(HEADER).read()
+    for bit, name in B.INFO_BITS.items():
+        assert re.search(rf"#define\s+{name}\s+{bit}\b", text), name
+    assert sorted(B.INFO_BITS) == [1, 2, 4, 8]
+
+
 def test_batch_plan_validation_and_query():
     L = B.lib()
     f = L.tucker_batch_plan_create

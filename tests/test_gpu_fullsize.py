@@ -9,10 +9,18 @@ benchmark times, on outputs the FP64 oracle can compute at that size:
 * for H-Tucker, every transfer tensor and the root transfer (row blocks of
   the root contraction summed in FP64).
 
-The end-to-end error gate runs at the oracle-sized versions of the same
-workloads (test_gpu_tucker, test_gpu_htucker, test_gpu_batch)."""
+* the error half of the metric: the device residual pass over the whole
+  tensor against the oracle's end-to-end relative error (its own factors
+  and core, or its own H-Tucker format), and the device residual pass at its
+  timed slab shape against the oracle's explicit residual on the same
+  factors (a sample of leading slabs).
+
+Each step prints a line to stderr so that a long host computation is seen
+to progress."""
 import gc
 import math
+import sys
+import time
 
 import numpy as np
 import pytest
@@ -54,6 +62,16 @@ def _check_mode(Xh, k, s, Y_gpu, U_gpu, r, dtype):
     _, U_or, sv = oracle.w_step(Q_or, Y_or, r)
     d = oracle.projector_distance(U_gpu, U_or)
     assert d < _factor_tol(sv, r, U_EFF[dtype]), (k, d)
+    return U_or
+
+
+def _say(msg):
+    sys.__stderr__.write(f"[fullsize] {time.strftime('%H:%M:%S')} {msg}\n")
+    sys.__stderr__.flush()
+
+
+# gate of |eps_gpu - eps_oracle| / eps_oracle per tensor dtype
+EPS_TOL = {"f64": 1e-10, "f32": 1e-5, "bf16": 3e-3, "f16": 3e-3}
 
 
 def _release():
@@ -76,14 +94,45 @@ def test_fullsize_tucker(which, dtype, ctol):
     res = T.sub_r_hosvd(X, ranks, skd)
     torch.cuda.synchronize()
     assert int(res.info.abs().sum()) == 0
+    # the device residual pass over the whole tensor, as the benchmark runs it
+    eps_gpu = T.rel_error(X, res.G, res.F)
+    # and over the first `ns` slabs of mode 0 (the kernel's timed slab shape;
+    # ns >= c_0 so that the restricted first factor is a valid factor)
+    ns = ranks[0]
+    F0s = res.F[0][:ns].contiguous()
+    r2s = T.residual(X[:ns], res.G, [F0s] + list(res.F[1:])).cpu().numpy()
+    _say(f"{which} {dtype}: device eps {eps_gpu:.6e}")
     F = [f.double().cpu().numpy() for f in res.F]
+    U_or = []
     for k in range(len(dims)):
-        _check_mode(inp.X, k, sk[k], _y_host(res.Y[k], dtype), F[k], ranks[k], dtype)
+        U_or.append(_check_mode(inp.X, k, sk[k], _y_host(res.Y[k], dtype), F[k], ranks[k], dtype))
     G = res.G.double().cpu().numpy()
-    del X, res
+    del X, res, F0s
     _release()
-    G_chk = oracle.core_chunked(inp.X, F, to64=lambda a: synthgen.to_f64(a, dtype))
+    to64 = (lambda a: synthgen.to_f64(a, dtype))
+    _say("factors checked; oracle core on the GPU's factors")
+    G_chk = oracle.core_chunked(inp.X, F, to64=to64)
     np.testing.assert_allclose(G, G_chk, rtol=0, atol=ctol * np.abs(G_chk).max())
+    # the residual kernel on the sample slabs against the oracle's explicit
+    # residual with the same (GPU) core and factors
+    _say("oracle residual of the sample slabs")
+    Xs = inp.X[:ns]
+    Fs = [F[0][:ns]] + F[1:]
+    num = den = 0.0
+    for i in range(ns):
+        xs = to64(Xs[i:i + 1])
+        xh = oracle.reconstruct(G, [Fs[0][i:i + 1]] + Fs[1:])
+        num += float(np.sum((xs - xh) ** 2))
+        den += float(np.sum(xs ** 2))
+    assert abs(r2s[1] - den) <= 1e-12 * den
+    assert abs(math.sqrt(r2s[0] / r2s[1]) - math.sqrt(num / den)) <= EPS_TOL[dtype] * math.sqrt(num / den)
+    # end to end: the oracle's own factors and core (orthonormal FP64 factors,
+    # so ||X - X_hat||^2 = ||X||^2 - ||G||^2)
+    _say("oracle core on its own factors")
+    G_or = oracle.core_chunked(inp.X, U_or, to64=to64)
+    eps_or = oracle.rel_error_orthonormal(G_or, oracle.sq_norm(inp.X, to64=to64))
+    _say(f"eps_gpu {eps_gpu:.6e} eps_oracle {eps_or:.6e} rel {abs(eps_gpu - eps_or) / eps_or:.2e}")
+    assert abs(eps_gpu - eps_or) <= EPS_TOL[dtype] * eps_or
 
 
 def test_fullsize_batch_512():
@@ -146,25 +195,47 @@ def test_fullsize_htucker_18x8():
     res = T.sub_r_rtl_ht(X, tr, ranks, {t: dsk[t - 1] for t in range(1, tr.num_nodes)})
     torch.cuda.synchronize()
     assert int(res.info.abs().sum()) == 0
+    leaves = {t: res.U[t] for t in res.U if tr.is_leaf(t)}
+    # the device residual pass of the format over the whole tensor
+    eps_gpu = T.ht_rel_error(X, tr, ranks, leaves, res.B)
+    _say(f"c5: device eps {eps_gpu:.6e}")
     U = {t: u.cpu().numpy() for t, u in res.U.items()}
     Bg = {t: b.cpu().numpy() for t, b in res.B.items()}
-    del X, res, dsk
+    del X, res, dsk, leaves
     _release()
+    U_or, B_or = {}, {}
     for t in range(1, tr.num_nodes):
         Y_or = oracle.gather_node(inp.X, tr, t, sk[t].idx)
         Q_or = oracle.orth(oracle.range_sketch(Y_or, sk[t].omega.astype(np.float64)))
-        _, U_or, sv = oracle.w_step(Q_or, Y_or, ranks[t])
-        d = oracle.projector_distance(U[t], U_or)
+        _, U_or[t], sv = oracle.w_step(Q_or, Y_or, ranks[t])
+        d = oracle.projector_distance(U[t], U_or[t])
         assert d < _factor_tol(sv, ranks[t], U_EFF["f64"]), (t, d)
         if not tr.is_leaf(t):
             B_chk = oracle.transfer_tensor(U[t], U[tr.left[t]], U[tr.right[t]])
             np.testing.assert_allclose(Bg[t], B_chk, rtol=0, atol=1e-12 * np.abs(B_chk).max())
-    # root: U_l^T X^(l) U_r, summed over blocks of rows of X^(l)
+    for t in range(1, tr.num_nodes):
+        if not tr.is_leaf(t):
+            B_or[t] = oracle.transfer_tensor(U_or[t], U_or[tr.left[t]], U_or[tr.right[t]])
+    _say("c5: bases checked; root transfers over row blocks")
+    # roots: U_l^T X^(l) U_r, summed over blocks of rows of X^(l), with the
+    # GPU's bases (checks the device root pass) and the oracle's
     L, R = tr.left[0], tr.right[0]
     nl = U[L].shape[0]
     Xm = inp.X.reshape(nl, -1)
-    B_chk = None
+    B_chk = B_or[0] = None
     for r0 in range(0, nl, 2048):
         part = oracle.root_transfer(Xm[r0:r0 + 2048], tr, U[L][r0:r0 + 2048], U[R])
         B_chk = part if B_chk is None else B_chk + part
+        part = oracle.root_transfer(Xm[r0:r0 + 2048], tr, U_or[L][r0:r0 + 2048], U_or[R])
+        B_or[0] = part if B_or[0] is None else B_or[0] + part
     np.testing.assert_allclose(Bg[0], B_chk, rtol=0, atol=1e-11 * np.abs(B_chk).max())
+    # the error half: the device residual against the oracle's residual of
+    # the GPU's own format (checks the residual pass) and of the oracle's
+    # format (end to end), in one streamed pass
+    _say("c5: oracle residuals over row blocks")
+    (r2_gpu_fmt, r2_or), n2 = oracle.ht_residuals_streamed(inp.X, tr, [(U, Bg), (U_or, B_or)])
+    eps_host = math.sqrt(r2_gpu_fmt / n2)
+    eps_or = math.sqrt(r2_or / n2)
+    _say(f"c5: eps_gpu {eps_gpu:.6e} host {eps_host:.6e} oracle {eps_or:.6e}")
+    assert abs(eps_gpu - eps_host) <= 1e-12 * eps_host
+    assert abs(eps_gpu - eps_or) <= EPS_TOL["f32"] * eps_or

@@ -11,6 +11,7 @@ import numpy as np
 import pytest
 import torch
 
+import ht_parity
 import oracle
 import synthgen
 
@@ -44,12 +45,12 @@ def _run(order, dtype, n=10, rank=5, p=3, alpha=2):
     U_or, B_or, _ = oracle.sub_r_rtl_ht(X64, tr, ranks, sk)
     U = {t: u.cpu().numpy() for t, u in res.U.items()}
     Bg = {t: b.cpu().numpy() for t, b in res.B.items()}
-    return tr, dense, U, Bg, U_or, B_or, X64, res.info.cpu().numpy()
+    return tr, dense, U, Bg, U_or, B_or, X64, res.info.cpu().numpy(), ranks, sk
 
 
 @pytest.mark.parametrize("order,expect", [(4, [1, 2]), (5, [1]), (6, [1, 2])])
 def test_dense_root_children_f64(order, expect):
-    tr, dense, U, Bg, U_or, B_or, X64, info = _run(order, "f64")
+    tr, dense, U, Bg, U_or, B_or, X64, info, ranks, sk = _run(order, "f64")
     assert dense == expect
     for t in U_or:
         assert oracle.projector_distance(U[t], U_or[t]) < 1e-9, t
@@ -57,14 +58,16 @@ def test_dense_root_children_f64(order, expect):
         np.testing.assert_allclose(Bg[t], B_or[t], atol=1e-9 * max(1.0, np.abs(B_or[t]).max()))
     eps_or = oracle.ht_rel_error(X64, tr, U_or, B_or)
     eps = oracle.ht_rel_error(X64, tr, U, Bg)
-    assert abs(eps - eps_or) <= 1e-8 * eps_or
+    spread = ht_parity.eps_spread(X64, tr, ranks, sk, eps_or)
+    assert abs(eps - eps_or) <= ht_parity.eps_gate(eps_or, spread, 1e-10)
 
 
 def test_dense_root_children_f32():
-    tr, dense, U, Bg, U_or, B_or, X64, info = _run(6, "f32")
+    tr, dense, U, Bg, U_or, B_or, X64, info, ranks, sk = _run(6, "f32")
     assert dense == [1, 2]
     eps_or = oracle.ht_rel_error(X64, tr, U_or, B_or)
     eps = oracle.ht_rel_error(X64, tr, U, Bg)
-    assert abs(eps - eps_or) <= 1e-4 * eps_or
+    spread = ht_parity.eps_spread(X64, tr, ranks, sk, eps_or)
+    assert abs(eps - eps_or) <= ht_parity.eps_gate(eps_or, spread, 1e-5)
     for t in U_or:
         assert oracle.projector_distance(U[t], U_or[t]) < 1e-5, t

@@ -9,6 +9,7 @@ import numpy as np
 import pytest
 import torch
 
+import ht_parity
 import oracle
 import synthgen
 
@@ -138,23 +139,31 @@ def _inverse_norm_run(order, dtype, n=15, rank=7, p=4, walpha=20):
     U_gpu = {t: u.cpu().numpy() for t, u in res.U.items()}
     B_gpu = {t: b.cpu().numpy() for t, b in res.B.items()}
     eps_gpu_format_on_host = oracle.ht_rel_error(X64, tr, U_gpu, B_gpu)
-    return eps_gpu, eps_gpu_format_on_host, eps_or
+    spread = ht_parity.eps_spread(X64, tr, ranks, sk, eps_or)
+    return eps_gpu, eps_gpu_format_on_host, eps_or, spread
 
 
 @pytest.mark.parametrize("order", [4, 5, 6])
 def test_inverse_norm_workload_f64(order):
-    eps_gpu, eps_host, eps_or = _inverse_norm_run(order, "f64")
-    # the device residual of the device format equals the host evaluation of it
-    assert abs(eps_gpu - eps_host) <= 1e-9 * eps_host
-    # and the device decomposition matches the oracle's
-    assert abs(eps_gpu - eps_or) <= 1e-8 * eps_or
+    eps_gpu, eps_host, eps_or, spread = _inverse_norm_run(order, "f64")
+    # the device residual of the device format equals the host evaluation of
+    # it (both FP64 sums, different orders)
+    assert abs(eps_gpu - eps_host) <= 1e-12 * eps_host
+    # and the device decomposition matches the oracle's: 1e-10 of the oracle's
+    # error plus the error's own spread under unit-roundoff perturbations of
+    # the inputs (the node sketches of this tensor are numerically
+    # rank-deficient; at order 6 that spread is about 5e-10 of the error)
+    gate = ht_parity.eps_gate(eps_or, spread, 1e-10)
+    print(f"order {order}: |eps_gpu - eps_or| / eps_or = {abs(eps_gpu - eps_or) / eps_or:.2e}, "
+          f"spread / eps_or = {spread / eps_or:.2e}, gate / eps_or = {gate / eps_or:.2e}")
+    assert abs(eps_gpu - eps_or) <= gate
     assert eps_or < 1e-2
 
 
 def test_inverse_norm_workload_f32():
-    eps_gpu, eps_host, eps_or = _inverse_norm_run(5, "f32")
-    assert abs(eps_gpu - eps_host) <= 1e-7 * eps_host
-    assert abs(eps_gpu - eps_or) <= 1e-3 * eps_or
+    eps_gpu, eps_host, eps_or, spread = _inverse_norm_run(5, "f32")
+    assert abs(eps_gpu - eps_host) <= 1e-12 * eps_host
+    assert abs(eps_gpu - eps_or) <= ht_parity.eps_gate(eps_or, spread, 1e-5)
 
 
 def test_ht_reconstruct_rejects_bad_arguments():

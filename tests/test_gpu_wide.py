@@ -1,7 +1,7 @@
 """Sketch widths above 64 (the wide QR / W-step path) against the oracle.
 
 The uneven shape follows the meteorological tensor of the Tucker experiments
-(Section 4.1.2): six modes from 5 to 270 with truncation ranks up to 150,
+(Section 3.3.2): six modes from 5 to 270 with truncation ranks up to 150,
 where ell = min(r + p, n) is capped at n on the first mode and exceeds 64 on
 the last.  The stand-in keeps the caps with a last mode of ell = 90.
 """

@@ -313,3 +313,27 @@ def test_inverse_norm_workload_values():
     np.testing.assert_array_equal(X, X.transpose(2, 0, 3, 1))
     X5 = synthgen.inverse_norm_tensor(3, 5, "f32")
     assert X5.dtype == np.float32 and X5[2, 2, 2, 2, 2] == np.float32(1.0 / math.sqrt(45.0))
+
+
+def test_ht_residuals_streamed_closed_form():
+    """X = X_hat(format A) + c Z: the streamed residual of format A is exactly
+    c^2 ||Z||^2, that of a second format equals its explicit residual, and
+    the squared norm is ||X||^2; row blocks of 7 leave a ragged tail."""
+    rng = np.random.default_rng(21)
+    dims = (4, 3, 5, 2)
+    tr = synthgen.balanced_tree(4)
+
+    def fmt(seed):
+        g = np.random.default_rng(seed)
+        U = {t: g.standard_normal((dims[tr.first[t]], 2)) for t in range(1, tr.num_nodes) if tr.is_leaf(t)}
+        B = {t: g.standard_normal(((1 if t == 0 else 2), 2, 2)) for t in range(tr.num_nodes)
+             if not tr.is_leaf(t)}
+        return U, B
+
+    A, Bf = fmt(1), fmt(2)
+    Z = rng.standard_normal(dims)
+    X = oracle.ht_full(dims, tr, *A) + 0.3 * Z
+    (rA, rB), n2 = oracle.ht_residuals_streamed(X, tr, [A, Bf], rows=7)
+    assert abs(rA - 0.09 * np.sum(Z ** 2)) <= 1e-12 * np.sum(Z ** 2)
+    assert abs(rB - np.sum((X - oracle.ht_full(dims, tr, *Bf)) ** 2)) <= 1e-12 * rB
+    assert abs(n2 - np.sum(X ** 2)) <= 1e-13 * n2

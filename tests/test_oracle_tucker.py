@@ -273,3 +273,70 @@ def test_projector_distance_large_n_form_matches_dense():
         P = A @ A.T - Bm @ Bm.T
         dense = np.linalg.norm(P) / math.sqrt(2 * c)
         assert abs(oracle.projector_distance(A, Bm) - dense) <= 1e-6 * dense
+
+
+def test_canonical_signs_hand_built_cases():
+    """The sign rule of the W step (the paper leaves singular-vector signs
+    open): each column's largest-magnitude entry is made positive, the first
+    such entry on ties, and an all-zero column keeps +1."""
+    U = np.array([[0.2, 0.5, -0.5, 0.0, 0.1],
+                  [-0.9, -0.5, 0.5, 0.0, -0.1],
+                  [0.3, 0.1, 0.1, 0.0, 0.7]])
+    s = oracle.canonical_signs(U)
+    np.testing.assert_array_equal(s, [-1.0, 1.0, -1.0, 1.0, 1.0])
+    V = U * s
+    for c in range(U.shape[1]):
+        col = V[:, c]
+        if not col.any():
+            continue
+        first = int(np.flatnonzero(np.abs(col) == np.abs(col).max())[0])
+        assert col[first] > 0
+
+
+def test_w_step_applies_the_sign_rule():
+    """U = Q W from the oracle's W step follows the same rule on every column,
+    whatever the sign the SVD routine returned."""
+    rng = np.random.default_rng(7)
+    Q = np.linalg.qr(rng.standard_normal((30, 9)))[0]
+    Y = rng.standard_normal((30, 50))
+    W, U, _ = oracle.w_step(Q, Y, 6)
+    for c in range(6):
+        j = int(np.argmax(np.abs(U[:, c])))
+        assert U[j, c] > 0
+    np.testing.assert_allclose(U, Q @ W, atol=1e-14)
+
+
+def test_sq_norm_chunks_match_loop():
+    """Squared norm over chunks (several chunks and a ragged tail) equals the
+    plain sum of squares over every entry."""
+    rng = np.random.default_rng(11)
+    X = rng.standard_normal((7, 9, 11)).astype(np.float32)
+    ref = sum(float(v) * float(v) for v in X.reshape(-1))
+    assert abs(oracle.sq_norm(X, rows=100) - ref) <= 1e-13 * ref
+
+
+def test_rel_error_orthonormal_closed_form():
+    """X = C x_k F_k + E with E orthogonal to Range(F_1) in mode 1: the
+    projection error is exactly ||E|| / ||X|| (||X||^2 = ||C||^2 + ||E||^2),
+    and the orthogonal-projection form agrees with the explicit residual;
+    below eps = 1e-4 it refuses (the subtraction would cancel)."""
+    rng = np.random.default_rng(12)
+    dims, cols = (9, 8, 7), (3, 4, 2)
+    Fs, comp = [], None
+    for k, (n, c) in enumerate(zip(dims, cols)):
+        Q = np.linalg.qr(rng.standard_normal((n, n)))[0]
+        Fs.append(Q[:, :c])
+        if k == 0:
+            comp = Q[:, c:]
+    C = rng.standard_normal(cols)
+    E = oracle.ttm(1e-2 * rng.standard_normal((comp.shape[1],) + dims[1:]), comp, 0)
+    X = oracle.multi_ttm(C, Fs) + E
+    G = oracle.core(X, Fs)
+    n2 = oracle.sq_norm(X)
+    exact = math.sqrt(np.sum(E ** 2) / (np.sum(C ** 2) + np.sum(E ** 2)))
+    eps = oracle.rel_error_orthonormal(G, n2)
+    assert abs(eps - exact) <= 1e-12 * exact
+    assert abs(eps - oracle.rel_error(X, G, Fs)) <= 1e-12 * exact
+    X0 = oracle.multi_ttm(C, Fs) + 1e-6 * E
+    with pytest.raises(ValueError):
+        oracle.rel_error_orthonormal(oracle.core(X0, Fs), oracle.sq_norm(X0))
