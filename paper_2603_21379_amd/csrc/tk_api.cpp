@@ -292,7 +292,9 @@ void chain_order(const int64_t* dims, const int32_t* cols, int first, CorePlan& 
   }
 }
 
-int core_kind(int xdt, int order, const int64_t* dims, const int32_t* cols) {
+// allow_h3: a third trailing mode may be folded into the pass (the
+// gradient path needs the partial core of exactly two trailing modes)
+int core_kind(int xdt, int order, const int64_t* dims, const int32_t* cols, bool allow_h3 = true) {
   if (fused2_supported(xdt, order, dims, cols)) return kCoreFused2;
   if (order < 3) return kCoreGeneric;
   const int64_t nI = dims[order - 2], nJ = dims[order - 1];
@@ -301,21 +303,17 @@ int core_kind(int xdt, int order, const int64_t* dims, const int32_t* cols) {
   if (A >= (int64_t(1) << 31)) return kCoreGeneric;
   // accumulate the third mode in registers when that still leaves work for
   // every wave of the grid (it shrinks the partial core n_H / c_H times)
-  static const bool h3_off = [] {
-    const char* e = getenv("TKMI_SLAB_H3");
-    return e && atoi(e) == 0;
-  }();
-  if (!h3_off && order >= 4 && cols[order - 3] <= 16 && dims[order - 3] <= 512 &&
+  if (allow_h3 && order >= 4 && cols[order - 3] <= 16 && dims[order - 3] <= 512 &&
       A / dims[order - 3] >= 2048)
     return kCoreSlab3;
   return kCoreSlab2;
 }
 
 tk_status plan_core(Workspace& ws, int xdt, int order, const int64_t* dims, const int32_t* cols,
-                    CorePlan& p) {
+                    CorePlan& p, bool allow_h3 = true) {
   int64_t shape[TK_MAX_ORDER];
   for (int k = 0; k < order; ++k) shape[k] = dims[k];
-  p.kind = core_kind(xdt, order, dims, cols);
+  p.kind = core_kind(xdt, order, dims, cols, allow_h3);
   p.fused_modes = p.kind == kCoreGeneric ? 0 : p.kind == kCoreSlab3 ? 3 : 2;
   int64_t mx = 0;
   const int first = p.fused_modes ? order - 1 - p.fused_modes : order - 1;
@@ -341,13 +339,10 @@ tk_status plan_core(Workspace& ws, int xdt, int order, const int64_t* dims, cons
   return TK_OK;
 }
 
-tk_status run_core(const void* X, int xdt, int order, const int64_t* dims,
-                   const void* const* F, const int32_t* cols, void* G, int fdt, const CorePlan& p,
-                   hipStream_t st) {
-  int64_t shape[TK_MAX_ORDER];
-  for (int k = 0; k < order; ++k) shape[k] = dims[k];
-  const void* cur = X;
-  int cur_dt = xdt;
+// The streaming pass of the core (the trailing modes fused into one read of
+// X, partial core into p.t32); nothing when the plan has no fused pass.
+tk_status run_core_pass(const void* X, int xdt, int order, const int64_t* dims,
+                        const void* const* F, const int32_t* cols, const CorePlan& p, hipStream_t st) {
   if (p.kind == kCoreFused2) {
     // the two trailing modes in one MFMA pass over X
     CoreFused2 f{};
@@ -384,6 +379,18 @@ tk_status run_core(const void* X, int xdt, int order, const int64_t* dims,
     TK_HIP(launch_core_slab(f, xdt, st));
     TK_HIP(profile_end(st));
   }
+  return TK_OK;
+}
+
+// The modes the streaming pass did not contract, from its partial core (or
+// from X itself when there is no fused pass), into G.
+tk_status run_core_rest(const void* X, int xdt, int order, const int64_t* dims,
+                        const void* const* F, const int32_t* cols, void* G, int fdt, const CorePlan& p,
+                        hipStream_t st) {
+  int64_t shape[TK_MAX_ORDER];
+  for (int k = 0; k < order; ++k) shape[k] = dims[k];
+  const void* cur = X;
+  int cur_dt = xdt;
   if (p.fused_modes) {
     for (int k = order - p.fused_modes; k < order; ++k) shape[k] = cols[k];
     cur = p.t32;
@@ -454,6 +461,13 @@ tk_status run_core(const void* X, int xdt, int order, const int64_t* dims,
   return TK_OK;
 }
 
+tk_status run_core(const void* X, int xdt, int order, const int64_t* dims,
+                   const void* const* F, const int32_t* cols, void* G, int fdt, const CorePlan& p,
+                   hipStream_t st) {
+  if (tk_status s = run_core_pass(X, xdt, order, dims, F, cols, p, st)) return s;
+  return run_core_rest(X, xdt, order, dims, F, cols, G, fdt, p, st);
+}
+
 hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
 
 // ------------------------------------------------------------------ VJP chains
@@ -484,11 +498,14 @@ int contract_order(int d, const int64_t* dims, const int32_t* cols, int k, int* 
   return n;
 }
 
-void plan_vjp(Workspace& ws, int d, const int64_t* dims, const int32_t* cols, VjpPlan& vp) {
+// contractions: room for the chains that contract X in every mode but k
+// (the generic factor gradients); without them only the expansions
+void plan_vjp(Workspace& ws, int d, const int64_t* dims, const int32_t* cols, VjpPlan& vp,
+              bool contractions = true) {
   int64_t mx = 1;
   int64_t shape[TK_MAX_ORDER];
   // contractions of X in every mode but k
-  for (int k = 0; k < d; ++k) {
+  for (int k = 0; k < d && contractions; ++k) {
     for (int j = 0; j < d; ++j) shape[j] = dims[j];
     int order[TK_MAX_ORDER];
     const int n = contract_order(d, dims, cols, k, order);
@@ -641,7 +658,7 @@ tk_status expand_full(const void* Gc, int fdt, int d, const int64_t* dims, const
 // dims[k] at mode k and B cols[k] (a_is_big: A's other modes are cols, else dims)
 tk_status unfold_product(const void* A, int adt, const void* B, int bdt, int d, const int64_t* dims,
                          const int32_t* cols, int k, bool a_is_big, void* out, int out_dt,
-                         bool accumulate, const VjpPlan& vp, hipStream_t st) {
+                         bool accumulate, double* upart, hipStream_t st) {
   int64_t pre = 1, post = 1;
   for (int j = 0; j < d; ++j) {
     if (j == k) continue;
@@ -652,7 +669,7 @@ tk_status unfold_product(const void* A, int adt, const void* B, int bdt, int d, 
   g.A = A;
   g.B = B;
   g.out = out;
-  g.partials = vp.upart;
+  g.partials = upart;
   g.pre = pre;
   g.post = post;
   g.n = (int32_t)dims[k];
@@ -663,6 +680,139 @@ tk_status unfold_product(const void* A, int adt, const void* B, int bdt, int d, 
   return TK_OK;
 }
 
+
+// ------------------------------------------------------------------ fused factor gradients
+// FP32 tensors whose two trailing modes take a fused streaming pass: for
+//   Fbar_k (+)= (Y x_{j != k} F_j^T)^(k) (C^(k))^T   (every mode k)
+// the streaming pass of the core gives T = Y x_I F_I^T x_J F_J^T (the two
+// trailing modes), from which the leading modes' gradients are small
+// contractions; the trailing modes' gradients come from one more pass over Y
+// (k_vjp_trail.hip) with K = C x_{j < d-2} F_j.  Y is read twice in all.
+struct GradPlan {
+  CorePlan cp;              // streaming pass of Y (cp.t32 = T) and its chain to a core
+  double* buf[2] = {nullptr, nullptr};   // FP64 chain intermediates
+  double* mt = nullptr;     // mode-product scratch
+  double* upart = nullptr;  // unfolded-product partials
+  float* K32 = nullptr;     // A x c_I x c_J
+  float* partI = nullptr;
+  float* partJ = nullptr;
+  int nblocks = 0;
+};
+
+bool grads_fused_ok(int ydt, int d, const int64_t* dims, const int32_t* cols) {
+  if (ydt != TK_F32 || d < 3) return false;
+  const int kind = core_kind(ydt, d, dims, cols, false);
+  if (kind != kCoreFused2 && kind != kCoreSlab2) return false;
+  return vjp_trail_supported(dims[d - 2], dims[d - 1], cols[d - 2], cols[d - 1], prod(dims, 0, d - 2));
+}
+
+void plan_grads(Workspace& ws, int d, const int64_t* dims, const int32_t* cols, GradPlan& g) {
+  plan_core(ws, TK_F32, d, dims, cols, g.cp, false);
+  const int64_t A = prod(dims, 0, d - 2);
+  const int64_t tsz = A * cols[d - 2] * cols[d - 1];   // |T| = |K|: every chain stays within it
+  g.buf[0] = ws.take<double>((size_t)tsz);
+  g.buf[1] = ws.take<double>((size_t)tsz);
+  int64_t smax = 0, umax = 0, crest = 1;
+  for (int k = 0; k < d; ++k) crest *= cols[k];
+  for (int k = 0; k < d; ++k) {
+    smax = std::max(smax, mode_product_scratch(cols[k], dims[k]));
+    smax = std::max(smax, mode_product_scratch(dims[k], cols[k]));
+    if (k < d - 2)
+      umax = std::max(umax, (int64_t)unfold_gemm_splits(dims[k], cols[k], crest / cols[k]) * dims[k] *
+                                cols[k]);
+  }
+  g.mt = ws.take<double>((size_t)smax);
+  g.upart = ws.take<double>((size_t)std::max<int64_t>(umax, 1));
+  g.K32 = ws.take<float>((size_t)tsz);
+  g.nblocks = vjp_trail_blocks(A);
+  const int64_t nIp = (dims[d - 2] + 31) / 32 * 32, nJp = (dims[d - 1] + 31) / 32 * 32;
+  g.partI = ws.take<float>((size_t)(g.nblocks * nIp * 32));
+  g.partJ = ws.take<float>((size_t)(g.nblocks * nJp * 32));
+}
+
+// after run_core_pass(Y) has written T = g.cp.t32
+tk_status run_grads(const void* Y, int d, const int64_t* dims, const void* const* F, const int32_t* cols,
+                    const void* C, int cdt, void* const* Fbar, int fdt, bool accumulate, const GradPlan& g,
+                    hipStream_t st) {
+  const int I = d - 2, J = d - 1;
+  int64_t shape[TK_MAX_ORDER];
+  // K = C x_{j < d-2} F_j: FP64 intermediates, the last expansion into FP32
+  if (Fbar[I] || Fbar[J]) {
+    for (int j = 0; j < d; ++j) shape[j] = cols[j];
+    const void* cur = C;
+    int cur_dt = cdt;
+    for (int j = 0; j < I; ++j) {
+      const bool last = j == I - 1;
+      ModeProduct mp{};
+      mp.in = cur;
+      mp.A = prod(shape, 0, j);
+      mp.Q = shape[j];
+      mp.B = prod(shape, j + 1, d);
+      mp.P = (int32_t)dims[j];
+      mp.M = F[j];
+      mp.Mt = g.mt;
+      mp.rs = cols[j];   // M[p][q] = F[p][q]
+      mp.cs = 1;
+      mp.out = last ? (void*)g.K32 : (void*)g.buf[j & 1];
+      TK_HIP(launch_mode_product(mp, cur_dt, last ? TK_F32 : TK_F64, TK_F32, st));
+      shape[j] = dims[j];
+      cur = mp.out;
+      cur_dt = last ? TK_F32 : TK_F64;
+    }
+    VjpTrail v{};
+    v.X = static_cast<const float*>(Y);
+    v.K = g.K32;
+    v.FI = static_cast<const float*>(F[I]);
+    v.FJ = static_cast<const float*>(F[J]);
+    v.partI = g.partI;
+    v.partJ = g.partJ;
+    v.A = prod(dims, 0, I);
+    v.nI = (int32_t)dims[I];
+    v.nJ = (int32_t)dims[J];
+    v.cI = cols[I];
+    v.cJ = cols[J];
+    v.nblocks = g.nblocks;
+    TK_HIP(launch_vjp_trail(v, Fbar[I], Fbar[J], fdt, accumulate ? 1 : 0, st));
+  }
+  // leading modes: P_k = T x_{j < d-2, j != k} F_j^T (the largest reduction
+  // first), then Fbar_k (+)= P_k^(k) (C^(k))^T
+  for (int k = 0; k < I; ++k) {
+    if (!Fbar[k]) continue;
+    for (int j = 0; j < d; ++j) shape[j] = j < I ? dims[j] : cols[j];
+    const void* cur = g.cp.t32;
+    int cur_dt = TK_F32;
+    bool used[TK_MAX_ORDER] = {};
+    used[k] = true;
+    int which = 0;
+    for (int step = 0; step + 1 < I; ++step) {
+      int best = -1;
+      for (int j = I - 1; j >= 0; --j) {
+        if (used[j]) continue;
+        if (best < 0 || dims[j] * (int64_t)cols[best] > dims[best] * (int64_t)cols[j]) best = j;
+      }
+      used[best] = true;
+      ModeProduct mp{};
+      mp.in = cur;
+      mp.A = prod(shape, 0, best);
+      mp.Q = shape[best];
+      mp.B = prod(shape, best + 1, d);
+      mp.P = cols[best];
+      mp.M = F[best];
+      mp.Mt = g.mt;
+      mp.rs = 1;   // M[p][q] = F[q][p]
+      mp.cs = cols[best];
+      mp.out = g.buf[which];
+      TK_HIP(launch_mode_product(mp, cur_dt, TK_F64, TK_F32, st));
+      shape[best] = cols[best];
+      cur = g.buf[which];
+      cur_dt = TK_F64;
+      which ^= 1;
+    }
+    if (tk_status s = unfold_product(cur, cur_dt, C, cdt, d, dims, cols, k, true, Fbar[k], fdt,
+                                     accumulate, g.upart, st)) return s;
+  }
+  return TK_OK;
+}
 
 // ------------------------------------------------------------------ batching form
 // All tensors and modes of a batch: the descriptor tables are built once on
@@ -1948,10 +2098,15 @@ tk_status tucker_core_vjp(const tk_tensor* X, const void* const* F, const int32_
   if (!ws_bytes) return set_error(TK_EINVAL, "tucker_core_vjp: ws_bytes is NULL");
   const int d = X->order;
   const int fdt = factor_dtype(X->dtype);
+  bool any_f = false;
+  for (int k = 0; Fbar && k < d; ++k) any_f |= Fbar[k] != nullptr;
+  const bool fused = any_f && grads_fused_ok(X->dtype, d, X->dims, cols);
   Workspace w;
   w.base = static_cast<char*>(ws);
   VjpPlan vp;
-  plan_vjp(w, d, X->dims, cols, vp);
+  plan_vjp(w, d, X->dims, cols, vp, !fused);
+  GradPlan gp;
+  if (fused) plan_grads(w, d, X->dims, cols, gp);
   if (!ws) {
     *ws_bytes = w.off;
     return TK_OK;
@@ -1963,6 +2118,10 @@ tk_status tucker_core_vjp(const tk_tensor* X, const void* const* F, const int32_
   if (Xbar)
     if (tk_status s = expand_full(Gbar, fdt, d, X->dims, F, cols, Xbar, accumulate != 0, vp, st)) return s;
   // Fbar_k (+)= (X x_{j!=k} F_j^T)^(k) (Gbar^(k))^T
+  if (fused) {
+    if (tk_status s = run_core_pass(X->data, X->dtype, d, X->dims, F, cols, gp.cp, st)) return s;
+    return run_grads(X->data, d, X->dims, F, cols, Gbar, fdt, Fbar, fdt, accumulate != 0, gp, st);
+  }
   if (Fbar)
     for (int k = 0; k < d; ++k) {
       if (!Fbar[k]) continue;
@@ -1970,7 +2129,7 @@ tk_status tucker_core_vjp(const tk_tensor* X, const void* const* F, const int32_
       int pdt = 0;
       if (tk_status s = contract_all_but(X->data, X->dtype, d, X->dims, F, cols, k, vp, st, &P, &pdt)) return s;
       if (tk_status s = unfold_product(P, pdt, Gbar, fdt, d, X->dims, cols, k, true, Fbar[k], fdt,
-                                       accumulate != 0, vp, st)) return s;
+                                       accumulate != 0, vp.upart, st)) return s;
     }
   return TK_OK;
 }
@@ -1989,12 +2148,20 @@ tk_status tucker_reconstruct_vjp(int32_t order, const int64_t* dims, int32_t fdt
   if (!G || !H) return set_error(TK_EINVAL, "tucker_reconstruct_vjp: G or H is NULL");
   if (tk_status s = check_factors(order, dims, F, cols, "tucker_reconstruct_vjp")) return s;
   if (!ws_bytes) return set_error(TK_EINVAL, "tucker_reconstruct_vjp: ws_bytes is NULL");
+  bool any_f = false;
+  for (int k = 0; Fbar && k < order; ++k) any_f |= Fbar[k] != nullptr;
+  const bool fused = grads_fused_ok(fdtype, order, dims, cols);
   Workspace w;
   w.base = static_cast<char*>(ws);
   VjpPlan vp;
-  plan_vjp(w, order, dims, cols, vp);
   CorePlan cp;
-  plan_core(w, fdtype, order, dims, cols, cp);
+  GradPlan gp;
+  if (fused) {
+    plan_grads(w, order, dims, cols, gp);
+  } else {
+    plan_vjp(w, order, dims, cols, vp);
+    plan_core(w, fdtype, order, dims, cols, cp);
+  }
   if (!ws) {
     *ws_bytes = w.off;
     return TK_OK;
@@ -2002,6 +2169,15 @@ tk_status tucker_reconstruct_vjp(int32_t order, const int64_t* dims, int32_t fdt
   if (*ws_bytes < w.off)
     return set_error(TK_EWORKSPACE, "tucker_reconstruct_vjp: workspace %zu < required %zu", *ws_bytes, w.off);
   hipStream_t st = as_stream(stream);
+  if (fused) {
+    // one streaming pass of H gives its partial core T: Gbar is T's remaining
+    // contractions, and the factor gradients start from T as well
+    if (tk_status s = run_core_pass(H, fdtype, order, dims, F, cols, gp.cp, st)) return s;
+    if (Gbar)
+      if (tk_status s = run_core_rest(H, fdtype, order, dims, F, cols, Gbar, fdtype, gp.cp, st)) return s;
+    if (!any_f) return TK_OK;
+    return run_grads(H, order, dims, F, cols, G, fdtype, Fbar, fdtype, false, gp, st);
+  }
   // Gbar = H x_1 F_1^T .. x_d F_d^T (the core projection of H)
   if (Gbar)
     if (tk_status s = run_core(H, fdtype, order, dims, F, cols, Gbar, fdtype, cp, st)) return s;
@@ -2016,7 +2192,7 @@ tk_status tucker_reconstruct_vjp(int32_t order, const int64_t* dims, int32_t fdt
       int pdt = 0;
       if (tk_status s = contract_all_but(H, fdtype, order, dims, F, cols, k, vp, st, &P, &pdt)) return s;
       if (tk_status s = unfold_product(P, pdt, G, fdtype, order, dims, cols, k, true, Fbar[k], fdtype,
-                                       false, vp, st)) return s;
+                                       false, vp.upart, st)) return s;
     }
   return TK_OK;
 }

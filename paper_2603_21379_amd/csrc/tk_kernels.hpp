@@ -386,6 +386,28 @@ struct UnfoldGemm {
 int32_t unfold_gemm_splits(int64_t n, int64_t c, int64_t pre_post);
 hipError_t launch_unfold_gemm(const UnfoldGemm& g, int a_dt, int b_dt, int out_dt, hipStream_t st);
 
+// ---------------------------------------------------------------- trailing factor gradients
+// Fbar_J = sum_a Y[a]^T F_I K[a], Fbar_I = sum_a Y[a] F_J K[a]^T over the A
+// slabs Y[a] (n_I x n_J) of an FP32 tensor, K[a] c_I x c_J (one pass on MFMA;
+// per-workgroup partials, then an FP64 sum in workgroup order).
+struct VjpTrail {
+  const float* X;       // A x n_I x n_J
+  const float* K;       // A x c_I x c_J
+  const float* FI;      // n_I x c_I
+  const float* FJ;      // n_J x c_J
+  float* partI;         // [nblocks][n_I padded to 32][32]
+  float* partJ;         // [nblocks][n_J padded to 32][32]
+  int64_t A;
+  int32_t nI, nJ, cI, cJ;
+  int32_t nblocks;
+  int32_t pad;
+};
+bool vjp_trail_supported(int64_t nI, int64_t nJ, int cI, int cJ, int64_t A);
+int vjp_trail_blocks(int64_t A);
+// out_dt: dtype of Fbar (TK_F32 or TK_F64); either Fbar may be NULL
+hipError_t launch_vjp_trail(const VjpTrail& p, void* FbarI, void* FbarJ, int out_dt, int accumulate,
+                            hipStream_t st);
+
 // ---------------------------------------------------------------- conversions
 hipError_t launch_convert(const double* in, void* out, int out_dt, int64_t n, hipStream_t st);
 hipError_t launch_to_f64(const void* in, int in_dt, double* out, int64_t n, hipStream_t st);

@@ -35,8 +35,19 @@ def test_loss_gradients_match_oracle_fp64(dims, cols):
         np.testing.assert_allclose(a, b, rtol=0, atol=1e-11 * np.abs(b).max())
 
 
-def test_loss_gradients_match_oracle_fp32():
-    dims, cols = (16, 20, 30, 132), (5, 6, 12, 20)
+# FP32 shapes: the first four take the fused path (the partial core of the two
+# trailing modes from the streaming pass, their gradients from one MFMA pass
+# over the tensor): ragged row tiles and column blocks, order 3 (one leading
+# mode, no contraction before its unfolded product), the 16x16-tile streaming
+# pass for small trailing modes; the last two keep the generic chains with
+# wide factors (the tiled unfolded product in FP32, one case per layout)
+FP32_CASES = [((16, 20, 30, 132), (5, 6, 12, 20)), ((16, 20, 40, 132), (4, 5, 31, 32)),
+              ((300, 48, 64), (7, 12, 9)), ((20, 30, 24, 36), (3, 4, 8, 12)),
+              ((80, 6, 5), (40, 3, 2)), ((5, 6, 80), (2, 3, 70))]
+
+
+@pytest.mark.parametrize("dims,cols", FP32_CASES)
+def test_loss_gradients_match_oracle_fp32(dims, cols):
     rng = np.random.default_rng(2)
     X = rng.standard_normal(dims).astype(np.float32)
     Fs = [np.linalg.qr(rng.standard_normal((n, c)))[0].astype(np.float32)
@@ -47,6 +58,53 @@ def test_loss_gradients_match_oracle_fp32():
     np.testing.assert_allclose(dX, dX0, rtol=0, atol=1e-5 * np.abs(dX0).max())
     for a, b in zip(dF, dF0):
         np.testing.assert_allclose(a, b, rtol=0, atol=1e-4 * np.abs(b).max())
+
+
+@pytest.mark.parametrize("dims,cols", FP32_CASES[:4])
+def test_vjps_match_oracle_fp32_fused_path(dims, cols):
+    """Both VJPs at arbitrary adjoints (not only the loss's), FP32, on the
+    fused path, against the oracle's closed forms on the same FP32 values."""
+    from paper_2603_21379_amd import binding as B
+    rng = np.random.default_rng(5)
+    X = rng.standard_normal(dims).astype(np.float32)
+    Fs = [rng.standard_normal((n, c)).astype(np.float32) for n, c in zip(dims, cols)]
+    Gb = rng.standard_normal(cols).astype(np.float32)
+    G = rng.standard_normal(cols).astype(np.float32)
+    H = rng.standard_normal(dims).astype(np.float32)
+    X64, F64 = X.astype(np.float64), [f.astype(np.float64) for f in Fs]
+    _, Fc0 = oracle.core_vjp(X64, F64, Gb.astype(np.float64))
+    Gr0, Fr0 = oracle.reconstruct_vjp(G.astype(np.float64), F64, H.astype(np.float64))
+    dev = lambda a: torch.from_numpy(a).cuda()
+    Fd = [dev(f) for f in Fs]
+    Fc = [torch.empty_like(f) for f in Fd]
+    B.tucker_core_vjp(dev(X), Fd, dev(Gb), Fbar=Fc)
+    Fr = [torch.empty_like(f) for f in Fd]
+    Gr = torch.empty_like(dev(G))
+    B.tucker_reconstruct_vjp(list(dims), dev(G), Fd, dev(H), Gbar=Gr, Fbar=Fr)
+    torch.cuda.synchronize()
+    for a, b in zip(Fc, Fc0):
+        np.testing.assert_allclose(a.double().cpu().numpy(), b, rtol=0, atol=2e-5 * np.abs(b).max())
+    for a, b in zip(Fr, Fr0):
+        np.testing.assert_allclose(a.double().cpu().numpy(), b, rtol=0, atol=2e-5 * np.abs(b).max())
+    np.testing.assert_allclose(Gr.double().cpu().numpy(), Gr0, rtol=0, atol=2e-5 * np.abs(Gr0).max())
+
+
+def test_core_vjp_fused_path_accumulates():
+    """accumulate = 1 adds the fused path's factor gradients to the outputs."""
+    from paper_2603_21379_amd import binding as B
+    dims, cols = FP32_CASES[1]
+    rng = np.random.default_rng(6)
+    X = torch.from_numpy(rng.standard_normal(dims).astype(np.float32)).cuda()
+    F = [torch.from_numpy(rng.standard_normal((n, c)).astype(np.float32)).cuda()
+         for n, c in zip(dims, cols)]
+    Gb = torch.from_numpy(rng.standard_normal(cols).astype(np.float32)).cuda()
+    ref = [torch.empty_like(f) for f in F]
+    B.tucker_core_vjp(X, F, Gb, Fbar=ref)
+    acc = [torch.full_like(f, 0.5) for f in F]
+    B.tucker_core_vjp(X, F, Gb, Fbar=acc, accumulate=True)
+    torch.cuda.synchronize()
+    for a, r in zip(acc, ref):
+        torch.testing.assert_close(a, r + 0.5, rtol=1e-6, atol=1e-6 * float(r.abs().max()))
 
 
 def test_gpu_directional_derivative_fd_4pow8():
