@@ -113,6 +113,22 @@ typedef struct {
 tk_status tucker_sketch_all_modes(const tk_tensor* X, const tk_sketch* sk, double* const* Z,
                                   void* const* Y, void* ws, size_t* ws_bytes, void* stream);
 
+/* tucker_sketch_all_modes for callers that cannot allocate device memory or
+ * provide a workspace (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid allocation): same arguments, validation, kernels and
+ * results, with the per-chunk partial sketches kept in a fixed 64 MiB device
+ * array inside the library instead of a caller workspace.  No hipMalloc,
+ * hipFree or other allocation is made.  Each GPU holds its own copy of the
+ * array from the first call on it until the process ends; every call on a
+ * GPU reuses it, so calls that overlap on one GPU (two streams, two host
+ * threads) race and must be ordered by the caller.  The scratch a call needs
+ * is sum over modes of ceil(s_k / 32) n_k ell_k doubles (256-byte aligned per
+ * mode): about 27.5 MB for four modes of n = 256, s = 2560, ell = 42.
+ * Errors: as tucker_sketch_all_modes, and TK_EUNSUPPORTED when the call
+ * needs more than the fixed 64 MiB (the message gives the size). */
+tk_status tucker_sketch_all_modes_noalloc(const tk_tensor* X, const tk_sketch* sk, double* const* Z,
+                                          void* const* Y, void* stream);
+
 /* Thin QR of a batch of sketches and the rank truncation of Algorithm 1
  * (orthonormal basis step, then W_k = dominant r_k left singular vectors of
  * Q_k^T Y_k and U_k = Q_k W_k).  The QR is CholeskyQR2 with an FP64 Gram and

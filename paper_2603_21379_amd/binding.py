@@ -59,7 +59,7 @@ EXPORTS = ("tucker_sketch_all_modes", "tucker_qr", "tucker_core", "tucker_recons
            "tk_version", "tk_profile_enable", "tk_profile_read", "tucker_batch_plan_create",
            "tucker_batch_run", "tucker_batch_autotune", "tucker_batch_plan_destroy",
            "tk_stream_read_blocks", "tk_stream_read", "tucker_draw_sketches",
-           "htucker_reconstruct", "htucker_reconstruct_vjp")
+           "htucker_reconstruct", "htucker_reconstruct_vjp", "tucker_sketch_all_modes_noalloc")
 
 
 def lib():
@@ -108,6 +108,9 @@ def lib():
                                                pp, pp, vp, vp, sz, vp, C.POINTER(C.c_void_p)]
             sig["tucker_batch_run"] = [vp, vp]
             sig["tucker_batch_autotune"] = [vp, vp, C.c_char_p, C.c_size_t]
+            L.tucker_sketch_all_modes_noalloc.argtypes = [C.POINTER(TkTensor), C.POINTER(TkSketch),
+                                                          pp, pp, vp]
+            L.tucker_sketch_all_modes_noalloc.restype = C.c_int
             L.tucker_batch_plan_destroy.argtypes = [vp]
             L.tucker_batch_plan_destroy.restype = None
             for name, args in sig.items():
@@ -223,6 +226,17 @@ def tucker_sketch_all_modes(X, sketches, Z, Y=None, stream=None, ws=None):
     sk = sketch_descs(sketches)
     args = [C.byref(xd), sk, ptr_array(Z), ptr_array(Y) if Y is not None else None]
     return _call("tucker_sketch_all_modes", args, X.device, stream, ws)
+
+
+def tucker_sketch_all_modes_noalloc(X, sketches, Z, Y=None, stream=None):
+    """tucker_sketch_all_modes with the library's fixed scratch array (no
+    workspace, no allocation)."""
+    xd = tensor_desc(X)
+    sk = sketch_descs(sketches)
+    _check("tucker_sketch_all_modes_noalloc",
+           lib().tucker_sketch_all_modes_noalloc(C.byref(xd), sk, ptr_array(Z),
+                                                 ptr_array(Y) if Y is not None else None,
+                                                 _stream(stream)))
 
 
 def tucker_qr(Z, Y=None, r=None, U=None, info=None, stream=None, ws=None):

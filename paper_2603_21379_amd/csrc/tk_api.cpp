@@ -51,6 +51,31 @@ static hipError_t prof_record(hipStream_t st) {
 hipError_t profile_begin(hipStream_t st) { return g_prof_on ? prof_record(st) : hipSuccess; }
 hipError_t profile_end(hipStream_t st) { return g_prof_on ? prof_record(st) : hipSuccess; }
 
+// Scratch of tucker_sketch_all_modes_noalloc (the per-chunk partial sketches
+// of every mode), a fixed device array: each GPU the library runs on holds
+// its own copy until the process ends.  In host code the array's name is
+// not a device address; its address on the current device comes from
+// hipGetSymbolAddress, taken once per device and kept.
+constexpr size_t kNoAllocScratchBytes = size_t(64) << 20;
+__device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+tk_status noalloc_scratch(char** out) {
+  static std::mutex mu;
+  static char* per_dev[64] = {};
+  int dev = 0;
+  TK_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= 64) return set_error(TK_EUNSUPPORTED, "device index %d above 63", dev);
+  std::lock_guard<std::mutex> lock(mu);
+  if (!per_dev[dev]) {
+    void* p = nullptr;
+    TK_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) return set_error(TK_EDEVICE, "hipGetSymbolAddress returned a NULL scratch address");
+    per_dev[dev] = static_cast<char*>(p);
+  }
+  *out = per_dev[dev];
+  return TK_OK;
+}
+
 namespace {
 
 bool valid_dtype(int dt) { return dt == TK_F64 || dt == TK_F32 || dt == TK_BF16 || dt == TK_F16; }
@@ -1198,6 +1223,23 @@ tk_status tucker_sketch_all_modes(const tk_tensor* X, const tk_sketch* sk, doubl
                      *ws_bytes, w.off);
   TK_HIP(launch_sketch(X->dtype, b, as_stream(stream)));
   return TK_OK;
+}
+
+tk_status tucker_sketch_all_modes_noalloc(const tk_tensor* X, const tk_sketch* sk, double* const* Z,
+                                          void* const* Y, void* stream) {
+  // the same validation, plan and kernels as tucker_sketch_all_modes, with
+  // the fixed scratch array as the workspace: nothing is allocated
+  size_t need = 0;
+  if (tk_status s = tucker_sketch_all_modes(X, sk, Z, Y, nullptr, &need, stream)) return s;
+  if (need > kNoAllocScratchBytes)
+    return set_error(TK_EUNSUPPORTED,
+                     "tucker_sketch_all_modes_noalloc: the call needs %zu bytes of scratch, above the "
+                     "fixed %zu (use tucker_sketch_all_modes with a workspace)",
+                     need, kNoAllocScratchBytes);
+  char* base = nullptr;
+  if (tk_status s = noalloc_scratch(&base)) return s;
+  size_t have = kNoAllocScratchBytes;
+  return tucker_sketch_all_modes(X, sk, Z, Y, base, &have, stream);
 }
 
 tk_status tucker_qr(int32_t nmat, const int64_t* m, const int32_t* ell, double* const* Z,

@@ -92,6 +92,21 @@ def test_sketch_validation_and_query():
                   (B.TkSketch * 2)(_sk(200, 193), _sk(100, 5)), _ptrs(2), None)[0] == 5
 
 
+def test_noalloc_sketch_validates_and_rejects_oversize_before_launch():
+    """The no-allocation sketch shares the workspace entry point's validation,
+    and a call whose partial sketches exceed the fixed 64 MiB scratch is
+    refused on the host (nothing enqueued, no device touched)."""
+    L = B.lib()
+    X = _tensor((8, 9, 10))
+    bad = (B.TkSketch * 3)(_sk(4, 5), _sk(30, 5), _sk(40, 5))
+    assert L.tucker_sketch_all_modes_noalloc(C.byref(X), bad, _ptrs(3), None, None) == 1
+    # 33 chunks of 32 fibers x 4096 rows x 64 columns of FP64 partials > 64 MiB
+    big = _tensor((4096, 2048))
+    sks = (B.TkSketch * 2)(_sk(1056, 64), _sk(1056, 64))
+    st = L.tucker_sketch_all_modes_noalloc(C.byref(big), sks, _ptrs(2), None, None)
+    assert st == 5 and "fixed" in L.tk_last_error().decode()
+
+
 def test_workspace_too_small_is_rejected_before_launch():
     X = _tensor((8, 9, 10))
     sks = (B.TkSketch * 3)(_sk(20, 5), _sk(30, 5), _sk(40, 5))
