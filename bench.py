@@ -142,8 +142,10 @@ def device_draw_ms(ncols, ss, ells, fdt, reps=5):
 
 def backward_ms(X, F, G):
     """A7 on the resident tensor: the core VJP (factor gradients for a given
-    core adjoint, X recontracted) and the reconstruction VJP (X standing in
-    for the adjoint of Xhat), each timed with events after a sizing call.
+    core adjoint, X recontracted), the reconstruction VJP (X standing in for
+    the adjoint of Xhat) and the whole backward of the projection loss
+    ||X - R(C(X, F), F)||^2 (gradients of X and of every factor), each timed
+    with events after a sizing call.
     FP32/FP64 tensors only (the backward entry points' dtypes)."""
     import torch
     from paper_2603_21379_amd import binding as B
@@ -153,8 +155,10 @@ def backward_ms(X, F, G):
     Gb = torch.empty_like(G)
     dims = list(X.shape)
     out = {}
+    Xb = torch.empty_like(X)
     for name, fn in (("ms_core_vjp", lambda: B.tucker_core_vjp(X, F, G, Fbar=Fb)),
-                     ("ms_reconstruct_vjp", lambda: B.tucker_reconstruct_vjp(dims, G, F, X, Gbar=Gb, Fbar=Fb))):
+                     ("ms_reconstruct_vjp", lambda: B.tucker_reconstruct_vjp(dims, G, F, X, Gbar=Gb, Fbar=Fb)),
+                     ("ms_projection_loss_vjp", lambda: B.tucker_projection_loss_vjp(X, F, G, Xbar=Xb, Fbar=Fb))):
         fn()
         torch.cuda.synchronize()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -330,7 +334,8 @@ def main():
     back = backward_ms(X, F, G)
     if back:
         log(f"backward (A7): core VJP {back['ms_core_vjp']:.2f} ms, reconstruction VJP "
-            f"{back['ms_reconstruct_vjp']:.2f} ms")
+            f"{back['ms_reconstruct_vjp']:.2f} ms, projection-loss backward "
+            f"{back['ms_projection_loss_vjp']:.2f} ms")
     log(f"sketch operands: device draw {ms_device_draw:.3f} ms; host generation "
         f"{ms_host_sketch:.1f} ms + upload {ms_upload_sketch:.2f} ms")
 

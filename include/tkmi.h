@@ -278,7 +278,11 @@ tk_status htucker_reconstruct_vjp(int32_t order, const int64_t* dims, const tk_t
  *   Fbar_k (+)= (X x_{j!=k} F_j^T)^(k) (Gbar^(k))^T  (n_k x c_k, factor dtype)
  * Xbar or Fbar (or individual Fbar[k]) may be NULL to skip them.  accumulate
  * != 0 adds to the outputs instead of overwriting them.  X is recontracted,
- * no unfolding is stored.  Errors: TK_EINVAL, TK_EWORKSPACE, TK_EDEVICE. */
+ * no unfolding is stored: for FP32 tensors whose two trailing modes take a
+ * fused streaming pass (sizes up to 256, c up to 32) the factor gradients
+ * read X twice (the partial core of the trailing modes, then one matrix-core
+ * pass for their gradients); otherwise once per mode.
+ * Errors: TK_EINVAL, TK_EWORKSPACE, TK_EDEVICE. */
 tk_status tucker_core_vjp(const tk_tensor* X, const void* const* F, const int32_t* cols,
                           const void* Gbar, void* Xbar, void* const* Fbar, int32_t accumulate,
                           void* ws, size_t* ws_bytes, void* stream);
@@ -292,6 +296,27 @@ tk_status tucker_reconstruct_vjp(int32_t order, const int64_t* dims, int32_t fdt
                                  const void* G, const void* const* F, const int32_t* cols,
                                  const void* H, void* Gbar, void* const* Fbar, void* ws,
                                  size_t* ws_bytes, void* stream);
+
+/* Backward of the projection loss L(X, F) = ||X - (X x_k F_k^T) x_k F_k||_F^2
+ * (the core projection followed by the reconstruction, F_k free n_k x c_k
+ * matrices; the two VJPs above chained with the loss's direct term):
+ *   H     = dL/dX_hat = -2 lbar (X - X_hat)
+ *   Gbar  = H x_k F_k^T
+ *   Fbar_k = H^(k) ((G x_{j!=k} F_j)^(k))^T + (X x_{j!=k} F_j^T)^(k) (Gbar^(k))^T
+ *   Xbar  = Gbar x_k F_k + 2 lbar (X - X_hat)
+ *   X      tensor, TK_F64 or TK_F32; F, cols as in tucker_core.
+ *   G      the forward's core X x_k F_k^T (c_1 x .. x c_d, X's dtype).
+ *   lbar   device double: the adjoint of L (NULL = 1).
+ *   Xbar   NULL or a device output shaped like X (X's dtype).  It also holds
+ *          H during the call; without it the workspace holds an X-sized H.
+ *   Fbar   NULL or host array of device outputs n_k x c_k (entries may be NULL).
+ * X is read three times and H is written once and read three times (in Xbar
+ * when given); no other X-sized buffer is used.
+ * Errors: TK_EINVAL, TK_EUNSUPPORTED (other dtypes, c_k > 192), TK_EWORKSPACE,
+ * TK_EDEVICE. */
+tk_status tucker_projection_loss_vjp(const tk_tensor* X, const void* const* F, const int32_t* cols,
+                                     const void* G, const double* lbar, void* Xbar, void* const* Fbar,
+                                     void* ws, size_t* ws_bytes, void* stream);
 
 /* Batching form of Sub-R-HOSVD (Algorithm 1 for many independent tensors at
  * once): every mode of every tensor is sketched, orthonormalised, truncated

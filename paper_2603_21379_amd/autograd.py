@@ -75,10 +75,41 @@ def tucker_reconstruct(G, F):
     return TuckerReconstruct.apply(G, *F)
 
 
+class ProjectionLoss(torch.autograd.Function):
+    """L = ||X - R(C(X, F), F)||_F^2 (C the core projection, R the
+    reconstruction), as an FP64 device scalar.  Forward: tucker_core and the
+    residual pass of tucker_reconstruct; backward: tucker_projection_loss_vjp,
+    which keeps the loss's adjoint in the output gradient of X (no other
+    X-sized buffer)."""
+
+    @staticmethod
+    def forward(ctx, X, *F):
+        X = X.contiguous()
+        F = [f.contiguous() for f in F]
+        G = torch.empty(_cols(F), dtype=B.factor_torch_dtype(X.dtype), device=X.device)
+        B.tucker_core(X, F, G)
+        r2 = torch.empty(2, dtype=torch.float64, device=X.device)
+        B.tucker_reconstruct(list(X.shape), G, F, Xref=X, resid2=r2)
+        ctx.save_for_backward(X, G, *F)
+        return r2[0]
+
+    @staticmethod
+    def backward(ctx, Lbar):
+        X, G, *F = ctx.saved_tensors
+        if Lbar.dtype != torch.float64:
+            Lbar = Lbar.to(torch.float64)
+        Lbar = Lbar.contiguous()
+        Xbar = torch.empty_like(X) if ctx.needs_input_grad[0] else None
+        Fbar = [torch.empty_like(f) if ctx.needs_input_grad[1 + k] else None
+                for k, f in enumerate(F)]
+        if Xbar is not None or any(f is not None for f in Fbar):
+            B.tucker_projection_loss_vjp(X, F, G, Lbar, Xbar=Xbar, Fbar=Fbar)
+        return (Xbar, *Fbar)
+
+
 def projection_loss(X, F):
-    """||X - R(C(X, F), F)||_F^2 with both maps differentiable."""
-    Xh = tucker_reconstruct(tucker_core(X, F), F)
-    return ((X - Xh) ** 2).sum()
+    """||X - R(C(X, F), F)||_F^2 with both maps differentiable (FP64 scalar)."""
+    return ProjectionLoss.apply(X, *F)
 
 
 class HTuckerFull(torch.autograd.Function):

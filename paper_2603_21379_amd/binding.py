@@ -59,7 +59,8 @@ EXPORTS = ("tucker_sketch_all_modes", "tucker_qr", "tucker_core", "tucker_recons
            "tk_version", "tk_profile_enable", "tk_profile_read", "tucker_batch_plan_create",
            "tucker_batch_run", "tucker_batch_autotune", "tucker_batch_plan_destroy",
            "tk_stream_read_blocks", "tk_stream_read", "tucker_draw_sketches",
-           "htucker_reconstruct", "htucker_reconstruct_vjp", "tucker_sketch_all_modes_noalloc")
+           "htucker_reconstruct", "htucker_reconstruct_vjp", "tucker_sketch_all_modes_noalloc",
+           "tucker_projection_loss_vjp")
 
 
 def lib():
@@ -103,6 +104,7 @@ def lib():
                 "tucker_core_vjp": [C.POINTER(TkTensor), pp, i32p, vp, vp, pp, C.c_int32, vp, sz, vp],
                 "tucker_reconstruct_vjp": [C.c_int32, i64p, C.c_int32, vp, pp, i32p, vp, vp, pp, vp,
                                            sz, vp],
+                "tucker_projection_loss_vjp": [C.POINTER(TkTensor), pp, i32p, vp, vp, vp, pp, vp, sz, vp],
             }
             sig["tucker_batch_plan_create"] = [C.c_int32, C.POINTER(TkTensor), i32p, C.POINTER(TkSketch),
                                                pp, pp, vp, vp, sz, vp, C.POINTER(C.c_void_p)]
@@ -343,6 +345,16 @@ def tucker_reconstruct_vjp(dims, G, F, H, Gbar=None, Fbar=None, stream=None, ws=
     args = [d, dd, dtype_code(G.dtype), G.data_ptr(), ptr_array(F), cols, H.data_ptr(),
             ptr(Gbar), ptr_array(Fbar) if Fbar is not None else None]
     return _call("tucker_reconstruct_vjp", args, G.device, stream, ws)
+
+
+def tucker_projection_loss_vjp(X, F, G, lbar=None, Xbar=None, Fbar=None, stream=None, ws=None):
+    """Backward of ||X - (X x_k F_k^T) x_k F_k||^2 given the forward's core G
+    and the loss adjoint lbar (a device FP64 scalar tensor, or None for 1)."""
+    xd = tensor_desc(X)
+    cols = (C.c_int32 * X.dim())(*[f.shape[1] for f in F])
+    args = [C.byref(xd), ptr_array(F), cols, G.data_ptr(), ptr(lbar), ptr(Xbar),
+            ptr_array(Fbar) if Fbar is not None else None]
+    return _call("tucker_projection_loss_vjp", args, X.device, stream, ws)
 
 
 class BatchPlan:

@@ -273,26 +273,32 @@ bool mode_last_mfma_supported(int64_t A, int64_t Q, int32_t P) {
 namespace {
 constexpr int kPairBlocks = 2048;
 
-__global__ __launch_bounds__(256) void resid_pair_kernel(const float* __restrict__ X,
-                                                         const float* __restrict__ Xh, int64_t n,
+// sums of (X - Xh)^2 and X^2 (FP64) per block; with D, also D = s (X - Xh)
+// (D may alias X or Xh: every entry is read and written by one thread)
+__global__ __launch_bounds__(256) void resid_pair_kernel(const float* X, const float* Xh, float* D,
+                                                         const double* scale, double smul, int64_t n,
                                                          double* __restrict__ partials) {
   __shared__ double red[2][4];
   const int tid = threadIdx.x;
+  const float ds = (float)(smul * (scale ? *scale : 1.0));
   double r2 = 0.0, x2 = 0.0;
   const int64_t n4 = n / 4;
   const float4* X4 = reinterpret_cast<const float4*>(X);
   const float4* H4 = reinterpret_cast<const float4*>(Xh);
+  float4* D4 = reinterpret_cast<float4*>(D);
   for (int64_t g = (int64_t)blockIdx.x * 256 + tid; g < n4; g += (int64_t)gridDim.x * 256) {
     const float4 x = X4[g], h = H4[g];
     const double d0 = (double)x.x - h.x, d1 = (double)x.y - h.y, d2 = (double)x.z - h.z,
                  d3 = (double)x.w - h.w;
     r2 = fma(d0, d0, fma(d1, d1, fma(d2, d2, fma(d3, d3, r2))));
     x2 = fma((double)x.x, x.x, fma((double)x.y, x.y, fma((double)x.z, x.z, fma((double)x.w, x.w, x2))));
+    if (D) D4[g] = make_float4(ds * (float)d0, ds * (float)d1, ds * (float)d2, ds * (float)d3);
   }
   if (blockIdx.x == 0 && tid < (int)(n - 4 * n4)) {
     const double x = X[4 * n4 + tid], d = x - (double)Xh[4 * n4 + tid];
     r2 = fma(d, d, r2);
     x2 = fma(x, x, x2);
+    if (D) D[4 * n4 + tid] = ds * (float)d;
   }
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) {
@@ -339,11 +345,16 @@ int64_t resid_pair_blocks(int64_t n) {
   return std::max<int64_t>(1, std::min<int64_t>(kPairBlocks, ceil_div(n / 4, 256)));
 }
 
-hipError_t launch_resid_pair_f32(const float* X, const float* Xh, int64_t n, double* partials,
-                                 double* resid2, hipStream_t st) {
+hipError_t launch_resid_pair_f32(const float* X, const float* Xh, int64_t n, float* D, const double* scale,
+                                 double smul, double* partials, double* resid2, hipStream_t st) {
   const int nb = (int)resid_pair_blocks(n);
-  hipLaunchKernelGGL(resid_pair_kernel, dim3(nb), dim3(256), 0, st, X, Xh, n, partials);
-  hipLaunchKernelGGL(pair_sum_kernel, dim3(1), dim3(256), 0, st, partials, nb, resid2);
+  hipLaunchKernelGGL(resid_pair_kernel, dim3(nb), dim3(256), 0, st, X, Xh, D, scale, smul, n, partials);
+  if (resid2) hipLaunchKernelGGL(pair_sum_kernel, dim3(1), dim3(256), 0, st, partials, nb, resid2);
+  return hipGetLastError();
+}
+
+hipError_t launch_pair_sum(const double* partials, int64_t npairs, double* resid2, hipStream_t st) {
+  hipLaunchKernelGGL(pair_sum_kernel, dim3(1), dim3(256), 0, st, partials, (int)npairs, resid2);
   return hipGetLastError();
 }
 

@@ -17,10 +17,14 @@
 //           K step ks takes registers 8 ks .. 8 ks + 7 as its K slots and the
 //           F_I pieces in LDS follow the same j order, so P feeds stage 2
 //           without moving between lanes.
-//  The output tiles of components c = 2 q, 2 q + 1 line up with a float2 of X
-//  per lane (X[a][i][b0 + 4 n + 2 q .. +1]), loaded coalesced and compared in
-//  FP64.  The next (row tile, component pair) of X is loaded while the
-//  current one is multiplied.
+//  The block is taken as two halves of 64 columns, q = 0, 1: in half q,
+//  lane n owns columns b0 + 64 q + 2 n + {0, 1}, a float2 of X per lane, so
+//  each load covers two 256-byte row segments and a half's cache lines are
+//  used within that half.  The two output tiles of a half line up with that
+//  float2 and are compared in FP64.  The next row tile of X is loaded while
+//  the current one is multiplied.
+//  Optionally D = s (X - X_hat) is written in place of (or beside) X_hat,
+//  with s a device scalar times a constant (the adjoint of ||X - X_hat||^2).
 #include "tk_kernels.hpp"
 
 namespace tk {
@@ -106,6 +110,8 @@ __global__ __launch_bounds__(256, 1) void resid2_f32_kernel(const ResidFused2 p)
   const int64_t nIJ = (int64_t)p.nI * p.nJ;
   const uint32_t slab_bytes = (uint32_t)(nIJ * 4);
   double r2 = 0.0, x2 = 0.0;
+  const bool want_d = p.D != nullptr;
+  const float dscale = (float)(p.smul * (p.scale ? *p.scale : 1.0));
 
   // the A operand of stage 1, T[a][j = l32][j' = 2 k + kh] (k = 0..15), is
   // loaded one slab ahead so the multiplies never wait on it
@@ -131,37 +137,40 @@ __global__ __launch_bounds__(256, 1) void resid2_f32_kernel(const ResidFused2 p)
     const __amdgpu_buffer_rsrc_t rxh = __builtin_amdgcn_make_buffer_rsrc(
         want_xh ? p.Xhat + (int64_t)slab * nIJ : const_cast<float*>(base), (short)0,
         want_xh ? (int)slab_bytes : 0, kRsrcWord3);
+    const __amdgpu_buffer_rsrc_t rd = __builtin_amdgcn_make_buffer_rsrc(
+        want_d ? p.D + (int64_t)slab * nIJ : const_cast<float*>(base), (short)0,
+        want_d ? (int)slab_bytes : 0, kRsrcWord3);
 
 #pragma unroll 1
     for (int h = 0; h < nH; ++h) {
       const int b0 = h * kCols;
-      const int b = b0 + 4 * l32;
-      const bool colok = b < p.nJ;
-      // one component pair q (columns b0 + 4 n + 2 q, + 1) at a time keeps two P
-      // tiles live instead of four; stage 1 costs the same either way
+      // one half q of the block (columns b0 + 64 q + 2 n, + 1 for lane n) at a
+      // time keeps two P tiles live instead of four; stage 1 costs the same
 #pragma unroll 1
       for (int q = 0; q < 2; ++q) {
+        const int b = b0 + 64 * q + 2 * l32;
+        const bool colok = b < p.nJ;
         auto load_unit = [&](int it, floatx2 (&buf)[16]) {
           // lanes past the column tail point far outside the range: they read zero
 #pragma unroll
           for (int v = 0; v < 16; ++v) {
             const int i = it * 32 + 8 * (v >> 2) + 4 * kh + (v & 3);
             const uint32_t off =
-                (colok && i < p.nI) ? (uint32_t)((i * p.nJ + b + 2 * q) * 4) : 0x80000000u;
+                (colok && i < p.nI) ? (uint32_t)((i * p.nJ + b) * 4) : 0x80000000u;
             buf[v] = __builtin_amdgcn_raw_buffer_load_b64(rs, off, 0, 2);
           }
         };
         // the first row tile of X is in flight during stage 1
         floatx2 bufA[16], bufB[16];
         load_unit(0, bufA);
-        // stage 1: P_c[j][n] = sum_j' T[a][j][j'] F_J[b0 + 4 n + c][j'], c = 2 q + {0, 1}
+        // stage 1: P_c[j][n] = sum_j' T[a][j][j'] F_J[b0 + 64 q + 2 n + c][j'], c = 0, 1
         floatx16 P0 = floatx16{}, P1 = floatx16{};
 #pragma unroll
         for (int k = 0; k < 16; ++k) {
           // A = T[a][j = l32][j' = 2 k + kh]
           const int jp = 2 * k + kh;
-          P0 = mfma32(tcur[k], sFJ[(b + 2 * q) * 32 + jp], P0);
-          P1 = mfma32(tcur[k], sFJ[(b + 2 * q + 1) * 32 + jp], P1);
+          P0 = mfma32(tcur[k], sFJ[b * 32 + jp], P0);
+          P1 = mfma32(tcur[k], sFJ[(b + 1) * 32 + jp], P1);
         }
         // P in BF16 pieces as the B operand of stage 2: step ks takes the
         // accumulator registers 8 ks .. 8 ks + 7 (j = 8 (v/4) + 4 kh + v%4)
@@ -214,7 +223,13 @@ __global__ __launch_bounds__(256, 1) void resid2_f32_kernel(const ResidFused2 p)
                 floatx2 w;
                 w[0] = o0[v];
                 w[1] = o1[v];
-                __builtin_amdgcn_raw_buffer_store_b64(w, rxh, (uint32_t)((i * p.nJ + b + 2 * q) * 4), 0, 0);
+                __builtin_amdgcn_raw_buffer_store_b64(w, rxh, (uint32_t)((i * p.nJ + b) * 4), 0, 0);
+              }
+              if (want_d) {
+                floatx2 w;
+                w[0] = dscale * (float)d0;
+                w[1] = dscale * (float)d1;
+                __builtin_amdgcn_raw_buffer_store_b64(w, rd, (uint32_t)((i * p.nJ + b) * 4), 0, 0);
               }
             }
           }

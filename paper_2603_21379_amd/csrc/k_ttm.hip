@@ -277,6 +277,8 @@ __global__ __launch_bounds__(256) void expand_residual_kernel(const ExpandResidu
   const TF* F = static_cast<const TF*>(e.F);
   const TX* X = static_cast<const TX*>(e.X);
   TF* Xh = static_cast<TF*>(e.Xhat);
+  TF* D = static_cast<TF*>(e.D);
+  const double ds = e.smul * (e.scale ? *e.scale : 1.0);
   double r2 = 0.0, x2 = 0.0;
   for (int64_t g = (int64_t)blockIdx.x * 256 + tid; g < total; g += (int64_t)gridDim.x * 256) {
     const int64_t a = g / e.n, i = g - a * e.n;
@@ -290,6 +292,7 @@ __global__ __launch_bounds__(256) void expand_residual_kernel(const ExpandResidu
       const double d = x - v;
       r2 = fma(d, d, r2);
       x2 = fma(x, x, x2);
+      if (D) D[g] = from_double<TF>(ds * d);
     }
   }
   if (!e.partials) return;
@@ -323,6 +326,8 @@ __global__ __launch_bounds__(256) void expand_residual_rows_kernel(const ExpandR
   const TF* F = static_cast<const TF*>(e.F);
   const TX* X = static_cast<const TX*>(e.X);
   TF* Xh = static_cast<TF*>(e.Xhat);
+  TF* D = static_cast<TF*>(e.D);
+  const double ds = e.smul * (e.scale ? *e.scale : 1.0);
   double f[CB];
 #pragma unroll
   for (int k = 0; k < CB; ++k) f[k] = (on && k < e.c) ? to_double(F[(int64_t)i * e.c + k]) : 0.0;
@@ -340,6 +345,7 @@ __global__ __launch_bounds__(256) void expand_residual_rows_kernel(const ExpandR
         const double d = x - v;
         r2 = fma(d, d, r2);
         x2 = fma(x, x, x2);
+        if (D) D[g] = from_double<TF>(ds * d);
       }
     }
   }

@@ -52,7 +52,7 @@ __global__ __launch_bounds__(256) void unfold_gemm_kernel(const UnfoldGemm g) {
   if (tid < cc) out[tid] = (red[tid] + red[CMAX + tid]) + (red[2 * CMAX + tid] + red[3 * CMAX + tid]);
 }
 
-// The same product for wide outputs (n >= 64, c > 32), where re-reading B for
+// The same product for wide outputs (n >= 64, c >= 16), where re-reading B for
 // every row i would dominate: 64 x 64 output tiles, (p, q) in chunks of 16
 // staged through LDS (A as [k][i], B as [k][a]), 4 x 4 outputs per thread,
 // the (p, q) range split over blocks into the same fixed-order partials.
@@ -127,7 +127,7 @@ __global__ __launch_bounds__(256) void unfold_tiled_kernel(const UnfoldGemm g) {
   }
 }
 
-bool tiled(int64_t n, int64_t c) { return n >= 64 && c > 32; }
+bool tiled(int64_t n, int64_t c) { return n >= 64 && c >= 16; }
 
 template <typename TO>
 __global__ void unfold_sum_kernel(const UnfoldGemm g) {

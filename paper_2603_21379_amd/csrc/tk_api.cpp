@@ -750,9 +750,8 @@ void plan_grads(Workspace& ws, int d, const int64_t* dims, const int32_t* cols, 
   g.upart = ws.take<double>((size_t)std::max<int64_t>(umax, 1));
   g.K32 = ws.take<float>((size_t)tsz);
   g.nblocks = vjp_trail_blocks(A);
-  const int64_t nIp = (dims[d - 2] + 31) / 32 * 32, nJp = (dims[d - 1] + 31) / 32 * 32;
-  g.partI = ws.take<float>((size_t)(g.nblocks * nIp * 32));
-  g.partJ = ws.take<float>((size_t)(g.nblocks * nJp * 32));
+  g.partI = ws.take<float>((size_t)(g.nblocks * vjp_trail_rows_i(dims[d - 2]) * 32));
+  g.partJ = ws.take<float>((size_t)(g.nblocks * vjp_trail_rows_j(dims[d - 1]) * 32));
 }
 
 // after run_core_pass(Y) has written T = g.cp.t32
@@ -1350,11 +1349,17 @@ tk_status tucker_core(const tk_tensor* X, const void* const* F, const int32_t* c
                   as_stream(stream));
 }
 
-tk_status tucker_reconstruct(int32_t order, const int64_t* dims, int32_t fdtype, const void* G,
-                             const void* const* F, const int32_t* cols, const tk_tensor* Xref,
-                             void* Xhat, double* resid2, void* ws, size_t* ws_bytes,
-                             void* stream) {
-  clear_error();
+}  // extern "C"
+
+namespace tk {
+namespace {
+// tucker_reconstruct, and with D = smul (*scale or 1) (Xref - X_hat) as one
+// more optional output (D may be Xref itself: every entry is read before it
+// is written, by the same thread)
+tk_status reconstruct_impl(int32_t order, const int64_t* dims, int32_t fdtype, const void* G,
+                           const void* const* F, const int32_t* cols, const tk_tensor* Xref,
+                           void* Xhat, void* D, const double* scale, double smul, double* resid2,
+                           void* ws, size_t* ws_bytes, void* stream) {
   if (order < 1 || order > TK_MAX_ORDER) return set_error(TK_EINVAL, "tucker_reconstruct: bad order %d", order);
   if (!dims) return set_error(TK_EINVAL, "tucker_reconstruct: dims is NULL");
   for (int k = 0; k < order; ++k)
@@ -1363,8 +1368,9 @@ tk_status tucker_reconstruct(int32_t order, const int64_t* dims, int32_t fdtype,
     return set_error(TK_EINVAL, "tucker_reconstruct: fdtype must be TK_F64 or TK_F32");
   if (!G) return set_error(TK_EINVAL, "tucker_reconstruct: G is NULL");
   if (tk_status s = check_factors(order, dims, F, cols, "tucker_reconstruct")) return s;
-  if (!Xhat && !resid2) return set_error(TK_EINVAL, "tucker_reconstruct: neither Xhat nor resid2 given");
+  if (!Xhat && !resid2 && !D) return set_error(TK_EINVAL, "tucker_reconstruct: neither Xhat nor resid2 given");
   if (resid2 && !Xref) return set_error(TK_EINVAL, "tucker_reconstruct: resid2 needs Xref");
+  if (D && !Xref) return set_error(TK_EINVAL, "tucker_reconstruct: the scaled difference needs Xref");
   if (!ws_bytes) return set_error(TK_EINVAL, "tucker_reconstruct: ws_bytes is NULL");
   if (Xref) {
     int64_t N;
@@ -1430,6 +1436,9 @@ tk_status tucker_reconstruct(int32_t order, const int64_t* dims, int32_t fdtype,
     r.FI = static_cast<const float*>(F[order - 2]);
     r.FJ = static_cast<const float*>(F[order - 1]);
     r.Xhat = static_cast<float*>(Xhat);
+    r.D = static_cast<float*>(D);
+    r.scale = scale;
+    r.smul = smul;
     r.partials = partials;
     r.resid2 = resid2;
     r.A = A;
@@ -1457,16 +1466,21 @@ tk_status tucker_reconstruct(int32_t order, const int64_t* dims, int32_t fdtype,
       shape[k] = dims[k];
       mx = std::max(mx, prod(shape, 0, order));
     }
-    const int64_t N = prod(dims, 0, order);
+    const int64_t n_l = dims[order - 1];
+    // X_hat goes to Xhat, else to a workspace buffer of a bounded number of
+    // rows, reused chunk by chunk (never to D, which may be Xref itself)
+    const int64_t rows = Xhat ? A_l : std::min<int64_t>(A_l, std::max<int64_t>(32, ((int64_t)64 << 20) / (n_l * 4)) / 32 * 32);
+    const int64_t nchunk = ceil_div(A_l, rows);
     Workspace w;
     w.base = static_cast<char*>(ws);
     double* buf[2] = {w.take<double>((size_t)mx), w.take<double>((size_t)mx)};
     float* T32 = w.take<float>((size_t)(A_l * cols[order - 1]));
-    float* Xh32 = Xhat ? static_cast<float*>(Xhat) : w.take<float>((size_t)N);
+    float* Xh32 = Xhat ? static_cast<float*>(Xhat) : w.take<float>((size_t)(rows * n_l));
     int64_t smax = 0;
     for (int k = 0; k < order; ++k) smax = std::max(smax, mode_product_scratch(dims[k], cols[k]));
     double* mt = w.take<double>((size_t)smax);
-    double* partials = w.take<double>((size_t)2 * resid_pair_blocks(N));
+    const int64_t nb = resid_pair_blocks(rows * n_l);
+    double* partials = w.take<double>((size_t)(2 * nb * nchunk));
     if (!ws) {
       *ws_bytes = w.off;
       return TK_OK;
@@ -1495,19 +1509,26 @@ tk_status tucker_reconstruct(int32_t order, const int64_t* dims, int32_t fdtype,
       cur = mp.out;
       cur_dt = to32 ? TK_F32 : TK_F64;
     }
-    ModeMfma mm{};
-    mm.in = T32;
-    mm.F = static_cast<const float*>(F[order - 1]);
-    mm.A = A_l;
-    mm.Q = cols[order - 1];
-    mm.B = 1;
-    mm.P = (int32_t)dims[order - 1];
-    mm.ftrans = 1;
-    mm.out = Xh32;
+    const float* X32 = Xref ? static_cast<const float*>(Xref->data) : nullptr;
     TK_HIP(profile_begin(st));
-    TK_HIP(launch_mode_last_mfma_f32(mm, TK_F32, st));
-    if (resid2)
-      TK_HIP(launch_resid_pair_f32(static_cast<const float*>(Xref->data), Xh32, N, partials, resid2, st));
+    for (int64_t c = 0; c < nchunk; ++c) {
+      const int64_t r0 = c * rows, nr = std::min<int64_t>(rows, A_l - r0);
+      float* xh = Xhat ? Xh32 + r0 * n_l : Xh32;
+      ModeMfma mm{};
+      mm.in = T32 + r0 * cols[order - 1];
+      mm.F = static_cast<const float*>(F[order - 1]);
+      mm.A = nr;
+      mm.Q = cols[order - 1];
+      mm.B = 1;
+      mm.P = (int32_t)n_l;
+      mm.ftrans = 1;
+      mm.out = xh;
+      TK_HIP(launch_mode_last_mfma_f32(mm, TK_F32, st));
+      if (X32 && (resid2 || D))
+        TK_HIP(launch_resid_pair_f32(X32 + r0 * n_l, xh, nr * n_l, D ? static_cast<float*>(D) + r0 * n_l : nullptr,
+                                     scale, smul, partials + 2 * nb * c, nullptr, st));
+    }
+    if (resid2) TK_HIP(launch_pair_sum(partials, nb * nchunk, resid2, st));
     TK_HIP(profile_end(st));
     return TK_OK;
   }
@@ -1567,6 +1588,9 @@ tk_status tucker_reconstruct(int32_t order, const int64_t* dims, int32_t fdtype,
   e.F = F[order - 1];
   e.X = Xref ? Xref->data : nullptr;
   e.Xhat = Xhat;
+  e.D = D;
+  e.scale = scale;
+  e.smul = smul;
   e.partials = resid2 ? partials : nullptr;
   e.resid2 = resid2;
   e.A = A_last;
@@ -1576,6 +1600,20 @@ tk_status tucker_reconstruct(int32_t order, const int64_t* dims, int32_t fdtype,
   TK_HIP(launch_expand_residual(e, Xref ? Xref->dtype : fdtype, fdtype, st));
   TK_HIP(profile_end(st));
   return TK_OK;
+}
+
+}  // namespace
+}  // namespace tk
+
+extern "C" {
+
+tk_status tucker_reconstruct(int32_t order, const int64_t* dims, int32_t fdtype, const void* G,
+                             const void* const* F, const int32_t* cols, const tk_tensor* Xref,
+                             void* Xhat, double* resid2, void* ws, size_t* ws_bytes,
+                             void* stream) {
+  clear_error();
+  return reconstruct_impl(order, dims, fdtype, G, F, cols, Xref, Xhat, nullptr, nullptr, 0.0, resid2, ws,
+                          ws_bytes, stream);
 }
 
 // The tree must be the balanced heap tree of this order (left child = first
@@ -2239,6 +2277,82 @@ tk_status tucker_reconstruct_vjp(int32_t order, const int64_t* dims, int32_t fdt
   return TK_OK;
 }
 
+
+tk_status tucker_projection_loss_vjp(const tk_tensor* X, const void* const* F, const int32_t* cols,
+                                     const void* G, const double* lbar, void* Xbar, void* const* Fbar,
+                                     void* ws, size_t* ws_bytes, void* stream) {
+  clear_error();
+  int64_t N;
+  if (tk_status s = check_tensor(X, "tucker_projection_loss_vjp", &N)) return s;
+  if (X->dtype != TK_F64 && X->dtype != TK_F32)
+    return set_error(TK_EUNSUPPORTED, "tucker_projection_loss_vjp: tensor dtype must be F64 or F32");
+  if (tk_status s = check_factors(X->order, X->dims, F, cols, "tucker_projection_loss_vjp")) return s;
+  if (!G) return set_error(TK_EINVAL, "tucker_projection_loss_vjp: G is NULL");
+  if (!ws_bytes) return set_error(TK_EINVAL, "tucker_projection_loss_vjp: ws_bytes is NULL");
+  const int d = X->order;
+  const int fdt = X->dtype;
+  const size_t esz = fdt == TK_F64 ? 8 : 4;
+  int64_t gsz = 1;
+  for (int k = 0; k < d; ++k) gsz *= cols[k];
+  bool any_f = false;
+  for (int k = 0; Fbar && k < d; ++k) any_f |= Fbar[k] != nullptr;
+  if (!Xbar && !any_f) return set_error(TK_EINVAL, "tucker_projection_loss_vjp: no output requested");
+  // own buffers: Gbar (the core of H) and, without Xbar, H itself; then one
+  // region that every sub-step reuses in stream order
+  Workspace w;
+  w.base = static_cast<char*>(ws);
+  void* Gb = w.take<char>((size_t)gsz * esz);
+  void* Hb = Xbar ? Xbar : (void*)w.take<char>((size_t)N * esz);
+  if (!ws) {
+    // size query: the sub-steps' own queries check their pointers only for
+    // being non-NULL and never dereference them
+    Gb = reinterpret_cast<void*>(uintptr_t(256));
+    if (!Hb) Hb = reinterpret_cast<void*>(uintptr_t(256));
+  }
+  const size_t sub_off = (w.off + 255) & ~size_t(255);
+  tk_tensor Ht = *X;
+  Ht.data = Hb;
+  void* null_fb[TK_MAX_ORDER] = {};
+  void* const* fb = Fbar ? Fbar : null_fb;
+  size_t need[4] = {0, 0, 0, 0};
+  if (tk_status s = reconstruct_impl(d, X->dims, fdt, G, F, cols, X, nullptr, Hb, lbar, -2.0, nullptr,
+                                     nullptr, &need[0], stream)) return s;
+  if (tk_status s = tucker_reconstruct_vjp(d, X->dims, fdt, G, F, cols, Hb, Gb, any_f ? fb : nullptr,
+                                           nullptr, &need[1], stream)) return s;
+  if (any_f)
+    if (tk_status s = tucker_core_vjp(X, F, cols, Gb, nullptr, fb, 1, nullptr, &need[2], stream)) return s;
+  if (Xbar)
+    if (tk_status s = reconstruct_impl(d, X->dims, fdt, Gb, F, cols, &Ht, nullptr, Xbar, nullptr, -1.0,
+                                       nullptr, nullptr, &need[3], stream)) return s;
+  const size_t sub = std::max(std::max(need[0], need[1]), std::max(need[2], need[3]));
+  const size_t total = sub_off + sub;
+  if (!ws) {
+    *ws_bytes = total;
+    return TK_OK;
+  }
+  if (*ws_bytes < total)
+    return set_error(TK_EWORKSPACE, "tucker_projection_loss_vjp: workspace %zu < required %zu", *ws_bytes, total);
+  char* sw = static_cast<char*>(ws) + sub_off;
+  size_t sb = sub;
+  // H = dL/dX_hat = -2 lbar (X - X_hat), X_hat = G x_k F_k
+  if (tk_status s = reconstruct_impl(d, X->dims, fdt, G, F, cols, X, nullptr, Hb, lbar, -2.0, nullptr, sw,
+                                     &sb, stream)) return s;
+  // through the reconstruction: Gbar = H x_k F_k^T, Fbar = its factor gradients
+  sb = sub;
+  if (tk_status s = tucker_reconstruct_vjp(d, X->dims, fdt, G, F, cols, Hb, Gb, any_f ? fb : nullptr, sw,
+                                           &sb, stream)) return s;
+  // through the core projection: Fbar += the factor gradients at Gbar
+  sb = sub;
+  if (any_f)
+    if (tk_status s = tucker_core_vjp(X, F, cols, Gb, nullptr, fb, 1, sw, &sb, stream)) return s;
+  // Xbar = Gbar x_k F_k + the direct term 2 lbar (X - X_hat) = Gbar x_k F_k - H
+  // (in place: the pass reads H from Xbar and writes -(H - Gbar x_k F_k))
+  sb = sub;
+  if (Xbar)
+    if (tk_status s = reconstruct_impl(d, X->dims, fdt, Gb, F, cols, &Ht, nullptr, Xbar, nullptr, -1.0,
+                                       nullptr, sw, &sb, stream)) return s;
+  return TK_OK;
+}
 
 struct tk_batch_plan {
   tk::BatchPlanData data;

@@ -174,6 +174,9 @@ struct ExpandResidual {
   const void* F;
   const void* X;        // reference or nullptr
   void* Xhat;           // output or nullptr
+  void* D;              // output D = s (X - xhat) in f_dt (needs X; may alias it), or nullptr
+  const double* scale;  // s = smul * (*scale or 1)
+  double smul;
   double* partials;     // [nblocks][2] or nullptr
   double* resid2;       // final [2] or nullptr
   int64_t A, n;
@@ -284,11 +287,15 @@ hipError_t launch_mode_mfma_f32(const ModeMfma& m, int out_dt, hipStream_t st);
 // the last mode (B = 1), up to 192 columns: out[a][p] = sum_q in[a][q] F[q][p]
 bool mode_last_mfma_supported(int64_t A, int64_t Q, int32_t P);
 hipError_t launch_mode_last_mfma_f32(const ModeMfma& m, int out_dt, hipStream_t st);
-// sum (X - Xh)^2 and sum X^2 over n FP32 entries into resid2[2] (FP64, fixed
-// order); partials holds 2 resid_pair_blocks(n) doubles
+// sum (X - Xh)^2 and sum X^2 over n FP32 entries (FP64): per-block pairs into
+// partials (2 resid_pair_blocks(n) doubles), summed into resid2[2] in a fixed
+// order when resid2 != NULL; with D, also D = smul (*scale or 1) (X - Xh)
+// (D may alias X or Xh)
 int64_t resid_pair_blocks(int64_t n);
-hipError_t launch_resid_pair_f32(const float* X, const float* Xh, int64_t n, double* partials,
-                                 double* resid2, hipStream_t st);
+hipError_t launch_resid_pair_f32(const float* X, const float* Xh, int64_t n, float* D, const double* scale,
+                                 double smul, double* partials, double* resid2, hipStream_t st);
+// resid2 = the fixed-order sum of npairs (r, x) pairs
+hipError_t launch_pair_sum(const double* partials, int64_t npairs, double* resid2, hipStream_t st);
 
 // ---------------------------------------------------------------- FP32 fused streaming residual
 // sum (X[a] - F_I T[a] F_J^T)^2 and sum X[a]^2 over the A slabs of an FP32 tensor.
@@ -298,6 +305,9 @@ struct ResidFused2 {
   const float* FI;     // n_I x c_I
   const float* FJ;     // n_J x c_J
   float* Xhat;         // optional output, prod(dims)
+  float* D;            // optional output D = s (X - X_hat), s = smul * (*scale or 1); may alias X
+  const double* scale; // device scalar or nullptr
+  double smul;
   double* partials;    // [resid2_waves(A)][2]
   double* resid2;      // [2] or nullptr
   int64_t A;
@@ -395,8 +405,8 @@ struct VjpTrail {
   const float* K;       // A x c_I x c_J
   const float* FI;      // n_I x c_I
   const float* FJ;      // n_J x c_J
-  float* partI;         // [nblocks][n_I padded to 32][32]
-  float* partJ;         // [nblocks][n_J padded to 32][32]
+  float* partI;         // [nblocks][vjp_trail_rows_i(n_I)][32]
+  float* partJ;         // [nblocks][vjp_trail_rows_j(n_J)][32]
   int64_t A;
   int32_t nI, nJ, cI, cJ;
   int32_t nblocks;
@@ -404,6 +414,8 @@ struct VjpTrail {
 };
 bool vjp_trail_supported(int64_t nI, int64_t nJ, int cI, int cJ, int64_t A);
 int vjp_trail_blocks(int64_t A);
+int64_t vjp_trail_rows_i(int64_t nI);
+int64_t vjp_trail_rows_j(int64_t nJ);
 // out_dt: dtype of Fbar (TK_F32 or TK_F64); either Fbar may be NULL
 hipError_t launch_vjp_trail(const VjpTrail& p, void* FbarI, void* FbarJ, int out_dt, int accumulate,
                             hipStream_t st);

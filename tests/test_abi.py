@@ -107,6 +107,28 @@ def test_noalloc_sketch_validates_and_rejects_oversize_before_launch():
     assert st == 5 and "fixed" in L.tk_last_error().decode()
 
 
+def test_projection_loss_vjp_validation_and_query():
+    """The projection-loss backward answers its size query without a GPU;
+    without an X output its workspace also holds the X-sized adjoint; a call
+    with no output or an unsupported dtype is refused."""
+    L = B.lib()
+    dims, cols_ = (16, 20, 40, 132), (4, 5, 31, 32)
+    X = _tensor(dims)
+    cols = (C.c_int32 * 4)(*cols_)
+    F = _ptrs(4)
+    n1, n2 = C.c_size_t(0), C.c_size_t(0)
+    assert L.tucker_projection_loss_vjp(C.byref(X), F, cols, C.c_void_p(FAKE), None, C.c_void_p(FAKE), F,
+                                        None, C.byref(n1), None) == 0
+    assert L.tucker_projection_loss_vjp(C.byref(X), F, cols, C.c_void_p(FAKE), None, None, F,
+                                        None, C.byref(n2), None) == 0
+    assert n2.value >= n1.value + 16 * 20 * 40 * 132 * 4
+    assert L.tucker_projection_loss_vjp(C.byref(X), F, cols, C.c_void_p(FAKE), None, None, None,
+                                        None, C.byref(n1), None) == 1
+    Xb = _tensor(dims, dtype=B.TK_BF16)
+    assert L.tucker_projection_loss_vjp(C.byref(Xb), F, cols, C.c_void_p(FAKE), None, C.c_void_p(FAKE), F,
+                                        None, C.byref(n1), None) == 5
+
+
 def test_workspace_too_small_is_rejected_before_launch():
     X = _tensor((8, 9, 10))
     sks = (B.TkSketch * 3)(_sk(20, 5), _sk(30, 5), _sk(40, 5))

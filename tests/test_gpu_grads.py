@@ -22,7 +22,8 @@ def _grads_gpu(X, Fs, dtype):
 
 @pytest.mark.parametrize("dims,cols", [((4,) * 8, (3,) * 8), ((6, 5, 7), (2, 3, 4)),
                                        ((9, 70, 33, 5), (4, 5, 6, 3)), ((80, 6, 5), (64, 3, 2)),
-                                       ((80, 6, 5), (70, 3, 2)), ((5, 6, 80), (2, 3, 70))])
+                                       ((80, 6, 5), (70, 3, 2)), ((5, 6, 80), (2, 3, 70)),
+                                       ((70, 6, 5), (20, 3, 2))])
 def test_loss_gradients_match_oracle_fp64(dims, cols):
     rng = np.random.default_rng(1)
     X = rng.standard_normal(dims)
@@ -35,14 +36,16 @@ def test_loss_gradients_match_oracle_fp64(dims, cols):
         np.testing.assert_allclose(a, b, rtol=0, atol=1e-11 * np.abs(b).max())
 
 
-# FP32 shapes: the first four take the fused path (the partial core of the two
+# FP32 shapes: the first five take the fused path (the partial core of the two
 # trailing modes from the streaming pass, their gradients from one MFMA pass
-# over the tensor): ragged row tiles and column blocks, order 3 (one leading
-# mode, no contraction before its unfolded product), the 16x16-tile streaming
-# pass for small trailing modes; the last two keep the generic chains with
-# wide factors (the tiled unfolded product in FP32, one case per layout)
+# over the tensor): ragged row groups and column chunks, order 3 with a long
+# leading mode (its unfolded product tiled), the 16x16-tile streaming pass for
+# small trailing modes, two row groups with a ragged last chunk; the last two
+# keep the generic chains with wide factors (the tiled unfolded product in
+# FP32, one case per layout)
 FP32_CASES = [((16, 20, 30, 132), (5, 6, 12, 20)), ((16, 20, 40, 132), (4, 5, 31, 32)),
-              ((300, 48, 64), (7, 12, 9)), ((20, 30, 24, 36), (3, 4, 8, 12)),
+              ((300, 48, 64), (20, 12, 9)), ((20, 30, 24, 36), (3, 4, 8, 12)),
+              ((260, 150, 200), (6, 31, 17)),
               ((80, 6, 5), (40, 3, 2)), ((5, 6, 80), (2, 3, 70))]
 
 
@@ -60,7 +63,7 @@ def test_loss_gradients_match_oracle_fp32(dims, cols):
         np.testing.assert_allclose(a, b, rtol=0, atol=1e-4 * np.abs(b).max())
 
 
-@pytest.mark.parametrize("dims,cols", FP32_CASES[:4])
+@pytest.mark.parametrize("dims,cols", FP32_CASES[:5])
 def test_vjps_match_oracle_fp32_fused_path(dims, cols):
     """Both VJPs at arbitrary adjoints (not only the loss's), FP32, on the
     fused path, against the oracle's closed forms on the same FP32 values."""
@@ -87,6 +90,31 @@ def test_vjps_match_oracle_fp32_fused_path(dims, cols):
     for a, b in zip(Fr, Fr0):
         np.testing.assert_allclose(a.double().cpu().numpy(), b, rtol=0, atol=2e-5 * np.abs(b).max())
     np.testing.assert_allclose(Gr.double().cpu().numpy(), Gr0, rtol=0, atol=2e-5 * np.abs(Gr0).max())
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_projection_loss_vjp_scaled_without_xbar(dtype):
+    """tucker_projection_loss_vjp with a loss adjoint of 0.37 and no X output
+    (H then lives in the workspace): the factor gradients are 0.37 times the
+    oracle's."""
+    from paper_2603_21379_amd import binding as B
+    dims, cols = ((16, 20, 40, 132), (4, 5, 31, 32)) if dtype == torch.float32 else ((9, 70, 33, 5), (4, 5, 6, 3))
+    rng = np.random.default_rng(8)
+    npdt = np.float32 if dtype == torch.float32 else np.float64
+    X = rng.standard_normal(dims).astype(npdt)
+    Fs = [np.linalg.qr(rng.standard_normal((n, c)))[0].astype(npdt) for n, c in zip(dims, cols)]
+    _, _, dF0 = oracle.loss_and_grads(X.astype(np.float64), [f.astype(np.float64) for f in Fs])
+    Xd = torch.from_numpy(X).cuda()
+    Fd = [torch.from_numpy(f).cuda() for f in Fs]
+    G = torch.empty(cols, dtype=dtype, device="cuda")
+    B.tucker_core(Xd, Fd, G)
+    lbar = torch.tensor(0.37, dtype=torch.float64, device="cuda")
+    Fb = [torch.empty_like(f) for f in Fd]
+    B.tucker_projection_loss_vjp(Xd, Fd, G, lbar, Xbar=None, Fbar=Fb)
+    torch.cuda.synchronize()
+    tol = 1e-4 if dtype == torch.float32 else 1e-11
+    for a, b in zip(Fb, dF0):
+        np.testing.assert_allclose(a.double().cpu().numpy(), 0.37 * b, rtol=0, atol=tol * np.abs(b).max())
 
 
 def test_core_vjp_fused_path_accumulates():
