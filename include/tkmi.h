@@ -188,7 +188,9 @@ tk_status tucker_core(const tk_tensor* X, const void* const* F, const int32_t* c
  *   Xref   NULL or the reference tensor (same dims; its dtype decides fdtype).
  *   Xhat   NULL or a device output of prod(dims) entries in fdtype.
  *   resid2 NULL or device double[2]: ||Xref - X_hat||_F^2 and ||Xref||_F^2,
- *          accumulated in FP64 (requires Xref).
+ *          accumulated in FP64 (requires Xref; the FP32 matrix-core pass sums
+ *          the squared differences of 32 entries in FP32 before adding them
+ *          to the FP64 sum).
  * At least one of Xhat and resid2 must be non-NULL.
  * Errors: TK_EINVAL, TK_EWORKSPACE, TK_EDEVICE. */
 tk_status tucker_reconstruct(int32_t order, const int64_t* dims, int32_t fdtype, const void* G,

@@ -1,6 +1,7 @@
 // Streaming residual of the Tucker reconstruction for FP32 tensors on MFMA:
 //   X_hat[a] = F_I T[a] F_J^T      (n_I x n_J, for the A slabs of X)
-//   sum (X[a] - X_hat[a])^2,  sum X[a]^2    (FP64, per wave, then a fixed-order sum)
+//   sum (X[a] - X_hat[a])^2,  sum X[a]^2    (FP64 per wave, the squared
+//   differences first summed in FP32 over 32 entries; a fixed-order final sum)
 // where T[a] (c_I x c_J, FP32) is the core expanded over the leading modes.
 // This is the last two expansions of the reconstruction (Tucker format,
 // Section 3) fused with the error of the approximation, so X_hat is never
@@ -211,14 +212,23 @@ __global__ __launch_bounds__(256, 1) void resid2_f32_kernel(const ResidFused2 p)
             o0 = mma_bf16(a[2], ph0[ks][0], o0);
             o1 = mma_bf16(a[2], ph1[ks][0], o1);
           }
+          // (x - x_hat)^2 in FP32 over the tile's 32 entries of this lane (x
+          // and x_hat are FP32, their difference is exact or within u |d|),
+          // then added to the FP64 sum; x^2 exactly in FP64.  Rows past n_I
+          // and columns past n_J hold x = x_hat = 0 and add nothing.
+          float r2t = 0.0f;
+#pragma unroll
+          for (int v = 0; v < 16; ++v) {
+            const float d0 = xb[v][0] - o0[v], d1 = xb[v][1] - o1[v];
+            r2t = fmaf(d0, d0, fmaf(d1, d1, r2t));
+            const double x0 = xb[v][0], x1 = xb[v][1];
+            x2 = fma(x0, x0, fma(x1, x1, x2));
+          }
+          r2 += (double)r2t;
 #pragma unroll
           for (int v = 0; v < 16; ++v) {
             const int i = it * 32 + 8 * (v >> 2) + 4 * kh + (v & 3);
-            if (colok && i < p.nI) {
-              const double x0 = xb[v][0], x1 = xb[v][1];
-              const double d0 = x0 - (double)o0[v], d1 = x1 - (double)o1[v];
-              r2 = fma(d0, d0, fma(d1, d1, r2));
-              x2 = fma(x0, x0, fma(x1, x1, x2));
+            if ((want_xh || want_d) && colok && i < p.nI) {
               if (want_xh) {
                 floatx2 w;
                 w[0] = o0[v];
@@ -227,8 +237,8 @@ __global__ __launch_bounds__(256, 1) void resid2_f32_kernel(const ResidFused2 p)
               }
               if (want_d) {
                 floatx2 w;
-                w[0] = dscale * (float)d0;
-                w[1] = dscale * (float)d1;
+                w[0] = dscale * (xb[v][0] - o0[v]);
+                w[1] = dscale * (xb[v][1] - o1[v]);
                 __builtin_amdgcn_raw_buffer_store_b64(w, rd, (uint32_t)((i * p.nJ + b) * 4), 0, 0);
               }
             }
