@@ -124,7 +124,9 @@ def test_fullsize_tucker(which, dtype, ctol):
         xh = oracle.reconstruct(G, [Fs[0][i:i + 1]] + Fs[1:])
         num += float(np.sum((xs - xh) ** 2))
         den += float(np.sum(xs ** 2))
-    assert abs(r2s[1] - den) <= 1e-12 * den
+    # the FP32 residual pass sums each lane's 32 entries of a row tile in FP32
+    # first: a sum of 32 nonnegative FP32 terms is within 32 u = 1.9e-6 relative
+    assert abs(r2s[1] - den) <= (2e-6 if dtype == "f32" else 1e-12) * den
     assert abs(math.sqrt(r2s[0] / r2s[1]) - math.sqrt(num / den)) <= EPS_TOL[dtype] * math.sqrt(num / den)
     # end to end: the oracle's own factors and core (orthonormal FP64 factors,
     # so ||X - X_hat||^2 = ||X||^2 - ||G||^2)
