@@ -199,10 +199,18 @@ __global__ __launch_bounds__(64) void apply_rinv_kernel(const S b, int pass) {
 
 // ------------------------------------------------------------------ small matrices
 // Every CholeskyQR pass of one matrix in one 256-thread workgroup (m x ell <=
-// kQRSmallElems): Gram from 32-row chunks staged in LDS, Cholesky in LDS, and
-// Q = Z R^{-1} by forward substitution with each row held in registers.
+// kQRSmallElems), Z resident in LDS:
+//  * Gram G = Z^T Z on v_mfma_f64_16x16x4f64 (wave w: tiles w, w + 4, ... of
+//    the 16 x 16 tiling; lane l supplies Z[k0 + l/16][16 t + l%16] for both
+//    operands, register v of the result is row 16 ti + l/16 + 4 v, column
+//    16 tj + l%16);
+//  * upper Cholesky factor R by one wave, right-looking, lane q holding
+//    column q of G in registers; row j of R goes through LDS to every lane
+//    for the rank-one update;
+//  * X = R^{-1} by one wave (lane j: column j in registers), written
+//    transposed over the unused lower triangle of the array that holds R;
+//  * Q = Z X on MFMA, each wave overwriting its own 16-row tiles of Z.
 // Same passes, shift rule and info bits as the multi-kernel path.
-constexpr int kSmallChunk = 32;
 
 // Within one wavefront LDS operations complete in issue order, so lanes of
 // that wave only need the compiler kept from reordering across this point.
@@ -213,159 +221,164 @@ constexpr int kSmallChunk = 32;
     __atomic_signal_fence(__ATOMIC_SEQ_CST);    \
   } while (0)
 
-// Upper Cholesky factor in place, by the 64 lanes of one wave (no barriers).
-// Left-looking: lane q owns column q and step j forms
-//   R[j][q] = (G[j][q] - sum_{k<j} R[k][j] R[k][q]) / R[j][j]   (q >= j),
-// reading only rows k < j, which are final; the dot products keep four
-// partial sums so their loads pipeline, and each step stores one entry per
-// lane.  The lower triangle is not touched (the Gram is reloaded from
-// registers for a shifted retry).
-__device__ bool cholesky_upper_wave(double (*G)[kMaxEll + 1], int n, int lane, double tol) {
-  const int q = lane;
-  const bool mine = q < n;
-  for (int j = 0; j < n; ++j) {
-    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-    if (mine && q >= j) {
-      int k = 0;
-      for (; k + 4 <= j; k += 4) {
-        s0 = fma(G[k][j], G[k][q], s0);
-        s1 = fma(G[k + 1][j], G[k + 1][q], s1);
-        s2 = fma(G[k + 2][j], G[k + 2][q], s2);
-        s3 = fma(G[k + 3][j], G[k + 3][q], s3);
+typedef double doublex4 __attribute__((ext_vector_type(4)));
+
+// 1 / x and 1 / sqrt(x) for normal positive x: the hardware estimates and
+// two Newton steps (within 2 u; no division or square-root sequence with its
+// range scaling on a chain of dependent steps)
+__device__ __forceinline__ double rcp_nr(double x) {
+  double y = __builtin_amdgcn_rcp(x);
+  y = fma(y, fma(-x, y, 1.0), y);
+  return fma(y, fma(-x, y, 1.0), y);
+}
+__device__ __forceinline__ double rsq_nr(double x) {
+  const double hx = 0.5 * x;
+  double y = __builtin_amdgcn_rsq(x);
+  y *= fma(-hx * y, y, 1.5);
+  return y * fma(-hx * y, y, 1.5);
+}
+__device__ __forceinline__ double lane_value(double v, int i) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), i);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), i);
+  return __hiloint2double(hi, lo);
+}
+
+// Upper Cholesky factor of G (n x n in LDS, zero past n in an E x E array,
+// E >= n) by the 64 lanes of one wave.  Lane q keeps column q in registers;
+// step j takes the pivot from lane j, forms row j of R (zero left of the
+// diagonal, so that column q ends up holding exactly column q of R), passes
+// it to every lane through rowbuf and applies the rank-one update to the
+// trailing columns.  A pivot not above tol fails the factorization (returns
+// false) unless `force`, which keeps the solve finite with r_jj = 1 instead.
+// On return with success or `force`, G holds R (zero below the diagonal and
+// past n) and rinv[j] = 1 / r_jj (zero past n).
+template <int E>
+__device__ __forceinline__ bool chol_wave(double (*G)[E + 1], int n, int lane, double tol, bool force,
+                                          double* rowbuf, double* rinv) {
+  const int q = lane < E ? lane : E - 1;   // lanes past E mirror column E - 1 and store nothing
+  double col[E];
+#pragma unroll
+  for (int p = 0; p < E; ++p) col[p] = G[p][q];
+  bool good = true;
+#pragma unroll
+  for (int j = 0; j < E; ++j) {
+    if (j < n && good) {
+      const double piv = lane_value(col[j], j);
+      double rj = 1.0, inv = 1.0;
+      if (piv > tol && piv >= 2.2250738585072014e-308) {
+        inv = rsq_nr(piv);
+        rj = piv * inv;
+      } else if (!force) {
+        good = false;
       }
-      for (; k < j; ++k) s0 = fma(G[k][j], G[k][q], s0);
+      if (good) {
+        int lj = lane;
+        asm volatile("" : "+v"(lj));   // the compares below stay in this step
+        const double rjq = lj > j ? col[j] * inv : (lj == j ? rj : 0.0);
+        col[j] = rjq;
+        TK_WAVE_SYNC();   // the previous step's reads of rowbuf are done
+        rowbuf[lane] = rjq;
+        TK_WAVE_SYNC();
+        // row j of R: every load issued before the updates
+        double rj_row[E];
+#pragma unroll
+        for (int p = j + 1; p < E; ++p) rj_row[p] = rowbuf[p];
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int p = j + 1; p < E; ++p) col[p] = fma(-rj_row[p], rjq, col[p]);
+        __builtin_amdgcn_sched_barrier(0);
+        if (lane == 0) rinv[j] = inv;
+      }
     }
-    const double val = (mine && q >= j) ? G[j][q] - ((s0 + s1) + (s2 + s3)) : 0.0;
-    const double piv = __shfl(val, j);
-    if (!(piv > tol)) return false;  // uniform: every lane holds lane j's pivot
-    const double rjj = sqrt(piv), inv = 1.0 / rjj;
-    if (mine && q > j) G[j][q] = val * inv;
-    if (q == j) G[j][j] = rjj;
-    TK_WAVE_SYNC();
   }
+  if (!good) return false;
+  TK_WAVE_SYNC();   // every lane has read G
+  if (lane < E) {
+#pragma unroll
+    for (int p = 0; p < E; ++p) G[p][lane] = col[p];
+    if (lane >= n) rinv[lane] = 0.0;
+  }
+  TK_WAVE_SYNC();
   return true;
 }
 
-// In-place inverse of the upper triangular R by one wave (as LAPACK's
-// unblocked trti2): column j of R^{-1} is -R^{-1}_{jj} R^{-1}(0:j, 0:j) R(0:j, j).
-__device__ void upper_inverse_wave(double (*R)[kMaxEll + 1], int n, int lane) {
-  for (int j = 0; j < n; ++j) {
-    const double rjj = 1.0 / R[j][j];
-    TK_WAVE_SYNC();
-    // four independent partial sums so the LDS reads pipeline
-    double x0 = 0.0, x1 = 0.0, x2 = 0.0, x3 = 0.0;
-    if (lane < j) {
-      int k = lane;
-      for (; k + 4 <= j; k += 4) {
-        x0 = fma(R[lane][k], R[k][j], x0);
-        x1 = fma(R[lane][k + 1], R[k + 1][j], x1);
-        x2 = fma(R[lane][k + 2], R[k + 2][j], x2);
-        x3 = fma(R[lane][k + 3], R[k + 3][j], x3);
-      }
-      for (; k < j; ++k) x0 = fma(R[lane][k], R[k][j], x0);
-    }
-    const double x = (x0 + x1) + (x2 + x3);
-    TK_WAVE_SYNC();
-    if (lane < j) R[lane][j] = -rjj * x;
-    if (lane == 0) R[j][j] = rjj;
-    TK_WAVE_SYNC();
-  }
-}
-
-// Q = Z R^{-1} in place on the LDS copy of Z, 64 rows at a time: thread t
-// forms the 4 x 4 output tile (rows 4 (t / 16), columns 4 (t % 16)) in
-// registers; the chunk is overwritten once every thread has read its rows.
-__device__ void apply_inverse_lds(double* sZ, int64_t m, int n, const double (*Ri)[kMaxEll + 1],
-                                  int tid) {
-  const int ti = tid >> 4, tj = tid & 15;
-  const int jmax = min(n, 4 * tj + 4);   // R^{-1} is upper triangular: k <= j
-  for (int64_t r0 = 0; r0 < m; r0 += 64) {
-    double acc[4][4];
-#pragma unroll
-    for (int a = 0; a < 4; ++a)
-#pragma unroll
-      for (int c = 0; c < 4; ++c) acc[a][c] = 0.0;
-    int64_t rows[4];
-#pragma unroll
-    for (int a = 0; a < 4; ++a) rows[a] = min<int64_t>(r0 + 4 * ti + a, m - 1);
-#pragma unroll 4
-    for (int k = 0; k < jmax; ++k) {
-      double z[4], w[4];
-#pragma unroll
-      for (int a = 0; a < 4; ++a) z[a] = sZ[rows[a] * n + k];
-#pragma unroll
-      for (int c = 0; c < 4; ++c) w[c] = (4 * tj + c < n) ? Ri[k][4 * tj + c] : 0.0;
-#pragma unroll
-      for (int a = 0; a < 4; ++a)
-#pragma unroll
-        for (int c = 0; c < 4; ++c) acc[a][c] = fma(z[a], w[c], acc[a][c]);
-    }
-    __syncthreads();   // every read of this chunk is done
-#pragma unroll
-    for (int a = 0; a < 4; ++a) {
-      const int64_t row = r0 + 4 * ti + a;
-#pragma unroll
-      for (int c = 0; c < 4; ++c) {
-        const int j = 4 * tj + c;
-        if (row < m && j < n) sZ[row * n + j] = acc[a][c];
-      }
-    }
-    __syncthreads();
-  }
-}
-
-template <typename S>
+template <typename S, int E>
 __global__ __launch_bounds__(256) void cholqr_small_kernel(const S b) {
   const QRMat& M = b.get(blockIdx.x);
   if (!M.small) return;
-  // Z stays in LDS for every pass (row stride ell): one coalesced read at the
-  // start, one write of Q at the end, no global latency inside the passes
+  // Z stays in LDS for every pass (row stride ell, then 4 ell + E zeros so
+  // that the Gram's row groups and a row's registers can run past the end
+  // without a bound check): one coalesced read at the start, one write of Q
+  // at the end
   extern __shared__ double sZ[];
-  __shared__ double G[kMaxEll][kMaxEll + 1];
+  __shared__ double G[E][E + 1];
+  __shared__ double rowbuf[64], rinv[E];
   __shared__ double red[2];
   __shared__ int ok;
-  const int n = M.ell, tid = threadIdx.x;
-  const int64_t mn = M.m * n;
+  const int n = M.ell, tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int l16 = lane & 15, g = lane >> 4;
+  const int64_t m = M.m, mn = m * n;
   for (int64_t e = tid; e < mn; e += 256) sZ[e] = M.Z[e];
+  for (int64_t e = tid; e < 4 * n + E; e += 256) sZ[mn + e] = 0.0;
+  for (int e = tid; e < E * (E + 1); e += 256) (&G[0][0])[e] = 0.0;
   __syncthreads();
-  const int ti = tid >> 4, tj = tid & 15;
+  const int nt = (n + 15) / 16;
   int owed = 2, info = 0;
   for (int pass = 1; pass <= kQRMaxPasses && owed > 0; ++pass) {
-    // Gram: thread t owns the 4 x 4 tile (4 (t / 16), 4 (t % 16)) of G, so a
-    // row costs 8 LDS reads for 16 FMAs; the tile stays in registers for a
-    // shifted retry
-    double acc[4][4];
+    // Gram on MFMA: wave w takes the row groups 4 k + (0..3), k = w, w + 4,
+    // ..., eight groups at a time with all their loads issued first, and
+    // accumulates every tile (ti <= tj) of the upper triangle in its own
+    // accumulator (independent chains); the loads need no bounds: columns
+    // past n read the next row (those tiles' entries past n are not kept)
+    // and rows past m read the zero padding
+    {
+      constexpr int kT = E / 16, kTiles = kT * (kT + 1) / 2, kB = 8;
+      doublex4 acc[kTiles];
 #pragma unroll
-    for (int a = 0; a < 4; ++a)
+      for (int t = 0; t < kTiles; ++t) acc[t] = doublex4{0.0, 0.0, 0.0, 0.0};
+      for (int64_t k0 = 4 * wave; k0 < m; k0 += 16 * kB) {
+        double zt[kB][kT];
 #pragma unroll
-      for (int c = 0; c < 4; ++c) acc[a][c] = 0.0;
-    int ca[4], cc[4];
+        for (int u = 0; u < kB; ++u) {
+          // groups past m start in the padding or beyond: read row m - 1's
+          // neighbourhood instead and contribute zero
+          const int64_t row = k0 + 16 * u + g;
+          const bool live = k0 + 16 * u < m;
+          const double* zr = sZ + (live ? row : 0) * n + l16;
 #pragma unroll
-    for (int a = 0; a < 4; ++a) {
-      ca[a] = min(4 * ti + a, n - 1);
-      cc[a] = min(4 * tj + a, n - 1);
-    }
-#pragma unroll 4
-    for (int64_t r = 0; r < M.m; ++r) {
-      const double* zr = sZ + r * n;
-      double x[4], y[4];
+          for (int t = 0; t < kT; ++t) zt[u][t] = live ? zr[16 * t] : 0.0;
+        }
 #pragma unroll
-      for (int a = 0; a < 4; ++a) x[a] = zr[ca[a]];
+        for (int u = 0; u < kB; ++u) {
+          int t = 0;
 #pragma unroll
-      for (int c = 0; c < 4; ++c) y[c] = zr[cc[c]];
+          for (int ti = 0; ti < kT; ++ti)
 #pragma unroll
-      for (int a = 0; a < 4; ++a)
-#pragma unroll
-        for (int c = 0; c < 4; ++c) acc[a][c] = fma(x[a], y[c], acc[a][c]);
-    }
-#pragma unroll
-    for (int a = 0; a < 4; ++a)
-#pragma unroll
-      for (int c = 0; c < 4; ++c) {
-        const int p = 4 * ti + a, q = 4 * tj + c;
-        if (p < n && q < n) G[p][q] = acc[a][c];
+            for (int tj = ti; tj < kT; ++tj, ++t)
+              acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(zt[u][ti], zt[u][tj], acc[t], 0, 0, 0);
+        }
       }
-    __syncthreads();
+      // the four waves' partial tiles, summed in wave order
+      for (int w = 0; w < 4; ++w) {
+        if (wave == w) {
+          int t = 0;
+#pragma unroll
+          for (int ti = 0; ti < kT; ++ti)
+#pragma unroll
+            for (int tj = ti; tj < kT; ++tj, ++t)
+#pragma unroll
+              for (int v = 0; v < 4; ++v) {
+                const int pr = 16 * ti + g + 4 * v, qc = 16 * tj + l16;
+                if (pr < n && qc < n) {
+                  const double x = w == 0 ? acc[t][v] : G[pr][qc] + acc[t][v];
+                  G[pr][qc] = x;
+                  if (w == 3 && ti != tj) G[qc][pr] = x;
+                }
+              }
+        }
+        __syncthreads();
+      }
+    }
     if (tid == 0) {
       double mx = 0.0, tr = 0.0;
       for (int j = 0; j < n; ++j) { mx = fmax(mx, G[j][j]); tr += G[j][j]; }
@@ -374,45 +387,98 @@ __global__ __launch_bounds__(256) void cholqr_small_kernel(const S b) {
     }
     __syncthreads();
     const double mx = red[0], tr = red[1];
-    // Cholesky by wave 0; on failure every thread rewrites its tile of the
-    // Gram with the shift and wave 0 factors again
-    if (tid < 64) {
-      const bool good = mx > 0.0 && cholesky_upper_wave(G, n, tid, 1e-14 * mx);
-      if (tid == 0) ok = good ? 0 : 1;
+    // Cholesky by wave 0; on failure again with the shift of shifted
+    // CholeskyQR (Fukaya et al. 2020): s = 11 (m n + n (n+1)) u ||Z||^2, with
+    // ||Z||_2^2 bounded by the trace of the Gram
+    if (wave == 0) {
+      int status = 0;
+      if (!(mx > 0.0 && chol_wave<E>(G, n, lane, 1e-14 * mx, false, rowbuf, rinv))) {
+        const double shift = 11.0 * ((double)m * n + (double)n * (n + 1)) * kUnit * fmax(tr, 1e-300);
+        if (lane < n) G[lane][lane] += shift;
+        TK_WAVE_SYNC();
+        status = chol_wave<E>(G, n, lane, 0.0, false, rowbuf, rinv) ? 1 : 2;
+        if (status == 2) chol_wave<E>(G, n, lane, 0.0, true, rowbuf, rinv);   // finite; flagged
+      }
+      if (lane == 0) ok = status;
     }
     __syncthreads();
-    if (ok != 0) {
-      const double shift = 11.0 * ((double)M.m * n + (double)n * (n + 1)) * kUnit * fmax(tr, 1e-300);
+    // X = R^{-1} by wave 0 (lane j: column j of X in registers, rows
+    // descending), written transposed below the diagonal of G (R, above it,
+    // is read only; the diagonal 1 / r_jj is rinv):
+    //   x_ij = (delta_ij - sum_{k>i} r_ik x_kj) / r_ii
+    // (rows past j come out zero: every x_kj with k > i > j is zero)
+    if (wave == 0 && lane < E) {
+      double x[E];
 #pragma unroll
-      for (int a = 0; a < 4; ++a)
+      for (int i = E - 1; i >= 0; --i) {
+        // delta_ij as a 0/1 factor from integer arithmetic (a compare here
+        // would be kept as a mask for every row at once)
+        const double delta = (double)(1 - min(1, abs(lane - i)));
+        // row i of R: every load issued before the products
+        double ri[E];
 #pragma unroll
-        for (int c = 0; c < 4; ++c) {
-          const int p = 4 * ti + a, q = 4 * tj + c;
-          if (p < n && q < n) G[p][q] = acc[a][c] + (p == q ? shift : 0.0);
+        for (int k = i + 1; k < E; ++k) ri[k] = G[i][k];
+        const double rii = rinv[i];
+        __builtin_amdgcn_sched_barrier(0);
+        double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+        for (int k = i + 1; k < E; ++k) {
+          if ((k - i) & 1) s0 = fma(ri[k], x[k], s0);
+          else s1 = fma(ri[k], x[k], s1);
         }
-      __syncthreads();
-      if (tid < 64) {
-        const bool good = cholesky_upper_wave(G, n, tid, 0.0);
-        if (!good) {
-          TK_WAVE_SYNC();
-          for (int j = tid; j < n; j += 64)
-            if (!(G[j][j] > 0.0)) G[j][j] = 1.0;  // keep the solve finite; flagged
-        }
-        if (tid == 0) ok = good ? 1 : 2;
+        x[i] = (delta - (s0 + s1)) * rii;
+        __builtin_amdgcn_sched_barrier(0);
       }
+      TK_WAVE_SYNC();   // every read of R is done
+#pragma unroll
+      for (int i = 0; i < E; ++i)
+        if (i < lane) G[lane][i] = x[i];
     }
-    // the triangular inverse by wave 0 (zero the strict lower triangle left
-    // over from the Gram first)
-    if (tid < 64) {
-      TK_WAVE_SYNC();
-      for (int e = tid; e < n * n; e += 64)
-        if (e / n > e % n) G[e / n][e % n] = 0.0;
-      TK_WAVE_SYNC();
-      upper_inverse_wave(G, n, tid);
+    __syncthreads();
+    // Q = Z X on MFMA, in place: wave w takes the 16-row tiles w, w + 4, ...
+    // (each reads and writes only its own rows); lane l supplies
+    // Z[r0 + l%16][k0 + l/16] and X[k0 + l/16][16 ct + l%16].  X's operands
+    // are loaded once, a tile's Z operands all before its multiplies.
+    {
+      constexpr int kT = E / 16, kK = E / 4;
+      double xb[kK][kT];
+#pragma unroll
+      for (int ks = 0; ks < kK; ++ks)
+#pragma unroll
+        for (int ct = 0; ct < kT; ++ct) {
+          const int k = 4 * ks + g, j = 16 * ct + l16;
+          xb[ks][ct] = k < j ? G[j][k] : (k == j ? rinv[j] : 0.0);
+        }
+      for (int64_t r0 = 16 * wave; r0 < m; r0 += 64) {
+        const int64_t arow = r0 + l16;
+        const bool rowok = arow < m;
+        double a[kK];
+#pragma unroll
+        for (int ks = 0; ks < kK; ++ks) {
+          const int k = 4 * ks + g;
+          a[ks] = (rowok && k < n) ? sZ[arow * n + k] : 0.0;
+        }
+        doublex4 acc[kT];
+#pragma unroll
+        for (int ct = 0; ct < kT; ++ct) acc[ct] = doublex4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int ks = 0; ks < kK; ++ks)
+#pragma unroll
+          for (int ct = 0; ct < kT; ++ct)
+            acc[ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[ks], xb[ks][ct], acc[ct], 0, 0, 0);
+        __builtin_amdgcn_wave_barrier();   // the wave's reads of these rows precede its writes
+#pragma unroll
+        for (int ct = 0; ct < kT; ++ct)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int64_t row = r0 + g + 4 * v;
+            const int j = 16 * ct + l16;
+            if (row < m && j < n) sZ[row * n + j] = acc[ct][v];
+          }
+      }
     }
     __syncthreads();
     const int status = ok;
-    apply_inverse_lds(sZ, M.m, n, G, tid);
     if (status != 0) info |= pass == 1 ? 1 : 2;
     if (status == 2) info |= 4;
     owed = status != 0 ? 2 : owed - 1;
@@ -518,21 +584,37 @@ __global__ __launch_bounds__(256) void mgram_kernel(const S b) {
   }
 }
 
-// Cyclic Jacobi (parallel round-robin ordering) on the summed ell x ell Gram;
-// W = eigenvectors of the r largest eigenvalues, in descending order.
-// One 256-thread workgroup per matrix: each round computes the ell/2
-// disjoint rotations, then applies them to rows (A <- J^T A) and to columns
-// (A <- A J, V <- V J); every thread owns a fixed set of (pair, index) items,
-// precomputed once.  The pairs of a round follow the fixed round-robin
-// schedule, so every wave computes all of the round's rotations itself (no
-// wave waits for another's parameters) and every thread derives its items'
-// indices arithmetically; a round is two barriers, one batch of LDS loads
-// per thread and the stores of the entries a rotation changes.
-// A rotation is skipped once |a_pq| <= 4 u max(|a_pp|, |a_qq|): the rotation
-// it would apply is then below rounding level relative to the pair's own
-// scale (a signal/noise pair is decoupled to ~u), whereas the stricter test
-// |a_pq| <= u sqrt(a_pp a_qq) can be unreachable in floating point for
-// strongly graded pairs.
+// W step: W = eigenvectors of the r largest eigenvalues (descending) of the
+// summed ell x ell Gram of M = Q^T Y, by cyclic Jacobi (parallel round-robin
+// ordering), then U = Q W with the column sign rule.  One 256-thread
+// workgroup per matrix.
+//  * A round computes its ell/2 disjoint rotations in every wave (lane k:
+//    rotation k, so no wave waits for another's parameters) and applies them
+//    to 2x2 blocks of A (A <- J^T A J) and to column pairs of V (V <- V J),
+//    each thread owning a fixed set of blocks and pairs.  A is double
+//    buffered: a round reads one copy and writes every block of the other, so
+//    one barrier per round suffices.
+//  * The rotation of a pair comes from the hardware estimates of 1/sqrt and
+//    1/x with two Newton steps each (within 2 u), not from the division and
+//    square-root sequences, whose range scaling would sit on the chain.  A is
+//    scaled by a power of two first (exact), so that its largest entry lies
+//    in [1, 2).
+//  * A rotation is skipped once |a_pq| <= tol max(|a_pp|, |a_qq|) (tol = 4 u
+//    for FP64 bases, 1e-12 for FP32 bases): the rotation it would apply is
+//    then below rounding level relative to the pair's own scale (a
+//    signal/noise pair is decoupled to ~u), whereas the stricter test
+//    |a_pq| <= u sqrt(a_pp a_qq) can be unreachable in floating point for
+//    strongly graded pairs.
+//  * Pairs of two indices that currently rank below the r largest diagonal
+//    entries are not rotated: such a rotation only mixes directions that are
+//    dropped.  Once no other pair rotates, a Gershgorin bound checks that the
+//    unreduced block of those indices lies below every kept diagonal entry
+//    (so the kept ones are the r largest eigenvalues); if it does not, full
+//    sweeps resume.  Sweeps exhausted with rotations still firing set info
+//    bit 3 (W may be inaccurate).
+//  * U = Q W on v_mfma_f64_16x16x4f64, twice: the first pass finds each
+//    column's entry of largest magnitude (lowest row on ties), the second
+//    stores U with that entry made positive.
 constexpr int kEigThreads = 256;
 constexpr int kEigMaxSweeps = 60;
 
@@ -541,17 +623,17 @@ constexpr int kEigMaxSweeps = 60;
 template <typename S, int IA, int IV, int E>
 __global__ __launch_bounds__(kEigThreads) void eig_kernel(const S b) {
   const QRMat& M = b.get(blockIdx.x);
-  __shared__ double A[E][E + 1];
+  __shared__ double Abuf[2][E][E + 1];
   __shared__ double V[E][E + 1];
   // (c, s) of the current round's rotations, one copy per wave
   __shared__ double2 rot_cs[kEigThreads / 64][E / 2];
+  __shared__ double red[kEigThreads / 64];
   const int n = M.ell, np = n + (n & 1), half = np / 2, tid = threadIdx.x;
-  // rotations stop below rounding level of the output precision (relative to
-  // the pair's own scale): FP64 bases need ~u, FP32 bases ~1e-12 suffices
+  const int wave = tid >> 6, lane = tid & 63;
   const double tol = M.udtype == TK_F64 ? 4.0 * kUnit : 1e-12;
   // summed Gram: every thread's elements over groups of four column chunks,
   // all loads of a group in flight together (each element still sums the
-  // chunks in index order)
+  // chunks in index order); then scaled by a power of two
   {
     constexpr int kE = E * E / kEigThreads;
     double v[kE];
@@ -572,12 +654,21 @@ __global__ __launch_bounds__(kEigThreads) void eig_kernel(const S b) {
 #pragma unroll
         for (int u = 0; u < 4; ++u) v[k] += t[k][u];
     }
+    double amax = 0.0;
+#pragma unroll
+    for (int k = 0; k < kE; ++k) amax = fmax(amax, fabs(v[k]));
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) amax = fmax(amax, __shfl_xor(amax, off));
+    if (lane == 0) red[wave] = amax;
+    __syncthreads();
+    amax = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+    const double sc = amax > 0.0 ? ldexp(1.0, -ilogb(amax)) : 1.0;
 #pragma unroll
     for (int k = 0; k < kE; ++k) {
       const int e = tid + kEigThreads * k;
       if (e < np * np) {
         const int p = e / np, q = e - p * np;
-        A[p][q] = v[k];
+        Abuf[0][p][q] = v[k] * sc;
         V[p][q] = p == q ? 1.0 : 0.0;
       }
     }
@@ -586,21 +677,19 @@ __global__ __launch_bounds__(kEigThreads) void eig_kernel(const S b) {
   // both kinds: the half x half 2x2 blocks of A (pair k1 rows, pair k2
   // columns: A <- J^T A J on the block) and the np x half column pairs of V
   // (V <- V J); codes k1 * 64 + k2 and k * 64 + i, or -1 past the end
-  constexpr int kItemsA = IA, kItemsV = IV;
-  int itemA[kItemsA], itemV[kItemsV];
+  int itemA[IA], itemV[IV];
   const int nblk = half * half, nv = np * half;
 #pragma unroll
-  for (int t = 0; t < kItemsA; ++t) {
+  for (int t = 0; t < IA; ++t) {
     const int e = tid + kEigThreads * t;
     itemA[t] = e < nblk ? (e / half) * 64 + (e % half) : -1;   // -1: none (loads a dummy)
   }
 #pragma unroll
-  for (int t = 0; t < kItemsV; ++t) {
+  for (int t = 0; t < IV; ++t) {
     const int e = tid + kEigThreads * t;
     itemV[t] = e < nv ? (e / np) * 64 + (e % np) : -1;
   }
   __syncthreads();
-  const int wave = tid >> 6, lane = tid & 63;
   // the pair (p < q) of rotation k in a round: fixed by the round-robin
   // ordering, so every thread computes it instead of reading it
   // (selects only: a branch here would split every item's loads)
@@ -614,15 +703,11 @@ __global__ __launch_bounds__(kEigThreads) void eig_kernel(const S b) {
     p = min(a, c);
     q = max(a, c);
   };
-  // Pairs of two indices that currently rank below the r largest diagonal
-  // entries are not rotated: such a rotation only mixes directions that are
-  // dropped, so it changes neither the kept eigenvectors nor their decoupling.
-  // Once no other pair rotates, a Gershgorin bound checks that the unreduced
-  // block of those indices lies below every kept diagonal entry (so the kept
-  // ones are the r largest eigenvalues); if it does not, full sweeps resume.
+  int cur = 0;   // the copy of A that holds the current matrix
   bool skip_dropped = M.r < n;
   bool converged = false;
   for (int sweep = 0; sweep < kEigMaxSweeps; ++sweep) {
+    double (*A)[E + 1] = Abuf[cur];
     bool rotated = false;   // any rotation in this sweep (wave-uniform, equal in every wave)
     uint64_t dropped = 0;   // indices ranked r or later by diagonal (ties: lower index first)
     if (skip_dropped) {
@@ -639,24 +724,27 @@ __global__ __launch_bounds__(kEigThreads) void eig_kernel(const S b) {
       dropped = __ballot(d);
     }
     for (int round = 0; round < np - 1; ++round) {
-      // every wave computes the round's ell/2 disjoint rotations (lane k:
-      // rotation k), so no wave waits for another's parameters
+      double (*Ac)[E + 1] = Abuf[cur];
+      double (*An)[E + 1] = Abuf[cur ^ 1];
       bool rot_now = false;
       if (lane < half) {
         int p, q;
         pair_of(lane, round, p, q);
         double c = 1.0, sn = 0.0;
         if (q < n && !(((dropped >> p) & 1) && ((dropped >> q) & 1))) {
-          const double apq = A[p][q], app = A[p][p], aqq = A[q][q];
-          if (fabs(apq) > tol * fmax(fabs(app), fabs(aqq))) {
-            // t = tan of the rotation angle, the root of t^2 + 2 theta t - 1
-            // of smaller magnitude, theta = (a_qq - a_pp) / (2 a_pq):
-            // t = 2 a_pq / (d + sign(d) sqrt(d^2 + 4 a_pq^2)), d = a_qq - a_pp
-            // (one square root and one division); c = 1 / sqrt(1 + t^2)
-            const double d = aqq - app;
-            const double root = sqrt(fma(d, d, 4.0 * apq * apq));
-            const double t = (2.0 * apq) / (d >= 0.0 ? d + root : d - root);
-            c = 1.0 / sqrt(fma(t, t, 1.0));
+          const double apq = Ac[p][q], app = Ac[p][p], aqq = Ac[q][q];
+          // t = tan of the rotation angle, the root of t^2 + 2 theta t - 1
+          // of smaller magnitude, theta = (a_qq - a_pp) / (2 a_pq):
+          // t = 2 a_pq / (d + sign(d) sqrt(d^2 + 4 a_pq^2)), d = a_qq - a_pp;
+          // c = 1 / sqrt(1 + t^2).  A pair whose d^2 + 4 a_pq^2 is below the
+          // normal range (entries below 1e-154 of the largest) counts as
+          // decoupled.
+          const double d = aqq - app;
+          const double x = fma(d, d, 4.0 * apq * apq);
+          if (fabs(apq) > tol * fmax(fabs(app), fabs(aqq)) && x >= 2.2250738585072014e-308) {
+            const double root = x * rsq_nr(x);
+            const double t = 2.0 * apq * rcp_nr(d >= 0.0 ? d + root : d - root);
+            c = rsq_nr(fma(t, t, 1.0));
             sn = t * c;
             rot_now = true;
           }
@@ -665,30 +753,31 @@ __global__ __launch_bounds__(kEigThreads) void eig_kernel(const S b) {
       }
       // identical in every wave, so every wave takes the same branch
       const bool round_rot = __any(rot_now);
-      rotated |= round_rot;
-      __syncthreads();   // every read of A for the rotations is done
       if (!round_rot) continue;
+      rotated = true;
+      __builtin_amdgcn_wave_barrier();
+      __atomic_signal_fence(__ATOMIC_SEQ_CST);
       // every load of this thread's items first (straight-line: an absent
-      // item loads the entries of block (0, 0)), then the updates; an item
-      // whose rotations are both the identity stores nothing
-      double blk[kItemsA][4], vv[kItemsV][2];
-      double2 r1[kItemsA], r2[kItemsA], rv[kItemsV];
-      int ia[kItemsA][4], iv[kItemsV][3];
+      // item loads the entries of block (0, 0)), then the updates; every
+      // block of the other copy is written
+      double blk[IA][4], vv[IV][2];
+      double2 r1[IA], r2[IA], rv[IV];
+      int ia[IA][4], iv[IV][3];
 #pragma unroll
-      for (int t = 0; t < kItemsA; ++t) {
+      for (int t = 0; t < IA; ++t) {
         const int code = itemA[t] < 0 ? 0 : itemA[t];
         const int k1 = code >> 6, k2 = code & 63;
         pair_of(k1, round, ia[t][0], ia[t][1]);
         pair_of(k2, round, ia[t][2], ia[t][3]);
         r1[t] = rot_cs[wave][k1];
         r2[t] = rot_cs[wave][k2];
-        blk[t][0] = A[ia[t][0]][ia[t][2]];
-        blk[t][1] = A[ia[t][0]][ia[t][3]];
-        blk[t][2] = A[ia[t][1]][ia[t][2]];
-        blk[t][3] = A[ia[t][1]][ia[t][3]];
+        blk[t][0] = Ac[ia[t][0]][ia[t][2]];
+        blk[t][1] = Ac[ia[t][0]][ia[t][3]];
+        blk[t][2] = Ac[ia[t][1]][ia[t][2]];
+        blk[t][3] = Ac[ia[t][1]][ia[t][3]];
       }
 #pragma unroll
-      for (int t = 0; t < kItemsV; ++t) {
+      for (int t = 0; t < IV; ++t) {
         const int code = itemV[t] < 0 ? 0 : itemV[t];
         const int k = code >> 6;
         iv[t][0] = code & 63;
@@ -698,21 +787,21 @@ __global__ __launch_bounds__(kEigThreads) void eig_kernel(const S b) {
         vv[t][1] = V[iv[t][0]][iv[t][2]];
       }
 #pragma unroll
-      for (int t = 0; t < kItemsA; ++t) {
-        if (itemA[t] >= 0 && (r1[t].y != 0.0 || r2[t].y != 0.0)) {
+      for (int t = 0; t < IA; ++t) {
+        if (itemA[t] >= 0) {
           const double c1 = r1[t].x, s1 = r1[t].y, c2 = r2[t].x, s2 = r2[t].y;
           const double a = blk[t][0], bb = blk[t][1], cc = blk[t][2], dd = blk[t][3];
           // rows (J^T from the left), then columns (J from the right)
           const double ra = c1 * a - s1 * cc, rb = c1 * bb - s1 * dd;
           const double rc = s1 * a + c1 * cc, rd = s1 * bb + c1 * dd;
-          A[ia[t][0]][ia[t][2]] = c2 * ra - s2 * rb;
-          A[ia[t][0]][ia[t][3]] = s2 * ra + c2 * rb;
-          A[ia[t][1]][ia[t][2]] = c2 * rc - s2 * rd;
-          A[ia[t][1]][ia[t][3]] = s2 * rc + c2 * rd;
+          An[ia[t][0]][ia[t][2]] = c2 * ra - s2 * rb;
+          An[ia[t][0]][ia[t][3]] = s2 * ra + c2 * rb;
+          An[ia[t][1]][ia[t][2]] = c2 * rc - s2 * rd;
+          An[ia[t][1]][ia[t][3]] = s2 * rc + c2 * rd;
         }
       }
 #pragma unroll
-      for (int t = 0; t < kItemsV; ++t) {
+      for (int t = 0; t < IV; ++t) {
         if (itemV[t] >= 0 && rv[t].y != 0.0) {
           const double cv = rv[t].x, sv = rv[t].y;
           const double vip = vv[t][0], viq = vv[t][1];
@@ -721,6 +810,7 @@ __global__ __launch_bounds__(kEigThreads) void eig_kernel(const S b) {
         }
       }
       __syncthreads();
+      cur ^= 1;
     }
     if (!rotated) {
       converged = true;
@@ -749,6 +839,8 @@ __global__ __launch_bounds__(kEigThreads) void eig_kernel(const S b) {
   }
   // sweeps exhausted with rotations still firing: W may be inaccurate
   if (!converged && tid == 0 && M.info) *M.info |= 8;
+  double (*A)[E + 1] = Abuf[cur];
+  double (*W)[E + 1] = Abuf[cur ^ 1];   // W[k][rank], zero padded
   // rank of each eigenvalue in descending order (ties: lower index first)
   __shared__ int rank_of[E];
   for (int i = tid; i < n; i += kEigThreads) {
@@ -763,95 +855,104 @@ __global__ __launch_bounds__(kEigThreads) void eig_kernel(const S b) {
       for (int k = 0; k < n; ++k) M.W[k * M.r + rank] = V[k][i];
   }
   if (!M.small) return;
+  const int r = M.r;
+  const int kp = (n + 3) & ~3, rp = (r + 15) & ~15;   // K padded to 4, columns to 16
+  for (int e = tid; e < kp * rp; e += kEigThreads) {
+    const int k = e / rp, j = e - k * rp;
+    W[k][j] = 0.0;
+  }
   __syncthreads();
-  // W into A (A[k][rank] = V[k][i]), then U = Q W with the column sign rule
   for (int e = tid; e < n * n; e += kEigThreads) {
     const int k = e / n, i = e - k * n;
-    if (rank_of[i] < M.r) A[k][rank_of[i]] = V[k][i];
+    if (rank_of[i] < r) W[k][rank_of[i]] = V[k][i];
   }
   __syncthreads();
-  const int r = M.r;
-  const int tpc = kEigThreads / r;            // threads per column
-  const int j = tid % r, slot = tid / r;      // column and this thread's row slot
-  const bool active = slot < tpc;
-  __shared__ double sQ[32][E + 1];
-  double best = -1.0, bval = 0.0;
-  int64_t bidx = INT64_MAX;
-  const bool f64 = M.udtype == TK_F64;
-  // rows of Q in chunks of 32, the next chunk's loads in flight (registers)
-  // while the current one is multiplied
-  constexpr int kPre = 32 * E / kEigThreads;
-  double pre[kPre];
-  auto fetch = [&](int64_t r0) {
-    const int rows = (int)min<int64_t>(32, M.m - r0);
+  // U = Q W: wave w takes row tiles w, w + 4, ...; lane l supplies
+  // Q[row0 + l%16][k0 + l/16] and W[k0 + l/16][16 ct + l%16]; register v of
+  // an accumulator holds row row0 + l/16 + 4 v, column 16 ct + l%16
+  constexpr int kCT = E / 16;
+  const int nct = rp / 16, nks = kp / 4, l16 = lane & 15, g = lane >> 4;
+  const int64_t nrt = (M.m + 15) / 16;
+  auto tile = [&](int64_t rt, doublex4 (&acc)[kCT]) {
 #pragma unroll
-    for (int u = 0; u < kPre; ++u) {
-      const int e = tid + kEigThreads * u;
-      pre[u] = (r0 < M.m && e < rows * n) ? M.Z[r0 * n + e] : 0.0;
+    for (int ct = 0; ct < kCT; ++ct) acc[ct] = doublex4{0.0, 0.0, 0.0, 0.0};
+    const int64_t row = rt * 16 + l16;
+    for (int ks = 0; ks < nks; ++ks) {
+      const int k = 4 * ks + g;
+      const double a = (row < M.m && k < n) ? M.Z[row * n + k] : 0.0;
+#pragma unroll
+      for (int ct = 0; ct < kCT; ++ct)
+        if (ct < nct) acc[ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, W[k][16 * ct + l16], acc[ct], 0, 0, 0);
     }
   };
-  fetch(0);
-  for (int64_t r0 = 0; r0 < M.m; r0 += 32) {
-    const int rows = (int)min<int64_t>(32, M.m - r0);
+  // pass 1: per column, the entry of largest magnitude (lowest row on ties)
+  double best[kCT], bval[kCT];
+  int64_t bidx[kCT];
 #pragma unroll
-    for (int u = 0; u < kPre; ++u) {
-      const int e = tid + kEigThreads * u;
-      if (e < rows * n) sQ[e / n][e % n] = pre[u];
-    }
-    fetch(r0 + 32);
-    __syncthreads();
-    if (active) {
-      for (int rr = slot; rr < rows; rr += tpc) {
-        double v = 0.0;
-        for (int k = 0; k < n; ++k) v = fma(sQ[rr][k], A[k][j], v);
-        const int64_t row = r0 + rr;
-        if (fabs(v) > best) { best = fabs(v); bval = v; bidx = row; }  // rows ascend
-        if (f64) static_cast<double*>(M.U)[row * r + j] = v;
-        else static_cast<float*>(M.U)[row * r + j] = (float)v;
-      }
-    }
-    __syncthreads();
+  for (int ct = 0; ct < kCT; ++ct) {
+    best[ct] = -1.0;
+    bval[ct] = 0.0;
+    bidx[ct] = INT64_MAX;
   }
-  // per column: largest |u|, lowest row on ties
-  __shared__ double cand_v[kEigThreads], cand_a[kEigThreads];
-  __shared__ int64_t cand_i[kEigThreads];
+  for (int64_t rt = wave; rt < nrt; rt += kEigThreads / 64) {
+    doublex4 acc[kCT];
+    tile(rt, acc);
+#pragma unroll
+    for (int ct = 0; ct < kCT; ++ct)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int64_t row = rt * 16 + g + 4 * v;   // ascending within a lane
+        const double u = acc[ct][v];
+        if (row < M.m && fabs(u) > best[ct]) {
+          best[ct] = fabs(u);
+          bval[ct] = u;
+          bidx[ct] = row;
+        }
+      }
+  }
+  __shared__ double cand_a[kEigThreads / 16][E], cand_v[kEigThreads / 16][E];
+  __shared__ int64_t cand_i[kEigThreads / 16][E];
   __shared__ double sgn[E];
-  cand_a[tid] = active ? best : -1.0;
-  cand_v[tid] = bval;
-  cand_i[tid] = bidx;
+#pragma unroll
+  for (int ct = 0; ct < kCT; ++ct)
+    if (ct < nct) {
+      cand_a[tid >> 4][16 * ct + l16] = best[ct];
+      cand_v[tid >> 4][16 * ct + l16] = bval[ct];
+      cand_i[tid >> 4][16 * ct + l16] = bidx[ct];
+    }
   __syncthreads();
   if (tid < r) {
     double ba = -1.0, bv = 0.0;
     int64_t bi = INT64_MAX;
-    for (int s2 = 0; s2 < tpc; ++s2) {
-      const int t = s2 * r + tid;
-      if (cand_a[t] > ba || (cand_a[t] == ba && cand_i[t] < bi)) {
-        ba = cand_a[t]; bv = cand_v[t]; bi = cand_i[t];
+    for (int s2 = 0; s2 < kEigThreads / 16; ++s2) {
+      const double ca = cand_a[s2][tid];
+      const int64_t ci = cand_i[s2][tid];
+      if (ca > ba || (ca == ba && ci < bi)) {
+        ba = ca;
+        bv = cand_v[s2][tid];
+        bi = ci;
       }
     }
     sgn[tid] = bv < 0.0 ? -1.0 : 1.0;
   }
   __syncthreads();
-  // flip the columns that need it (exact in either storage type); each thread
-  // rewrites only entries it wrote itself
-  // (eight loads in flight, then the eight stores)
-  if (active && sgn[j] < 0.0) {
-    constexpr int kB = 8;
-    for (int64_t row0 = slot; row0 < M.m; row0 += (int64_t)kB * tpc) {
-      double u[kB];
+  // pass 2: U with the sign rule applied
+  const bool f64 = M.udtype == TK_F64;
+  for (int64_t rt = wave; rt < nrt; rt += kEigThreads / 64) {
+    doublex4 acc[kCT];
+    tile(rt, acc);
 #pragma unroll
-      for (int q = 0; q < kB; ++q) {
-        const int64_t row = row0 + (int64_t)q * tpc;
-        if (row < M.m)
-          u[q] = f64 ? static_cast<const double*>(M.U)[row * r + j]
-                     : (double)static_cast<const float*>(M.U)[row * r + j];
-      }
+    for (int ct = 0; ct < kCT; ++ct) {
+      const int j = 16 * ct + l16;
+      if (ct < nct && j < r) {
+        const double sj = sgn[j];
 #pragma unroll
-      for (int q = 0; q < kB; ++q) {
-        const int64_t row = row0 + (int64_t)q * tpc;
-        if (row < M.m) {
-          if (f64) static_cast<double*>(M.U)[row * r + j] = -u[q];
-          else static_cast<float*>(M.U)[row * r + j] = (float)-u[q];
+        for (int v = 0; v < 4; ++v) {
+          const int64_t row = rt * 16 + g + 4 * v;
+          if (row < M.m) {
+            if (f64) static_cast<double*>(M.U)[row * r + j] = sj * acc[ct][v];
+            else static_cast<float*>(M.U)[row * r + j] = (float)(sj * acc[ct][v]);
+          }
         }
       }
     }
@@ -948,8 +1049,17 @@ hipError_t cholqr_impl(const S& src, const QRMat* host, int count, hipStream_t s
   if (any_small) {
     int64_t lds = 0;
     for (int i = 0; i < count; ++i)
-      if (host[i].small) lds = std::max<int64_t>(lds, host[i].m * host[i].ell * (int64_t)sizeof(double));
-    hipLaunchKernelGGL(cholqr_small_kernel<S>, dim3(count), dim3(256), (size_t)lds, st, src);
+      if (host[i].small)
+        lds = std::max<int64_t>(lds, ((host[i].m + 4) * host[i].ell + 64) * (int64_t)sizeof(double));
+    int ellmax = 1;
+    for (int i = 0; i < count; ++i)
+      if (host[i].small) ellmax = std::max(ellmax, host[i].ell);
+    if (ellmax <= 32)
+      hipLaunchKernelGGL((cholqr_small_kernel<S, 32>), dim3(count), dim3(256), (size_t)lds, st, src);
+    else if (ellmax <= 48)
+      hipLaunchKernelGGL((cholqr_small_kernel<S, 48>), dim3(count), dim3(256), (size_t)lds, st, src);
+    else
+      hipLaunchKernelGGL((cholqr_small_kernel<S, 64>), dim3(count), dim3(256), (size_t)lds, st, src);
   }
   if (!any_big) return hipGetLastError();
   // CholeskyQR2 needs two passes; every shifted pass owes two more plain ones,
@@ -982,14 +1092,18 @@ hipError_t wstep_impl(const S& src, const QRMat* host, int count, int ydtype, in
     }
     hipLaunchKernelGGL(mgram_kernel<S>, dim3(ncc, count), dim3(256), 0, st, src);
   }
-  // items per thread for the widest sketch: half^2 A blocks and np * half V pairs
+  // LDS sized for the widest sketch of the batch (E = 32 or 64): narrow
+  // sketches then fit several workgroups per CU, which a batch of many
+  // matrices needs
+  // items per thread for the widest sketch: half^2 A blocks and np * half V
+  // pairs; LDS sized for the widest sketch too (E = 32 or 64): narrow
+  // sketches then fit several workgroups per CU, which a batch of many
+  // matrices needs
   int ellmax = 1;
   for (int i = 0; i < count; ++i) ellmax = std::max(ellmax, host[i].ell);
   const int np = ellmax + (ellmax & 1), half = np / 2;
   const int ia = (int)ceil_div((int64_t)half * half, kEigThreads);
   const int iv = (int)ceil_div((int64_t)np * half, kEigThreads);
-  // LDS sized for the widest sketch too (E = 32 or 64): narrow sketches then
-  // fit several workgroups per CU, which a batch of many matrices needs
   if (np <= 32)
     hipLaunchKernelGGL((eig_kernel<S, 1, 2, 32>), dim3(count), dim3(kEigThreads), 0, st, src);
   else if (ia <= 2 && iv <= 4)

@@ -2,7 +2,9 @@
 residual) against the FP64 oracle on the same seeded inputs and sketches.
 
 Tolerances (relative reconstruction error eps vs the oracle's):
-FP64 1e-10, FP32 1e-5, BF16/FP16 3e-3 (as |eps_gpu - eps_or| / eps_or).
+FP64 1e-10, FP32 1e-5, BF16/FP16 3e-3 (as |eps_gpu - eps_or| / eps_or); the
+FP64 cases at 64^3 add four times the error's spread under unit-roundoff
+perturbations of the test matrices (tests/tucker_parity.py).
 Factor comparisons go through projectors and canonical column signs.
 """
 import math
@@ -13,6 +15,7 @@ import torch
 
 import oracle
 import synthgen
+import tucker_parity
 from synthgen import configs
 
 pytestmark = pytest.mark.gpu
@@ -54,7 +57,7 @@ def run_case(dims, ranks, decay, noise, p, ss, dtype, cfg, dense=False, core_fac
     return out
 
 
-def check_common(o, dtype, ptol):
+def check_common(o, dtype, ptol, eps_gate=None):
     # the gather is a copy: bit-exact
     for a, b in zip(o["Y"], o["Y_or"]):
         np.testing.assert_array_equal(a, b)
@@ -72,7 +75,8 @@ def check_common(o, dtype, ptol):
     # operand), so the core carries a few 1e-6 of max|G| where FP32 carries 1e-7
     ctol = {"f64": 1e-12, "f32": 1e-6, "bf16": 2e-5, "f16": 2e-5}[dtype]
     rel = abs(o["eps_gpu"] - o["eps_or"]) / o["eps_or"]
-    assert rel <= TOL[dtype], (o["eps_gpu"], o["eps_or"], rel)
+    gate = TOL[dtype] if eps_gate is None else eps_gate / o["eps_or"]
+    assert rel <= gate, (o["eps_gpu"], o["eps_or"], rel, gate)
     np.testing.assert_allclose(o["G"], G_chk, rtol=0, atol=ctol * scale)
 
 
@@ -80,7 +84,10 @@ def test_c1_fp64_sampled():
     c = configs.C1
     o = run_case(c.dims, c.ranks, c.decay, c.noise, c.p, synthgen.default_s(c.dims), c.dtype,
                  c.cfg_id)
-    check_common(o, "f64", 1e-10)
+    # 1e-10 of the error plus the error's own spread under unit-roundoff
+    # perturbations of the test matrices (about 6e-11 of it here)
+    spread = tucker_parity.eps_spread(o["X64"], c.ranks, o["sk"], o["eps_or"])
+    check_common(o, "f64", 1e-10, tucker_parity.eps_gate(o["eps_or"], spread, 1e-10))
     # thin QR is unique (R_ii > 0); its columns are determined to ~u kappa(Z)
     for z, zo, Z in zip(o["Q"], o["Q_or"], o["Z_or"]):
         sv = np.linalg.svd(Z, compute_uv=False)
@@ -94,7 +101,8 @@ def test_c1_fp64_sampled():
 def test_c1_fp64_dense_sketch():
     c = configs.C1
     o = run_case(c.dims, c.ranks, c.decay, c.noise, c.p, [0, 0, 0], c.dtype, c.cfg_id, dense=True)
-    check_common(o, "f64", 1e-10)
+    spread = tucker_parity.eps_spread(o["X64"], c.ranks, o["sk"], o["eps_or"])
+    check_common(o, "f64", 1e-10, tucker_parity.eps_gate(o["eps_or"], spread, 1e-10))
 
 
 def test_c1_exact_rank_shifted_qr():
@@ -116,8 +124,8 @@ def test_c1_q_core():
     c = configs.C1
     o = run_case(c.dims, c.ranks, c.decay, c.noise, c.p, synthgen.default_s(c.dims), c.dtype,
                  c.cfg_id, core_factor="Q")
-    rel = abs(o["eps_gpu"] - o["eps_or"]) / o["eps_or"]
-    assert rel <= TOL["f64"]
+    spread = tucker_parity.eps_spread(o["X64"], c.ranks, o["sk"], o["eps_or"], core_factor="Q")
+    assert abs(o["eps_gpu"] - o["eps_or"]) <= tucker_parity.eps_gate(o["eps_or"], spread, 1e-10)
     # Range(Q_k) includes noise directions determined only to ~u kappa(Z_k)
     for a, b, Z in zip(o["F"], o["Q_or"], o["Z_or"]):
         sv = np.linalg.svd(Z, compute_uv=False)
