@@ -558,6 +558,95 @@ __global__ __launch_bounds__(256) void qty_partial_kernel(const S b, int count) 
   }
 }
 
+// Small matrices (m x ell in one workgroup's reach), both products of the
+// Gram of M = Q^T Y in one kernel on v_mfma_f64_16x16x4f64, one workgroup per
+// 64-column chunk cc of Y:
+//   M_cc = Q^T Y[:, cc]   (ell x 64, K = m; wave w: columns 16 w .., every
+//                          16-row tile of ell; eight K steps of loads in
+//                          flight ahead of their multiplies)
+//   cpart[cc] = M_cc M_cc^T (K = 64, M_cc through LDS; wave w: tiles w,
+//                          w + 4, ... of the upper triangle)
+template <typename TY, typename S>
+__global__ __launch_bounds__(256) void qty_gram_kernel(const S b) {
+  const QRMat& M = b.get(blockIdx.y);
+  const int cc = blockIdx.x;
+  if (cc >= M.ncc) return;
+  __shared__ double sM[kMaxEll][kQRColChunk + 1];
+  const int ell = M.ell, tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int l16 = lane & 15, g = lane >> 4;
+  const int nt = (ell + 15) / 16;
+  const TY* Y = static_cast<const TY*>(M.Y);
+  const int64_t t = (int64_t)cc * kQRColChunk + 16 * wave + l16;   // this lane's column of Y
+  const bool tok = t < M.s;
+  constexpr int kMT = kMaxEll / 16, kB = 8;
+  doublex4 acc[kMT];
+#pragma unroll
+  for (int pt = 0; pt < kMT; ++pt) acc[pt] = doublex4{0.0, 0.0, 0.0, 0.0};
+  auto fetch = [&](int64_t k0, double (&qa)[kB][kMT], double (&yb)[kB]) {
+#pragma unroll
+    for (int u = 0; u < kB; ++u) {
+      const int64_t k = k0 + 4 * u + g;
+      const bool kok = k < M.m;
+      yb[u] = (kok && tok) ? to_double(Y[k * M.s + t]) : 0.0;
+#pragma unroll
+      for (int pt = 0; pt < kMT; ++pt) {
+        const int p = 16 * pt + l16;
+        qa[u][pt] = (kok && pt < nt && p < ell) ? M.Z[k * ell + p] : 0.0;
+      }
+    }
+  };
+  auto multiply = [&](const double (&qa)[kB][kMT], const double (&yb)[kB]) {
+#pragma unroll
+    for (int u = 0; u < kB; ++u)
+#pragma unroll
+      for (int pt = 0; pt < kMT; ++pt)
+        if (pt < nt) acc[pt] = __builtin_amdgcn_mfma_f64_16x16x4f64(qa[u][pt], yb[u], acc[pt], 0, 0, 0);
+  };
+  // two batches of loads: the next one in flight while the current one is
+  // multiplied (a batch past m loads zeros)
+  double qa0[kB][kMT], yb0[kB], qa1[kB][kMT], yb1[kB];
+  fetch(0, qa0, yb0);
+  for (int64_t k0 = 0; k0 < M.m; k0 += 8 * kB) {
+    fetch(k0 + 4 * kB, qa1, yb1);
+    multiply(qa0, yb0);
+    if (k0 + 4 * kB >= M.m) break;
+    fetch(k0 + 8 * kB, qa0, yb0);
+    multiply(qa1, yb1);
+  }
+  // register v of an accumulator: row 16 pt + l/16 + 4 v, column 16 w + l%16
+#pragma unroll
+  for (int pt = 0; pt < kMT; ++pt)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int p = 16 * pt + g + 4 * v;
+      if (pt < nt && p < ell) sM[p][16 * wave + l16] = acc[pt][v];
+    }
+  __syncthreads();
+  double* C = M.cpart + (int64_t)cc * ell * ell;
+  const int ntiles = nt * (nt + 1) / 2;
+  for (int tile = wave; tile < ntiles; tile += 4) {
+    int pi = 0, rem = tile;
+    while (rem >= nt - pi) { rem -= nt - pi; ++pi; }
+    const int pj = pi + rem;
+    doublex4 c = {0.0, 0.0, 0.0, 0.0};
+    const int ri = 16 * pi + l16, rj = 16 * pj + l16;
+#pragma unroll
+    for (int k0 = 0; k0 < kQRColChunk; k0 += 4) {
+      const double a = ri < ell ? sM[ri][k0 + g] : 0.0;
+      const double bb = rj < ell ? sM[rj][k0 + g] : 0.0;
+      c = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bb, c, 0, 0, 0);
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int p = 16 * pi + g + 4 * v, q = 16 * pj + l16;
+      if (p < ell && q < ell) {
+        C[p * ell + q] = c[v];
+        if (pi != pj) C[q * ell + p] = c[v];
+      }
+    }
+  }
+}
+
 // cpart[cc] = M_cc M_cc^T with M_cc = sum_rc mpart[rc][:, cc]
 template <typename S>
 __global__ __launch_bounds__(256) void mgram_kernel(const S b) {
@@ -1081,7 +1170,18 @@ hipError_t wstep_impl(const S& src, const QRMat* host, int count, int ydtype, in
   const int ncc = max_field(host, count, 1), nrb = max_field(host, count, 2);
   int64_t qty_blocks = 0;
   for (int i = 0; i < count; ++i) qty_blocks = host[i].qty_begin + (int64_t)host[i].nrc * host[i].ncc;
-  if (!gram_given) {
+  bool all_small = true;
+  for (int i = 0; i < count; ++i) all_small &= host[i].small != 0;
+  if (!gram_given && all_small) {
+    const dim3 gg((unsigned)ncc, (unsigned)count);
+    switch (ydtype) {
+      case TK_F64: hipLaunchKernelGGL((qty_gram_kernel<double, S>), gg, dim3(256), 0, st, src); break;
+      case TK_F32: hipLaunchKernelGGL((qty_gram_kernel<float, S>), gg, dim3(256), 0, st, src); break;
+      case TK_BF16: hipLaunchKernelGGL((qty_gram_kernel<bf16, S>), gg, dim3(256), 0, st, src); break;
+      case TK_F16: hipLaunchKernelGGL((qty_gram_kernel<f16, S>), gg, dim3(256), 0, st, src); break;
+      default: return hipErrorInvalidValue;
+    }
+  } else if (!gram_given) {
     const dim3 gq((unsigned)qty_blocks);
     switch (ydtype) {
       case TK_F64: hipLaunchKernelGGL((qty_partial_kernel<double, S>), gq, dim3(256), 0, st, src, count); break;
