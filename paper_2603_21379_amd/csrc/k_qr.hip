@@ -709,227 +709,15 @@ constexpr int kEigMaxSweeps = 60;
 
 // IA, IV: A-block and V-pair items per thread, sized by the launcher for the
 // widest sketch of the batch so the per-round loads are straight-line code
-template <typename S, int IA, int IV, int E>
-__global__ __launch_bounds__(kEigThreads) void eig_kernel(const S b) {
-  const QRMat& M = b.get(blockIdx.x);
-  __shared__ double Abuf[2][E][E + 1];
-  __shared__ double V[E][E + 1];
-  // (c, s) of the current round's rotations, one copy per wave
-  __shared__ double2 rot_cs[kEigThreads / 64][E / 2];
-  __shared__ double red[kEigThreads / 64];
-  const int n = M.ell, np = n + (n & 1), half = np / 2, tid = threadIdx.x;
-  const int wave = tid >> 6, lane = tid & 63;
-  const double tol = M.udtype == TK_F64 ? 4.0 * kUnit : 1e-12;
-  // summed Gram: every thread's elements over groups of four column chunks,
-  // all loads of a group in flight together (each element still sums the
-  // chunks in index order); then scaled by a power of two
-  {
-    constexpr int kE = E * E / kEigThreads;
-    double v[kE];
-#pragma unroll
-    for (int k = 0; k < kE; ++k) v[k] = 0.0;
-    for (int c0 = 0; c0 < M.ncc; c0 += 4) {
-      double t[kE][4];
-#pragma unroll
-      for (int k = 0; k < kE; ++k) {
-        const int e = tid + kEigThreads * k, p = e / np, q = e - (e / np) * np;
-        const bool live = e < np * np && p < n && q < n;
-#pragma unroll
-        for (int u = 0; u < 4; ++u)
-          t[k][u] = (live && c0 + u < M.ncc) ? M.cpart[(int64_t)(c0 + u) * n * n + p * n + q] : 0.0;
-      }
-#pragma unroll
-      for (int k = 0; k < kE; ++k)
-#pragma unroll
-        for (int u = 0; u < 4; ++u) v[k] += t[k][u];
-    }
-    double amax = 0.0;
-#pragma unroll
-    for (int k = 0; k < kE; ++k) amax = fmax(amax, fabs(v[k]));
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) amax = fmax(amax, __shfl_xor(amax, off));
-    if (lane == 0) red[wave] = amax;
-    __syncthreads();
-    amax = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
-    const double sc = amax > 0.0 ? ldexp(1.0, -ilogb(amax)) : 1.0;
-#pragma unroll
-    for (int k = 0; k < kE; ++k) {
-      const int e = tid + kEigThreads * k;
-      if (e < np * np) {
-        const int p = e / np, q = e - p * np;
-        Abuf[0][p][q] = v[k] * sc;
-        V[p][q] = p == q ? 1.0 : 0.0;
-      }
-    }
-  }
-  // this thread's items, in two loops of one kind each so a wave never runs
-  // both kinds: the half x half 2x2 blocks of A (pair k1 rows, pair k2
-  // columns: A <- J^T A J on the block) and the np x half column pairs of V
-  // (V <- V J); codes k1 * 64 + k2 and k * 64 + i, or -1 past the end
-  int itemA[IA], itemV[IV];
-  const int nblk = half * half, nv = np * half;
-#pragma unroll
-  for (int t = 0; t < IA; ++t) {
-    const int e = tid + kEigThreads * t;
-    itemA[t] = e < nblk ? (e / half) * 64 + (e % half) : -1;   // -1: none (loads a dummy)
-  }
-#pragma unroll
-  for (int t = 0; t < IV; ++t) {
-    const int e = tid + kEigThreads * t;
-    itemV[t] = e < nv ? (e / np) * 64 + (e % np) : -1;
-  }
-  __syncthreads();
-  // the pair (p < q) of rotation k in a round: fixed by the round-robin
-  // ordering, so every thread computes it instead of reading it
-  // (selects only: a branch here would split every item's loads)
-  auto pair_of = [&](int k, int round, int& p, int& q) {
-    const int m = np - 1;
-    int a = round + k, c = round - k;
-    a = a >= m ? a - m : a;
-    c = c < 0 ? c + m : c;
-    a = k == 0 ? m : a;
-    c = k == 0 ? round : c;
-    p = min(a, c);
-    q = max(a, c);
-  };
-  int cur = 0;   // the copy of A that holds the current matrix
-  bool skip_dropped = M.r < n;
-  bool converged = false;
-  for (int sweep = 0; sweep < kEigMaxSweeps; ++sweep) {
-    double (*A)[E + 1] = Abuf[cur];
-    bool rotated = false;   // any rotation in this sweep (wave-uniform, equal in every wave)
-    uint64_t dropped = 0;   // indices ranked r or later by diagonal (ties: lower index first)
-    if (skip_dropped) {
-      bool d = false;
-      if (lane < n) {
-        const double di = A[lane][lane];
-        int rk = 0;
-        for (int j = 0; j < n; ++j) {
-          const double dj = A[j][j];
-          rk += (dj > di) || (dj == di && j < lane);
-        }
-        d = rk >= M.r;
-      }
-      dropped = __ballot(d);
-    }
-    for (int round = 0; round < np - 1; ++round) {
-      double (*Ac)[E + 1] = Abuf[cur];
-      double (*An)[E + 1] = Abuf[cur ^ 1];
-      bool rot_now = false;
-      if (lane < half) {
-        int p, q;
-        pair_of(lane, round, p, q);
-        double c = 1.0, sn = 0.0;
-        if (q < n && !(((dropped >> p) & 1) && ((dropped >> q) & 1))) {
-          const double apq = Ac[p][q], app = Ac[p][p], aqq = Ac[q][q];
-          // t = tan of the rotation angle, the root of t^2 + 2 theta t - 1
-          // of smaller magnitude, theta = (a_qq - a_pp) / (2 a_pq):
-          // t = 2 a_pq / (d + sign(d) sqrt(d^2 + 4 a_pq^2)), d = a_qq - a_pp;
-          // c = 1 / sqrt(1 + t^2).  A pair whose d^2 + 4 a_pq^2 is below the
-          // normal range (entries below 1e-154 of the largest) counts as
-          // decoupled.
-          const double d = aqq - app;
-          const double x = fma(d, d, 4.0 * apq * apq);
-          if (fabs(apq) > tol * fmax(fabs(app), fabs(aqq)) && x >= 2.2250738585072014e-308) {
-            const double root = x * rsq_nr(x);
-            const double t = 2.0 * apq * rcp_nr(d >= 0.0 ? d + root : d - root);
-            c = rsq_nr(fma(t, t, 1.0));
-            sn = t * c;
-            rot_now = true;
-          }
-        }
-        rot_cs[wave][lane] = make_double2(c, sn);
-      }
-      // identical in every wave, so every wave takes the same branch
-      const bool round_rot = __any(rot_now);
-      if (!round_rot) continue;
-      rotated = true;
-      __builtin_amdgcn_wave_barrier();
-      __atomic_signal_fence(__ATOMIC_SEQ_CST);
-      // every load of this thread's items first (straight-line: an absent
-      // item loads the entries of block (0, 0)), then the updates; every
-      // block of the other copy is written
-      double blk[IA][4], vv[IV][2];
-      double2 r1[IA], r2[IA], rv[IV];
-      int ia[IA][4], iv[IV][3];
-#pragma unroll
-      for (int t = 0; t < IA; ++t) {
-        const int code = itemA[t] < 0 ? 0 : itemA[t];
-        const int k1 = code >> 6, k2 = code & 63;
-        pair_of(k1, round, ia[t][0], ia[t][1]);
-        pair_of(k2, round, ia[t][2], ia[t][3]);
-        r1[t] = rot_cs[wave][k1];
-        r2[t] = rot_cs[wave][k2];
-        blk[t][0] = Ac[ia[t][0]][ia[t][2]];
-        blk[t][1] = Ac[ia[t][0]][ia[t][3]];
-        blk[t][2] = Ac[ia[t][1]][ia[t][2]];
-        blk[t][3] = Ac[ia[t][1]][ia[t][3]];
-      }
-#pragma unroll
-      for (int t = 0; t < IV; ++t) {
-        const int code = itemV[t] < 0 ? 0 : itemV[t];
-        const int k = code >> 6;
-        iv[t][0] = code & 63;
-        pair_of(k, round, iv[t][1], iv[t][2]);
-        rv[t] = rot_cs[wave][k];
-        vv[t][0] = V[iv[t][0]][iv[t][1]];
-        vv[t][1] = V[iv[t][0]][iv[t][2]];
-      }
-#pragma unroll
-      for (int t = 0; t < IA; ++t) {
-        if (itemA[t] >= 0) {
-          const double c1 = r1[t].x, s1 = r1[t].y, c2 = r2[t].x, s2 = r2[t].y;
-          const double a = blk[t][0], bb = blk[t][1], cc = blk[t][2], dd = blk[t][3];
-          // rows (J^T from the left), then columns (J from the right)
-          const double ra = c1 * a - s1 * cc, rb = c1 * bb - s1 * dd;
-          const double rc = s1 * a + c1 * cc, rd = s1 * bb + c1 * dd;
-          An[ia[t][0]][ia[t][2]] = c2 * ra - s2 * rb;
-          An[ia[t][0]][ia[t][3]] = s2 * ra + c2 * rb;
-          An[ia[t][1]][ia[t][2]] = c2 * rc - s2 * rd;
-          An[ia[t][1]][ia[t][3]] = s2 * rc + c2 * rd;
-        }
-      }
-#pragma unroll
-      for (int t = 0; t < IV; ++t) {
-        if (itemV[t] >= 0 && rv[t].y != 0.0) {
-          const double cv = rv[t].x, sv = rv[t].y;
-          const double vip = vv[t][0], viq = vv[t][1];
-          V[iv[t][0]][iv[t][1]] = cv * vip - sv * viq;
-          V[iv[t][0]][iv[t][2]] = sv * vip + cv * viq;
-        }
-      }
-      __syncthreads();
-      cur ^= 1;
-    }
-    if (!rotated) {
-      converged = true;
-      if (dropped == 0) break;
-      double top_min = INFINITY, drop_max = -INFINITY;
-      if (lane < n) {
-        const double di = A[lane][lane];
-        if ((dropped >> lane) & 1) {
-          double rad = 0.0;
-          for (int j = 0; j < n; ++j)
-            if (j != lane && ((dropped >> j) & 1)) rad += fabs(A[lane][j]);
-          drop_max = di + rad;
-        } else {
-          top_min = di;
-        }
-      }
-#pragma unroll
-      for (int off = 32; off > 0; off >>= 1) {
-        top_min = fmin(top_min, __shfl_xor(top_min, off));
-        drop_max = fmax(drop_max, __shfl_xor(drop_max, off));
-      }
-      if (drop_max < top_min) break;
-      converged = false;
-      skip_dropped = false;
-    }
-  }
-  // sweeps exhausted with rotations still firing: W may be inaccurate
-  if (!converged && tid == 0 && M.info) *M.info |= 8;
-  double (*A)[E + 1] = Abuf[cur];
-  double (*W)[E + 1] = Abuf[cur ^ 1];   // W[k][rank], zero padded
+// The end of the W step for one matrix: the eigenvalues on the diagonal of
+// A, the eigenvectors in the columns of V (both in LDS); W (an E x (E + 1)
+// LDS array free for use) receives W.  Ranks the eigenvalues, then writes W
+// to global memory (large matrices) or U = Q W with the sign rule (small
+// ones).  Called by every thread of the 256-thread workgroup.
+template <int E>
+__device__ __forceinline__ void wstep_finish(const QRMat& M, double (*A)[E + 1], double (*V)[E + 1],
+                                             double (*W)[E + 1], int tid) {
+  const int n = M.ell, wave = tid >> 6, lane = tid & 63;
   // rank of each eigenvalue in descending order (ties: lower index first)
   __shared__ int rank_of[E];
   for (int i = tid; i < n; i += kEigThreads) {
@@ -1046,6 +834,227 @@ __global__ __launch_bounds__(kEigThreads) void eig_kernel(const S b) {
       }
     }
   }
+}
+
+template <typename S, int IA, int IV, int E>
+__global__ __launch_bounds__(kEigThreads) void eig_kernel(const S b) {
+  const QRMat& M = b.get(blockIdx.x);
+  __shared__ double Abuf[2][E][E + 1];
+  __shared__ double V[E][E + 1];
+  // (c, s) of the current round's rotations, one copy per wave
+  __shared__ double2 rot_cs[kEigThreads / 64][E / 2];
+  __shared__ double red[kEigThreads / 64];
+  const int n = M.ell, np = n + (n & 1), half = np / 2, tid = threadIdx.x;
+  const int wave = tid >> 6, lane = tid & 63;
+  const double tol = M.udtype == TK_F64 ? 4.0 * kUnit : 1e-12;
+  // summed Gram: every thread's elements over groups of four column chunks,
+  // all loads of a group in flight together (each element still sums the
+  // chunks in index order); then scaled by a power of two
+  {
+    constexpr int kE = E * E / kEigThreads;
+    double v[kE];
+#pragma unroll
+    for (int k = 0; k < kE; ++k) v[k] = 0.0;
+    for (int c0 = 0; c0 < M.ncc; c0 += 4) {
+      double t[kE][4];
+#pragma unroll
+      for (int k = 0; k < kE; ++k) {
+        const int e = tid + kEigThreads * k, p = e / np, q = e - (e / np) * np;
+        const bool live = e < np * np && p < n && q < n;
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+          t[k][u] = (live && c0 + u < M.ncc) ? M.cpart[(int64_t)(c0 + u) * n * n + p * n + q] : 0.0;
+      }
+#pragma unroll
+      for (int k = 0; k < kE; ++k)
+#pragma unroll
+        for (int u = 0; u < 4; ++u) v[k] += t[k][u];
+    }
+    double amax = 0.0;
+#pragma unroll
+    for (int k = 0; k < kE; ++k) amax = fmax(amax, fabs(v[k]));
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) amax = fmax(amax, __shfl_xor(amax, off));
+    if (lane == 0) red[wave] = amax;
+    __syncthreads();
+    amax = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+    const double sc = amax > 0.0 ? ldexp(1.0, -ilogb(amax)) : 1.0;
+#pragma unroll
+    for (int k = 0; k < kE; ++k) {
+      const int e = tid + kEigThreads * k;
+      if (e < np * np) {
+        const int p = e / np, q = e - p * np;
+        Abuf[0][p][q] = v[k] * sc;
+        V[p][q] = p == q ? 1.0 : 0.0;
+      }
+    }
+  }
+  // this thread's items, in two loops of one kind each so a wave never runs
+  // both kinds: the half x half 2x2 blocks of A (pair k1 rows, pair k2
+  // columns: A <- J^T A J on the block) and the np x half column pairs of V
+  // (V <- V J); codes k1 * 64 + k2 and k * 64 + i, or -1 past the end
+  int itemA[IA], itemV[IV];
+  const int nblk = half * half, nv = np * half;
+#pragma unroll
+  for (int t = 0; t < IA; ++t) {
+    const int e = tid + kEigThreads * t;
+    itemA[t] = e < nblk ? (e / half) * 64 + (e % half) : -1;   // -1: none (loads a dummy)
+  }
+#pragma unroll
+  for (int t = 0; t < IV; ++t) {
+    const int e = tid + kEigThreads * t;
+    itemV[t] = e < nv ? (e / np) * 64 + (e % np) : -1;
+  }
+  __syncthreads();
+  // the pair (p < q) of rotation k in a round: fixed by the round-robin
+  // ordering, so every thread computes it instead of reading it
+  // (selects only: a branch here would split every item's loads)
+  auto pair_of = [&](int k, int round, int& p, int& q) {
+    const int m = np - 1;
+    int a = round + k, c = round - k;
+    a = a >= m ? a - m : a;
+    c = c < 0 ? c + m : c;
+    a = k == 0 ? m : a;
+    c = k == 0 ? round : c;
+    p = min(a, c);
+    q = max(a, c);
+  };
+  int cur = 0;   // the copy of A that holds the current matrix
+  bool skip_dropped = M.r < n;
+  bool converged = false;
+  for (int sweep = 0; sweep < kEigMaxSweeps; ++sweep) {
+    double (*A)[E + 1] = Abuf[cur];
+    bool rotated = false;   // any rotation in this sweep (wave-uniform, equal in every wave)
+    uint64_t dropped = 0;   // indices ranked r or later by diagonal (ties: lower index first)
+    if (skip_dropped) {
+      bool d = false;
+      if (lane < n) {
+        const double di = A[lane][lane];
+        int rk = 0;
+        for (int j = 0; j < n; ++j) {
+          const double dj = A[j][j];
+          rk += (dj > di) || (dj == di && j < lane);
+        }
+        d = rk >= M.r;
+      }
+      dropped = __ballot(d);
+    }
+    for (int round = 0; round < np - 1; ++round) {
+      double (*Ac)[E + 1] = Abuf[cur];
+      double (*An)[E + 1] = Abuf[cur ^ 1];
+      bool rot_now = false;
+      if (lane < half) {
+        int p, q;
+        pair_of(lane, round, p, q);
+        // t = tan of the rotation angle, the root of t^2 + 2 theta t - 1 of
+        // smaller magnitude, theta = (a_qq - a_pp) / (2 a_pq):
+        // t = 2 a_pq / (d + sign(d) sqrt(d^2 + 4 a_pq^2)), d = a_qq - a_pp;
+        // c = 1 / sqrt(1 + t^2).  A pair whose d^2 + 4 a_pq^2 is below the
+        // normal range (entries below 1e-154 of the largest) counts as
+        // decoupled.  Computed for every pair (selects, no branch: the pad
+        // index np - 1 exists in A), then kept or replaced by the identity.
+        const double apq = Ac[p][q], app = Ac[p][p], aqq = Ac[q][q];
+        const double d = aqq - app;
+        const double x = fma(d, d, 4.0 * apq * apq);
+        rot_now = q < n && !(((dropped >> p) & 1) && ((dropped >> q) & 1)) &&
+                  fabs(apq) > tol * fmax(fabs(app), fabs(aqq)) && x >= 2.2250738585072014e-308;
+        const double xs = rot_now ? x : 1.0;
+        const double root = xs * rsq_nr(xs);
+        const double t = 2.0 * apq * rcp_nr(d >= 0.0 ? d + root : d - root);
+        const double c = rsq_nr(fma(t, t, 1.0));
+        rot_cs[wave][lane] = rot_now ? make_double2(c, t * c) : make_double2(1.0, 0.0);
+      }
+      // identical in every wave, so every wave takes the same branch
+      const bool round_rot = __any(rot_now);
+      if (!round_rot) continue;
+      rotated = true;
+      __builtin_amdgcn_wave_barrier();
+      __atomic_signal_fence(__ATOMIC_SEQ_CST);
+      // every load of this thread's items first (straight-line: an absent
+      // item loads the entries of block (0, 0)), then the updates; every
+      // block of the other copy is written
+      double blk[IA][4], vv[IV][2];
+      double2 r1[IA], r2[IA], rv[IV];
+      int ia[IA][4], iv[IV][3];
+#pragma unroll
+      for (int t = 0; t < IA; ++t) {
+        const int code = itemA[t] < 0 ? 0 : itemA[t];
+        const int k1 = code >> 6, k2 = code & 63;
+        pair_of(k1, round, ia[t][0], ia[t][1]);
+        pair_of(k2, round, ia[t][2], ia[t][3]);
+        r1[t] = rot_cs[wave][k1];
+        r2[t] = rot_cs[wave][k2];
+        blk[t][0] = Ac[ia[t][0]][ia[t][2]];
+        blk[t][1] = Ac[ia[t][0]][ia[t][3]];
+        blk[t][2] = Ac[ia[t][1]][ia[t][2]];
+        blk[t][3] = Ac[ia[t][1]][ia[t][3]];
+      }
+#pragma unroll
+      for (int t = 0; t < IV; ++t) {
+        const int code = itemV[t] < 0 ? 0 : itemV[t];
+        const int k = code >> 6;
+        iv[t][0] = code & 63;
+        pair_of(k, round, iv[t][1], iv[t][2]);
+        rv[t] = rot_cs[wave][k];
+        vv[t][0] = V[iv[t][0]][iv[t][1]];
+        vv[t][1] = V[iv[t][0]][iv[t][2]];
+      }
+#pragma unroll
+      for (int t = 0; t < IA; ++t) {
+        if (itemA[t] >= 0) {
+          const double c1 = r1[t].x, s1 = r1[t].y, c2 = r2[t].x, s2 = r2[t].y;
+          const double a = blk[t][0], bb = blk[t][1], cc = blk[t][2], dd = blk[t][3];
+          // rows (J^T from the left), then columns (J from the right)
+          const double ra = c1 * a - s1 * cc, rb = c1 * bb - s1 * dd;
+          const double rc = s1 * a + c1 * cc, rd = s1 * bb + c1 * dd;
+          An[ia[t][0]][ia[t][2]] = c2 * ra - s2 * rb;
+          An[ia[t][0]][ia[t][3]] = s2 * ra + c2 * rb;
+          An[ia[t][1]][ia[t][2]] = c2 * rc - s2 * rd;
+          An[ia[t][1]][ia[t][3]] = s2 * rc + c2 * rd;
+        }
+      }
+#pragma unroll
+      for (int t = 0; t < IV; ++t) {
+        if (itemV[t] >= 0 && rv[t].y != 0.0) {
+          const double cv = rv[t].x, sv = rv[t].y;
+          const double vip = vv[t][0], viq = vv[t][1];
+          V[iv[t][0]][iv[t][1]] = cv * vip - sv * viq;
+          V[iv[t][0]][iv[t][2]] = sv * vip + cv * viq;
+        }
+      }
+      __syncthreads();
+      cur ^= 1;
+    }
+    if (!rotated) {
+      converged = true;
+      if (dropped == 0) break;
+      double top_min = INFINITY, drop_max = -INFINITY;
+      if (lane < n) {
+        const double di = A[lane][lane];
+        if ((dropped >> lane) & 1) {
+          double rad = 0.0;
+          for (int j = 0; j < n; ++j)
+            if (j != lane && ((dropped >> j) & 1)) rad += fabs(A[lane][j]);
+          drop_max = di + rad;
+        } else {
+          top_min = di;
+        }
+      }
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) {
+        top_min = fmin(top_min, __shfl_xor(top_min, off));
+        drop_max = fmax(drop_max, __shfl_xor(drop_max, off));
+      }
+      if (drop_max < top_min) break;
+      converged = false;
+      skip_dropped = false;
+    }
+  }
+  // sweeps exhausted with rotations still firing: W may be inaccurate
+  if (!converged && tid == 0 && M.info) *M.info |= 8;
+  double (*A)[E + 1] = Abuf[cur];
+  double (*W)[E + 1] = Abuf[cur ^ 1];   // W[k][rank], zero padded
+  wstep_finish<E>(M, A, V, W, tid);
 }
 
 // utmp = Q W for a block of 64 rows, plus per-block column argmax of |u|.
