@@ -64,22 +64,15 @@ def parse():
 # HBM bytes per launch of the streaming pass, from rocprofv3 FETCH_SIZE and
 # WRITE_SIZE runs scaled by a plain copy of known size; valid only for the
 # kernel source it was taken on
-# HBM traffic summaries of the FP32 streaming pass, one per kernel form: the
-# BF16-piece form (default) and the FP32-MFMA form (TKMI_CORE_X6=0)
+# HBM traffic summaries of the streaming pass over X: the FP32 256^4 pass
+# (the BF16-piece form, fused2x6_kernel)
 TRAFFIC = {
     "x6": (os.path.join(ROOT, "profiles", "core_stream_x6_256x4_traffic.txt"),
            os.path.join(ROOT, "paper_2603_21379_amd", "csrc", "k_core_x6.hip")),
-    "f32": (os.path.join(ROOT, "profiles", "core_stream_f32_256x4_traffic.txt"),
-            os.path.join(ROOT, "paper_2603_21379_amd", "csrc", "k_core_f32.hip")),
     # the uneven shape's pass over X: the middle-mode MFMA contraction (112 -> 28)
     "uneven": (os.path.join(ROOT, "profiles", "core_pass_mode_mfma_uneven_5x10x12x112x80x270_traffic.txt"),
                os.path.join(ROOT, "paper_2603_21379_amd", "csrc", "k_mode_f32.hip")),
 }
-
-
-def core_form():
-    e = os.environ.get("TKMI_CORE_X6")
-    return "f32" if (e is not None and e.strip() == "0") else "x6"
 
 
 def measured_traffic(workload_name):
@@ -87,7 +80,7 @@ def measured_traffic(workload_name):
     form that runs, or None when the summary is missing or the kernel source
     changed since the counters were taken."""
     import hashlib
-    path, src = TRAFFIC["uneven" if workload_name.startswith("c8_") else core_form()]
+    path, src = TRAFFIC["uneven" if workload_name.startswith("c8_") else "x6"]
     if not os.path.exists(path):
         return None
     kv = {}

@@ -104,8 +104,11 @@ __device__ __forceinline__ floatx4 mma_f32(float a, float b, floatx4 c) {
 // TX: float, bf16 or f16.  NK: column chunks of stage 1 (32 columns for
 // 16-bit, 16 for FP32), NT: row tiles (16 rows), both upper bounds of the
 // runtime sizes.  H3: accumulate the third trailing mode.
+// two workgroups per CU, except for the FP32 forms with the third mode and
+// six or more K chunks, whose registers do not fit 256 (one, without spills)
 template <typename TX, int NK, int NT, int TG, bool H3, int NBUF>
-__global__ __launch_bounds__(256, 2) void core_slab_kernel(const CoreSlab p) {
+__global__ __launch_bounds__(256, (sizeof(TX) == 4 && H3 && NK >= 6) ? 1 : 2) void core_slab_kernel(
+    const CoreSlab p) {
   constexpr bool kF32 = sizeof(TX) == 4;
   constexpr int kChunk = kF32 ? 16 : 32;      // columns per chunk
   constexpr int kPer = kF32 ? 4 : 8;          // values per lane per chunk
@@ -422,23 +425,13 @@ hipError_t launch_variant(CoreSlab p, size_t lds, hipStream_t st) {
   return hipGetLastError();
 }
 
-// Units of loads in the register pipeline (2 or 3): 0 = default (2).
-static int slab_nbuf() {
-  static int env = [] {
-    const char* e = getenv("TKMI_SLAB_NBUF");
-    return e ? atoi(e) : 0;
-  }();
-  return env;
-}
-
 // TG tiles per unit keep one unit's loads at 32-48 registers
 template <typename TX, int NK, int NT, bool H3>
 hipError_t launch_depth(const CoreSlab& p, size_t lds, hipStream_t st) {
   constexpr int kTG0 = 12 / NK < 1 ? 1 : 12 / NK;
   constexpr int kTG1 = kTG0 > NT ? NT : kTG0;
   constexpr int TG = sizeof(TX) == 4 ? kTG1 : (kTG1 < 2 ? 2 : kTG1 & ~1);
-  if (slab_nbuf() == 3) return launch_variant<TX, NK, NT, TG, H3, 3>(p, lds, st);
-  return launch_variant<TX, NK, NT, TG, H3, 2>(p, lds, st);
+  return launch_variant<TX, NK, NT, TG, H3, 2>(p, lds, st);   // two units of loads in flight
 }
 
 template <typename TX, int NK, int NT>

@@ -255,16 +255,6 @@ bool fused2x6_supported(int dtype, int order, const int64_t* dims, const int32_t
          fused2x6_lds_bytes((int)nI, (int)nJ) <= 80 * 1024;
 }
 
-// The BF16-piece form is the default for the shapes it covers;
-// TKMI_CORE_X6=0 selects the FP32-MFMA pass instead.
-bool fused2x6_enabled() {
-  static const bool on = [] {
-    const char* e = getenv("TKMI_CORE_X6");
-    return !(e && atoi(e) == 0);
-  }();
-  return on;
-}
-
 template <int NBUF>
 hipError_t launch_x6_depth(CoreFused2 p, hipStream_t st) {
   const size_t lds = fused2x6_lds_bytes(p.nI, p.nJ);
@@ -282,17 +272,7 @@ hipError_t launch_x6_depth(CoreFused2 p, hipStream_t st) {
   return hipGetLastError();
 }
 
-// Units of loads in the register pipeline (TKMI_X6_NBUF: 2 or 3).
-static int x6_nbuf() {
-  static const int v = [] {
-    const char* e = getenv("TKMI_X6_NBUF");
-    return e ? atoi(e) : 2;
-  }();
-  return v;
-}
-
-hipError_t launch_fused2x6(const CoreFused2& p, hipStream_t st) {
-  return x6_nbuf() == 3 ? launch_x6_depth<3>(p, st) : launch_x6_depth<2>(p, st);
-}
+// two units of loads in the register pipeline (three spill)
+hipError_t launch_fused2x6(const CoreFused2& p, hipStream_t st) { return launch_x6_depth<2>(p, st); }
 
 }  // namespace tk

@@ -279,14 +279,20 @@ __device__ __forceinline__ bool chol_wave(double (*G)[E + 1], int n, int lane, d
         TK_WAVE_SYNC();   // the previous step's reads of rowbuf are done
         rowbuf[lane] = rjq;
         TK_WAVE_SYNC();
-        // row j of R: every load issued before the updates
-        double rj_row[E];
+        if constexpr (E <= 48) {
+          // row j of R: every load issued before the updates
+          double rj_row[E];
 #pragma unroll
-        for (int p = j + 1; p < E; ++p) rj_row[p] = rowbuf[p];
-        __builtin_amdgcn_sched_barrier(0);
+          for (int p = j + 1; p < E; ++p) rj_row[p] = rowbuf[p];
+          __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-        for (int p = j + 1; p < E; ++p) col[p] = fma(-rj_row[p], rjq, col[p]);
-        __builtin_amdgcn_sched_barrier(0);
+          for (int p = j + 1; p < E; ++p) col[p] = fma(-rj_row[p], rjq, col[p]);
+          __builtin_amdgcn_sched_barrier(0);
+        } else {
+          // (64 columns: a second register row would not fit)
+#pragma unroll
+          for (int p = j + 1; p < E; ++p) col[p] = fma(-rowbuf[p], rjq, col[p]);
+        }
         if (lane == 0) rinv[j] = inv;
       }
     }
@@ -414,20 +420,32 @@ __global__ __launch_bounds__(256) void cholqr_small_kernel(const S b) {
         // delta_ij as a 0/1 factor from integer arithmetic (a compare here
         // would be kept as a mask for every row at once)
         const double delta = (double)(1 - min(1, abs(lane - i)));
-        // row i of R: every load issued before the products
-        double ri[E];
+        if constexpr (E <= 48) {
+          // row i of R: every load issued before the products
+          double ri[E];
 #pragma unroll
-        for (int k = i + 1; k < E; ++k) ri[k] = G[i][k];
-        const double rii = rinv[i];
-        __builtin_amdgcn_sched_barrier(0);
-        double s0 = 0.0, s1 = 0.0;
+          for (int k = i + 1; k < E; ++k) ri[k] = G[i][k];
+          const double rii = rinv[i];
+          __builtin_amdgcn_sched_barrier(0);
+          double s0 = 0.0, s1 = 0.0;
 #pragma unroll
-        for (int k = i + 1; k < E; ++k) {
-          if ((k - i) & 1) s0 = fma(ri[k], x[k], s0);
-          else s1 = fma(ri[k], x[k], s1);
+          for (int k = i + 1; k < E; ++k) {
+            if ((k - i) & 1) s0 = fma(ri[k], x[k], s0);
+            else s1 = fma(ri[k], x[k], s1);
+          }
+          x[i] = (delta - (s0 + s1)) * rii;
+          __builtin_amdgcn_sched_barrier(0);
+        } else {
+          // (64 columns: a register row of R would not fit beside x)
+          double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+          for (int k = i + 1; k < E; ++k) {
+            if ((k - i) & 1) s0 = fma(G[i][k], x[k], s0);
+            else s1 = fma(G[i][k], x[k], s1);
+          }
+          x[i] = (delta - (s0 + s1)) * rinv[i];
+          if ((i & 3) == 0) __builtin_amdgcn_sched_barrier(0);
         }
-        x[i] = (delta - (s0 + s1)) * rii;
-        __builtin_amdgcn_sched_barrier(0);
       }
       TK_WAVE_SYNC();   // every read of R is done
 #pragma unroll

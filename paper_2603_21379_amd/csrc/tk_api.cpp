@@ -15,6 +15,8 @@
 
 #include <stdlib.h>
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 #include "tk_kernels.hpp"
 
 namespace tk {
@@ -31,6 +33,15 @@ tk_status set_error(tk_status s, const char* fmt, ...) {
   return s;
 }
 void clear_error() { g_last_error.clear(); }
+
+// a roctx range around each C-ABI call, named after the entry point (seen
+// by rocprofv3 --marker-trace; free when no tool listens)
+struct ApiRange {
+  explicit ApiRange(const char* name) { roctxRangePushA(name); }
+  ~ApiRange() { roctxRangePop(); }
+  ApiRange(const ApiRange&) = delete;
+  ApiRange& operator=(const ApiRange&) = delete;
+};
 
 // ------------------------------------------------------------------ profiler
 static bool g_prof_on = false;
@@ -380,7 +391,7 @@ tk_status run_core_pass(const void* X, int xdt, int order, const int64_t* dims,
     f.nJ = (int32_t)dims[order - 1];
     f.cI = cols[order - 2];
     f.cJ = cols[order - 1];
-    const bool x6 = fused2x6_enabled() && fused2x6_supported(xdt, order, dims, cols);
+    const bool x6 = fused2x6_supported(xdt, order, dims, cols);
     TK_HIP(profile_begin(st));
     TK_HIP(x6 ? launch_fused2x6(f, st) : launch_fused2_f32(f, st));
     TK_HIP(profile_end(st));
@@ -1138,6 +1149,7 @@ void tk_profile_enable(int32_t on) { g_prof_on = on != 0; }
 
 tk_status tk_profile_read(double* ms, int64_t* launches, int32_t reset) {
   clear_error();
+  const ApiRange range_("tk_profile_read");
   double total = 0.0;
   const size_t pairs = g_prof_used / 2;
   for (size_t i = 0; i < pairs; ++i) {
@@ -1157,6 +1169,7 @@ tk_status tucker_draw_sketches(int32_t nunits, const int64_t* ncols, const int32
                                uint64_t seed, int64_t* const* idx, void* const* omega, int32_t omega_dtype,
                                void* stream) {
   clear_error();
+  const ApiRange range_("tucker_draw_sketches");
   if (nunits < 1 || nunits > kMaxUnits)
     return set_error(TK_EINVAL, "tucker_draw_sketches: nunits %d outside [1, %d]", nunits, kMaxUnits);
   if (!ncols || !s || !ell || !idx || !omega)
@@ -1186,6 +1199,7 @@ int32_t tk_stream_read_blocks(void) { return (int32_t)stream_read_blocks(); }
 
 tk_status tk_stream_read(const void* x, int64_t bytes, double* partials, int32_t npartials, void* stream) {
   clear_error();
+  const ApiRange range_("tk_stream_read");
   if (!x || !partials || bytes < 0) return set_error(TK_EINVAL, "tk_stream_read: null buffer or negative size");
   const int32_t blocks = (int32_t)stream_read_blocks();
   if (npartials < blocks)
@@ -1197,6 +1211,7 @@ tk_status tk_stream_read(const void* x, int64_t bytes, double* partials, int32_t
 tk_status tucker_sketch_all_modes(const tk_tensor* X, const tk_sketch* sk, double* const* Z,
                                   void* const* Y, void* ws, size_t* ws_bytes, void* stream) {
   clear_error();
+  const ApiRange range_("tucker_sketch_all_modes");
   int64_t N;
   if (tk_status s = check_tensor(X, "tucker_sketch_all_modes", &N)) return s;
   if (!sk || !Z) return set_error(TK_EINVAL, "tucker_sketch_all_modes: sk or Z is NULL");
@@ -1226,6 +1241,7 @@ tk_status tucker_sketch_all_modes(const tk_tensor* X, const tk_sketch* sk, doubl
 
 tk_status tucker_sketch_all_modes_noalloc(const tk_tensor* X, const tk_sketch* sk, double* const* Z,
                                           void* const* Y, void* stream) {
+  const ApiRange range_("tucker_sketch_all_modes_noalloc");
   // the same validation, plan and kernels as tucker_sketch_all_modes, with
   // the fixed scratch array as the workspace: nothing is allocated
   size_t need = 0;
@@ -1246,6 +1262,7 @@ tk_status tucker_qr(int32_t nmat, const int64_t* m, const int32_t* ell, double* 
                     void* const* U, int32_t udtype, int32_t* info, void* ws, size_t* ws_bytes,
                     void* stream) {
   clear_error();
+  const ApiRange range_("tucker_qr");
   if (nmat < 0) return set_error(TK_EINVAL, "tucker_qr: nmat < 0");
   if (!ws_bytes) return set_error(TK_EINVAL, "tucker_qr: ws_bytes is NULL");
   if (nmat > 0 && (!m || !ell || !Z)) return set_error(TK_EINVAL, "tucker_qr: m, ell or Z is NULL");
@@ -1330,6 +1347,7 @@ tk_status tucker_qr(int32_t nmat, const int64_t* m, const int32_t* ell, double* 
 tk_status tucker_core(const tk_tensor* X, const void* const* F, const int32_t* cols, void* G,
                       void* ws, size_t* ws_bytes, void* stream) {
   clear_error();
+  const ApiRange range_("tucker_core");
   int64_t N;
   if (tk_status s = check_tensor(X, "tucker_core", &N)) return s;
   if (tk_status s = check_factors(X->order, X->dims, F, cols, "tucker_core")) return s;
@@ -1612,6 +1630,7 @@ tk_status tucker_reconstruct(int32_t order, const int64_t* dims, int32_t fdtype,
                              void* Xhat, double* resid2, void* ws, size_t* ws_bytes,
                              void* stream) {
   clear_error();
+  const ApiRange range_("tucker_reconstruct");
   return reconstruct_impl(order, dims, fdtype, G, F, cols, Xref, Xhat, nullptr, nullptr, 0.0, resid2, ws,
                           ws_bytes, stream);
 }
@@ -1664,6 +1683,7 @@ tk_status htucker_decompose(const tk_tensor* X, const tk_tree* tree, const int32
                             const tk_sketch* sk, void* const* U, void* const* B, int32_t* info,
                             void* ws, size_t* ws_bytes, void* stream) {
   clear_error();
+  const ApiRange range_("htucker_decompose");
   int64_t N;
   if (tk_status s = check_tensor(X, "htucker_decompose", &N)) return s;
   const int d = X->order;
@@ -1987,6 +2007,7 @@ tk_status htucker_reconstruct(int32_t order, const int64_t* dims, const tk_tree*
                               void* Xhat, int32_t xhat_dtype, double* resid2, void* ws, size_t* ws_bytes,
                               void* stream) {
   clear_error();
+  const ApiRange range_("htucker_reconstruct");
   const char* nm = "htucker_reconstruct";
   HTFormat f;
   if (tk_status s = check_ht_format(order, dims, tree, rank, U, B, nm, f)) return s;
@@ -2042,6 +2063,7 @@ tk_status htucker_reconstruct_vjp(int32_t order, const int64_t* dims, const tk_t
                                   const void* H, int32_t h_dtype, void* const* Bbar, void* const* Ubar,
                                   void* ws, size_t* ws_bytes, void* stream) {
   clear_error();
+  const ApiRange range_("htucker_reconstruct_vjp");
   const char* nm = "htucker_reconstruct_vjp";
   HTFormat f;
   if (tk_status s = check_ht_format(order, dims, tree, rank, U, B, nm, f)) return s;
@@ -2169,6 +2191,7 @@ tk_status tucker_core_vjp(const tk_tensor* X, const void* const* F, const int32_
                           const void* Gbar, void* Xbar, void* const* Fbar, int32_t accumulate,
                           void* ws, size_t* ws_bytes, void* stream) {
   clear_error();
+  const ApiRange range_("tucker_core_vjp");
   int64_t N;
   if (tk_status s = check_tensor(X, "tucker_core_vjp", &N)) return s;
   if (X->dtype != TK_F64 && X->dtype != TK_F32)
@@ -2219,6 +2242,7 @@ tk_status tucker_reconstruct_vjp(int32_t order, const int64_t* dims, int32_t fdt
                                  const void* H, void* Gbar, void* const* Fbar, void* ws,
                                  size_t* ws_bytes, void* stream) {
   clear_error();
+  const ApiRange range_("tucker_reconstruct_vjp");
   if (order < 1 || order > TK_MAX_ORDER) return set_error(TK_EINVAL, "tucker_reconstruct_vjp: bad order %d", order);
   if (!dims) return set_error(TK_EINVAL, "tucker_reconstruct_vjp: dims is NULL");
   for (int k = 0; k < order; ++k)
@@ -2282,6 +2306,7 @@ tk_status tucker_projection_loss_vjp(const tk_tensor* X, const void* const* F, c
                                      const void* G, const double* lbar, void* Xbar, void* const* Fbar,
                                      void* ws, size_t* ws_bytes, void* stream) {
   clear_error();
+  const ApiRange range_("tucker_projection_loss_vjp");
   int64_t N;
   if (tk_status s = check_tensor(X, "tucker_projection_loss_vjp", &N)) return s;
   if (X->dtype != TK_F64 && X->dtype != TK_F32)
@@ -2363,6 +2388,7 @@ tk_status tucker_batch_plan_create(int32_t count, const tk_tensor* X, const int3
                                    const tk_sketch* sk, void* const* U, void* const* G, int32_t* info,
                                    void* ws, size_t* ws_bytes, void* stream, tk_batch_plan** plan) {
   clear_error();
+  const ApiRange range_("tucker_batch_plan_create");
   if (!ws_bytes) return set_error(TK_EINVAL, "tucker_batch_plan_create: ws_bytes is NULL");
   Workspace w;
   w.base = static_cast<char*>(ws);
@@ -2390,12 +2416,14 @@ tk_status tucker_batch_plan_create(int32_t count, const tk_tensor* X, const int3
 
 tk_status tucker_batch_run(const tk_batch_plan* plan, void* stream) {
   clear_error();
+  const ApiRange range_("tucker_batch_run");
   if (!plan) return set_error(TK_EINVAL, "tucker_batch_run: plan is NULL");
   return batch_run(plan->data, as_stream(stream));
 }
 
 tk_status tucker_batch_autotune(tk_batch_plan* plan, void* stream, char* report, size_t report_bytes) {
   clear_error();
+  const ApiRange range_("tucker_batch_autotune");
   if (!plan) return set_error(TK_EINVAL, "tucker_batch_autotune: plan is NULL");
   BatchPlanData& P = plan->data;
   hipStream_t st = as_stream(stream);

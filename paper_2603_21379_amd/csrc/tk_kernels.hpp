@@ -203,7 +203,6 @@ hipError_t launch_fused2_f32(const CoreFused2& p, hipStream_t st);
 // the same pass with the stage-1 products on BF16 matrix cores at FP32
 // accuracy (three-piece split, six products); n_I, n_J in [64, 512]
 bool fused2x6_supported(int dtype, int order, const int64_t* dims, const int32_t* cols);
-bool fused2x6_enabled();
 hipError_t launch_fused2x6(const CoreFused2& p, hipStream_t st);
 
 // ---------------------------------------------------------------- small-mode streaming core
