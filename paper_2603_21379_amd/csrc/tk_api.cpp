@@ -1469,6 +1469,72 @@ tk_status reconstruct_impl(int32_t order, const int64_t* dims, int32_t fdtype, c
     TK_HIP(profile_end(st));
     return TK_OK;
   }
+  // small trailing modes (n <= 64, ranks <= 16), residual only, FP32 factors:
+  // expand the leading modes (the last of them into FP32), then one MFMA pass
+  // over X (BF16, FP16 or FP32) for the two trailing modes and the residual
+  if (Xref && resid2 && !Xhat && !D && fdtype == TK_F32 &&
+      resid_slab_supported(Xref->dtype, order, dims, cols)) {
+    int64_t shape[TK_MAX_ORDER];
+    for (int k = 0; k < order; ++k) shape[k] = cols[k];
+    int64_t mx = 1;
+    for (int k = 0; k < order - 2; ++k) {
+      shape[k] = dims[k];
+      mx = std::max(mx, prod(shape, 0, order));
+    }
+    Workspace w;
+    w.base = static_cast<char*>(ws);
+    double* buf[2] = {w.take<double>((size_t)mx), w.take<double>((size_t)mx)};
+    float* T32 = w.take<float>((size_t)mx);
+    int64_t smax = 0;
+    for (int k = 0; k < order; ++k) smax = std::max(smax, mode_product_scratch(dims[k], cols[k]));
+    double* mt = w.take<double>((size_t)smax);
+    const int64_t A = prod(dims, 0, order - 2);
+    double* partials = w.take<double>((size_t)2 * resid_slab_waves(A));
+    if (!ws) {
+      *ws_bytes = w.off;
+      return TK_OK;
+    }
+    if (*ws_bytes < w.off)
+      return set_error(TK_EWORKSPACE, "tucker_reconstruct: workspace %zu < required %zu", *ws_bytes, w.off);
+    hipStream_t st = as_stream(stream);
+    for (int k = 0; k < order; ++k) shape[k] = cols[k];
+    const void* cur = G;
+    int cur_dt = fdtype;
+    for (int k = 0; k < order - 2; ++k) {
+      const bool last = k == order - 3;
+      ModeProduct mp{};
+      mp.in = cur;
+      mp.A = prod(shape, 0, k);
+      mp.Q = shape[k];
+      mp.B = prod(shape, k + 1, order);
+      mp.P = (int32_t)dims[k];
+      mp.M = F[k];
+      mp.Mt = mt;
+      mp.rs = cols[k];   // M[p][q] = F[p][q]
+      mp.cs = 1;
+      mp.out = last ? (void*)T32 : (void*)buf[k & 1];
+      TK_HIP(launch_mode_product(mp, cur_dt, last ? TK_F32 : TK_F64, fdtype, st));
+      shape[k] = dims[k];
+      cur = mp.out;
+      cur_dt = last ? TK_F32 : TK_F64;
+    }
+    ResidSlab r{};
+    r.X = Xref->data;
+    r.T = T32;
+    r.FI = static_cast<const float*>(F[order - 2]);
+    r.FJ = static_cast<const float*>(F[order - 1]);
+    r.partials = partials;
+    r.resid2 = resid2;
+    r.A = A;
+    r.nI = (int32_t)dims[order - 2];
+    r.nJ = (int32_t)dims[order - 1];
+    r.cI = cols[order - 2];
+    r.cJ = cols[order - 1];
+    TK_HIP(profile_begin(st));
+    TK_HIP(launch_resid_slab(r, Xref->dtype, st));
+    TK_HIP(profile_end(st));
+    return TK_OK;
+  }
   // FP32, last factor wider than 64 columns: expand modes 0 .. d-2 (the last
   // of them into FP32), the last mode on MFMA into X_hat (or a workspace
   // copy), then the residual over (X, X_hat) in one streaming pass

@@ -318,6 +318,25 @@ bool resid2_supported(int dtype, int order, const int64_t* dims, const int32_t* 
 int64_t resid2_waves(int64_t A);
 hipError_t launch_resid2_f32(const ResidFused2& p, hipStream_t st);
 
+// ---------------------------------------------------------------- small-mode streaming residual
+// sum (X[a] - F_I T[a] F_J^T)^2 and sum X[a]^2 over the A slabs (n_I x n_J,
+// both <= 64; ranks <= 16) of a BF16, FP16 or FP32 tensor, FP32 factors and T
+struct ResidSlab {
+  const void* X;
+  const float* T;       // A x c_I x c_J
+  const float* FI;      // n_I x c_I
+  const float* FJ;      // n_J x c_J
+  double* partials;     // [resid_slab_waves(A)][2]
+  double* resid2;       // [2] or nullptr
+  int64_t A;
+  int32_t nI, nJ, cI, cJ;
+  int32_t nwaves;       // set by the launcher
+  int32_t pad;
+};
+bool resid_slab_supported(int x_dtype, int order, const int64_t* dims, const int32_t* cols);
+int64_t resid_slab_waves(int64_t A);
+hipError_t launch_resid_slab(const ResidSlab& p, int x_dtype, hipStream_t st);
+
 // ---------------------------------------------------------------- H-Tucker transfers
 // B[i][j][k] = sum_{a,b} US[a*nr + b][i] Ul[a][j] Ur[b][k]
 struct Transfer {

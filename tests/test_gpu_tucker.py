@@ -240,6 +240,35 @@ def test_fp32_fused_residual_and_xhat(dims, cols):
     np.testing.assert_allclose(r2h[0], np.sum((X64 - ref) ** 2), rtol=2e-6)
 
 
+@pytest.mark.parametrize("dtype", ["f32", "bf16", "f16"])
+@pytest.mark.parametrize("dims,cols", [((30, 40, 40), (5, 10, 10)),       # the 40^6 slab shape
+                                       ((7, 9, 33, 17), (3, 4, 16, 7)),  # ragged tiles, full 16 ranks
+                                       ((3, 64, 64), (2, 16, 16)),       # largest slab
+                                       ((5000, 3, 5), (2, 2, 3))])       # many tiny slabs
+def test_small_mode_streaming_residual(dims, cols, dtype):
+    """The small-mode MFMA residual pass (BF16, FP16, FP32 tensors): the FP64
+    sums ||X - X_hat||^2, ||X||^2 against the oracle's on the stored values
+    and the same core and factors."""
+    from paper_2603_21379_amd import binding as Bd
+    rng = np.random.default_rng(11)
+    X64 = rng.standard_normal(dims)
+    Xs = synthgen.to_storage(X64, dtype)
+    Xo = synthgen.to_f64(Xs, dtype)
+    G = rng.standard_normal(cols).astype(np.float32)
+    F = [np.linalg.qr(rng.standard_normal((n, c)))[0].astype(np.float32) for n, c in zip(dims, cols)]
+    r2 = torch.zeros(2, dtype=torch.float64, device="cuda")
+    Bd.tucker_reconstruct(list(dims), torch.from_numpy(G).cuda(), [torch.from_numpy(f).cuda() for f in F],
+                          Xref=to_device(Xs, dtype), resid2=r2)
+    torch.cuda.synchronize()
+    ref = oracle.reconstruct(G.astype(np.float64), [f.astype(np.float64) for f in F])
+    r2h = r2.cpu().numpy()
+    # X_hat in FP32 (FP32 expanded core, FP32 MFMA): |d| ~ |x| here, so about
+    # 1e-7 relative in ||X - X_hat||^2; the squares summed in FP32 over at most
+    # 64 terms per lane and slab before the FP64 sum: within 64 u = 3.8e-6
+    np.testing.assert_allclose(r2h[1], np.sum(Xo ** 2), rtol=4e-6)
+    np.testing.assert_allclose(r2h[0], np.sum((Xo - ref) ** 2), rtol=4e-6)
+
+
 def _core_direct(dims, cols, dtype, seed):
     """G = X x_k F_k^T on the GPU vs the FP64 oracle on the stored values."""
     from paper_2603_21379_amd import binding as Bd
