@@ -324,7 +324,9 @@ tk_status tucker_projection_loss_vjp(const tk_tensor* X, const void* const* F, c
  * once): every mode of every tensor is sketched, orthonormalised, truncated
  * and projected by one fixed sequence of persistent launches (sketch, QR,
  * W step, streaming core pass, remaining modes), whatever the orders and
- * sizes of the tensors.  A plan holds the descriptor tables in the caller's
+ * sizes of the tensors; optionally followed by the reconstruction residual
+ * of every tensor (Tucker format, Section 3: the core expanded back over the
+ * leading modes, then one pass over X that never stores X_hat).  A plan holds the descriptor tables in the caller's
  * workspace; running it allocates nothing, does not synchronise and records
  * no memset, so a run can be captured in a HIP graph and replayed.
  *
@@ -341,6 +343,10 @@ tk_status tucker_projection_loss_vjp(const tk_tensor* X, const void* const* F, c
  *           row-major (U_k = Q_k W_k, sign rule as in tucker_qr).
  *   G       host array [count] of device outputs, r_1 x .. x r_d FP32.
  *   info    device int32 [sum of orders] or NULL (as in tucker_qr).
+ *   resid2  NULL, or device double [2 count]: every run then also writes
+ *           ||X_t - X_hat_t||_F^2 and ||X_t||_F^2 of tensor t at [2t], [2t+1]
+ *           (X_hat_t = G_t x_1 U_1 .. x_d U_d from this run's outputs; FP32
+ *           products, FP64 sums in an order fixed by the plan).
  *   ws      caller workspace; NULL is a size query (nothing else happens).
  *   stream  stream for the table upload (the call waits for it).
  *   plan    receives the plan (host object; valid while ws, the tensors,
@@ -354,7 +360,8 @@ tk_status tucker_projection_loss_vjp(const tk_tensor* X, const void* const* F, c
 typedef struct tk_batch_plan tk_batch_plan;
 tk_status tucker_batch_plan_create(int32_t count, const tk_tensor* X, const int32_t* ranks,
                                    const tk_sketch* sk, void* const* U, void* const* G, int32_t* info,
-                                   void* ws, size_t* ws_bytes, void* stream, tk_batch_plan** plan);
+                                   double* resid2, void* ws, size_t* ws_bytes, void* stream,
+                                   tk_batch_plan** plan);
 tk_status tucker_batch_run(const tk_batch_plan* plan, void* stream);
 tk_status tucker_batch_autotune(tk_batch_plan* plan, void* stream, char* report, size_t report_bytes);
 void tucker_batch_plan_destroy(tk_batch_plan* plan);

@@ -107,7 +107,7 @@ def lib():
                 "tucker_projection_loss_vjp": [C.POINTER(TkTensor), pp, i32p, vp, vp, vp, pp, vp, sz, vp],
             }
             sig["tucker_batch_plan_create"] = [C.c_int32, C.POINTER(TkTensor), i32p, C.POINTER(TkSketch),
-                                               pp, pp, vp, vp, sz, vp, C.POINTER(C.c_void_p)]
+                                               pp, pp, vp, vp, vp, sz, vp, C.POINTER(C.c_void_p)]
             sig["tucker_batch_run"] = [vp, vp]
             sig["tucker_batch_autotune"] = [vp, vp, C.c_char_p, C.c_size_t]
             L.tucker_sketch_all_modes_noalloc.argtypes = [C.POINTER(TkTensor), C.POINTER(TkSketch),
@@ -361,9 +361,15 @@ class BatchPlan:
     """Owner of a tucker_batch_plan: keeps the workspace, the descriptor
     arrays and the tensors they point to alive while the plan exists."""
 
-    def __init__(self, X, ranks, sketches, U, G, info=None, stream=None):
+    def __init__(self, X, ranks, sketches, U, G, info=None, resid2=None, stream=None):
+        """resid2: None, or a CUDA float64 tensor of 2 len(X) values that
+        every run fills with (||X_t - X_hat_t||^2, ||X_t||^2) per tensor."""
         n = len(X)
-        self._keep = (list(X), list(U), list(G), info, [t for sk in sketches for t in sk if t is not None])
+        if resid2 is not None and (resid2.dtype != torch.float64 or resid2.numel() < 2 * n
+                                   or not resid2.is_contiguous()):
+            raise ValueError("resid2 must be a contiguous float64 tensor of 2 len(X) values")
+        self._keep = (list(X), list(U), list(G), info, resid2,
+                      [t for sk in sketches for t in sk if t is not None])
         xd = (TkTensor * n)()
         for i, x in enumerate(X):
             xd[i] = tensor_desc(x)
@@ -375,13 +381,13 @@ class BatchPlan:
         f = lib().tucker_batch_plan_create
         nbytes = C.c_size_t(0)
         _check("tucker_batch_plan_create",
-               f(n, xd, rk, sk, Up, Gp, ptr(info), None, C.byref(nbytes), _stream(stream), None))
+               f(n, xd, rk, sk, Up, Gp, ptr(info), ptr(resid2), None, C.byref(nbytes), _stream(stream), None))
         dev = X[0].device
         self.ws = torch.empty(max(int(nbytes.value), 256), dtype=torch.uint8, device=dev)
         h = C.c_void_p()
         n2 = C.c_size_t(self.ws.numel())
         _check("tucker_batch_plan_create",
-               f(n, xd, rk, sk, Up, Gp, ptr(info), C.c_void_p(self.ws.data_ptr()), C.byref(n2),
+               f(n, xd, rk, sk, Up, Gp, ptr(info), ptr(resid2), C.c_void_p(self.ws.data_ptr()), C.byref(n2),
                  _stream(stream), C.byref(h)))
         self.handle = h
         self.ws_bytes = int(nbytes.value)

@@ -13,7 +13,8 @@
 // batch_mode_kernel: one remaining mode of every tensor that still has one,
 //   out[a][p][b] = sum_q F[q][p] in[a][q][b], as the single-tensor MFMA mode
 //   contraction; each descriptor's units are padded to whole workgroups so a
-//   workgroup shares one F^T table.
+//   workgroup shares one F^T table.  The same kernel expands a core back over
+//   a mode (F read transposed, 32 output rows per descriptor).
 #include "tk_kernels.hpp"
 
 namespace tk {
@@ -242,7 +243,7 @@ __global__ __launch_bounds__(256) void batch_mode_kernel(const BatchMode bm) {
   const int Qp = (int)((m.Q + 2 * kKB - 1) / (2 * kKB)) * 2 * kKB;
   for (int e = threadIdx.x; e < Qp * 32; e += blockDim.x) {
     const int q = e >> 5, p = e & 31;
-    sF[e] = (q < m.Q && p < m.P) ? m.F[(int64_t)q * m.P + p] : 0.0f;
+    sF[e] = (q < m.Q && p < m.P) ? m.F[m.ftrans ? (int64_t)p * m.Q + q : (int64_t)q * m.P + p] : 0.0f;
   }
   __syncthreads();
 
@@ -294,7 +295,7 @@ __global__ __launch_bounds__(256) void batch_mode_kernel(const BatchMode bm) {
   }
   if (bq < nb) compute(bq * 2 * kKB, bufA);
   if (!colok) return;
-  float* out = m.out + a * (int64_t)m.P * m.B;
+  float* out = m.out + a * m.out_slab;
   const int ncol = (int)min<int64_t>(4, m.B - b);
 #pragma unroll
   for (int v = 0; v < 16; ++v) {

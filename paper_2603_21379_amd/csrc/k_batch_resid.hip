@@ -1,0 +1,255 @@
+// Batching form of the reconstruction residual (Tucker format, Section 3;
+// the error measure of Algorithm 1's experiments) for many FP32 tensors of
+// uneven order and size in one launch:
+//   X_hat_t[a] = F_I T_t[a] F_J^T            (n_I x n_J slabs of tensor t)
+//   r2_t = sum (X_t - X_hat_t)^2,  x2_t = sum X_t^2
+// where T_t[a] (c_I x c_J) is the core of tensor t expanded over its leading
+// modes (done before this pass by the batched mode contraction), so X is read
+// once and X_hat is never stored.
+//
+// The work list is the chunk schedule of the batched core pass (chunks of
+// consecutive slabs of one tensor, assigned to waves on the host), built for
+// this kernel's resident waves.  Per slab, on v_mfma_f32_16x16x4f32:
+//  stage 1  P = T[a] F_J^T (c_I x n_J) into the wave's LDS table;
+//  stage 2  the transposed tiles (F_I P)^T = P^T F_I^T, so register v of
+//           lane l holds X_hat[16 it + l%16][16 jt + 4 (l/16) + v]: four
+//           consecutive columns of one row, which meet X loaded as one
+//           16-byte buffer load per tile (rows past n_I read zero from past
+//           the slab; columns past n_J of the last column tile are masked).
+// The tile counts are a template parameter chosen per chunk from the
+// tensor's trailing sizes, so small tensors do not pay for the largest.
+// Squares are summed in FP32 per lane and slab, then in FP64; each chunk
+// writes one (r2, x2) pair and a second kernel sums a tensor's chunks in
+// order, so the result does not depend on the schedule's timing.
+#include "tk_kernels.hpp"
+
+namespace tk {
+namespace {
+
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef unsigned int uintx4 __attribute__((ext_vector_type(4)));
+
+constexpr int kWaves = 4;
+constexpr int kRsrcWord3 = 0x00020000;
+constexpr int kPW = kBatchMaxN + 1;   // row stride of the P table (floats)
+
+__device__ __forceinline__ floatx4 mma16(float a, float b, floatx4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+// per wave: F_I and F_J of the chunk's tensor ([i][k], row stride 17) and the P table
+constexpr int kFW = kBatchMaxC + 1;
+constexpr int kWaveLds = 2 * kBatchMaxN * kFW + kBatchMaxC * kPW;   // floats
+
+template <int NT, int D>
+__device__ __forceinline__ void resid_chunk(const BatchTensor& td, int64_t a0, int64_t a1, float* wl, int lane,
+                                            double& r2, double& x2) {
+  const int g = lane >> 4, l16 = lane & 15;
+  const int nI = td.nI, nJ = td.nJ, cI = td.cI, cJ = td.cJ;
+  const int kI = (cI + 3) >> 2, kJ = (cJ + 3) >> 2;
+  const int nTI = (nI + 15) >> 4, nTJ = (nJ + 15) >> 4;
+  float(*sFI)[kFW] = reinterpret_cast<float(*)[kFW]>(wl);
+  float(*sFJ)[kFW] = reinterpret_cast<float(*)[kFW]>(wl + kBatchMaxN * kFW);
+  float(*sP)[kPW] = reinterpret_cast<float(*)[kPW]>(wl + 2 * kBatchMaxN * kFW);
+  // the factors of this tensor (zero past n and c); the previous chunk's
+  // reads of these tables came first in this wave's program order
+  for (int e = lane; e < 16 * NT * 16; e += 64) {
+    const int i = e >> 4, k = e & 15;
+    sFI[i][k] = (i < nI && k < cI) ? td.FI[i * cI + k] : 0.0f;
+    sFJ[i][k] = (i < nJ && k < cJ) ? td.FJ[i * cJ + k] : 0.0f;
+  }
+  __builtin_amdgcn_wave_barrier();
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+  const uint32_t rowb = (uint32_t)nJ * 4u, slab_bytes = (uint32_t)(nI * nJ) * 4u;
+  // this lane's byte offset of tile (0, jt): row l%16, columns 16 jt + 4 (l/16) ..
+  uint32_t coff[NT];
+#pragma unroll
+  for (int jt = 0; jt < NT; ++jt) {
+    const int col = 16 * jt + 4 * g;
+    coff[jt] = (jt < nTJ && col < nJ) ? (uint32_t)l16 * rowb + (uint32_t)col * 4u : 0x80000000u;
+  }
+  uintx4 lastmask;
+  {
+    const int valid = nJ - (16 * (nTJ - 1) + 4 * g);
+#pragma unroll
+    for (int c = 0; c < 4; ++c) lastmask[c] = c < valid ? 0xFFFFFFFFu : 0u;
+  }
+  const int cIJ = cI * cJ;
+  // T[a] as the stage-1 A operand: lane l gives T[a][l%16][4 ks + l/16]
+  uint32_t toff[4];
+#pragma unroll
+  for (int ks = 0; ks < 4; ++ks) {
+    const int k = 4 * ks + g;
+    toff[ks] = (l16 < cI && k < cJ) ? (uint32_t)(l16 * cJ + k) * 4u : 0x80000000u;
+  }
+  // the loads of one slab (X in the stage-2 layout, its T block); a slab
+  // past the chunk gets empty ranges (every load reads zero, no traffic)
+  auto issue = [&](int64_t a, uintx4 (&xr)[NT][NT], float (&ta)[4]) {
+    const bool live = a < a1;
+    const char* xs = reinterpret_cast<const char*>(td.X) + (live ? a : a0) * (int64_t)slab_bytes;
+#pragma unroll
+    for (int it = 0; it < NT; ++it) {
+      // one range per row tile (from its first row to the slab's end), so
+      // the lane offsets are the same for every row tile
+      const int rt = 16 * it * (int)rowb;
+      const bool on = live && it < nTI;
+      const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+          const_cast<char*>(xs) + (on ? rt : 0), (short)0, on ? (int)slab_bytes - rt : 0, kRsrcWord3);
+#pragma unroll
+      for (int jt = 0; jt < NT; ++jt)
+        xr[it][jt] = __builtin_bit_cast(uintx4, __builtin_amdgcn_raw_buffer_load_b128(rs, coff[jt], 0, 0));
+    }
+    const __amdgpu_buffer_rsrc_t rt = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<float*>(td.T) + (live ? a : a0) * cIJ, (short)0, live ? cIJ * 4 : 0, kRsrcWord3);
+#pragma unroll
+    for (int ks = 0; ks < 4; ++ks) ta[ks] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rt, toff[ks], 0, 0));
+  };
+  auto compute = [&](const uintx4 (&xr)[NT][NT], const float (&ta)[4]) {
+    // stage 1: P = T[a] F_J^T (B operand lane l: F_J[16 jt + l%16][4 ks + l/16])
+#pragma unroll
+    for (int jt = 0; jt < NT; ++jt) {
+      if (jt >= nTJ) continue;
+      float fj[4];
+#pragma unroll
+      for (int ks = 0; ks < 4; ++ks) fj[ks] = sFJ[16 * jt + l16][4 * ks + g];
+      floatx4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+      for (int ks = 0; ks < 4; ++ks)
+        if (ks < kJ) acc = mma16(ta[ks], fj[ks], acc);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) sP[4 * g + v][16 * jt + l16] = acc[v];
+    }
+    // ordered LDS accesses of one wave: the reads below see the writes
+    __builtin_amdgcn_wave_barrier();
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    // stage 2 and the squares (A operand lane l: P[4 ks + l/16][16 jt + l%16])
+    float r2t = 0.0f, x2t = 0.0f;
+#pragma unroll
+    for (int it = 0; it < NT; ++it) {
+      if (it >= nTI) continue;
+      float fi[4];   // B operand lane l: F_I[16 it + l%16][4 ks + l/16]
+#pragma unroll
+      for (int ks = 0; ks < 4; ++ks) fi[ks] = sFI[16 * it + l16][4 * ks + g];
+#pragma unroll
+      for (int jt = 0; jt < NT; ++jt) {
+        if (jt >= nTJ) continue;
+        floatx4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+        for (int ks = 0; ks < 4; ++ks)
+          if (ks < kI) acc = mma16(sP[4 * ks + g][16 * jt + l16], fi[ks], acc);
+        uintx4 xu = xr[it][jt];
+        if (jt == nTJ - 1) xu &= lastmask;
+        const floatx4 x = __builtin_bit_cast(floatx4, xu);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const float d = x[v] - acc[v];
+          r2t = fmaf(d, d, r2t);
+          x2t = fmaf(x[v], x[v], x2t);
+        }
+      }
+    }
+    r2 += (double)r2t;
+    x2 += (double)x2t;
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    __builtin_amdgcn_wave_barrier();   // this slab's reads of P precede the next slab's writes
+  };
+  // D slabs in flight: slot s of a group is multiplied while the loads of
+  // the D - 1 slabs after it are pending.  Full groups carry no exit test
+  // (one would leave skipped loads pending at the loop head and force a wait
+  // for all of them); the tail multiplies the slabs still in flight.
+  uintx4 xr[D][NT][NT];
+  float ta[D][4];
+  int64_t next = a0;
+#pragma unroll
+  for (int s = 0; s < D - 1; ++s) issue(next++, xr[s], ta[s]);
+  int64_t left = a1 - a0;
+  for (; left >= D; left -= D) {
+#pragma unroll
+    for (int s = 0; s < D; ++s) {
+      const int ls = (s + D - 1) % D;
+      issue(next++, xr[ls], ta[ls]);
+      __builtin_amdgcn_sched_barrier(0);
+      compute(xr[s], ta[s]);
+    }
+  }
+#pragma unroll
+  for (int s = 0; s < D - 1; ++s)
+    if (s < left) compute(xr[s], ta[s]);
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+  __builtin_amdgcn_wave_barrier();   // the reads of the factor tables precede the next chunk's writes
+}
+
+__global__ __launch_bounds__(64 * kWaves, 2) void batch_resid_kernel(const BatchResid br) {
+  extern __shared__ float lds[];
+  float* wl = lds + (threadIdx.x >> 6) * kWaveLds;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int gwave = __builtin_amdgcn_readfirstlane((int)blockIdx.x * kWaves + wv);
+  if (gwave >= br.nwaves) return;   // no workgroup barrier follows
+  const int c_begin = wave_uniform(br.wave_begin[gwave]), c_end = wave_uniform(br.wave_begin[gwave + 1]);
+  for (int ci = c_begin; ci < c_end; ++ci) {
+    const int cid = wave_uniform(br.wave_chunks[ci]);
+    const BatchChunk ch = wave_uniform(br.chunks[cid]);
+    const BatchTensor td = wave_uniform(br.tensors[ch.tensor]);
+    const int nt = (max(td.nI, td.nJ) + 15) >> 4;
+    double r2 = 0.0, x2 = 0.0;
+    switch (nt) {
+      case 1: resid_chunk<1, 8>(td, ch.a0, ch.a1, wl, lane, r2, x2); break;
+      case 2: resid_chunk<2, 6>(td, ch.a0, ch.a1, wl, lane, r2, x2); break;
+      case 3: resid_chunk<3, 3>(td, ch.a0, ch.a1, wl, lane, r2, x2); break;
+      case 4: resid_chunk<4, 2>(td, ch.a0, ch.a1, wl, lane, r2, x2); break;
+      case 5: resid_chunk<5, 1>(td, ch.a0, ch.a1, wl, lane, r2, x2); break;
+      default: resid_chunk<6, 1>(td, ch.a0, ch.a1, wl, lane, r2, x2); break;
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+      r2 += __shfl_xor(r2, o);
+      x2 += __shfl_xor(x2, o);
+    }
+    if (lane == 0) {
+      br.partials[2 * cid] = r2;
+      br.partials[2 * cid + 1] = x2;
+    }
+  }
+}
+
+// one thread per tensor: its chunks' pairs in chunk order
+__global__ void batch_resid_sum_kernel(const double* partials, const int32_t* chunk_begin, int32_t count,
+                                       double* resid2) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= count) return;
+  double r2 = 0.0, x2 = 0.0;
+  for (int c = chunk_begin[t]; c < chunk_begin[t + 1]; ++c) {
+    r2 += partials[2 * c];
+    x2 += partials[2 * c + 1];
+  }
+  resid2[2 * t] = r2;
+  resid2[2 * t + 1] = x2;
+}
+
+}  // namespace
+
+int batch_resid_waves() {
+  int per_cu = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batch_resid_kernel, 64 * kWaves,
+                                                   kWaves * kWaveLds * sizeof(float)) != hipSuccess ||
+      per_cu < 1)
+    per_cu = 1;
+  int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
+    cus = 256;
+  return per_cu * cus * kWaves;
+}
+
+hipError_t launch_batch_resid(const BatchResid& br, hipStream_t st) {
+  if (br.count <= 0) return hipSuccess;
+  if (br.nwaves > 0) {
+    hipLaunchKernelGGL(batch_resid_kernel, dim3((unsigned)ceil_div(br.nwaves, kWaves)), dim3(64 * kWaves),
+                       kWaves * kWaveLds * sizeof(float), st, br);
+    if (hipError_t e = hipGetLastError()) return e;
+  }
+  hipLaunchKernelGGL(batch_resid_sum_kernel, dim3((unsigned)ceil_div(br.count, 256)), dim3(256), 0, st,
+                     br.partials, br.tensor_chunk_begin, br.count, br.resid2);
+  return hipGetLastError();
+}
+
+}  // namespace tk

@@ -328,7 +328,6 @@ __global__ __launch_bounds__(256) void cholqr_small_kernel(const S b) {
   for (int64_t e = tid; e < 4 * n + E; e += 256) sZ[mn + e] = 0.0;
   for (int e = tid; e < E * (E + 1); e += 256) (&G[0][0])[e] = 0.0;
   __syncthreads();
-  const int nt = (n + 15) / 16;
   int owed = 2, info = 0;
   for (int pass = 1; pass <= kQRMaxPasses && owed > 0; ++pass) {
     // Gram on MFMA: wave w takes the row groups 4 k + (0..3), k = w, w + 4,

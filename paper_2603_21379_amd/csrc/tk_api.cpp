@@ -856,6 +856,7 @@ tk_status run_grads(const void* Y, int d, const int64_t* dims, const void* const
 // no host synchronisation and no memset, so it can be captured in a graph.
 constexpr int kBatchWaveCap = 16384;              // schedule capacity (waves)
 constexpr int64_t kBatchChunkMin = 32 << 10;     // smallest chunk the tuner tries (bytes)
+constexpr int64_t kBatchResidChunk = 512 << 10;  // residual pass chunk (bytes)
 
 struct BatchPlanData {
   int count = 0;
@@ -878,6 +879,20 @@ struct BatchPlanData {
   BatchSlab bs{};
   int tg = 1, nbuf = 2;
   int64_t chunk_bytes = 512 << 10;
+  // residual (when requested): expansion of each core over its leading
+  // modes into the tensor's T, then the residual pass over its own schedule
+  double* resid2 = nullptr;
+  std::vector<std::vector<BatchModeDesc>> esteps;
+  std::vector<int64_t> estep_units, estep_qmax;
+  std::vector<BatchModeDesc*> d_esteps;
+  std::vector<BatchChunk> rchunks;
+  std::vector<int32_t> rwb, rwc, rtcb;
+  BatchChunk* d_rchunks = nullptr;
+  int32_t* d_rwb = nullptr;
+  int32_t* d_rwc = nullptr;
+  int32_t* d_rtcb = nullptr;
+  double* d_rpart = nullptr;
+  BatchResid br{};
 };
 
 int64_t batch_chunk_slabs(const BatchTensor& t, int64_t chunk_bytes) {
@@ -934,7 +949,8 @@ void batch_schedule(const std::vector<BatchTensor>& ts, int64_t chunk_bytes, int
 }
 
 tk_status plan_batch(Workspace& ws, int count, const tk_tensor* X, const int32_t* ranks,
-                     const tk_sketch* sk, void* const* U, void* const* G, int32_t* info, BatchPlanData& P) {
+                     const tk_sketch* sk, void* const* U, void* const* G, int32_t* info, double* resid2,
+                     BatchPlanData& P) {
   if (count < 1) return set_error(TK_EINVAL, "tucker_batch_plan_create: count = %d < 1", count);
   if (!X || !ranks || !sk || !U || !G)
     return set_error(TK_EINVAL, "tucker_batch_plan_create: a descriptor array is NULL");
@@ -992,6 +1008,8 @@ tk_status plan_batch(Workspace& ws, int count, const tk_tensor* X, const int32_t
   }
   // core: streaming pass per tensor, then the remaining modes step by step
   P.steps.assign(max_order - 2, {});
+  P.resid2 = resid2;
+  if (resid2) P.esteps.assign(max_order - 2, {});
   m0 = 0;
   for (int t = 0; t < count; ++t) {
     const tk_tensor& x = X[t];
@@ -1031,10 +1049,37 @@ tk_status plan_batch(Workspace& ws, int count, const tk_tensor* X, const int32_t
       md.Q = shape[k];
       md.B = prod(shape, k + 1, d);
       md.P = c[k];
+      md.out_slab = (int64_t)md.P * md.B;
       md.out = k == 0 ? static_cast<float*>(G[t]) : buf[s & 1];
       P.steps[s].push_back(md);
       shape[k] = c[k];
       cur = md.out;
+    }
+    if (resid2) {
+      // T = G x_0 U_0 .. x_{d-3} U_{d-3}: the same intermediate shapes as the
+      // projection in reverse, so its two buffers serve
+      for (int k = 0; k < d; ++k) shape[k] = c[k];
+      const float* ecur = static_cast<const float*>(G[t]);
+      for (int k = 0; k < d - 2; ++k) {
+        const int64_t n = x.dims[k];
+        float* out = k == d - 3 ? bt.T : buf[k & 1];
+        const int64_t Bk = prod(shape, k + 1, d);
+        for (int64_t p0 = 0; p0 < n; p0 += 32) {
+          BatchModeDesc md{};
+          md.in = ecur;
+          md.F = static_cast<const float*>(U[m0 + k]) + p0 * c[k];
+          md.out = out + p0 * Bk;
+          md.A = prod(shape, 0, k);
+          md.Q = c[k];
+          md.B = Bk;
+          md.P = (int32_t)std::min<int64_t>(32, n - p0);
+          md.out_slab = n * Bk;
+          md.ftrans = 1;
+          P.esteps[k].push_back(md);
+        }
+        shape[k] = n;
+        ecur = out;
+      }
     }
     P.tensors.push_back(bt);
     m0 += d;
@@ -1046,14 +1091,19 @@ tk_status plan_batch(Workspace& ws, int count, const tk_tensor* X, const int32_t
       qb += (int64_t)q.nrc * q.ncc;
     }
   }
-  P.step_units.assign(P.steps.size(), 0);
-  P.step_qmax.assign(P.steps.size(), 1);
-  for (size_t s = 0; s < P.steps.size(); ++s)
-    for (auto& md : P.steps[s]) {
-      md.unit_begin = P.step_units[s];
-      P.step_units[s] += batch_mode_units(md.A, md.B);
-      P.step_qmax[s] = std::max(P.step_qmax[s], md.Q);
-    }
+  auto number_units = [](std::vector<std::vector<BatchModeDesc>>& steps, std::vector<int64_t>& units,
+                         std::vector<int64_t>& qmax) {
+    units.assign(steps.size(), 0);
+    qmax.assign(steps.size(), 1);
+    for (size_t s = 0; s < steps.size(); ++s)
+      for (auto& md : steps[s]) {
+        md.unit_begin = units[s];
+        units[s] += batch_mode_units(md.A, md.B);
+        qmax[s] = std::max(qmax[s], md.Q);
+      }
+  };
+  number_units(P.steps, P.step_units, P.step_qmax);
+  number_units(P.esteps, P.estep_units, P.estep_qmax);
   // device tables
   P.chunk_cap = 0;
   for (auto& bt : P.tensors) P.chunk_cap += (size_t)ceil_div(bt.A, batch_chunk_slabs(bt, kBatchChunkMin));
@@ -1065,6 +1115,29 @@ tk_status plan_batch(Workspace& ws, int count, const tk_tensor* X, const int32_t
   P.d_wave_begin = ws.take<int32_t>(kBatchWaveCap + 1);
   P.d_wave_chunks = ws.take<int32_t>(P.chunk_cap);
   for (auto& st : P.steps) P.d_steps.push_back(ws.take<BatchModeDesc>(st.size()));
+  if (resid2) {
+    for (auto& st : P.esteps) P.d_esteps.push_back(ws.take<BatchModeDesc>(st.size()));
+    // chunks of 512 KB on the residual kernel's resident waves, fixed at plan time
+    const int waves = ws.base ? std::min(kBatchWaveCap, batch_resid_waves()) : kBatchWaveCap;
+    batch_schedule(P.tensors, kBatchResidChunk, waves, P.rchunks, P.rwb, P.rwc);
+    P.rtcb.assign(count + 1, (int32_t)P.rchunks.size());
+    for (int i = (int)P.rchunks.size() - 1; i >= 0; --i) P.rtcb[P.rchunks[i].tensor] = i;
+    for (int t = count - 1; t >= 0; --t) P.rtcb[t] = std::min(P.rtcb[t], P.rtcb[t + 1]);
+    P.d_rchunks = ws.take<BatchChunk>(P.rchunks.size());
+    P.d_rwb = ws.take<int32_t>(kBatchWaveCap + 1);   // the size query counts the most waves
+    P.d_rwc = ws.take<int32_t>(P.rwc.size());
+    P.d_rtcb = ws.take<int32_t>(P.rtcb.size());
+    P.d_rpart = ws.take<double>(2 * P.rchunks.size());
+    P.br.tensors = P.d_tensors;
+    P.br.chunks = P.d_rchunks;
+    P.br.wave_begin = P.d_rwb;
+    P.br.wave_chunks = P.d_rwc;
+    P.br.tensor_chunk_begin = P.d_rtcb;
+    P.br.partials = P.d_rpart;
+    P.br.resid2 = resid2;
+    P.br.nwaves = (int32_t)P.rwb.size() - 1;
+    P.br.count = count;
+  }
   P.sl.u = P.d_units;
   P.sl.block_unit = P.d_block_unit;
   P.sl.count = (int32_t)P.units.size();
@@ -1110,6 +1183,16 @@ tk_status batch_upload(BatchPlanData& P, hipStream_t st) {
   for (size_t s = 0; s < P.steps.size(); ++s)
     TK_HIP(hipMemcpyAsync(P.d_steps[s], P.steps[s].data(), P.steps[s].size() * sizeof(BatchModeDesc),
                           hipMemcpyHostToDevice, st));
+  if (P.resid2) {
+    for (size_t s = 0; s < P.esteps.size(); ++s)
+      TK_HIP(hipMemcpyAsync(P.d_esteps[s], P.esteps[s].data(), P.esteps[s].size() * sizeof(BatchModeDesc),
+                            hipMemcpyHostToDevice, st));
+    TK_HIP(hipMemcpyAsync(P.d_rchunks, P.rchunks.data(), P.rchunks.size() * sizeof(BatchChunk),
+                          hipMemcpyHostToDevice, st));
+    TK_HIP(hipMemcpyAsync(P.d_rwb, P.rwb.data(), P.rwb.size() * sizeof(int32_t), hipMemcpyHostToDevice, st));
+    TK_HIP(hipMemcpyAsync(P.d_rwc, P.rwc.data(), P.rwc.size() * sizeof(int32_t), hipMemcpyHostToDevice, st));
+    TK_HIP(hipMemcpyAsync(P.d_rtcb, P.rtcb.data(), P.rtcb.size() * sizeof(int32_t), hipMemcpyHostToDevice, st));
+  }
   return batch_set_schedule(P, P.tg, P.nbuf, P.chunk_bytes, st);
 }
 
@@ -1133,7 +1216,16 @@ tk_status batch_run(const BatchPlanData& P, hipStream_t st) {
   ql.count = (int32_t)P.qr.size();
   TK_HIP(launch_cholqr_list(ql, P.qr.data(), st));
   TK_HIP(launch_wstep_list(ql, P.qr.data(), TK_F32, TK_F32, st));
-  return batch_core(P, st);
+  if (tk_status s = batch_core(P, st)) return s;
+  if (!P.resid2) return TK_OK;
+  for (size_t s = 0; s < P.esteps.size(); ++s) {
+    BatchMode bm{};
+    bm.descs = P.d_esteps[s];
+    bm.count = (int32_t)P.esteps[s].size();
+    TK_HIP(launch_batch_mode(bm, P.estep_units[s], P.estep_qmax[s], st));
+  }
+  TK_HIP(launch_batch_resid(P.br, st));
+  return TK_OK;
 }
 
 }  // namespace
@@ -2452,14 +2544,15 @@ struct tk_batch_plan {
 
 tk_status tucker_batch_plan_create(int32_t count, const tk_tensor* X, const int32_t* ranks,
                                    const tk_sketch* sk, void* const* U, void* const* G, int32_t* info,
-                                   void* ws, size_t* ws_bytes, void* stream, tk_batch_plan** plan) {
+                                   double* resid2, void* ws, size_t* ws_bytes, void* stream,
+                                   tk_batch_plan** plan) {
   clear_error();
   const ApiRange range_("tucker_batch_plan_create");
   if (!ws_bytes) return set_error(TK_EINVAL, "tucker_batch_plan_create: ws_bytes is NULL");
   Workspace w;
   w.base = static_cast<char*>(ws);
   BatchPlanData P;
-  if (tk_status s = plan_batch(w, count, X, ranks, sk, U, G, info, P)) return s;
+  if (tk_status s = plan_batch(w, count, X, ranks, sk, U, G, info, resid2, P)) return s;
   if (!ws) {
     *ws_bytes = w.off;
     return TK_OK;

@@ -252,15 +252,37 @@ size_t batch_slab_lds_bytes();
 int batch_slab_waves(int tg, int nbuf);   // resident waves of a variant
 hipError_t launch_batch_slab(const BatchSlab& bs, int tg, int nbuf, hipStream_t st);
 
-// One remaining mode of many tensors: out[a][p][b] = sum_q F[q][p] in[a][q][b].
+// Residual of every tensor of a batch over its chunk schedule: each chunk
+// writes (r2, x2) into partials[2 chunk], then resid2[2 t], resid2[2 t + 1]
+// is the sum over tensor t's chunks [tensor_chunk_begin[t], [t + 1]).
+// T of each tensor holds its core expanded over the leading modes.
+struct BatchResid {
+  const BatchTensor* tensors;
+  const BatchChunk* chunks;
+  const int32_t* wave_begin;
+  const int32_t* wave_chunks;
+  const int32_t* tensor_chunk_begin;
+  double* partials;
+  double* resid2;
+  int32_t nwaves;
+  int32_t count;
+};
+int batch_resid_waves();
+hipError_t launch_batch_resid(const BatchResid& br, hipStream_t st);
+
+// One remaining mode of many tensors: out[a][p][b] = sum_q F[q][p] in[a][q][b]
+// (a projection by F = U_k, Q x P), or with ftrans the expansion
+// out[a][p][b] = sum_q F[p][q] in[a][q][b] by rows [p0, p0 + P) of U_k (F
+// then points at row p0, row length Q; out at row p0 of the first slab).
 struct BatchModeDesc {
   const float* in;
-  const float* F;       // Q x P
-  float* out;           // (A, P, B)
+  const float* F;
+  float* out;
   int64_t A, Q, B;
+  int64_t out_slab;     // floats between consecutive a in out (P B, or n_k B for an expansion)
   int64_t unit_begin;   // first unit (multiple of 4) of this descriptor
-  int32_t P;
-  int32_t pad;
+  int32_t P;            // <= 32
+  int32_t ftrans;
 };
 struct BatchMode {
   const BatchModeDesc* descs;

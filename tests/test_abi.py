@@ -255,20 +255,24 @@ def test_batch_plan_validation_and_query():
     U = (C.c_void_p * 3)(FAKE, FAKE, FAKE)
     G = (C.c_void_p * 1)(FAKE)
     n = C.c_size_t(0)
-    assert f(1, X, ranks, sk, U, G, None, None, C.byref(n), None, None) == 0
+    assert f(1, X, ranks, sk, U, G, None, None, None, C.byref(n), None, None) == 0
     assert n.value > 0
+    # the residual's tables (expansion steps, its chunk schedule) add to the workspace
+    n_r = C.c_size_t(0)
+    assert f(1, X, ranks, sk, U, G, None, C.c_void_p(FAKE), None, C.byref(n_r), None, None) == 0
+    assert n_r.value > n.value
     # FP64 tensors, order 2 and wide trailing modes are outside the batch form
     X[0] = _tensor(dims, dtype=B.TK_F64)
-    assert f(1, X, ranks, sk, U, G, None, None, C.byref(n), None, None) == 5
+    assert f(1, X, ranks, sk, U, G, None, None, None, C.byref(n), None, None) == 5
     X[0] = _tensor((20, 300, 40))
-    assert f(1, X, ranks, sk, U, G, None, None, C.byref(n), None, None) == 5
+    assert f(1, X, ranks, sk, U, G, None, None, None, C.byref(n), None, None) == 5
     X[0] = _tensor(dims)
     ranks[2] = 11    # above ell
-    assert f(1, X, ranks, sk, U, G, None, None, C.byref(n), None, None) == 1
+    assert f(1, X, ranks, sk, U, G, None, None, None, C.byref(n), None, None) == 1
     ranks[2] = 5
     G[0] = None
-    assert f(1, X, ranks, sk, U, G, None, None, C.byref(n), None, None) == 1
-    assert f(0, X, ranks, sk, U, G, None, None, C.byref(n), None, None) == 1
+    assert f(1, X, ranks, sk, U, G, None, None, None, C.byref(n), None, None) == 1
+    assert f(0, X, ranks, sk, U, G, None, None, None, C.byref(n), None, None) == 1
 
 
 def _ht_args(dims, rank_of):

@@ -26,7 +26,9 @@ def make_batch(specs, cfg=44):
     return items
 
 
-def plan_for(items):
+def plan_for(items, resid=False):
+    """The plan of a batch; with resid, every run also writes the per-tensor
+    (||X - X_hat||^2, ||X||^2) into the returned FP64 vector."""
     from paper_2603_21379_amd import binding as B
     X = [it[3] for it in items]
     ranks = [it[0].ranks for it in items]
@@ -35,7 +37,10 @@ def plan_for(items):
          for n, r in zip(it[0].dims, it[0].ranks)]
     G = [torch.empty(it[0].ranks, dtype=torch.float32, device="cuda") for it in items]
     info = torch.zeros(sum(len(it[0].dims) for it in items), dtype=torch.int32, device="cuda")
-    plan = B.BatchPlan(X, ranks, sketches, U, G, info)
+    r2 = torch.full((2 * len(items),), float("nan"), dtype=torch.float64, device="cuda") if resid else None
+    plan = B.BatchPlan(X, ranks, sketches, U, G, info, resid2=r2)
+    if resid:
+        return plan, U, G, info, r2
     return plan, U, G, info
 
 
@@ -43,13 +48,55 @@ def small_specs():
     return synthgen.batch_specs(12, cfg=44, nmin=5, nmax=40, rmin=2, rmax=9, cap=60000)
 
 
+def wide_specs():
+    # trailing modes up to 96 (six 16-row tiles), ranks up to 16, ragged sizes
+    return synthgen.batch_specs(8, cfg=47, nmin=5, nmax=96, rmin=2, rmax=16, cap=300000)
+
+
+U32 = 2.0 ** -24
+
+
+def r2_rtol(eps, N):
+    """Relative tolerance of ||X - X_hat||^2 from the batched pass.  X_hat is
+    formed in FP32 (FP32 expanded core, FP32 P, FP32 MFMA sums of <= 16
+    terms): an error delta of at most about 8 u x_rms per entry, with no
+    relation to d = x - x_hat.  It moves sum d^2 by 2 sum d delta (random
+    sign: relative std 2 delta / (d_rms sqrt N), five of them allowed) and by
+    sum delta^2 ((delta / d_rms)^2), with d_rms = eps x_rms; the squares go
+    through FP32 sums of at most 144 terms per lane and slab before the FP64
+    sums (<= 144 u)."""
+    rd = 8 * U32 / eps
+    return 144 * U32 + 10 * rd / np.sqrt(N) + rd * rd
+
+
+def check_resid2(items, U, G, r2):
+    """The batched residual against the oracle's, per tensor, on the stored
+    tensor and the run's own core and factors."""
+    r2h = r2.cpu().numpy()
+    m = 0
+    for ti, it in enumerate(items):
+        sp, inp = it[0], it[1]
+        d = len(sp.dims)
+        X64 = inp.X.astype(np.float64)
+        Ub = [u.double().cpu().numpy() for u in U[m:m + d]]
+        Gb = G[ti].double().cpu().numpy()
+        ref = oracle.reconstruct(Gb, Ub)
+        x2, d2 = np.sum(X64 ** 2), np.sum((X64 - ref) ** 2)
+        np.testing.assert_allclose(r2h[2 * ti + 1], x2, rtol=144 * U32, err_msg=str(sp.dims))
+        tol = r2_rtol(np.sqrt(d2 / x2), X64.size)
+        np.testing.assert_allclose(r2h[2 * ti], d2, rtol=tol, err_msg=str(sp.dims))
+        m += d
+    return r2h
+
+
 def test_batch_matches_oracle_and_single_path():
     from paper_2603_21379_amd import tucker as T
     items = make_batch(small_specs())
-    plan, U, G, info = plan_for(items)
+    plan, U, G, info, r2 = plan_for(items, resid=True)
     plan.run()
     torch.cuda.synchronize()
     assert int(info.abs().sum()) == 0
+    r2h = check_resid2(items, U, G, r2)
     m = 0
     for ti, (sp, inp, sk, X, skd) in enumerate(items):
         d = len(sp.dims)
@@ -71,18 +118,37 @@ def test_batch_matches_oracle_and_single_path():
         eps_gpu = oracle.rel_error(X64, Gb, Ub)
         eps_or = oracle.rel_error(X64, oracle.core(X64, U_or32), U_or32)
         assert abs(eps_gpu - eps_or) <= 1e-5 * eps_or, (sp.dims, eps_gpu, eps_or)
+        # the run's own residual, as the error it reports
+        eps_run = float(np.sqrt(r2h[2 * ti] / r2h[2 * ti + 1]))
+        tol = 1e-5 + 0.5 * r2_rtol(eps_or, X64.size) + 72 * U32
+        assert abs(eps_run - eps_or) <= tol * eps_or, (sp.dims, eps_run, eps_or)
         for a, b in zip(Ub, U_or):
             assert oracle.projector_distance(a, b) < 1e-4
         m += d
 
 
+def test_batch_residual_wide_trailing_modes():
+    """Trailing modes up to 96 and ranks up to 16: every tile count of the
+    residual pass, ragged last tiles, leading-mode expansions over several
+    32-row blocks."""
+    specs = wide_specs()
+    assert max(max(sp.dims[-2:]) for sp in specs) > 80
+    items = make_batch(specs, cfg=47)
+    plan, U, G, info, r2 = plan_for(items, resid=True)
+    plan.run()
+    torch.cuda.synchronize()
+    assert int(info.abs().sum()) == 0
+    check_resid2(items, U, G, r2)
+
+
 def test_batch_graph_replays_match_eager():
     items = make_batch(small_specs(), cfg=45)
-    plan, U, G, info = plan_for(items)
+    plan, U, G, info, r2 = plan_for(items, resid=True)
     plan.run()
     torch.cuda.synchronize()
     ref_U = [u.clone() for u in U]
     ref_G = [g.clone() for g in G]
+    ref_r2 = r2.clone()
     s = torch.cuda.Stream()
     s.wait_stream(torch.cuda.current_stream())
     graph = torch.cuda.CUDAGraph()
@@ -93,7 +159,7 @@ def test_batch_graph_replays_match_eager():
         plan.run(stream=s)
     torch.cuda.synchronize()
     for rep in range(3):
-        for t in U + G:
+        for t in U + G + [r2]:
             t.fill_(float("nan"))     # eager work between the replays
         torch.cuda.synchronize()
         graph.replay()
@@ -102,6 +168,7 @@ def test_batch_graph_replays_match_eager():
             assert torch.equal(a, b), rep
         for a, b in zip(G, ref_G):
             assert torch.equal(a, b), rep
+        assert torch.equal(r2, ref_r2), rep
 
 
 def test_batch_autotune_keeps_results():
