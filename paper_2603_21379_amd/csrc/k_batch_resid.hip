@@ -46,7 +46,6 @@ __device__ __forceinline__ void resid_chunk(const BatchTensor& td, int64_t a0, i
                                             double& r2, double& x2) {
   const int g = lane >> 4, l16 = lane & 15;
   const int nI = td.nI, nJ = td.nJ, cI = td.cI, cJ = td.cJ;
-  const int kI = (cI + 3) >> 2, kJ = (cJ + 3) >> 2;
   const int nTI = (nI + 15) >> 4, nTJ = (nJ + 15) >> 4;
   float(*sFI)[kFW] = reinterpret_cast<float(*)[kFW]>(wl);
   float(*sFJ)[kFW] = reinterpret_cast<float(*)[kFW]>(wl + kBatchMaxN * kFW);
@@ -104,18 +103,24 @@ __device__ __forceinline__ void resid_chunk(const BatchTensor& td, int64_t a0, i
 #pragma unroll
     for (int ks = 0; ks < 4; ++ks) ta[ks] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rt, toff[ks], 0, 0));
   };
+  // Rank steps, and for up to three tiles the tiles, past the tensor's
+  // sizes multiply zeros (X reads zero there and the factor tables are
+  // zero-padded), so those multiplies run without tests: a uniform branch per
+  // step costs more than the MFMA it would skip.  From four tiles on, the
+  // tile tests stay (they also keep the scheduler from hoisting operand
+  // reads across tiles, which spills with a whole slab in registers).
+  constexpr bool kSkip = NT >= 4;
   auto compute = [&](const uintx4 (&xr)[NT][NT], const float (&ta)[4]) {
     // stage 1: P = T[a] F_J^T (B operand lane l: F_J[16 jt + l%16][4 ks + l/16])
 #pragma unroll
     for (int jt = 0; jt < NT; ++jt) {
-      if (jt >= nTJ) continue;
+      if (kSkip && jt >= nTJ) continue;
       float fj[4];
 #pragma unroll
       for (int ks = 0; ks < 4; ++ks) fj[ks] = sFJ[16 * jt + l16][4 * ks + g];
       floatx4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
-      for (int ks = 0; ks < 4; ++ks)
-        if (ks < kJ) acc = mma16(ta[ks], fj[ks], acc);
+      for (int ks = 0; ks < 4; ++ks) acc = mma16(ta[ks], fj[ks], acc);
 #pragma unroll
       for (int v = 0; v < 4; ++v) sP[4 * g + v][16 * jt + l16] = acc[v];
     }
@@ -123,23 +128,29 @@ __device__ __forceinline__ void resid_chunk(const BatchTensor& td, int64_t a0, i
     __builtin_amdgcn_wave_barrier();
     __atomic_signal_fence(__ATOMIC_SEQ_CST);
     // stage 2 and the squares (A operand lane l: P[4 ks + l/16][16 jt + l%16])
+    constexpr bool kKeepP = NT <= 4;
+    float pv[kKeepP ? NT : 1][4];
+    if constexpr (kKeepP) {
+#pragma unroll
+      for (int jt = 0; jt < NT; ++jt)
+#pragma unroll
+        for (int ks = 0; ks < 4; ++ks) pv[jt][ks] = sP[4 * ks + g][16 * jt + l16];
+    }
     float r2t = 0.0f, x2t = 0.0f;
 #pragma unroll
     for (int it = 0; it < NT; ++it) {
-      if (it >= nTI) continue;
+      if (kSkip && it >= nTI) continue;
       float fi[4];   // B operand lane l: F_I[16 it + l%16][4 ks + l/16]
 #pragma unroll
       for (int ks = 0; ks < 4; ++ks) fi[ks] = sFI[16 * it + l16][4 * ks + g];
 #pragma unroll
       for (int jt = 0; jt < NT; ++jt) {
-        if (jt >= nTJ) continue;
+        if (kSkip && jt >= nTJ) continue;
         floatx4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
         for (int ks = 0; ks < 4; ++ks)
-          if (ks < kI) acc = mma16(sP[4 * ks + g][16 * jt + l16], fi[ks], acc);
-        uintx4 xu = xr[it][jt];
-        if (jt == nTJ - 1) xu &= lastmask;
-        const floatx4 x = __builtin_bit_cast(floatx4, xu);
+          acc = mma16(kKeepP ? pv[kKeepP ? jt : 0][ks] : sP[4 * ks + g][16 * jt + l16], fi[ks], acc);
+        const floatx4 x = __builtin_bit_cast(floatx4, xr[it][jt] & (jt == nTJ - 1 ? lastmask : ~uintx4{}));
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           const float d = x[v] - acc[v];
