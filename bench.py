@@ -54,6 +54,8 @@ def parse():
     ap.add_argument("--config", default="c2")
     ap.add_argument("--core", default="U", choices=["U", "Q"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
+    ap.add_argument("--autotune-cache", default=None,
+                    help="c4: JSON file of stored batch schedules keyed by shape class (read, then updated)")
     ap.add_argument("--cpu-slabs", type=int, default=12,
                     help="mode-0 slabs of X the oracle core baseline processes")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -425,7 +427,7 @@ def bench_batch(args):
     resid2 = torch.full((2 * len(specs),), float("nan"), dtype=torch.float64, device=dev)
     log(f"generated and uploaded in {time.time() - t0:.1f}s; planning")
     plan = B.BatchPlan(X, ranks, sketches, U, G, info, resid2=resid2)
-    report = plan.autotune()
+    report = plan.autotune(cache=args.autotune_cache)
     log("autotune:\n" + report.strip())
     # eager runs with the streaming pass bracketed by the library's events
     for _ in range(args.warmup):

@@ -366,6 +366,21 @@ tk_status tucker_batch_run(const tk_batch_plan* plan, void* stream);
 tk_status tucker_batch_autotune(tk_batch_plan* plan, void* stream, char* report, size_t report_bytes);
 void tucker_batch_plan_destroy(tk_batch_plan* plan);
 
+/* The streaming pass's schedule of a plan (what tucker_batch_autotune
+ * chooses), so that a caller can store a tuned choice and apply it to a later
+ * plan of the same shapes without timing again.
+ *   tiles_per_unit, buffers  the pass's form: (1, 2), (2, 2) or (1, 3).
+ *   chunk_bytes  bytes of X per scheduled chunk, in [32 KiB, 64 MiB].
+ * tucker_batch_set_schedule rebuilds and uploads the chunk schedule on
+ * `stream` and waits for it (do not call it while capturing).  Results do not
+ * depend on the schedule.
+ * Errors: TK_EINVAL (NULL arguments, another form, chunk size out of range),
+ * TK_EDEVICE. */
+tk_status tucker_batch_get_schedule(const tk_batch_plan* plan, int32_t* tiles_per_unit, int32_t* buffers,
+                                    int64_t* chunk_bytes);
+tk_status tucker_batch_set_schedule(tk_batch_plan* plan, int32_t tiles_per_unit, int32_t buffers,
+                                    int64_t chunk_bytes, void* stream);
+
 /* Seeded device-side draw of sampled sketches (the sampling of Algorithm 1,
  * Section 3.1: column indices uniform without repetition and a Gaussian
  * test matrix), so no host generation or upload is needed.  For each unit

@@ -9,6 +9,8 @@ fallback path.  If the library is missing, `lib()` raises.
 from __future__ import annotations
 
 import ctypes as C
+import hashlib
+import json
 import os
 import threading
 
@@ -60,7 +62,7 @@ EXPORTS = ("tucker_sketch_all_modes", "tucker_qr", "tucker_core", "tucker_recons
            "tucker_batch_run", "tucker_batch_autotune", "tucker_batch_plan_destroy",
            "tk_stream_read_blocks", "tk_stream_read", "tucker_draw_sketches",
            "htucker_reconstruct", "htucker_reconstruct_vjp", "tucker_sketch_all_modes_noalloc",
-           "tucker_projection_loss_vjp")
+           "tucker_projection_loss_vjp", "tucker_batch_get_schedule", "tucker_batch_set_schedule")
 
 
 def lib():
@@ -110,6 +112,8 @@ def lib():
                                                pp, pp, vp, vp, vp, sz, vp, C.POINTER(C.c_void_p)]
             sig["tucker_batch_run"] = [vp, vp]
             sig["tucker_batch_autotune"] = [vp, vp, C.c_char_p, C.c_size_t]
+            sig["tucker_batch_get_schedule"] = [vp, i32p, i32p, i64p]
+            sig["tucker_batch_set_schedule"] = [vp, C.c_int32, C.c_int32, C.c_int64, vp]
             L.tucker_sketch_all_modes_noalloc.argtypes = [C.POINTER(TkTensor), C.POINTER(TkSketch),
                                                           pp, pp, vp]
             L.tucker_sketch_all_modes_noalloc.restype = C.c_int
@@ -357,6 +361,20 @@ def tucker_projection_loss_vjp(X, F, G, lbar=None, Xbar=None, Fbar=None, stream=
     return _call("tucker_projection_loss_vjp", args, X.device, stream, ws)
 
 
+def batch_shape_class(dims, ells) -> str:
+    """Key of a batch for stored schedules: the multiset of per-tensor classes
+    (order, 16-wide buckets of the two trailing sizes, 16-wide bucket of the
+    widest sketch), canonically ordered and hashed."""
+    classes, m = [], 0
+    for d in dims:
+        o = len(d)
+        cls = (o, (d[-2] + 15) // 16, (d[-1] + 15) // 16, (max(ells[m:m + o]) + 15) // 16)
+        classes.append(cls)
+        m += o
+    canon = ";".join(f"{a},{b},{c},{e}" for a, b, c, e in sorted(classes))
+    return f"n{len(dims)}-" + hashlib.sha1(canon.encode()).hexdigest()[:16]
+
+
 class BatchPlan:
     """Owner of a tucker_batch_plan: keeps the workspace, the descriptor
     arrays and the tensors they point to alive while the plan exists."""
@@ -365,6 +383,8 @@ class BatchPlan:
         """resid2: None, or a CUDA float64 tensor of 2 len(X) values that
         every run fills with (||X_t - X_hat_t||^2, ||X_t||^2) per tensor."""
         n = len(X)
+        self.shape_class = batch_shape_class([tuple(x.shape) for x in X],
+                                             [int(sk[1].shape[1]) for sk in sketches])
         if resid2 is not None and (resid2.dtype != torch.float64 or resid2.numel() < 2 * n
                                    or not resid2.is_contiguous()):
             raise ValueError("resid2 must be a contiguous float64 tensor of 2 len(X) values")
@@ -395,10 +415,42 @@ class BatchPlan:
     def run(self, stream=None):
         _check("tucker_batch_run", lib().tucker_batch_run(self.handle, _stream(stream)))
 
-    def autotune(self, stream=None) -> str:
+    def autotune(self, stream=None, cache=None) -> str:
+        """Choose the streaming pass's schedule by timing (synchronises).  With
+        `cache` (a JSON file path), a choice stored there for this plan's shape
+        class is applied without timing, and a new choice is stored."""
+        if cache and os.path.exists(cache):
+            with open(cache) as f:
+                stored = json.load(f).get(self.shape_class)
+            if stored:
+                self.set_schedule(*stored["schedule"], stream=stream)
+                return f"cached: {stored['schedule']} for shape class {self.shape_class}\n"
         buf = C.create_string_buffer(4096)
         _check("tucker_batch_autotune", lib().tucker_batch_autotune(self.handle, _stream(stream), buf, 4096))
-        return buf.value.decode()
+        report = buf.value.decode()
+        if cache:
+            data = {}
+            if os.path.exists(cache):
+                with open(cache) as f:
+                    data = json.load(f)
+            data[self.shape_class] = {"schedule": list(self.schedule()), "choice": report.strip().splitlines()[-1]}
+            tmp = f"{cache}.{os.getpid()}.tmp"
+            with open(tmp, "w") as f:
+                json.dump(data, f, indent=1, sort_keys=True)
+            os.replace(tmp, cache)
+        return report
+
+    def schedule(self):
+        """(tiles per unit, buffers, chunk bytes) of the streaming pass."""
+        tg, nb, cb = C.c_int32(0), C.c_int32(0), C.c_int64(0)
+        _check("tucker_batch_get_schedule",
+               lib().tucker_batch_get_schedule(self.handle, C.byref(tg), C.byref(nb), C.byref(cb)))
+        return tg.value, nb.value, cb.value
+
+    def set_schedule(self, tiles_per_unit, buffers, chunk_bytes, stream=None):
+        _check("tucker_batch_set_schedule",
+               lib().tucker_batch_set_schedule(self.handle, int(tiles_per_unit), int(buffers), int(chunk_bytes),
+                                               _stream(stream)))
 
     def close(self):
         if getattr(self, "handle", None):

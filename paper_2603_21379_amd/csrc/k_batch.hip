@@ -4,11 +4,12 @@
 // batch_slab_kernel: the streaming pass of every tensor, T[a] = F_I^T X[a] F_J
 //   for the slabs X[a] of its two trailing modes (n <= 96, ranks <= 16), on
 //   v_mfma_f32_16x16x4f32 exactly as the single-tensor small-mode pass.  The
-//   work is a list of chunks (tensor, slab range) assigned to waves on the
-//   host by longest-processing-time first, so the waves finish together and
-//   the schedule is fixed (no counters to reset between graph replays).  A
-//   wave keeps its tensor's F_J in registers and F_I^T in its own LDS region,
-//   reloading both when its next chunk belongs to another tensor.
+//   work is a list of chunks (tensor, slab range) that the resident waves
+//   take from a queue, largest first, so the waves finish together (the
+//   counter is cleared by a one-thread kernel before each pass, so runs can
+//   be replayed from a graph).  A wave keeps its tensor's F_J in registers
+//   and F_I^T in its own LDS region, reloading both when its next chunk
+//   belongs to another tensor.
 //
 // batch_mode_kernel: one remaining mode of every tensor that still has one,
 //   out[a][p][b] = sum_q F[q][p] in[a][q][b], as the single-tensor MFMA mode
@@ -39,9 +40,13 @@ __global__ __launch_bounds__(256, 2) void batch_slab_kernel(const BatchSlab bs) 
   const int lane = threadIdx.x & 63, g = lane >> 4, l16 = lane & 15;
   const int wv = threadIdx.x >> 6;
   float* sA = lds + wv * (NT * 256);   // this wave's F_I^T table [t][v][lane]
-  const int gwave = __builtin_amdgcn_readfirstlane((int)blockIdx.x * kWaves + wv);
-  if (gwave >= bs.nwaves) return;
-  const int c_begin = wave_uniform(bs.wave_begin[gwave]), c_end = wave_uniform(bs.wave_begin[gwave + 1]);
+  // chunks from the queue, largest first; the next ticket is taken when a
+  // chunk starts, so its round trip overlaps the chunk
+  auto take = [&]() {
+    int q = 0;
+    if (lane == 0) q = atomicAdd(bs.queue, 1);
+    return __builtin_amdgcn_readfirstlane(q);
+  };
 
   int cur_tensor = -1;
   float fj[NK][4];
@@ -50,8 +55,10 @@ __global__ __launch_bounds__(256, 2) void batch_slab_kernel(const BatchSlab bs) 
   int nT = 0, nK = 0;
   uint32_t lane_off = 0, tile_bytes = 0, slab_bytes = 0;
 
-  for (int ci = c_begin; ci < c_end; ++ci) {
-    const BatchChunk ch = wave_uniform(bs.chunks[wave_uniform(bs.wave_chunks[ci])]);
+  int qt = take();
+  while (qt < bs.nchunks) {
+    const int qnext = take();
+    const BatchChunk ch = wave_uniform(bs.chunks[wave_uniform(bs.order[qt])]);
     const int tid = ch.tensor;
     if (tid != cur_tensor) {
       cur_tensor = tid;
@@ -219,8 +226,11 @@ __global__ __launch_bounds__(256, 2) void batch_slab_kernel(const BatchSlab bs) 
     for (int s = 0; s < NBUF - 1; ++s)
       if (s < left) compute_unit(ua[s], ug[s], buf[s]);
     flush();
+    qt = qnext;
   }
 }
+
+__global__ void batch_slab_queue_reset_kernel(int32_t* queue) { *queue = 0; }
 
 // ---------------------------------------------------------------- remaining modes
 constexpr int kCols = 128;
@@ -329,7 +339,9 @@ int batch_slab_waves(int tg, int nbuf) {
 }
 
 hipError_t launch_batch_slab(const BatchSlab& bs, int tg, int nbuf, hipStream_t st) {
-  if (bs.nwaves <= 0) return hipSuccess;
+  if (bs.nwaves <= 0 || bs.nchunks <= 0) return hipSuccess;
+  // a fill kernel, not a memset: the run may be captured in a graph
+  hipLaunchKernelGGL(batch_slab_queue_reset_kernel, dim3(1), dim3(1), 0, st, bs.queue);
   const dim3 grid((unsigned)ceil_div(bs.nwaves, kWaves));
   const size_t lds = batch_slab_lds_bytes();
   if (tg == 1 && nbuf == 2) hipLaunchKernelGGL((batch_slab_kernel<1, 2>), grid, dim3(256), lds, st, bs);

@@ -7,9 +7,9 @@
 // modes (done before this pass by the batched mode contraction), so X is read
 // once and X_hat is never stored.
 //
-// The work list is the chunk schedule of the batched core pass (chunks of
-// consecutive slabs of one tensor, assigned to waves on the host), built for
-// this kernel's resident waves.  Per slab, on v_mfma_f32_16x16x4f32:
+// The work is a list of chunks (consecutive slabs of one tensor), largest
+// first, taken from a queue by the resident waves (the counter is cleared by
+// a one-thread kernel before each pass, so runs can be replayed from a graph).  Per slab, on v_mfma_f32_16x16x4f32:
 //  stage 1  P = T[a] F_J^T (c_I x n_J) into the wave's LDS table;
 //  stage 2  the transposed tiles (F_I P)^T = P^T F_I^T, so register v of
 //           lane l holds X_hat[16 it + l%16][16 jt + 4 (l/16) + v]: four
@@ -193,12 +193,19 @@ __device__ __forceinline__ void resid_chunk(const BatchTensor& td, int64_t a0, i
 __global__ __launch_bounds__(64 * kWaves, 2) void batch_resid_kernel(const BatchResid br) {
   extern __shared__ float lds[];
   float* wl = lds + (threadIdx.x >> 6) * kWaveLds;
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int gwave = __builtin_amdgcn_readfirstlane((int)blockIdx.x * kWaves + wv);
-  if (gwave >= br.nwaves) return;   // no workgroup barrier follows
-  const int c_begin = wave_uniform(br.wave_begin[gwave]), c_end = wave_uniform(br.wave_begin[gwave + 1]);
-  for (int ci = c_begin; ci < c_end; ++ci) {
-    const int cid = wave_uniform(br.wave_chunks[ci]);
+  const int lane = threadIdx.x & 63;
+  // chunks handed out by a queue in the plan's order (largest first): a wave
+  // takes its next ticket when it starts a chunk, so the ticket's round trip
+  // overlaps the chunk's work
+  auto take = [&]() {
+    int q = 0;
+    if (lane == 0) q = atomicAdd(br.queue, 1);
+    return __builtin_amdgcn_readfirstlane(q);
+  };
+  int q = take();
+  while (q < br.nchunks) {
+    const int qn = take();
+    const int cid = wave_uniform(br.order[q]);
     const BatchChunk ch = wave_uniform(br.chunks[cid]);
     const BatchTensor td = wave_uniform(br.tensors[ch.tensor]);
     const int nt = (max(td.nI, td.nJ) + 15) >> 4;
@@ -219,8 +226,11 @@ __global__ __launch_bounds__(64 * kWaves, 2) void batch_resid_kernel(const Batch
       br.partials[2 * cid] = r2;
       br.partials[2 * cid + 1] = x2;
     }
+    q = qn;
   }
 }
+
+__global__ void batch_queue_reset_kernel(int32_t* queue) { *queue = 0; }
 
 // one thread per tensor: its chunks' pairs in chunk order
 __global__ void batch_resid_sum_kernel(const double* partials, const int32_t* chunk_begin, int32_t count,
@@ -254,6 +264,8 @@ int batch_resid_waves() {
 hipError_t launch_batch_resid(const BatchResid& br, hipStream_t st) {
   if (br.count <= 0) return hipSuccess;
   if (br.nwaves > 0) {
+    // a fill kernel, not a memset: the run may be captured in a graph
+    hipLaunchKernelGGL(batch_queue_reset_kernel, dim3(1), dim3(1), 0, st, br.queue);
     hipLaunchKernelGGL(batch_resid_kernel, dim3((unsigned)ceil_div(br.nwaves, kWaves)), dim3(64 * kWaves),
                        kWaves * kWaveLds * sizeof(float), st, br);
     if (hipError_t e = hipGetLastError()) return e;

@@ -857,6 +857,7 @@ tk_status run_grads(const void* Y, int d, const int64_t* dims, const void* const
 constexpr int kBatchWaveCap = 16384;              // schedule capacity (waves)
 constexpr int64_t kBatchChunkMin = 32 << 10;     // smallest chunk the tuner tries (bytes)
 constexpr int64_t kBatchResidChunk = 512 << 10;  // residual pass chunk (bytes)
+constexpr int64_t kBatchChunkMax = 64 << 20;     // largest chunk a stored schedule may ask for
 
 struct BatchPlanData {
   int count = 0;
@@ -871,8 +872,8 @@ struct BatchPlanData {
   QRMat* d_qr = nullptr;
   BatchTensor* d_tensors = nullptr;
   BatchChunk* d_chunks = nullptr;
-  int32_t* d_wave_begin = nullptr;
-  int32_t* d_wave_chunks = nullptr;
+  int32_t* d_order = nullptr;
+  int32_t* d_queue = nullptr;
   size_t chunk_cap = 0;
   std::vector<BatchModeDesc*> d_steps;
   SketchList sl{};
@@ -886,11 +887,11 @@ struct BatchPlanData {
   std::vector<int64_t> estep_units, estep_qmax;
   std::vector<BatchModeDesc*> d_esteps;
   std::vector<BatchChunk> rchunks;
-  std::vector<int32_t> rwb, rwc, rtcb;
+  std::vector<int32_t> rorder, rtcb;
   BatchChunk* d_rchunks = nullptr;
-  int32_t* d_rwb = nullptr;
-  int32_t* d_rwc = nullptr;
+  int32_t* d_rorder = nullptr;
   int32_t* d_rtcb = nullptr;
+  int32_t* d_rqueue = nullptr;
   double* d_rpart = nullptr;
   BatchResid br{};
 };
@@ -900,10 +901,12 @@ int64_t batch_chunk_slabs(const BatchTensor& t, int64_t chunk_bytes) {
   return std::max<int64_t>(1, chunk_bytes / sb);
 }
 
-// Chunks of every tensor, assigned to waves longest first onto the least
-// loaded wave; each wave's list is then ordered by tensor.
-void batch_schedule(const std::vector<BatchTensor>& ts, int64_t chunk_bytes, int nwaves,
-                    std::vector<BatchChunk>& chunks, std::vector<int32_t>& wb, std::vector<int32_t>& wc) {
+// Chunks of consecutive slabs of every tensor, in tensor order, and the
+// order in which the waves take them from the queue: largest first (cost =
+// slab tiles, plus a start-up term per chunk), so the last chunks taken are
+// the short ones and the waves finish together.
+void batch_chunks(const std::vector<BatchTensor>& ts, int64_t chunk_bytes, std::vector<BatchChunk>& chunks,
+                  std::vector<int32_t>& order) {
   chunks.clear();
   std::vector<int64_t> cost;
   for (int t = 0; t < (int)ts.size(); ++t) {
@@ -915,37 +918,12 @@ void batch_schedule(const std::vector<BatchTensor>& ts, int64_t chunk_bytes, int
       c.a0 = a0;
       c.a1 = std::min(ts[t].A, a0 + S);
       chunks.push_back(c);
-      cost.push_back((c.a1 - c.a0) * tile_work + 4);   // + per-chunk start-up
+      cost.push_back((c.a1 - c.a0) * tile_work + 4);
     }
   }
-  std::vector<int32_t> order(chunks.size());
+  order.resize(chunks.size());
   for (size_t i = 0; i < order.size(); ++i) order[i] = (int32_t)i;
   std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return cost[a] > cost[b]; });
-  nwaves = std::max(1, std::min<int>(nwaves, (int)chunks.size()));
-  std::vector<std::pair<int64_t, int32_t>> heap;   // (load, wave), min-heap
-  for (int w = 0; w < nwaves; ++w) heap.push_back({0, w});
-  auto cmp = [](const std::pair<int64_t, int32_t>& a, const std::pair<int64_t, int32_t>& b) {
-    return a.first != b.first ? a.first > b.first : a.second > b.second;
-  };
-  std::make_heap(heap.begin(), heap.end(), cmp);
-  std::vector<std::vector<int32_t>> lists(nwaves);
-  for (int32_t c : order) {
-    std::pop_heap(heap.begin(), heap.end(), cmp);
-    auto& top = heap.back();
-    lists[top.second].push_back(c);
-    top.first += cost[c];
-    std::push_heap(heap.begin(), heap.end(), cmp);
-  }
-  wb.assign(nwaves + 1, 0);
-  wc.clear();
-  for (int w = 0; w < nwaves; ++w) {
-    std::sort(lists[w].begin(), lists[w].end(), [&](int32_t a, int32_t b) {
-      return chunks[a].tensor != chunks[b].tensor ? chunks[a].tensor < chunks[b].tensor : chunks[a].a0 < chunks[b].a0;
-    });
-    wb[w] = (int32_t)wc.size();
-    wc.insert(wc.end(), lists[w].begin(), lists[w].end());
-  }
-  wb[nwaves] = (int32_t)wc.size();
 }
 
 tk_status plan_batch(Workspace& ws, int count, const tk_tensor* X, const int32_t* ranks,
@@ -1112,30 +1090,32 @@ tk_status plan_batch(Workspace& ws, int count, const tk_tensor* X, const int32_t
   P.d_qr = ws.take<QRMat>(P.qr.size());
   P.d_tensors = ws.take<BatchTensor>(P.tensors.size());
   P.d_chunks = ws.take<BatchChunk>(P.chunk_cap);
-  P.d_wave_begin = ws.take<int32_t>(kBatchWaveCap + 1);
-  P.d_wave_chunks = ws.take<int32_t>(P.chunk_cap);
+  P.d_order = ws.take<int32_t>(P.chunk_cap);
+  P.d_queue = ws.take<int32_t>(1);
   for (auto& st : P.steps) P.d_steps.push_back(ws.take<BatchModeDesc>(st.size()));
   if (resid2) {
     for (auto& st : P.esteps) P.d_esteps.push_back(ws.take<BatchModeDesc>(st.size()));
-    // chunks of 512 KB on the residual kernel's resident waves, fixed at plan time
-    const int waves = ws.base ? std::min(kBatchWaveCap, batch_resid_waves()) : kBatchWaveCap;
-    batch_schedule(P.tensors, kBatchResidChunk, waves, P.rchunks, P.rwb, P.rwc);
-    P.rtcb.assign(count + 1, (int32_t)P.rchunks.size());
-    for (int i = (int)P.rchunks.size() - 1; i >= 0; --i) P.rtcb[P.rchunks[i].tensor] = i;
+    // chunks of 512 KB, handed out largest first from a queue to the
+    // residual kernel's resident waves
+    batch_chunks(P.tensors, kBatchResidChunk, P.rchunks, P.rorder);
+    const int nrc = (int)P.rchunks.size();
+    P.rtcb.assign(count + 1, nrc);
+    for (int i = nrc - 1; i >= 0; --i) P.rtcb[P.rchunks[i].tensor] = i;
     for (int t = count - 1; t >= 0; --t) P.rtcb[t] = std::min(P.rtcb[t], P.rtcb[t + 1]);
-    P.d_rchunks = ws.take<BatchChunk>(P.rchunks.size());
-    P.d_rwb = ws.take<int32_t>(kBatchWaveCap + 1);   // the size query counts the most waves
-    P.d_rwc = ws.take<int32_t>(P.rwc.size());
+    P.d_rchunks = ws.take<BatchChunk>(nrc);
+    P.d_rorder = ws.take<int32_t>(nrc);
     P.d_rtcb = ws.take<int32_t>(P.rtcb.size());
-    P.d_rpart = ws.take<double>(2 * P.rchunks.size());
+    P.d_rqueue = ws.take<int32_t>(1);
+    P.d_rpart = ws.take<double>(2 * (size_t)nrc);
     P.br.tensors = P.d_tensors;
     P.br.chunks = P.d_rchunks;
-    P.br.wave_begin = P.d_rwb;
-    P.br.wave_chunks = P.d_rwc;
+    P.br.order = P.d_rorder;
     P.br.tensor_chunk_begin = P.d_rtcb;
     P.br.partials = P.d_rpart;
     P.br.resid2 = resid2;
-    P.br.nwaves = (int32_t)P.rwb.size() - 1;
+    P.br.queue = P.d_rqueue;
+    P.br.nwaves = ws.base ? std::min(kBatchWaveCap, batch_resid_waves()) : 0;
+    P.br.nchunks = nrc;
     P.br.count = count;
   }
   P.sl.u = P.d_units;
@@ -1146,25 +1126,24 @@ tk_status plan_batch(Workspace& ws, int count, const tk_tensor* X, const int32_t
   return TK_OK;
 }
 
-// schedule of the streaming pass for a variant and chunk size (synchronous upload)
+// chunk list of the streaming pass for a variant and chunk size (synchronous upload)
 tk_status batch_set_schedule(BatchPlanData& P, int tg, int nbuf, int64_t chunk_bytes, hipStream_t st) {
   std::vector<BatchChunk> chunks;
-  std::vector<int32_t> wb, wc;
-  const int waves = std::min(kBatchWaveCap, batch_slab_waves(tg, nbuf));
-  batch_schedule(P.tensors, std::max(chunk_bytes, kBatchChunkMin), waves, chunks, wb, wc);
+  std::vector<int32_t> order;
+  batch_chunks(P.tensors, std::max(chunk_bytes, kBatchChunkMin), chunks, order);
   if (chunks.size() > P.chunk_cap) return set_error(TK_EINVAL, "batch schedule exceeds its table");
   TK_HIP(hipMemcpyAsync(P.d_chunks, chunks.data(), chunks.size() * sizeof(BatchChunk), hipMemcpyHostToDevice, st));
-  TK_HIP(hipMemcpyAsync(P.d_wave_begin, wb.data(), wb.size() * sizeof(int32_t), hipMemcpyHostToDevice, st));
-  TK_HIP(hipMemcpyAsync(P.d_wave_chunks, wc.data(), wc.size() * sizeof(int32_t), hipMemcpyHostToDevice, st));
+  TK_HIP(hipMemcpyAsync(P.d_order, order.data(), order.size() * sizeof(int32_t), hipMemcpyHostToDevice, st));
   TK_HIP(hipStreamSynchronize(st));
   P.tg = tg;
   P.nbuf = nbuf;
   P.chunk_bytes = chunk_bytes;
   P.bs.tensors = P.d_tensors;
   P.bs.chunks = P.d_chunks;
-  P.bs.wave_begin = P.d_wave_begin;
-  P.bs.wave_chunks = P.d_wave_chunks;
-  P.bs.nwaves = (int32_t)(wb.size() - 1);
+  P.bs.order = P.d_order;
+  P.bs.queue = P.d_queue;
+  P.bs.nchunks = (int32_t)chunks.size();
+  P.bs.nwaves = std::min(kBatchWaveCap, batch_slab_waves(tg, nbuf));
   return TK_OK;
 }
 
@@ -1189,8 +1168,8 @@ tk_status batch_upload(BatchPlanData& P, hipStream_t st) {
                             hipMemcpyHostToDevice, st));
     TK_HIP(hipMemcpyAsync(P.d_rchunks, P.rchunks.data(), P.rchunks.size() * sizeof(BatchChunk),
                           hipMemcpyHostToDevice, st));
-    TK_HIP(hipMemcpyAsync(P.d_rwb, P.rwb.data(), P.rwb.size() * sizeof(int32_t), hipMemcpyHostToDevice, st));
-    TK_HIP(hipMemcpyAsync(P.d_rwc, P.rwc.data(), P.rwc.size() * sizeof(int32_t), hipMemcpyHostToDevice, st));
+    TK_HIP(hipMemcpyAsync(P.d_rorder, P.rorder.data(), P.rorder.size() * sizeof(int32_t), hipMemcpyHostToDevice,
+                          st));
     TK_HIP(hipMemcpyAsync(P.d_rtcb, P.rtcb.data(), P.rtcb.size() * sizeof(int32_t), hipMemcpyHostToDevice, st));
   }
   return batch_set_schedule(P, P.tg, P.nbuf, P.chunk_bytes, st);
@@ -2634,6 +2613,34 @@ tk_status tucker_batch_autotune(tk_batch_plan* plan, void* stream, char* report,
     report[report_bytes - 1] = 0;
   }
   return TK_OK;
+}
+
+tk_status tucker_batch_get_schedule(const tk_batch_plan* plan, int32_t* tiles_per_unit, int32_t* buffers,
+                                    int64_t* chunk_bytes) {
+  clear_error();
+  const ApiRange range_("tucker_batch_get_schedule");
+  if (!plan || !tiles_per_unit || !buffers || !chunk_bytes)
+    return set_error(TK_EINVAL, "tucker_batch_get_schedule: NULL argument");
+  *tiles_per_unit = plan->data.tg;
+  *buffers = plan->data.nbuf;
+  *chunk_bytes = plan->data.chunk_bytes;
+  return TK_OK;
+}
+
+tk_status tucker_batch_set_schedule(tk_batch_plan* plan, int32_t tiles_per_unit, int32_t buffers,
+                                    int64_t chunk_bytes, void* stream) {
+  clear_error();
+  const ApiRange range_("tucker_batch_set_schedule");
+  if (!plan) return set_error(TK_EINVAL, "tucker_batch_set_schedule: plan is NULL");
+  const bool variant = (tiles_per_unit == 1 && buffers == 2) || (tiles_per_unit == 2 && buffers == 2) ||
+                       (tiles_per_unit == 1 && buffers == 3);
+  if (!variant)
+    return set_error(TK_EINVAL, "tucker_batch_set_schedule: no streaming-pass form with %d tiles per unit and %d "
+                     "buffers", tiles_per_unit, buffers);
+  if (chunk_bytes < kBatchChunkMin || chunk_bytes > kBatchChunkMax)
+    return set_error(TK_EINVAL, "tucker_batch_set_schedule: chunk of %lld bytes outside [%lld, %lld]",
+                     (long long)chunk_bytes, (long long)kBatchChunkMin, (long long)kBatchChunkMax);
+  return batch_set_schedule(plan->data, tiles_per_unit, buffers, chunk_bytes, as_stream(stream));
 }
 
 void tucker_batch_plan_destroy(tk_batch_plan* plan) { delete plan; }

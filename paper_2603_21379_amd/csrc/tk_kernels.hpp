@@ -241,10 +241,10 @@ struct BatchChunk {
 struct BatchSlab {
   const BatchTensor* tensors;
   const BatchChunk* chunks;
-  const int32_t* wave_begin;   // [nwaves + 1]: chunk list of each wave (CSR)
-  const int32_t* wave_chunks;
-  int32_t nwaves;
-  int32_t pad;
+  const int32_t* order;        // chunk ids in the order the waves take them
+  int32_t* queue;              // one counter, cleared by the launcher
+  int32_t nwaves;              // resident waves launched
+  int32_t nchunks;
 };
 constexpr int kBatchMaxN = 96;
 constexpr int kBatchMaxC = 16;
@@ -252,20 +252,23 @@ size_t batch_slab_lds_bytes();
 int batch_slab_waves(int tg, int nbuf);   // resident waves of a variant
 hipError_t launch_batch_slab(const BatchSlab& bs, int tg, int nbuf, hipStream_t st);
 
-// Residual of every tensor of a batch over its chunk schedule: each chunk
-// writes (r2, x2) into partials[2 chunk], then resid2[2 t], resid2[2 t + 1]
-// is the sum over tensor t's chunks [tensor_chunk_begin[t], [t + 1]).
-// T of each tensor holds its core expanded over the leading modes.
+// Residual of every tensor of a batch over its chunks (taken by the waves
+// from a queue in `order`): each chunk writes (r2, x2) into partials[2 chunk],
+// then resid2[2 t], resid2[2 t + 1] is the sum over tensor t's chunks
+// [tensor_chunk_begin[t], [t + 1]).  T of each tensor holds its core expanded
+// over the leading modes.
 struct BatchResid {
   const BatchTensor* tensors;
   const BatchChunk* chunks;
-  const int32_t* wave_begin;
-  const int32_t* wave_chunks;
+  const int32_t* order;         // chunk ids, largest first
   const int32_t* tensor_chunk_begin;
   double* partials;
   double* resid2;
+  int32_t* queue;               // one counter, cleared by the launcher
   int32_t nwaves;
+  int32_t nchunks;
   int32_t count;
+  int32_t pad;
 };
 int batch_resid_waves();
 hipError_t launch_batch_resid(const BatchResid& br, hipStream_t st);

@@ -275,6 +275,27 @@ def test_batch_plan_validation_and_query():
     assert f(0, X, ranks, sk, U, G, None, None, None, C.byref(n), None, None) == 1
 
 
+def test_batch_schedule_entry_points_validate():
+    L = B.lib()
+    a, b, c = C.c_int32(0), C.c_int32(0), C.c_int64(0)
+    assert L.tucker_batch_get_schedule(None, C.byref(a), C.byref(b), C.byref(c)) == 1
+    assert L.tucker_batch_set_schedule(None, 1, 2, 1 << 20, None) == 1
+
+
+def test_batch_shape_class_key():
+    """Stored schedules are keyed by the multiset of per-tensor classes: the
+    order of the tensors does not matter, a size in another 16-wide bucket
+    does."""
+    dims = [(20, 30, 40), (16, 16, 16, 16), (50, 60, 70)]
+    ells = [8, 9, 10, 6, 6, 6, 6, 12, 12, 13]
+    k1 = B.batch_shape_class(dims, ells)
+    k2 = B.batch_shape_class([dims[2], dims[0], dims[1]], ells[7:] + ells[:3] + ells[3:7])
+    assert k1 == k2 and k1.startswith("n3-")
+    assert B.batch_shape_class([(20, 30, 41)] + dims[1:], ells) == k1     # same buckets
+    assert B.batch_shape_class([(20, 30, 49)] + dims[1:], ells) != k1     # trailing size bucket
+    assert B.batch_shape_class(dims, [8, 9, 17] + ells[3:]) != k1        # sketch width bucket
+
+
 def _ht_args(dims, rank_of):
     import synthgen
     tr = synthgen.balanced_tree(len(dims))

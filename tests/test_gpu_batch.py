@@ -171,19 +171,28 @@ def test_batch_graph_replays_match_eager():
         assert torch.equal(r2, ref_r2), rep
 
 
-def test_batch_autotune_keeps_results():
+def test_batch_autotune_keeps_results(tmp_path):
     items = make_batch(small_specs(), cfg=46)
     plan, U, G, info = plan_for(items)
     plan.run()
     torch.cuda.synchronize()
     ref = [g.clone() for g in G]
-    report = plan.autotune()
+    cache = str(tmp_path / "schedules.json")
+    report = plan.autotune(cache=cache)
     assert "chosen" in report
     for g in G:
         g.zero_()
     plan.run()
     torch.cuda.synchronize()
     for a, b in zip(G, ref):
+        assert torch.equal(a, b)
+    # a second plan of the same shapes takes the stored choice without timing
+    plan2, U2, G2, _ = plan_for(items)
+    report2 = plan2.autotune(cache=cache)
+    assert report2.startswith("cached") and plan2.schedule() == plan.schedule()
+    plan2.run()
+    torch.cuda.synchronize()
+    for a, b in zip(G2, ref):
         assert torch.equal(a, b)
 
 
