@@ -369,7 +369,9 @@ void tucker_batch_plan_destroy(tk_batch_plan* plan);
 /* The streaming pass's schedule of a plan (what tucker_batch_autotune
  * chooses), so that a caller can store a tuned choice and apply it to a later
  * plan of the same shapes without timing again.
- *   tiles_per_unit, buffers  the pass's form: (1, 2), (2, 2) or (1, 3).
+ *   tiles_per_unit, buffers  the pass's form: (0, 0) whole slabs in a
+ *           pipeline of several slabs per wave, or 16-row tile units with
+ *           (1, 2), (2, 2) or (1, 3) (tiles per unit, buffers in flight).
  *   chunk_bytes  bytes of X per scheduled chunk, in [32 KiB, 64 MiB].
  * tucker_batch_set_schedule rebuilds and uploads the chunk schedule on
  * `stream` and waits for it (do not call it while capturing).  Results do not

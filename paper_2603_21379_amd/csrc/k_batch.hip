@@ -232,6 +232,128 @@ __global__ __launch_bounds__(256, 2) void batch_slab_kernel(const BatchSlab bs) 
 
 __global__ void batch_slab_queue_reset_kernel(int32_t* queue) { *queue = 0; }
 
+// Whole-slab form of the streaming pass: a wave keeps D slabs of a chunk in
+// flight (X of a slab in registers as one 16-byte load per 16 x 16 tile:
+// row 16 it + l%16, columns 16 jt + 4 (l/16) .. + 3), so small slabs put as
+// many bytes in flight as large ones.  Per slab, on v_mfma_f32_16x16x4f32:
+//   stage A  (X F_J) of row tile it: the four values of a load are the
+//            A operands of four K steps (K index l/16 stands for column
+//            16 jt + 4 (l/16) + c of step c), F_J[16 jt + 4 (l/16) + c][l%16]
+//            the B operands;
+//   stage B  T += F_I^T (X F_J): register v of the stage-A result (row
+//            16 it + 4 (l/16) + v) is the B operand of K step v, with
+//            F_I[16 it + 4 (l/16) + v][l%16] as the A operand.
+// Columns past n_J of the last column tile hold the next row's values (or
+// zero past the slab): they meet zero rows of F_J, so no mask is needed.
+// The factor operands live in registers (reloaded per chunk); no LDS.
+template <int NT, int D>
+__device__ __forceinline__ void core_chunk(const BatchTensor& td, int64_t a0, int64_t a1, int lane) {
+  const int g = lane >> 4, l16 = lane & 15;
+  const int nI = td.nI, nJ = td.nJ, cI = td.cI, cJ = td.cJ;
+  const int nTI = (nI + 15) >> 4, nTJ = (nJ + 15) >> 4;
+  constexpr bool kSkip = NT >= 4;   // tile tests: see the residual pass
+  float fj[NT][4], fi[NT][4];
+#pragma unroll
+  for (int t = 0; t < NT; ++t)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const int r = 16 * t + 4 * g + c;
+      fj[t][c] = (r < nJ && l16 < cJ) ? td.FJ[r * cJ + l16] : 0.0f;
+      fi[t][c] = (r < nI && l16 < cI) ? td.FI[r * cI + l16] : 0.0f;
+    }
+  const uint32_t rowb = (uint32_t)nJ * 4u, slab_bytes = (uint32_t)(nI * nJ) * 4u;
+  uint32_t coff[NT];
+#pragma unroll
+  for (int jt = 0; jt < NT; ++jt) {
+    const int col = 16 * jt + 4 * g;
+    coff[jt] = (jt < nTJ && col < nJ) ? (uint32_t)l16 * rowb + (uint32_t)col * 4u : 0x80000000u;
+  }
+  const int cIJ = cI * cJ;
+  uint32_t toff[4];
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int p = 4 * g + v;
+    toff[v] = (p < cI && l16 < cJ) ? (uint32_t)(p * cJ + l16) * 4u : 0x80000000u;
+  }
+  auto issue = [&](int64_t a, uintx4 (&xr)[NT][NT]) {
+    const bool live = a < a1;
+    const char* xs = reinterpret_cast<const char*>(td.X) + (live ? a : a0) * (int64_t)slab_bytes;
+#pragma unroll
+    for (int it = 0; it < NT; ++it) {
+      // one range per row tile (from its first row to the slab's end)
+      const int rt = 16 * it * (int)rowb;
+      const bool on = live && it < nTI;
+      const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+          const_cast<char*>(xs) + (on ? rt : 0), (short)0, on ? (int)slab_bytes - rt : 0, kRsrcWord3);
+#pragma unroll
+      for (int jt = 0; jt < NT; ++jt)
+        xr[it][jt] = __builtin_bit_cast(uintx4, __builtin_amdgcn_raw_buffer_load_b128(rs, coff[jt], 0, 0));
+    }
+  };
+  auto compute = [&](int64_t a, const uintx4 (&xr)[NT][NT]) {
+    floatx4 tacc = floatx4{};
+#pragma unroll
+    for (int it = 0; it < NT; ++it) {
+      if (kSkip && it >= nTI) continue;
+      floatx4 acc = floatx4{};
+#pragma unroll
+      for (int jt = 0; jt < NT; ++jt) {
+        if (kSkip && jt >= nTJ) continue;
+        const floatx4 x = __builtin_bit_cast(floatx4, xr[it][jt]);
+#pragma unroll
+        for (int c = 0; c < 4; ++c) acc = mma_f32(x[c], fj[jt][c], acc);
+      }
+#pragma unroll
+      for (int v = 0; v < 4; ++v) tacc = mma_f32(fi[it][v], acc[v], tacc);
+    }
+    const __amdgpu_buffer_rsrc_t ro = __builtin_amdgcn_make_buffer_rsrc(td.T + a * cIJ, (short)0, cIJ * 4,
+                                                                        kRsrcWord3);
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
+      __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(tacc[v]), ro, toff[v], 0, kOutStorePolicy);
+  };
+  uintx4 xr[D][NT][NT];
+  int64_t next = a0, cur = a0;
+#pragma unroll
+  for (int s = 0; s < D - 1; ++s) issue(next++, xr[s]);
+  int64_t left = a1 - a0;
+  for (; left >= D; left -= D) {
+#pragma unroll
+    for (int s = 0; s < D; ++s) {
+      issue(next++, xr[(s + D - 1) % D]);
+      __builtin_amdgcn_sched_barrier(0);
+      compute(cur++, xr[s]);
+    }
+  }
+#pragma unroll
+  for (int s = 0; s < D - 1; ++s)
+    if (s < left) compute(cur++, xr[s]);
+}
+
+__global__ __launch_bounds__(256, 2) void batch_core_pipe_kernel(const BatchSlab bs) {
+  const int lane = threadIdx.x & 63;
+  auto take = [&]() {
+    int q = 0;
+    if (lane == 0) q = atomicAdd(bs.queue, 1);
+    return __builtin_amdgcn_readfirstlane(q);
+  };
+  int qt = take();
+  while (qt < bs.nchunks) {
+    const int qnext = take();
+    const BatchChunk ch = wave_uniform(bs.chunks[wave_uniform(bs.order[qt])]);
+    const BatchTensor td = wave_uniform(bs.tensors[ch.tensor]);
+    switch ((max(td.nI, td.nJ) + 15) >> 4) {
+      case 1: core_chunk<1, 8>(td, ch.a0, ch.a1, lane); break;
+      case 2: core_chunk<2, 6>(td, ch.a0, ch.a1, lane); break;
+      case 3: core_chunk<3, 3>(td, ch.a0, ch.a1, lane); break;
+      case 4: core_chunk<4, 2>(td, ch.a0, ch.a1, lane); break;
+      case 5: core_chunk<5, 1>(td, ch.a0, ch.a1, lane); break;
+      default: core_chunk<6, 1>(td, ch.a0, ch.a1, lane); break;
+    }
+    qt = qnext;
+  }
+}
+
 // ---------------------------------------------------------------- remaining modes
 constexpr int kCols = 128;
 constexpr int kKB = 8;
@@ -330,6 +452,7 @@ int batch_slab_waves(int tg, int nbuf) {
   if (tg == 1 && nbuf == 2) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batch_slab_kernel<1, 2>, 256, lds);
   if (tg == 2 && nbuf == 2) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batch_slab_kernel<2, 2>, 256, lds);
   if (tg == 1 && nbuf == 3) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batch_slab_kernel<1, 3>, 256, lds);
+  if (tg == 0) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batch_core_pipe_kernel, 256, 0);
   if (e != hipSuccess || per_cu < 1) per_cu = 1;
   int dev = 0, cus = 0;
   if (hipGetDevice(&dev) != hipSuccess ||
@@ -344,7 +467,8 @@ hipError_t launch_batch_slab(const BatchSlab& bs, int tg, int nbuf, hipStream_t 
   hipLaunchKernelGGL(batch_slab_queue_reset_kernel, dim3(1), dim3(1), 0, st, bs.queue);
   const dim3 grid((unsigned)ceil_div(bs.nwaves, kWaves));
   const size_t lds = batch_slab_lds_bytes();
-  if (tg == 1 && nbuf == 2) hipLaunchKernelGGL((batch_slab_kernel<1, 2>), grid, dim3(256), lds, st, bs);
+  if (tg == 0 && nbuf == 0) hipLaunchKernelGGL(batch_core_pipe_kernel, grid, dim3(256), 0, st, bs);
+  else if (tg == 1 && nbuf == 2) hipLaunchKernelGGL((batch_slab_kernel<1, 2>), grid, dim3(256), lds, st, bs);
   else if (tg == 2 && nbuf == 2) hipLaunchKernelGGL((batch_slab_kernel<2, 2>), grid, dim3(256), lds, st, bs);
   else if (tg == 1 && nbuf == 3) hipLaunchKernelGGL((batch_slab_kernel<1, 3>), grid, dim3(256), lds, st, bs);
   else return hipErrorInvalidValue;

@@ -878,8 +878,8 @@ struct BatchPlanData {
   std::vector<BatchModeDesc*> d_steps;
   SketchList sl{};
   BatchSlab bs{};
-  int tg = 1, nbuf = 2;
-  int64_t chunk_bytes = 512 << 10;
+  int tg = 0, nbuf = 0;               // whole-slab pipeline form until tuned
+  int64_t chunk_bytes = 128 << 10;
   // residual (when requested): expansion of each core over its leading
   // modes into the tensor's T, then the residual pass over its own schedule
   double* resid2 = nullptr;
@@ -2567,7 +2567,7 @@ tk_status tucker_batch_autotune(tk_batch_plan* plan, void* stream, char* report,
   hipStream_t st = as_stream(stream);
   // factors for the timed passes
   if (tk_status s = batch_run(P, st)) return s;
-  const int variants[3][2] = {{1, 2}, {2, 2}, {1, 3}};
+  const int variants[4][2] = {{0, 0}, {1, 2}, {2, 2}, {1, 3}};
   const int64_t chunk_sizes[3] = {kBatchChunkMin, 128 << 10, 512 << 10};
   hipEvent_t e0, e1;
   TK_HIP(hipEventCreate(&e0));
@@ -2576,7 +2576,7 @@ tk_status tucker_batch_autotune(tk_batch_plan* plan, void* stream, char* report,
   float best = 1e30f;
   int bv = 0, bc = 1;
   tk_status status = TK_OK;
-  for (int v = 0; v < 3 && status == TK_OK; ++v)
+  for (int v = 0; v < 4 && status == TK_OK; ++v)
     for (int c = 0; c < 3 && status == TK_OK; ++c) {
       if ((status = batch_set_schedule(P, variants[v][0], variants[v][1], chunk_sizes[c], st))) break;
       if ((status = batch_core(P, st))) break;   // warm-up
@@ -2632,8 +2632,8 @@ tk_status tucker_batch_set_schedule(tk_batch_plan* plan, int32_t tiles_per_unit,
   clear_error();
   const ApiRange range_("tucker_batch_set_schedule");
   if (!plan) return set_error(TK_EINVAL, "tucker_batch_set_schedule: plan is NULL");
-  const bool variant = (tiles_per_unit == 1 && buffers == 2) || (tiles_per_unit == 2 && buffers == 2) ||
-                       (tiles_per_unit == 1 && buffers == 3);
+  const bool variant = (tiles_per_unit == 0 && buffers == 0) || (tiles_per_unit == 1 && buffers == 2) ||
+                       (tiles_per_unit == 2 && buffers == 2) || (tiles_per_unit == 1 && buffers == 3);
   if (!variant)
     return set_error(TK_EINVAL, "tucker_batch_set_schedule: no streaming-pass form with %d tiles per unit and %d "
                      "buffers", tiles_per_unit, buffers);
