@@ -1905,6 +1905,29 @@ tk_status htucker_decompose(const tk_tensor* X, const tk_tree* tree, const int32
   for (int t = 1; t < nn; ++t)
     if (dense[t]) dpart = std::max<int64_t>(dpart, (int64_t)kDenseSplit * sk[t].ell * std::max(nc[t], nS[t]));
   double* dense_part = dpart > 1 ? w.take<double>((size_t)dpart) : nullptr;
+  // both children of the root dense (a prefix and a suffix of X's modes): the
+  // sketch products X Omega_l and Omega_r^T X share one read of X, and so do
+  // the W-step products Q_l^T X and X Q_r
+  const int L0 = tree->left[0], R0 = tree->right[0];
+  const bool two_sided = dense[L0] && dense[R0] && A[L0] == 1 && Bv[R0] == 1 &&
+                         twoside_supported(X->dtype, nS[L0], nS[R0], sk[L0].ell, sk[R0].ell);
+  double* ts_part = two_sided ? w.take<double>((size_t)twoside_partials(nS[L0], nS[R0])) : nullptr;
+  auto two_side = [&](const void* P1, int k1, const void* P2, int k2, int p_dt, double* o1, double* o2,
+                      bool o2t) -> hipError_t {
+    TwoSide x{};
+    x.X = static_cast<const float*>(X->data);
+    x.P1 = P1;
+    x.P2 = P2;
+    x.out1 = o1;
+    x.out2 = o2;
+    x.part1 = ts_part;
+    x.n1 = nS[L0];
+    x.n2 = nS[R0];
+    x.k1 = k1;
+    x.k2 = k2;
+    x.out2_transposed = o2t ? 1 : 0;
+    return launch_twoside(x, p_dt, as_stream(stream));
+  };
   // transfers of internal non-root nodes
   std::vector<Transfer> tr;
   for (int t = 1; t < nn; ++t) {
@@ -1958,8 +1981,10 @@ tk_status htucker_decompose(const tk_tensor* X, const tk_tree* tree, const int32
     mp.qsplit_max = kDenseSplit;
     return launch_mode_product(mp, in_dt, TK_F64, m_dt, st);
   };
+  if (two_sided)   // Z_l = X Omega_l; Z_r^T = Omega_r^T X, written transposed
+    TK_HIP(two_side(sk[L0].omega, sk[L0].ell, sk[R0].omega, sk[R0].ell, odt, Z[L0], Z[R0], true));
   for (int t = 1; t < nn; ++t) {
-    if (!dense[t]) continue;
+    if (!dense[t] || (two_sided && (t == L0 || t == R0))) continue;
     const int ell = sk[t].ell;
     if (A[t] == 1) {     // prefix: X^(S) is X viewed n_S x n_notS, Z = X Omega
       TK_HIP(mode_x(nS[t], nc[t], 1, ell, sk[t].omega, odt, Z[t], X->data, X->dtype));
@@ -1974,17 +1999,20 @@ tk_status htucker_decompose(const tk_tensor* X, const tk_tree* tree, const int32
   std::vector<QRMat> sparse_m, dense_m;
   for (int t = 1; t < nn; ++t) (dense[t] ? dense_m : sparse_m).push_back(mats[t - 1]);
   if (tk_status s = run_wstep(sparse_m, X->dtype, fdt, false, st)) return s;
+  if (two_sided)   // M_l = Q_l^T X (ell_l x n_r) and M_r^T = X Q_r (n_l x ell_r)
+    TK_HIP(two_side(mats[R0 - 1].Z, sk[R0].ell, mats[L0 - 1].Z, sk[L0].ell, TK_F64, Md[R0], Md[L0], false));
   for (int t = 1; t < nn; ++t) {
     if (!dense[t]) continue;
     const int ell = sk[t].ell;
     const QRMat& q = mats[t - 1];
+    const bool done = two_sided && (t == L0 || t == R0);
     UnfoldGemm g{};
     if (A[t] == 1) {     // M = Q^T X^(S): ell x n_notS
-      TK_HIP(mode_x(1, nS[t], nc[t], ell, q.Z, TK_F64, Md[t], X->data, X->dtype));
+      if (!done) TK_HIP(mode_x(1, nS[t], nc[t], ell, q.Z, TK_F64, Md[t], X->data, X->dtype));
       g.pre = 1;
       g.post = nc[t];
     } else {             // M^T = X_(n_notS x n_S) Q: n_notS x ell
-      TK_HIP(mode_x(nc[t], nS[t], 1, ell, q.Z, TK_F64, Md[t], X->data, X->dtype));
+      if (!done) TK_HIP(mode_x(nc[t], nS[t], 1, ell, q.Z, TK_F64, Md[t], X->data, X->dtype));
       g.pre = nc[t];
       g.post = 1;
     }

@@ -375,6 +375,27 @@ struct Transfer {
 };
 hipError_t launch_transfer(const Transfer& t, int f_dt, hipStream_t st);
 
+// ---------------------------------------------------------------- two-sided product
+// O1 = X P1 (n1 x k1) and O2 = P2^T X (k2 x n2) in one read of an FP32 X
+// (n1 x n2 row-major), FP64 accumulation, P1 / P2 FP32 or FP64, k1, k2 <= 16.
+struct TwoSide {
+  const float* X;
+  const void* P1;       // n2 x k1
+  const void* P2;       // n1 x k2
+  double* out1;         // n1 x k1
+  double* out2;         // k2 x n2, or n2 x k2 with out2_transposed
+  double* part1;        // twoside_partials(n1, n2) doubles (part2 follows part1)
+  double* part2;        // set by the launcher
+  int64_t n1, n2;
+  int32_t k1, k2;
+  int32_t out2_transposed;
+  int32_t nrt, nct;     // set by the launcher
+  int32_t pad;
+};
+bool twoside_supported(int x_dtype, int64_t n1, int64_t n2, int k1, int k2);
+int64_t twoside_partials(int64_t n1, int64_t n2);
+hipError_t launch_twoside(const TwoSide& ts, int p_dtype, hipStream_t st);
+
 // ---------------------------------------------------------------- H-Tucker root pass
 // B_R[j][k] = sum_{a,b} UL[a][j] X[a][b] UR[b][k] for an FP32 X (nL x nR), FP64 bases.
 struct RootPass {

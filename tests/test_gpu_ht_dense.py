@@ -62,8 +62,12 @@ def test_dense_root_children_f64(order, expect):
     assert abs(eps - eps_or) <= ht_parity.eps_gate(eps_or, spread, 1e-10)
 
 
-def test_dense_root_children_f32():
-    tr, dense, U, Bg, U_or, B_or, X64, info, ranks, sk = _run(6, "f32")
+@pytest.mark.parametrize("order,n", [(6, 10), (6, 15), (4, 40)])
+def test_dense_root_children_f32(order, n):
+    """Both children of the root dense with ell <= 16: the sketches and the
+    W-step products of the two children are two-sided passes over X (one
+    1024 x 1024 tile at 10^6, ragged 4 x 4 and 2 x 2 tiles at 15^6 and 40^4)."""
+    tr, dense, U, Bg, U_or, B_or, X64, info, ranks, sk = _run(order, "f32", n=n)
     assert dense == [1, 2]
     eps_or = oracle.ht_rel_error(X64, tr, U_or, B_or)
     eps = oracle.ht_rel_error(X64, tr, U, Bg)
