@@ -173,6 +173,102 @@ __global__ __launch_bounds__(256) void ht_expand_kernel(const HTExpand p) {
   }
 }
 
+// Residual-only form for FP32 X and r_r <= 16 on v_mfma_f64_16x16x4f64: the
+// same workgroup partition (a column tile of 256 C columns and a group of
+// rows), each wave a quarter of the columns in strips of 64, each 16 x 16
+// tile of X_hat as K = rpad / 4 MFMA steps (A operand T[a][4 s + l/16], B
+// operand U_Rr[b][4 s + l/16] for column b = l%16 of the tile).  Register v
+// of lane l is row l/16 + 4 v, column l%16, so X comes in as four b32 loads
+// per tile (rows of 16 consecutive columns), the next row tile in flight
+// while this one is multiplied; the squares are FP64.  The VALU form spends
+// about 22 instructions per entry at r_r = 12.
+template <int KS>
+__global__ __launch_bounds__(256) void ht_resid_mfma_kernel(const HTExpand p) {
+  typedef double doublex4 __attribute__((ext_vector_type(4)));
+  constexpr int R = 4 * KS;
+  constexpr int C = 64 / R;                 // columns per lane in the VALU form's partition
+  constexpr int kStrips = C;                // 64-column strips per wave (a quarter of 256 C columns)
+  __shared__ double red[2][4];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, g = lane >> 4, l16 = lane & 15;
+  const int64_t tile = blockIdx.x % p.ntile, grp = blockIdx.x / p.ntile;
+  const int64_t a0 = grp * p.rows_per_group;
+  const int64_t a1 = min(a0 + p.rows_per_group, p.nL);
+  const int nrt = (int)((a1 - a0 + 15) / 16);
+  const float* X = static_cast<const float*>(p.X);
+  double r2 = 0.0, x2 = 0.0;
+  for (int cs = 0; cs < kStrips; ++cs) {
+    const int64_t cb = tile * (256 * C) + (int64_t)(wv * kStrips + cs) * 64;
+    // B operands of the strip's four column tiles
+    double ub[4][KS];
+    uint32_t coff[4];
+#pragma unroll
+    for (int ct = 0; ct < 4; ++ct) {
+      const int64_t b = cb + 16 * ct + l16;
+#pragma unroll
+      for (int k = 0; k < KS; ++k) ub[ct][k] = (b < p.nR && 4 * k + g < p.rr) ? p.UR[b * p.rr + 4 * k + g] : 0.0;
+      coff[ct] = b < p.nR ? (uint32_t)(b * 4) : 0x80000000u;
+    }
+    auto issue = [&](int rt, float (&xv)[4][4]) {
+      const int64_t row0 = a0 + 16 * (int64_t)rt;
+      const int64_t rows = rt < nrt ? min<int64_t>(16, a1 - row0) : 0;
+      const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+          const_cast<float*>(X) + (rows > 0 ? row0 * p.nR : 0), (short)0, (int)(rows * p.nR * 4), 0x00020000);
+#pragma unroll
+      for (int ct = 0; ct < 4; ++ct)
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+          xv[ct][v] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(
+              rs, coff[ct] + (uint32_t)((g + 4 * v) * p.nR * 4), 0, 0));
+    };
+    auto tile_rt = [&](int rt, const float (&xv)[4][4]) {
+      const int64_t row = a0 + 16 * (int64_t)rt + l16;
+      double ta[KS];
+#pragma unroll
+      for (int k = 0; k < KS; ++k) ta[k] = row < a1 ? p.T[row * p.rpad + 4 * k + g] : 0.0;
+#pragma unroll
+      for (int ct = 0; ct < 4; ++ct) {
+        doublex4 acc = doublex4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int k = 0; k < KS; ++k) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(ta[k], ub[ct][k], acc, 0, 0, 0);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const double x = (double)xv[ct][v], d = x - acc[v];
+          r2 = fma(d, d, r2);
+          x2 = fma(x, x, x2);
+        }
+      }
+    };
+    // the next row tile in flight while this one is multiplied (four in
+    // flight was slower: 12.9 against 10.5 ms at 18^8)
+    float xa[4][4], xb[4][4];
+    issue(0, xa);
+    int rt = 0;
+    for (; rt + 2 <= nrt; rt += 2) {
+      issue(rt + 1, xb);
+      __builtin_amdgcn_sched_barrier(0);
+      tile_rt(rt, xa);
+      issue(rt + 2, xa);
+      __builtin_amdgcn_sched_barrier(0);
+      tile_rt(rt + 1, xb);
+    }
+    if (rt < nrt) tile_rt(rt, xa);
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    r2 += __shfl_xor(r2, off);
+    x2 += __shfl_xor(x2, off);
+  }
+  if (lane == 0) {
+    red[0][wv] = r2;
+    red[1][wv] = x2;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    p.partials[2 * blockIdx.x] = (red[0][0] + red[0][1]) + (red[0][2] + red[0][3]);
+    p.partials[2 * blockIdx.x + 1] = (red[1][0] + red[1][1]) + (red[1][2] + red[1][3]);
+  }
+}
+
 // out[0..1] = sums of the workgroup partials, in a fixed order
 __global__ __launch_bounds__(256) void ht_sum_kernel(const double* partials, int64_t nblocks, double* out) {
   __shared__ double red[2][256];
@@ -280,7 +376,13 @@ hipError_t launch_ht_expand(const HTExpand& p, int x_dt, int out_dt, hipStream_t
   if (p.rpad != 8 && p.rpad != 12 && p.rpad != 16 && p.rpad != 32 && p.rpad != 64)
     return hipErrorInvalidValue;
   hipError_t e = hipErrorInvalidValue;
-  switch (x_dt) {
+  if (x_dt == TK_F32 && out_dt == -1 && p.partials && p.rpad <= 16 && p.nR * 64 < (int64_t(1) << 31)) {
+    const dim3 grid((unsigned)(p.ntile * p.groups));
+    if (p.rpad == 8) hipLaunchKernelGGL(ht_resid_mfma_kernel<2>, grid, dim3(256), 0, st, p);
+    else if (p.rpad == 12) hipLaunchKernelGGL(ht_resid_mfma_kernel<3>, grid, dim3(256), 0, st, p);
+    else hipLaunchKernelGGL(ht_resid_mfma_kernel<4>, grid, dim3(256), 0, st, p);
+    e = hipGetLastError();
+  } else switch (x_dt) {
     case -1: e = out_dt == -1 ? hipErrorInvalidValue : expand_by_out<None>(p, out_dt, st); break;
     case TK_F64: e = expand_by_out<double>(p, out_dt, st); break;
     case TK_F32: e = expand_by_out<float>(p, out_dt, st); break;

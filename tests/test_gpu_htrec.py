@@ -92,6 +92,31 @@ def test_ht_residual_matches_oracle(case, xdtype):
 
 
 @pytest.mark.parametrize("case", range(len(CASES)))
+@pytest.mark.parametrize("xdtype", ["f64", "f32", "bf16"])
+def test_ht_residual_only_matches_oracle(case, xdtype):
+    """The residual without X_hat: for FP32 X and a root right child of rank
+    <= 16 the FP64-MFMA pass (ragged row and column tiles, padded ranks 8, 12
+    and 16), otherwise the FP64 VALU pass; the same gates as with X_hat."""
+    from paper_2603_21379_amd import tucker as T
+    dims, rule, seed = CASES[case]
+    tr, ranks, U, Bt = _format(dims, rule, seed)
+    ref = oracle.ht_full(dims, tr, U, Bt)
+    rng = np.random.default_rng(200 + seed)
+    Xs = synthgen.to_storage(ref + 1e-3 * rng.standard_normal(dims), xdtype)
+    X64 = synthgen.to_f64(Xs, xdtype)
+    r2_ref = float(np.sum((X64 - ref) ** 2))
+    n2_ref = float(np.sum(X64 ** 2))
+    Xd = torch.from_numpy(Xs.view(np.int16) if xdtype == "bf16" else Xs).cuda()
+    if xdtype == "bf16":
+        Xd = Xd.view(torch.bfloat16)
+    Xh, r2 = T.ht_reconstruct(dims, tr, ranks, _dev(U), _dev(Bt), Xref=Xd)
+    assert Xh is None
+    r2 = r2.cpu().numpy()
+    assert abs(r2[0] - r2_ref) <= 1e-9 * r2_ref
+    assert abs(r2[1] - n2_ref) <= 1e-12 * n2_ref
+
+
+@pytest.mark.parametrize("case", range(len(CASES)))
 @pytest.mark.parametrize("hdtype", [np.float64, np.float32])
 def test_ht_vjp_matches_oracle(case, hdtype):
     from paper_2603_21379_amd import tucker as T
