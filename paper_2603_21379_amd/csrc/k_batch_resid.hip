@@ -37,13 +37,49 @@ __device__ __forceinline__ floatx4 mma16(float a, float b, floatx4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
 
+// Four consecutive entries of X in one load: 16 bytes of FP32 or 8 bytes of
+// BF16 / FP16, widened to FP32.
+template <typename TX> struct Quad;
+template <> struct Quad<float> {
+  typedef uintx4 raw;
+  static __device__ __forceinline__ raw load(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+    return __builtin_bit_cast(uintx4, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0));
+  }
+  static __device__ __forceinline__ floatx4 widen(raw v) { return __builtin_bit_cast(floatx4, v); }
+};
+typedef unsigned int uintx2 __attribute__((ext_vector_type(2)));
+template <> struct Quad<bf16> {
+  typedef uintx2 raw;
+  static __device__ __forceinline__ raw load(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+    return __builtin_bit_cast(uintx2, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+  }
+  static __device__ __forceinline__ floatx4 widen(raw v) {
+    return floatx4{__uint_as_float(v[0] << 16), __uint_as_float(v[0] & 0xFFFF0000u), __uint_as_float(v[1] << 16),
+                   __uint_as_float(v[1] & 0xFFFF0000u)};
+  }
+};
+template <> struct Quad<f16> {
+  typedef uintx2 raw;
+  static __device__ __forceinline__ raw load(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+    return __builtin_bit_cast(uintx2, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+  }
+  static __device__ __forceinline__ floatx4 widen(raw v) {
+    return floatx4{(float)__builtin_bit_cast(_Float16, (unsigned short)(v[0] & 0xFFFFu)),
+                   (float)__builtin_bit_cast(_Float16, (unsigned short)(v[0] >> 16)),
+                   (float)__builtin_bit_cast(_Float16, (unsigned short)(v[1] & 0xFFFFu)),
+                   (float)__builtin_bit_cast(_Float16, (unsigned short)(v[1] >> 16))};
+  }
+};
+
 // per wave: F_I and F_J of the chunk's tensor ([i][k], row stride 17) and the P table
 constexpr int kFW = kBatchMaxC + 1;
 constexpr int kWaveLds = 2 * kBatchMaxN * kFW + kBatchMaxC * kPW;   // floats
 
-template <int NT, int D>
-__device__ __forceinline__ void resid_chunk(const BatchTensor& td, int64_t a0, int64_t a1, float* wl, int lane,
-                                            double& r2, double& x2) {
+template <typename TX, int NT, int D>
+__device__ __forceinline__ void resid_chunk(const BatchTensor& td, const TX* Xp, int64_t a0, int64_t a1, float* wl,
+                                            int lane, double& r2, double& x2) {
+  typedef typename Quad<TX>::raw raw;
+  constexpr uint32_t kB = sizeof(TX);
   const int g = lane >> 4, l16 = lane & 15;
   const int nI = td.nI, nJ = td.nJ, cI = td.cI, cJ = td.cJ;
   const int nTI = (nI + 15) >> 4, nTJ = (nJ + 15) >> 4;
@@ -59,13 +95,13 @@ __device__ __forceinline__ void resid_chunk(const BatchTensor& td, int64_t a0, i
   }
   __builtin_amdgcn_wave_barrier();
   __atomic_signal_fence(__ATOMIC_SEQ_CST);
-  const uint32_t rowb = (uint32_t)nJ * 4u, slab_bytes = (uint32_t)(nI * nJ) * 4u;
+  const uint32_t rowb = (uint32_t)nJ * kB, slab_bytes = (uint32_t)(nI * nJ) * kB;
   // this lane's byte offset of tile (0, jt): row l%16, columns 16 jt + 4 (l/16) ..
   uint32_t coff[NT];
 #pragma unroll
   for (int jt = 0; jt < NT; ++jt) {
     const int col = 16 * jt + 4 * g;
-    coff[jt] = (jt < nTJ && col < nJ) ? (uint32_t)l16 * rowb + (uint32_t)col * 4u : 0x80000000u;
+    coff[jt] = (jt < nTJ && col < nJ) ? (uint32_t)l16 * rowb + (uint32_t)col * kB : 0x80000000u;
   }
   uintx4 lastmask;
   {
@@ -83,9 +119,9 @@ __device__ __forceinline__ void resid_chunk(const BatchTensor& td, int64_t a0, i
   }
   // the loads of one slab (X in the stage-2 layout, its T block); a slab
   // past the chunk gets empty ranges (every load reads zero, no traffic)
-  auto issue = [&](int64_t a, uintx4 (&xr)[NT][NT], float (&ta)[4]) {
+  auto issue = [&](int64_t a, raw (&xr)[NT][NT], float (&ta)[4]) {
     const bool live = a < a1;
-    const char* xs = reinterpret_cast<const char*>(td.X) + (live ? a : a0) * (int64_t)slab_bytes;
+    const char* xs = reinterpret_cast<const char*>(Xp) + (live ? a : a0) * (int64_t)slab_bytes;
 #pragma unroll
     for (int it = 0; it < NT; ++it) {
       // one range per row tile (from its first row to the slab's end), so
@@ -95,8 +131,7 @@ __device__ __forceinline__ void resid_chunk(const BatchTensor& td, int64_t a0, i
       const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
           const_cast<char*>(xs) + (on ? rt : 0), (short)0, on ? (int)slab_bytes - rt : 0, kRsrcWord3);
 #pragma unroll
-      for (int jt = 0; jt < NT; ++jt)
-        xr[it][jt] = __builtin_bit_cast(uintx4, __builtin_amdgcn_raw_buffer_load_b128(rs, coff[jt], 0, 0));
+      for (int jt = 0; jt < NT; ++jt) xr[it][jt] = Quad<TX>::load(rs, coff[jt]);
     }
     const __amdgpu_buffer_rsrc_t rt = __builtin_amdgcn_make_buffer_rsrc(
         const_cast<float*>(td.T) + (live ? a : a0) * cIJ, (short)0, live ? cIJ * 4 : 0, kRsrcWord3);
@@ -110,7 +145,7 @@ __device__ __forceinline__ void resid_chunk(const BatchTensor& td, int64_t a0, i
   // tile tests stay (they also keep the scheduler from hoisting operand
   // reads across tiles, which spills with a whole slab in registers).
   constexpr bool kSkip = NT >= 4;
-  auto compute = [&](const uintx4 (&xr)[NT][NT], const float (&ta)[4]) {
+  auto compute = [&](const raw (&xr)[NT][NT], const float (&ta)[4]) {
     // stage 1: P = T[a] F_J^T (B operand lane l: F_J[16 jt + l%16][4 ks + l/16])
 #pragma unroll
     for (int jt = 0; jt < NT; ++jt) {
@@ -150,7 +185,8 @@ __device__ __forceinline__ void resid_chunk(const BatchTensor& td, int64_t a0, i
 #pragma unroll
         for (int ks = 0; ks < 4; ++ks)
           acc = mma16(kKeepP ? pv[kKeepP ? jt : 0][ks] : sP[4 * ks + g][16 * jt + l16], fi[ks], acc);
-        const floatx4 x = __builtin_bit_cast(floatx4, xr[it][jt] & (jt == nTJ - 1 ? lastmask : ~uintx4{}));
+        const floatx4 x = __builtin_bit_cast(
+            floatx4, __builtin_bit_cast(uintx4, Quad<TX>::widen(xr[it][jt])) & (jt == nTJ - 1 ? lastmask : ~uintx4{}));
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           const float d = x[v] - acc[v];
@@ -168,7 +204,7 @@ __device__ __forceinline__ void resid_chunk(const BatchTensor& td, int64_t a0, i
   // the D - 1 slabs after it are pending.  Full groups carry no exit test
   // (one would leave skipped loads pending at the loop head and force a wait
   // for all of them); the tail multiplies the slabs still in flight.
-  uintx4 xr[D][NT][NT];
+  raw xr[D][NT][NT];
   float ta[D][4];
   int64_t next = a0;
 #pragma unroll
@@ -211,12 +247,12 @@ __global__ __launch_bounds__(64 * kWaves, 2) void batch_resid_kernel(const Batch
     const int nt = (max(td.nI, td.nJ) + 15) >> 4;
     double r2 = 0.0, x2 = 0.0;
     switch (nt) {
-      case 1: resid_chunk<1, 8>(td, ch.a0, ch.a1, wl, lane, r2, x2); break;
-      case 2: resid_chunk<2, 6>(td, ch.a0, ch.a1, wl, lane, r2, x2); break;
-      case 3: resid_chunk<3, 3>(td, ch.a0, ch.a1, wl, lane, r2, x2); break;
-      case 4: resid_chunk<4, 2>(td, ch.a0, ch.a1, wl, lane, r2, x2); break;
-      case 5: resid_chunk<5, 1>(td, ch.a0, ch.a1, wl, lane, r2, x2); break;
-      default: resid_chunk<6, 1>(td, ch.a0, ch.a1, wl, lane, r2, x2); break;
+      case 1: resid_chunk<float, 1, 8>(td, td.X, ch.a0, ch.a1, wl, lane, r2, x2); break;
+      case 2: resid_chunk<float, 2, 6>(td, td.X, ch.a0, ch.a1, wl, lane, r2, x2); break;
+      case 3: resid_chunk<float, 3, 3>(td, td.X, ch.a0, ch.a1, wl, lane, r2, x2); break;
+      case 4: resid_chunk<float, 4, 2>(td, td.X, ch.a0, ch.a1, wl, lane, r2, x2); break;
+      case 5: resid_chunk<float, 5, 1>(td, td.X, ch.a0, ch.a1, wl, lane, r2, x2); break;
+      default: resid_chunk<float, 6, 1>(td, td.X, ch.a0, ch.a1, wl, lane, r2, x2); break;
     }
     for (int o = 32; o > 0; o >>= 1) {
       r2 += __shfl_xor(r2, o);
@@ -231,6 +267,49 @@ __global__ __launch_bounds__(64 * kWaves, 2) void batch_resid_kernel(const Batch
 }
 
 __global__ void batch_queue_reset_kernel(int32_t* queue) { *queue = 0; }
+
+// The same pass for one tensor whose trailing modes are at most 64 (the
+// small-mode residual of the single-tensor path): chunks of equal slab
+// counts taken round-robin by the resident waves (equal costs, so no queue);
+// one (r2, x2) pair per wave, summed in wave order by the launcher's kernel.
+template <typename TX>
+__global__ __launch_bounds__(64 * kWaves, 2) void slab_resid_kernel(const ResidSlab p, int64_t chunk) {
+  extern __shared__ float lds[];
+  float* wl = lds + (threadIdx.x >> 6) * kWaveLds;
+  const int lane = threadIdx.x & 63;
+  const int gwave = __builtin_amdgcn_readfirstlane((int)blockIdx.x * kWaves + (int)(threadIdx.x >> 6));
+  if (gwave >= p.nwaves) return;   // no workgroup barrier follows
+  BatchTensor td{};
+  td.FI = p.FI;
+  td.FJ = p.FJ;
+  td.T = const_cast<float*>(p.T);
+  td.A = p.A;
+  td.nI = p.nI;
+  td.nJ = p.nJ;
+  td.cI = p.cI;
+  td.cJ = p.cJ;
+  const TX* X = static_cast<const TX*>(p.X);
+  const int nt = (max(p.nI, p.nJ) + 15) >> 4;
+  const int64_t nch = (p.A + chunk - 1) / chunk;
+  double r2 = 0.0, x2 = 0.0;
+  for (int64_t c = gwave; c < nch; c += p.nwaves) {
+    const int64_t a0 = c * chunk, a1 = min(p.A, a0 + chunk);
+    switch (nt) {
+      case 1: resid_chunk<TX, 1, 8>(td, X, a0, a1, wl, lane, r2, x2); break;
+      case 2: resid_chunk<TX, 2, 6>(td, X, a0, a1, wl, lane, r2, x2); break;
+      case 3: resid_chunk<TX, 3, 3>(td, X, a0, a1, wl, lane, r2, x2); break;
+      default: resid_chunk<TX, 4, 2>(td, X, a0, a1, wl, lane, r2, x2); break;
+    }
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    r2 += __shfl_xor(r2, o);
+    x2 += __shfl_xor(x2, o);
+  }
+  if (lane == 0) {
+    p.partials[2 * gwave] = r2;
+    p.partials[2 * gwave + 1] = x2;
+  }
+}
 
 // one thread per tensor: its chunks' pairs in chunk order
 __global__ void batch_resid_sum_kernel(const double* partials, const int32_t* chunk_begin, int32_t count,
@@ -259,6 +338,40 @@ int batch_resid_waves() {
       hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
     cus = 256;
   return per_cu * cus * kWaves;
+}
+
+bool slab_resid_pipe_supported(int x_dtype, int64_t nI, int64_t nJ) {
+  // two-byte entries are read four at a time as 8-byte loads: rows of an
+  // even length keep every such load 4-byte aligned
+  return nI <= 64 && nJ <= 64 && (x_dtype == TK_F32 || ((x_dtype == TK_BF16 || x_dtype == TK_F16) && nJ % 2 == 0));
+}
+
+hipError_t launch_slab_resid_pipe(const ResidSlab& pin, int x_dtype, int max_waves, hipStream_t st) {
+  ResidSlab p = pin;
+  const int64_t slab = (int64_t)p.nI * p.nJ * (x_dtype == TK_F32 ? 4 : 2);
+  const int64_t chunk = std::max<int64_t>(1, (256 << 10) / slab);
+  const int64_t nch = ceil_div(p.A, chunk);
+  int per_cu = 0;
+  const size_t lds = kWaves * kWaveLds * sizeof(float);
+  hipError_t e = x_dtype == TK_F32
+                     ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, slab_resid_kernel<float>, 64 * kWaves, lds)
+                     : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, slab_resid_kernel<bf16>, 64 * kWaves, lds);
+  if (e != hipSuccess || per_cu < 1) per_cu = 1;
+  int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
+    cus = 256;
+  // waves: resident ones, at most one per chunk, within the partials the caller sized
+  p.nwaves = (int32_t)std::max<int64_t>(1, std::min<int64_t>({(int64_t)per_cu * cus * kWaves, nch, (int64_t)max_waves}));
+  const dim3 grid((unsigned)ceil_div(p.nwaves, kWaves));
+  switch (x_dtype) {
+    case TK_F32: hipLaunchKernelGGL(slab_resid_kernel<float>, grid, dim3(64 * kWaves), lds, st, p, chunk); break;
+    case TK_BF16: hipLaunchKernelGGL(slab_resid_kernel<bf16>, grid, dim3(64 * kWaves), lds, st, p, chunk); break;
+    default: hipLaunchKernelGGL(slab_resid_kernel<f16>, grid, dim3(64 * kWaves), lds, st, p, chunk); break;
+  }
+  if (hipError_t e2 = hipGetLastError()) return e2;
+  if (p.resid2) return launch_pair_sum(p.partials, p.nwaves, p.resid2, st);
+  return hipSuccess;
 }
 
 hipError_t launch_batch_resid(const BatchResid& br, hipStream_t st) {

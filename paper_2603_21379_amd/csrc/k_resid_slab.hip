@@ -173,6 +173,8 @@ int64_t resid_slab_waves(int64_t A) {
 }
 
 hipError_t launch_resid_slab(const ResidSlab& pin, int x_dtype, hipStream_t st) {
+  if (slab_resid_pipe_supported(x_dtype, pin.nI, pin.nJ))
+    return launch_slab_resid_pipe(pin, x_dtype, (int)resid_slab_waves(pin.A), st);
   ResidSlab p = pin;
   p.nwaves = (int32_t)resid_slab_waves(p.A);
   const int nt = (int)ceil_div(std::max(p.nI, p.nJ), 16);

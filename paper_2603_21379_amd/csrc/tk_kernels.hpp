@@ -359,6 +359,10 @@ struct ResidSlab {
   int32_t pad;
 };
 bool resid_slab_supported(int x_dtype, int order, const int64_t* dims, const int32_t* cols);
+// the pipelined form (several slabs in flight per wave, 16- or 8-byte loads of
+// four entries), used by launch_resid_slab where it applies
+bool slab_resid_pipe_supported(int x_dtype, int64_t nI, int64_t nJ);
+hipError_t launch_slab_resid_pipe(const ResidSlab& p, int x_dtype, int max_waves, hipStream_t st);
 int64_t resid_slab_waves(int64_t A);
 hipError_t launch_resid_slab(const ResidSlab& p, int x_dtype, hipStream_t st);
 

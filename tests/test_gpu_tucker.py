@@ -243,6 +243,7 @@ def test_fp32_fused_residual_and_xhat(dims, cols):
 @pytest.mark.parametrize("dtype", ["f32", "bf16", "f16"])
 @pytest.mark.parametrize("dims,cols", [((30, 40, 40), (5, 10, 10)),       # the 40^6 slab shape
                                        ((7, 9, 33, 17), (3, 4, 16, 7)),  # ragged tiles, full 16 ranks
+                                       ((7, 9, 33, 18), (3, 4, 16, 7)),  # ragged, even rows: 8-byte loads of 2-byte entries
                                        ((3, 64, 64), (2, 16, 16)),       # largest slab
                                        ((5000, 3, 5), (2, 2, 3))])       # many tiny slabs
 def test_small_mode_streaming_residual(dims, cols, dtype):
