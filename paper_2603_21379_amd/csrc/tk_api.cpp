@@ -1007,19 +1007,22 @@ tk_status plan_batch(Workspace& ws, int count, const tk_tensor* X, const int32_t
     for (int k = 0; k < d; ++k) shape[k] = x.dims[k];
     shape[d - 2] = c[d - 2];
     shape[d - 1] = c[d - 1];
+    // The leading modes are contracted first mode first (and expanded back
+    // last mode first), so the steps that read or write the partial core T,
+    // the largest, run with B = everything after mode 0: whole 128-column
+    // blocks, where B = c_I c_J alone (often below 128) would leave lanes idle.
     int64_t mx = 1;
     {
       int64_t sh[TK_MAX_ORDER];
       for (int k = 0; k < d; ++k) sh[k] = shape[k];
-      for (int k = d - 3; k >= 1; --k) {
+      for (int k = 0; k < d - 3; ++k) {
         sh[k] = c[k];
         mx = std::max(mx, prod(sh, 0, d));
       }
     }
     float* buf[2] = {ws.take<float>((size_t)mx), ws.take<float>((size_t)mx)};
     const float* cur = bt.T;
-    for (int s = 0; s < d - 2; ++s) {
-      const int k = d - 3 - s;
+    for (int k = 0; k < d - 2; ++k) {
       BatchModeDesc md{};
       md.in = cur;
       md.F = static_cast<const float*>(U[m0 + k]);
@@ -1028,19 +1031,20 @@ tk_status plan_batch(Workspace& ws, int count, const tk_tensor* X, const int32_t
       md.B = prod(shape, k + 1, d);
       md.P = c[k];
       md.out_slab = (int64_t)md.P * md.B;
-      md.out = k == 0 ? static_cast<float*>(G[t]) : buf[s & 1];
-      P.steps[s].push_back(md);
+      md.out = k == d - 3 ? static_cast<float*>(G[t]) : buf[k & 1];
+      P.steps[k].push_back(md);
       shape[k] = c[k];
       cur = md.out;
     }
     if (resid2) {
-      // T = G x_0 U_0 .. x_{d-3} U_{d-3}: the same intermediate shapes as the
-      // projection in reverse, so its two buffers serve
+      // T = G x_{d-3} U_{d-3} .. x_0 U_0: the projection's intermediate shapes
+      // in reverse, so its two buffers serve
       for (int k = 0; k < d; ++k) shape[k] = c[k];
       const float* ecur = static_cast<const float*>(G[t]);
-      for (int k = 0; k < d - 2; ++k) {
+      for (int e = 0; e < d - 2; ++e) {
+        const int k = d - 3 - e;
         const int64_t n = x.dims[k];
-        float* out = k == d - 3 ? bt.T : buf[k & 1];
+        float* out = k == 0 ? bt.T : buf[e & 1];
         const int64_t Bk = prod(shape, k + 1, d);
         for (int64_t p0 = 0; p0 < n; p0 += 32) {
           BatchModeDesc md{};
@@ -1053,7 +1057,7 @@ tk_status plan_batch(Workspace& ws, int count, const tk_tensor* X, const int32_t
           md.P = (int32_t)std::min<int64_t>(32, n - p0);
           md.out_slab = n * Bk;
           md.ftrans = 1;
-          P.esteps[k].push_back(md);
+          P.esteps[e].push_back(md);
         }
         shape[k] = n;
         ecur = out;
