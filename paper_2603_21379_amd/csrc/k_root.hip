@@ -9,7 +9,7 @@
 // exactly; v_mfma_f64_16x16x4f64 accumulates in FP64.
 //
 // A workgroup owns 256 rows (four waves of four 16-row tiles) and walks the
-// columns in chunks of 32: the chunk of U_r (32 x 16, FP64) is staged in LDS
+// columns in chunks of 64: the chunk of U_r (64 x 16, FP64) is staged in LDS
 // once for the workgroup, each lane loads float4s of X (rows 16 t + l%16,
 // columns 16 s + 4 (l/16) .. +3; component c is the A operand of one K = 4
 // step, K <-> column 16 s + 4 k + c), and the B operand (a row of U_r) is
@@ -21,8 +21,9 @@
 // written; two more kernels sum them in fixed order (segments of workgroups,
 // then the segments).  U_r of the next chunk is loaded into registers while
 // the current chunk is multiplied and every step issues the same loads, so
-// the waits count loads; 32-column chunks keep the kernel at two waves per
-// SIMD.
+// the waits count loads.  64-column chunks (16 KB of X in flight per wave,
+// two waves per SIMD) against 32 (8 KB, three waves): equal at 18^8, 4 %
+// faster at 15^8.
 #include "tk_kernels.hpp"
 
 namespace tk {
@@ -32,7 +33,7 @@ typedef double doublex4 __attribute__((ext_vector_type(4)));
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 
 constexpr int kRows = 256;        // rows per workgroup
-constexpr int kChunk = 32;        // columns per chunk
+constexpr int kChunk = 64;        // columns per chunk
 constexpr int kS = kChunk / 16;   // float4 column groups per lane and chunk
 constexpr int kRsrcWord3 = 0x00020000;
 
@@ -57,7 +58,7 @@ __global__ __launch_bounds__(256) void root_pass_kernel(const RootPass p) {
   const int c0 = qs * per;
   const int nchunks = max(0, min(allchunks, c0 + per) - c0);
 
-  // U_r rows of chunk ck (32 x 16 FP64, two per thread), loaded into
+  // U_r rows of chunk ck (64 x 16 FP64, four per thread), loaded into
   // registers one chunk ahead and written to LDS slot ck % 2 after the
   // previous multiply; rows past n_r and chunks past the end read zero
   constexpr int kUPer = kChunk * 16 / 256;
