@@ -475,6 +475,12 @@ def bench_batch(args):
     log(f"timed {args.steps} graph replays: {ms_per_step:.3f} ms/step; streaming pass "
         f"{core_avg:.3f} ms; eps max {max(errs):.3e} median {float(np.median(errs)):.3e} "
         f"(vs single-tensor residual: {cross:.1e} relative); info nonzero {int((info != 0).sum())}")
+    # QR / W-step flags of the modes (1, 2: a CholeskyQR pass was shifted; 4: a
+    # Cholesky failed even with the shift; 8: the eigensolver ran out of sweeps)
+    flags = {}
+    for v in info.cpu().tolist():
+        if v:
+            flags[str(v)] = flags.get(str(v), 0) + 1
     result = {
         "metric": "tensor GB/s streamed (sketch+core+residual), frac of HBM roofline; rel err vs FP64 oracle",
         "value": round(value, 2), "unit": "GB/s", "n_gpus": 1, "steps": args.steps,
@@ -485,6 +491,7 @@ def bench_batch(args):
         "frac_hbm_step": round(value / HBM_PEAK_GBS, 4),
         "rel_err_gpu": {"max": max(errs), "median": float(np.median(errs)), "from": "graph replay residual",
                         "vs_single_tensor_path": cross},
+        "info_flags": flags,
         "autotune": report.strip().splitlines()[-1],
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
