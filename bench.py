@@ -75,7 +75,14 @@ TRAFFIC = {
     # the uneven shape's pass over X: the middle-mode MFMA contraction (112 -> 28)
     "uneven": (os.path.join(ROOT, "profiles", "core_pass_mode_mfma_uneven_5x10x12x112x80x270_traffic.txt"),
                os.path.join(ROOT, "paper_2603_21379_amd", "csrc", "k_mode_f32.hip")),
+    # the batched core pass (whole-slab form) of the 512-tensor batch
+    "batch": (os.path.join(ROOT, "profiles", "batch_512_f32_order3to5_core_pass_traffic.txt"),
+              os.path.join(ROOT, "paper_2603_21379_amd", "csrc", "k_batch.hip")),
+    # the H-Tucker root pass at 18^8
+    "root": (os.path.join(ROOT, "profiles", "htucker_root_pass_f32_18x8_traffic.txt"),
+             os.path.join(ROOT, "paper_2603_21379_amd", "csrc", "k_root.hip")),
 }
+TRAFFIC_KEY = {"c8_": "uneven", "c4_": "batch", "c5_": "root"}
 
 
 def measured_traffic(workload_name):
@@ -83,7 +90,8 @@ def measured_traffic(workload_name):
     form that runs, or None when the summary is missing or the kernel source
     changed since the counters were taken."""
     import hashlib
-    path, src = TRAFFIC["uneven" if workload_name.startswith("c8_") else "x6"]
+    key = next((v for k, v in TRAFFIC_KEY.items() if workload_name.startswith(k)), "x6")
+    path, src = TRAFFIC[key]
     if not os.path.exists(path):
         return None
     kv = {}
@@ -494,7 +502,8 @@ def bench_batch(args):
         "info_flags": flags,
         "autotune": report.strip().splitlines()[-1],
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": measured_traffic("c4_batch_512_f32_order3to5"),
                      "kernel": "batched streaming pass", "avg_ms": round(core_avg, 4),
                      "bytes_per_launch": b_core},
     }
@@ -604,7 +613,8 @@ def bench_ht(args):
         "rel_error": eps, "ms_resid": round(ms_resid, 4), "ms_format_vjp": round(ms_vjp, 3),
         "resid_gbs": round(N * 4 / ms_resid / 1e6, 1),
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": measured_traffic(c.name),
                      "kernel": "root contraction pass", "avg_ms": round(root_avg, 4),
                      "bytes_per_launch": b_root},
     }
