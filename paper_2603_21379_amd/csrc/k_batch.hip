@@ -247,7 +247,7 @@ __global__ void batch_slab_queue_reset_kernel(int32_t* queue) { *queue = 0; }
 // zero past the slab): they meet zero rows of F_J, so no mask is needed.
 // The factor operands live in registers (reloaded per chunk); no LDS.
 template <int NT, int D>
-__device__ __forceinline__ void core_chunk(const BatchTensor& td, int64_t a0, int64_t a1, int lane) {
+__device__ __forceinline__ void core_chunk(const BatchTensor& td, int64_t a0, int64_t a1, int lane, float* so) {
   const int g = lane >> 4, l16 = lane & 15;
   const int nI = td.nI, nJ = td.nJ, cI = td.cI, cJ = td.cJ;
   const int nTI = (nI + 15) >> 4, nTJ = (nJ + 15) >> 4;
@@ -290,6 +290,31 @@ __device__ __forceinline__ void core_chunk(const BatchTensor& td, int64_t a0, in
         xr[it][jt] = __builtin_bit_cast(uintx4, __builtin_amdgcn_raw_buffer_load_b128(rs, coff[jt], 0, 0));
     }
   };
+  // Output staging: the partial cores of consecutive slabs are contiguous, so
+  // runs of them collect in the wave's LDS block and leave as 16-byte stores
+  // (rows of c_J < 16 floats as b32 stores filled only part of each 64-byte
+  // segment: 1.5x the bytes of T in writes).  Needs c_I c_J divisible by 4.
+  constexpr int kStage = 1024;
+  const bool staged = (cIJ & 3) == 0;
+  int64_t sa0 = 0;
+  int sn = 0;
+  auto flush = [&]() {
+    if (sn == 0) return;
+    __builtin_amdgcn_wave_barrier();   // ordered LDS accesses of one wave: the reads see the writes
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    const int nf = sn * cIJ;
+    const __amdgpu_buffer_rsrc_t ro = __builtin_amdgcn_make_buffer_rsrc(td.T + sa0 * cIJ, (short)0, nf * 4, kRsrcWord3);
+#pragma unroll
+    for (int u = 0; u < kStage / 256; ++u) {
+      const int f = (u * 64 + lane) * 4;
+      const floatx4 w = *reinterpret_cast<const floatx4*>(so + f);
+      const uint32_t o = f < nf ? (uint32_t)(f * 4) : 0x80000000u;
+      __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(uintx4, w), ro, o, 0, kOutStorePolicy);
+    }
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    __builtin_amdgcn_wave_barrier();   // the reads precede the next run's writes
+    sn = 0;
+  };
   auto compute = [&](int64_t a, const uintx4 (&xr)[NT][NT]) {
     floatx4 tacc = floatx4{};
 #pragma unroll
@@ -306,11 +331,24 @@ __device__ __forceinline__ void core_chunk(const BatchTensor& td, int64_t a0, in
 #pragma unroll
       for (int v = 0; v < 4; ++v) tacc = mma_f32(fi[it][v], acc[v], tacc);
     }
-    const __amdgpu_buffer_rsrc_t ro = __builtin_amdgcn_make_buffer_rsrc(td.T + a * cIJ, (short)0, cIJ * 4,
-                                                                        kRsrcWord3);
+    if (staged) {
+      // the slab's c_I x c_J block after the run's previous ones in this
+      // wave's LDS block; a full block goes out as 16-byte stores
 #pragma unroll
-    for (int v = 0; v < 4; ++v)
-      __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(tacc[v]), ro, toff[v], 0, kOutStorePolicy);
+      for (int v = 0; v < 4; ++v) {
+        const int pr = 4 * g + v;
+        if (pr < cI && l16 < cJ) so[sn * cIJ + pr * cJ + l16] = tacc[v];
+      }
+      if (sn == 0) sa0 = a;
+      ++sn;
+      if ((sn + 1) * cIJ > kStage) flush();
+    } else {
+      const __amdgpu_buffer_rsrc_t ro = __builtin_amdgcn_make_buffer_rsrc(td.T + a * cIJ, (short)0, cIJ * 4,
+                                                                          kRsrcWord3);
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+        __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(tacc[v]), ro, toff[v], 0, kOutStorePolicy);
+    }
   };
   uintx4 xr[D][NT][NT];
   int64_t next = a0, cur = a0;
@@ -328,10 +366,13 @@ __device__ __forceinline__ void core_chunk(const BatchTensor& td, int64_t a0, in
 #pragma unroll
   for (int s = 0; s < D - 1; ++s)
     if (s < left) compute(cur++, xr[s]);
+  flush();
 }
 
 __global__ __launch_bounds__(256, 2) void batch_core_pipe_kernel(const BatchSlab bs) {
+  __shared__ float sOut[kWaves][1024];   // each wave's output staging block
   const int lane = threadIdx.x & 63;
+  float* so = sOut[threadIdx.x >> 6];
   auto take = [&]() {
     int q = 0;
     if (lane == 0) q = atomicAdd(bs.queue, 1);
@@ -343,12 +384,12 @@ __global__ __launch_bounds__(256, 2) void batch_core_pipe_kernel(const BatchSlab
     const BatchChunk ch = wave_uniform(bs.chunks[wave_uniform(bs.order[qt])]);
     const BatchTensor td = wave_uniform(bs.tensors[ch.tensor]);
     switch ((max(td.nI, td.nJ) + 15) >> 4) {
-      case 1: core_chunk<1, 8>(td, ch.a0, ch.a1, lane); break;
-      case 2: core_chunk<2, 6>(td, ch.a0, ch.a1, lane); break;
-      case 3: core_chunk<3, 3>(td, ch.a0, ch.a1, lane); break;
-      case 4: core_chunk<4, 2>(td, ch.a0, ch.a1, lane); break;
-      case 5: core_chunk<5, 1>(td, ch.a0, ch.a1, lane); break;
-      default: core_chunk<6, 1>(td, ch.a0, ch.a1, lane); break;
+      case 1: core_chunk<1, 8>(td, ch.a0, ch.a1, lane, so); break;
+      case 2: core_chunk<2, 6>(td, ch.a0, ch.a1, lane, so); break;
+      case 3: core_chunk<3, 3>(td, ch.a0, ch.a1, lane, so); break;
+      case 4: core_chunk<4, 2>(td, ch.a0, ch.a1, lane, so); break;
+      case 5: core_chunk<5, 1>(td, ch.a0, ch.a1, lane, so); break;
+      default: core_chunk<6, 1>(td, ch.a0, ch.a1, lane, so); break;
     }
     qt = qnext;
   }
