@@ -269,12 +269,6 @@ __device__ __forceinline__ void core_chunk(const BatchTensor& td, int64_t a0, in
     coff[jt] = (jt < nTJ && col < nJ) ? (uint32_t)l16 * rowb + (uint32_t)col * 4u : 0x80000000u;
   }
   const int cIJ = cI * cJ;
-  uint32_t toff[4];
-#pragma unroll
-  for (int v = 0; v < 4; ++v) {
-    const int p = 4 * g + v;
-    toff[v] = (p < cI && l16 < cJ) ? (uint32_t)(p * cJ + l16) * 4u : 0x80000000u;
-  }
   auto issue = [&](int64_t a, uintx4 (&xr)[NT][NT]) {
     const bool live = a < a1;
     const char* xs = reinterpret_cast<const char*>(td.X) + (live ? a : a0) * (int64_t)slab_bytes;
@@ -291,11 +285,13 @@ __device__ __forceinline__ void core_chunk(const BatchTensor& td, int64_t a0, in
     }
   };
   // Output staging: the partial cores of consecutive slabs are contiguous, so
-  // runs of them collect in the wave's LDS block and leave as 16-byte stores
-  // (rows of c_J < 16 floats as b32 stores filled only part of each 64-byte
-  // segment: 1.5x the bytes of T in writes).  Needs c_I c_J divisible by 4.
+  // runs of them collect in the wave's LDS block and leave as contiguous
+  // stores: 16 bytes per lane when c_I c_J is a multiple of 4, else 4 bytes
+  // per lane of consecutive floats (storing each tile entry in place filled
+  // only part of each 64-byte segment for rows of c_J < 16 floats: 1.5x the
+  // bytes of T in writes).
   constexpr int kStage = 1024;
-  const bool staged = (cIJ & 3) == 0;
+  const bool quads = (cIJ & 3) == 0;
   int64_t sa0 = 0;
   int sn = 0;
   auto flush = [&]() {
@@ -304,12 +300,21 @@ __device__ __forceinline__ void core_chunk(const BatchTensor& td, int64_t a0, in
     __atomic_signal_fence(__ATOMIC_SEQ_CST);
     const int nf = sn * cIJ;
     const __amdgpu_buffer_rsrc_t ro = __builtin_amdgcn_make_buffer_rsrc(td.T + sa0 * cIJ, (short)0, nf * 4, kRsrcWord3);
+    if (quads) {
 #pragma unroll
-    for (int u = 0; u < kStage / 256; ++u) {
-      const int f = (u * 64 + lane) * 4;
-      const floatx4 w = *reinterpret_cast<const floatx4*>(so + f);
-      const uint32_t o = f < nf ? (uint32_t)(f * 4) : 0x80000000u;
-      __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(uintx4, w), ro, o, 0, kOutStorePolicy);
+      for (int u = 0; u < kStage / 256; ++u) {
+        const int f = (u * 64 + lane) * 4;
+        const floatx4 w = *reinterpret_cast<const floatx4*>(so + f);
+        const uint32_t o = f < nf ? (uint32_t)(f * 4) : 0x80000000u;
+        __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(uintx4, w), ro, o, 0, kOutStorePolicy);
+      }
+    } else {
+#pragma unroll 2
+      for (int u = 0; u < kStage / 64; ++u) {
+        const int f = u * 64 + lane;
+        const uint32_t o = f < nf ? (uint32_t)(f * 4) : 0x80000000u;
+        __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(so[f]), ro, o, 0, kOutStorePolicy);
+      }
     }
     __atomic_signal_fence(__ATOMIC_SEQ_CST);
     __builtin_amdgcn_wave_barrier();   // the reads precede the next run's writes
@@ -331,24 +336,16 @@ __device__ __forceinline__ void core_chunk(const BatchTensor& td, int64_t a0, in
 #pragma unroll
       for (int v = 0; v < 4; ++v) tacc = mma_f32(fi[it][v], acc[v], tacc);
     }
-    if (staged) {
-      // the slab's c_I x c_J block after the run's previous ones in this
-      // wave's LDS block; a full block goes out as 16-byte stores
+    // the slab's c_I x c_J block after the run's previous ones in this
+    // wave's LDS block; a full block goes out as contiguous stores
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int pr = 4 * g + v;
-        if (pr < cI && l16 < cJ) so[sn * cIJ + pr * cJ + l16] = tacc[v];
-      }
-      if (sn == 0) sa0 = a;
-      ++sn;
-      if ((sn + 1) * cIJ > kStage) flush();
-    } else {
-      const __amdgpu_buffer_rsrc_t ro = __builtin_amdgcn_make_buffer_rsrc(td.T + a * cIJ, (short)0, cIJ * 4,
-                                                                          kRsrcWord3);
-#pragma unroll
-      for (int v = 0; v < 4; ++v)
-        __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(tacc[v]), ro, toff[v], 0, kOutStorePolicy);
+    for (int v = 0; v < 4; ++v) {
+      const int pr = 4 * g + v;
+      if (pr < cI && l16 < cJ) so[sn * cIJ + pr * cJ + l16] = tacc[v];
     }
+    if (sn == 0) sa0 = a;
+    ++sn;
+    if ((sn + 1) * cIJ > kStage) flush();
   };
   uintx4 xr[D][NT][NT];
   int64_t next = a0, cur = a0;
