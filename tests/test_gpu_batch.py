@@ -139,6 +139,18 @@ def test_batch_residual_wide_trailing_modes():
     torch.cuda.synchronize()
     assert int(info.abs().sum()) == 0
     check_resid2(items, U, G, r2)
+    # the core of every tensor (whole-slab core pass with four to six tiles,
+    # partial cores leaving through LDS in 16- and 4-byte runs) against the
+    # oracle's core on the same factors
+    assert any((sp.ranks[-1] * sp.ranks[-2]) % 4 for sp in specs)
+    m = 0
+    for ti, (sp, inp, sk, X, skd) in enumerate(items):
+        d = len(sp.dims)
+        Ub = [u.double().cpu().numpy() for u in U[m:m + d]]
+        G_chk = oracle.core(inp.X.astype(np.float64), Ub)
+        np.testing.assert_allclose(G[ti].double().cpu().numpy(), G_chk, rtol=0, atol=1e-6 * np.abs(G_chk).max(),
+                                   err_msg=str(sp.dims))
+        m += d
 
 
 def test_batch_graph_replays_match_eager():
